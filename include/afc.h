@@ -1,0 +1,180 @@
+/*
+ * afc.h -- C ABI of the MI355X algebraic flux correction (AFC) library.
+ *
+ * The library advances P1/Q1 finite element discretizations of the
+ * convection-diffusion-reaction (CDR) equation with algebraic flux correction
+ * as defined in Jha, Partl, Ahmed, Kuzmin, "An Assessment of Solvers for
+ * Algebraically Stabilized Discretizations of Convection-Diffusion-Reaction
+ * Equations" (arXiv 2110.15676):
+ *   - Zalesak's FCT limiter with the explicit SSP scheme (Sec. 2.1.2, 2.1.3),
+ *   - Zalesak's FCT limiter with Crank-Nicolson, nonlinear form solved by
+ *     fixed-point iteration (Sec. 2.1.1, Sec. 4),
+ *   - the monolithic convex limiter (MCL) for the stationary problem
+ *     (Sec. 3.1, Sec. 2.2 eqs. (22)-(23), Remark 1), fixed-point iteration,
+ *   - BiCGStab and restarted GMRES with Jacobi preconditioning (Sec. 4,
+ *     solver and preconditioner tables), optionally FP32-inner / FP64-outer.
+ *
+ * Conventions
+ *   The semi-discrete problem is M_C du/dt = K u + F, i.e. K = -A where A is
+ *   the paper's matrix a_ij of eq. (4).  The graph viscosity used internally is
+ *   d+_ij = max(-k_ij, 0, -k_ji) = -d_ij (eq. (5)).
+ *   All matrices share one CSR pattern: int32 row_ptr[N+1], int32 col_idx[nnz],
+ *   columns sorted ascending within a row, diagonal stored, pattern
+ *   structurally symmetric.  Values are float64 in CSR order.
+ *
+ * Memory and streams
+ *   afc_create copies everything it needs into device memory it owns; the
+ *   caller's arrays may be freed after it returns.  Vectors passed to the
+ *   step/solve calls (u, F, ...) are DEVICE pointers to N float64 values that
+ *   the library borrows for the duration of the call; they must be usable on
+ *   the stream given in afc_options.stream (NULL = the default stream).  Every
+ *   call is synchronous on return (it needs convergence information).
+ *   A handle is not thread safe: use one handle per host thread/stream.
+ *
+ * Errors
+ *   Functions return afc_status; nothing is thrown across the ABI.  Negative
+ *   values are errors, positive values warnings with a usable result.
+ *   afc_last_error(h) returns a description of the last error on h.
+ */
+#ifndef AFC_H_
+#define AFC_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct afc_handle_s afc_handle;
+
+typedef enum {
+  AFC_OK = 0,
+  AFC_WMAXIT = 1,        /* iteration cap reached; u holds the last iterate  */
+  AFC_EINVAL = -1,       /* invalid argument / malformed CSR                  */
+  AFC_ENOMEM = -2,       /* device allocation failed                          */
+  AFC_ENOCONV = -3,      /* linear solver did not converge within its cap     */
+  AFC_EBREAKDOWN = -4,   /* BiCGStab breakdown (rho or omega = 0) twice       */
+  AFC_ENAN = -5,         /* a norm became non-finite                          */
+  AFC_EDEVICE = -6       /* HIP runtime error                                 */
+} afc_status;
+
+enum { AFC_MEM_HOST = 0, AFC_MEM_DEVICE = 1 };
+/* alpha_mode: LIMITED applies the limiter; ONE gives the Galerkin scheme
+ * (alpha_ij = 1), ZERO the low-order scheme (alpha_ij = 0) (Sec. 2, eq. (10)). */
+enum { AFC_ALPHA_LIMITED = 0, AFC_ALPHA_ONE = 1, AFC_ALPHA_ZERO = 2 };
+enum { AFC_KRYLOV_BICGSTAB = 0, AFC_KRYLOV_GMRES = 1 };
+/* MIXED: Krylov SpMVs/vectors in FP32 inside FP64 iterative refinement;
+ * limiter, bounds, flux sums and nonlinear/outer residuals stay FP64. */
+enum { AFC_PREC_FP64 = 0, AFC_PREC_MIXED = 1 };
+/* Nonlinear stopping: ABS_SQRTN is R < sqrt(N) * fp_tol (eq. (28));
+ * REL is R <= fp_tol * R_0.  R is the Euclidean norm of the nonlinear
+ * residual over non-Dirichlet rows. */
+enum { AFC_TOL_ABS_SQRTN = 0, AFC_TOL_REL = 1 };
+
+typedef struct {
+  int32_t n;                /* number of nodes N (> 0)                         */
+  int64_t nnz;              /* number of stored entries (< 2^31)               */
+  int32_t mem_space;        /* AFC_MEM_HOST or AFC_MEM_DEVICE for all arrays   */
+  const int32_t *row_ptr;   /* [N+1], row_ptr[0] = 0, row_ptr[N] = nnz         */
+  const int32_t *col_idx;   /* [nnz], sorted per row, diagonal present         */
+  const double *M;          /* [nnz] consistent mass m_ij (symmetric)          */
+  const double *K;          /* [nnz] K = -A (eq. (4) with opposite sign)       */
+  const double *K_conv;     /* [nnz] optional convective part of K; MCL builds
+                               its graph viscosity and bar states from it
+                               (Remark 1).  NULL: use K.                       */
+  const double *ML;         /* [N] optional lumped mass m_i > 0; NULL: row sums
+                               of M (eq. (5))                                  */
+  int32_t n_dir;            /* number of Dirichlet nodes                       */
+  const int32_t *dir_idx;   /* [n_dir] distinct node indices                   */
+  const double *dir_val;    /* [n_dir] Dirichlet values u_D (time independent) */
+} afc_problem;
+
+typedef struct {
+  int32_t alpha_mode;       /* AFC_ALPHA_*                                     */
+  int32_t krylov;           /* AFC_KRYLOV_*                                    */
+  int32_t restart;          /* GMRES restart length m, 1..64 (default 30)      */
+  int32_t precision;        /* AFC_PREC_*                                      */
+  double lin_atol;          /* linear stop: ||b - A x|| <= max(atol, rtol*||b||) */
+  double lin_rtol;
+  int32_t lin_maxit;        /* Krylov iteration cap per linear solve           */
+  double inner_rtol;        /* MIXED: FP32 inner solve relative tolerance      */
+  int32_t inner_maxit;      /* MIXED: FP32 inner iteration cap per sweep       */
+  int32_t refine_maxit;     /* MIXED: cap on FP64 refinement sweeps            */
+  double fp_tol;            /* nonlinear tolerance (see fp_tol_mode)           */
+  int32_t fp_tol_mode;      /* AFC_TOL_*                                       */
+  int32_t fp_maxit;         /* cap on fixed-point linear solves                */
+  double prelimit;          /* CN prelimiting constant L of eq. (13); 0 = off  */
+  double omega;             /* fixed-point relaxation, (0, 1]                   */
+  int32_t dynamic_damping;  /* 1: halve omega on residual growth, else grow    */
+  int32_t ssp_stages;       /* 3: Shu-Osher SSP-RK3; 2: Heun (paper); 1: one
+                               forward-Euler stage of eq. (18)                 */
+  int32_t lanes_per_row;    /* 0 = automatic; else 8, 16, 32 or 64             */
+  void *stream;             /* hipStream_t; NULL = default stream              */
+} afc_options;
+
+typedef struct {
+  int32_t status;           /* same as the return value                        */
+  int32_t fp_iters;         /* fixed-point linear solves performed             */
+  int64_t krylov_iters;     /* total Krylov iterations (FP64 + FP32 inner)     */
+  int64_t inner_iters;      /* FP32 inner iterations (MIXED)                   */
+  int32_t refine_sweeps;    /* FP64 refinement sweeps (MIXED)                  */
+  double res0;              /* first nonlinear residual norm                   */
+  double res;               /* last nonlinear residual norm                    */
+  double lin_res;           /* last linear true residual norm                  */
+} afc_stats;
+
+/* Fill *opt with defaults: LIMITED, GMRES(30), FP64, lin_atol 1e-12,
+ * lin_rtol 0, lin_maxit 10000, inner_rtol 1e-5, inner_maxit 300,
+ * refine_maxit 50, fp_tol 1e-12 ABS_SQRTN, fp_maxit 50, prelimit 2,
+ * omega 1, no dynamic damping, ssp_stages 3, automatic lanes, NULL stream. */
+void afc_default_options(afc_options *opt);
+
+/* Create a handle: validates the CSR data (EINVAL on a malformed pattern,
+ * non-positive lumped mass, out-of-range Dirichlet index), precomputes the
+ * graph viscosities d+_ij of eq. (5) from K (FCT) and from K_conv (MCL), the
+ * low-order operators A + D of eq. (6) with Dirichlet rows replaced by identity
+ * rows, and the FP32 Jacobi-scaled copies; uploads everything to the current
+ * HIP device.  *out is NULL on failure.  opt may be NULL (defaults). */
+afc_status afc_create(const afc_problem *prob, const afc_options *opt, afc_handle **out);
+
+/* Replace the options of an existing handle (same validation as afc_create). */
+afc_status afc_set_options(afc_handle *h, const afc_options *opt);
+
+/* One explicit time step of length dt (Sec. 2.1.2): forward-Euler stages of
+ * eq. (18), each limited by Zalesak's algorithm (Sec. 2.1.3) with the
+ * predictor of eq. (19) and the fluxes of eqs. (20)-(21); composed as
+ * Shu-Osher SSP-RK3 (ssp_stages = 3), Heun (2) or a single stage (1).
+ * u: in u^{n-1}, out u^n (device).  F: load vector (device), constant in the
+ * step.  stats may be NULL. */
+afc_status afc_step_ssprk3(afc_handle *h, double *u, const double *F, double dt, afc_stats *stats);
+
+/* One Crank-Nicolson FCT step, eq. (11) with fluxes eq. (12), prelimiting
+ * eq. (13) and the predictor eq. (14), solved by the fixed-point iteration of
+ * Sec. 4 with matrix M_L/dt + A_low/2.  u: in u^{n-1}, out u^n (device).
+ * F_old, F_new: load vectors at t_{n-1}, t_n (device).  Returns WMAXIT when
+ * fp_maxit solves did not reach fp_tol (u holds the last iterate). */
+afc_status afc_step_cn(afc_handle *h, double *u, const double *F_old, const double *F_new, double dt,
+                       afc_stats *stats);
+
+/* Stationary MCL scheme (Sec. 3.1): fixed-point iteration of Sec. 4 for
+ * A_low u = F + F*(u), where F* sums the fluxes r^ss_ij = d_ij (u_j - u_i)
+ * of eq. (25) limited by eq. (22).  u: in initial guess, out solution
+ * (device).  If init_low_order is nonzero the guess is first replaced by the
+ * low-order solution A_low u = F.  F: load vector (device). */
+afc_status afc_solve_stationary(afc_handle *h, double *u, const double *F, int32_t init_low_order,
+                                afc_stats *stats);
+
+/* Release every device and host resource of h (NULL is ignored). */
+void afc_destroy(afc_handle *h);
+
+/* Static description of a status code. */
+const char *afc_status_str(int32_t status);
+
+/* Description of the last error on h (empty string if none; h may be NULL). */
+const char *afc_last_error(const afc_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AFC_H_ */

@@ -1,0 +1,591 @@
+"""Plain FP64 CPU oracle of algebraic flux correction (AFC) for CDR equations.
+
+TEST INFRASTRUCTURE.  Only tests/, __graft_entry__.smoke() and the CPU-baseline
+leg of bench.py may import this module.  The GPU library never calls it, and it
+shares no code with the GPU library: both sides only receive the same matrices
+from paper_2110_15676_amd.inputs.
+
+Everything is float64 numpy over the CSR entries (one array element per matrix
+entry k = (i, j)), written in the order and notation of the paper:
+  Jha, Partl, Ahmed, Kuzmin, "An Assessment of Solvers for Algebraically
+  Stabilized Discretizations of Convection-Diffusion-Reaction Equations"
+  (arXiv 2110.15676).
+Section / equation numbers refer to that paper: Sec. 2 (evolutionary CDR,
+eqs. (1)-(23)), Sec. 2.1.1 (Crank-Nicolson FCT, eqs. (11)-(14)), Sec. 2.1.2
+(SSP scheme, eqs. (15)-(21)), Sec. 2.1.3 (Zalesak's limiter), Sec. 2.2 and
+3.1 (monolithic convex limiter, eqs. (22)-(23), Remark 1), Sec. 3 (stationary
+problem, eq. (25)), Sec. 4 (fixed-point iteration and linear-solver stopping
+rules, eq. (28)).
+
+Sign conventions.  The caller passes K = -A, where A is the paper's stiffness
+matrix a_ij of eq. (4) (so M_C du/dt = K u + F).  The oracle works with the
+paper's a_ij = -k_ij and the paper's artificial diffusion d_ij <= 0 of eq. (5).
+
+Readings where the paper is silent or ambiguous (each one is applied the same
+way here and on the GPU):
+  * Q_i^+- (Sec. 2.1.3, step 2) range over the neighbours j in N_i \\ {i}.
+  * prelimiting (eq. (13)) uses the Crank-Nicolson midpoint
+    u = (u^nu + u^{n-1})/2 in L d_ij (u_j - u_i); minmod(a, b) = 0 when ab = 0.
+  * the SSP low-order rate is zero at Dirichlet nodes (time-independent u_D);
+    the predictors are set to u_D there (Sec. 2.1.1).
+  * for the monolithic convex limiter on CDR problems, D is built from the
+    convective operator only (Remark 1); when d_ij = 0 the bar state is
+    undefined and the limited flux is 0.
+  * the fixed-point iteration of Sec. 4 is applied as a relaxation
+    u^{nu+1} = u^nu + omega (w - u^nu), where w solves the fixed-point matrix
+    system with the current correction; omega = 1 by default, optional dynamic
+    rule: halve omega (not below 1/64) when the residual grows, otherwise
+    omega <- min(1, 1.25 omega).
+  * nonlinear residual: Euclidean norm over non-Dirichlet rows, evaluated at
+    u^nu before each solve; stopping either R < sqrt(N) tol (eq. (28)) or
+    R <= tol R_0 (relative form).
+  * linear solves: right Jacobi preconditioning, stopping on the true residual
+    ||b - A x||_2 <= max(atol, rtol ||b||_2) (the paper itself sets rtol = 0).
+  * SSP-RK3 (Shu-Osher) is composed of the forward-Euler stage of eq. (18);
+    the paper's own Heun (SSP-RK2) form is provided too.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+STATUS_OK = 0
+STATUS_WMAXIT = 1
+STATUS_EBREAKDOWN = -4
+
+
+# ----------------------------------------------------------------------------
+# Problem data and the AFC splitting (Sec. 2, eqs. (2)-(10))
+# ----------------------------------------------------------------------------
+
+
+class AFCProblem:
+    """CSR pattern + matrices of one instance, with the AFC splitting helpers."""
+
+    def __init__(self, row_ptr, col, M, K, K_conv=None, ML=None, dir_idx=None, dir_val=None):
+        self.row_ptr = np.asarray(row_ptr, dtype=np.int64)
+        self.col = np.asarray(col, dtype=np.int64)
+        self.N = self.row_ptr.shape[0] - 1
+        N = self.N
+        self.rows = np.repeat(np.arange(N, dtype=np.int64), np.diff(self.row_ptr))
+        self.offd = self.rows != self.col
+        self.m_ij = np.asarray(M, dtype=np.float64)
+        # a_ij of eq. (4): the caller's K is -A
+        self.a = -np.asarray(K, dtype=np.float64)
+        # convective part (eps = 0, c = 0), Remark 1 in Sec. 2.2
+        self.c = self.a if K_conv is None else -np.asarray(K_conv, dtype=np.float64)
+        # position of entry (j, i) for every entry (i, j)
+        keys = self.rows * N + self.col
+        self.tpos = np.searchsorted(keys, self.col * N + self.rows)
+        self.diag_pos = self._diag_positions()
+        self.m = lumped_mass(self) if ML is None else np.asarray(ML, dtype=np.float64)
+        self.is_dir = np.zeros(N, dtype=bool)
+        self.uD = np.zeros(N)
+        if dir_idx is not None and len(dir_idx):
+            di = np.asarray(dir_idx, dtype=np.int64)
+            self.is_dir[di] = True
+            self.uD[di] = np.asarray(dir_val, dtype=np.float64)
+
+    def _diag_positions(self):
+        pos = np.nonzero(~self.offd)[0]
+        assert pos.shape[0] == self.N, "every row must store its diagonal"
+        return pos
+
+    # --- plain CSR helpers -------------------------------------------------
+    def matvec(self, vals, x):
+        return np.bincount(self.rows, weights=vals * x[self.col], minlength=self.N)
+
+    def row_sum(self, vals):
+        return np.bincount(self.rows, weights=vals, minlength=self.N)
+
+    def row_max(self, vals):
+        return np.maximum.reduceat(vals, self.row_ptr[:-1])
+
+    def row_min(self, vals):
+        return np.minimum.reduceat(vals, self.row_ptr[:-1])
+
+    def with_dirichlet_rows(self, vals):
+        """Copy of a matrix whose Dirichlet rows are replaced by identity rows."""
+        out = vals.copy()
+        drow = self.is_dir[self.rows]
+        out[drow] = 0.0
+        out[self.diag_pos[self.is_dir]] = 1.0
+        return out
+
+    def dense(self, vals):
+        A = np.zeros((self.N, self.N))
+        A[self.rows, self.col] = vals
+        return A
+
+
+def lumped_mass(P: AFCProblem) -> np.ndarray:
+    """m_i = sum_j m_ij (Sec. 2, eq. (5))."""
+    return P.row_sum(P.m_ij)
+
+
+def artificial_diffusion(P: AFCProblem, a: np.ndarray) -> np.ndarray:
+    """d_ij = -max{a_ij, 0, a_ji} for i != j, d_ii = -sum_{j != i} d_ij (eq. (5))."""
+    d = -np.maximum(np.maximum(a, 0.0), a[P.tpos])
+    d[~P.offd] = 0.0
+    d[P.diag_pos] = -P.row_sum(d)
+    return d
+
+
+def low_order_operator(P: AFCProblem, a: np.ndarray, d: np.ndarray) -> np.ndarray:
+    """The M-matrix  A_low = A + D of eq. (6)."""
+    return a + d
+
+
+# ----------------------------------------------------------------------------
+# Limiters
+# ----------------------------------------------------------------------------
+
+
+def minmod(a, b):
+    """minmod of eq. (13): 0 if ab <= 0, else the argument of smaller modulus."""
+    out = np.zeros_like(a)
+    both_pos = (a > 0) & (b > 0)
+    both_neg = (a < 0) & (b < 0)
+    out[both_pos] = np.minimum(a[both_pos], b[both_pos])
+    out[both_neg] = np.maximum(a[both_neg], b[both_neg])
+    return out
+
+
+def zalesak_Q(P: AFCProblem, ut: np.ndarray):
+    """Step 2 of Zalesak's limiter (Sec. 2.1.3): Q_i^+- from the low-order predictor."""
+    diff = ut[P.col] - ut[P.rows]
+    Qp = np.maximum(0.0, P.row_max(np.where(P.offd, diff, -np.inf)))
+    Qm = np.minimum(0.0, P.row_min(np.where(P.offd, diff, np.inf)))
+    return Qp, Qm
+
+
+def zalesak_alpha(P: AFCProblem, r: np.ndarray, Qp, Qm, dt: float):
+    """Steps 1, 3 and 4 of Zalesak's limiter (Sec. 2.1.3).
+
+    r holds r_ij for every off-diagonal entry of a non-Dirichlet row (zero
+    elsewhere).  Returns (alpha_ij per entry, R^+, R^-, P^+, P^-)."""
+    Pp = P.row_sum(np.where(P.offd, np.maximum(r, 0.0), 0.0))
+    Pm = P.row_sum(np.where(P.offd, np.minimum(r, 0.0), 0.0))
+    Rp = np.ones(P.N)
+    Rm = np.ones(P.N)
+    nzp = Pp != 0.0
+    nzm = Pm != 0.0
+    Rp[nzp] = np.minimum(1.0, P.m[nzp] * Qp[nzp] / (dt * Pp[nzp]))
+    Rm[nzm] = np.minimum(1.0, P.m[nzm] * Qm[nzm] / (dt * Pm[nzm]))
+    Rp[P.is_dir] = 1.0
+    Rm[P.is_dir] = 1.0
+    i, j = P.rows, P.col
+    alpha = np.where(r > 0.0, np.minimum(Rp[i], Rm[j]), np.minimum(Rm[i], Rp[j]))
+    alpha = np.where(P.offd & ~P.is_dir[i], alpha, 0.0)
+    return alpha, Rp, Rm, Pp, Pm
+
+
+def mcl_limited_fluxes(P: AFCProblem, u: np.ndarray, c: np.ndarray, d: np.ndarray):
+    """Monolithic convex limiting of r_ij = d_ij (u_j - u_i) (eqs. (22), (23), (25)).
+
+    Bar states 2 d_ij ubar_ij = d_ij (u_i + u_j) + c_ij (u_j - u_i), with c the
+    convective a_ij (Remark 1); u_i^max/min over N_i including i.  Returns
+    r*_ij per entry (zero on the diagonal and on Dirichlet rows)."""
+    i, j = P.rows, P.col
+    umax = P.row_max(u[j])
+    umin = P.row_min(u[j])
+    r = d * (u[j] - u[i])
+    S_ij = d * (u[i] + u[j]) + c * (u[j] - u[i])  # 2 d_ij ubar_ij
+    S_ji = d * (u[i] + u[j]) + c[P.tpos] * (u[i] - u[j])  # 2 d_ji ubar_ji
+    two_d = 2.0 * d
+    lim_pos = np.minimum(r, np.minimum(S_ij - two_d * umax[i], two_d * umin[j] - S_ji))
+    lim_neg = np.maximum(r, np.maximum(S_ij - two_d * umin[i], two_d * umax[j] - S_ji))
+    rstar = np.where(r > 0.0, lim_pos, lim_neg)
+    rstar = np.where(P.offd & ~P.is_dir[i] & (d != 0.0), rstar, 0.0)
+    return rstar, umax, umin
+
+
+# ----------------------------------------------------------------------------
+# Explicit SSP scheme (Sec. 2.1.2)
+# ----------------------------------------------------------------------------
+
+
+@dataclass
+class StageInfo:
+    ut: np.ndarray
+    udot: np.ndarray
+    r: np.ndarray
+    alpha: np.ndarray
+    Fstar: np.ndarray
+    Qp: np.ndarray
+    Qm: np.ndarray
+
+
+def fe_ssp_stage(P: AFCProblem, u, F, dt, alpha_mode="limited", info=False):
+    """One forward-Euler update u_new = u + dt M_L^{-1} (F + F*(u) - A_low u), eq. (18),
+    limited with Zalesak's algorithm using the predictor of eq. (19) and the
+    fluxes of eqs. (20)-(21)."""
+    d = artificial_diffusion(P, P.a)
+    AL = low_order_operator(P, P.a, d)
+    udot = (F - P.matvec(AL, u)) / P.m  # eq. (21)
+    udot[P.is_dir] = 0.0
+    ut = u + dt * udot  # eq. (19)
+    ut[P.is_dir] = P.uD[P.is_dir]
+    i, j = P.rows, P.col
+    r = P.m_ij * (udot[i] - udot[j]) + d * (u[j] - u[i])  # eq. (20)
+    r = np.where(P.offd & ~P.is_dir[i], r, 0.0)
+    Qp, Qm = zalesak_Q(P, ut)
+    if alpha_mode == "limited":
+        alpha = zalesak_alpha(P, r, Qp, Qm, dt)[0]
+    elif alpha_mode == "one":
+        alpha = np.where(r != 0.0, 1.0, 0.0)
+    elif alpha_mode == "zero":
+        alpha = np.zeros_like(r)
+    else:
+        raise ValueError(alpha_mode)
+    Fstar = P.row_sum(alpha * r)  # eq. (10)
+    unew = ut + dt * Fstar / P.m
+    unew[P.is_dir] = P.uD[P.is_dir]
+    if info:
+        return unew, StageInfo(ut, udot, r, alpha, Fstar, Qp, Qm)
+    return unew
+
+
+def ssp_rk3_step(P: AFCProblem, u, F, dt, alpha_mode="limited"):
+    """Shu-Osher SSP-RK3 composed of three stages of eq. (18)."""
+    u1 = fe_ssp_stage(P, u, F, dt, alpha_mode)
+    u2 = 0.75 * u + 0.25 * fe_ssp_stage(P, u1, F, dt, alpha_mode)
+    return (1.0 / 3.0) * u + (2.0 / 3.0) * fe_ssp_stage(P, u2, F, dt, alpha_mode)
+
+
+def ssp_rk2_step(P: AFCProblem, u, F, dt, alpha_mode="limited"):
+    """Heun's method of Sec. 2.1.2: u^n = (u^{n,0} + u^{n,2}) / 2."""
+    u1 = fe_ssp_stage(P, u, F, dt, alpha_mode)
+    u2 = fe_ssp_stage(P, u1, F, dt, alpha_mode)
+    return 0.5 * (u + u2)
+
+
+# ----------------------------------------------------------------------------
+# Krylov solvers with Jacobi preconditioning (Sec. 4, solver and PC tables)
+# ----------------------------------------------------------------------------
+
+
+@dataclass
+class KrylovResult:
+    x: np.ndarray
+    iters: int
+    res: float
+    res0: float
+    status: int
+
+
+def _true_res(P, A, b, x):
+    return float(np.linalg.norm(b - P.matvec(A, x)))
+
+
+def bicgstab(P: AFCProblem, A, b, x0, atol=0.0, rtol=0.0, maxit=10000):
+    """BiCGStab (van der Vorst) with right Jacobi preconditioning."""
+    dinv = 1.0 / A[P.diag_pos]
+    x = x0.copy()
+    r = b - P.matvec(A, x)
+    res0 = float(np.linalg.norm(r))
+    tol = max(atol, rtol * float(np.linalg.norm(b)))
+    if res0 <= tol:
+        return KrylovResult(x, 0, res0, res0, STATUS_OK)
+    it = 0
+    restarts = 0
+    while it < maxit:
+        rhat = r.copy()
+        rho = alpha = omega = 1.0
+        v = np.zeros_like(x)
+        p = np.zeros_like(x)
+        breakdown = False
+        while it < maxit:
+            rho_new = float(rhat @ r)
+            if rho_new == 0.0:
+                breakdown = True
+                break
+            beta = (rho_new / rho) * (alpha / omega)
+            p = r + beta * (p - omega * v)
+            phat = dinv * p
+            v = P.matvec(A, phat)
+            rv = float(rhat @ v)
+            if rv == 0.0:
+                breakdown = True
+                break
+            alpha = rho_new / rv
+            s = r - alpha * v
+            it += 1
+            if float(np.linalg.norm(s)) <= tol:
+                x = x + alpha * phat
+                r = s
+                break
+            shat = dinv * s
+            t = P.matvec(A, shat)
+            tt = float(t @ t)
+            omega = float(t @ s) / tt if tt != 0.0 else 0.0
+            x = x + alpha * phat + omega * shat
+            r = s - omega * t
+            rho = rho_new
+            if omega == 0.0:
+                breakdown = True
+                break
+            if float(np.linalg.norm(r)) <= tol:
+                break
+        true = _true_res(P, A, b, x)
+        if true <= tol:
+            return KrylovResult(x, it, true, res0, STATUS_OK)
+        if breakdown:
+            restarts += 1
+            if restarts > 1:
+                return KrylovResult(x, it, true, res0, STATUS_EBREAKDOWN)
+        r = b - P.matvec(A, x)
+    return KrylovResult(x, it, _true_res(P, A, b, x), res0, STATUS_WMAXIT)
+
+
+def gmres(P: AFCProblem, A, b, x0, restart=30, atol=0.0, rtol=0.0, maxit=10000):
+    """Restarted GMRES(m) with right Jacobi preconditioning (modified Gram-Schmidt,
+    Givens rotations); cycles end early when the residual estimate meets tol,
+    and convergence is confirmed on the true residual."""
+    dinv = 1.0 / A[P.diag_pos]
+    x = x0.copy()
+    r = b - P.matvec(A, x)
+    beta = float(np.linalg.norm(r))
+    res0 = beta
+    tol = max(atol, rtol * float(np.linalg.norm(b)))
+    it = 0
+    while True:
+        if beta <= tol:
+            return KrylovResult(x, it, beta, res0, STATUS_OK)
+        if it >= maxit:
+            return KrylovResult(x, it, beta, res0, STATUS_WMAXIT)
+        m = restart
+        V = np.zeros((m + 1, P.N))
+        H = np.zeros((m + 1, m))
+        cs = np.zeros(m)
+        sn = np.zeros(m)
+        g = np.zeros(m + 1)
+        V[0] = r / beta
+        g[0] = beta
+        k_used = 0
+        for k in range(m):
+            w = P.matvec(A, dinv * V[k])
+            for jj in range(k + 1):
+                H[jj, k] = float(V[jj] @ w)
+                w = w - H[jj, k] * V[jj]
+            H[k + 1, k] = float(np.linalg.norm(w))
+            if H[k + 1, k] != 0.0:
+                V[k + 1] = w / H[k + 1, k]
+            for jj in range(k):
+                t = cs[jj] * H[jj, k] + sn[jj] * H[jj + 1, k]
+                H[jj + 1, k] = -sn[jj] * H[jj, k] + cs[jj] * H[jj + 1, k]
+                H[jj, k] = t
+            den = math.hypot(H[k, k], H[k + 1, k])
+            cs[k] = H[k, k] / den
+            sn[k] = H[k + 1, k] / den
+            H[k, k] = den
+            H[k + 1, k] = 0.0
+            g[k + 1] = -sn[k] * g[k]
+            g[k] = cs[k] * g[k]
+            it += 1
+            k_used = k + 1
+            if abs(g[k + 1]) <= tol or it >= maxit or H[k, k] == 0.0:
+                break
+        y = np.linalg.solve(np.triu(H[:k_used, :k_used]), g[:k_used]) if k_used else np.zeros(0)
+        x = x + dinv * (V[:k_used].T @ y)
+        r = b - P.matvec(A, x)
+        beta = float(np.linalg.norm(r))
+
+
+def krylov(P, A, b, x0, method, atol, rtol, maxit, restart=30):
+    if method == "bicgstab":
+        return bicgstab(P, A, b, x0, atol=atol, rtol=rtol, maxit=maxit)
+    if method == "gmres":
+        return gmres(P, A, b, x0, restart=restart, atol=atol, rtol=rtol, maxit=maxit)
+    raise ValueError(method)
+
+
+# ----------------------------------------------------------------------------
+# Fixed-point iteration (Sec. 4) -- shared control logic of the implicit schemes
+# ----------------------------------------------------------------------------
+
+
+@dataclass
+class FixedPointStats:
+    iters: int = 0
+    krylov_iters: list = field(default_factory=list)
+    residuals: list = field(default_factory=list)
+    status: int = STATUS_OK
+
+
+def _fp_converged(R, R0, N, tol, tol_mode):
+    if tol_mode == "abs":
+        return R < math.sqrt(N) * tol  # eq. (28)
+    return R <= tol * R0
+
+
+def _next_omega(omega, R, R_prev, dynamic):
+    if not dynamic or R_prev is None:
+        return omega
+    if R > R_prev:
+        return max(omega * 0.5, 1.0 / 64.0)
+    return min(1.0, omega * 1.25)
+
+
+# ----------------------------------------------------------------------------
+# Crank-Nicolson FCT (Sec. 2.1.1), nonlinear form solved by fixed point
+# ----------------------------------------------------------------------------
+
+
+def cn_predictor(P: AFCProblem, u_old, F_old, dt):
+    """Low-order predictor of eq. (14): forward Euler for eq. (6) with step dt/2,
+    constrained to u_D at Dirichlet nodes."""
+    d = artificial_diffusion(P, P.a)
+    AL = low_order_operator(P, P.a, d)
+    ut = u_old - 0.5 * dt * (P.matvec(AL, u_old) - F_old) / P.m
+    ut[P.is_dir] = P.uD[P.is_dir]
+    return ut
+
+
+def cn_fluxes(P: AFCProblem, u, u_old, d, dt, prelimit):
+    """Antidiffusive CN fluxes r_ij of eq. (12), prelimited by eq. (13) when
+    prelimit = L > 0 (midpoint reading of u); zero on the diagonal and on
+    Dirichlet rows."""
+    i, j = P.rows, P.col
+    du = u - u_old
+    su = u + u_old
+    r = P.m_ij / dt * (du[i] - du[j]) + 0.5 * d * (su[j] - su[i])
+    if prelimit:
+        ubar = 0.5 * su
+        r = minmod(r, prelimit * d * (ubar[j] - ubar[i]))
+    return np.where(P.offd & ~P.is_dir[i], r, 0.0)
+
+
+def cn_fct_step(P: AFCProblem, u_old, F_old, F_new, dt, *, alpha_mode="limited", prelimit=2.0,
+                tol=1e-12, tol_mode="abs", maxit=50, lin="bicgstab", lin_atol=1e-12, lin_rtol=0.0,
+                lin_maxit=10000, omega=1.0, dynamic_damping=False, restart=30):
+    """One step of eq. (11) with the fluxes of eq. (12), prelimiting eq. (13) and
+    Zalesak's limiter with the predictor of eq. (14).  Returns (u^n, stats)."""
+    d = artificial_diffusion(P, P.a)
+    AL = low_order_operator(P, P.a, d)
+    y = P.matvec(AL, u_old)
+    ut = cn_predictor(P, u_old, F_old, dt)
+    Qp, Qm = zalesak_Q(P, ut)
+    g = P.m / dt * u_old - 0.5 * y + 0.5 * (F_old + F_new)  # right-hand side of eq. (11)
+    g[P.is_dir] = P.uD[P.is_dir]
+    Acn = 0.5 * AL
+    Acn[P.diag_pos] += P.m / dt
+    Acn = P.with_dirichlet_rows(Acn)
+    i, j = P.rows, P.col
+    u = u_old.copy()
+    u[P.is_dir] = P.uD[P.is_dir]
+    st = FixedPointStats()
+    R0 = None
+    R_prev = None
+    w_omega = omega
+    nu = 0
+    while True:
+        r = cn_fluxes(P, u, u_old, d, dt, prelimit)
+        if alpha_mode == "limited":
+            alpha = zalesak_alpha(P, r, Qp, Qm, dt)[0]
+        elif alpha_mode == "one":
+            alpha = np.where(r != 0.0, 1.0, 0.0)
+        else:
+            alpha = np.zeros_like(r)
+        b = g + P.row_sum(alpha * r)
+        b[P.is_dir] = P.uD[P.is_dir]
+        res = b - P.matvec(Acn, u)
+        R = float(np.linalg.norm(res[~P.is_dir]))
+        if R0 is None:
+            R0 = R
+        st.residuals.append(R)
+        if R == 0.0 or _fp_converged(R, R0, P.N, tol, tol_mode):
+            break
+        if nu >= maxit:
+            st.status = STATUS_WMAXIT
+            break
+        w_omega = _next_omega(w_omega, R, R_prev, dynamic_damping)
+        kr = krylov(P, Acn, b, u, lin, lin_atol, lin_rtol, lin_maxit, restart)
+        st.krylov_iters.append(kr.iters)
+        if kr.status < 0:
+            st.status = kr.status
+            u = kr.x
+            break
+        u = u + w_omega * (kr.x - u)
+        R_prev = R
+        nu += 1
+    st.iters = nu
+    return u, st
+
+
+# ----------------------------------------------------------------------------
+# Stationary problem with the monolithic convex limiter (Sec. 3.1, Sec. 4)
+# ----------------------------------------------------------------------------
+
+
+def stationary_matrix(P: AFCProblem):
+    """(d^conv, A_low with Dirichlet identity rows) of the stationary MCL scheme."""
+    d = artificial_diffusion(P, P.c)
+    AL = low_order_operator(P, P.a, d)
+    return d, P.with_dirichlet_rows(AL)
+
+
+def low_order_solution(P: AFCProblem, F, *, lin="gmres", lin_atol=0.0, lin_rtol=1e-12, lin_maxit=20000,
+                       restart=30):
+    """Solution of A_low u = F (the alpha = 0 scheme), from the zero vector."""
+    d, As = stationary_matrix(P)
+    b = F.copy()
+    b[P.is_dir] = P.uD[P.is_dir]
+    x0 = np.zeros(P.N)
+    x0[P.is_dir] = P.uD[P.is_dir]
+    return krylov(P, As, b, x0, lin, lin_atol, lin_rtol, lin_maxit, restart)
+
+
+def stationary_mcl(P: AFCProblem, F, u0, *, alpha_mode="limited", tol=1e-8, tol_mode="rel", maxit=500,
+                   lin="gmres", lin_atol=0.0, lin_rtol=1e-10, lin_maxit=20000, restart=30, omega=1.0,
+                   dynamic_damping=False):
+    """Fixed-point iteration for A_low u = F + F*(u) (Sec. 4) with F* from the
+    monolithic convex limiter applied to r^ss_ij = d_ij (u_j - u_i) (Sec. 3.1)."""
+    d, As = stationary_matrix(P)
+    u = np.asarray(u0, dtype=np.float64).copy()
+    u[P.is_dir] = P.uD[P.is_dir]
+    st = FixedPointStats()
+    R0 = None
+    R_prev = None
+    w_omega = omega
+    nu = 0
+    while True:
+        if alpha_mode == "limited":
+            rstar = mcl_limited_fluxes(P, u, P.c, d)[0]
+        elif alpha_mode == "one":
+            i, j = P.rows, P.col
+            rstar = np.where(P.offd & ~P.is_dir[i], d * (u[j] - u[i]), 0.0)
+        else:
+            rstar = np.zeros_like(d)
+        b = F + P.row_sum(rstar)
+        b[P.is_dir] = P.uD[P.is_dir]
+        res = b - P.matvec(As, u)
+        R = float(np.linalg.norm(res[~P.is_dir]))
+        if R0 is None:
+            R0 = R
+        st.residuals.append(R)
+        if R == 0.0 or _fp_converged(R, R0, P.N, tol, tol_mode):
+            break
+        if nu >= maxit:
+            st.status = STATUS_WMAXIT
+            break
+        w_omega = _next_omega(w_omega, R, R_prev, dynamic_damping)
+        kr = krylov(P, As, b, u, lin, lin_atol, lin_rtol, lin_maxit, restart)
+        st.krylov_iters.append(kr.iters)
+        if kr.status < 0:
+            st.status = kr.status
+            u = kr.x
+            break
+        u = u + w_omega * (kr.x - u)
+        R_prev = R
+        nu += 1
+    st.iters = nu
+    return u, st
+
+
+def problem_from_instance(inst, conv=True) -> AFCProblem:
+    """AFCProblem of an inputs.Instance (K_conv passed when conv is True)."""
+    return AFCProblem(inst.row_ptr, inst.col, inst.M, inst.K, inst.K_conv if conv else None, None,
+                      inst.dir_idx, inst.dir_val)

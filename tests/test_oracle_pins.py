@@ -1,0 +1,390 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: values worked
+by hand from the limiter's definition, dense direct solves of the Galerkin and
+low-order systems (alpha = 1 / alpha = 0, Sec. 2 eq. (10)), closed forms,
+conservation, local bounds, and a brute-force edge-list coding.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import afc_oracle as O
+from paper_2110_15676_amd import inputs as I
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _chain3(dirichlet=False):
+    g = json.load(open(os.path.join(GOLDEN, "zalesak_chain3.json")))
+    rp = np.array(g["pattern"]["row_ptr"])
+    col = np.array(g["pattern"]["col"])
+    nnz = col.shape[0]
+    P = O.AFCProblem(rp, col, np.zeros(nnz), np.zeros(nnz), None, np.array(g["m"]),
+                     [2] if dirichlet else None, [0.0] if dirichlet else None)
+    r = np.zeros(nnz)
+    for key, v in g["r_offdiag"].items():
+        i, j = map(int, key.split(","))
+        if dirichlet and i == 2:
+            continue
+        k = rp[i] + list(col[rp[i]:rp[i + 1]]).index(j)
+        r[k] = v
+    return g, P, r
+
+
+def test_minmod_truth_table():
+    # eq. (13): 0 if ab < 0; min if both > 0; max if both < 0; (ab = 0 -> 0, reading)
+    a = np.array([1.0, 3.0, -1.0, -3.0, 1.0, -1.0, 0.0, 2.0, 0.0])
+    b = np.array([3.0, 1.0, -3.0, -1.0, -1.0, 1.0, 5.0, 0.0, 0.0])
+    exp = np.array([1.0, 1.0, -1.0, -1.0, 0.0, 0.0, 0.0, 0.0, 0.0])
+    assert np.array_equal(O.minmod(a, b), exp)
+
+
+@pytest.mark.parametrize("dirichlet", [False, True])
+def test_zalesak_hand_worked_chain(dirichlet):
+    g, P, r = _chain3(dirichlet)
+    ut = np.array(g["u_tilde"])
+    Qp, Qm = O.zalesak_Q(P, ut)
+    alpha, Rp, Rm, Pp, Pm = O.zalesak_alpha(P, r, Qp, Qm, g["dt"])
+    np.testing.assert_allclose(Qp, g["Q_plus"], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(Qm, g["Q_minus"], rtol=0, atol=1e-15)
+    ref = g["dirichlet_variant"] if dirichlet else g
+    np.testing.assert_allclose(Rp, ref["R_plus"], rtol=1e-14)
+    np.testing.assert_allclose(Rm, ref["R_minus"], rtol=1e-14)
+    Fs = P.row_sum(alpha * r)
+    np.testing.assert_allclose(Fs, ref["F_star"], rtol=1e-14, atol=1e-16)
+    if not dirichlet:
+        np.testing.assert_allclose(Pp, g["P_plus"], rtol=1e-15)
+        np.testing.assert_allclose(Pm, g["P_minus"], rtol=1e-15)
+        for key, v in g["alpha_offdiag"].items():
+            i, j = map(int, key.split(","))
+            k = P.row_ptr[i] + list(P.col[P.row_ptr[i]:P.row_ptr[i + 1]]).index(j)
+            assert alpha[k] == pytest.approx(v, rel=1e-14)
+
+
+def _zalesak_edge_list(P, r, ut, dt):
+    """Brute-force coding of Sec. 2.1.3 with explicit loops over (i, j) pairs."""
+    N = P.N
+    nbrs = [list(P.col[P.row_ptr[i]:P.row_ptr[i + 1]]) for i in range(N)]
+    rij = {}
+    for i in range(N):
+        for k in range(P.row_ptr[i], P.row_ptr[i + 1]):
+            rij[(i, int(P.col[k]))] = r[k]
+    Pp = [0.0] * N
+    Pm = [0.0] * N
+    Qp = [0.0] * N
+    Qm = [0.0] * N
+    for i in range(N):
+        for j in nbrs[i]:
+            if j == i:
+                continue
+            Pp[i] += max(rij[(i, j)], 0.0)
+            Pm[i] += min(rij[(i, j)], 0.0)
+            Qp[i] = max(Qp[i], ut[j] - ut[i])
+            Qm[i] = min(Qm[i], ut[j] - ut[i])
+    Rp = [1.0 if (Pp[i] == 0 or P.is_dir[i]) else min(1.0, P.m[i] * Qp[i] / (dt * Pp[i])) for i in range(N)]
+    Rm = [1.0 if (Pm[i] == 0 or P.is_dir[i]) else min(1.0, P.m[i] * Qm[i] / (dt * Pm[i])) for i in range(N)]
+    Fs = np.zeros(N)
+    for i in range(N):
+        if P.is_dir[i]:
+            continue
+        for j in nbrs[i]:
+            if j == i:
+                continue
+            rr = rij[(i, j)]
+            a = min(Rp[i], Rm[j]) if rr > 0 else min(Rm[i], Rp[j])
+            Fs[i] += a * rr
+    return Fs
+
+
+def test_zalesak_row_coding_matches_edge_list():
+    inst = I.build("Q1", 3, 1e-3, I.ROTATING_B, 0.0, dirichlet="inflow",
+                   u0_fn=lambda X: (np.linalg.norm(X - 0.4, axis=1) < 0.35).astype(float))
+    P = O.problem_from_instance(inst, conv=False)
+    dt = 0.05
+    unew, info = O.fe_ssp_stage(P, inst.u0, inst.F, dt, info=True)
+    Fs_brute = _zalesak_edge_list(P, info.r, info.ut, dt)
+    np.testing.assert_allclose(info.Fstar, Fs_brute, rtol=1e-14, atol=1e-17)
+
+
+def _dense_ops(inst):
+    M = np.zeros((inst.N, inst.N))
+    A = np.zeros((inst.N, inst.N))
+    rows = inst.row_index()
+    M[rows, inst.col] = inst.M
+    A[rows, inst.col] = -inst.K
+    return M, A
+
+
+def test_artificial_diffusion_properties():
+    # eq. (5): D symmetric, zero row sums, A + D has non-positive off-diagonals (eq. (6))
+    inst = I.build("P1", 3, 1e-3, I.affine_field([1.0, -0.5, 0.25]), 0.5, dirichlet="none")
+    P = O.problem_from_instance(inst, conv=False)
+    d = O.artificial_diffusion(P, P.a)
+    assert np.array_equal(d, d[P.tpos])
+    assert np.max(np.abs(P.row_sum(d))) < 1e-15
+    AL = O.low_order_operator(P, P.a, d)
+    assert np.all(AL[P.offd] <= 0.0)
+    # pure diffusion on non-obtuse Kuhn tetrahedra is already an M-matrix: D = 0
+    inst2 = I.build("P1", 3, 1.0, I.affine_field([0.0, 0.0, 0.0]), 0.0, dirichlet="none")
+    P2 = O.problem_from_instance(inst2, conv=False)
+    assert np.all(O.artificial_diffusion(P2, P2.a) == 0.0)
+    # pure convection with constant b: on interior pairs a_ji = -a_ij, so d_ij = -|a_ij|
+    inst3 = I.build("Q1", 3, 0.0, I.affine_field([1.0, 0.5, 0.25]), 0.0, dirichlet="none")
+    P3 = O.problem_from_instance(inst3, conv=False)
+    d3 = O.artificial_diffusion(P3, P3.a)
+    inner = P3.offd & np.isclose(P3.a[P3.tpos], -P3.a)
+    np.testing.assert_array_equal(d3[inner], -np.abs(P3.a[inner]))
+
+
+@pytest.mark.parametrize("elem", ["P1", "Q1"])
+def test_ssp_stage_alpha_one_and_zero_closed_forms(elem):
+    # alpha = 1: F* = (M_L - M_C) udot + D u, so u_new = u + dt M_L^-1 (F - A u + (M_L - M_C) udot)
+    inst = I.build(elem, 3, 1e-2, I.ROTATING_B, 0.3, dirichlet="none",
+                   u0_fn=lambda X: np.sin(3 * X[:, 0]) + X[:, 1] * X[:, 2])
+    F = np.linspace(-1, 1, inst.N)
+    P = O.problem_from_instance(inst, conv=False)
+    Md, Ad = _dense_ops(inst)
+    mL = Md.sum(axis=1)
+    dt = 0.01
+    u = inst.u0
+    unew1, info = O.fe_ssp_stage(P, u, F, dt, alpha_mode="one", info=True)
+    udot = info.udot
+    closed = u + dt * (F - Ad @ u + mL * udot - Md @ udot) / mL
+    np.testing.assert_allclose(unew1, closed, rtol=1e-12, atol=1e-14)
+    # alpha = 0: the low-order predictor itself
+    unew0 = O.fe_ssp_stage(P, u, F, dt, alpha_mode="zero")
+    np.testing.assert_array_equal(unew0, info.ut)
+
+
+@pytest.mark.parametrize("elem", ["P1", "Q1"])
+@pytest.mark.parametrize("lin", ["bicgstab", "gmres"])
+def test_cn_alpha_one_is_cn_galerkin_and_zero_is_low_order(elem, lin):
+    inst = I.build(elem, 4, 0.05, I.affine_field([1.0, -0.5, 0.25]), 0.5, dirichlet="inflow",
+                   u0_fn=lambda X: np.exp(-20 * np.sum((X - 0.4) ** 2, axis=1)))
+    P = O.problem_from_instance(inst, conv=False)
+    Md, Ad = _dense_ops(inst)
+    dt = 0.02
+    Fo = np.full(inst.N, 0.1)
+    Fn = np.full(inst.N, 0.3)
+    u = inst.u0
+    dirs = inst.dir_idx
+    # CN-Galerkin (M_C/dt + A/2) u^n = (M_C/dt - A/2) u^{n-1} + (F^n + F^{n-1})/2
+    L = Md / dt + 0.5 * Ad
+    rhs = (Md / dt - 0.5 * Ad) @ u + 0.5 * (Fo + Fn)
+    L[dirs, :] = 0.0
+    L[dirs, dirs] = 1.0
+    rhs[dirs] = inst.dir_val
+    ref1 = np.linalg.solve(L, rhs)
+    u1, st = O.cn_fct_step(P, u, Fo, Fn, dt, alpha_mode="one", prelimit=0.0, tol=1e-13, tol_mode="rel",
+                           maxit=1000, lin=lin, lin_atol=0.0, lin_rtol=1e-15)
+    assert st.status == O.STATUS_OK
+    # the fixed point is reached to ~1e-13 R_0; a dropped or mis-signed term would be O(1) off
+    np.testing.assert_allclose(u1, ref1, rtol=0, atol=1e-10 * np.abs(ref1).max())
+    # alpha = 0: (M_L/dt + A_low/2) u^n = (M_L/dt - A_low/2) u^{n-1} + (F^n + F^{n-1})/2
+    mL = Md.sum(axis=1)
+    Dd = np.zeros_like(Ad)
+    for i in range(inst.N):
+        for j in range(inst.N):
+            if i != j and Md[i, j] != 0.0:
+                Dd[i, j] = -max(Ad[i, j], 0.0, Ad[j, i])
+        Dd[i, i] = -Dd[i].sum()
+    AL = Ad + Dd
+    L0 = np.diag(mL) / dt + 0.5 * AL
+    rhs0 = (np.diag(mL) / dt - 0.5 * AL) @ u + 0.5 * (Fo + Fn)
+    L0[dirs, :] = 0.0
+    L0[dirs, dirs] = 1.0
+    rhs0[dirs] = inst.dir_val
+    ref0 = np.linalg.solve(L0, rhs0)
+    u0, st0 = O.cn_fct_step(P, u, Fo, Fn, dt, alpha_mode="zero", tol=1e-15, tol_mode="rel", maxit=5,
+                            lin=lin, lin_atol=0.0, lin_rtol=1e-15)
+    np.testing.assert_allclose(u0, ref0, rtol=0, atol=1e-12 * np.abs(ref0).max())
+
+
+@pytest.mark.parametrize("elem", ["P1", "Q1"])
+def test_stationary_alpha_one_is_galerkin_zero_is_low_order(elem):
+    # MCL scheme with r*_ij = r_ij reduces to A u = F; with r* = 0 to A_low u = F
+    inst = I.build(elem, 4, 0.1, I.affine_field([1.0, 0.5, 0.25]), 1.0, load=("box", [0.25] * 3, [0.75] * 3),
+                   dirichlet="all", dir_fn=lambda X: X[:, 0])
+    P = O.problem_from_instance(inst, conv=True)
+    Md, Ad = _dense_ops(inst)
+    dirs = inst.dir_idx
+    L = Ad.copy()
+    L[dirs, :] = 0.0
+    L[dirs, dirs] = 1.0
+    rhs = inst.F.copy()
+    rhs[dirs] = inst.dir_val
+    ref = np.linalg.solve(L, rhs)
+    u, st = O.stationary_mcl(P, inst.F, np.zeros(inst.N), alpha_mode="one", tol=1e-12, tol_mode="rel",
+                             maxit=500, lin_rtol=1e-15)
+    assert st.status == O.STATUS_OK
+    np.testing.assert_allclose(u, ref, rtol=0, atol=1e-10 * np.abs(ref).max())
+    # low order: D from the convective part only (Remark 1)
+    C = np.zeros_like(Ad)
+    C[inst.row_index(), inst.col] = -inst.K_conv
+    Dc = np.zeros_like(Ad)
+    for i in range(inst.N):
+        for j in range(inst.N):
+            if i != j and Md[i, j] != 0.0:
+                Dc[i, j] = -max(C[i, j], 0.0, C[j, i])
+        Dc[i, i] = -Dc[i].sum()
+    L0 = Ad + Dc
+    L0[dirs, :] = 0.0
+    L0[dirs, dirs] = 1.0
+    ref0 = np.linalg.solve(L0, rhs)
+    u0, _ = O.stationary_mcl(P, inst.F, np.zeros(inst.N), alpha_mode="zero", tol=1e-14, tol_mode="rel",
+                             maxit=3, lin_rtol=1e-15)
+    np.testing.assert_allclose(u0, ref0, rtol=0, atol=1e-11 * np.abs(ref0).max())
+
+
+@pytest.mark.parametrize("lin,restart", [("bicgstab", 30), ("gmres", 30), ("gmres", 5)])
+def test_krylov_matches_dense_solve(lin, restart):
+    inst = I.build("Q1", 4, 1e-3, I.ROTATING_B, 0.2, dirichlet="inflow")
+    P = O.problem_from_instance(inst, conv=False)
+    d = O.artificial_diffusion(P, P.a)
+    A = P.with_dirichlet_rows(O.low_order_operator(P, P.a, d))
+    A[P.diag_pos] += P.m / 0.01
+    b = np.cos(np.arange(inst.N))
+    ref = np.linalg.solve(P.dense(A), b)
+    kr = O.krylov(P, A, b, np.zeros(inst.N), lin, atol=1e-13, rtol=0.0, maxit=5000, restart=restart)
+    assert kr.status == O.STATUS_OK
+    assert kr.iters <= 100  # a well-conditioned 125-unknown system; far fewer than a broken method needs
+    assert kr.res <= 1e-13
+    np.testing.assert_allclose(kr.x, ref, rtol=0, atol=1e-11)
+
+
+def test_ssp_invariants_bounds_symmetry_conservation():
+    inst = I.config2(12)
+    P = O.problem_from_instance(inst, conv=False)
+    dt = inst.params["dt"]
+    u = inst.u0.copy()
+    ulp = np.finfo(float).eps
+    for _ in range(6):
+        unew, info = O.fe_ssp_stage(P, u, inst.F, dt, info=True)
+        a = info.alpha
+        assert a.min() >= 0.0 and a.max() <= 1.0
+        nz = (info.r != 0) & P.offd & ~P.is_dir[P.rows] & ~P.is_dir[P.col]
+        np.testing.assert_array_equal(a[nz], a[P.tpos][nz])
+        np.testing.assert_array_equal(info.r[nz], -info.r[P.tpos][nz])
+        flux = a * info.r
+        both = ~P.is_dir[P.rows] & ~P.is_dir[P.col]
+        assert abs(flux[both].sum()) <= 1e-14 * np.abs(flux).sum() + 1e-300
+        lo = P.row_min(info.ut[P.col])
+        hi = P.row_max(info.ut[P.col])
+        tol = 4 * ulp * np.maximum(1.0, np.abs(info.ut))
+        assert np.all(unew >= lo - tol) and np.all(unew <= hi + tol)
+        u = unew
+
+
+def test_cn_predictor_is_half_step_forward_euler_and_bounded():
+    # Sec. 2.1.1: u~ is the forward-Euler solution of eq. (6) at t_{n-1/2} (step dt/2); the
+    # remark after eq. (14): bound preserving under a CFL-like condition (F = 0 here)
+    inst = I.config1(6)
+    P = O.problem_from_instance(inst, conv=False)
+    rng = np.random.default_rng(3)
+    u = rng.uniform(0.0, 1.0, inst.N)
+    u[P.is_dir] = 0.0
+    dt = 1e-3
+    ut = O.cn_predictor(P, u, inst.F, dt)
+    half = O.fe_ssp_stage(P, u, inst.F, 0.5 * dt, alpha_mode="zero")
+    np.testing.assert_allclose(ut, half, rtol=1e-15, atol=1e-17)
+    assert ut.min() >= -1e-15 and ut.max() <= 1.0 + 1e-15
+    # and it is not the full step
+    full = O.fe_ssp_stage(P, u, inst.F, dt, alpha_mode="zero")
+    assert np.abs(full - ut).max() > 1e-6
+
+
+def test_cn_predictor_bounds_hold_for_limited_correction():
+    inst = I.config1(6)
+    P = O.problem_from_instance(inst, conv=False)
+    dt = 1e-3
+    u = inst.u0
+    # pieces of one CN iteration: u~ + dt F*/m lies in [u~ + Q-, u~ + Q+] (Sec. 2.1.3)
+    d = O.artificial_diffusion(P, P.a)
+    ut = O.cn_predictor(P, u, inst.F, dt)
+    Qp, Qm = O.zalesak_Q(P, ut)
+    unu, _ = O.cn_fct_step(P, u, inst.F, inst.F, dt, maxit=3)
+    r = O.cn_fluxes(P, unu, u, d, dt, 2.0)
+    # antisymmetric on pairs of free nodes (eqs. (12), (13))
+    both = P.offd & ~P.is_dir[P.rows] & ~P.is_dir[P.col]
+    np.testing.assert_array_equal(r[both], -r[P.tpos][both])
+    alpha = O.zalesak_alpha(P, r, Qp, Qm, dt)[0]
+    Fs = P.row_sum(alpha * r)
+    val = ut + dt * Fs / P.m
+    tol = 4 * np.finfo(float).eps
+    free = ~P.is_dir
+    assert np.all(val[free] >= (ut + Qm)[free] - tol)
+    assert np.all(val[free] <= (ut + Qp)[free] + tol)
+
+
+def test_mcl_antisymmetry_and_edge_clip():
+    inst = I.config3(6)
+    P = O.problem_from_instance(inst, conv=True)
+    rng = np.random.default_rng(7)
+    u = rng.uniform(-0.2, 1.0, inst.N)
+    u[P.is_dir] = 0.0
+    d = O.artificial_diffusion(P, P.c)
+    rstar, umax, umin = O.mcl_limited_fluxes(P, u, P.c, d)
+    both = P.offd & ~P.is_dir[P.rows] & ~P.is_dir[P.col]
+    np.testing.assert_array_equal(rstar[both], -rstar[P.tpos][both])
+    # on pairs with c_ji = -c_ij the bar state lies between u_i and u_j, so r* lies between 0 and r
+    r = d * (u[P.col] - u[P.rows])
+    # (the product form S_ij - 2 d_ij u^max_i rounds, so allow a few ulp of |d| max|u|)
+    inner = both & (P.c[P.tpos] == -P.c)
+    tol = 16 * np.finfo(float).eps * np.abs(d[inner]) * np.abs(u).max()
+    assert np.all(np.minimum(0, r[inner]) - tol <= rstar[inner])
+    assert np.all(rstar[inner] <= np.maximum(0, r[inner]) + tol)
+    assert np.count_nonzero(np.abs(rstar[inner]) < np.abs(r[inner]) - tol) > 0  # the clip is active somewhere
+    # u_max/u_min include the node itself (eq. (23))
+    assert np.all(umax >= u) and np.all(umin <= u)
+
+
+def test_mcl_pure_convection_steady_state_obeys_dmp():
+    # eps = c = 0, inflow data in [0, 1], f = 0: converged MCL solution stays in [0, 1]
+    def u_in(X):
+        return (X[:, 1] > 0.5).astype(float)
+
+    inst = I.build("Q1", 8, 0.0, I.affine_field([1.0, 0.3, 0.2]), 0.0, dirichlet="inflow", dir_fn=u_in)
+    P = O.problem_from_instance(inst, conv=True)
+    lo = O.low_order_solution(P, inst.F)
+    u, st = O.stationary_mcl(P, inst.F, lo.x, tol=1e-10, tol_mode="rel", maxit=2000, lin_rtol=1e-14)
+    assert st.status == O.STATUS_OK
+    ulp = 4 * np.finfo(float).eps
+    assert u.min() >= -ulp and u.max() <= 1.0 + ulp
+
+
+def _l2(P, e):
+    return math.sqrt(float(np.sum(P.m * e * e)))
+
+
+@pytest.mark.slow
+def test_second_order_convergence_on_smooth_solution():
+    """O(h^2) discrete L2 error for a smooth monotone solution (Galerkin, MCL, CN-FCT)."""
+    errs = {"galerkin": [], "mcl": [], "cn": []}
+    ns = [4, 8, 16]
+    for n in ns:
+        inst, ue = I.manufactured("Q1", n)
+        P = O.problem_from_instance(inst, conv=True)
+        ug, _ = O.stationary_mcl(P, inst.F, ue * 0, alpha_mode="one", tol=1e-13, tol_mode="rel", maxit=400,
+                                 lin_rtol=1e-14)
+        errs["galerkin"].append(_l2(P, ug - ue))
+        um, _ = O.stationary_mcl(P, inst.F, ug, tol=1e-12, tol_mode="rel", maxit=400, lin_rtol=1e-14)
+        errs["mcl"].append(_l2(P, um - ue))
+        # CN-FCT, u* e^{-t} from t = 0 to t = 0.1 with dt = h/4
+        inst0, _ = I.manufactured("Q1", n, t=0.0)
+        dt = (1.0 / n) / 4
+        steps = int(round(0.1 / dt))
+        P0 = O.problem_from_instance(inst0, conv=False)
+        u = inst0.u0.copy()
+        for s in range(steps):
+            ia, _ = I.manufactured("Q1", n, t=s * dt)
+            ib, ub = I.manufactured("Q1", n, t=(s + 1) * dt)
+            Pb = O.AFCProblem(inst0.row_ptr, inst0.col, inst0.M, inst0.K, None, None, ib.dir_idx, ib.dir_val)
+            u, _ = O.cn_fct_step(Pb, u, ia.F, ib.F, dt, tol=1e-13, tol_mode="rel", maxit=100, lin_rtol=1e-14)
+        errs["cn"].append(_l2(P0, u - ub))
+    for k, e in errs.items():
+        rate = math.log2(e[-2] / e[-1])
+        assert rate >= 1.8, (k, e, rate)
