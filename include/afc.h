@@ -97,8 +97,9 @@ typedef struct {
   double lin_atol;          /* linear stop: ||b - A x|| <= max(atol, rtol*||b||) */
   double lin_rtol;
   int32_t lin_maxit;        /* Krylov iteration cap per linear solve           */
-  double inner_rtol;        /* MIXED: FP32 inner solve relative tolerance      */
-  int32_t inner_maxit;      /* MIXED: FP32 inner iteration cap per sweep       */
+  double inner_rtol;        /* MIXED: a sweep's FP32 GMRES cycle stops early
+                               once its residual estimate falls by this factor */
+  int32_t inner_maxit;      /* MIXED: FP32 steps per sweep (<= restart)        */
   int32_t refine_maxit;     /* MIXED: cap on FP64 refinement sweeps            */
   double fp_tol;            /* nonlinear tolerance (see fp_tol_mode)           */
   int32_t fp_tol_mode;      /* AFC_TOL_*                                       */
@@ -125,7 +126,7 @@ typedef struct {
 
 /* Fill *opt with defaults: LIMITED, GMRES(30), FP64, lin_atol 1e-12,
  * lin_rtol 0, lin_maxit 10000, inner_rtol 1e-5, inner_maxit 300,
- * refine_maxit 50, fp_tol 1e-12 ABS_SQRTN, fp_maxit 50, prelimit 2,
+ * refine_maxit 1000, fp_tol 1e-12 ABS_SQRTN, fp_maxit 50, prelimit 2,
  * omega 1, no dynamic damping, ssp_stages 3, automatic lanes, NULL stream. */
 void afc_default_options(afc_options *opt);
 

@@ -1,0 +1,216 @@
+"""ctypes binding of libafc.so (C ABI in include/afc.h).
+
+Argument marshalling only: every step of the AFC path runs in the HIP
+library.  Entry points keep the C names.  Vectors passed to the step/solve
+calls are torch float64 tensors on the GPU (device pointers); afc_create takes
+numpy arrays (host memory) or torch GPU tensors (device memory).
+
+The library is loaded on first use; if it has not been built this raises
+instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_char_p, c_double, c_int32, c_int64, c_void_p
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libafc.so")
+
+AFC_OK, AFC_WMAXIT = 0, 1
+AFC_EINVAL, AFC_ENOMEM, AFC_ENOCONV, AFC_EBREAKDOWN, AFC_ENAN, AFC_EDEVICE = -1, -2, -3, -4, -5, -6
+AFC_MEM_HOST, AFC_MEM_DEVICE = 0, 1
+AFC_ALPHA_LIMITED, AFC_ALPHA_ONE, AFC_ALPHA_ZERO = 0, 1, 2
+AFC_KRYLOV_BICGSTAB, AFC_KRYLOV_GMRES = 0, 1
+AFC_PREC_FP64, AFC_PREC_MIXED = 0, 1
+AFC_TOL_ABS_SQRTN, AFC_TOL_REL = 0, 1
+
+
+class afc_problem(ctypes.Structure):
+    _fields_ = [
+        ("n", c_int32), ("nnz", c_int64), ("mem_space", c_int32),
+        ("row_ptr", c_void_p), ("col_idx", c_void_p), ("M", c_void_p), ("K", c_void_p),
+        ("K_conv", c_void_p), ("ML", c_void_p), ("n_dir", c_int32), ("dir_idx", c_void_p), ("dir_val", c_void_p),
+    ]
+
+
+class afc_options(ctypes.Structure):
+    _fields_ = [
+        ("alpha_mode", c_int32), ("krylov", c_int32), ("restart", c_int32), ("precision", c_int32),
+        ("lin_atol", c_double), ("lin_rtol", c_double), ("lin_maxit", c_int32),
+        ("inner_rtol", c_double), ("inner_maxit", c_int32), ("refine_maxit", c_int32),
+        ("fp_tol", c_double), ("fp_tol_mode", c_int32), ("fp_maxit", c_int32),
+        ("prelimit", c_double), ("omega", c_double), ("dynamic_damping", c_int32),
+        ("ssp_stages", c_int32), ("lanes_per_row", c_int32), ("stream", c_void_p),
+    ]
+
+
+class afc_stats(ctypes.Structure):
+    _fields_ = [
+        ("status", c_int32), ("fp_iters", c_int32), ("krylov_iters", c_int64), ("inner_iters", c_int64),
+        ("refine_sweeps", c_int32), ("res0", c_double), ("res", c_double), ("lin_res", c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+EXPORTS = [
+    "afc_default_options", "afc_create", "afc_set_options", "afc_step_ssprk3", "afc_step_cn",
+    "afc_solve_stationary", "afc_destroy", "afc_status_str", "afc_last_error",
+]
+
+_lib = None
+
+
+def lib():
+    """Load libafc.so (once).  Raises if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libafc.so is not built (run python -m paper_2110_15676_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        L.afc_default_options.argtypes = [POINTER(afc_options)]
+        L.afc_default_options.restype = None
+        L.afc_create.argtypes = [POINTER(afc_problem), POINTER(afc_options), POINTER(c_void_p)]
+        L.afc_create.restype = c_int32
+        L.afc_set_options.argtypes = [c_void_p, POINTER(afc_options)]
+        L.afc_set_options.restype = c_int32
+        L.afc_step_ssprk3.argtypes = [c_void_p, c_void_p, c_void_p, c_double, POINTER(afc_stats)]
+        L.afc_step_ssprk3.restype = c_int32
+        L.afc_step_cn.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_double, POINTER(afc_stats)]
+        L.afc_step_cn.restype = c_int32
+        L.afc_solve_stationary.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, POINTER(afc_stats)]
+        L.afc_solve_stationary.restype = c_int32
+        L.afc_destroy.argtypes = [c_void_p]
+        L.afc_destroy.restype = None
+        L.afc_status_str.argtypes = [c_int32]
+        L.afc_status_str.restype = c_char_p
+        L.afc_last_error.argtypes = [c_void_p]
+        L.afc_last_error.restype = c_char_p
+        _lib = L
+    return _lib
+
+
+class AFCError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s (%d): %s" % (afc_status_str(status), status, msg))
+        self.status = status
+
+
+def afc_status_str(status: int) -> str:
+    return lib().afc_status_str(int(status)).decode()
+
+
+def afc_last_error(h=None) -> str:
+    return lib().afc_last_error(h).decode()
+
+
+def afc_default_options(**overrides) -> afc_options:
+    o = afc_options()
+    lib().afc_default_options(ctypes.byref(o))
+    for k, v in overrides.items():
+        setattr(o, k, v)
+    return o
+
+
+def _ptr(a):
+    """(address, keepalive) of a contiguous numpy array or torch tensor."""
+    if a is None:
+        return None, None
+    if isinstance(a, np.ndarray):
+        a = np.ascontiguousarray(a)
+        return a.ctypes.data, a
+    if not a.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return a.data_ptr(), a
+
+
+def _current_stream():
+    import torch
+
+    return torch.cuda.current_stream().cuda_stream
+
+
+def afc_create(row_ptr, col_idx, M, K, K_conv=None, ML=None, dir_idx=None, dir_val=None, opts=None):
+    """Create a handle from CSR arrays.  All arrays either numpy (host) or torch
+    GPU tensors (device): int32 row_ptr/col_idx/dir_idx, float64 values."""
+    is_np = isinstance(row_ptr, np.ndarray)
+    if is_np:
+        row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
+        col_idx = np.ascontiguousarray(col_idx, dtype=np.int32)
+        M = np.ascontiguousarray(M, dtype=np.float64)
+        K = np.ascontiguousarray(K, dtype=np.float64)
+        K_conv = None if K_conv is None else np.ascontiguousarray(K_conv, dtype=np.float64)
+        ML = None if ML is None else np.ascontiguousarray(ML, dtype=np.float64)
+        dir_idx = np.zeros(0, np.int32) if dir_idx is None else np.ascontiguousarray(dir_idx, dtype=np.int32)
+        dir_val = np.zeros(0) if dir_val is None else np.ascontiguousarray(dir_val, dtype=np.float64)
+    keep = []
+    p = afc_problem()
+    p.n = int(row_ptr.shape[0] - 1)
+    p.nnz = int(col_idx.shape[0])
+    p.mem_space = AFC_MEM_HOST if is_np else AFC_MEM_DEVICE
+    for name, arr in (("row_ptr", row_ptr), ("col_idx", col_idx), ("M", M), ("K", K), ("K_conv", K_conv),
+                      ("ML", ML), ("dir_idx", dir_idx), ("dir_val", dir_val)):
+        addr, ka = _ptr(arr)
+        keep.append(ka)
+        setattr(p, name, addr)
+    p.n_dir = 0 if dir_idx is None else int(dir_idx.shape[0])
+    if opts is None:
+        opts = afc_default_options()
+    h = c_void_p()
+    st = lib().afc_create(ctypes.byref(p), ctypes.byref(opts), ctypes.byref(h))
+    if st != AFC_OK:
+        raise AFCError(st, afc_last_error(None))
+    return h
+
+
+def afc_create_instance(inst, opts=None, conv=True):
+    """afc_create from a paper_2110_15676_amd.inputs.Instance (host arrays)."""
+    return afc_create(inst.row_ptr, inst.col, inst.M, inst.K, inst.K_conv if conv else None, None,
+                      inst.dir_idx, inst.dir_val, opts)
+
+
+def afc_set_options(h, opts):
+    st = lib().afc_set_options(h, ctypes.byref(opts))
+    if st != AFC_OK:
+        raise AFCError(st, afc_last_error(h))
+
+
+def _check_vec(t, n):
+    import torch
+
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+            and t.numel() == n):
+        raise ValueError("expected a contiguous float64 GPU tensor of %d elements" % n)
+
+
+def _finish(h, st, stats, raise_on_error):
+    if raise_on_error and st < 0:
+        raise AFCError(st, afc_last_error(h))
+    return st, stats.as_dict()
+
+
+def afc_step_ssprk3(h, u, F, dt, raise_on_error=True):
+    stats = afc_stats()
+    st = lib().afc_step_ssprk3(h, u.data_ptr(), F.data_ptr(), float(dt), ctypes.byref(stats))
+    return _finish(h, st, stats, raise_on_error)
+
+
+def afc_step_cn(h, u, F_old, F_new, dt, raise_on_error=True):
+    stats = afc_stats()
+    st = lib().afc_step_cn(h, u.data_ptr(), F_old.data_ptr(), F_new.data_ptr(), float(dt), ctypes.byref(stats))
+    return _finish(h, st, stats, raise_on_error)
+
+
+def afc_solve_stationary(h, u, F, init_low_order=False, raise_on_error=True):
+    stats = afc_stats()
+    st = lib().afc_solve_stationary(h, u.data_ptr(), F.data_ptr(), int(bool(init_low_order)), ctypes.byref(stats))
+    return _finish(h, st, stats, raise_on_error)
+
+
+def afc_destroy(h):
+    if h is not None and h.value:
+        lib().afc_destroy(h)

@@ -1,0 +1,761 @@
+// C ABI of libafc: validation, setup of the AFC operators, Krylov drivers
+// and the time-step / stationary drivers.  The drivers only enqueue kernels;
+// the host waits once per fixed-point iteration (nonlinear residual) and once
+// per Krylov chunk (BiCGStab) or cycle (GMRES).
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstddef>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "afc_kernels.h"
+
+using afc::KState;
+using afc::kMaxRestart;
+using afc::kRedBlocks;
+using afc::kMaxRed;
+
+namespace {
+
+// work vector slots
+enum Slot { W_ARN = 0, W_B, W_R, W_X, W_A, W_B2, W_RP, W_RM, W_UOLD, W_UT, W_G, W_S1, W_S2,
+            W_RHAT, W_P, W_V, W_S, W_T, W_COUNT };
+
+struct Fail {
+  afc_status st;
+};
+
+#define HIP_OK(expr)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess) {                                                              \
+      if (h) h->last_error = std::string(#expr) + ": " + hipGetErrorString(e_);          \
+      throw Fail{AFC_EDEVICE};                                                           \
+    }                                                                                    \
+  } while (0)
+
+[[noreturn]] void fail(afc_handle* h, afc_status st, const std::string& msg) {
+  if (h) h->last_error = msg;
+  throw Fail{st};
+}
+
+std::string g_create_error;  // errors of afc_create before a handle exists
+
+afc_status check_options(const afc_options& o, std::string& why) {
+  if (o.alpha_mode < 0 || o.alpha_mode > 2) return why = "alpha_mode", AFC_EINVAL;
+  if (o.krylov != AFC_KRYLOV_BICGSTAB && o.krylov != AFC_KRYLOV_GMRES) return why = "krylov", AFC_EINVAL;
+  if (o.restart < 1 || o.restart > kMaxRestart) return why = "restart must be in 1..64", AFC_EINVAL;
+  if (o.precision != AFC_PREC_FP64 && o.precision != AFC_PREC_MIXED) return why = "precision", AFC_EINVAL;
+  if (o.precision == AFC_PREC_MIXED && o.krylov != AFC_KRYLOV_GMRES)
+    return why = "mixed precision is implemented with GMRES", AFC_EINVAL;
+  if (!(o.lin_atol >= 0) || !(o.lin_rtol >= 0) || !(o.inner_rtol >= 0) || !(o.fp_tol >= 0))
+    return why = "tolerances must be >= 0", AFC_EINVAL;
+  if (o.lin_maxit < 1 || o.inner_maxit < 1 || o.refine_maxit < 1 || o.fp_maxit < 0)
+    return why = "iteration caps", AFC_EINVAL;
+  if (o.fp_tol_mode != AFC_TOL_ABS_SQRTN && o.fp_tol_mode != AFC_TOL_REL) return why = "fp_tol_mode", AFC_EINVAL;
+  if (!(o.prelimit >= 0) || !std::isfinite(o.prelimit)) return why = "prelimit", AFC_EINVAL;
+  if (!(o.omega > 0 && o.omega <= 1)) return why = "omega must be in (0, 1]", AFC_EINVAL;
+  if (o.ssp_stages < 1 || o.ssp_stages > 3) return why = "ssp_stages must be 1, 2 or 3", AFC_EINVAL;
+  if (o.lanes_per_row != 0 && o.lanes_per_row != 8 && o.lanes_per_row != 16 && o.lanes_per_row != 32 &&
+      o.lanes_per_row != 64)
+    return why = "lanes_per_row must be 0, 8, 16, 32 or 64", AFC_EINVAL;
+  return AFC_OK;
+}
+
+template <typename T>
+std::vector<T> fetch(afc_handle* h, const T* p, size_t n, int mem_space) {
+  std::vector<T> v(n);
+  if (n == 0) return v;
+  if (mem_space == AFC_MEM_DEVICE)
+    HIP_OK(hipMemcpy(v.data(), p, n * sizeof(T), hipMemcpyDeviceToHost));
+  else
+    std::memcpy(v.data(), p, n * sizeof(T));
+  return v;
+}
+
+template <typename T>
+T* upload(afc_handle* h, const std::vector<T>& v) {
+  T* d = nullptr;
+  const size_t bytes = std::max<size_t>(1, v.size()) * sizeof(T);
+  if (hipMalloc(&d, bytes) != hipSuccess) fail(h, AFC_ENOMEM, "hipMalloc failed during afc_create");
+  if (!v.empty()) HIP_OK(hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return d;
+}
+
+template <typename T>
+T* dalloc(afc_handle* h, size_t n) {
+  T* d = nullptr;
+  if (hipMalloc(&d, std::max<size_t>(1, n) * sizeof(T)) != hipSuccess) fail(h, AFC_ENOMEM, "hipMalloc failed");
+  return d;
+}
+
+int pick_lanes(int64_t nnz, int N, int forced) {
+  if (forced) return forced;
+  const double avg = double(nnz) / double(N);
+  if (avg <= 8.0) return 8;
+  if (avg <= 16.0) return 16;
+  if (avg <= 32.0) return 32;
+  return 64;
+}
+
+void free_all(afc_handle* h) {
+  auto f = [](auto*& p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+  };
+  f(h->row_ptr); f(h->col); f(h->is_dir); f(h->uD); f(h->ml);
+  f(h->mij); f(h->dp_fct); f(h->AL_fct);
+  f(h->cc); f(h->ccT); f(h->AL_mcl); f(h->dinv_mcl); f(h->A32_mcl);
+  f(h->A_cn); f(h->dinv_cn); f(h->A32_cn);
+  for (auto*& p : h->w) f(p);
+  h->w.clear();
+  f(h->V64); f(h->V32);
+  f(h->partials); f(h->counters); f(h->ks);
+  if (h->host_status) (void)hipHostFree(h->host_status);
+  h->host_status = nullptr;
+}
+
+void sync_status(afc_handle* h) {
+  HIP_OK(hipGetLastError());
+  HIP_OK(hipMemcpyAsync(h->host_status, h->ks, afc::kStatusBytes, hipMemcpyDeviceToHost, h->stream));
+  HIP_OK(hipStreamSynchronize(h->stream));
+}
+
+void ensure_basis(afc_handle* h, int m, bool fp32) {
+  if (h->Vm < m) {
+    if (h->V64) (void)hipFree(h->V64);
+    if (h->V32) (void)hipFree(h->V32);
+    h->V64 = nullptr;
+    h->V32 = nullptr;
+    h->Vm = m;
+  }
+  const size_t n = (size_t)(h->Vm + 1) * (size_t)h->N;
+  if (fp32 && !h->V32) h->V32 = dalloc<float>(h, n);
+  if (!fp32 && !h->V64) h->V64 = dalloc<double>(h, n);
+}
+
+struct SysMat {
+  const double* A;
+  const double* dinv;
+  const float* A32;
+};
+
+struct SolveOut {
+  afc_status st = AFC_OK;
+  int64_t iters = 0;
+  int64_t inner = 0;
+  int sweeps = 0;
+  double res = 0.0;
+};
+
+// GMRES(m), right Jacobi.  x: in x0, out solution; r: b - A x0 on entry, with
+// ||r||^2 in ks->red[red_idx].  FP64 mode runs the Arnoldi process in FP64;
+// MIXED runs it in FP32 on the Jacobi-scaled FP32 matrix and recomputes the
+// FP64 residual after every cycle (iterative refinement, one sweep per cycle).
+SolveOut solve_gmres(afc_handle* h, const SysMat& S, const double* b, double* x, double* r, int red_idx,
+                     double tol) {
+  SolveOut o;
+  const bool mixed = h->opt.precision == AFC_PREC_MIXED;
+  // MIXED: one refinement sweep = one FP32 cycle of at most min(restart, inner_maxit) steps
+  const int m = mixed ? std::min(h->opt.restart, h->opt.inner_maxit) : h->opt.restart;
+  ensure_basis(h, m, mixed);
+  const double inner_rel = mixed ? h->opt.inner_rtol : 0.0;
+  const int64_t cap = h->opt.lin_maxit;
+  if (mixed) {
+    afc::cycle_start(h, 2, red_idx, tol, inner_rel);
+    afc::cast_v0(h, r);
+  } else {
+    afc::copy(h, h->V64, r);
+    afc::cycle_start(h, 1, red_idx, tol, 0.0);
+  }
+  sync_status(h);
+  const int it0 = h->host_status->iters;
+  double res = h->host_status->beta;
+  if (!std::isfinite(res)) {
+    o.st = AFC_ENAN;
+    o.res = res;
+    return o;
+  }
+  while (res > tol) {
+    for (int k = 0; k < m; ++k) {
+      if (mixed)
+        afc::gmres_spmv32(h, S.A32, k);
+      else
+        afc::gmres_spmv64(h, S.A, S.dinv, k);
+      afc::gmres_dots(h, mixed, k, m);
+      afc::gmres_update(h, mixed, k, m);
+    }
+    afc::gmres_solve(h, m);
+    afc::gmres_xupdate(h, mixed, S.dinv, x);
+    if (mixed) {
+      afc::residual(h, S.A, b, x, r, 2, tol, inner_rel);
+      afc::cast_v0(h, r);
+    } else {
+      afc::residual(h, S.A, b, x, h->V64, 1, tol, 0.0);
+    }
+    o.sweeps += 1;
+    sync_status(h);
+    res = h->host_status->beta;
+    const int64_t its = h->host_status->iters - it0;
+    if (!std::isfinite(res)) {
+      o.st = AFC_ENAN;
+      break;
+    }
+    if (its >= cap || (mixed && o.sweeps >= h->opt.refine_maxit)) {
+      if (res > tol) o.st = AFC_ENOCONV;
+      break;
+    }
+  }
+  o.iters = h->host_status->iters - it0;
+  if (mixed) o.inner = o.iters;
+  o.res = res;
+  return o;
+}
+
+// BiCGStab, right Jacobi, FP64.  Same contract as solve_gmres.
+SolveOut solve_bicgstab(afc_handle* h, const SysMat& S, const double* b, double* x, double* r, double tol) {
+  SolveOut o;
+  afc::BicgVec v{x, r, h->w[W_RHAT], h->w[W_P], h->w[W_V], h->w[W_S], h->w[W_T]};
+  sync_status(h);
+  const int it0 = h->host_status->iters;
+  int restarts = 0;
+  while (true) {
+    afc::bicg_init(h, v, tol);
+    sync_status(h);
+    if (h->host_status->flag == 2) {
+      o.st = AFC_ENAN;
+      o.res = h->host_status->res;
+      break;
+    }
+    int chunk = 2;
+    while (!h->host_status->done && h->host_status->iters - it0 < h->opt.lin_maxit) {
+      const int n = std::min<int>(chunk, h->opt.lin_maxit - (h->host_status->iters - it0));
+      for (int c = 0; c < n; ++c) afc::bicg_iter(h, S.A, S.dinv, v);
+      sync_status(h);
+      chunk = std::min(chunk * 2, 16);
+    }
+    if (h->host_status->flag == 2) {
+      o.st = AFC_ENAN;
+      o.res = h->host_status->res;
+      break;
+    }
+    const bool breakdown = h->host_status->flag == 1;
+    // confirm on the true residual
+    afc::residual(h, S.A, b, x, r, 0, 0.0, 0.0);
+    sync_status(h);
+    const double res = std::sqrt(h->host_status->red[0]);
+    o.res = res;
+    if (!std::isfinite(res)) {
+      o.st = AFC_ENAN;
+      break;
+    }
+    if (res <= tol) break;
+    if (breakdown && ++restarts > 1) {
+      o.st = AFC_EBREAKDOWN;
+      break;
+    }
+    if (h->host_status->iters - it0 >= h->opt.lin_maxit) {
+      o.st = AFC_ENOCONV;
+      break;
+    }
+  }
+  o.iters = h->host_status->iters - it0;
+  return o;
+}
+
+SolveOut linear_solve(afc_handle* h, const SysMat& S, const double* b, double* x, double* r, int red_idx,
+                      double tol) {
+  if (h->opt.krylov == AFC_KRYLOV_GMRES) return solve_gmres(h, S, b, x, r, red_idx, tol);
+  return solve_bicgstab(h, S, b, x, r, tol);
+}
+
+void add_solve(afc_stats* st, const SolveOut& o) {
+  if (!st) return;
+  st->krylov_iters += o.iters;
+  st->inner_iters += o.inner;
+  st->refine_sweeps += o.sweeps;
+  st->lin_res = o.res;
+}
+
+bool fp_converged(const afc_handle* h, double R, double R0) {
+  if (h->opt.fp_tol_mode == AFC_TOL_ABS_SQRTN) return R < std::sqrt((double)h->N) * h->opt.fp_tol;
+  return R <= h->opt.fp_tol * R0;
+}
+
+double next_omega(const afc_handle* h, double omega, double R, double R_prev, bool have_prev) {
+  if (!h->opt.dynamic_damping || !have_prev) return omega;
+  if (R > R_prev) return std::max(omega * 0.5, 1.0 / 64.0);
+  return std::min(1.0, omega * 1.25);
+}
+
+// Fixed-point loop of Sec. 4 shared by the CN and stationary drivers.
+// `eval` enqueues the limiter + residual kernels writing b, r and the
+// reductions R^2, ||b||^2, ||r||^2 into ks->red[0..2].
+template <typename Eval>
+afc_status fixed_point(afc_handle* h, double* u, const SysMat& S, Eval eval, afc_stats* st) {
+  double* b = h->w[W_B];
+  double* r = h->w[W_R];
+  double R0 = 0.0, R_prev = 0.0;
+  bool have_prev = false;
+  double omega = h->opt.omega;
+  afc_status status = AFC_OK;
+  int nu = 0;
+  while (true) {
+    eval(u, b, r);
+    sync_status(h);
+    const double R = std::sqrt(h->host_status->red[0]);
+    const double bn = std::sqrt(h->host_status->red[1]);
+    if (!std::isfinite(R) || !std::isfinite(bn)) {
+      status = AFC_ENAN;
+      h->last_error = "non-finite nonlinear residual";
+      break;
+    }
+    if (nu == 0) R0 = R;
+    if (st) {
+      if (nu == 0) st->res0 = R;
+      st->res = R;
+    }
+    if (R == 0.0 || fp_converged(h, R, R0)) break;
+    if (nu >= h->opt.fp_maxit) {
+      status = AFC_WMAXIT;
+      break;
+    }
+    omega = next_omega(h, omega, R, R_prev, have_prev);
+    const bool relax = omega != 1.0;
+    double* x = u;
+    if (relax) {
+      x = h->w[W_X];
+      afc::copy(h, x, u);
+    }
+    const double tol = std::max(h->opt.lin_atol, h->opt.lin_rtol * bn);
+    const SolveOut o = linear_solve(h, S, b, x, r, 2, tol);
+    add_solve(st, o);
+    if (o.st == AFC_ENAN || o.st == AFC_EBREAKDOWN) {
+      status = o.st;
+      h->last_error = o.st == AFC_ENAN ? "non-finite linear residual" : "BiCGStab breakdown";
+      break;
+    }
+    if (relax) afc::relax(h, u, x, omega);
+    R_prev = R;
+    have_prev = true;
+    ++nu;
+  }
+  if (st) st->fp_iters = nu;
+  return status;
+}
+
+void ensure_work(afc_handle* h) {
+  if ((int)h->w.size() == W_COUNT) return;
+  h->w.assign(W_COUNT, nullptr);
+  for (int s = 0; s < W_COUNT; ++s) h->w[s] = dalloc<double>(h, (size_t)h->N);
+}
+
+afc_status guard(afc_handle* h, afc_stats* st, afc_status (*body)(afc_handle*, void*), void* ctx) {
+  if (!h) return AFC_EINVAL;
+  h->last_error.clear();
+  if (st) std::memset(st, 0, sizeof(*st));
+  afc_status s;
+  try {
+    HIP_OK(hipSetDevice(h->device));
+    ensure_work(h);
+    s = body(h, ctx);
+  } catch (const Fail& f) {
+    s = f.st;
+  } catch (...) {
+    h->last_error = "unexpected host exception";
+    s = AFC_EDEVICE;
+  }
+  if (st) st->status = s;
+  return s;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+extern "C" {
+
+void afc_default_options(afc_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->alpha_mode = AFC_ALPHA_LIMITED;
+  o->krylov = AFC_KRYLOV_GMRES;
+  o->restart = 30;
+  o->precision = AFC_PREC_FP64;
+  o->lin_atol = 1e-12;
+  o->lin_rtol = 0.0;
+  o->lin_maxit = 10000;
+  o->inner_rtol = 1e-5;
+  o->inner_maxit = 300;
+  o->refine_maxit = 1000;
+  o->fp_tol = 1e-12;
+  o->fp_tol_mode = AFC_TOL_ABS_SQRTN;
+  o->fp_maxit = 50;
+  o->prelimit = 2.0;
+  o->omega = 1.0;
+  o->dynamic_damping = 0;
+  o->ssp_stages = 3;
+  o->lanes_per_row = 0;
+  o->stream = nullptr;
+}
+
+const char* afc_status_str(int32_t s) {
+  switch (s) {
+    case AFC_OK: return "ok";
+    case AFC_WMAXIT: return "iteration cap reached";
+    case AFC_EINVAL: return "invalid argument";
+    case AFC_ENOMEM: return "out of device memory";
+    case AFC_ENOCONV: return "linear solver did not converge";
+    case AFC_EBREAKDOWN: return "BiCGStab breakdown";
+    case AFC_ENAN: return "non-finite value";
+    case AFC_EDEVICE: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+const char* afc_last_error(const afc_handle* h) { return h ? h->last_error.c_str() : g_create_error.c_str(); }
+
+afc_status afc_set_options(afc_handle* h, const afc_options* opt) {
+  if (!h || !opt) return AFC_EINVAL;
+  std::string why;
+  const afc_status s = check_options(*opt, why);
+  if (s != AFC_OK) {
+    h->last_error = "invalid options: " + why;
+    return s;
+  }
+  h->opt = *opt;
+  h->stream = static_cast<hipStream_t>(opt->stream);
+  h->G = pick_lanes(h->nnz, h->N, opt->lanes_per_row);
+  return AFC_OK;
+}
+
+afc_status afc_create(const afc_problem* p, const afc_options* opt, afc_handle** out) {
+  g_create_error.clear();
+  if (out) *out = nullptr;
+  if (!p || !out) return g_create_error = "null argument", AFC_EINVAL;
+  afc_options o;
+  afc_default_options(&o);
+  if (opt) o = *opt;
+  std::string why;
+  if (check_options(o, why) != AFC_OK) return g_create_error = "invalid options: " + why, AFC_EINVAL;
+  if (p->n <= 0 || p->nnz <= 0 || p->nnz >= (int64_t)std::numeric_limits<int>::max())
+    return g_create_error = "need n > 0 and 0 < nnz < 2^31", AFC_EINVAL;
+  if (p->mem_space != AFC_MEM_HOST && p->mem_space != AFC_MEM_DEVICE)
+    return g_create_error = "mem_space", AFC_EINVAL;
+  if (!p->row_ptr || !p->col_idx || !p->M || !p->K || (p->n_dir > 0 && (!p->dir_idx || !p->dir_val)) ||
+      p->n_dir < 0)
+    return g_create_error = "null array", AFC_EINVAL;
+
+  afc_handle* h = new afc_handle();
+  try {
+    h->opt = o;
+    h->stream = static_cast<hipStream_t>(o.stream);
+    const int N = p->n;
+    const int64_t nnz = p->nnz;
+    h->N = N;
+    h->nnz = nnz;
+    h->n_dir = p->n_dir;
+    h->G = pick_lanes(nnz, N, o.lanes_per_row);
+    const int ms = p->mem_space;
+    const std::vector<int> rp = fetch(h, p->row_ptr, (size_t)N + 1, ms);
+    const std::vector<int> col = fetch(h, p->col_idx, (size_t)nnz, ms);
+    const std::vector<double> M = fetch(h, p->M, (size_t)nnz, ms);
+    const std::vector<double> K = fetch(h, p->K, (size_t)nnz, ms);
+    const std::vector<double> Kc = p->K_conv ? fetch(h, p->K_conv, (size_t)nnz, ms) : std::vector<double>();
+    std::vector<double> ml = p->ML ? fetch(h, p->ML, (size_t)N, ms) : std::vector<double>();
+    const std::vector<int> didx = fetch(h, p->dir_idx, (size_t)p->n_dir, ms);
+    const std::vector<double> dval = fetch(h, p->dir_val, (size_t)p->n_dir, ms);
+
+    // --- pattern checks -------------------------------------------------------
+    if (rp[0] != 0 || rp[N] != nnz) fail(h, AFC_EINVAL, "row_ptr[0] must be 0 and row_ptr[N] = nnz");
+    std::vector<int> diag(N, -1);
+    for (int i = 0; i < N; ++i) {
+      if (rp[i + 1] < rp[i]) fail(h, AFC_EINVAL, "row_ptr not monotone");
+      for (int k = rp[i]; k < rp[i + 1]; ++k) {
+        const int j = col[k];
+        if (j < 0 || j >= N) fail(h, AFC_EINVAL, "column index out of range");
+        if (k > rp[i] && col[k - 1] >= j) fail(h, AFC_EINVAL, "columns not strictly ascending in a row");
+        if (j == i) diag[i] = k;
+      }
+      if (diag[i] < 0) fail(h, AFC_EINVAL, "missing diagonal entry in row " + std::to_string(i));
+    }
+    std::vector<int> tpos((size_t)nnz);
+    for (int i = 0; i < N; ++i) {
+      for (int k = rp[i]; k < rp[i + 1]; ++k) {
+        const int j = col[k];
+        const int* b0 = col.data() + rp[j];
+        const int* b1 = col.data() + rp[j + 1];
+        const int* f = std::lower_bound(b0, b1, i);
+        if (f == b1 || *f != i) fail(h, AFC_EINVAL, "pattern is not structurally symmetric");
+        tpos[k] = (int)(f - col.data());
+      }
+    }
+    for (int64_t k = 0; k < nnz; ++k)
+      if (!std::isfinite(M[k]) || !std::isfinite(K[k]) || (!Kc.empty() && !std::isfinite(Kc[k])))
+        fail(h, AFC_ENAN, "non-finite matrix entry");
+    // lumped mass m_i = sum_j m_ij (eq. (5))
+    if (ml.empty()) {
+      ml.assign(N, 0.0);
+      for (int i = 0; i < N; ++i)
+        for (int k = rp[i]; k < rp[i + 1]; ++k) ml[i] += M[k];
+    }
+    for (int i = 0; i < N; ++i)
+      if (!(ml[i] > 0.0) || !std::isfinite(ml[i])) fail(h, AFC_EINVAL, "lumped mass must be positive");
+    std::vector<uint8_t> is_dir(N, 0);
+    std::vector<double> uD(N, 0.0);
+    for (int q = 0; q < p->n_dir; ++q) {
+      const int i = didx[q];
+      if (i < 0 || i >= N) fail(h, AFC_EINVAL, "Dirichlet index out of range");
+      if (is_dir[i]) fail(h, AFC_EINVAL, "duplicate Dirichlet index");
+      if (!std::isfinite(dval[q])) fail(h, AFC_ENAN, "non-finite Dirichlet value");
+      is_dir[i] = 1;
+      uD[i] = dval[q];
+    }
+
+    // --- AFC operators -----------------------------------------------------------
+    // a_ij = -k_ij (eq. (4)); d+_ij = max(a_ij, 0, a_ji) = -d_ij (eq. (5));
+    // A_low = A + D (eq. (6)) with Dirichlet rows replaced by identity rows.
+    auto build_low = [&](const std::vector<double>& a_src, std::vector<double>& dp, std::vector<double>& AL) {
+      dp.assign((size_t)nnz, 0.0);
+      AL.assign((size_t)nnz, 0.0);
+      for (int i = 0; i < N; ++i) {
+        double dsum = 0.0;
+        for (int k = rp[i]; k < rp[i + 1]; ++k) {
+          if (col[k] == i) continue;
+          dp[k] = std::max(std::max(a_src[k], 0.0), a_src[tpos[k]]);
+          dsum += dp[k];
+        }
+        for (int k = rp[i]; k < rp[i + 1]; ++k) {
+          const double aik = -K[k];
+          AL[k] = col[k] == i ? aik + dsum : aik - dp[k];
+          if (is_dir[i]) AL[k] = col[k] == i ? 1.0 : 0.0;
+        }
+      }
+    };
+    std::vector<double> a((size_t)nnz);
+    for (int64_t k = 0; k < nnz; ++k) a[k] = -K[k];
+    std::vector<double> dp, AL;
+    build_low(a, dp, AL);
+    HIP_OK(hipGetDevice(&h->device));
+    h->row_ptr = upload(h, rp);
+    h->col = upload(h, col);
+    h->is_dir = upload(h, is_dir);
+    h->uD = upload(h, uD);
+    h->ml = upload(h, ml);
+    h->mij = upload(h, M);
+    h->dp_fct = upload(h, dp);
+    h->AL_fct = upload(h, AL);
+    // MCL: c = -K_conv (or a), c^T in CSR order, A_low from the convective D (Remark 1)
+    std::vector<double> c(a);
+    if (!Kc.empty())
+      for (int64_t k = 0; k < nnz; ++k) c[k] = -Kc[k];
+    std::vector<double> cT((size_t)nnz);
+    for (int64_t k = 0; k < nnz; ++k) cT[k] = c[tpos[k]];
+    std::vector<double> dpc, ALc;
+    build_low(c, dpc, ALc);
+    std::vector<double> dinv(N);
+    for (int i = 0; i < N; ++i) {
+      const double d = ALc[diag[i]];
+      if (!(d != 0.0) || !std::isfinite(d)) fail(h, AFC_EINVAL, "zero diagonal in the low-order operator");
+      dinv[i] = 1.0 / d;
+    }
+    std::vector<float> A32((size_t)nnz);
+    for (int64_t k = 0; k < nnz; ++k) A32[k] = (float)(ALc[k] * dinv[col[k]]);
+    h->cc = upload(h, c);
+    h->ccT = upload(h, cT);
+    h->AL_mcl = upload(h, ALc);
+    h->dinv_mcl = upload(h, dinv);
+    h->A32_mcl = upload(h, A32);
+    // CN system storage (values built per dt on the device)
+    h->A_cn = dalloc<double>(h, (size_t)nnz);
+    h->A32_cn = dalloc<float>(h, (size_t)nnz);
+    h->dinv_cn = dalloc<double>(h, (size_t)N);
+    // solver state
+    h->partials = dalloc<double>(h, (size_t)kMaxRed * kRedBlocks);
+    h->counters = dalloc<unsigned>(h, 16);
+    HIP_OK(hipMemset(h->counters, 0, 16 * sizeof(unsigned)));
+    h->ks = dalloc<KState>(h, 1);
+    HIP_OK(hipMemset(h->ks, 0, sizeof(KState)));
+    if (hipHostMalloc((void**)&h->host_status, sizeof(KState), hipHostMallocDefault) != hipSuccess)
+      fail(h, AFC_ENOMEM, "hipHostMalloc failed");
+    std::memset(h->host_status, 0, sizeof(KState));
+    HIP_OK(hipDeviceSynchronize());
+  } catch (const Fail& f) {
+    g_create_error = h->last_error;
+    free_all(h);
+    delete h;
+    return f.st;
+  } catch (...) {
+    g_create_error = "host allocation failed";
+    free_all(h);
+    delete h;
+    return AFC_ENOMEM;
+  }
+  *out = h;
+  return AFC_OK;
+}
+
+void afc_destroy(afc_handle* h) {
+  if (!h) return;
+  (void)hipSetDevice(h->device);
+  (void)hipStreamSynchronize(h->stream);
+  free_all(h);
+  delete h;
+}
+
+struct SspArgs {
+  double* u;
+  const double* F;
+  double dt;
+};
+
+afc_status afc_step_ssprk3(afc_handle* h, double* u, const double* F, double dt, afc_stats* st) {
+  if (!h) return AFC_EINVAL;
+  if (!u || !F || !(dt > 0) || !std::isfinite(dt)) {
+    h->last_error = "afc_step_ssprk3: need device u, F and dt > 0";
+    return AFC_EINVAL;
+  }
+  SspArgs a{u, F, dt};
+  return guard(
+      h, st,
+      [](afc_handle* h, void* ctx) -> afc_status {
+        const SspArgs& a = *static_cast<SspArgs*>(ctx);
+        double* s1 = h->w[W_S1];
+        double* s2 = h->w[W_S2];
+        double* udot = h->w[W_G];
+        double* ut = h->w[W_UT];
+        double* Rp = h->w[W_RP];
+        double* Rm = h->w[W_RM];
+        struct Stage {
+          const double* in;
+          double* out;
+          double c0, c1;
+        };
+        Stage stages[3];
+        int ns = 0;
+        if (h->opt.ssp_stages == 3) {  // Shu-Osher SSP-RK3
+          stages[ns++] = {a.u, s1, 0.0, 1.0};
+          stages[ns++] = {s1, s2, 0.75, 0.25};
+          stages[ns++] = {s2, a.u, 1.0 / 3.0, 2.0 / 3.0};
+        } else if (h->opt.ssp_stages == 2) {  // Heun, u^n = (u^{n,0} + u^{n,2}) / 2
+          stages[ns++] = {a.u, s1, 0.0, 1.0};
+          stages[ns++] = {s1, a.u, 0.5, 0.5};
+        } else {
+          stages[ns++] = {a.u, s1, 0.0, 1.0};
+        }
+        for (int s = 0; s < ns; ++s) {
+          afc::ssp_lowrate(h, stages[s].in, a.F, a.dt, udot, ut);
+          afc::ssp_limit_R(h, stages[s].in, udot, ut, a.dt, Rp, Rm);
+          afc::ssp_apply(h, stages[s].in, udot, ut, Rp, Rm, a.dt, a.u, stages[s].c0, stages[s].c1, stages[s].out);
+        }
+        if (ns == 1) afc::copy(h, a.u, s1);
+        HIP_OK(hipGetLastError());
+        HIP_OK(hipStreamSynchronize(h->stream));
+        return AFC_OK;
+      },
+      &a);
+}
+
+struct CnArgs {
+  double* u;
+  const double* Fo;
+  const double* Fn;
+  double dt;
+  afc_stats* st;
+};
+
+afc_status afc_step_cn(afc_handle* h, double* u, const double* F_old, const double* F_new, double dt,
+                       afc_stats* st) {
+  if (!h) return AFC_EINVAL;
+  if (!u || !F_old || !F_new || !(dt > 0) || !std::isfinite(dt)) {
+    h->last_error = "afc_step_cn: need device u, F_old, F_new and dt > 0";
+    return AFC_EINVAL;
+  }
+  CnArgs a{u, F_old, F_new, dt, st};
+  return guard(
+      h, st,
+      [](afc_handle* h, void* ctx) -> afc_status {
+        const CnArgs& a = *static_cast<CnArgs*>(ctx);
+        if (h->cn_dt != a.dt) {
+          afc::build_cn_matrix(h, a.dt);
+          h->cn_dt = a.dt;
+        }
+        double* uo = h->w[W_UOLD];
+        double* ut = h->w[W_UT];
+        double* g = h->w[W_G];
+        double* Qp = h->w[W_A];
+        double* Qm = h->w[W_B2];
+        double* Rp = h->w[W_RP];
+        double* Rm = h->w[W_RM];
+        afc::copy(h, uo, a.u);
+        afc::cn_predict(h, uo, a.Fo, a.Fn, a.dt, ut, g);  // eq. (14) and the right-hand side of eq. (11)
+        afc::zalesak_Q(h, ut, Qp, Qm);
+        afc::set_dirichlet(h, a.u);
+        const SysMat S{h->A_cn, h->dinv_cn, h->A32_cn};
+        const double dt = a.dt;
+        auto eval = [&](double* u, double* b, double* r) {
+          afc::cn_limit_R(h, u, uo, Qp, Qm, dt, Rp, Rm);
+          afc::cn_apply(h, u, uo, Rp, Rm, g, dt, b, r);
+        };
+        return fixed_point(h, a.u, S, eval, a.st);
+      },
+      &a);
+}
+
+struct StatArgs {
+  double* u;
+  const double* F;
+  int init_low;
+  afc_stats* st;
+};
+
+afc_status afc_solve_stationary(afc_handle* h, double* u, const double* F, int32_t init_low_order,
+                                afc_stats* st) {
+  if (!h) return AFC_EINVAL;
+  if (!u || !F) {
+    h->last_error = "afc_solve_stationary: need device u and F";
+    return AFC_EINVAL;
+  }
+  StatArgs a{u, F, init_low_order, st};
+  return guard(
+      h, st,
+      [](afc_handle* h, void* ctx) -> afc_status {
+        const StatArgs& a = *static_cast<StatArgs*>(ctx);
+        const SysMat S{h->AL_mcl, h->dinv_mcl, h->A32_mcl};
+        double* b = h->w[W_B];
+        double* r = h->w[W_R];
+        if (a.init_low) {  // low-order solution A_low u = F (alpha = 0), from zero
+          afc::rhs_dirichlet(h, b, a.F);
+          afc::fill(h, a.u, 0.0);
+          afc::set_dirichlet(h, a.u);
+          afc::norm2(h, b, 1);
+          afc::residual(h, S.A, b, a.u, r, 0, 0.0, 0.0);
+          sync_status(h);
+          const double tol = std::max(h->opt.lin_atol, h->opt.lin_rtol * std::sqrt(h->host_status->red[1]));
+          const SolveOut o = linear_solve(h, S, b, a.u, r, 0, tol);
+          add_solve(a.st, o);
+          if (o.st == AFC_ENAN) {
+            h->last_error = "non-finite residual in the low-order solve";
+            return AFC_ENAN;
+          }
+        }
+        afc::set_dirichlet(h, a.u);
+        double* umax = h->w[W_A];
+        double* umin = h->w[W_B2];
+        auto eval = [&](double* u, double* bb, double* rr) {
+          afc::mcl_bounds(h, u, umax, umin);
+          afc::mcl_apply(h, u, umax, umin, a.F, bb, rr);
+        };
+        return fixed_point(h, a.u, S, eval, a.st);
+      },
+      &a);
+}
+
+}  // extern "C"

@@ -1,0 +1,94 @@
+// Internal definitions shared by the HIP translation units of libafc.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/afc.h"
+
+namespace afc {
+
+constexpr int kBlock = 256;        // threads per workgroup (4 wave64)
+constexpr int kMaxRestart = 64;    // GMRES restart cap (Hessenberg lives on device)
+constexpr int kMaxRed = 72;        // values a single fused reduction may produce
+constexpr int kRedBlocks = 2048;   // cap on workgroups of reduction kernels
+
+// Device-resident scalars of the Krylov solvers (one per handle).  Every
+// scalar decision (step lengths, Givens rotations, convergence) is taken on
+// the device so that the host only synchronises once per chunk or cycle.
+struct KState {
+  // decision scalars first: the host copies this head after each chunk/cycle
+  double tol;       // absolute tolerance of the running cycle/solve
+  double beta;      // norm of the cycle's start residual
+  double res;       // latest residual (estimate) norm
+  double rho, alpha, omega, bcg_beta;  // BiCGStab scalars
+  double pad_d;
+  int m;            // restart length of the running cycle
+  int k;            // Arnoldi columns completed in the cycle
+  int done;         // converged or stopped: kernels of the chunk become no-ops
+  int flag;         // 1 breakdown, 2 non-finite
+  int iters;        // Krylov iterations, cumulative over the handle's life
+  int half;         // BiCGStab: ||s|| already below tol in this iteration
+  int pad_i[2];
+  double red[kMaxRed];                        // last finalized reduction
+  double H[(kMaxRestart + 1) * kMaxRestart];  // Hessenberg, column k at H[k*(m+1)]
+  double cs[kMaxRestart], sn[kMaxRestart];    // Givens rotations
+  double g[kMaxRestart + 1];                  // rotated right-hand side
+  double sc[kMaxRestart + 1];                 // basis scales: v_j = sc_j * V[j]
+  double coef[kMaxRestart + 1];               // update coefficients y_j * sc_j
+};
+
+// bytes of KState copied back to the host: scalars + red[0..7]
+constexpr size_t kStatusBytes = 8 * sizeof(double) + 8 * sizeof(int) + 8 * sizeof(double);
+
+}  // namespace afc
+
+struct afc_handle_s {
+  // problem
+  int N = 0;
+  int64_t nnz = 0;
+  int G = 32;  // lanes per row
+  int n_dir = 0;
+  afc_options opt{};
+  hipStream_t stream = nullptr;
+  int device = 0;
+  std::string last_error;
+
+  // pattern and node data (device)
+  int* row_ptr = nullptr;
+  int* col = nullptr;
+  uint8_t* is_dir = nullptr;
+  double* uD = nullptr;     // u_D on Dirichlet nodes, 0 elsewhere
+  double* ml = nullptr;     // lumped mass m_i
+
+  // FCT data: m_ij, d+_ij from K, A_low = A + D (Dirichlet rows = identity)
+  double* mij = nullptr;
+  double* dp_fct = nullptr;
+  double* AL_fct = nullptr;
+
+  // MCL data: convective c_ij, c_ji (transposed, CSR order), A_low from K_conv
+  double* cc = nullptr;
+  double* ccT = nullptr;
+  double* AL_mcl = nullptr;
+  double* dinv_mcl = nullptr;
+  float* A32_mcl = nullptr;  // A_low D^{-1} in FP32
+
+  // CN system M_L/dt + A_low/2 (built for the last dt used)
+  double cn_dt = 0.0;
+  double* A_cn = nullptr;
+  double* dinv_cn = nullptr;
+  float* A32_cn = nullptr;
+
+  // work vectors (FP64, N each)
+  std::vector<double*> w;
+  double* V64 = nullptr;  // (m+1) x N
+  float* V32 = nullptr;   // (m+1) x N
+  int Vm = 0;
+  double* partials = nullptr;  // kMaxRed * kRedBlocks
+  unsigned* counters = nullptr;
+  afc::KState* ks = nullptr;
+  afc::KState* host_status = nullptr;  // pinned copy of the KState head
+};

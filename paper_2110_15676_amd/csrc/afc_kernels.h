@@ -1,0 +1,63 @@
+// Launch wrappers of the HIP kernels (defined in afc_kernels.hip).
+#pragma once
+
+#include "afc_internal.h"
+
+namespace afc {
+
+using H = afc_handle_s;
+
+// --- plain vector helpers ---------------------------------------------------
+void copy(H* h, double* dst, const double* src);
+void set_dirichlet(H* h, double* u);                        // u_i = u_D,i on Dirichlet nodes
+void rhs_dirichlet(H* h, double* b, const double* F);       // b = F, b_i = u_D,i on Dirichlet nodes
+void relax(H* h, double* u, const double* x, double omega); // u += omega (x - u)
+void fill(H* h, double* u, double v);
+void norm2(H* h, const double* x, int red_idx);             // ||x||^2 into ks->red[red_idx]
+
+// --- setup --------------------------------------------------------------------
+void build_cn_matrix(H* h, double dt);  // A_cn = M_L/dt + A_low/2 (+ dinv, FP32 scaled copy)
+
+// --- residual of a linear system (FP64 SpMV) -----------------------------------
+// r = b - A x and ||r||^2 into ks->red[0]; mode selects the cycle start that
+// the last workgroup performs (0: none, 1: GMRES FP64 restart into V64[0],
+// 2: GMRES mixed restart, V32[0] cast done by cast_v0).
+void residual(H* h, const double* A, const double* b, const double* x, double* r, int mode, double tol_abs,
+              double tol_rel);
+void cycle_start(H* h, int mode, int red_idx, double tol_abs, double tol_rel);  // from a finished reduction
+void cast_v0(H* h, const double* r);
+
+// --- GMRES (right Jacobi), FP64 or FP32 Arnoldi --------------------------------
+void gmres_spmv64(H* h, const double* A, const double* dinv, int k);
+void gmres_spmv32(H* h, const float* A32, int k);
+void gmres_dots(H* h, bool fp32, int k, int m);
+void gmres_update(H* h, bool fp32, int k, int m);
+void gmres_solve(H* h, int m);
+void gmres_xupdate(H* h, bool fp32, const double* dinv, double* x);
+
+// --- BiCGStab (right Jacobi, FP64) ----------------------------------------------
+struct BicgVec { double *x, *r, *rhat, *p, *v, *s, *t; };
+void bicg_init(H* h, const BicgVec& b, double tol);
+void bicg_iter(H* h, const double* A, const double* dinv, const BicgVec& b);
+
+// --- Zalesak FCT, explicit SSP stage -------------------------------------------
+void ssp_lowrate(H* h, const double* u, const double* F, double dt, double* udot, double* ut);
+void ssp_limit_R(H* h, const double* u, const double* udot, const double* ut, double dt, double* Rp, double* Rm);
+void ssp_apply(H* h, const double* u, const double* udot, const double* ut, const double* Rp, const double* Rm,
+               double dt, const double* base, double c0, double c1, double* out);
+
+// --- Zalesak FCT, Crank-Nicolson --------------------------------------------------
+void cn_predict(H* h, const double* u_old, const double* F_old, const double* F_new, double dt, double* ut,
+                double* g);
+void zalesak_Q(H* h, const double* ut, double* Qp, double* Qm);
+void cn_limit_R(H* h, const double* u, const double* u_old, const double* Qp, const double* Qm, double dt,
+                double* Rp, double* Rm);
+void cn_apply(H* h, const double* u, const double* u_old, const double* Rp, const double* Rm, const double* g,
+              double dt, double* b, double* r);
+
+// --- monolithic convex limiter, stationary ------------------------------------------
+void mcl_bounds(H* h, const double* u, double* umax, double* umin);
+void mcl_apply(H* h, const double* u, const double* umax, const double* umin, const double* F, double* b,
+               double* r);
+
+}  // namespace afc

@@ -1,0 +1,1238 @@
+// HIP kernels of the AFC hot path for gfx950 (CDNA4, wave64).
+//
+// Row kernels map G consecutive lanes to one CSR row (G = 8/16/32/64, chosen
+// from the mean row length): the G lanes stream the row's entries with
+// coalesced loads, gather neighbour values, and reduce with intra-group
+// shuffles.  Each workgroup takes a contiguous range of row tiles, and
+// workgroup ids are remapped so that each of the 8 XCDs works on one
+// contiguous slab of rows (workgroups are dispatched round-robin over XCDs),
+// which keeps the neighbour gathers inside that XCD's L2.
+//
+// Reductions (norms, dot products) are deterministic: per-workgroup partials
+// in fixed slots, summed in a fixed order by the last workgroup to finish
+// (agent-scope fence + atomic ticket).  The same last workgroup performs the
+// scalar step of the solver (Givens rotation, BiCGStab coefficients,
+// convergence flag), so the host never waits inside a Krylov cycle.
+
+#include <algorithm>
+#include <cmath>
+
+#include "afc_kernels.h"
+
+namespace afc {
+namespace {
+
+constexpr int kRowGridCap = 32768;
+
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int x = b & 7, k = b >> 3;
+  const int per = nb >> 3, rem = nb & 7;
+  return x * per + min(x, rem) + k;
+}
+
+__device__ __forceinline__ void tile_range(int ntiles, int& t0, int& t1) {
+  const int nb = gridDim.x;
+  const int b = xcd_block(blockIdx.x, nb);
+  const int per = (ntiles + nb - 1) / nb;
+  t0 = min(b * per, ntiles);
+  t1 = min(t0 + per, ntiles);
+}
+
+template <int G>
+__device__ __forceinline__ double gsum(double v) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
+  return v;
+}
+template <int G>
+__device__ __forceinline__ float gsumf(float v) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
+  return v;
+}
+template <int G>
+__device__ __forceinline__ double gmax(double v) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, G));
+  return v;
+}
+template <int G>
+__device__ __forceinline__ double gmin(double v) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, G));
+  return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Block totals of nv per-thread values into partials[q * kRedBlocks + slot].
+template <int KMAX>
+__device__ void block_partials(const double (&v)[KMAX], int nv, double* partials, int slot) {
+  __shared__ double sh[KMAX][kBlock / 64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q) {
+    if (q < nv) {
+      const double s = wave_sum(v[q]);
+      if (lane == 0) sh[q][wv] = s;
+    }
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < nv; q += kBlock) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) s += sh[q][w];
+    partials[(size_t)q * kRedBlocks + slot] = s;
+  }
+}
+
+// Last-arriving workgroup sums the partials of all nb workgroups (fixed
+// order) into out[0..nv) and returns true; every other workgroup returns false.
+__device__ bool finalize(double* partials, int nb, int nv, unsigned* counter, double* out) {
+  __shared__ int is_last;
+  __shared__ double sh[kMaxRed][kBlock / 64];
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) is_last = (atomicAdd(counter, 1u) == (unsigned)(nb - 1));
+  __syncthreads();
+  if (!is_last) return false;
+  __threadfence();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int q = 0; q < nv; ++q) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kBlock) s += partials[(size_t)q * kRedBlocks + b];
+    s = wave_sum(s);
+    if (lane == 0) sh[q][wv] = s;
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < nv; q += kBlock) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) s += sh[q][w];
+    out[q] = s;
+  }
+  if (threadIdx.x == 0) *counter = 0u;
+  __syncthreads();
+  return true;
+}
+
+// Start of a Krylov cycle from the squared norm of its residual.
+__device__ void cycle_start_dev(KState* ks, int mode, double rr, double tol_abs, double tol_rel) {
+  const double beta = sqrt(rr);
+  ks->beta = beta;
+  ks->res = beta;
+  ks->k = 0;
+  ks->g[0] = beta;
+  ks->tol = fmax(tol_abs, tol_rel * beta);
+  ks->flag = isfinite(beta) ? 0 : 2;
+  ks->done = (!isfinite(beta) || beta <= ks->tol) ? 1 : 0;
+  if (mode == 1) ks->sc[0] = beta > 0.0 ? 1.0 / beta : 0.0;
+  if (mode == 2) ks->sc[0] = 1.0;
+}
+
+// ---------------------------------------------------------------------------
+// vector helpers
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_copy(int N, double* __restrict__ d, const double* __restrict__ s) {
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) d[i] = s[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_set_dirichlet(int N, double* __restrict__ u,
+                                                          const uint8_t* __restrict__ is_dir,
+                                                          const double* __restrict__ uD) {
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock)
+    if (is_dir[i]) u[i] = uD[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_rhs_dirichlet(int N, double* __restrict__ b, const double* __restrict__ F,
+                                                          const uint8_t* __restrict__ is_dir,
+                                                          const double* __restrict__ uD) {
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) b[i] = is_dir[i] ? uD[i] : F[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill(int N, double* __restrict__ u, double v) {
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) u[i] = v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_norm2(int N, const double* __restrict__ x, KState* ks, int idx,
+                                                  double* partials, unsigned* counter) {
+  double acc[1] = {0.0};
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) acc[0] += x[i] * x[i];
+  block_partials<1>(acc, 1, partials, blockIdx.x);
+  finalize(partials, gridDim.x, 1, counter, ks->red + idx);
+}
+
+__global__ __launch_bounds__(kBlock) void k_relax(int N, double* __restrict__ u, const double* __restrict__ x,
+                                                  double omega) {
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) u[i] += omega * (x[i] - u[i]);
+}
+
+// ---------------------------------------------------------------------------
+// CN system matrix M_L/dt + A_low/2 (Dirichlet rows identity) and its FP32
+// Jacobi-scaled copy
+// ---------------------------------------------------------------------------
+
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_build_cn(int N, const int* __restrict__ rp, const int* __restrict__ col,
+                                                     const double* __restrict__ AL, const double* __restrict__ ml,
+                                                     const uint8_t* __restrict__ is_dir, double inv_dt,
+                                                     double* __restrict__ Acn, double* __restrict__ dinv) {
+  constexpr int RPB = kBlock / G;
+  const int lane = threadIdx.x % G, sub = threadIdx.x / G;
+  int t0, t1;
+  tile_range((N + RPB - 1) / RPB, t0, t1);
+  for (int t = t0; t < t1; ++t) {
+    const int i = t * RPB + sub;
+    if (i >= N) continue;
+    const bool dir = is_dir[i];
+    const int e = rp[i + 1];
+    for (int k = rp[i] + lane; k < e; k += G) {
+      const int j = col[k];
+      double v;
+      if (dir) {
+        v = (j == i) ? 1.0 : 0.0;
+      } else {
+        v = 0.5 * AL[k];
+        if (j == i) v += ml[i] * inv_dt;
+      }
+      Acn[k] = v;
+      if (j == i) dinv[i] = 1.0 / v;
+    }
+  }
+}
+
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_scale32(int N, const int* __restrict__ rp, const int* __restrict__ col,
+                                                    const double* __restrict__ A, const double* __restrict__ dinv,
+                                                    float* __restrict__ A32) {
+  constexpr int RPB = kBlock / G;
+  const int lane = threadIdx.x % G, sub = threadIdx.x / G;
+  int t0, t1;
+  tile_range((N + RPB - 1) / RPB, t0, t1);
+  for (int t = t0; t < t1; ++t) {
+    const int i = t * RPB + sub;
+    if (i >= N) continue;
+    const int e = rp[i + 1];
+    for (int k = rp[i] + lane; k < e; k += G) A32[k] = (float)(A[k] * dinv[col[k]]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// SpMV family
+// ---------------------------------------------------------------------------
+
+// y = mul * A (s .* x)   (s optional column scaling = right Jacobi preconditioner)
+template <int G, bool SCALE>
+__global__ __launch_bounds__(kBlock) void k_spmv64(int N, const int* __restrict__ rp, const int* __restrict__ col,
+                                                   const double* __restrict__ A, const double* __restrict__ s,
+                                                   const double* __restrict__ x, const double* __restrict__ mulp,
+                                                   double* __restrict__ y, const int* __restrict__ done) {
+  if (done != nullptr && *done) return;
+  constexpr int RPB = kBlock / G;
+  const int lane = threadIdx.x % G, sub = threadIdx.x / G;
+  const double mul = mulp != nullptr ? *mulp : 1.0;
+  int t0, t1;
+  tile_range((N + RPB - 1) / RPB, t0, t1);
+  for (int t = t0; t < t1; ++t) {
+    const int i = t * RPB + sub;
+    if (i >= N) continue;
+    double acc = 0.0;
+    const int e = rp[i + 1];
+    for (int k = rp[i] + lane; k < e; k += G) {
+      const int j = col[k];
+      double xj = x[j];
+      if (SCALE) xj *= s[j];
+      acc += A[k] * xj;
+    }
+    acc = gsum<G>(acc);
+    if (lane == 0) y[i] = mul * acc;
+  }
+}
+
+// FP32: y = mul * A32 x
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_spmv32(int N, const int* __restrict__ rp, const int* __restrict__ col,
+                                                   const float* __restrict__ A, const float* __restrict__ x,
+                                                   const double* __restrict__ mulp, float* __restrict__ y,
+                                                   const int* __restrict__ done) {
+  if (*done) return;
+  constexpr int RPB = kBlock / G;
+  const int lane = threadIdx.x % G, sub = threadIdx.x / G;
+  const float mul = (float)*mulp;
+  int t0, t1;
+  tile_range((N + RPB - 1) / RPB, t0, t1);
+  for (int t = t0; t < t1; ++t) {
+    const int i = t * RPB + sub;
+    if (i >= N) continue;
+    float acc = 0.0f;
+    const int e = rp[i + 1];
+    for (int k = rp[i] + lane; k < e; k += G) acc += A[k] * x[col[k]];
+    acc = gsumf<G>(acc);
+    if (lane == 0) y[i] = mul * acc;
+  }
+}
+
+// r = b - A x, ||r||^2, optional Krylov cycle start
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_residual(int N, const int* __restrict__ rp, const int* __restrict__ col,
+                                                     const double* __restrict__ A, const double* __restrict__ b,
+                                                     const double* __restrict__ x, double* __restrict__ r,
+                                                     KState* ks, double* partials, unsigned* counter, int mode,
+                                                     double tol_abs, double tol_rel) {
+  constexpr int RPB = kBlock / G;
+  const int lane = threadIdx.x % G, sub = threadIdx.x / G;
+  double nrm[1] = {0.0};
+  int t0, t1;
+  tile_range((N + RPB - 1) / RPB, t0, t1);
+  for (int t = t0; t < t1; ++t) {
+    const int i = t * RPB + sub;
+    if (i >= N) continue;
+    double acc = 0.0;
+    const int e = rp[i + 1];
+    for (int k = rp[i] + lane; k < e; k += G) acc += A[k] * x[col[k]];
+    acc = gsum<G>(acc);
+    if (lane == 0) {
+      const double ri = b[i] - acc;
+      r[i] = ri;
+      nrm[0] += ri * ri;
+    }
+  }
+  block_partials<1>(nrm, 1, partials, blockIdx.x);
+  if (finalize(partials, gridDim.x, 1, counter, ks->red)) {
+    if (threadIdx.x == 0 && mode != 0) cycle_start_dev(ks, mode, ks->red[0], tol_abs, tol_rel);
+  }
+}
+
+__global__ void k_cycle_start(KState* ks, int mode, int idx, double tol_abs, double tol_rel) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) cycle_start_dev(ks, mode, ks->red[idx], tol_abs, tol_rel);
+}
+
+__global__ __launch_bounds__(kBlock) void k_cast_v0(int N, const double* __restrict__ r, float* __restrict__ V0,
+                                                    const KState* __restrict__ ks) {
+  const double beta = ks->beta;
+  const double inv = beta > 0.0 ? 1.0 / beta : 0.0;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) V0[i] = (float)(r[i] * inv);
+}
+
+// ---------------------------------------------------------------------------
+// GMRES: classical Gram-Schmidt with unnormalized basis vectors V[j] and
+// scales sc_j (v_j = sc_j V[j]); Givens rotations on the device.
+// ---------------------------------------------------------------------------
+
+template <typename T, int KMAX>
+__global__ __launch_bounds__(kBlock) void k_gmres_dots(int N, const T* __restrict__ V, const T* __restrict__ W,
+                                                       int k, int m, KState* ks, double* partials,
+                                                       unsigned* counter) {
+  if (ks->done) return;
+  const int nv = k + 1;
+  double acc[KMAX];
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q) acc[q] = 0.0;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) {
+    const double w = (double)W[i];
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q)
+      if (q < nv) acc[q] += (double)V[(size_t)q * N + i] * w;
+  }
+  block_partials<KMAX>(acc, nv, partials, blockIdx.x);
+  if (finalize(partials, gridDim.x, nv, counter, ks->red)) {
+    double* Hk = ks->H + (size_t)k * (m + 1);
+    for (int q = threadIdx.x; q < nv; q += kBlock) Hk[q] = ks->sc[q] * ks->red[q];
+  }
+}
+
+__device__ void givens_step(KState* ks, int k, int m) {
+  double* Hk = ks->H + (size_t)k * (m + 1);
+  const double hk1 = sqrt(ks->red[0]);
+  if (!isfinite(hk1)) {
+    ks->flag = 2;
+    ks->done = 1;
+    return;
+  }
+  Hk[k + 1] = hk1;
+  ks->sc[k + 1] = hk1 > 0.0 ? 1.0 / hk1 : 0.0;
+  for (int jj = 0; jj < k; ++jj) {
+    const double a = Hk[jj], b = Hk[jj + 1];
+    Hk[jj] = ks->cs[jj] * a + ks->sn[jj] * b;
+    Hk[jj + 1] = -ks->sn[jj] * a + ks->cs[jj] * b;
+  }
+  const double den = hypot(Hk[k], Hk[k + 1]);
+  if (den == 0.0) {  // w = 0 in exact arithmetic: the column adds nothing
+    ks->done = 1;
+    return;
+  }
+  ks->cs[k] = Hk[k] / den;
+  ks->sn[k] = Hk[k + 1] / den;
+  Hk[k] = den;
+  Hk[k + 1] = 0.0;
+  ks->g[k + 1] = -ks->sn[k] * ks->g[k];
+  ks->g[k] = ks->cs[k] * ks->g[k];
+  ks->k = k + 1;
+  ks->iters += 1;
+  ks->res = fabs(ks->g[k + 1]);
+  if (ks->res <= ks->tol || hk1 == 0.0) ks->done = 1;
+}
+
+template <typename T, int KMAX>
+__global__ __launch_bounds__(kBlock) void k_gmres_update(int N, T* __restrict__ V, const T* __restrict__ W, int k,
+                                                         int m, KState* ks, double* partials, unsigned* counter) {
+  if (ks->done) return;
+  const int nv = k + 1;
+  double t[KMAX];
+  const double* Hk = ks->H + (size_t)k * (m + 1);
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q) t[q] = (q < nv) ? Hk[q] * ks->sc[q] : 0.0;
+  T* __restrict__ out = V + (size_t)(k + 1) * N;
+  double nrm[1] = {0.0};
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) {
+    double w = (double)W[i];
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q)
+      if (q < nv) w -= t[q] * (double)V[(size_t)q * N + i];
+    const T wo = (T)w;
+    out[i] = wo;
+    nrm[0] += (double)wo * (double)wo;
+  }
+  block_partials<1>(nrm, 1, partials, blockIdx.x);
+  if (finalize(partials, gridDim.x, 1, counter, ks->red)) {
+    if (threadIdx.x == 0) givens_step(ks, k, m);
+  }
+}
+
+// back substitution R y = g over the columns completed in the cycle
+__global__ void k_gmres_solve(KState* ks, int m) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int kk = ks->k;
+  double y[kMaxRestart];
+  for (int i = kk - 1; i >= 0; --i) {
+    double s = ks->g[i];
+    for (int j = i + 1; j < kk; ++j) s -= ks->H[(size_t)j * (m + 1) + i] * y[j];
+    y[i] = s / ks->H[(size_t)i * (m + 1) + i];
+  }
+  for (int i = 0; i < kk; ++i) ks->coef[i] = y[i] * ks->sc[i];
+}
+
+// x += D^{-1} sum_j coef_j V[j]
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_gmres_xupdate(int N, const T* __restrict__ V,
+                                                          const double* __restrict__ dinv, double* __restrict__ x,
+                                                          const KState* __restrict__ ks) {
+  __shared__ double coef[kMaxRestart];
+  const int kk = ks->k;
+  for (int q = threadIdx.x; q < kk; q += kBlock) coef[q] = ks->coef[q];
+  __syncthreads();
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) {
+    double acc = 0.0;
+    for (int q = 0; q < kk; ++q) acc += coef[q] * (double)V[(size_t)q * N + i];
+    x[i] += dinv[i] * acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// BiCGStab (van der Vorst), right Jacobi preconditioning, FP64.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_bicg_init(int N, const double* __restrict__ r, double* __restrict__ rhat,
+                                                      double* __restrict__ p, double* __restrict__ v, KState* ks,
+                                                      double* partials, unsigned* counter, double tol) {
+  double acc[1] = {0.0};
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) {
+    const double ri = r[i];
+    rhat[i] = ri;
+    p[i] = ri;
+    v[i] = 0.0;
+    acc[0] += ri * ri;
+  }
+  block_partials<1>(acc, 1, partials, blockIdx.x);
+  if (finalize(partials, gridDim.x, 1, counter, ks->red)) {
+    if (threadIdx.x == 0) {
+      const double rr = ks->red[0];
+      ks->rho = rr;
+      ks->alpha = 1.0;
+      ks->omega = 1.0;
+      ks->bcg_beta = 0.0;
+      ks->res = sqrt(rr);
+      ks->tol = tol;
+      ks->half = 0;
+      ks->flag = isfinite(rr) ? 0 : 2;
+      ks->done = (!isfinite(rr) || ks->res <= tol) ? 1 : 0;
+    }
+  }
+}
+
+// v = A D^{-1} p ; alpha = rho / (rhat, v)
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_bicg_v(int N, const int* __restrict__ rp, const int* __restrict__ col,
+                                                   const double* __restrict__ A, const double* __restrict__ dinv,
+                                                   const double* __restrict__ p, const double* __restrict__ rhat,
+                                                   double* __restrict__ v, KState* ks, double* partials,
+                                                   unsigned* counter) {
+  if (ks->done) return;
+  constexpr int RPB = kBlock / G;
+  const int lane = threadIdx.x % G, sub = threadIdx.x / G;
+  double acc[1] = {0.0};
+  int t0, t1;
+  tile_range((N + RPB - 1) / RPB, t0, t1);
+  for (int t = t0; t < t1; ++t) {
+    const int i = t * RPB + sub;
+    if (i >= N) continue;
+    double s = 0.0;
+    const int e = rp[i + 1];
+    for (int k = rp[i] + lane; k < e; k += G) {
+      const int j = col[k];
+      s += A[k] * (dinv[j] * p[j]);
+    }
+    s = gsum<G>(s);
+    if (lane == 0) {
+      v[i] = s;
+      acc[0] += rhat[i] * s;
+    }
+  }
+  block_partials<1>(acc, 1, partials, blockIdx.x);
+  if (finalize(partials, gridDim.x, 1, counter, ks->red)) {
+    if (threadIdx.x == 0) {
+      const double rv = ks->red[0];
+      ks->half = 0;
+      if (rv == 0.0 || !isfinite(rv)) {
+        ks->flag = isfinite(rv) ? 1 : 2;
+        ks->done = 1;
+      } else {
+        ks->alpha = ks->rho / rv;
+      }
+    }
+  }
+}
+
+// s = r - alpha v ; stop early when ||s|| <= tol
+__global__ __launch_bounds__(kBlock) void k_bicg_s(int N, const double* __restrict__ r, const double* __restrict__ v,
+                                                   double* __restrict__ s, KState* ks, double* partials,
+                                                   unsigned* counter) {
+  if (ks->done) return;
+  const double alpha = ks->alpha;
+  double acc[1] = {0.0};
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) {
+    const double si = r[i] - alpha * v[i];
+    s[i] = si;
+    acc[0] += si * si;
+  }
+  block_partials<1>(acc, 1, partials, blockIdx.x);
+  if (finalize(partials, gridDim.x, 1, counter, ks->red)) {
+    if (threadIdx.x == 0 && sqrt(ks->red[0]) <= ks->tol) {
+      ks->half = 1;
+      ks->omega = 0.0;
+    }
+  }
+}
+
+// t = A D^{-1} s ; omega = (t, s) / (t, t)
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_bicg_t(int N, const int* __restrict__ rp, const int* __restrict__ col,
+                                                   const double* __restrict__ A, const double* __restrict__ dinv,
+                                                   const double* __restrict__ s, double* __restrict__ tv, KState* ks,
+                                                   double* partials, unsigned* counter) {
+  if (ks->done || ks->half) return;
+  constexpr int RPB = kBlock / G;
+  const int lane = threadIdx.x % G, sub = threadIdx.x / G;
+  double acc[2] = {0.0, 0.0};
+  int t0, t1;
+  tile_range((N + RPB - 1) / RPB, t0, t1);
+  for (int t = t0; t < t1; ++t) {
+    const int i = t * RPB + sub;
+    if (i >= N) continue;
+    double q = 0.0;
+    const int e = rp[i + 1];
+    for (int k = rp[i] + lane; k < e; k += G) {
+      const int j = col[k];
+      q += A[k] * (dinv[j] * s[j]);
+    }
+    q = gsum<G>(q);
+    if (lane == 0) {
+      tv[i] = q;
+      acc[0] += q * s[i];
+      acc[1] += q * q;
+    }
+  }
+  block_partials<2>(acc, 2, partials, blockIdx.x);
+  if (finalize(partials, gridDim.x, 2, counter, ks->red)) {
+    if (threadIdx.x == 0) {
+      const double ts = ks->red[0], tt = ks->red[1];
+      ks->omega = tt != 0.0 ? ts / tt : 0.0;
+      if (!isfinite(ks->omega)) {
+        ks->flag = 2;
+        ks->done = 1;
+      }
+    }
+  }
+}
+
+// x += alpha D^{-1} p + omega D^{-1} s ; r = s - omega t ; rho_new = (rhat, r)
+__global__ __launch_bounds__(kBlock) void k_bicg_xr(int N, const double* __restrict__ dinv,
+                                                    const double* __restrict__ p, const double* __restrict__ s,
+                                                    const double* __restrict__ tv, const double* __restrict__ rhat,
+                                                    double* __restrict__ x, double* __restrict__ r, KState* ks,
+                                                    double* partials, unsigned* counter) {
+  if (ks->done) return;
+  const double alpha = ks->alpha, omega = ks->omega;
+  const bool half = ks->half != 0;
+  double acc[2] = {0.0, 0.0};
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) {
+    const double di = dinv[i];
+    double ri;
+    if (half) {
+      x[i] += alpha * (di * p[i]);
+      ri = s[i];
+    } else {
+      x[i] += alpha * (di * p[i]) + omega * (di * s[i]);
+      ri = s[i] - omega * tv[i];
+    }
+    r[i] = ri;
+    acc[0] += rhat[i] * ri;
+    acc[1] += ri * ri;
+  }
+  block_partials<2>(acc, 2, partials, blockIdx.x);
+  if (finalize(partials, gridDim.x, 2, counter, ks->red)) {
+    if (threadIdx.x == 0) {
+      const double rho_new = ks->red[0];
+      const double res = sqrt(ks->red[1]);
+      ks->iters += 1;
+      ks->res = res;
+      if (!isfinite(res)) {
+        ks->flag = 2;
+        ks->done = 1;
+      } else if (res <= ks->tol) {
+        ks->done = 1;
+      } else if (rho_new == 0.0 || ks->omega == 0.0) {
+        ks->flag = 1;
+        ks->done = 1;
+      } else {
+        ks->bcg_beta = (rho_new / ks->rho) * (ks->alpha / ks->omega);
+        ks->rho = rho_new;
+      }
+    }
+  }
+}
+
+// p = r + beta (p - omega v)
+__global__ __launch_bounds__(kBlock) void k_bicg_p(int N, const double* __restrict__ r, const double* __restrict__ v,
+                                                   double* __restrict__ p, const KState* __restrict__ ks) {
+  if (ks->done) return;
+  const double beta = ks->bcg_beta, omega = ks->omega;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock)
+    p[i] = r[i] + beta * (p[i] - omega * v[i]);
+}
+
+// ---------------------------------------------------------------------------
+// Zalesak FCT, explicit SSP stage (eqs. (18)-(21), limiter steps 1-4)
+// ---------------------------------------------------------------------------
+
+// udot = M_L^{-1} (F - A_low u) (0 on Dirichlet nodes), ut = u + dt udot (u_D)
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_ssp_lowrate(int N, const int* __restrict__ rp,
+                                                        const int* __restrict__ col, const double* __restrict__ AL,
+                                                        const double* __restrict__ u, const double* __restrict__ F,
+                                                        const double* __restrict__ ml,
+                                                        const uint8_t* __restrict__ is_dir,
+                                                        const double* __restrict__ uD, double dt,
+                                                        double* __restrict__ udot, double* __restrict__ ut) {
+  constexpr int RPB = kBlock / G;
+  const int lane = threadIdx.x % G, sub = threadIdx.x / G;
+  int t0, t1;
+  tile_range((N + RPB - 1) / RPB, t0, t1);
+  for (int t = t0; t < t1; ++t) {
+    const int i = t * RPB + sub;
+    if (i >= N) continue;
+    if (is_dir[i]) {
+      if (lane == 0) {
+        udot[i] = 0.0;
+        ut[i] = uD[i];
+      }
+      continue;
+    }
+    double acc = 0.0;
+    const int e = rp[i + 1];
+    for (int k = rp[i] + lane; k < e; k += G) acc += AL[k] * u[col[k]];
+    acc = gsum<G>(acc);
+    if (lane == 0) {
+      const double ud = (F[i] - acc) / ml[i];
+      udot[i] = ud;
+      ut[i] = u[i] + dt * ud;
+    }
+  }
+}
+
+__device__ __forceinline__ double zalesak_R(double mi, double Q, double P, double dt) {
+  return P != 0.0 ? fmin(1.0, mi * Q / (dt * P)) : 1.0;
+}
+
+// P+-, Q+- (from ut) and R+- of the SSP fluxes r_ij = m_ij (udot_i - udot_j) + d_ij (u_j - u_i)
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_ssp_limit_R(int N, const int* __restrict__ rp,
+                                                        const int* __restrict__ col,
+                                                        const double* __restrict__ mij,
+                                                        const double* __restrict__ dp, const double* __restrict__ u,
+                                                        const double* __restrict__ udot,
+                                                        const double* __restrict__ ut, const double* __restrict__ ml,
+                                                        const uint8_t* __restrict__ is_dir, double dt,
+                                                        double* __restrict__ Rp, double* __restrict__ Rm) {
+  constexpr int RPB = kBlock / G;
+  const int lane = threadIdx.x % G, sub = threadIdx.x / G;
+  int t0, t1;
+  tile_range((N + RPB - 1) / RPB, t0, t1);
+  for (int t = t0; t < t1; ++t) {
+    const int i = t * RPB + sub;
+    if (i >= N) continue;
+    if (is_dir[i]) {
+      if (lane == 0) Rp[i] = Rm[i] = 1.0;
+      continue;
+    }
+    const double ui = u[i], udi = udot[i], uti = ut[i];
+    double pp = 0.0, pm = 0.0, qp = 0.0, qm = 0.0;
+    const int e = rp[i + 1];
+    for (int k = rp[i] + lane; k < e; k += G) {
+      const int j = col[k];
+      if (j == i) continue;
+      const double d = -dp[k];
+      const double r = mij[k] * (udi - udot[j]) + d * (u[j] - ui);
+      pp += fmax(r, 0.0);
+      pm += fmin(r, 0.0);
+      const double du = ut[j] - uti;
+      qp = fmax(qp, du);
+      qm = fmin(qm, du);
+    }
+    pp = gsum<G>(pp);
+    pm = gsum<G>(pm);
+    qp = gmax<G>(qp);
+    qm = gmin<G>(qm);
+    if (lane == 0) {
+      Rp[i] = zalesak_R(ml[i], qp, pp, dt);
+      Rm[i] = zalesak_R(ml[i], qm, pm, dt);
+    }
+  }
+}
+
+// F*_i = sum_j alpha_ij r_ij ; out = c0 * base + c1 * (ut + dt F* / m)
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_ssp_apply(
+    int N, const int* __restrict__ rp, const int* __restrict__ col, const double* __restrict__ mij,
+    const double* __restrict__ dp, const double* __restrict__ u, const double* __restrict__ udot,
+    const double* __restrict__ ut, const double* __restrict__ Rp, const double* __restrict__ Rm,
+    const double* __restrict__ ml, const uint8_t* __restrict__ is_dir, const double* __restrict__ uD, double dt,
+    int alpha_mode, const double* __restrict__ base, double c0, double c1, double* __restrict__ out) {
+  constexpr int RPB = kBlock / G;
+  const int lane = threadIdx.x % G, sub = threadIdx.x / G;
+  int t0, t1;
+  tile_range((N + RPB - 1) / RPB, t0, t1);
+  for (int t = t0; t < t1; ++t) {
+    const int i = t * RPB + sub;
+    if (i >= N) continue;
+    if (is_dir[i]) {
+      if (lane == 0) out[i] = uD[i];
+      continue;
+    }
+    double fs = 0.0;
+    if (alpha_mode != AFC_ALPHA_ZERO) {
+      const double ui = u[i], udi = udot[i], rpi = Rp[i], rmi = Rm[i];
+      const int e = rp[i + 1];
+      for (int k = rp[i] + lane; k < e; k += G) {
+        const int j = col[k];
+        if (j == i) continue;
+        const double d = -dp[k];
+        const double r = mij[k] * (udi - udot[j]) + d * (u[j] - ui);
+        double a = 1.0;
+        if (alpha_mode == AFC_ALPHA_LIMITED) a = r > 0.0 ? fmin(rpi, Rm[j]) : fmin(rmi, Rp[j]);
+        fs += a * r;
+      }
+      fs = gsum<G>(fs);
+    }
+    if (lane == 0) {
+      const double unew = ut[i] + dt * fs / ml[i];
+      out[i] = (c0 == 0.0) ? c1 * unew : c0 * base[i] + c1 * unew;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Zalesak FCT, Crank-Nicolson (eqs. (11)-(14))
+// ---------------------------------------------------------------------------
+
+// ut = u_old - dt/2 M_L^{-1} (A_low u_old - F_old) ; g = (M_L/dt - A_low/2) u_old + (F_old + F_new)/2
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_cn_predict(int N, const int* __restrict__ rp,
+                                                       const int* __restrict__ col, const double* __restrict__ AL,
+                                                       const double* __restrict__ uo,
+                                                       const double* __restrict__ Fo, const double* __restrict__ Fn,
+                                                       const double* __restrict__ ml,
+                                                       const uint8_t* __restrict__ is_dir,
+                                                       const double* __restrict__ uD, double dt,
+                                                       double* __restrict__ ut, double* __restrict__ g) {
+  constexpr int RPB = kBlock / G;
+  const int lane = threadIdx.x % G, sub = threadIdx.x / G;
+  int t0, t1;
+  tile_range((N + RPB - 1) / RPB, t0, t1);
+  for (int t = t0; t < t1; ++t) {
+    const int i = t * RPB + sub;
+    if (i >= N) continue;
+    if (is_dir[i]) {
+      if (lane == 0) ut[i] = g[i] = uD[i];
+      continue;
+    }
+    double y = 0.0;
+    const int e = rp[i + 1];
+    for (int k = rp[i] + lane; k < e; k += G) y += AL[k] * uo[col[k]];
+    y = gsum<G>(y);
+    if (lane == 0) {
+      const double mi = ml[i];
+      ut[i] = uo[i] - 0.5 * dt * (y - Fo[i]) / mi;
+      g[i] = mi / dt * uo[i] - 0.5 * y + 0.5 * (Fo[i] + Fn[i]);
+    }
+  }
+}
+
+// Q+-_i = max/min(0, ext_{j != i} (ut_j - ut_i))
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_zalesak_Q(int N, const int* __restrict__ rp, const int* __restrict__ col,
+                                                      const double* __restrict__ ut, double* __restrict__ Qp,
+                                                      double* __restrict__ Qm) {
+  constexpr int RPB = kBlock / G;
+  const int lane = threadIdx.x % G, sub = threadIdx.x / G;
+  int t0, t1;
+  tile_range((N + RPB - 1) / RPB, t0, t1);
+  for (int t = t0; t < t1; ++t) {
+    const int i = t * RPB + sub;
+    if (i >= N) continue;
+    const double uti = ut[i];
+    double qp = 0.0, qm = 0.0;
+    const int e = rp[i + 1];
+    for (int k = rp[i] + lane; k < e; k += G) {
+      const int j = col[k];
+      if (j == i) continue;
+      const double du = ut[j] - uti;
+      qp = fmax(qp, du);
+      qm = fmin(qm, du);
+    }
+    qp = gmax<G>(qp);
+    qm = gmin<G>(qm);
+    if (lane == 0) {
+      Qp[i] = qp;
+      Qm[i] = qm;
+    }
+  }
+}
+
+__device__ __forceinline__ double minmod(double a, double b) {
+  if (a > 0.0 && b > 0.0) return fmin(a, b);
+  if (a < 0.0 && b < 0.0) return fmax(a, b);
+  return 0.0;
+}
+
+// CN flux r_ij of eq. (12), prelimited by eq. (13) (midpoint reading)
+__device__ __forceinline__ double cn_flux(double mij, double d, double inv_dt, double dui, double duj, double sui,
+                                          double suj, double L) {
+  double r = mij * inv_dt * (dui - duj) + 0.5 * d * (suj - sui);
+  if (L != 0.0) r = minmod(r, L * d * (0.5 * suj - 0.5 * sui));
+  return r;
+}
+
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_cn_limit_R(int N, const int* __restrict__ rp,
+                                                       const int* __restrict__ col,
+                                                       const double* __restrict__ mij, const double* __restrict__ dp,
+                                                       const double* __restrict__ u,
+                                                       const double* __restrict__ uo, const double* __restrict__ Qp,
+                                                       const double* __restrict__ Qm, const double* __restrict__ ml,
+                                                       const uint8_t* __restrict__ is_dir, double dt, double L,
+                                                       double* __restrict__ Rp, double* __restrict__ Rm) {
+  constexpr int RPB = kBlock / G;
+  const int lane = threadIdx.x % G, sub = threadIdx.x / G;
+  const double inv_dt = 1.0 / dt;
+  int t0, t1;
+  tile_range((N + RPB - 1) / RPB, t0, t1);
+  for (int t = t0; t < t1; ++t) {
+    const int i = t * RPB + sub;
+    if (i >= N) continue;
+    if (is_dir[i]) {
+      if (lane == 0) Rp[i] = Rm[i] = 1.0;
+      continue;
+    }
+    const double dui = u[i] - uo[i], sui = u[i] + uo[i];
+    double pp = 0.0, pm = 0.0;
+    const int e = rp[i + 1];
+    for (int k = rp[i] + lane; k < e; k += G) {
+      const int j = col[k];
+      if (j == i) continue;
+      const double uj = u[j], uoj = uo[j];
+      const double r = cn_flux(mij[k], -dp[k], inv_dt, dui, uj - uoj, sui, uj + uoj, L);
+      pp += fmax(r, 0.0);
+      pm += fmin(r, 0.0);
+    }
+    pp = gsum<G>(pp);
+    pm = gsum<G>(pm);
+    if (lane == 0) {
+      Rp[i] = zalesak_R(ml[i], Qp[i], pp, dt);
+      Rm[i] = zalesak_R(ml[i], Qm[i], pm, dt);
+    }
+  }
+}
+
+// b = g + F*(u), r = b - A_cn u ; reductions: R^2 (free rows), ||b||^2, ||r||^2
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_cn_apply(
+    int N, const int* __restrict__ rp, const int* __restrict__ col, const double* __restrict__ mij,
+    const double* __restrict__ dp, const double* __restrict__ Acn, const double* __restrict__ u,
+    const double* __restrict__ uo, const double* __restrict__ Rp, const double* __restrict__ Rm,
+    const double* __restrict__ g, const uint8_t* __restrict__ is_dir, const double* __restrict__ uD, double dt,
+    double L, int alpha_mode, double* __restrict__ b, double* __restrict__ r, KState* ks, double* partials,
+    unsigned* counter) {
+  constexpr int RPB = kBlock / G;
+  const int lane = threadIdx.x % G, sub = threadIdx.x / G;
+  const double inv_dt = 1.0 / dt;
+  double acc[3] = {0.0, 0.0, 0.0};
+  int t0, t1;
+  tile_range((N + RPB - 1) / RPB, t0, t1);
+  for (int t = t0; t < t1; ++t) {
+    const int i = t * RPB + sub;
+    if (i >= N) continue;
+    if (is_dir[i]) {
+      if (lane == 0) {
+        const double bi = uD[i], ri = uD[i] - u[i];
+        b[i] = bi;
+        r[i] = ri;
+        acc[1] += bi * bi;
+        acc[2] += ri * ri;
+      }
+      continue;
+    }
+    const double dui = u[i] - uo[i], sui = u[i] + uo[i], rpi = Rp[i], rmi = Rm[i];
+    double fs = 0.0, au = 0.0;
+    const int e = rp[i + 1];
+    for (int k = rp[i] + lane; k < e; k += G) {
+      const int j = col[k];
+      const double uj = u[j];
+      au += Acn[k] * uj;
+      if (j == i || alpha_mode == AFC_ALPHA_ZERO) continue;
+      const double uoj = uo[j];
+      const double rf = cn_flux(mij[k], -dp[k], inv_dt, dui, uj - uoj, sui, uj + uoj, L);
+      double a = 1.0;
+      if (alpha_mode == AFC_ALPHA_LIMITED) a = rf > 0.0 ? fmin(rpi, Rm[j]) : fmin(rmi, Rp[j]);
+      fs += a * rf;
+    }
+    fs = gsum<G>(fs);
+    au = gsum<G>(au);
+    if (lane == 0) {
+      const double bi = g[i] + fs, ri = bi - au;
+      b[i] = bi;
+      r[i] = ri;
+      acc[0] += ri * ri;
+      acc[1] += bi * bi;
+      acc[2] += ri * ri;
+    }
+  }
+  block_partials<3>(acc, 3, partials, blockIdx.x);
+  finalize(partials, gridDim.x, 3, counter, ks->red);
+}
+
+// ---------------------------------------------------------------------------
+// Monolithic convex limiter (eqs. (22)-(23), (25), Remark 1)
+// ---------------------------------------------------------------------------
+
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_mcl_bounds(int N, const int* __restrict__ rp,
+                                                       const int* __restrict__ col, const double* __restrict__ u,
+                                                       double* __restrict__ umax, double* __restrict__ umin) {
+  constexpr int RPB = kBlock / G;
+  const int lane = threadIdx.x % G, sub = threadIdx.x / G;
+  int t0, t1;
+  tile_range((N + RPB - 1) / RPB, t0, t1);
+  for (int t = t0; t < t1; ++t) {
+    const int i = t * RPB + sub;
+    if (i >= N) continue;
+    double mx = -INFINITY, mn = INFINITY;
+    const int e = rp[i + 1];
+    for (int k = rp[i] + lane; k < e; k += G) {
+      const double uj = u[col[k]];
+      mx = fmax(mx, uj);
+      mn = fmin(mn, uj);
+    }
+    mx = gmax<G>(mx);
+    mn = gmin<G>(mn);
+    if (lane == 0) {
+      umax[i] = mx;
+      umin[i] = mn;
+    }
+  }
+}
+
+// r*_ij from d_ij = -max(c_ij, 0, c_ji) and the bar states in product form
+// 2 d_ij ubar_ij = d_ij (u_i + u_j) + c_ij (u_j - u_i); F*_i = sum_j r*_ij;
+// b = F + F*, r = b - A_low u ; reductions: R^2 (free rows), ||b||^2, ||r||^2
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_mcl_apply(
+    int N, const int* __restrict__ rp, const int* __restrict__ col, const double* __restrict__ cc,
+    const double* __restrict__ ccT, const double* __restrict__ AL, const double* __restrict__ u,
+    const double* __restrict__ umax, const double* __restrict__ umin, const double* __restrict__ F,
+    const uint8_t* __restrict__ is_dir, const double* __restrict__ uD, int alpha_mode, double* __restrict__ b,
+    double* __restrict__ r, KState* ks, double* partials, unsigned* counter) {
+  constexpr int RPB = kBlock / G;
+  const int lane = threadIdx.x % G, sub = threadIdx.x / G;
+  double acc[3] = {0.0, 0.0, 0.0};
+  int t0, t1;
+  tile_range((N + RPB - 1) / RPB, t0, t1);
+  for (int t = t0; t < t1; ++t) {
+    const int i = t * RPB + sub;
+    if (i >= N) continue;
+    if (is_dir[i]) {
+      if (lane == 0) {
+        const double bi = uD[i], ri = uD[i] - u[i];
+        b[i] = bi;
+        r[i] = ri;
+        acc[1] += bi * bi;
+        acc[2] += ri * ri;
+      }
+      continue;
+    }
+    const double ui = u[i], umaxi = umax[i], umini = umin[i];
+    double fs = 0.0, au = 0.0;
+    const int e = rp[i + 1];
+    for (int k = rp[i] + lane; k < e; k += G) {
+      const int j = col[k];
+      const double uj = u[j];
+      au += AL[k] * uj;
+      if (j == i || alpha_mode == AFC_ALPHA_ZERO) continue;
+      const double c = cc[k], ct = ccT[k];
+      const double d = -fmax(fmax(c, 0.0), ct);
+      if (d == 0.0) continue;
+      const double rf = d * (uj - ui);
+      if (alpha_mode == AFC_ALPHA_ONE) {
+        fs += rf;
+        continue;
+      }
+      const double sij = d * (ui + uj) + c * (uj - ui);
+      const double sji = d * (ui + uj) + ct * (ui - uj);
+      const double two_d = 2.0 * d;
+      double rs;
+      if (rf > 0.0)
+        rs = fmin(rf, fmin(sij - two_d * umaxi, two_d * umin[j] - sji));
+      else
+        rs = fmax(rf, fmax(sij - two_d * umini, two_d * umax[j] - sji));
+      fs += rs;
+    }
+    fs = gsum<G>(fs);
+    au = gsum<G>(au);
+    if (lane == 0) {
+      const double bi = F[i] + fs, ri = bi - au;
+      b[i] = bi;
+      r[i] = ri;
+      acc[0] += ri * ri;
+      acc[1] += bi * bi;
+      acc[2] += ri * ri;
+    }
+  }
+  block_partials<3>(acc, 3, partials, blockIdx.x);
+  finalize(partials, gridDim.x, 3, counter, ks->red);
+}
+
+// ---------------------------------------------------------------------------
+// launch helpers
+// ---------------------------------------------------------------------------
+
+int row_grid(const H* h, bool reduce) {
+  const int rpb = kBlock / h->G;
+  const int nt = (h->N + rpb - 1) / rpb;
+  return std::max(1, std::min(nt, reduce ? kRedBlocks : kRowGridCap));
+}
+
+int vec_grid(const H* h) { return std::max(1, std::min((h->N + kBlock - 1) / kBlock, kRedBlocks)); }
+
+#define AFC_DISPATCH_G(h, KERNEL, GRID, ...)                                                   \
+  do {                                                                                           \
+    switch ((h)->G) {                                                                            \
+      case 8: KERNEL<8><<<(GRID), kBlock, 0, (h)->stream>>>(__VA_ARGS__); break;                 \
+      case 16: KERNEL<16><<<(GRID), kBlock, 0, (h)->stream>>>(__VA_ARGS__); break;               \
+      case 32: KERNEL<32><<<(GRID), kBlock, 0, (h)->stream>>>(__VA_ARGS__); break;               \
+      default: KERNEL<64><<<(GRID), kBlock, 0, (h)->stream>>>(__VA_ARGS__); break;               \
+    }                                                                                            \
+  } while (0)
+
+}  // namespace
+
+void copy(H* h, double* dst, const double* src) { k_copy<<<vec_grid(h), kBlock, 0, h->stream>>>(h->N, dst, src); }
+
+void set_dirichlet(H* h, double* u) {
+  k_set_dirichlet<<<vec_grid(h), kBlock, 0, h->stream>>>(h->N, u, h->is_dir, h->uD);
+}
+
+void rhs_dirichlet(H* h, double* b, const double* F) {
+  k_rhs_dirichlet<<<vec_grid(h), kBlock, 0, h->stream>>>(h->N, b, F, h->is_dir, h->uD);
+}
+
+void fill(H* h, double* u, double v) { k_fill<<<vec_grid(h), kBlock, 0, h->stream>>>(h->N, u, v); }
+
+void norm2(H* h, const double* x, int red_idx) {
+  k_norm2<<<vec_grid(h), kBlock, 0, h->stream>>>(h->N, x, h->ks, red_idx, h->partials, h->counters);
+}
+
+void relax(H* h, double* u, const double* x, double omega) {
+  k_relax<<<vec_grid(h), kBlock, 0, h->stream>>>(h->N, u, x, omega);
+}
+
+void build_cn_matrix(H* h, double dt) {
+  AFC_DISPATCH_G(h, k_build_cn, row_grid(h, false), h->N, h->row_ptr, h->col, h->AL_fct, h->ml, h->is_dir,
+                 1.0 / dt, h->A_cn, h->dinv_cn);
+  AFC_DISPATCH_G(h, k_scale32, row_grid(h, false), h->N, h->row_ptr, h->col, h->A_cn, h->dinv_cn, h->A32_cn);
+}
+
+void residual(H* h, const double* A, const double* b, const double* x, double* r, int mode, double tol_abs,
+              double tol_rel) {
+  AFC_DISPATCH_G(h, k_residual, row_grid(h, true), h->N, h->row_ptr, h->col, A, b, x, r, h->ks, h->partials,
+                 h->counters, mode, tol_abs, tol_rel);
+}
+
+void cycle_start(H* h, int mode, int red_idx, double tol_abs, double tol_rel) {
+  k_cycle_start<<<1, 64, 0, h->stream>>>(h->ks, mode, red_idx, tol_abs, tol_rel);
+}
+
+void cast_v0(H* h, const double* r) { k_cast_v0<<<vec_grid(h), kBlock, 0, h->stream>>>(h->N, r, h->V32, h->ks); }
+
+void gmres_spmv64(H* h, const double* A, const double* dinv, int k) {
+  const size_t N = (size_t)h->N;
+  double* W = h->w[0];
+  const double* x = h->V64 + (size_t)k * N;
+  const double* mul = &h->ks->sc[k];
+  switch (h->G) {
+    case 8: k_spmv64<8, true><<<row_grid(h, false), kBlock, 0, h->stream>>>(h->N, h->row_ptr, h->col, A, dinv, x, mul, W, &h->ks->done); break;
+    case 16: k_spmv64<16, true><<<row_grid(h, false), kBlock, 0, h->stream>>>(h->N, h->row_ptr, h->col, A, dinv, x, mul, W, &h->ks->done); break;
+    case 32: k_spmv64<32, true><<<row_grid(h, false), kBlock, 0, h->stream>>>(h->N, h->row_ptr, h->col, A, dinv, x, mul, W, &h->ks->done); break;
+    default: k_spmv64<64, true><<<row_grid(h, false), kBlock, 0, h->stream>>>(h->N, h->row_ptr, h->col, A, dinv, x, mul, W, &h->ks->done); break;
+  }
+}
+
+void gmres_spmv32(H* h, const float* A32, int k) {
+  const size_t N = (size_t)h->N;
+  float* W = reinterpret_cast<float*>(h->w[0]);
+  const float* x = h->V32 + (size_t)k * N;
+  AFC_DISPATCH_G(h, k_spmv32, row_grid(h, false), h->N, h->row_ptr, h->col, A32, x, &h->ks->sc[k], W,
+                 &h->ks->done);
+}
+
+namespace {
+template <typename T>
+void launch_dots(H* h, const T* V, const T* W, int k, int m) {
+  const int g = vec_grid(h);
+  const int nv = k + 1;
+  if (nv <= 8)
+    k_gmres_dots<T, 8><<<g, kBlock, 0, h->stream>>>(h->N, V, W, k, m, h->ks, h->partials, h->counters);
+  else if (nv <= 16)
+    k_gmres_dots<T, 16><<<g, kBlock, 0, h->stream>>>(h->N, V, W, k, m, h->ks, h->partials, h->counters);
+  else if (nv <= 32)
+    k_gmres_dots<T, 32><<<g, kBlock, 0, h->stream>>>(h->N, V, W, k, m, h->ks, h->partials, h->counters);
+  else
+    k_gmres_dots<T, 64><<<g, kBlock, 0, h->stream>>>(h->N, V, W, k, m, h->ks, h->partials, h->counters);
+}
+template <typename T>
+void launch_update(H* h, T* V, const T* W, int k, int m) {
+  const int g = vec_grid(h);
+  const int nv = k + 1;
+  if (nv <= 8)
+    k_gmres_update<T, 8><<<g, kBlock, 0, h->stream>>>(h->N, V, W, k, m, h->ks, h->partials, h->counters);
+  else if (nv <= 16)
+    k_gmres_update<T, 16><<<g, kBlock, 0, h->stream>>>(h->N, V, W, k, m, h->ks, h->partials, h->counters);
+  else if (nv <= 32)
+    k_gmres_update<T, 32><<<g, kBlock, 0, h->stream>>>(h->N, V, W, k, m, h->ks, h->partials, h->counters);
+  else
+    k_gmres_update<T, 64><<<g, kBlock, 0, h->stream>>>(h->N, V, W, k, m, h->ks, h->partials, h->counters);
+}
+}  // namespace
+
+void gmres_dots(H* h, bool fp32, int k, int m) {
+  if (fp32)
+    launch_dots<float>(h, h->V32, reinterpret_cast<const float*>(h->w[0]), k, m);
+  else
+    launch_dots<double>(h, h->V64, h->w[0], k, m);
+}
+
+void gmres_update(H* h, bool fp32, int k, int m) {
+  if (fp32)
+    launch_update<float>(h, h->V32, reinterpret_cast<const float*>(h->w[0]), k, m);
+  else
+    launch_update<double>(h, h->V64, h->w[0], k, m);
+}
+
+void gmres_solve(H* h, int m) { k_gmres_solve<<<1, 64, 0, h->stream>>>(h->ks, m); }
+
+void gmres_xupdate(H* h, bool fp32, const double* dinv, double* x) {
+  if (fp32)
+    k_gmres_xupdate<float><<<vec_grid(h), kBlock, 0, h->stream>>>(h->N, h->V32, dinv, x, h->ks);
+  else
+    k_gmres_xupdate<double><<<vec_grid(h), kBlock, 0, h->stream>>>(h->N, h->V64, dinv, x, h->ks);
+}
+
+void bicg_init(H* h, const BicgVec& b, double tol) {
+  k_bicg_init<<<vec_grid(h), kBlock, 0, h->stream>>>(h->N, b.r, b.rhat, b.p, b.v, h->ks, h->partials, h->counters,
+                                                     tol);
+}
+
+void bicg_iter(H* h, const double* A, const double* dinv, const BicgVec& b) {
+  AFC_DISPATCH_G(h, k_bicg_v, row_grid(h, true), h->N, h->row_ptr, h->col, A, dinv, b.p, b.rhat, b.v, h->ks,
+                 h->partials, h->counters);
+  k_bicg_s<<<vec_grid(h), kBlock, 0, h->stream>>>(h->N, b.r, b.v, b.s, h->ks, h->partials, h->counters);
+  AFC_DISPATCH_G(h, k_bicg_t, row_grid(h, true), h->N, h->row_ptr, h->col, A, dinv, b.s, b.t, h->ks, h->partials,
+                 h->counters);
+  k_bicg_xr<<<vec_grid(h), kBlock, 0, h->stream>>>(h->N, dinv, b.p, b.s, b.t, b.rhat, b.x, b.r, h->ks, h->partials,
+                                                   h->counters);
+  k_bicg_p<<<vec_grid(h), kBlock, 0, h->stream>>>(h->N, b.r, b.v, b.p, h->ks);
+}
+
+void ssp_lowrate(H* h, const double* u, const double* F, double dt, double* udot, double* ut) {
+  AFC_DISPATCH_G(h, k_ssp_lowrate, row_grid(h, false), h->N, h->row_ptr, h->col, h->AL_fct, u, F, h->ml, h->is_dir,
+                 h->uD, dt, udot, ut);
+}
+
+void ssp_limit_R(H* h, const double* u, const double* udot, const double* ut, double dt, double* Rp, double* Rm) {
+  AFC_DISPATCH_G(h, k_ssp_limit_R, row_grid(h, false), h->N, h->row_ptr, h->col, h->mij, h->dp_fct, u, udot, ut,
+                 h->ml, h->is_dir, dt, Rp, Rm);
+}
+
+void ssp_apply(H* h, const double* u, const double* udot, const double* ut, const double* Rp, const double* Rm,
+               double dt, const double* base, double c0, double c1, double* out) {
+  AFC_DISPATCH_G(h, k_ssp_apply, row_grid(h, false), h->N, h->row_ptr, h->col, h->mij, h->dp_fct, u, udot, ut, Rp,
+                 Rm, h->ml, h->is_dir, h->uD, dt, h->opt.alpha_mode, base, c0, c1, out);
+}
+
+void cn_predict(H* h, const double* u_old, const double* F_old, const double* F_new, double dt, double* ut,
+                double* g) {
+  AFC_DISPATCH_G(h, k_cn_predict, row_grid(h, false), h->N, h->row_ptr, h->col, h->AL_fct, u_old, F_old, F_new,
+                 h->ml, h->is_dir, h->uD, dt, ut, g);
+}
+
+void zalesak_Q(H* h, const double* ut, double* Qp, double* Qm) {
+  AFC_DISPATCH_G(h, k_zalesak_Q, row_grid(h, false), h->N, h->row_ptr, h->col, ut, Qp, Qm);
+}
+
+void cn_limit_R(H* h, const double* u, const double* u_old, const double* Qp, const double* Qm, double dt,
+                double* Rp, double* Rm) {
+  AFC_DISPATCH_G(h, k_cn_limit_R, row_grid(h, false), h->N, h->row_ptr, h->col, h->mij, h->dp_fct, u, u_old, Qp,
+                 Qm, h->ml, h->is_dir, dt, h->opt.prelimit, Rp, Rm);
+}
+
+void cn_apply(H* h, const double* u, const double* u_old, const double* Rp, const double* Rm, const double* g,
+              double dt, double* b, double* r) {
+  AFC_DISPATCH_G(h, k_cn_apply, row_grid(h, true), h->N, h->row_ptr, h->col, h->mij, h->dp_fct, h->A_cn, u, u_old,
+                 Rp, Rm, g, h->is_dir, h->uD, dt, h->opt.prelimit, h->opt.alpha_mode, b, r, h->ks, h->partials,
+                 h->counters);
+}
+
+void mcl_bounds(H* h, const double* u, double* umax, double* umin) {
+  AFC_DISPATCH_G(h, k_mcl_bounds, row_grid(h, false), h->N, h->row_ptr, h->col, u, umax, umin);
+}
+
+void mcl_apply(H* h, const double* u, const double* umax, const double* umin, const double* F, double* b, double* r) {
+  AFC_DISPATCH_G(h, k_mcl_apply, row_grid(h, true), h->N, h->row_ptr, h->col, h->cc, h->ccT, h->AL_mcl, u, umax,
+                 umin, F, h->is_dir, h->uD, h->opt.alpha_mode, b, r, h->ks, h->partials, h->counters);
+}
+
+}  // namespace afc
