@@ -1,0 +1,228 @@
+#!/usr/bin/env python3
+"""Throughput of the AFC hot path on one MI355X.
+
+Workload: the stationary monolithic-convex-limiter (MCL) problem on Q1
+128^3 (2,146,689 nodes, 57,066,625 nonzeros): eps = 1e-6, b = (1,1,1)/sqrt(3),
+c = 1, f = 1 on [0.25, 0.5]^3, u = 0 on the boundary.  One step is one
+fixed-point iteration of the paper's scheme (Sec. 4): MCL bounds, limited
+fluxes and the FP64 nonlinear residual, then the linear solve of the
+low-order matrix to ||b - A x|| <= 1e-10 ||b|| with GMRES(30)-Jacobi, FP32
+Arnoldi inside FP64 iterative refinement.  Steps continue from the low-order
+solution (computed before timing).  value = nodes x steps / seconds
+(DOF-iterations/s).
+
+Also reported: the plain-FP64 GMRES rate, Krylov iterations per step, the
+roofline of the dominant kernel (FP32 CSR SpMV) from HIP-event timings taken
+live in this process, and the FP64 CPU oracle timed on a bounded sample.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "spmv32_stream_q1_128_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2110_15676_amd", "csrc", "afc_kernels.hip")
+
+
+def kernel_source_hash():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def spmv32_bytes(N, nnz):
+    """Algorithmic bytes of one FP32 CSR SpMV: values + column indices, row
+    pointers, one read of x and one write of y (4-byte words)."""
+    return 8 * nnz + 4 * (N + 1) + 4 * N + 4 * N
+
+
+def step_model_bytes(N, nnz, krylov, sweeps, steps):
+    """Algorithmic HBM bytes of `steps` fixed-point iterations (model)."""
+    L = krylov / max(sweeps, 1)  # mean FP32 GMRES cycle length
+    kbar = (L - 1) / 2.0         # mean Arnoldi index inside a cycle
+    per_it = spmv32_bytes(N, nnz) + (kbar + 2) * 4 * N + (kbar + 3) * 4 * N
+    per_sweep = 12 * nnz + 4 * (N + 1) + 24 * N + kbar * 4 * N + 16 * N + 12 * N
+    per_fp = (4 * nnz + 4 * (N + 1) + 24 * N) + (28 * nnz + 4 * (N + 1) + 57 * N)
+    return krylov * per_it + sweeps * per_sweep + steps * per_fp
+
+
+def cpu_baseline(seconds):
+    """The FP64 oracle on a bounded sample: fixed-point iterations of the same
+    problem on the 32^3 mesh, from its low-order solution, single thread."""
+    import numpy as np  # noqa: F401
+    from threadpoolctl import threadpool_limits
+
+    from oracle import afc_oracle as O
+    from paper_2110_15676_amd import inputs as I
+
+    n = 32
+    inst = I.config3(n)
+    with threadpool_limits(1):
+        P = O.problem_from_instance(inst, conv=True)
+        lo = O.low_order_solution(P, inst.F, lin_rtol=1e-12)
+        t = time.perf_counter()
+        O.stationary_mcl(P, inst.F, lo.x, tol=0.0, tol_mode="rel", maxit=1, lin_rtol=1e-10)
+        t1 = time.perf_counter() - t
+        its = max(1, min(200, int(seconds / max(t1, 1e-3))))
+        t = time.perf_counter()
+        _, st = O.stationary_mcl(P, inst.F, lo.x, tol=0.0, tol_mode="rel", maxit=its, lin_rtol=1e-10)
+        dt = time.perf_counter() - t
+    return {
+        "value": inst.N * st.iters / dt,
+        "unit": "DOF-iterations/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": "%d fixed-point iterations (%d GMRES(30) iterations) of the same MCL problem on Q1 %d^3 "
+                  "(%d nodes) from its low-order solution, numpy FP64, one thread; %.1f s"
+                  % (st.iters, sum(st.krylov_iters), n, inst.N, dt),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=128, help="cells per direction (128 is the workload)")
+    ap.add_argument("--fp64-steps", type=int, default=5)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2110_15676_amd import afc
+    from paper_2110_15676_amd import inputs as I
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    print("bench: building Q1 %d^3 MCL instance" % args.n, file=sys.stderr, flush=True)
+    inst = I.config3(args.n)
+    N, nnz = inst.N, inst.nnz
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def opts(**kw):
+        o = afc.afc_default_options(precision=afc.AFC_PREC_MIXED, krylov=afc.AFC_KRYLOV_GMRES, restart=30,
+                                    fp_tol=0.0, fp_tol_mode=afc.AFC_TOL_REL, lin_atol=0.0, lin_rtol=1e-10,
+                                    lin_maxit=100000, **kw)
+        o.stream = stream
+        return o
+
+    h = afc.afc_create_instance(inst, opts(fp_maxit=0), conv=True)
+    u = torch.zeros(N, dtype=torch.float64, device=dev)
+    F = torch.tensor(inst.F, device=dev)
+    afc.afc_solve_stationary(h, u, F, init_low_order=True)  # low-order start, not timed
+    print("bench: warmup %d" % args.warmup, file=sys.stderr, flush=True)
+    if args.warmup > 0:
+        afc.afc_set_options(h, opts(fp_maxit=args.warmup))
+        afc.afc_solve_stationary(h, u, F)
+
+    # --- timed region: exactly `steps` fixed-point iterations ---------------
+    afc.afc_set_options(h, opts(fp_maxit=args.steps))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, s = afc.afc_solve_stationary(h, u, F)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    assert s["fp_iters"] == args.steps, s
+    value = N * args.steps / elapsed
+    ms_per_step = 1e3 * elapsed / args.steps
+    model_bytes = step_model_bytes(N, nnz, s["krylov_iters"], s["refine_sweeps"], args.steps)
+    print("bench: %.1f ms/step, %d Krylov its" % (ms_per_step, s["krylov_iters"]), file=sys.stderr, flush=True)
+
+    # --- the same steps again with per-kernel HIP events (roofline) ----------
+    afc.afc_set_options(h, opts(fp_maxit=args.steps, profile=1))
+    for kid in range(afc.AFC_KERNEL_COUNT):
+        afc.afc_kernel_time(h, kid, reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st2, s2 = afc.afc_solve_stationary(h, u, F)
+    torch.cuda.synchronize()
+    elapsed_prof = time.perf_counter() - t0
+    spmv_ms, spmv_launches = afc.afc_kernel_time(h, afc.AFC_KERNEL_SPMV32)
+    kernel_ms = {name: afc.afc_kernel_time(h, kid)[0] for name, kid in (
+        ("spmv32", afc.AFC_KERNEL_SPMV32), ("dots", afc.AFC_KERNEL_DOTS), ("update", afc.AFC_KERNEL_UPDATE),
+        ("residual", afc.AFC_KERNEL_RESIDUAL), ("mcl", afc.AFC_KERNEL_MCL), ("finish", afc.AFC_KERNEL_FINISH))}
+    # launches after convergence of a cycle are no-ops; divide by SpMVs performed
+    spmv_avg_s = 1e-3 * spmv_ms / max(1, s2["krylov_iters"])
+    spmv_b = spmv32_bytes(N, nnz)
+    achieved = spmv_b / spmv_avg_s / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as f:
+            tr = json.load(f)
+        if tr.get("kernel_source_sha") == kernel_source_hash() and tr.get("nnz") == nnz:
+            traffic = tr.get("bytes_per_launch")
+    roofline = {
+        "kernel": "k_spmv32_stream (FP32 CSR SpMV, GMRES inner)",
+        "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+        "bytes_per_launch": spmv_b, "avg_launch_us": round(spmv_avg_s * 1e6, 2),
+        "launches": spmv_launches, "spmv_performed": s2["krylov_iters"],
+        "kernel_ms_per_step": {k: round(v / args.steps, 3) for k, v in kernel_ms.items()},
+        "profiled_ms_per_step": round(1e3 * elapsed_prof / args.steps, 3),
+    }
+
+    # --- plain FP64 GMRES for comparison (secondary) ------------------------
+    fp64 = None
+    if args.fp64_steps > 0:
+        o = opts(fp_maxit=args.fp64_steps)
+        o.precision = afc.AFC_PREC_FP64
+        afc.afc_set_options(h, o)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, s3 = afc.afc_solve_stationary(h, u, F)
+        torch.cuda.synchronize()
+        e3 = time.perf_counter() - t0
+        fp64 = {"value": N * s3["fp_iters"] / e3, "ms_per_step": 1e3 * e3 / max(1, s3["fp_iters"]),
+                "krylov_per_step": s3["krylov_iters"] / max(1, s3["fp_iters"]), "steps": s3["fp_iters"]}
+    afc.afc_destroy(h)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("bench: cpu baseline", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(args.cpu_seconds)
+
+    line = {
+        "metric": "AFC DOF-iterations/s at 128^3 Q1 (stationary MCL fixed-point iterations)",
+        "value": value,
+        "unit": "DOF-iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 limiter/outer + f32 Krylov inner",
+        "data": "synthetic",
+        "config": {
+            "workload": "stationary MCL, Q1 %d^3 (%d nodes, %d nnz), eps=1e-6, b=(1,1,1)/sqrt3, c=1, "
+                        "f=1 on [0.25,0.5]^3, u=0 on the boundary; fixed-point iterations from the low-order "
+                        "solution, GMRES(30)-Jacobi FP32 inner + FP64 refinement to 1e-10 ||b||" % (args.n, N, nnz),
+            "nodes": N, "nnz": nnz, "parallelism": "1 GPU",
+        },
+        "krylov_per_step": s["krylov_iters"] / args.steps,
+        "refine_sweeps_per_step": s["refine_sweeps"] / args.steps,
+        "dof_krylov_its_per_s": N * s["krylov_iters"] / elapsed,
+        "hbm_gbs_model": model_bytes / elapsed / 1e9,
+        "nonlinear_residual": {"first": s["res0"], "last": s["res"]},
+        "fp64": fp64,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

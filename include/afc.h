@@ -110,8 +110,22 @@ typedef struct {
   int32_t ssp_stages;       /* 3: Shu-Osher SSP-RK3; 2: Heun (paper); 1: one
                                forward-Euler stage of eq. (18)                 */
   int32_t lanes_per_row;    /* 0 = automatic; else 8, 16, 32 or 64             */
+  int32_t profile;          /* 1: time every launch of the hot kernels with HIP
+                               events on the handle's stream (afc_kernel_time) */
   void *stream;             /* hipStream_t; NULL = default stream              */
 } afc_options;
+
+/* Kernel classes timed when afc_options.profile is set. */
+enum {
+  AFC_KERNEL_SPMV32 = 0,    /* FP32 CSR SpMV of the mixed-precision GMRES      */
+  AFC_KERNEL_SPMV64 = 1,    /* FP64 CSR SpMV (Jacobi-scaled) of FP64 GMRES     */
+  AFC_KERNEL_DOTS = 2,      /* GMRES Gram-Schmidt projections                  */
+  AFC_KERNEL_UPDATE = 3,    /* GMRES orthogonalization update + norm           */
+  AFC_KERNEL_RESIDUAL = 4,  /* FP64 residual b - A x                           */
+  AFC_KERNEL_MCL = 5,       /* MCL bounds + limited fluxes + residual          */
+  AFC_KERNEL_FINISH = 6,    /* reduction finish (scalar solver steps)          */
+  AFC_KERNEL_COUNT = 7
+};
 
 typedef struct {
   int32_t status;           /* same as the return value                        */
@@ -164,6 +178,12 @@ afc_status afc_step_cn(afc_handle *h, double *u, const double *F_old, const doub
  * low-order solution A_low u = F.  F: load vector (device). */
 afc_status afc_solve_stationary(afc_handle *h, double *u, const double *F, int32_t init_low_order,
                                 afc_stats *stats);
+
+/* Accumulated HIP-event time (milliseconds) and launch count of one kernel
+ * class since the handle was created or the last reset (reset != 0 clears
+ * the counters after reading).  Only launches made while options.profile was
+ * set are counted.  Returns EINVAL for an unknown kernel id. */
+afc_status afc_kernel_time(afc_handle *h, int32_t kernel, double *total_ms, int64_t *launches, int32_t reset);
 
 /* Release every device and host resource of h (NULL is ignored). */
 void afc_destroy(afc_handle *h);

@@ -43,7 +43,7 @@ class afc_options(ctypes.Structure):
         ("inner_rtol", c_double), ("inner_maxit", c_int32), ("refine_maxit", c_int32),
         ("fp_tol", c_double), ("fp_tol_mode", c_int32), ("fp_maxit", c_int32),
         ("prelimit", c_double), ("omega", c_double), ("dynamic_damping", c_int32),
-        ("ssp_stages", c_int32), ("lanes_per_row", c_int32), ("stream", c_void_p),
+        ("ssp_stages", c_int32), ("lanes_per_row", c_int32), ("profile", c_int32), ("stream", c_void_p),
     ]
 
 
@@ -59,8 +59,11 @@ class afc_stats(ctypes.Structure):
 
 EXPORTS = [
     "afc_default_options", "afc_create", "afc_set_options", "afc_step_ssprk3", "afc_step_cn",
-    "afc_solve_stationary", "afc_destroy", "afc_status_str", "afc_last_error",
+    "afc_solve_stationary", "afc_destroy", "afc_status_str", "afc_last_error", "afc_kernel_time",
 ]
+
+AFC_KERNEL_SPMV32, AFC_KERNEL_SPMV64, AFC_KERNEL_DOTS, AFC_KERNEL_UPDATE = 0, 1, 2, 3
+AFC_KERNEL_RESIDUAL, AFC_KERNEL_MCL, AFC_KERNEL_FINISH, AFC_KERNEL_COUNT = 4, 5, 6, 7
 
 _lib = None
 
@@ -84,6 +87,8 @@ def lib():
         L.afc_step_cn.restype = c_int32
         L.afc_solve_stationary.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, POINTER(afc_stats)]
         L.afc_solve_stationary.restype = c_int32
+        L.afc_kernel_time.argtypes = [c_void_p, c_int32, POINTER(c_double), POINTER(c_int64), c_int32]
+        L.afc_kernel_time.restype = c_int32
         L.afc_destroy.argtypes = [c_void_p]
         L.afc_destroy.restype = None
         L.afc_status_str.argtypes = [c_int32]
@@ -209,6 +214,16 @@ def afc_solve_stationary(h, u, F, init_low_order=False, raise_on_error=True):
     stats = afc_stats()
     st = lib().afc_solve_stationary(h, u.data_ptr(), F.data_ptr(), int(bool(init_low_order)), ctypes.byref(stats))
     return _finish(h, st, stats, raise_on_error)
+
+
+def afc_kernel_time(h, kernel, reset=False):
+    """(total milliseconds, launches) of one kernel class timed with HIP events."""
+    ms = c_double()
+    n = c_int64()
+    st = lib().afc_kernel_time(h, int(kernel), ctypes.byref(ms), ctypes.byref(n), int(bool(reset)))
+    if st != AFC_OK:
+        raise AFCError(st, "afc_kernel_time")
+    return ms.value, n.value
 
 
 def afc_destroy(h):

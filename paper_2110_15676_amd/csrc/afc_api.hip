@@ -61,6 +61,7 @@ afc_status check_options(const afc_options& o, std::string& why) {
   if (!(o.prelimit >= 0) || !std::isfinite(o.prelimit)) return why = "prelimit", AFC_EINVAL;
   if (!(o.omega > 0 && o.omega <= 1)) return why = "omega must be in (0, 1]", AFC_EINVAL;
   if (o.ssp_stages < 1 || o.ssp_stages > 3) return why = "ssp_stages must be 1, 2 or 3", AFC_EINVAL;
+  if (o.profile != 0 && o.profile != 1) return why = "profile must be 0 or 1", AFC_EINVAL;
   if (o.lanes_per_row != 0 && o.lanes_per_row != 8 && o.lanes_per_row != 16 && o.lanes_per_row != 32 &&
       o.lanes_per_row != 64)
     return why = "lanes_per_row must be 0, 8, 16, 32 or 64", AFC_EINVAL;
@@ -115,15 +116,17 @@ void free_all(afc_handle* h) {
   for (auto*& p : h->w) f(p);
   h->w.clear();
   f(h->V64); f(h->V32);
-  f(h->partials); f(h->counters); f(h->ks);
+  f(h->partials); f(h->ks);
   if (h->host_status) (void)hipHostFree(h->host_status);
   h->host_status = nullptr;
+  afc::prof_release(h);
 }
 
 void sync_status(afc_handle* h) {
   HIP_OK(hipGetLastError());
   HIP_OK(hipMemcpyAsync(h->host_status, h->ks, afc::kStatusBytes, hipMemcpyDeviceToHost, h->stream));
   HIP_OK(hipStreamSynchronize(h->stream));
+  if (!h->ev_pending.empty()) afc::prof_collect(h);
 }
 
 void ensure_basis(afc_handle* h, int m, bool fp32) {
@@ -134,9 +137,15 @@ void ensure_basis(afc_handle* h, int m, bool fp32) {
     h->V32 = nullptr;
     h->Vm = m;
   }
-  const size_t n = (size_t)(h->Vm + 1) * (size_t)h->N;
-  if (fp32 && !h->V32) h->V32 = dalloc<float>(h, n);
-  if (!fp32 && !h->V64) h->V64 = dalloc<double>(h, n);
+  const size_t n = (size_t)(h->Vm + 1) * (size_t)h->ldv;
+  if (fp32 && !h->V32) {
+    h->V32 = dalloc<float>(h, n);
+    HIP_OK(hipMemsetAsync(h->V32, 0, n * sizeof(float), h->stream));
+  }
+  if (!fp32 && !h->V64) {
+    h->V64 = dalloc<double>(h, n);
+    HIP_OK(hipMemsetAsync(h->V64, 0, n * sizeof(double), h->stream));
+  }
 }
 
 struct SysMat {
@@ -352,7 +361,10 @@ afc_status fixed_point(afc_handle* h, double* u, const SysMat& S, Eval eval, afc
 void ensure_work(afc_handle* h) {
   if ((int)h->w.size() == W_COUNT) return;
   h->w.assign(W_COUNT, nullptr);
-  for (int s = 0; s < W_COUNT; ++s) h->w[s] = dalloc<double>(h, (size_t)h->N);
+  for (int s = 0; s < W_COUNT; ++s) {
+    h->w[s] = dalloc<double>(h, (size_t)h->ldv);
+    HIP_OK(hipMemsetAsync(h->w[s], 0, (size_t)h->ldv * sizeof(double), h->stream));
+  }
 }
 
 afc_status guard(afc_handle* h, afc_stats* st, afc_status (*body)(afc_handle*, void*), void* ctx) {
@@ -460,6 +472,7 @@ afc_status afc_create(const afc_problem* p, const afc_options* opt, afc_handle**
     const int N = p->n;
     const int64_t nnz = p->nnz;
     h->N = N;
+    h->ldv = (N + 63) / 64 * 64;
     h->nnz = nnz;
     h->n_dir = p->n_dir;
     h->G = pick_lanes(nnz, N, o.lanes_per_row);
@@ -579,8 +592,6 @@ afc_status afc_create(const afc_problem* p, const afc_options* opt, afc_handle**
     h->dinv_cn = dalloc<double>(h, (size_t)N);
     // solver state
     h->partials = dalloc<double>(h, (size_t)kMaxRed * kRedBlocks);
-    h->counters = dalloc<unsigned>(h, 16);
-    HIP_OK(hipMemset(h->counters, 0, 16 * sizeof(unsigned)));
     h->ks = dalloc<KState>(h, 1);
     HIP_OK(hipMemset(h->ks, 0, sizeof(KState)));
     if (hipHostMalloc((void**)&h->host_status, sizeof(KState), hipHostMallocDefault) != hipSuccess)
@@ -599,6 +610,20 @@ afc_status afc_create(const afc_problem* p, const afc_options* opt, afc_handle**
     return AFC_ENOMEM;
   }
   *out = h;
+  return AFC_OK;
+}
+
+afc_status afc_kernel_time(afc_handle* h, int32_t kernel, double* total_ms, int64_t* launches, int32_t reset) {
+  if (!h || kernel < 0 || kernel >= AFC_KERNEL_COUNT) return AFC_EINVAL;
+  (void)hipSetDevice(h->device);
+  (void)hipStreamSynchronize(h->stream);
+  afc::prof_collect(h);
+  if (total_ms) *total_ms = h->prof_ms[kernel];
+  if (launches) *launches = h->prof_n[kernel];
+  if (reset) {
+    h->prof_ms[kernel] = 0.0;
+    h->prof_n[kernel] = 0;
+  }
   return AFC_OK;
 }
 
@@ -658,6 +683,7 @@ afc_status afc_step_ssprk3(afc_handle* h, double* u, const double* F, double dt,
         if (ns == 1) afc::copy(h, a.u, s1);
         HIP_OK(hipGetLastError());
         HIP_OK(hipStreamSynchronize(h->stream));
+        afc::prof_collect(h);
         return AFC_OK;
       },
       &a);

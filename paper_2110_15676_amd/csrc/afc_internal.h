@@ -87,8 +87,31 @@ struct afc_handle_s {
   double* V64 = nullptr;  // (m+1) x N
   float* V32 = nullptr;   // (m+1) x N
   int Vm = 0;
+  int ldv = 0;  // basis / work vector stride: N rounded up to 64 (16-byte aligned rows)
   double* partials = nullptr;  // kMaxRed * kRedBlocks
-  unsigned* counters = nullptr;
   afc::KState* ks = nullptr;
   afc::KState* host_status = nullptr;  // pinned copy of the KState head
+
+  // optional per-kernel timing (options.profile)
+  struct ProfEv {
+    hipEvent_t a, b;
+    int kid;
+  };
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<ProfEv> ev_pending;
+  double prof_ms[AFC_KERNEL_COUNT] = {};
+  int64_t prof_n[AFC_KERNEL_COUNT] = {};
 };
+
+namespace afc {
+// Brackets the launches of one kernel class with HIP events when profiling.
+struct ProfScope {
+  afc_handle_s* h;
+  int kid;
+  hipEvent_t b = nullptr;
+  ProfScope(afc_handle_s* h_, int kid_);
+  ~ProfScope();
+};
+void prof_collect(afc_handle_s* h);  // fold completed event pairs into the totals
+void prof_release(afc_handle_s* h);
+}  // namespace afc

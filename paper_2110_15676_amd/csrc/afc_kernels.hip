@@ -90,36 +90,6 @@ __device__ void block_partials(const double (&v)[KMAX], int nv, double* partials
   }
 }
 
-// Last-arriving workgroup sums the partials of all nb workgroups (fixed
-// order) into out[0..nv) and returns true; every other workgroup returns false.
-__device__ bool finalize(double* partials, int nb, int nv, unsigned* counter, double* out) {
-  __shared__ int is_last;
-  __shared__ double sh[kMaxRed][kBlock / 64];
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) is_last = (atomicAdd(counter, 1u) == (unsigned)(nb - 1));
-  __syncthreads();
-  if (!is_last) return false;
-  __threadfence();
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int q = 0; q < nv; ++q) {
-    double s = 0.0;
-    for (int b = threadIdx.x; b < nb; b += kBlock) s += partials[(size_t)q * kRedBlocks + b];
-    s = wave_sum(s);
-    if (lane == 0) sh[q][wv] = s;
-  }
-  __syncthreads();
-  for (int q = threadIdx.x; q < nv; q += kBlock) {
-    double s = 0.0;
-#pragma unroll
-    for (int w = 0; w < kBlock / 64; ++w) s += sh[q][w];
-    out[q] = s;
-  }
-  if (threadIdx.x == 0) *counter = 0u;
-  __syncthreads();
-  return true;
-}
-
 // Start of a Krylov cycle from the squared norm of its residual.
 __device__ void cycle_start_dev(KState* ks, int mode, double rr, double tol_abs, double tol_rel) {
   const double beta = sqrt(rr);
@@ -160,11 +130,10 @@ __global__ __launch_bounds__(kBlock) void k_fill(int N, double* __restrict__ u, 
 }
 
 __global__ __launch_bounds__(kBlock) void k_norm2(int N, const double* __restrict__ x, KState* ks, int idx,
-                                                  double* partials, unsigned* counter) {
+                                                  double* partials) {
   double acc[1] = {0.0};
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) acc[0] += x[i] * x[i];
   block_partials<1>(acc, 1, partials, blockIdx.x);
-  finalize(partials, gridDim.x, 1, counter, ks->red + idx);
 }
 
 __global__ __launch_bounds__(kBlock) void k_relax(int N, double* __restrict__ u, const double* __restrict__ x,
@@ -222,92 +191,6 @@ __global__ __launch_bounds__(kBlock) void k_scale32(int N, const int* __restrict
   }
 }
 
-// ---------------------------------------------------------------------------
-// SpMV family
-// ---------------------------------------------------------------------------
-
-// y = mul * A (s .* x)   (s optional column scaling = right Jacobi preconditioner)
-template <int G, bool SCALE>
-__global__ __launch_bounds__(kBlock) void k_spmv64(int N, const int* __restrict__ rp, const int* __restrict__ col,
-                                                   const double* __restrict__ A, const double* __restrict__ s,
-                                                   const double* __restrict__ x, const double* __restrict__ mulp,
-                                                   double* __restrict__ y, const int* __restrict__ done) {
-  if (done != nullptr && *done) return;
-  constexpr int RPB = kBlock / G;
-  const int lane = threadIdx.x % G, sub = threadIdx.x / G;
-  const double mul = mulp != nullptr ? *mulp : 1.0;
-  int t0, t1;
-  tile_range((N + RPB - 1) / RPB, t0, t1);
-  for (int t = t0; t < t1; ++t) {
-    const int i = t * RPB + sub;
-    if (i >= N) continue;
-    double acc = 0.0;
-    const int e = rp[i + 1];
-    for (int k = rp[i] + lane; k < e; k += G) {
-      const int j = col[k];
-      double xj = x[j];
-      if (SCALE) xj *= s[j];
-      acc += A[k] * xj;
-    }
-    acc = gsum<G>(acc);
-    if (lane == 0) y[i] = mul * acc;
-  }
-}
-
-// FP32: y = mul * A32 x
-template <int G>
-__global__ __launch_bounds__(kBlock) void k_spmv32(int N, const int* __restrict__ rp, const int* __restrict__ col,
-                                                   const float* __restrict__ A, const float* __restrict__ x,
-                                                   const double* __restrict__ mulp, float* __restrict__ y,
-                                                   const int* __restrict__ done) {
-  if (*done) return;
-  constexpr int RPB = kBlock / G;
-  const int lane = threadIdx.x % G, sub = threadIdx.x / G;
-  const float mul = (float)*mulp;
-  int t0, t1;
-  tile_range((N + RPB - 1) / RPB, t0, t1);
-  for (int t = t0; t < t1; ++t) {
-    const int i = t * RPB + sub;
-    if (i >= N) continue;
-    float acc = 0.0f;
-    const int e = rp[i + 1];
-    for (int k = rp[i] + lane; k < e; k += G) acc += A[k] * x[col[k]];
-    acc = gsumf<G>(acc);
-    if (lane == 0) y[i] = mul * acc;
-  }
-}
-
-// r = b - A x, ||r||^2, optional Krylov cycle start
-template <int G>
-__global__ __launch_bounds__(kBlock) void k_residual(int N, const int* __restrict__ rp, const int* __restrict__ col,
-                                                     const double* __restrict__ A, const double* __restrict__ b,
-                                                     const double* __restrict__ x, double* __restrict__ r,
-                                                     KState* ks, double* partials, unsigned* counter, int mode,
-                                                     double tol_abs, double tol_rel) {
-  constexpr int RPB = kBlock / G;
-  const int lane = threadIdx.x % G, sub = threadIdx.x / G;
-  double nrm[1] = {0.0};
-  int t0, t1;
-  tile_range((N + RPB - 1) / RPB, t0, t1);
-  for (int t = t0; t < t1; ++t) {
-    const int i = t * RPB + sub;
-    if (i >= N) continue;
-    double acc = 0.0;
-    const int e = rp[i + 1];
-    for (int k = rp[i] + lane; k < e; k += G) acc += A[k] * x[col[k]];
-    acc = gsum<G>(acc);
-    if (lane == 0) {
-      const double ri = b[i] - acc;
-      r[i] = ri;
-      nrm[0] += ri * ri;
-    }
-  }
-  block_partials<1>(nrm, 1, partials, blockIdx.x);
-  if (finalize(partials, gridDim.x, 1, counter, ks->red)) {
-    if (threadIdx.x == 0 && mode != 0) cycle_start_dev(ks, mode, ks->red[0], tol_abs, tol_rel);
-  }
-}
-
 __global__ void k_cycle_start(KState* ks, int mode, int idx, double tol_abs, double tol_rel) {
   if (threadIdx.x == 0 && blockIdx.x == 0) cycle_start_dev(ks, mode, ks->red[idx], tol_abs, tol_rel);
 }
@@ -320,29 +203,267 @@ __global__ __launch_bounds__(kBlock) void k_cast_v0(int N, const double* __restr
 }
 
 // ---------------------------------------------------------------------------
+// CSR-stream SpMV: a workgroup owns a tile of consecutive rows, streams the
+// tile's nonzeros with fully coalesced loads (one entry per lane per pass),
+// stages the products in LDS and sums each row from LDS.  Tiles whose
+// nonzeros do not fit in LDS fall back to one wave per row.
+// ---------------------------------------------------------------------------
+
+constexpr int kTileRowsF = 256;   // FP32: rows per tile (one row per thread when summing)
+constexpr int kTileNnzF = 8192;   // FP32 products staged per tile (32 KB)
+constexpr int kTileRowsD = 128;   // FP64
+constexpr int kTileNnzD = 4096;   // FP64 products staged per tile (32 KB)
+
+__device__ __forceinline__ float wave_sumf(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// y = mul * A x (FP32, Jacobi-scaled matrix of the mixed-precision GMRES)
+__global__ __launch_bounds__(kBlock) void k_spmv32_stream(int N, const int* __restrict__ rp,
+                                                          const int* __restrict__ col, const float* __restrict__ A,
+                                                          const float* __restrict__ x,
+                                                          const double* __restrict__ mulp, float* __restrict__ y,
+                                                          const int* __restrict__ done) {
+  if (*done) return;
+  __shared__ float prod[kTileNnzF];
+  __shared__ int rps[kTileRowsF + 1];
+  const float mul = (float)*mulp;
+  int t0, t1;
+  tile_range((N + kTileRowsF - 1) / kTileRowsF, t0, t1);
+  for (int t = t0; t < t1; ++t) {
+    const int r0 = t * kTileRowsF;
+    const int nr = min(kTileRowsF, N - r0);
+    for (int q = threadIdx.x; q <= nr; q += kBlock) rps[q] = rp[r0 + q];
+    __syncthreads();
+    const int k0 = rps[0];
+    const int len = rps[nr] - k0;
+    if (len <= kTileNnzF) {
+#pragma unroll 4
+      for (int e = threadIdx.x; e < len; e += kBlock) prod[e] = A[k0 + e] * x[col[k0 + e]];
+      __syncthreads();
+      if (threadIdx.x < nr) {
+        float s = 0.0f;
+        const int a = rps[threadIdx.x] - k0, b = rps[threadIdx.x + 1] - k0;
+        for (int e = a; e < b; ++e) s += prod[e];
+        y[r0 + threadIdx.x] = mul * s;
+      }
+    } else {
+      const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+      for (int rr = wv; rr < nr; rr += kBlock / 64) {
+        float s = 0.0f;
+        for (int kk = rps[rr] + lane; kk < rps[rr + 1]; kk += 64) s += A[kk] * x[col[kk]];
+        s = wave_sumf(s);
+        if (lane == 0) y[r0 + rr] = mul * s;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// y = mul * A (s .* x) (FP64, right Jacobi scaling applied on the fly)
+__global__ __launch_bounds__(kBlock) void k_spmv64_stream(int N, const int* __restrict__ rp,
+                                                          const int* __restrict__ col, const double* __restrict__ A,
+                                                          const double* __restrict__ sc,
+                                                          const double* __restrict__ x,
+                                                          const double* __restrict__ mulp, double* __restrict__ y,
+                                                          const int* __restrict__ done) {
+  if (*done) return;
+  __shared__ double prod[kTileNnzD];
+  __shared__ int rps[kTileRowsD + 1];
+  const double mul = *mulp;
+  int t0, t1;
+  tile_range((N + kTileRowsD - 1) / kTileRowsD, t0, t1);
+  for (int t = t0; t < t1; ++t) {
+    const int r0 = t * kTileRowsD;
+    const int nr = min(kTileRowsD, N - r0);
+    for (int q = threadIdx.x; q <= nr; q += kBlock) rps[q] = rp[r0 + q];
+    __syncthreads();
+    const int k0 = rps[0];
+    const int len = rps[nr] - k0;
+    if (len <= kTileNnzD) {
+#pragma unroll 4
+      for (int e = threadIdx.x; e < len; e += kBlock) {
+        const int j = col[k0 + e];
+        prod[e] = A[k0 + e] * (sc[j] * x[j]);
+      }
+      __syncthreads();
+      if (threadIdx.x < nr) {
+        double s = 0.0;
+        const int a = rps[threadIdx.x] - k0, b = rps[threadIdx.x + 1] - k0;
+        for (int e = a; e < b; ++e) s += prod[e];
+        y[r0 + threadIdx.x] = mul * s;
+      }
+    } else {
+      const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+      for (int rr = wv; rr < nr; rr += kBlock / 64) {
+        double s = 0.0;
+        for (int kk = rps[rr] + lane; kk < rps[rr + 1]; kk += 64) {
+          const int j = col[kk];
+          s += A[kk] * (sc[j] * x[j]);
+        }
+        s = wave_sum(s);
+        if (lane == 0) y[r0 + rr] = mul * s;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// r = b - A x (FP64), ||r||^2, optional Krylov cycle start
+__global__ __launch_bounds__(kBlock) void k_residual_stream(int N, const int* __restrict__ rp,
+                                                            const int* __restrict__ col,
+                                                            const double* __restrict__ A,
+                                                            const double* __restrict__ b,
+                                                            const double* __restrict__ x, double* __restrict__ r,
+                                                            KState* ks, double* partials,
+                                                            int mode, double tol_abs, double tol_rel) {
+  __shared__ double prod[kTileNnzD];
+  __shared__ int rps[kTileRowsD + 1];
+  double nrm[1] = {0.0};
+  int t0, t1;
+  tile_range((N + kTileRowsD - 1) / kTileRowsD, t0, t1);
+  for (int t = t0; t < t1; ++t) {
+    const int r0 = t * kTileRowsD;
+    const int nr = min(kTileRowsD, N - r0);
+    for (int q = threadIdx.x; q <= nr; q += kBlock) rps[q] = rp[r0 + q];
+    __syncthreads();
+    const int k0 = rps[0];
+    const int len = rps[nr] - k0;
+    if (len <= kTileNnzD) {
+#pragma unroll 4
+      for (int e = threadIdx.x; e < len; e += kBlock) prod[e] = A[k0 + e] * x[col[k0 + e]];
+      __syncthreads();
+      if (threadIdx.x < nr) {
+        double s = 0.0;
+        const int a = rps[threadIdx.x] - k0, bb = rps[threadIdx.x + 1] - k0;
+        for (int e = a; e < bb; ++e) s += prod[e];
+        const double ri = b[r0 + threadIdx.x] - s;
+        r[r0 + threadIdx.x] = ri;
+        nrm[0] += ri * ri;
+      }
+    } else {
+      const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+      for (int rr = wv; rr < nr; rr += kBlock / 64) {
+        double s = 0.0;
+        for (int kk = rps[rr] + lane; kk < rps[rr + 1]; kk += 64) s += A[kk] * x[col[kk]];
+        s = wave_sum(s);
+        if (lane == 0) {
+          const double ri = b[r0 + rr] - s;
+          r[r0 + rr] = ri;
+          nrm[0] += ri * ri;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  block_partials<1>(nrm, 1, partials, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
 // GMRES: classical Gram-Schmidt with unnormalized basis vectors V[j] and
 // scales sc_j (v_j = sc_j V[j]); Givens rotations on the device.
 // ---------------------------------------------------------------------------
 
-template <typename T, int KMAX>
-__global__ __launch_bounds__(kBlock) void k_gmres_dots(int N, const T* __restrict__ V, const T* __restrict__ W,
-                                                       int k, int m, KState* ks, double* partials,
-                                                       unsigned* counter) {
-  if (ks->done) return;
-  const int nv = k + 1;
-  double acc[KMAX];
+// 16-byte vector access with a scalar tail (basis vectors use a padded,
+// 16-byte aligned stride ldv; the tail guard keeps every access below N).
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+  using type = float4;
+};
+template <>
+struct Vec16<double> {
+  using type = double2;
+};
+
+template <typename T>
+__device__ __forceinline__ void load16(const T* __restrict__ p, int e, int N, T (&out)[16 / sizeof(T)]) {
+  constexpr int VN = 16 / sizeof(T);
+  if (e + VN <= N) {
+    const typename Vec16<T>::type v = *reinterpret_cast<const typename Vec16<T>::type*>(p + e);
+    __builtin_memcpy(out, &v, 16);
+  } else {
 #pragma unroll
-  for (int q = 0; q < KMAX; ++q) acc[q] = 0.0;
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) {
-    const double w = (double)W[i];
-#pragma unroll
-    for (int q = 0; q < KMAX; ++q)
-      if (q < nv) acc[q] += (double)V[(size_t)q * N + i] * w;
+    for (int c = 0; c < VN; ++c) out[c] = (e + c < N) ? p[e + c] : T(0);
   }
-  block_partials<KMAX>(acc, nv, partials, blockIdx.x);
-  if (finalize(partials, gridDim.x, nv, counter, ks->red)) {
-    double* Hk = ks->H + (size_t)k * (m + 1);
-    for (int q = threadIdx.x; q < nv; q += kBlock) Hk[q] = ks->sc[q] * ks->red[q];
+}
+
+template <typename T>
+__device__ __forceinline__ void store16(T* __restrict__ p, int e, int N, const T (&in)[16 / sizeof(T)]) {
+  constexpr int VN = 16 / sizeof(T);
+  if (e + VN <= N) {
+    typename Vec16<T>::type v;
+    __builtin_memcpy(&v, in, 16);
+    *reinterpret_cast<typename Vec16<T>::type*>(p + e) = v;
+  } else {
+#pragma unroll
+    for (int c = 0; c < VN; ++c)
+      if (e + c < N) p[e + c] = in[c];
+  }
+}
+
+// h_{q,k} = sc_q (V[q], W), q = 0..k.  Each block streams chunks of
+// 2 x 16 B per thread of W and of every basis vector (four vectors per pass
+// for memory-level parallelism); per-wave sums accumulate in LDS.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_gmres_dots(int N, int ldv, const T* __restrict__ V,
+                                                       const T* __restrict__ W, int k, int m, KState* ks,
+                                                       double* partials) {
+  if (ks->done) return;
+  constexpr int VN = 16 / sizeof(T);
+  constexpr int CH = kBlock * VN * 2;
+  constexpr int NW = kBlock / 64;
+  __shared__ double sh[kMaxRestart + 1][NW];
+  const int nv = k + 1;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int q = threadIdx.x; q < nv * NW; q += kBlock) sh[q / NW][q % NW] = 0.0;
+  __syncthreads();
+  for (int base = blockIdx.x * CH; base < N; base += gridDim.x * CH) {
+    const int e0 = base + threadIdx.x * VN, e1 = e0 + kBlock * VN;
+    T w0[VN], w1[VN];
+    load16(W, e0, N, w0);
+    load16(W, e1, N, w1);
+    int q = 0;
+    for (; q + 4 <= nv; q += 4) {
+      T a[4][VN], b[4][VN];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        load16(V + (size_t)(q + u) * ldv, e0, N, a[u]);
+        load16(V + (size_t)(q + u) * ldv, e1, N, b[u]);
+      }
+      double sum[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        double t = 0.0;
+#pragma unroll
+        for (int c = 0; c < VN; ++c) t += (double)a[u][c] * (double)w0[c] + (double)b[u][c] * (double)w1[c];
+        sum[u] = wave_sum(t);
+      }
+      if (lane == 0) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) sh[q + u][wv] += sum[u];
+      }
+    }
+    for (; q < nv; ++q) {
+      T a[VN], b[VN];
+      load16(V + (size_t)q * ldv, e0, N, a);
+      load16(V + (size_t)q * ldv, e1, N, b);
+      double t = 0.0;
+#pragma unroll
+      for (int c = 0; c < VN; ++c) t += (double)a[c] * (double)w0[c] + (double)b[c] * (double)w1[c];
+      t = wave_sum(t);
+      if (lane == 0) sh[q][wv] += t;
+    }
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < nv; q += kBlock) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) t += sh[q][w];
+    partials[(size_t)q * kRedBlocks + blockIdx.x] = t;
   }
 }
 
@@ -378,58 +499,245 @@ __device__ void givens_step(KState* ks, int k, int m) {
   if (ks->res <= ks->tol || hk1 == 0.0) ks->done = 1;
 }
 
-template <typename T, int KMAX>
-__global__ __launch_bounds__(kBlock) void k_gmres_update(int N, T* __restrict__ V, const T* __restrict__ W, int k,
-                                                         int m, KState* ks, double* partials, unsigned* counter) {
+// V[k+1] = W - sum_q h_{q,k} sc_q V[q], its squared norm, then the Givens step.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_gmres_update(int N, int ldv, T* __restrict__ V,
+                                                         const T* __restrict__ W, int k, int m, KState* ks,
+                                                         double* partials) {
   if (ks->done) return;
+  constexpr int VN = 16 / sizeof(T);
+  constexpr int CH = kBlock * VN * 2;
+  __shared__ double tq[kMaxRestart + 1];
   const int nv = k + 1;
-  double t[KMAX];
   const double* Hk = ks->H + (size_t)k * (m + 1);
-#pragma unroll
-  for (int q = 0; q < KMAX; ++q) t[q] = (q < nv) ? Hk[q] * ks->sc[q] : 0.0;
-  T* __restrict__ out = V + (size_t)(k + 1) * N;
+  for (int q = threadIdx.x; q < nv; q += kBlock) tq[q] = Hk[q] * ks->sc[q];
+  __syncthreads();
+  T* __restrict__ out = V + (size_t)(k + 1) * ldv;
   double nrm[1] = {0.0};
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) {
-    double w = (double)W[i];
+  for (int base = blockIdx.x * CH; base < N; base += gridDim.x * CH) {
+    const int e0 = base + threadIdx.x * VN, e1 = e0 + kBlock * VN;
+    T w0[VN], w1[VN];
+    load16(W, e0, N, w0);
+    load16(W, e1, N, w1);
+    double c0[VN], c1[VN];
 #pragma unroll
-    for (int q = 0; q < KMAX; ++q)
-      if (q < nv) w -= t[q] * (double)V[(size_t)q * N + i];
-    const T wo = (T)w;
-    out[i] = wo;
-    nrm[0] += (double)wo * (double)wo;
+    for (int c = 0; c < VN; ++c) {
+      c0[c] = (double)w0[c];
+      c1[c] = (double)w1[c];
+    }
+    int q = 0;
+    for (; q + 4 <= nv; q += 4) {
+      T a[4][VN], b[4][VN];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        load16(V + (size_t)(q + u) * ldv, e0, N, a[u]);
+        load16(V + (size_t)(q + u) * ldv, e1, N, b[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double t = tq[q + u];
+#pragma unroll
+        for (int c = 0; c < VN; ++c) {
+          c0[c] -= t * (double)a[u][c];
+          c1[c] -= t * (double)b[u][c];
+        }
+      }
+    }
+    for (; q < nv; ++q) {
+      T a[VN], b[VN];
+      load16(V + (size_t)q * ldv, e0, N, a);
+      load16(V + (size_t)q * ldv, e1, N, b);
+      const double t = tq[q];
+#pragma unroll
+      for (int c = 0; c < VN; ++c) {
+        c0[c] -= t * (double)a[c];
+        c1[c] -= t * (double)b[c];
+      }
+    }
+    T o0[VN], o1[VN];
+#pragma unroll
+    for (int c = 0; c < VN; ++c) {
+      o0[c] = (T)c0[c];
+      o1[c] = (T)c1[c];
+      nrm[0] += (double)o0[c] * (double)o0[c] + (double)o1[c] * (double)o1[c];
+    }
+    store16(out, e0, N, o0);
+    store16(out, e1, N, o1);
   }
   block_partials<1>(nrm, 1, partials, blockIdx.x);
-  if (finalize(partials, gridDim.x, 1, counter, ks->red)) {
-    if (threadIdx.x == 0) givens_step(ks, k, m);
-  }
 }
 
-// back substitution R y = g over the columns completed in the cycle
-__global__ void k_gmres_solve(KState* ks, int m) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// back substitution R y = g over the columns completed in the cycle (one wave)
+__global__ __launch_bounds__(64) void k_gmres_solve(KState* ks, int m) {
+  __shared__ double R[kMaxRestart][kMaxRestart + 1];
+  __shared__ double g[kMaxRestart];
   const int kk = ks->k;
-  double y[kMaxRestart];
-  for (int i = kk - 1; i >= 0; --i) {
-    double s = ks->g[i];
-    for (int j = i + 1; j < kk; ++j) s -= ks->H[(size_t)j * (m + 1) + i] * y[j];
-    y[i] = s / ks->H[(size_t)i * (m + 1) + i];
+  for (int e = threadIdx.x; e < kk * kk; e += 64) {
+    const int c = e / kk, row = e % kk;
+    R[row][c] = row <= c ? ks->H[(size_t)c * (m + 1) + row] : 0.0;
   }
-  for (int i = 0; i < kk; ++i) ks->coef[i] = y[i] * ks->sc[i];
+  for (int i = threadIdx.x; i < kk; i += 64) g[i] = ks->g[i];
+  __syncthreads();
+  for (int i = kk - 1; i >= 0; --i) {
+    const double yi = g[i] / R[i][i];
+    __syncthreads();
+    for (int j = threadIdx.x; j < i; j += 64) g[j] -= R[j][i] * yi;
+    if (threadIdx.x == 0) g[i] = yi;
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < kk; i += 64) ks->coef[i] = g[i] * ks->sc[i];
 }
 
-// x += D^{-1} sum_j coef_j V[j]
+// x += D^{-1} sum_q coef_q V[q]
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_gmres_xupdate(int N, const T* __restrict__ V,
+__global__ __launch_bounds__(kBlock) void k_gmres_xupdate(int N, int ldv, const T* __restrict__ V,
                                                           const double* __restrict__ dinv, double* __restrict__ x,
                                                           const KState* __restrict__ ks) {
-  __shared__ double coef[kMaxRestart];
+  constexpr int VN = 16 / sizeof(T);
+  constexpr int CH = kBlock * VN;
+  __shared__ double coef[kMaxRestart + 1];
   const int kk = ks->k;
   for (int q = threadIdx.x; q < kk; q += kBlock) coef[q] = ks->coef[q];
   __syncthreads();
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) {
-    double acc = 0.0;
-    for (int q = 0; q < kk; ++q) acc += coef[q] * (double)V[(size_t)q * N + i];
-    x[i] += dinv[i] * acc;
+  for (int base = blockIdx.x * CH; base < N; base += gridDim.x * CH) {
+    const int e0 = base + threadIdx.x * VN;
+    double acc[VN];
+#pragma unroll
+    for (int c = 0; c < VN; ++c) acc[c] = 0.0;
+    for (int q = 0; q < kk; ++q) {
+      T a[VN];
+      load16(V + (size_t)q * ldv, e0, N, a);
+      const double cq = coef[q];
+#pragma unroll
+      for (int c = 0; c < VN; ++c) acc[c] += cq * (double)a[c];
+    }
+#pragma unroll
+    for (int c = 0; c < VN; ++c)
+      if (e0 + c < N) x[e0 + c] += dinv[e0 + c] * acc[c];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Reduction finish: one workgroup sums the per-workgroup partials of the
+// preceding kernel in a fixed order (wave q-strided, lanes block-strided) into
+// ks->red and takes the solver's scalar step.  Being a separate kernel, it
+// sees the partials through the kernel boundary; the producing kernels need
+// no device-scope fence.
+// ---------------------------------------------------------------------------
+
+enum FinishAct {
+  ACT_STORE = 0,   // red[off..off+nv) only
+  ACT_DOTS,        // Arnoldi column: H[q,k] = sc_q red[q]
+  ACT_GIVENS,      // norm of the new basis vector + Givens rotation
+  ACT_CYCLE,       // residual norm -> Krylov cycle start (mode 1 / 2)
+  ACT_BICG_INIT,
+  ACT_BICG_ALPHA,
+  ACT_BICG_S,
+  ACT_BICG_OMEGA,
+  ACT_BICG_RHO
+};
+
+constexpr int kFinish = 1024;
+
+__global__ __launch_bounds__(kFinish) void k_finish(KState* ks, const double* __restrict__ partials, int nb, int nv,
+                                                    int act, int red_off, int k, int m, int mode, double p1,
+                                                    double p2) {
+  switch (act) {
+    case ACT_DOTS:
+    case ACT_GIVENS:
+    case ACT_BICG_ALPHA:
+    case ACT_BICG_S:
+    case ACT_BICG_RHO:
+      if (ks->done) return;
+      break;
+    case ACT_BICG_OMEGA:
+      if (ks->done || ks->half) return;
+      break;
+    default:
+      break;
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double* red = ks->red + red_off;
+  for (int q = wv; q < nv; q += kFinish / 64) {
+    double s = 0.0;
+    for (int b = lane; b < nb; b += 64) s += partials[(size_t)q * kRedBlocks + b];
+    s = wave_sum(s);
+    if (lane == 0) red[q] = s;
+  }
+  __syncthreads();
+  if (act == ACT_DOTS) {
+    double* Hk = ks->H + (size_t)k * (m + 1);
+    for (int q = threadIdx.x; q < nv; q += kFinish) Hk[q] = ks->sc[q] * red[q];
+    return;
+  }
+  if (threadIdx.x != 0) return;
+  switch (act) {
+    case ACT_GIVENS:
+      givens_step(ks, k, m);
+      break;
+    case ACT_CYCLE:
+      if (mode != 0) cycle_start_dev(ks, mode, red[0], p1, p2);
+      break;
+    case ACT_BICG_INIT: {
+      const double rr = red[0];
+      ks->rho = rr;
+      ks->alpha = 1.0;
+      ks->omega = 1.0;
+      ks->bcg_beta = 0.0;
+      ks->res = sqrt(rr);
+      ks->tol = p1;
+      ks->half = 0;
+      ks->flag = isfinite(rr) ? 0 : 2;
+      ks->done = (!isfinite(rr) || ks->res <= p1) ? 1 : 0;
+      break;
+    }
+    case ACT_BICG_ALPHA: {
+      const double rv = red[0];
+      ks->half = 0;
+      if (rv == 0.0 || !isfinite(rv)) {
+        ks->flag = isfinite(rv) ? 1 : 2;
+        ks->done = 1;
+      } else {
+        ks->alpha = ks->rho / rv;
+      }
+      break;
+    }
+    case ACT_BICG_S:
+      if (sqrt(red[0]) <= ks->tol) {
+        ks->half = 1;
+        ks->omega = 0.0;
+      }
+      break;
+    case ACT_BICG_OMEGA: {
+      const double ts = red[0], tt = red[1];
+      ks->omega = tt != 0.0 ? ts / tt : 0.0;
+      if (!isfinite(ks->omega)) {
+        ks->flag = 2;
+        ks->done = 1;
+      }
+      break;
+    }
+    case ACT_BICG_RHO: {
+      const double rho_new = red[0];
+      const double res = sqrt(red[1]);
+      ks->iters += 1;
+      ks->res = res;
+      if (!isfinite(res)) {
+        ks->flag = 2;
+        ks->done = 1;
+      } else if (res <= ks->tol) {
+        ks->done = 1;
+      } else if (rho_new == 0.0 || ks->omega == 0.0) {
+        ks->flag = 1;
+        ks->done = 1;
+      } else {
+        ks->bcg_beta = (rho_new / ks->rho) * (ks->alpha / ks->omega);
+        ks->rho = rho_new;
+      }
+      break;
+    }
+    default:
+      break;
   }
 }
 
@@ -439,7 +747,7 @@ __global__ __launch_bounds__(kBlock) void k_gmres_xupdate(int N, const T* __rest
 
 __global__ __launch_bounds__(kBlock) void k_bicg_init(int N, const double* __restrict__ r, double* __restrict__ rhat,
                                                       double* __restrict__ p, double* __restrict__ v, KState* ks,
-                                                      double* partials, unsigned* counter, double tol) {
+                                                      double* partials, double tol) {
   double acc[1] = {0.0};
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) {
     const double ri = r[i];
@@ -449,20 +757,6 @@ __global__ __launch_bounds__(kBlock) void k_bicg_init(int N, const double* __res
     acc[0] += ri * ri;
   }
   block_partials<1>(acc, 1, partials, blockIdx.x);
-  if (finalize(partials, gridDim.x, 1, counter, ks->red)) {
-    if (threadIdx.x == 0) {
-      const double rr = ks->red[0];
-      ks->rho = rr;
-      ks->alpha = 1.0;
-      ks->omega = 1.0;
-      ks->bcg_beta = 0.0;
-      ks->res = sqrt(rr);
-      ks->tol = tol;
-      ks->half = 0;
-      ks->flag = isfinite(rr) ? 0 : 2;
-      ks->done = (!isfinite(rr) || ks->res <= tol) ? 1 : 0;
-    }
-  }
 }
 
 // v = A D^{-1} p ; alpha = rho / (rhat, v)
@@ -470,8 +764,7 @@ template <int G>
 __global__ __launch_bounds__(kBlock) void k_bicg_v(int N, const int* __restrict__ rp, const int* __restrict__ col,
                                                    const double* __restrict__ A, const double* __restrict__ dinv,
                                                    const double* __restrict__ p, const double* __restrict__ rhat,
-                                                   double* __restrict__ v, KState* ks, double* partials,
-                                                   unsigned* counter) {
+                                                   double* __restrict__ v, KState* ks, double* partials) {
   if (ks->done) return;
   constexpr int RPB = kBlock / G;
   const int lane = threadIdx.x % G, sub = threadIdx.x / G;
@@ -494,24 +787,11 @@ __global__ __launch_bounds__(kBlock) void k_bicg_v(int N, const int* __restrict_
     }
   }
   block_partials<1>(acc, 1, partials, blockIdx.x);
-  if (finalize(partials, gridDim.x, 1, counter, ks->red)) {
-    if (threadIdx.x == 0) {
-      const double rv = ks->red[0];
-      ks->half = 0;
-      if (rv == 0.0 || !isfinite(rv)) {
-        ks->flag = isfinite(rv) ? 1 : 2;
-        ks->done = 1;
-      } else {
-        ks->alpha = ks->rho / rv;
-      }
-    }
-  }
 }
 
 // s = r - alpha v ; stop early when ||s|| <= tol
 __global__ __launch_bounds__(kBlock) void k_bicg_s(int N, const double* __restrict__ r, const double* __restrict__ v,
-                                                   double* __restrict__ s, KState* ks, double* partials,
-                                                   unsigned* counter) {
+                                                   double* __restrict__ s, KState* ks, double* partials) {
   if (ks->done) return;
   const double alpha = ks->alpha;
   double acc[1] = {0.0};
@@ -521,12 +801,6 @@ __global__ __launch_bounds__(kBlock) void k_bicg_s(int N, const double* __restri
     acc[0] += si * si;
   }
   block_partials<1>(acc, 1, partials, blockIdx.x);
-  if (finalize(partials, gridDim.x, 1, counter, ks->red)) {
-    if (threadIdx.x == 0 && sqrt(ks->red[0]) <= ks->tol) {
-      ks->half = 1;
-      ks->omega = 0.0;
-    }
-  }
 }
 
 // t = A D^{-1} s ; omega = (t, s) / (t, t)
@@ -534,7 +808,7 @@ template <int G>
 __global__ __launch_bounds__(kBlock) void k_bicg_t(int N, const int* __restrict__ rp, const int* __restrict__ col,
                                                    const double* __restrict__ A, const double* __restrict__ dinv,
                                                    const double* __restrict__ s, double* __restrict__ tv, KState* ks,
-                                                   double* partials, unsigned* counter) {
+                                                   double* partials) {
   if (ks->done || ks->half) return;
   constexpr int RPB = kBlock / G;
   const int lane = threadIdx.x % G, sub = threadIdx.x / G;
@@ -558,16 +832,6 @@ __global__ __launch_bounds__(kBlock) void k_bicg_t(int N, const int* __restrict_
     }
   }
   block_partials<2>(acc, 2, partials, blockIdx.x);
-  if (finalize(partials, gridDim.x, 2, counter, ks->red)) {
-    if (threadIdx.x == 0) {
-      const double ts = ks->red[0], tt = ks->red[1];
-      ks->omega = tt != 0.0 ? ts / tt : 0.0;
-      if (!isfinite(ks->omega)) {
-        ks->flag = 2;
-        ks->done = 1;
-      }
-    }
-  }
 }
 
 // x += alpha D^{-1} p + omega D^{-1} s ; r = s - omega t ; rho_new = (rhat, r)
@@ -575,7 +839,7 @@ __global__ __launch_bounds__(kBlock) void k_bicg_xr(int N, const double* __restr
                                                     const double* __restrict__ p, const double* __restrict__ s,
                                                     const double* __restrict__ tv, const double* __restrict__ rhat,
                                                     double* __restrict__ x, double* __restrict__ r, KState* ks,
-                                                    double* partials, unsigned* counter) {
+                                                    double* partials) {
   if (ks->done) return;
   const double alpha = ks->alpha, omega = ks->omega;
   const bool half = ks->half != 0;
@@ -595,26 +859,6 @@ __global__ __launch_bounds__(kBlock) void k_bicg_xr(int N, const double* __restr
     acc[1] += ri * ri;
   }
   block_partials<2>(acc, 2, partials, blockIdx.x);
-  if (finalize(partials, gridDim.x, 2, counter, ks->red)) {
-    if (threadIdx.x == 0) {
-      const double rho_new = ks->red[0];
-      const double res = sqrt(ks->red[1]);
-      ks->iters += 1;
-      ks->res = res;
-      if (!isfinite(res)) {
-        ks->flag = 2;
-        ks->done = 1;
-      } else if (res <= ks->tol) {
-        ks->done = 1;
-      } else if (rho_new == 0.0 || ks->omega == 0.0) {
-        ks->flag = 1;
-        ks->done = 1;
-      } else {
-        ks->bcg_beta = (rho_new / ks->rho) * (ks->alpha / ks->omega);
-        ks->rho = rho_new;
-      }
-    }
-  }
 }
 
 // p = r + beta (p - omega v)
@@ -886,8 +1130,7 @@ __global__ __launch_bounds__(kBlock) void k_cn_apply(
     const double* __restrict__ dp, const double* __restrict__ Acn, const double* __restrict__ u,
     const double* __restrict__ uo, const double* __restrict__ Rp, const double* __restrict__ Rm,
     const double* __restrict__ g, const uint8_t* __restrict__ is_dir, const double* __restrict__ uD, double dt,
-    double L, int alpha_mode, double* __restrict__ b, double* __restrict__ r, KState* ks, double* partials,
-    unsigned* counter) {
+    double L, int alpha_mode, double* __restrict__ b, double* __restrict__ r, KState* ks, double* partials) {
   constexpr int RPB = kBlock / G;
   const int lane = threadIdx.x % G, sub = threadIdx.x / G;
   const double inv_dt = 1.0 / dt;
@@ -933,7 +1176,6 @@ __global__ __launch_bounds__(kBlock) void k_cn_apply(
     }
   }
   block_partials<3>(acc, 3, partials, blockIdx.x);
-  finalize(partials, gridDim.x, 3, counter, ks->red);
 }
 
 // ---------------------------------------------------------------------------
@@ -976,7 +1218,7 @@ __global__ __launch_bounds__(kBlock) void k_mcl_apply(
     const double* __restrict__ ccT, const double* __restrict__ AL, const double* __restrict__ u,
     const double* __restrict__ umax, const double* __restrict__ umin, const double* __restrict__ F,
     const uint8_t* __restrict__ is_dir, const double* __restrict__ uD, int alpha_mode, double* __restrict__ b,
-    double* __restrict__ r, KState* ks, double* partials, unsigned* counter) {
+    double* __restrict__ r, KState* ks, double* partials) {
   constexpr int RPB = kBlock / G;
   const int lane = threadIdx.x % G, sub = threadIdx.x / G;
   double acc[3] = {0.0, 0.0, 0.0};
@@ -1033,7 +1275,6 @@ __global__ __launch_bounds__(kBlock) void k_mcl_apply(
     }
   }
   block_partials<3>(acc, 3, partials, blockIdx.x);
-  finalize(partials, gridDim.x, 3, counter, ks->red);
 }
 
 // ---------------------------------------------------------------------------
@@ -1060,6 +1301,52 @@ int vec_grid(const H* h) { return std::max(1, std::min((h->N + kBlock - 1) / kBl
 
 }  // namespace
 
+ProfScope::ProfScope(afc_handle_s* h_, int kid_) : h(h_), kid(kid_) {
+  if (!h->opt.profile) return;
+  hipEvent_t a;
+  if (h->ev_pool.size() >= 2) {
+    a = h->ev_pool.back();
+    h->ev_pool.pop_back();
+    b = h->ev_pool.back();
+    h->ev_pool.pop_back();
+  } else {
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&b);
+  }
+  (void)hipEventRecord(a, h->stream);
+  h->ev_pending.push_back({a, b, kid});
+}
+
+ProfScope::~ProfScope() {
+  if (b) (void)hipEventRecord(b, h->stream);
+}
+
+void prof_collect(afc_handle_s* h) {
+  for (auto& e : h->ev_pending) {
+    (void)hipEventSynchronize(e.b);
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, e.a, e.b) == hipSuccess) {
+      h->prof_ms[e.kid] += ms;
+      h->prof_n[e.kid] += 1;
+    }
+    h->ev_pool.push_back(e.a);
+    h->ev_pool.push_back(e.b);
+  }
+  h->ev_pending.clear();
+}
+
+void prof_release(afc_handle_s* h) {
+  prof_collect(h);
+  for (auto e : h->ev_pool) (void)hipEventDestroy(e);
+  h->ev_pool.clear();
+}
+
+void finish(H* h, int nb, int nv, int act, int red_off = 0, int k = 0, int m = 0, int mode = 0, double p1 = 0.0,
+            double p2 = 0.0) {
+  ProfScope ps(h, AFC_KERNEL_FINISH);
+  k_finish<<<1, kFinish, 0, h->stream>>>(h->ks, h->partials, nb, nv, act, red_off, k, m, mode, p1, p2);
+}
+
 void copy(H* h, double* dst, const double* src) { k_copy<<<vec_grid(h), kBlock, 0, h->stream>>>(h->N, dst, src); }
 
 void set_dirichlet(H* h, double* u) {
@@ -1073,7 +1360,9 @@ void rhs_dirichlet(H* h, double* b, const double* F) {
 void fill(H* h, double* u, double v) { k_fill<<<vec_grid(h), kBlock, 0, h->stream>>>(h->N, u, v); }
 
 void norm2(H* h, const double* x, int red_idx) {
-  k_norm2<<<vec_grid(h), kBlock, 0, h->stream>>>(h->N, x, h->ks, red_idx, h->partials, h->counters);
+  const int nb = vec_grid(h);
+  k_norm2<<<nb, kBlock, 0, h->stream>>>(h->N, x, h->ks, red_idx, h->partials);
+  finish(h, nb, 1, ACT_STORE, red_idx);
 }
 
 void relax(H* h, double* u, const double* x, double omega) {
@@ -1086,10 +1375,23 @@ void build_cn_matrix(H* h, double dt) {
   AFC_DISPATCH_G(h, k_scale32, row_grid(h, false), h->N, h->row_ptr, h->col, h->A_cn, h->dinv_cn, h->A32_cn);
 }
 
+
+int stream_grid(const H* h, int rows, bool reduce) {
+  const int nt = (h->N + rows - 1) / rows;
+  return std::max(1, std::min(nt, reduce ? kRedBlocks : kRowGridCap));
+}
+
+int vec16_grid(const H* h, int elems_per_block) {
+  return std::max(1, std::min((h->N + elems_per_block - 1) / elems_per_block, kRedBlocks));
+}
+
 void residual(H* h, const double* A, const double* b, const double* x, double* r, int mode, double tol_abs,
               double tol_rel) {
-  AFC_DISPATCH_G(h, k_residual, row_grid(h, true), h->N, h->row_ptr, h->col, A, b, x, r, h->ks, h->partials,
-                 h->counters, mode, tol_abs, tol_rel);
+  const int nb = stream_grid(h, kTileRowsD, true);
+  ProfScope ps(h, AFC_KERNEL_RESIDUAL);
+  k_residual_stream<<<nb, kBlock, 0, h->stream>>>(h->N, h->row_ptr, h->col, A, b, x, r, h->ks, h->partials, mode,
+                                                  tol_abs, tol_rel);
+  finish(h, nb, 1, ACT_CYCLE, 0, 0, 0, mode, tol_abs, tol_rel);
 }
 
 void cycle_start(H* h, int mode, int red_idx, double tol_abs, double tol_rel) {
@@ -1099,92 +1401,73 @@ void cycle_start(H* h, int mode, int red_idx, double tol_abs, double tol_rel) {
 void cast_v0(H* h, const double* r) { k_cast_v0<<<vec_grid(h), kBlock, 0, h->stream>>>(h->N, r, h->V32, h->ks); }
 
 void gmres_spmv64(H* h, const double* A, const double* dinv, int k) {
-  const size_t N = (size_t)h->N;
-  double* W = h->w[0];
-  const double* x = h->V64 + (size_t)k * N;
-  const double* mul = &h->ks->sc[k];
-  switch (h->G) {
-    case 8: k_spmv64<8, true><<<row_grid(h, false), kBlock, 0, h->stream>>>(h->N, h->row_ptr, h->col, A, dinv, x, mul, W, &h->ks->done); break;
-    case 16: k_spmv64<16, true><<<row_grid(h, false), kBlock, 0, h->stream>>>(h->N, h->row_ptr, h->col, A, dinv, x, mul, W, &h->ks->done); break;
-    case 32: k_spmv64<32, true><<<row_grid(h, false), kBlock, 0, h->stream>>>(h->N, h->row_ptr, h->col, A, dinv, x, mul, W, &h->ks->done); break;
-    default: k_spmv64<64, true><<<row_grid(h, false), kBlock, 0, h->stream>>>(h->N, h->row_ptr, h->col, A, dinv, x, mul, W, &h->ks->done); break;
-  }
+  ProfScope ps(h, AFC_KERNEL_SPMV64);
+  k_spmv64_stream<<<stream_grid(h, kTileRowsD, false), kBlock, 0, h->stream>>>(
+      h->N, h->row_ptr, h->col, A, dinv, h->V64 + (size_t)k * h->ldv, &h->ks->sc[k], h->w[0], &h->ks->done);
 }
 
 void gmres_spmv32(H* h, const float* A32, int k) {
-  const size_t N = (size_t)h->N;
-  float* W = reinterpret_cast<float*>(h->w[0]);
-  const float* x = h->V32 + (size_t)k * N;
-  AFC_DISPATCH_G(h, k_spmv32, row_grid(h, false), h->N, h->row_ptr, h->col, A32, x, &h->ks->sc[k], W,
-                 &h->ks->done);
+  ProfScope ps(h, AFC_KERNEL_SPMV32);
+  k_spmv32_stream<<<stream_grid(h, kTileRowsF, false), kBlock, 0, h->stream>>>(
+      h->N, h->row_ptr, h->col, A32, h->V32 + (size_t)k * h->ldv, &h->ks->sc[k],
+      reinterpret_cast<float*>(h->w[0]), &h->ks->done);
 }
-
-namespace {
-template <typename T>
-void launch_dots(H* h, const T* V, const T* W, int k, int m) {
-  const int g = vec_grid(h);
-  const int nv = k + 1;
-  if (nv <= 8)
-    k_gmres_dots<T, 8><<<g, kBlock, 0, h->stream>>>(h->N, V, W, k, m, h->ks, h->partials, h->counters);
-  else if (nv <= 16)
-    k_gmres_dots<T, 16><<<g, kBlock, 0, h->stream>>>(h->N, V, W, k, m, h->ks, h->partials, h->counters);
-  else if (nv <= 32)
-    k_gmres_dots<T, 32><<<g, kBlock, 0, h->stream>>>(h->N, V, W, k, m, h->ks, h->partials, h->counters);
-  else
-    k_gmres_dots<T, 64><<<g, kBlock, 0, h->stream>>>(h->N, V, W, k, m, h->ks, h->partials, h->counters);
-}
-template <typename T>
-void launch_update(H* h, T* V, const T* W, int k, int m) {
-  const int g = vec_grid(h);
-  const int nv = k + 1;
-  if (nv <= 8)
-    k_gmres_update<T, 8><<<g, kBlock, 0, h->stream>>>(h->N, V, W, k, m, h->ks, h->partials, h->counters);
-  else if (nv <= 16)
-    k_gmres_update<T, 16><<<g, kBlock, 0, h->stream>>>(h->N, V, W, k, m, h->ks, h->partials, h->counters);
-  else if (nv <= 32)
-    k_gmres_update<T, 32><<<g, kBlock, 0, h->stream>>>(h->N, V, W, k, m, h->ks, h->partials, h->counters);
-  else
-    k_gmres_update<T, 64><<<g, kBlock, 0, h->stream>>>(h->N, V, W, k, m, h->ks, h->partials, h->counters);
-}
-}  // namespace
 
 void gmres_dots(H* h, bool fp32, int k, int m) {
+  const int nb = vec16_grid(h, fp32 ? kBlock * 8 : kBlock * 4);
+  {
+  ProfScope ps(h, AFC_KERNEL_DOTS);
   if (fp32)
-    launch_dots<float>(h, h->V32, reinterpret_cast<const float*>(h->w[0]), k, m);
+    k_gmres_dots<float><<<nb, kBlock, 0, h->stream>>>(h->N, h->ldv, h->V32, reinterpret_cast<const float*>(h->w[0]),
+                                                      k, m, h->ks, h->partials);
   else
-    launch_dots<double>(h, h->V64, h->w[0], k, m);
+    k_gmres_dots<double><<<nb, kBlock, 0, h->stream>>>(h->N, h->ldv, h->V64, h->w[0], k, m, h->ks, h->partials);
+  }
+  finish(h, nb, k + 1, ACT_DOTS, 0, k, m);
 }
 
 void gmres_update(H* h, bool fp32, int k, int m) {
+  const int nb = vec16_grid(h, fp32 ? kBlock * 8 : kBlock * 4);
+  {
+  ProfScope ps(h, AFC_KERNEL_UPDATE);
   if (fp32)
-    launch_update<float>(h, h->V32, reinterpret_cast<const float*>(h->w[0]), k, m);
+    k_gmres_update<float><<<nb, kBlock, 0, h->stream>>>(h->N, h->ldv, h->V32,
+                                                        reinterpret_cast<const float*>(h->w[0]), k, m, h->ks,
+                                                        h->partials);
   else
-    launch_update<double>(h, h->V64, h->w[0], k, m);
+    k_gmres_update<double><<<nb, kBlock, 0, h->stream>>>(h->N, h->ldv, h->V64, h->w[0], k, m, h->ks, h->partials);
+  }
+  finish(h, nb, 1, ACT_GIVENS, 0, k, m);
 }
 
 void gmres_solve(H* h, int m) { k_gmres_solve<<<1, 64, 0, h->stream>>>(h->ks, m); }
 
 void gmres_xupdate(H* h, bool fp32, const double* dinv, double* x) {
   if (fp32)
-    k_gmres_xupdate<float><<<vec_grid(h), kBlock, 0, h->stream>>>(h->N, h->V32, dinv, x, h->ks);
+    k_gmres_xupdate<float><<<vec16_grid(h, kBlock * 4), kBlock, 0, h->stream>>>(h->N, h->ldv, h->V32, dinv, x,
+                                                                                h->ks);
   else
-    k_gmres_xupdate<double><<<vec_grid(h), kBlock, 0, h->stream>>>(h->N, h->V64, dinv, x, h->ks);
+    k_gmres_xupdate<double><<<vec16_grid(h, kBlock * 2), kBlock, 0, h->stream>>>(h->N, h->ldv, h->V64, dinv, x,
+                                                                                 h->ks);
 }
 
 void bicg_init(H* h, const BicgVec& b, double tol) {
-  k_bicg_init<<<vec_grid(h), kBlock, 0, h->stream>>>(h->N, b.r, b.rhat, b.p, b.v, h->ks, h->partials, h->counters,
-                                                     tol);
+  const int nb = vec_grid(h);
+  k_bicg_init<<<nb, kBlock, 0, h->stream>>>(h->N, b.r, b.rhat, b.p, b.v, h->ks, h->partials, tol);
+  finish(h, nb, 1, ACT_BICG_INIT, 0, 0, 0, 0, tol);
 }
 
 void bicg_iter(H* h, const double* A, const double* dinv, const BicgVec& b) {
-  AFC_DISPATCH_G(h, k_bicg_v, row_grid(h, true), h->N, h->row_ptr, h->col, A, dinv, b.p, b.rhat, b.v, h->ks,
-                 h->partials, h->counters);
-  k_bicg_s<<<vec_grid(h), kBlock, 0, h->stream>>>(h->N, b.r, b.v, b.s, h->ks, h->partials, h->counters);
-  AFC_DISPATCH_G(h, k_bicg_t, row_grid(h, true), h->N, h->row_ptr, h->col, A, dinv, b.s, b.t, h->ks, h->partials,
-                 h->counters);
-  k_bicg_xr<<<vec_grid(h), kBlock, 0, h->stream>>>(h->N, dinv, b.p, b.s, b.t, b.rhat, b.x, b.r, h->ks, h->partials,
-                                                   h->counters);
-  k_bicg_p<<<vec_grid(h), kBlock, 0, h->stream>>>(h->N, b.r, b.v, b.p, h->ks);
+  const int nr = row_grid(h, true), nv = vec_grid(h);
+  AFC_DISPATCH_G(h, k_bicg_v, nr, h->N, h->row_ptr, h->col, A, dinv, b.p, b.rhat, b.v, h->ks, h->partials);
+  finish(h, nr, 1, ACT_BICG_ALPHA);
+  k_bicg_s<<<nv, kBlock, 0, h->stream>>>(h->N, b.r, b.v, b.s, h->ks, h->partials);
+  finish(h, nv, 1, ACT_BICG_S);
+  AFC_DISPATCH_G(h, k_bicg_t, nr, h->N, h->row_ptr, h->col, A, dinv, b.s, b.t, h->ks, h->partials);
+  finish(h, nr, 2, ACT_BICG_OMEGA);
+  k_bicg_xr<<<nv, kBlock, 0, h->stream>>>(h->N, dinv, b.p, b.s, b.t, b.rhat, b.x, b.r, h->ks, h->partials);
+  finish(h, nv, 2, ACT_BICG_RHO);
+  k_bicg_p<<<nv, kBlock, 0, h->stream>>>(h->N, b.r, b.v, b.p, h->ks);
 }
 
 void ssp_lowrate(H* h, const double* u, const double* F, double dt, double* udot, double* ut) {
@@ -1221,18 +1504,25 @@ void cn_limit_R(H* h, const double* u, const double* u_old, const double* Qp, co
 
 void cn_apply(H* h, const double* u, const double* u_old, const double* Rp, const double* Rm, const double* g,
               double dt, double* b, double* r) {
-  AFC_DISPATCH_G(h, k_cn_apply, row_grid(h, true), h->N, h->row_ptr, h->col, h->mij, h->dp_fct, h->A_cn, u, u_old,
-                 Rp, Rm, g, h->is_dir, h->uD, dt, h->opt.prelimit, h->opt.alpha_mode, b, r, h->ks, h->partials,
-                 h->counters);
+  const int nb = row_grid(h, true);
+  AFC_DISPATCH_G(h, k_cn_apply, nb, h->N, h->row_ptr, h->col, h->mij, h->dp_fct, h->A_cn, u, u_old, Rp, Rm, g,
+                 h->is_dir, h->uD, dt, h->opt.prelimit, h->opt.alpha_mode, b, r, h->ks, h->partials);
+  finish(h, nb, 3, ACT_STORE);
 }
 
 void mcl_bounds(H* h, const double* u, double* umax, double* umin) {
+  ProfScope ps(h, AFC_KERNEL_MCL);
   AFC_DISPATCH_G(h, k_mcl_bounds, row_grid(h, false), h->N, h->row_ptr, h->col, u, umax, umin);
 }
 
 void mcl_apply(H* h, const double* u, const double* umax, const double* umin, const double* F, double* b, double* r) {
-  AFC_DISPATCH_G(h, k_mcl_apply, row_grid(h, true), h->N, h->row_ptr, h->col, h->cc, h->ccT, h->AL_mcl, u, umax,
-                 umin, F, h->is_dir, h->uD, h->opt.alpha_mode, b, r, h->ks, h->partials, h->counters);
+  const int nb = row_grid(h, true);
+  {
+  ProfScope ps(h, AFC_KERNEL_MCL);
+  AFC_DISPATCH_G(h, k_mcl_apply, nb, h->N, h->row_ptr, h->col, h->cc, h->ccT, h->AL_mcl, u, umax, umin, F,
+                 h->is_dir, h->uD, h->opt.alpha_mode, b, r, h->ks, h->partials);
+  }
+  finish(h, nb, 3, ACT_STORE);
 }
 
 }  // namespace afc
