@@ -27,7 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "spmv32_stream_q1_128_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sell_spmv32_q1_128_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2110_15676_amd", "csrc", "afc_kernels.hip")
 
 
@@ -36,18 +36,35 @@ def kernel_source_hash():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def spmv32_bytes(N, nnz):
-    """Algorithmic bytes of one FP32 CSR SpMV: values + column indices, row
-    pointers, one read of x and one write of y (4-byte words)."""
-    return 8 * nnz + 4 * (N + 1) + 4 * N + 4 * N
+def sell_layout(row_ptr, col):
+    """(slots, bytes per column delta) of the library's SELL-64 layout: 64-row
+    slices padded to their longest row, column deltas j - i in 16 bits when
+    every |j - i| fits."""
+    import numpy as np
+
+    N = row_ptr.shape[0] - 1
+    rl = np.diff(row_ptr).astype(np.int64)
+    nsl = (N + 63) // 64
+    pad = np.zeros(nsl * 64, dtype=np.int64)
+    pad[:N] = rl
+    slots = int(64 * pad.reshape(nsl, 64).max(axis=1).sum())
+    rows = np.repeat(np.arange(N), rl)
+    dbytes = 2 if int(np.abs(col.astype(np.int64) - rows).max()) <= 32767 else 4
+    return slots, dbytes
 
 
-def step_model_bytes(N, nnz, krylov, sweeps, steps):
+def spmv32_bytes(N, slots, dbytes):
+    """Algorithmic bytes of one FP32 SELL-64 SpMV: FP32 values and column
+    deltas of every slot, slice offsets, one read of x and one write of y."""
+    return (4 + dbytes) * slots + 4 * ((N + 63) // 64 + 1) + 4 * N + 4 * N
+
+
+def step_model_bytes(N, nnz, slots, dbytes, krylov, sweeps, steps):
     """Algorithmic HBM bytes of `steps` fixed-point iterations (model)."""
     L = krylov / max(sweeps, 1)  # mean FP32 GMRES cycle length
     kbar = (L - 1) / 2.0         # mean Arnoldi index inside a cycle
-    per_it = spmv32_bytes(N, nnz) + (kbar + 2) * 4 * N + (kbar + 3) * 4 * N
-    per_sweep = 12 * nnz + 4 * (N + 1) + 24 * N + kbar * 4 * N + 16 * N + 12 * N
+    per_it = spmv32_bytes(N, slots, dbytes) + (kbar + 2) * 4 * N + (kbar + 3) * 4 * N
+    per_sweep = (8 + dbytes) * slots + 4 * (N // 64 + 1) + 24 * N + kbar * 4 * N + 16 * N + 12 * N
     per_fp = (4 * nnz + 4 * (N + 1) + 24 * N) + (28 * nnz + 4 * (N + 1) + 57 * N)
     return krylov * per_it + sweeps * per_sweep + steps * per_fp
 
@@ -109,6 +126,7 @@ def main():
     print("bench: building Q1 %d^3 MCL instance" % args.n, file=sys.stderr, flush=True)
     inst = I.config3(args.n)
     N, nnz = inst.N, inst.nnz
+    slots, dbytes = sell_layout(inst.row_ptr, inst.col)
     stream = torch.cuda.current_stream().cuda_stream
 
     def opts(**kw):
@@ -137,7 +155,7 @@ def main():
     assert s["fp_iters"] == args.steps, s
     value = N * args.steps / elapsed
     ms_per_step = 1e3 * elapsed / args.steps
-    model_bytes = step_model_bytes(N, nnz, s["krylov_iters"], s["refine_sweeps"], args.steps)
+    model_bytes = step_model_bytes(N, nnz, slots, dbytes, s["krylov_iters"], s["refine_sweeps"], args.steps)
     print("bench: %.1f ms/step, %d Krylov its" % (ms_per_step, s["krylov_iters"]), file=sys.stderr, flush=True)
 
     # --- the same steps again with per-kernel HIP events (roofline) ----------
@@ -155,7 +173,7 @@ def main():
         ("residual", afc.AFC_KERNEL_RESIDUAL), ("mcl", afc.AFC_KERNEL_MCL), ("finish", afc.AFC_KERNEL_FINISH))}
     # launches after convergence of a cycle are no-ops; divide by SpMVs performed
     spmv_avg_s = 1e-3 * spmv_ms / max(1, s2["krylov_iters"])
-    spmv_b = spmv32_bytes(N, nnz)
+    spmv_b = spmv32_bytes(N, slots, dbytes)
     achieved = spmv_b / spmv_avg_s / 1e9
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
@@ -164,7 +182,8 @@ def main():
         if tr.get("kernel_source_sha") == kernel_source_hash() and tr.get("nnz") == nnz:
             traffic = tr.get("bytes_per_launch")
     roofline = {
-        "kernel": "k_spmv32_stream (FP32 CSR SpMV, GMRES inner)",
+        "kernel": "k_sell_spmv32 (FP32 SELL-64 SpMV, GMRES inner)",
+        "sell_slots": slots, "delta_bytes": dbytes,
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
         "bytes_per_launch": spmv_b, "avg_launch_us": round(spmv_avg_s * 1e6, 2),

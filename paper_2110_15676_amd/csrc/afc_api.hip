@@ -113,6 +113,7 @@ void free_all(afc_handle* h) {
   f(h->mij); f(h->dp_fct); f(h->AL_fct);
   f(h->cc); f(h->ccT); f(h->AL_mcl); f(h->dinv_mcl); f(h->A32_mcl);
   f(h->A_cn); f(h->dinv_cn); f(h->A32_cn);
+  f(h->sl_ptr); f(h->sl_dlt); f(h->sell_pos); f(h->S64_mcl); f(h->S32_mcl); f(h->S64_cn); f(h->S32_cn);
   for (auto*& p : h->w) f(p);
   h->w.clear();
   f(h->V64); f(h->V32);
@@ -149,9 +150,10 @@ void ensure_basis(afc_handle* h, int m, bool fp32) {
 }
 
 struct SysMat {
-  const double* A;
-  const double* dinv;
-  const float* A32;
+  const double* A;    // CSR values (BiCGStab)
+  const double* dinv; // inverse diagonal (right Jacobi)
+  const double* S64;  // same matrix in SELL order (GMRES FP64, residuals)
+  const float* S32;   // Jacobi-scaled FP32 copy in SELL order (mixed GMRES)
 };
 
 struct SolveOut {
@@ -193,19 +195,20 @@ SolveOut solve_gmres(afc_handle* h, const SysMat& S, const double* b, double* x,
   while (res > tol) {
     for (int k = 0; k < m; ++k) {
       if (mixed)
-        afc::gmres_spmv32(h, S.A32, k);
+        afc::gmres_spmv32(h, S.S32, k, m);
       else
-        afc::gmres_spmv64(h, S.A, S.dinv, k);
+        afc::gmres_spmv64(h, S.S64, S.dinv, k, m);
       afc::gmres_dots(h, mixed, k, m);
       afc::gmres_update(h, mixed, k, m);
     }
+    afc::gmres_last_givens(h, mixed, m - 1, m);
     afc::gmres_solve(h, m);
     afc::gmres_xupdate(h, mixed, S.dinv, x);
     if (mixed) {
-      afc::residual(h, S.A, b, x, r, 2, tol, inner_rel);
+      afc::residual(h, S.S64, b, x, r, 2, tol, inner_rel);
       afc::cast_v0(h, r);
     } else {
-      afc::residual(h, S.A, b, x, h->V64, 1, tol, 0.0);
+      afc::residual(h, S.S64, b, x, h->V64, 1, tol, 0.0);
     }
     o.sweeps += 1;
     sync_status(h);
@@ -255,7 +258,7 @@ SolveOut solve_bicgstab(afc_handle* h, const SysMat& S, const double* b, double*
     }
     const bool breakdown = h->host_status->flag == 1;
     // confirm on the true residual
-    afc::residual(h, S.A, b, x, r, 0, 0.0, 0.0);
+    afc::residual(h, S.S64, b, x, r, 0, 0.0, 0.0);
     sync_status(h);
     const double res = std::sqrt(h->host_status->red[0]);
     o.res = res;
@@ -590,6 +593,57 @@ afc_status afc_create(const afc_problem* p, const afc_options* opt, afc_handle**
     h->A_cn = dalloc<double>(h, (size_t)nnz);
     h->A32_cn = dalloc<float>(h, (size_t)nnz);
     h->dinv_cn = dalloc<double>(h, (size_t)N);
+    // SELL-64 layout of the Krylov matrices: slices of 64 rows padded to the
+    // slice's longest row, column deltas j - i (16-bit when they fit)
+    {
+      const int nsl = (N + 63) / 64;
+      std::vector<int> slp(nsl + 1, 0);
+      int maxd = 0;
+      for (int sl = 0; sl < nsl; ++sl) {
+        int L = 0;
+        for (int i = sl * 64; i < std::min(N, sl * 64 + 64); ++i) {
+          L = std::max(L, rp[i + 1] - rp[i]);
+          for (int k = rp[i]; k < rp[i + 1]; ++k) maxd = std::max(maxd, std::abs(col[k] - i));
+        }
+        if ((int64_t)slp[sl] + 64LL * L >= (int64_t)std::numeric_limits<int>::max())
+          fail(h, AFC_EINVAL, "SELL layout exceeds 2^31 slots");
+        slp[sl + 1] = slp[sl] + 64 * L;
+      }
+      const size_t slots = (size_t)slp[nsl];
+      h->nslices = nsl;
+      h->sell_slots = (int64_t)slots;
+      h->dlt16 = maxd <= 32767;
+      std::vector<int> pos((size_t)nnz);
+      std::vector<int16_t> d16(h->dlt16 ? slots : 0, 0);
+      std::vector<int32_t> d32(h->dlt16 ? 0 : slots, 0);
+      for (int i = 0; i < N; ++i) {
+        const int sl = i / 64, lane = i % 64;
+        for (int k = rp[i]; k < rp[i + 1]; ++k) {
+          const int q = slp[sl] + 64 * (k - rp[i]) + lane;
+          pos[k] = q;
+          if (h->dlt16)
+            d16[q] = (int16_t)(col[k] - i);
+          else
+            d32[q] = col[k] - i;
+        }
+      }
+      h->sl_ptr = upload(h, slp);
+      h->sell_pos = upload(h, pos);
+      if (h->dlt16)
+        h->sl_dlt = upload(h, d16);
+      else
+        h->sl_dlt = upload(h, d32);
+      h->S64_mcl = dalloc<double>(h, slots);
+      h->S32_mcl = dalloc<float>(h, slots);
+      h->S64_cn = dalloc<double>(h, slots);
+      h->S32_cn = dalloc<float>(h, slots);
+      HIP_OK(hipMemset(h->S64_mcl, 0, slots * sizeof(double)));
+      HIP_OK(hipMemset(h->S32_mcl, 0, slots * sizeof(float)));
+      HIP_OK(hipMemset(h->S64_cn, 0, slots * sizeof(double)));
+      HIP_OK(hipMemset(h->S32_cn, 0, slots * sizeof(float)));
+      afc::to_sell64(h, h->AL_mcl, h->S64_mcl);
+      afc::to_sell32_scaled(h, h->AL_mcl, h->dinv_mcl, h->S32_mcl);
+    }
     // solver state
     h->partials = dalloc<double>(h, (size_t)kMaxRed * kRedBlocks);
     h->ks = dalloc<KState>(h, 1);
@@ -724,7 +778,7 @@ afc_status afc_step_cn(afc_handle* h, double* u, const double* F_old, const doub
         afc::cn_predict(h, uo, a.Fo, a.Fn, a.dt, ut, g);  // eq. (14) and the right-hand side of eq. (11)
         afc::zalesak_Q(h, ut, Qp, Qm);
         afc::set_dirichlet(h, a.u);
-        const SysMat S{h->A_cn, h->dinv_cn, h->A32_cn};
+        const SysMat S{h->A_cn, h->dinv_cn, h->S64_cn, h->S32_cn};
         const double dt = a.dt;
         auto eval = [&](double* u, double* b, double* r) {
           afc::cn_limit_R(h, u, uo, Qp, Qm, dt, Rp, Rm);
@@ -754,7 +808,7 @@ afc_status afc_solve_stationary(afc_handle* h, double* u, const double* F, int32
       h, st,
       [](afc_handle* h, void* ctx) -> afc_status {
         const StatArgs& a = *static_cast<StatArgs*>(ctx);
-        const SysMat S{h->AL_mcl, h->dinv_mcl, h->A32_mcl};
+        const SysMat S{h->AL_mcl, h->dinv_mcl, h->S64_mcl, h->S32_mcl};
         double* b = h->w[W_B];
         double* r = h->w[W_R];
         if (a.init_low) {  // low-order solution A_low u = F (alpha = 0), from zero
@@ -762,7 +816,7 @@ afc_status afc_solve_stationary(afc_handle* h, double* u, const double* F, int32
           afc::fill(h, a.u, 0.0);
           afc::set_dirichlet(h, a.u);
           afc::norm2(h, b, 1);
-          afc::residual(h, S.A, b, a.u, r, 0, 0.0, 0.0);
+          afc::residual(h, S.S64, b, a.u, r, 0, 0.0, 0.0);
           sync_status(h);
           const double tol = std::max(h->opt.lin_atol, h->opt.lin_rtol * std::sqrt(h->host_status->red[1]));
           const SolveOut o = linear_solve(h, S, b, a.u, r, 0, tol);

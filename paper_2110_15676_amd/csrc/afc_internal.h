@@ -76,6 +76,20 @@ struct afc_handle_s {
   double* dinv_mcl = nullptr;
   float* A32_mcl = nullptr;  // A_low D^{-1} in FP32
 
+  // SELL-64 layout of the Krylov system matrices (one 64-row slice per wave,
+  // entries column-major in a slice, column deltas j - i); padding entries
+  // have value 0 and delta 0.  sell_pos maps each CSR entry to its slot.
+  int nslices = 0;
+  int* sl_ptr = nullptr;      // [nslices + 1] slot offsets (multiples of 64)
+  void* sl_dlt = nullptr;     // int16 when every |j - i| <= 32767, else int32
+  bool dlt16 = true;
+  int* sell_pos = nullptr;    // [nnz]
+  double* S64_mcl = nullptr;  // A_low (MCL) in SELL order
+  float* S32_mcl = nullptr;   // A_low D^{-1} (MCL) in SELL order, FP32
+  double* S64_cn = nullptr;
+  float* S32_cn = nullptr;
+  int64_t sell_slots = 0;
+
   // CN system M_L/dt + A_low/2 (built for the last dt used)
   double cn_dt = 0.0;
   double* A_cn = nullptr;

@@ -16,10 +16,12 @@ void fill(H* h, double* u, double v);
 void norm2(H* h, const double* x, int red_idx);             // ||x||^2 into ks->red[red_idx]
 
 // --- setup --------------------------------------------------------------------
-void build_cn_matrix(H* h, double dt);  // A_cn = M_L/dt + A_low/2 (+ dinv, FP32 scaled copy)
+void build_cn_matrix(H* h, double dt);  // A_cn = M_L/dt + A_low/2 (+ dinv, SELL FP64 and scaled FP32 copies)
+void to_sell64(H* h, const double* csr, double* sell);                       // CSR values -> SELL slots
+void to_sell32_scaled(H* h, const double* csr, const double* dinv, float* sell);  // (a_ij dinv_j) in FP32
 
 // --- residual of a linear system (FP64 SpMV) -----------------------------------
-// r = b - A x and ||r||^2 into ks->red[0]; mode selects the cycle start that
+// r = b - A x (A in SELL order) and ||r||^2 into ks->red[0]; mode selects the cycle start that
 // the last workgroup performs (0: none, 1: GMRES FP64 restart into V64[0],
 // 2: GMRES mixed restart, V32[0] cast done by cast_v0).
 void residual(H* h, const double* A, const double* b, const double* x, double* r, int mode, double tol_abs,
@@ -28,10 +30,13 @@ void cycle_start(H* h, int mode, int red_idx, double tol_abs, double tol_rel);  
 void cast_v0(H* h, const double* r);
 
 // --- GMRES (right Jacobi), FP64 or FP32 Arnoldi --------------------------------
-void gmres_spmv64(H* h, const double* A, const double* dinv, int k);
-void gmres_spmv32(H* h, const float* A32, int k);
+// Arnoldi step k = spmv (finishes step k-1) + dots + update (finishes the
+// projections); the last step of a cycle is finished by gmres_last_givens.
+void gmres_spmv64(H* h, const double* A, const double* dinv, int k, int m);
+void gmres_spmv32(H* h, const float* A32, int k, int m);
 void gmres_dots(H* h, bool fp32, int k, int m);
 void gmres_update(H* h, bool fp32, int k, int m);
+void gmres_last_givens(H* h, bool fp32, int k, int m);
 void gmres_solve(H* h, int m);
 void gmres_xupdate(H* h, bool fp32, const double* dinv, double* x);
 

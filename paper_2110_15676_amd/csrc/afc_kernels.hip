@@ -69,6 +69,27 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Block totals of NV per-thread values for workgroups of NT threads.
+template <int NT, int NV>
+__device__ void block_partials_n(const double (&v)[NV], int nv, double* partials, int slot) {
+  __shared__ double sh[NV][NT / 64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    if (q < nv) {
+      const double s = wave_sum(v[q]);
+      if (lane == 0) sh[q][wv] = s;
+    }
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < nv; q += NT) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) s += sh[q][w];
+    partials[(size_t)q * kRedBlocks + slot] = s;
+  }
+}
+
 // Block totals of nv per-thread values into partials[q * kRedBlocks + slot].
 template <int KMAX>
 __device__ void block_partials(const double (&v)[KMAX], int nv, double* partials, int slot) {
@@ -88,6 +109,27 @@ __device__ void block_partials(const double (&v)[KMAX], int nv, double* partials
     for (int w = 0; w < kBlock / 64; ++w) s += sh[q][w];
     partials[(size_t)q * kRedBlocks + slot] = s;
   }
+}
+
+// Partial rows used by the fused GMRES step: projection partials in rows
+// 0..k, the squared norm of the new basis vector in the last row.
+constexpr int kNormRow = kMaxRed - 1;
+constexpr int kVecBlock = 1024;  // workgroup of the GMRES vector kernels (16 waves)
+
+// Every workgroup of the calling kernel sums the same partials in the same
+// fixed order (wave q takes rows q, q + NW, ...; lanes stride the slots), so
+// all workgroups obtain bitwise identical totals.  out is LDS.
+template <int NT>
+__device__ void sum_partial_rows(const double* __restrict__ partials, int row0, int nrows, int nb,
+                                 double* out) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int q = wv; q < nrows; q += NT / 64) {
+    double s = 0.0;
+    for (int b = lane; b < nb; b += 64) s += partials[(size_t)(row0 + q) * kRedBlocks + b];
+    s = wave_sum(s);
+    if (lane == 0) out[q] = s;
+  }
+  __syncthreads();
 }
 
 // Start of a Krylov cycle from the squared norm of its residual.
@@ -202,163 +244,216 @@ __global__ __launch_bounds__(kBlock) void k_cast_v0(int N, const double* __restr
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) V0[i] = (float)(r[i] * inv);
 }
 
+// Givens step for Arnoldi column k, called by every thread of one workgroup:
+// the column and the previous rotations are staged in LDS in parallel, one
+// thread applies the rotation chain carrying the running entry in a register,
+// and the updated column is written back in parallel.
+__device__ void givens_step(KState* ks, int k, int m, double hk1sq) {
+  __shared__ double col[kMaxRestart + 1], c[kMaxRestart], sgn[kMaxRestart];
+  double* Hk = ks->H + (size_t)k * (m + 1);
+  for (int q = threadIdx.x; q <= k; q += blockDim.x) col[q] = Hk[q];
+  for (int q = threadIdx.x; q < k; q += blockDim.x) {
+    c[q] = ks->cs[q];
+    sgn[q] = ks->sn[q];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double hk1 = sqrt(hk1sq);
+    if (!isfinite(hk1)) {
+      ks->flag = 2;
+      ks->done = 1;
+    } else {
+      ks->sc[k + 1] = hk1 > 0.0 ? 1.0 / hk1 : 0.0;
+      double cur = col[0];
+      for (int jj = 0; jj < k; ++jj) {
+        const double nxt = col[jj + 1];
+        col[jj] = c[jj] * cur + sgn[jj] * nxt;
+        cur = -sgn[jj] * cur + c[jj] * nxt;
+      }
+      const double den = hypot(cur, hk1);
+      if (den == 0.0) {  // w = 0 in exact arithmetic: the column adds nothing
+        ks->done = 1;
+        col[k] = cur;
+        col[k + 1] = hk1;
+      } else {
+        const double cs = cur / den, sn = hk1 / den;
+        ks->cs[k] = cs;
+        ks->sn[k] = sn;
+        col[k] = den;
+        col[k + 1] = 0.0;
+        const double gk = ks->g[k];
+        ks->g[k + 1] = -sn * gk;
+        ks->g[k] = cs * gk;
+        ks->k = k + 1;
+        ks->iters += 1;
+        ks->res = fabs(ks->g[k + 1]);
+        if (ks->res <= ks->tol || hk1 == 0.0) ks->done = 1;
+      }
+    }
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q <= k + 1; q += blockDim.x) Hk[q] = col[q];
+}
+
+// ks->done read once per workgroup (workgroup 0 of the fused SpMV may set it
+// while other workgroups start), so the early return is workgroup-uniform.
+__device__ bool block_done(const KState* ks) {
+  __shared__ int d;
+  if (threadIdx.x == 0) d = __hip_atomic_load(&ks->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  const bool r = d != 0;
+  __syncthreads();
+  return r;
+}
+
+// Finish of Arnoldi step k - 1 at the start of step k's projections: every
+// workgroup sums the norm partials of V[k] in the same order, workgroup 0
+// applies the Givens rotation of column k - 1 (which sets sc_k and may end the
+// cycle).  A cycle that converged at step k - 1 thus runs one redundant SpMV
+// and projection pass; later kernels see ks->done and return.
+__device__ void finish_prev_step(KState* ks, const double* __restrict__ partials, int nbu, int k, int m) {
+  if (k == 0) return;
+  __shared__ double nrm2[1];
+  sum_partial_rows<kVecBlock>(partials, kNormRow, 1, nbu, nrm2);
+  if (blockIdx.x == 0) givens_step(ks, k - 1, m, nrm2[0]);
+}
+
 // ---------------------------------------------------------------------------
-// CSR-stream SpMV: a workgroup owns a tile of consecutive rows, streams the
-// tile's nonzeros with fully coalesced loads (one entry per lane per pass),
-// stages the products in LDS and sums each row from LDS.  Tiles whose
-// nonzeros do not fit in LDS fall back to one wave per row.
+// SELL-64 SpMV: one wave per 64-row slice, one row per lane.  Entry p of
+// the slice's rows lies at slot base + 64 p + lane, so value and delta loads
+// are contiguous across the wave, and on a structured mesh the gathers
+// x[i + delta] of neighbouring lanes hit neighbouring addresses.  Rows are
+// accumulated in registers; no LDS and no shuffles.
 // ---------------------------------------------------------------------------
 
-constexpr int kTileRowsF = 256;   // FP32: rows per tile (one row per thread when summing)
-constexpr int kTileNnzF = 8192;   // FP32 products staged per tile (32 KB)
-constexpr int kTileRowsD = 128;   // FP64
-constexpr int kTileNnzD = 4096;   // FP64 products staged per tile (32 KB)
-
-__device__ __forceinline__ float wave_sumf(float v) {
+template <typename TI>
+__global__ __launch_bounds__(kBlock) void k_sell_spmv32(int N, int nsl, const int* __restrict__ sl_ptr,
+                                                        const TI* __restrict__ dlt, const float* __restrict__ val,
+                                                        const float* __restrict__ x, KState* ks,
+                                                        const double* __restrict__ partials, int nbu, int k, int m,
+                                                        float* __restrict__ y) {
+  if (ks->done) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int t0, t1;
+  tile_range((nsl + kBlock / 64 - 1) / (kBlock / 64), t0, t1);
+  for (int t = t0; t < t1; ++t) {
+    const int s = t * (kBlock / 64) + wv;
+    if (s >= nsl) continue;
+    const int i = s * 64 + lane;
+    if (i >= N) continue;
+    const int b = sl_ptr[s];
+    const int L = (sl_ptr[s + 1] - b) >> 6;
+    const TI* __restrict__ d = dlt + b + lane;
+    const float* __restrict__ v = val + b + lane;
+    float acc = 0.0f;
+    int p = 0;
+    for (; p + 8 <= L; p += 8) {
+      int j[8];
+      float a[8];
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-// y = mul * A x (FP32, Jacobi-scaled matrix of the mixed-precision GMRES)
-__global__ __launch_bounds__(kBlock) void k_spmv32_stream(int N, const int* __restrict__ rp,
-                                                          const int* __restrict__ col, const float* __restrict__ A,
-                                                          const float* __restrict__ x,
-                                                          const double* __restrict__ mulp, float* __restrict__ y,
-                                                          const int* __restrict__ done) {
-  if (*done) return;
-  __shared__ float prod[kTileNnzF];
-  __shared__ int rps[kTileRowsF + 1];
-  const float mul = (float)*mulp;
-  int t0, t1;
-  tile_range((N + kTileRowsF - 1) / kTileRowsF, t0, t1);
-  for (int t = t0; t < t1; ++t) {
-    const int r0 = t * kTileRowsF;
-    const int nr = min(kTileRowsF, N - r0);
-    for (int q = threadIdx.x; q <= nr; q += kBlock) rps[q] = rp[r0 + q];
-    __syncthreads();
-    const int k0 = rps[0];
-    const int len = rps[nr] - k0;
-    if (len <= kTileNnzF) {
-#pragma unroll 4
-      for (int e = threadIdx.x; e < len; e += kBlock) prod[e] = A[k0 + e] * x[col[k0 + e]];
-      __syncthreads();
-      if (threadIdx.x < nr) {
-        float s = 0.0f;
-        const int a = rps[threadIdx.x] - k0, b = rps[threadIdx.x + 1] - k0;
-        for (int e = a; e < b; ++e) s += prod[e];
-        y[r0 + threadIdx.x] = mul * s;
+      for (int u = 0; u < 8; ++u) {
+        j[u] = i + d[64 * (p + u)];
+        a[u] = v[64 * (p + u)];
       }
-    } else {
-      const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-      for (int rr = wv; rr < nr; rr += kBlock / 64) {
-        float s = 0.0f;
-        for (int kk = rps[rr] + lane; kk < rps[rr + 1]; kk += 64) s += A[kk] * x[col[kk]];
-        s = wave_sumf(s);
-        if (lane == 0) y[r0 + rr] = mul * s;
-      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc += a[u] * x[j[u]];
     }
-    __syncthreads();
+    for (; p < L; ++p) acc += v[64 * p] * x[i + d[64 * p]];
+    y[i] = acc;
   }
 }
 
-// y = mul * A (s .* x) (FP64, right Jacobi scaling applied on the fly)
-__global__ __launch_bounds__(kBlock) void k_spmv64_stream(int N, const int* __restrict__ rp,
-                                                          const int* __restrict__ col, const double* __restrict__ A,
-                                                          const double* __restrict__ sc,
-                                                          const double* __restrict__ x,
-                                                          const double* __restrict__ mulp, double* __restrict__ y,
-                                                          const int* __restrict__ done) {
-  if (*done) return;
-  __shared__ double prod[kTileNnzD];
-  __shared__ int rps[kTileRowsD + 1];
-  const double mul = *mulp;
+// FP64: y = mul * A (s .* x)
+template <typename TI>
+__global__ __launch_bounds__(kBlock) void k_sell_spmv64(int N, int nsl, const int* __restrict__ sl_ptr,
+                                                        const TI* __restrict__ dlt, const double* __restrict__ val,
+                                                        const double* __restrict__ sc, const double* __restrict__ x,
+                                                        KState* ks, const double* __restrict__ partials, int nbu,
+                                                        int k, int m, double* __restrict__ y) {
+  if (ks->done) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   int t0, t1;
-  tile_range((N + kTileRowsD - 1) / kTileRowsD, t0, t1);
+  tile_range((nsl + kBlock / 64 - 1) / (kBlock / 64), t0, t1);
   for (int t = t0; t < t1; ++t) {
-    const int r0 = t * kTileRowsD;
-    const int nr = min(kTileRowsD, N - r0);
-    for (int q = threadIdx.x; q <= nr; q += kBlock) rps[q] = rp[r0 + q];
-    __syncthreads();
-    const int k0 = rps[0];
-    const int len = rps[nr] - k0;
-    if (len <= kTileNnzD) {
-#pragma unroll 4
-      for (int e = threadIdx.x; e < len; e += kBlock) {
-        const int j = col[k0 + e];
-        prod[e] = A[k0 + e] * (sc[j] * x[j]);
-      }
-      __syncthreads();
-      if (threadIdx.x < nr) {
-        double s = 0.0;
-        const int a = rps[threadIdx.x] - k0, b = rps[threadIdx.x + 1] - k0;
-        for (int e = a; e < b; ++e) s += prod[e];
-        y[r0 + threadIdx.x] = mul * s;
-      }
-    } else {
-      const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-      for (int rr = wv; rr < nr; rr += kBlock / 64) {
-        double s = 0.0;
-        for (int kk = rps[rr] + lane; kk < rps[rr + 1]; kk += 64) {
-          const int j = col[kk];
-          s += A[kk] * (sc[j] * x[j]);
-        }
-        s = wave_sum(s);
-        if (lane == 0) y[r0 + rr] = mul * s;
-      }
+    const int s = t * (kBlock / 64) + wv;
+    if (s >= nsl) continue;
+    const int i = s * 64 + lane;
+    if (i >= N) continue;
+    const int b = sl_ptr[s];
+    const int L = (sl_ptr[s + 1] - b) >> 6;
+    const TI* __restrict__ d = dlt + b + lane;
+    const double* __restrict__ v = val + b + lane;
+    double acc = 0.0;
+    int p = 0;
+    for (; p + 4 <= L; p += 4) {
+      const int j0 = i + d[64 * p], j1 = i + d[64 * (p + 1)], j2 = i + d[64 * (p + 2)], j3 = i + d[64 * (p + 3)];
+      const double a0 = v[64 * p], a1 = v[64 * (p + 1)], a2 = v[64 * (p + 2)], a3 = v[64 * (p + 3)];
+      acc += a0 * (sc[j0] * x[j0]);
+      acc += a1 * (sc[j1] * x[j1]);
+      acc += a2 * (sc[j2] * x[j2]);
+      acc += a3 * (sc[j3] * x[j3]);
     }
-    __syncthreads();
+    for (; p < L; ++p) {
+      const int j = i + d[64 * p];
+      acc += v[64 * p] * (sc[j] * x[j]);
+    }
+    y[i] = acc;
   }
 }
 
-// r = b - A x (FP64), ||r||^2, optional Krylov cycle start
-__global__ __launch_bounds__(kBlock) void k_residual_stream(int N, const int* __restrict__ rp,
-                                                            const int* __restrict__ col,
-                                                            const double* __restrict__ A,
-                                                            const double* __restrict__ b,
-                                                            const double* __restrict__ x, double* __restrict__ r,
-                                                            KState* ks, double* partials,
-                                                            int mode, double tol_abs, double tol_rel) {
-  __shared__ double prod[kTileNnzD];
-  __shared__ int rps[kTileRowsD + 1];
+// r = b - A x (FP64) with ||r||^2 partials
+template <typename TI>
+__global__ __launch_bounds__(kBlock) void k_sell_residual(int N, int nsl, const int* __restrict__ sl_ptr,
+                                                          const TI* __restrict__ dlt,
+                                                          const double* __restrict__ val,
+                                                          const double* __restrict__ bvec,
+                                                          const double* __restrict__ x, double* __restrict__ r,
+                                                          double* partials) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double nrm[1] = {0.0};
   int t0, t1;
-  tile_range((N + kTileRowsD - 1) / kTileRowsD, t0, t1);
+  tile_range((nsl + kBlock / 64 - 1) / (kBlock / 64), t0, t1);
   for (int t = t0; t < t1; ++t) {
-    const int r0 = t * kTileRowsD;
-    const int nr = min(kTileRowsD, N - r0);
-    for (int q = threadIdx.x; q <= nr; q += kBlock) rps[q] = rp[r0 + q];
-    __syncthreads();
-    const int k0 = rps[0];
-    const int len = rps[nr] - k0;
-    if (len <= kTileNnzD) {
-#pragma unroll 4
-      for (int e = threadIdx.x; e < len; e += kBlock) prod[e] = A[k0 + e] * x[col[k0 + e]];
-      __syncthreads();
-      if (threadIdx.x < nr) {
-        double s = 0.0;
-        const int a = rps[threadIdx.x] - k0, bb = rps[threadIdx.x + 1] - k0;
-        for (int e = a; e < bb; ++e) s += prod[e];
-        const double ri = b[r0 + threadIdx.x] - s;
-        r[r0 + threadIdx.x] = ri;
-        nrm[0] += ri * ri;
-      }
-    } else {
-      const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-      for (int rr = wv; rr < nr; rr += kBlock / 64) {
-        double s = 0.0;
-        for (int kk = rps[rr] + lane; kk < rps[rr + 1]; kk += 64) s += A[kk] * x[col[kk]];
-        s = wave_sum(s);
-        if (lane == 0) {
-          const double ri = b[r0 + rr] - s;
-          r[r0 + rr] = ri;
-          nrm[0] += ri * ri;
-        }
-      }
+    const int s = t * (kBlock / 64) + wv;
+    if (s >= nsl) continue;
+    const int i = s * 64 + lane;
+    if (i >= N) continue;
+    const int b = sl_ptr[s];
+    const int L = (sl_ptr[s + 1] - b) >> 6;
+    const TI* __restrict__ d = dlt + b + lane;
+    const double* __restrict__ v = val + b + lane;
+    double acc = 0.0;
+    int p = 0;
+    for (; p + 4 <= L; p += 4) {
+      const int j0 = i + d[64 * p], j1 = i + d[64 * (p + 1)], j2 = i + d[64 * (p + 2)], j3 = i + d[64 * (p + 3)];
+      const double a0 = v[64 * p], a1 = v[64 * (p + 1)], a2 = v[64 * (p + 2)], a3 = v[64 * (p + 3)];
+      acc += a0 * x[j0];
+      acc += a1 * x[j1];
+      acc += a2 * x[j2];
+      acc += a3 * x[j3];
     }
-    __syncthreads();
+    for (; p < L; ++p) acc += v[64 * p] * x[i + d[64 * p]];
+    const double ri = bvec[i] - acc;
+    r[i] = ri;
+    nrm[0] += ri * ri;
   }
   block_partials<1>(nrm, 1, partials, blockIdx.x);
+}
+
+// CSR values -> SELL slots (padding slots were zeroed at allocation)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_to_sell(int nnz, const int* __restrict__ pos, const T* __restrict__ src,
+                                                    T* __restrict__ dst) {
+  for (int k = blockIdx.x * kBlock + threadIdx.x; k < nnz; k += gridDim.x * kBlock) dst[pos[k]] = src[k];
+}
+
+__global__ __launch_bounds__(kBlock) void k_to_sell_scaled32(int nnz, const int* __restrict__ pos,
+                                                             const int* __restrict__ col,
+                                                             const double* __restrict__ src,
+                                                             const double* __restrict__ dinv,
+                                                             float* __restrict__ dst) {
+  for (int k = blockIdx.x * kBlock + threadIdx.x; k < nnz; k += gridDim.x * kBlock)
+    dst[pos[k]] = (float)(src[k] * dinv[col[k]]);
 }
 
 // ---------------------------------------------------------------------------
@@ -408,21 +503,23 @@ __device__ __forceinline__ void store16(T* __restrict__ p, int e, int N, const T
 // h_{q,k} = sc_q (V[q], W), q = 0..k.  Each block streams chunks of
 // 2 x 16 B per thread of W and of every basis vector (four vectors per pass
 // for memory-level parallelism); per-wave sums accumulate in LDS.
+// Raw projections (V[q], W), q = 0..k, of the unscaled SpMV output W.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_gmres_dots(int N, int ldv, const T* __restrict__ V,
+__global__ __launch_bounds__(kVecBlock) void k_gmres_dots(int N, int ldv, const T* __restrict__ V,
                                                        const T* __restrict__ W, int k, int m, KState* ks,
-                                                       double* partials) {
-  if (ks->done) return;
+                                                       double* partials, int nbu) {
+  if (block_done(ks)) return;
+  finish_prev_step(ks, partials, nbu, k, m);
   constexpr int VN = 16 / sizeof(T);
-  constexpr int CH = kBlock * VN * 2;
-  constexpr int NW = kBlock / 64;
+  constexpr int CH = kVecBlock * VN * 2;
+  constexpr int NW = kVecBlock / 64;
   __shared__ double sh[kMaxRestart + 1][NW];
   const int nv = k + 1;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int q = threadIdx.x; q < nv * NW; q += kBlock) sh[q / NW][q % NW] = 0.0;
+  for (int q = threadIdx.x; q < nv * NW; q += kVecBlock) sh[q / NW][q % NW] = 0.0;
   __syncthreads();
   for (int base = blockIdx.x * CH; base < N; base += gridDim.x * CH) {
-    const int e0 = base + threadIdx.x * VN, e1 = e0 + kBlock * VN;
+    const int e0 = base + threadIdx.x * VN, e1 = e0 + kVecBlock * VN;
     T w0[VN], w1[VN];
     load16(W, e0, N, w0);
     load16(W, e1, N, w1);
@@ -459,7 +556,7 @@ __global__ __launch_bounds__(kBlock) void k_gmres_dots(int N, int ldv, const T* 
     }
   }
   __syncthreads();
-  for (int q = threadIdx.x; q < nv; q += kBlock) {
+  for (int q = threadIdx.x; q < nv; q += kVecBlock) {
     double t = 0.0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) t += sh[q][w];
@@ -467,63 +564,38 @@ __global__ __launch_bounds__(kBlock) void k_gmres_dots(int N, int ldv, const T* 
   }
 }
 
-__device__ void givens_step(KState* ks, int k, int m) {
-  double* Hk = ks->H + (size_t)k * (m + 1);
-  const double hk1 = sqrt(ks->red[0]);
-  if (!isfinite(hk1)) {
-    ks->flag = 2;
-    ks->done = 1;
-    return;
-  }
-  Hk[k + 1] = hk1;
-  ks->sc[k + 1] = hk1 > 0.0 ? 1.0 / hk1 : 0.0;
-  for (int jj = 0; jj < k; ++jj) {
-    const double a = Hk[jj], b = Hk[jj + 1];
-    Hk[jj] = ks->cs[jj] * a + ks->sn[jj] * b;
-    Hk[jj + 1] = -ks->sn[jj] * a + ks->cs[jj] * b;
-  }
-  const double den = hypot(Hk[k], Hk[k + 1]);
-  if (den == 0.0) {  // w = 0 in exact arithmetic: the column adds nothing
-    ks->done = 1;
-    return;
-  }
-  ks->cs[k] = Hk[k] / den;
-  ks->sn[k] = Hk[k + 1] / den;
-  Hk[k] = den;
-  Hk[k + 1] = 0.0;
-  ks->g[k + 1] = -ks->sn[k] * ks->g[k];
-  ks->g[k] = ks->cs[k] * ks->g[k];
-  ks->k = k + 1;
-  ks->iters += 1;
-  ks->res = fabs(ks->g[k + 1]);
-  if (ks->res <= ks->tol || hk1 == 0.0) ks->done = 1;
-}
-
 // V[k+1] = W - sum_q h_{q,k} sc_q V[q], its squared norm, then the Givens step.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_gmres_update(int N, int ldv, T* __restrict__ V,
+__global__ __launch_bounds__(kVecBlock) void k_gmres_update(int N, int ldv, T* __restrict__ V,
                                                          const T* __restrict__ W, int k, int m, KState* ks,
-                                                         double* partials) {
+                                                         double* partials, int nbd) {
   if (ks->done) return;
   constexpr int VN = 16 / sizeof(T);
-  constexpr int CH = kBlock * VN * 2;
+  constexpr int CH = kVecBlock * VN * 2;
   __shared__ double tq[kMaxRestart + 1];
   const int nv = k + 1;
-  const double* Hk = ks->H + (size_t)k * (m + 1);
-  for (int q = threadIdx.x; q < nv; q += kBlock) tq[q] = Hk[q] * ks->sc[q];
+  // projections h_{q,k} = sc_q sc_k (V[q], W): same fixed-order sums in every workgroup
+  sum_partial_rows<kVecBlock>(partials, 0, nv, nbd, tq);
+  const double sck = ks->sc[k];
+  double* Hk = ks->H + (size_t)k * (m + 1);
+  for (int q = threadIdx.x; q < nv; q += kVecBlock) {
+    const double hq = ks->sc[q] * sck * tq[q];
+    if (blockIdx.x == 0) Hk[q] = hq;
+    tq[q] = hq * ks->sc[q];
+  }
   __syncthreads();
   T* __restrict__ out = V + (size_t)(k + 1) * ldv;
   double nrm[1] = {0.0};
   for (int base = blockIdx.x * CH; base < N; base += gridDim.x * CH) {
-    const int e0 = base + threadIdx.x * VN, e1 = e0 + kBlock * VN;
+    const int e0 = base + threadIdx.x * VN, e1 = e0 + kVecBlock * VN;
     T w0[VN], w1[VN];
     load16(W, e0, N, w0);
     load16(W, e1, N, w1);
     double c0[VN], c1[VN];
 #pragma unroll
     for (int c = 0; c < VN; ++c) {
-      c0[c] = (double)w0[c];
-      c1[c] = (double)w1[c];
+      c0[c] = sck * (double)w0[c];
+      c1[c] = sck * (double)w1[c];
     }
     int q = 0;
     for (; q + 4 <= nv; q += 4) {
@@ -564,7 +636,7 @@ __global__ __launch_bounds__(kBlock) void k_gmres_update(int N, int ldv, T* __re
     store16(out, e0, N, o0);
     store16(out, e1, N, o1);
   }
-  block_partials<1>(nrm, 1, partials, blockIdx.x);
+  block_partials_n<kVecBlock, 1>(nrm, 1, partials + (size_t)kNormRow * kRedBlocks, blockIdx.x);
 }
 
 // back substitution R y = g over the columns completed in the cycle (one wave)
@@ -641,7 +713,7 @@ constexpr int kFinish = 1024;
 
 __global__ __launch_bounds__(kFinish) void k_finish(KState* ks, const double* __restrict__ partials, int nb, int nv,
                                                     int act, int red_off, int k, int m, int mode, double p1,
-                                                    double p2) {
+                                                    double p2, int prow) {
   switch (act) {
     case ACT_DOTS:
     case ACT_GIVENS:
@@ -660,7 +732,7 @@ __global__ __launch_bounds__(kFinish) void k_finish(KState* ks, const double* __
   double* red = ks->red + red_off;
   for (int q = wv; q < nv; q += kFinish / 64) {
     double s = 0.0;
-    for (int b = lane; b < nb; b += 64) s += partials[(size_t)q * kRedBlocks + b];
+    for (int b = lane; b < nb; b += 64) s += partials[(size_t)(prow + q) * kRedBlocks + b];
     s = wave_sum(s);
     if (lane == 0) red[q] = s;
   }
@@ -670,11 +742,12 @@ __global__ __launch_bounds__(kFinish) void k_finish(KState* ks, const double* __
     for (int q = threadIdx.x; q < nv; q += kFinish) Hk[q] = ks->sc[q] * red[q];
     return;
   }
+  if (act == ACT_GIVENS) {
+    givens_step(ks, k, m, red[0]);
+    return;
+  }
   if (threadIdx.x != 0) return;
   switch (act) {
-    case ACT_GIVENS:
-      givens_step(ks, k, m);
-      break;
     case ACT_CYCLE:
       if (mode != 0) cycle_start_dev(ks, mode, red[0], p1, p2);
       break;
@@ -1342,9 +1415,9 @@ void prof_release(afc_handle_s* h) {
 }
 
 void finish(H* h, int nb, int nv, int act, int red_off = 0, int k = 0, int m = 0, int mode = 0, double p1 = 0.0,
-            double p2 = 0.0) {
+            double p2 = 0.0, int prow = 0) {
   ProfScope ps(h, AFC_KERNEL_FINISH);
-  k_finish<<<1, kFinish, 0, h->stream>>>(h->ks, h->partials, nb, nv, act, red_off, k, m, mode, p1, p2);
+  k_finish<<<1, kFinish, 0, h->stream>>>(h->ks, h->partials, nb, nv, act, red_off, k, m, mode, p1, p2, prow);
 }
 
 void copy(H* h, double* dst, const double* src) { k_copy<<<vec_grid(h), kBlock, 0, h->stream>>>(h->N, dst, src); }
@@ -1369,29 +1442,40 @@ void relax(H* h, double* u, const double* x, double omega) {
   k_relax<<<vec_grid(h), kBlock, 0, h->stream>>>(h->N, u, x, omega);
 }
 
-void build_cn_matrix(H* h, double dt) {
-  AFC_DISPATCH_G(h, k_build_cn, row_grid(h, false), h->N, h->row_ptr, h->col, h->AL_fct, h->ml, h->is_dir,
-                 1.0 / dt, h->A_cn, h->dinv_cn);
-  AFC_DISPATCH_G(h, k_scale32, row_grid(h, false), h->N, h->row_ptr, h->col, h->A_cn, h->dinv_cn, h->A32_cn);
-}
 
-
-int stream_grid(const H* h, int rows, bool reduce) {
-  const int nt = (h->N + rows - 1) / rows;
-  return std::max(1, std::min(nt, reduce ? kRedBlocks : kRowGridCap));
-}
 
 int vec16_grid(const H* h, int elems_per_block) {
   return std::max(1, std::min((h->N + elems_per_block - 1) / elems_per_block, kRedBlocks));
 }
 
+int sell_grid(const H* h, bool reduce) {
+  const int nt = (h->nslices + kBlock / 64 - 1) / (kBlock / 64);
+  return std::max(1, std::min(nt, reduce ? kRedBlocks : kRowGridCap));
+}
+
 void residual(H* h, const double* A, const double* b, const double* x, double* r, int mode, double tol_abs,
               double tol_rel) {
-  const int nb = stream_grid(h, kTileRowsD, true);
-  ProfScope ps(h, AFC_KERNEL_RESIDUAL);
-  k_residual_stream<<<nb, kBlock, 0, h->stream>>>(h->N, h->row_ptr, h->col, A, b, x, r, h->ks, h->partials, mode,
-                                                  tol_abs, tol_rel);
+  const int nb = sell_grid(h, true);
+  {
+    ProfScope ps(h, AFC_KERNEL_RESIDUAL);
+    if (h->dlt16)
+      k_sell_residual<int16_t><<<nb, kBlock, 0, h->stream>>>(h->N, h->nslices, h->sl_ptr,
+                                                             static_cast<const int16_t*>(h->sl_dlt), A, b, x, r,
+                                                             h->partials);
+    else
+      k_sell_residual<int32_t><<<nb, kBlock, 0, h->stream>>>(h->N, h->nslices, h->sl_ptr,
+                                                             static_cast<const int32_t*>(h->sl_dlt), A, b, x, r,
+                                                             h->partials);
+  }
   finish(h, nb, 1, ACT_CYCLE, 0, 0, 0, mode, tol_abs, tol_rel);
+}
+
+void to_sell64(H* h, const double* csr, double* sell) {
+  k_to_sell<double><<<vec_grid(h), kBlock, 0, h->stream>>>((int)h->nnz, h->sell_pos, csr, sell);
+}
+
+void to_sell32_scaled(H* h, const double* csr, const double* dinv, float* sell) {
+  k_to_sell_scaled32<<<vec_grid(h), kBlock, 0, h->stream>>>((int)h->nnz, h->sell_pos, h->col, csr, dinv, sell);
 }
 
 void cycle_start(H* h, int mode, int red_idx, double tol_abs, double tol_rel) {
@@ -1400,44 +1484,62 @@ void cycle_start(H* h, int mode, int red_idx, double tol_abs, double tol_rel) {
 
 void cast_v0(H* h, const double* r) { k_cast_v0<<<vec_grid(h), kBlock, 0, h->stream>>>(h->N, r, h->V32, h->ks); }
 
-void gmres_spmv64(H* h, const double* A, const double* dinv, int k) {
+int upd_grid(const H* h, bool fp32) { return vec16_grid(h, fp32 ? kVecBlock * 8 : kVecBlock * 4); }
+
+void gmres_spmv64(H* h, const double* A, const double* dinv, int k, int m) {
   ProfScope ps(h, AFC_KERNEL_SPMV64);
-  k_spmv64_stream<<<stream_grid(h, kTileRowsD, false), kBlock, 0, h->stream>>>(
-      h->N, h->row_ptr, h->col, A, dinv, h->V64 + (size_t)k * h->ldv, &h->ks->sc[k], h->w[0], &h->ks->done);
+  const double* x = h->V64 + (size_t)k * h->ldv;
+  const int nbu = upd_grid(h, false);
+  if (h->dlt16)
+    k_sell_spmv64<int16_t><<<sell_grid(h, false), kBlock, 0, h->stream>>>(
+        h->N, h->nslices, h->sl_ptr, static_cast<const int16_t*>(h->sl_dlt), A, dinv, x, h->ks, h->partials, nbu, k,
+        m, h->w[0]);
+  else
+    k_sell_spmv64<int32_t><<<sell_grid(h, false), kBlock, 0, h->stream>>>(
+        h->N, h->nslices, h->sl_ptr, static_cast<const int32_t*>(h->sl_dlt), A, dinv, x, h->ks, h->partials, nbu, k,
+        m, h->w[0]);
 }
 
-void gmres_spmv32(H* h, const float* A32, int k) {
+void gmres_spmv32(H* h, const float* A32, int k, int m) {
   ProfScope ps(h, AFC_KERNEL_SPMV32);
-  k_spmv32_stream<<<stream_grid(h, kTileRowsF, false), kBlock, 0, h->stream>>>(
-      h->N, h->row_ptr, h->col, A32, h->V32 + (size_t)k * h->ldv, &h->ks->sc[k],
-      reinterpret_cast<float*>(h->w[0]), &h->ks->done);
+  const float* x = h->V32 + (size_t)k * h->ldv;
+  float* y = reinterpret_cast<float*>(h->w[0]);
+  const int nbu = upd_grid(h, true);
+  if (h->dlt16)
+    k_sell_spmv32<int16_t><<<sell_grid(h, false), kBlock, 0, h->stream>>>(
+        h->N, h->nslices, h->sl_ptr, static_cast<const int16_t*>(h->sl_dlt), A32, x, h->ks, h->partials, nbu, k, m,
+        y);
+  else
+    k_sell_spmv32<int32_t><<<sell_grid(h, false), kBlock, 0, h->stream>>>(
+        h->N, h->nslices, h->sl_ptr, static_cast<const int32_t*>(h->sl_dlt), A32, x, h->ks, h->partials, nbu, k, m,
+        y);
 }
 
 void gmres_dots(H* h, bool fp32, int k, int m) {
-  const int nb = vec16_grid(h, fp32 ? kBlock * 8 : kBlock * 4);
-  {
+  const int nb = vec16_grid(h, fp32 ? kVecBlock * 8 : kVecBlock * 4);
   ProfScope ps(h, AFC_KERNEL_DOTS);
   if (fp32)
-    k_gmres_dots<float><<<nb, kBlock, 0, h->stream>>>(h->N, h->ldv, h->V32, reinterpret_cast<const float*>(h->w[0]),
-                                                      k, m, h->ks, h->partials);
+    k_gmres_dots<float><<<nb, kVecBlock, 0, h->stream>>>(h->N, h->ldv, h->V32, reinterpret_cast<const float*>(h->w[0]),
+                                                         k, m, h->ks, h->partials, nb);
   else
-    k_gmres_dots<double><<<nb, kBlock, 0, h->stream>>>(h->N, h->ldv, h->V64, h->w[0], k, m, h->ks, h->partials);
-  }
-  finish(h, nb, k + 1, ACT_DOTS, 0, k, m);
+    k_gmres_dots<double><<<nb, kVecBlock, 0, h->stream>>>(h->N, h->ldv, h->V64, h->w[0], k, m, h->ks, h->partials,
+                                                          nb);
 }
 
 void gmres_update(H* h, bool fp32, int k, int m) {
-  const int nb = vec16_grid(h, fp32 ? kBlock * 8 : kBlock * 4);
-  {
+  const int nb = upd_grid(h, fp32);
   ProfScope ps(h, AFC_KERNEL_UPDATE);
   if (fp32)
-    k_gmres_update<float><<<nb, kBlock, 0, h->stream>>>(h->N, h->ldv, h->V32,
-                                                        reinterpret_cast<const float*>(h->w[0]), k, m, h->ks,
-                                                        h->partials);
+    k_gmres_update<float><<<nb, kVecBlock, 0, h->stream>>>(h->N, h->ldv, h->V32,
+                                                           reinterpret_cast<const float*>(h->w[0]), k, m, h->ks,
+                                                           h->partials, nb);
   else
-    k_gmres_update<double><<<nb, kBlock, 0, h->stream>>>(h->N, h->ldv, h->V64, h->w[0], k, m, h->ks, h->partials);
-  }
-  finish(h, nb, 1, ACT_GIVENS, 0, k, m);
+    k_gmres_update<double><<<nb, kVecBlock, 0, h->stream>>>(h->N, h->ldv, h->V64, h->w[0], k, m, h->ks, h->partials,
+                                                            nb);
+}
+
+void gmres_last_givens(H* h, bool fp32, int k, int m) {
+  finish(h, upd_grid(h, fp32), 1, ACT_GIVENS, 0, k, m, 0, 0.0, 0.0, kNormRow);
 }
 
 void gmres_solve(H* h, int m) { k_gmres_solve<<<1, 64, 0, h->stream>>>(h->ks, m); }
@@ -1523,6 +1625,14 @@ void mcl_apply(H* h, const double* u, const double* umax, const double* umin, co
                  h->is_dir, h->uD, h->opt.alpha_mode, b, r, h->ks, h->partials);
   }
   finish(h, nb, 3, ACT_STORE);
+}
+
+void build_cn_matrix(H* h, double dt) {
+  AFC_DISPATCH_G(h, k_build_cn, row_grid(h, false), h->N, h->row_ptr, h->col, h->AL_fct, h->ml, h->is_dir,
+                 1.0 / dt, h->A_cn, h->dinv_cn);
+  AFC_DISPATCH_G(h, k_scale32, row_grid(h, false), h->N, h->row_ptr, h->col, h->A_cn, h->dinv_cn, h->A32_cn);
+  to_sell64(h, h->A_cn, h->S64_cn);
+  to_sell32_scaled(h, h->A_cn, h->dinv_cn, h->S32_cn);
 }
 
 }  // namespace afc
