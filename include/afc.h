@@ -188,6 +188,37 @@ afc_status afc_kernel_time(afc_handle *h, int32_t kernel, double *total_ms, int6
 /* Release every device and host resource of h (NULL is ignored). */
 void afc_destroy(afc_handle *h);
 
+/* ---- Batched Crank-Nicolson FCT ------------------------------------------
+ * Many independent instances (each its own CSR pattern, coefficients and dt)
+ * advanced by one persistent launch: every workgroup takes whole instances
+ * from a device queue (largest first) and runs all their CN steps (eqs. (11)-
+ * (14), Zalesak's limiter, fixed-point iteration with BiCGStab-Jacobi) with
+ * workgroup-local barriers only.  An instance's result does not depend on the
+ * other instances in the batch.  Vectors are packed: instance k occupies
+ * entries [offsets[k], offsets[k+1]) of u and F (afc_batch_offsets). */
+typedef struct afc_batch_s afc_batch;
+
+/* Create from count problems (same rules as afc_create).  The options must
+ * select BiCGStab and FP64; the other fields apply to every instance. */
+afc_status afc_batch_create(int32_t count, const afc_problem *probs, const afc_options *opt, afc_batch **out);
+
+/* offsets: host array of count + 1 entries; offsets[count] is the packed length. */
+afc_status afc_batch_offsets(const afc_batch *b, int64_t *offsets);
+
+/* Advance every instance by `steps` CN-FCT steps of its own dt (host array of
+ * count entries) with the time-independent load F (packed, device).  u:
+ * packed device vector, in u^{n}, out u^{n+steps}.  stats: NULL or a host
+ * array of count entries (fp_iters and krylov_iters summed over the steps).
+ * Returns the most severe per-instance status. */
+afc_status afc_batch_step_cn(afc_batch *b, double *u, const double *F, const double *dt, int32_t steps,
+                             afc_stats *stats);
+
+/* Description of the last error on b (b may be NULL: last creation error). */
+const char *afc_batch_last_error(const afc_batch *b);
+
+/* Release the batch (NULL is ignored). */
+void afc_batch_destroy(afc_batch *b);
+
 /* Static description of a status code. */
 const char *afc_status_str(int32_t status);
 

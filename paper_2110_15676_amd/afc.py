@@ -60,6 +60,7 @@ class afc_stats(ctypes.Structure):
 EXPORTS = [
     "afc_default_options", "afc_create", "afc_set_options", "afc_step_ssprk3", "afc_step_cn",
     "afc_solve_stationary", "afc_destroy", "afc_status_str", "afc_last_error", "afc_kernel_time",
+    "afc_batch_create", "afc_batch_offsets", "afc_batch_step_cn", "afc_batch_last_error", "afc_batch_destroy",
 ]
 
 AFC_KERNEL_SPMV32, AFC_KERNEL_SPMV64, AFC_KERNEL_DOTS, AFC_KERNEL_UPDATE = 0, 1, 2, 3
@@ -89,6 +90,17 @@ def lib():
         L.afc_solve_stationary.restype = c_int32
         L.afc_kernel_time.argtypes = [c_void_p, c_int32, POINTER(c_double), POINTER(c_int64), c_int32]
         L.afc_kernel_time.restype = c_int32
+        L.afc_batch_create.argtypes = [c_int32, POINTER(afc_problem), POINTER(afc_options), POINTER(c_void_p)]
+        L.afc_batch_create.restype = c_int32
+        L.afc_batch_offsets.argtypes = [c_void_p, POINTER(c_int64)]
+        L.afc_batch_offsets.restype = c_int32
+        L.afc_batch_step_cn.argtypes = [c_void_p, c_void_p, c_void_p, POINTER(c_double), c_int32,
+                                        POINTER(afc_stats)]
+        L.afc_batch_step_cn.restype = c_int32
+        L.afc_batch_last_error.argtypes = [c_void_p]
+        L.afc_batch_last_error.restype = c_char_p
+        L.afc_batch_destroy.argtypes = [c_void_p]
+        L.afc_batch_destroy.restype = None
         L.afc_destroy.argtypes = [c_void_p]
         L.afc_destroy.restype = None
         L.afc_status_str.argtypes = [c_int32]
@@ -229,3 +241,65 @@ def afc_kernel_time(h, kernel, reset=False):
 def afc_destroy(h):
     if h is not None and h.value:
         lib().afc_destroy(h)
+
+
+# ---------------------------------------------------------------------------
+# batched CN-FCT
+# ---------------------------------------------------------------------------
+
+
+def _host_problem(row_ptr, col, M, K, dir_idx, dir_val, keep):
+    arrs = [np.ascontiguousarray(row_ptr, dtype=np.int32), np.ascontiguousarray(col, dtype=np.int32),
+            np.ascontiguousarray(M, dtype=np.float64), np.ascontiguousarray(K, dtype=np.float64),
+            np.ascontiguousarray(dir_idx, dtype=np.int32), np.ascontiguousarray(dir_val, dtype=np.float64)]
+    keep.extend(arrs)
+    p = afc_problem()
+    p.n = int(arrs[0].shape[0] - 1)
+    p.nnz = int(arrs[1].shape[0])
+    p.mem_space = AFC_MEM_HOST
+    p.row_ptr, p.col_idx, p.M, p.K = (a.ctypes.data for a in arrs[:4])
+    p.K_conv = None
+    p.ML = None
+    p.n_dir = int(arrs[4].shape[0])
+    p.dir_idx = arrs[4].ctypes.data
+    p.dir_val = arrs[5].ctypes.data
+    return p
+
+
+def afc_batch_create(instances, opts=None):
+    """Batch handle from a list of inputs.Instance (host arrays)."""
+    keep = []
+    probs = (afc_problem * len(instances))()
+    for q, inst in enumerate(instances):
+        probs[q] = _host_problem(inst.row_ptr, inst.col, inst.M, inst.K, inst.dir_idx, inst.dir_val, keep)
+    if opts is None:
+        opts = afc_default_options(krylov=AFC_KRYLOV_BICGSTAB)
+    b = c_void_p()
+    st = lib().afc_batch_create(len(instances), probs, ctypes.byref(opts), ctypes.byref(b))
+    if st != AFC_OK:
+        raise AFCError(st, lib().afc_batch_last_error(None).decode())
+    return b
+
+
+def afc_batch_offsets(b, count):
+    off = (c_int64 * (count + 1))()
+    st = lib().afc_batch_offsets(b, off)
+    if st != AFC_OK:
+        raise AFCError(st, "afc_batch_offsets")
+    return np.array(off[:], dtype=np.int64)
+
+
+def afc_batch_step_cn(b, u, F, dt, steps, raise_on_error=True):
+    """Advance every instance by `steps` CN-FCT steps; dt: one value per instance."""
+    dt = np.ascontiguousarray(dt, dtype=np.float64)
+    stats = (afc_stats * dt.shape[0])()
+    st = lib().afc_batch_step_cn(b, u.data_ptr(), F.data_ptr(), dt.ctypes.data_as(POINTER(c_double)), int(steps),
+                                 stats)
+    if raise_on_error and st < 0:
+        raise AFCError(st, lib().afc_batch_last_error(b).decode())
+    return st, [s.as_dict() for s in stats]
+
+
+def afc_batch_destroy(b):
+    if b is not None and b.value:
+        lib().afc_batch_destroy(b)

@@ -10,9 +10,11 @@
 #include <cstddef>
 #include <cstring>
 #include <limits>
+#include <numeric>
 #include <string>
 #include <vector>
 
+#include "afc_batch_internal.h"
 #include "afc_kernels.h"
 
 using afc::KState;
@@ -28,20 +30,22 @@ enum Slot { W_ARN = 0, W_B, W_R, W_X, W_A, W_B2, W_RP, W_RM, W_UOLD, W_UT, W_G, 
 
 struct Fail {
   afc_status st;
+  std::string msg;
 };
 
 #define HIP_OK(expr)                                                                     \
   do {                                                                                   \
     hipError_t e_ = (expr);                                                              \
     if (e_ != hipSuccess) {                                                              \
-      if (h) h->last_error = std::string(#expr) + ": " + hipGetErrorString(e_);          \
-      throw Fail{AFC_EDEVICE};                                                           \
+      const std::string m_ = std::string(#expr) + ": " + hipGetErrorString(e_);          \
+      if (h) h->last_error = m_;                                                         \
+      throw Fail{AFC_EDEVICE, m_};                                                       \
     }                                                                                    \
   } while (0)
 
 [[noreturn]] void fail(afc_handle* h, afc_status st, const std::string& msg) {
   if (h) h->last_error = msg;
-  throw Fail{st};
+  throw Fail{st, msg};
 }
 
 std::string g_create_error;  // errors of afc_create before a handle exists
@@ -111,8 +115,8 @@ void free_all(afc_handle* h) {
   };
   f(h->row_ptr); f(h->col); f(h->is_dir); f(h->uD); f(h->ml);
   f(h->mij); f(h->dp_fct); f(h->AL_fct);
-  f(h->cc); f(h->ccT); f(h->AL_mcl); f(h->dinv_mcl); f(h->A32_mcl);
-  f(h->A_cn); f(h->dinv_cn); f(h->A32_cn);
+  f(h->cc); f(h->ccT); f(h->AL_mcl); f(h->dinv_mcl);
+  f(h->A_cn); f(h->dinv_cn);
   f(h->sl_ptr); f(h->sl_dlt); f(h->sell_pos); f(h->S64_mcl); f(h->S32_mcl); f(h->S64_cn); f(h->S32_cn);
   for (auto*& p : h->w) f(p);
   h->w.clear();
@@ -370,6 +374,142 @@ void ensure_work(afc_handle* h) {
   }
 }
 
+// Host-side setup shared by afc_create and afc_batch_create: fetch, validate,
+// and build the AFC operators of eqs. (4)-(6).
+struct HostOps {
+  int N = 0;
+  int64_t nnz = 0;
+  std::vector<int> rp, col, diag, tpos;
+  std::vector<double> M, K, Kc, ml, uD;
+  std::vector<uint8_t> is_dir;
+  std::vector<double> dp, AL;              // FCT: d+ from K, A_low (Dirichlet rows identity)
+  std::vector<double> c, cT, ALc, dinv;    // MCL: convective c, c^T, A_low from it, 1/diag
+};
+
+void check_problem(const afc_problem* p) {
+  if (p->n <= 0 || p->nnz <= 0 || p->nnz >= (int64_t)std::numeric_limits<int>::max())
+    throw Fail{AFC_EINVAL, "need n > 0 and 0 < nnz < 2^31"};
+  if (p->mem_space != AFC_MEM_HOST && p->mem_space != AFC_MEM_DEVICE) throw Fail{AFC_EINVAL, "mem_space"};
+  if (!p->row_ptr || !p->col_idx || !p->M || !p->K || (p->n_dir > 0 && (!p->dir_idx || !p->dir_val)) ||
+      p->n_dir < 0)
+    throw Fail{AFC_EINVAL, "null array"};
+}
+
+void prepare_ops(afc_handle* h, const afc_problem* p, HostOps& o) {
+  check_problem(p);
+  const int N = p->n;
+  const int64_t nnz = p->nnz;
+  const int ms = p->mem_space;
+  o.N = N;
+  o.nnz = nnz;
+  std::vector<int>& rp = o.rp;
+  std::vector<int>& col = o.col;
+  std::vector<double>& M = o.M;
+  std::vector<double>& K = o.K;
+  std::vector<double>& Kc = o.Kc;
+  std::vector<double>& ml = o.ml;
+  o.rp = fetch(h, p->row_ptr, (size_t)N + 1, ms);
+  o.col = fetch(h, p->col_idx, (size_t)nnz, ms);
+  o.M = fetch(h, p->M, (size_t)nnz, ms);
+  o.K = fetch(h, p->K, (size_t)nnz, ms);
+  o.Kc = p->K_conv ? fetch(h, p->K_conv, (size_t)nnz, ms) : std::vector<double>();
+  o.ml = p->ML ? fetch(h, p->ML, (size_t)N, ms) : std::vector<double>();
+  const std::vector<int> didx = fetch(h, p->dir_idx, (size_t)p->n_dir, ms);
+  const std::vector<double> dval = fetch(h, p->dir_val, (size_t)p->n_dir, ms);
+
+  // --- pattern checks -------------------------------------------------------
+  if (rp[0] != 0 || rp[N] != nnz) fail(h, AFC_EINVAL, "row_ptr[0] must be 0 and row_ptr[N] = nnz");
+  std::vector<int>& diag = o.diag;
+  diag.assign(N, -1);
+  for (int i = 0; i < N; ++i) {
+    if (rp[i + 1] < rp[i]) fail(h, AFC_EINVAL, "row_ptr not monotone");
+    for (int k = rp[i]; k < rp[i + 1]; ++k) {
+      const int j = col[k];
+      if (j < 0 || j >= N) fail(h, AFC_EINVAL, "column index out of range");
+      if (k > rp[i] && col[k - 1] >= j) fail(h, AFC_EINVAL, "columns not strictly ascending in a row");
+      if (j == i) diag[i] = k;
+    }
+    if (diag[i] < 0) fail(h, AFC_EINVAL, "missing diagonal entry in row " + std::to_string(i));
+  }
+  std::vector<int>& tpos = o.tpos;
+  tpos.assign((size_t)nnz, 0);
+  for (int i = 0; i < N; ++i) {
+    for (int k = rp[i]; k < rp[i + 1]; ++k) {
+      const int j = col[k];
+      const int* b0 = col.data() + rp[j];
+      const int* b1 = col.data() + rp[j + 1];
+      const int* f = std::lower_bound(b0, b1, i);
+      if (f == b1 || *f != i) fail(h, AFC_EINVAL, "pattern is not structurally symmetric");
+      tpos[k] = (int)(f - col.data());
+    }
+  }
+  for (int64_t k = 0; k < nnz; ++k)
+    if (!std::isfinite(M[k]) || !std::isfinite(K[k]) || (!Kc.empty() && !std::isfinite(Kc[k])))
+      fail(h, AFC_ENAN, "non-finite matrix entry");
+  // lumped mass m_i = sum_j m_ij (eq. (5))
+  if (ml.empty()) {
+    ml.assign(N, 0.0);
+    for (int i = 0; i < N; ++i)
+      for (int k = rp[i]; k < rp[i + 1]; ++k) ml[i] += M[k];
+  }
+  for (int i = 0; i < N; ++i)
+    if (!(ml[i] > 0.0) || !std::isfinite(ml[i])) fail(h, AFC_EINVAL, "lumped mass must be positive");
+  std::vector<uint8_t>& is_dir = o.is_dir;
+  std::vector<double>& uD = o.uD;
+  is_dir.assign(N, 0);
+  uD.assign(N, 0.0);
+  for (int q = 0; q < p->n_dir; ++q) {
+    const int i = didx[q];
+    if (i < 0 || i >= N) fail(h, AFC_EINVAL, "Dirichlet index out of range");
+    if (is_dir[i]) fail(h, AFC_EINVAL, "duplicate Dirichlet index");
+    if (!std::isfinite(dval[q])) fail(h, AFC_ENAN, "non-finite Dirichlet value");
+    is_dir[i] = 1;
+    uD[i] = dval[q];
+  }
+
+  // --- AFC operators -----------------------------------------------------------
+  // a_ij = -k_ij (eq. (4)); d+_ij = max(a_ij, 0, a_ji) = -d_ij (eq. (5));
+  // A_low = A + D (eq. (6)) with Dirichlet rows replaced by identity rows.
+  auto build_low = [&](const std::vector<double>& a_src, std::vector<double>& dp, std::vector<double>& AL) {
+    dp.assign((size_t)nnz, 0.0);
+    AL.assign((size_t)nnz, 0.0);
+    for (int i = 0; i < N; ++i) {
+      double dsum = 0.0;
+      for (int k = rp[i]; k < rp[i + 1]; ++k) {
+        if (col[k] == i) continue;
+        dp[k] = std::max(std::max(a_src[k], 0.0), a_src[tpos[k]]);
+        dsum += dp[k];
+      }
+      for (int k = rp[i]; k < rp[i + 1]; ++k) {
+        const double aik = -K[k];
+        AL[k] = col[k] == i ? aik + dsum : aik - dp[k];
+        if (is_dir[i]) AL[k] = col[k] == i ? 1.0 : 0.0;
+      }
+    }
+  };
+  std::vector<double> a((size_t)nnz);
+  for (int64_t k = 0; k < nnz; ++k) a[k] = -K[k];
+  build_low(a, o.dp, o.AL);
+  // MCL: c = -K_conv (or a), c^T in CSR order, A_low from the convective D (Remark 1)
+  std::vector<double>& c = o.c;
+  c = a;
+  if (!Kc.empty())
+    for (int64_t k = 0; k < nnz; ++k) c[k] = -Kc[k];
+  std::vector<double>& cT = o.cT;
+  cT.assign((size_t)nnz, 0.0);
+  for (int64_t k = 0; k < nnz; ++k) cT[k] = c[tpos[k]];
+  std::vector<double> dpc;
+  build_low(c, dpc, o.ALc);
+  const std::vector<double>& ALc = o.ALc;
+  std::vector<double>& dinv = o.dinv;
+  dinv.assign(N, 0.0);
+  for (int i = 0; i < N; ++i) {
+    const double d = ALc[diag[i]];
+    if (!(d != 0.0) || !std::isfinite(d)) fail(h, AFC_EINVAL, "zero diagonal in the low-order operator");
+    dinv[i] = 1.0 / d;
+  }
+}
+
 afc_status guard(afc_handle* h, afc_stats* st, afc_status (*body)(afc_handle*, void*), void* ctx) {
   if (!h) return AFC_EINVAL;
   h->last_error.clear();
@@ -460,138 +600,37 @@ afc_status afc_create(const afc_problem* p, const afc_options* opt, afc_handle**
   if (opt) o = *opt;
   std::string why;
   if (check_options(o, why) != AFC_OK) return g_create_error = "invalid options: " + why, AFC_EINVAL;
-  if (p->n <= 0 || p->nnz <= 0 || p->nnz >= (int64_t)std::numeric_limits<int>::max())
-    return g_create_error = "need n > 0 and 0 < nnz < 2^31", AFC_EINVAL;
-  if (p->mem_space != AFC_MEM_HOST && p->mem_space != AFC_MEM_DEVICE)
-    return g_create_error = "mem_space", AFC_EINVAL;
-  if (!p->row_ptr || !p->col_idx || !p->M || !p->K || (p->n_dir > 0 && (!p->dir_idx || !p->dir_val)) ||
-      p->n_dir < 0)
-    return g_create_error = "null array", AFC_EINVAL;
 
   afc_handle* h = new afc_handle();
   try {
     h->opt = o;
     h->stream = static_cast<hipStream_t>(o.stream);
-    const int N = p->n;
-    const int64_t nnz = p->nnz;
-    h->N = N;
-    h->ldv = (N + 63) / 64 * 64;
-    h->nnz = nnz;
+    h->N = p->n;
+    h->ldv = (p->n + 63) / 64 * 64;
+    h->nnz = p->nnz;
     h->n_dir = p->n_dir;
-    h->G = pick_lanes(nnz, N, o.lanes_per_row);
-    const int ms = p->mem_space;
-    const std::vector<int> rp = fetch(h, p->row_ptr, (size_t)N + 1, ms);
-    const std::vector<int> col = fetch(h, p->col_idx, (size_t)nnz, ms);
-    const std::vector<double> M = fetch(h, p->M, (size_t)nnz, ms);
-    const std::vector<double> K = fetch(h, p->K, (size_t)nnz, ms);
-    const std::vector<double> Kc = p->K_conv ? fetch(h, p->K_conv, (size_t)nnz, ms) : std::vector<double>();
-    std::vector<double> ml = p->ML ? fetch(h, p->ML, (size_t)N, ms) : std::vector<double>();
-    const std::vector<int> didx = fetch(h, p->dir_idx, (size_t)p->n_dir, ms);
-    const std::vector<double> dval = fetch(h, p->dir_val, (size_t)p->n_dir, ms);
-
-    // --- pattern checks -------------------------------------------------------
-    if (rp[0] != 0 || rp[N] != nnz) fail(h, AFC_EINVAL, "row_ptr[0] must be 0 and row_ptr[N] = nnz");
-    std::vector<int> diag(N, -1);
-    for (int i = 0; i < N; ++i) {
-      if (rp[i + 1] < rp[i]) fail(h, AFC_EINVAL, "row_ptr not monotone");
-      for (int k = rp[i]; k < rp[i + 1]; ++k) {
-        const int j = col[k];
-        if (j < 0 || j >= N) fail(h, AFC_EINVAL, "column index out of range");
-        if (k > rp[i] && col[k - 1] >= j) fail(h, AFC_EINVAL, "columns not strictly ascending in a row");
-        if (j == i) diag[i] = k;
-      }
-      if (diag[i] < 0) fail(h, AFC_EINVAL, "missing diagonal entry in row " + std::to_string(i));
-    }
-    std::vector<int> tpos((size_t)nnz);
-    for (int i = 0; i < N; ++i) {
-      for (int k = rp[i]; k < rp[i + 1]; ++k) {
-        const int j = col[k];
-        const int* b0 = col.data() + rp[j];
-        const int* b1 = col.data() + rp[j + 1];
-        const int* f = std::lower_bound(b0, b1, i);
-        if (f == b1 || *f != i) fail(h, AFC_EINVAL, "pattern is not structurally symmetric");
-        tpos[k] = (int)(f - col.data());
-      }
-    }
-    for (int64_t k = 0; k < nnz; ++k)
-      if (!std::isfinite(M[k]) || !std::isfinite(K[k]) || (!Kc.empty() && !std::isfinite(Kc[k])))
-        fail(h, AFC_ENAN, "non-finite matrix entry");
-    // lumped mass m_i = sum_j m_ij (eq. (5))
-    if (ml.empty()) {
-      ml.assign(N, 0.0);
-      for (int i = 0; i < N; ++i)
-        for (int k = rp[i]; k < rp[i + 1]; ++k) ml[i] += M[k];
-    }
-    for (int i = 0; i < N; ++i)
-      if (!(ml[i] > 0.0) || !std::isfinite(ml[i])) fail(h, AFC_EINVAL, "lumped mass must be positive");
-    std::vector<uint8_t> is_dir(N, 0);
-    std::vector<double> uD(N, 0.0);
-    for (int q = 0; q < p->n_dir; ++q) {
-      const int i = didx[q];
-      if (i < 0 || i >= N) fail(h, AFC_EINVAL, "Dirichlet index out of range");
-      if (is_dir[i]) fail(h, AFC_EINVAL, "duplicate Dirichlet index");
-      if (!std::isfinite(dval[q])) fail(h, AFC_ENAN, "non-finite Dirichlet value");
-      is_dir[i] = 1;
-      uD[i] = dval[q];
-    }
-
-    // --- AFC operators -----------------------------------------------------------
-    // a_ij = -k_ij (eq. (4)); d+_ij = max(a_ij, 0, a_ji) = -d_ij (eq. (5));
-    // A_low = A + D (eq. (6)) with Dirichlet rows replaced by identity rows.
-    auto build_low = [&](const std::vector<double>& a_src, std::vector<double>& dp, std::vector<double>& AL) {
-      dp.assign((size_t)nnz, 0.0);
-      AL.assign((size_t)nnz, 0.0);
-      for (int i = 0; i < N; ++i) {
-        double dsum = 0.0;
-        for (int k = rp[i]; k < rp[i + 1]; ++k) {
-          if (col[k] == i) continue;
-          dp[k] = std::max(std::max(a_src[k], 0.0), a_src[tpos[k]]);
-          dsum += dp[k];
-        }
-        for (int k = rp[i]; k < rp[i + 1]; ++k) {
-          const double aik = -K[k];
-          AL[k] = col[k] == i ? aik + dsum : aik - dp[k];
-          if (is_dir[i]) AL[k] = col[k] == i ? 1.0 : 0.0;
-        }
-      }
-    };
-    std::vector<double> a((size_t)nnz);
-    for (int64_t k = 0; k < nnz; ++k) a[k] = -K[k];
-    std::vector<double> dp, AL;
-    build_low(a, dp, AL);
+    h->G = pick_lanes(p->nnz, p->n, o.lanes_per_row);
+    HostOps ops;
+    prepare_ops(h, p, ops);
+    const int N = ops.N;
+    const int64_t nnz = ops.nnz;
+    const std::vector<int>& rp = ops.rp;
+    const std::vector<int>& col = ops.col;
     HIP_OK(hipGetDevice(&h->device));
-    h->row_ptr = upload(h, rp);
-    h->col = upload(h, col);
-    h->is_dir = upload(h, is_dir);
-    h->uD = upload(h, uD);
-    h->ml = upload(h, ml);
-    h->mij = upload(h, M);
-    h->dp_fct = upload(h, dp);
-    h->AL_fct = upload(h, AL);
-    // MCL: c = -K_conv (or a), c^T in CSR order, A_low from the convective D (Remark 1)
-    std::vector<double> c(a);
-    if (!Kc.empty())
-      for (int64_t k = 0; k < nnz; ++k) c[k] = -Kc[k];
-    std::vector<double> cT((size_t)nnz);
-    for (int64_t k = 0; k < nnz; ++k) cT[k] = c[tpos[k]];
-    std::vector<double> dpc, ALc;
-    build_low(c, dpc, ALc);
-    std::vector<double> dinv(N);
-    for (int i = 0; i < N; ++i) {
-      const double d = ALc[diag[i]];
-      if (!(d != 0.0) || !std::isfinite(d)) fail(h, AFC_EINVAL, "zero diagonal in the low-order operator");
-      dinv[i] = 1.0 / d;
-    }
-    std::vector<float> A32((size_t)nnz);
-    for (int64_t k = 0; k < nnz; ++k) A32[k] = (float)(ALc[k] * dinv[col[k]]);
-    h->cc = upload(h, c);
-    h->ccT = upload(h, cT);
-    h->AL_mcl = upload(h, ALc);
-    h->dinv_mcl = upload(h, dinv);
-    h->A32_mcl = upload(h, A32);
+    h->row_ptr = upload(h, ops.rp);
+    h->col = upload(h, ops.col);
+    h->is_dir = upload(h, ops.is_dir);
+    h->uD = upload(h, ops.uD);
+    h->ml = upload(h, ops.ml);
+    h->mij = upload(h, ops.M);
+    h->dp_fct = upload(h, ops.dp);
+    h->AL_fct = upload(h, ops.AL);
+    h->cc = upload(h, ops.c);
+    h->ccT = upload(h, ops.cT);
+    h->AL_mcl = upload(h, ops.ALc);
+    h->dinv_mcl = upload(h, ops.dinv);
     // CN system storage (values built per dt on the device)
     h->A_cn = dalloc<double>(h, (size_t)nnz);
-    h->A32_cn = dalloc<float>(h, (size_t)nnz);
     h->dinv_cn = dalloc<double>(h, (size_t)N);
     // SELL-64 layout of the Krylov matrices: slices of 64 rows padded to the
     // slice's longest row, column deltas j - i (16-bit when they fit)
@@ -653,7 +692,7 @@ afc_status afc_create(const afc_problem* p, const afc_options* opt, afc_handle**
     std::memset(h->host_status, 0, sizeof(KState));
     HIP_OK(hipDeviceSynchronize());
   } catch (const Fail& f) {
-    g_create_error = h->last_error;
+    g_create_error = f.msg;
     free_all(h);
     delete h;
     return f.st;
@@ -836,6 +875,205 @@ afc_status afc_solve_stationary(afc_handle* h, double* u, const double* F, int32
         return fixed_point(h, a.u, S, eval, a.st);
       },
       &a);
+}
+
+
+// ---------------------------------------------------------------------------
+// batched CN-FCT
+// ---------------------------------------------------------------------------
+
+static std::string g_batch_error;
+
+afc_status afc_batch_create(int32_t count, const afc_problem* probs, const afc_options* opt, afc_batch** out) {
+  g_batch_error.clear();
+  if (out) *out = nullptr;
+  if (count <= 0 || !probs || !out) return g_batch_error = "need count > 0, probs and out", AFC_EINVAL;
+  afc_options o;
+  afc_default_options(&o);
+  if (opt) o = *opt;
+  std::string why;
+  if (check_options(o, why) != AFC_OK) return g_batch_error = "invalid options: " + why, AFC_EINVAL;
+  if (o.krylov != AFC_KRYLOV_BICGSTAB || o.precision != AFC_PREC_FP64)
+    return g_batch_error = "the batched launch runs BiCGStab in FP64", AFC_EINVAL;
+  afc_batch* b = new afc_batch();
+  afc_handle* h = nullptr;  // HIP_OK / fail record messages only in the thrown Fail
+  try {
+    b->count = count;
+    b->opt = o;
+    b->stream = static_cast<hipStream_t>(o.stream);
+    b->bopt = afc::BatchOpts{o.alpha_mode, o.fp_tol_mode, o.fp_maxit, o.lin_maxit, o.dynamic_damping,
+                             o.fp_tol, o.lin_atol, o.lin_rtol, o.prelimit, o.omega};
+    std::vector<int> slp;
+    std::vector<int16_t> dlt;
+    std::vector<double> mij, dp, AL, ml, uD;
+    std::vector<uint8_t> is_dir;
+    b->host_insts.resize(count);
+    int64_t node_off = 0, slot_off = 0, sl_off = 0, nnz_tot = 0;
+    for (int q = 0; q < count; ++q) {
+      HostOps ops;
+      try {
+        prepare_ops(h, &probs[q], ops);
+      } catch (const Fail& f) {
+        throw Fail{f.st, "instance " + std::to_string(q) + ": " + f.msg};
+      }
+      const int N = ops.N;
+      const int nsl = (N + 63) / 64;
+      afc::BInst& in = b->host_insts[q];
+      in.N = N;
+      in.nnz = (int)ops.nnz;
+      in.nsl = nsl;
+      in.node_off = node_off;
+      in.slot_off = slot_off;
+      in.sl_off = sl_off;
+      in.dt = 0.0;
+      // SELL-64 with the diagonal in slot 0 of every row
+      std::vector<int> lp(nsl + 1, 0);
+      for (int sl = 0; sl < nsl; ++sl) {
+        int L = 0;
+        for (int i = sl * 64; i < std::min(N, sl * 64 + 64); ++i) L = std::max(L, ops.rp[i + 1] - ops.rp[i]);
+        lp[sl + 1] = lp[sl] + 64 * L;
+      }
+      const size_t slots = (size_t)lp[nsl];
+      const size_t s0 = dlt.size();
+      dlt.resize(s0 + slots, 0);
+      mij.resize(s0 + slots, 0.0);
+      dp.resize(s0 + slots, 0.0);
+      AL.resize(s0 + slots, 0.0);
+      for (int i = 0; i < N; ++i) {
+        const int sl = i / 64, lane = i % 64;
+        int p = 1;
+        for (int k = ops.rp[i]; k < ops.rp[i + 1]; ++k) {
+          const int j = ops.col[k];
+          const int pos = (j == i) ? 0 : p++;
+          const size_t slot = s0 + (size_t)lp[sl] + 64 * (size_t)pos + lane;
+          if (std::abs(j - i) > 32767) throw Fail{AFC_EINVAL, "batched instance bandwidth exceeds 16-bit deltas"};
+          dlt[slot] = (int16_t)(j - i);
+          mij[slot] = ops.M[k];
+          dp[slot] = ops.dp[k];
+          AL[slot] = ops.AL[k];
+        }
+      }
+      slp.insert(slp.end(), lp.begin(), lp.end());
+      ml.insert(ml.end(), ops.ml.begin(), ops.ml.end());
+      uD.insert(uD.end(), ops.uD.begin(), ops.uD.end());
+      is_dir.insert(is_dir.end(), ops.is_dir.begin(), ops.is_dir.end());
+      node_off += N;
+      slot_off += (int64_t)slots;
+      sl_off += nsl + 1;
+      nnz_tot += ops.nnz;
+      if (slot_off >= (int64_t)std::numeric_limits<int>::max()) throw Fail{AFC_EINVAL, "batch too large"};
+    }
+    b->total_slots = slot_off;
+    b->total_nodes = node_off;
+    b->total_nnz = nnz_tot;
+    // workgroups take the largest instances first
+    b->host_order.resize(count);
+    std::iota(b->host_order.begin(), b->host_order.end(), 0);
+    std::stable_sort(b->host_order.begin(), b->host_order.end(),
+                     [&](int a, int c) { return b->host_insts[a].nnz > b->host_insts[c].nnz; });
+    HIP_OK(hipGetDevice(&b->device));
+    b->slp = upload(h, slp);
+    b->dlt = upload(h, dlt);
+    b->mij = upload(h, mij);
+    b->dp = upload(h, dp);
+    b->AL = upload(h, AL);
+    b->ml = upload(h, ml);
+    b->uD = upload(h, uD);
+    b->is_dir = upload(h, is_dir);
+    b->Acn = dalloc<double>(h, (size_t)slot_off);
+    b->dinv = dalloc<double>(h, (size_t)node_off);
+    b->work = dalloc<double>(h, (size_t)afc::batch_work_vectors() * (size_t)node_off);
+    b->insts = upload(h, b->host_insts);
+    b->order = upload(h, b->host_order);
+    b->queue = dalloc<int>(h, 1);
+    b->stats_d = dalloc<afc::BStat>(h, (size_t)count);
+    b->dev = afc::BatchDev{b->slp, b->dlt, b->mij, b->dp, b->AL, b->ml, b->uD, b->is_dir, b->Acn, b->dinv, b->work,
+                           node_off};
+    HIP_OK(hipDeviceSynchronize());
+  } catch (const Fail& f) {
+    g_batch_error = f.msg;
+    afc_batch_destroy(b);
+    return f.st;
+  } catch (...) {
+    g_batch_error = "host allocation failed";
+    afc_batch_destroy(b);
+    return AFC_ENOMEM;
+  }
+  *out = b;
+  return AFC_OK;
+}
+
+afc_status afc_batch_offsets(const afc_batch* b, int64_t* offsets) {
+  if (!b || !offsets) return AFC_EINVAL;
+  for (int q = 0; q < b->count; ++q) offsets[q] = b->host_insts[q].node_off;
+  offsets[b->count] = b->total_nodes;
+  return AFC_OK;
+}
+
+static int severity(int s) { return s < 0 ? 100 - s : s; }
+
+afc_status afc_batch_step_cn(afc_batch* b, double* u, const double* F, const double* dt, int32_t steps,
+                             afc_stats* stats) {
+  if (!b) return AFC_EINVAL;
+  b->last_error.clear();
+  if (!u || !F || !dt || steps < 0) {
+    b->last_error = "afc_batch_step_cn: need device u, F, host dt and steps >= 0";
+    return AFC_EINVAL;
+  }
+  for (int q = 0; q < b->count; ++q)
+    if (!(dt[q] > 0) || !std::isfinite(dt[q])) {
+      b->last_error = "dt must be positive for every instance";
+      return AFC_EINVAL;
+    }
+  afc_handle* h = nullptr;
+  try {
+    HIP_OK(hipSetDevice(b->device));
+    for (int q = 0; q < b->count; ++q) b->host_insts[q].dt = dt[q];
+    HIP_OK(hipMemcpyAsync(b->insts, b->host_insts.data(), sizeof(afc::BInst) * b->count, hipMemcpyHostToDevice,
+                          b->stream));
+    HIP_OK(hipMemsetAsync(b->queue, 0, sizeof(int), b->stream));
+    int cus = 0;
+    HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device));
+    const int grid = std::max(1, std::min(b->count, 2 * cus));
+    afc::batch_launch(b, u, F, steps, grid);
+    HIP_OK(hipGetLastError());
+    std::vector<afc::BStat> hs(b->count);
+    HIP_OK(hipMemcpyAsync(hs.data(), b->stats_d, sizeof(afc::BStat) * b->count, hipMemcpyDeviceToHost, b->stream));
+    HIP_OK(hipStreamSynchronize(b->stream));
+    int worst = AFC_OK;
+    for (int q = 0; q < b->count; ++q) {
+      if (severity(hs[q].status) > severity(worst)) worst = hs[q].status;
+      if (stats) {
+        std::memset(&stats[q], 0, sizeof(afc_stats));
+        stats[q].status = hs[q].status;
+        stats[q].fp_iters = hs[q].fp_iters;
+        stats[q].krylov_iters = hs[q].krylov_iters;
+        stats[q].res0 = hs[q].res0;
+        stats[q].res = hs[q].res;
+        stats[q].lin_res = hs[q].lin_res;
+      }
+    }
+    if (worst < 0) b->last_error = std::string("an instance failed: ") + afc_status_str(worst);
+    return (afc_status)worst;
+  } catch (const Fail& f) {
+    b->last_error = f.msg;
+    return f.st;
+  }
+}
+
+const char* afc_batch_last_error(const afc_batch* b) { return b ? b->last_error.c_str() : g_batch_error.c_str(); }
+
+void afc_batch_destroy(afc_batch* b) {
+  if (!b) return;
+  (void)hipSetDevice(b->device);
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  auto f = [](auto*& p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+  };
+  f(b->slp); f(b->dlt); f(b->mij); f(b->dp); f(b->AL); f(b->ml); f(b->uD); f(b->is_dir);
+  f(b->Acn); f(b->dinv); f(b->work); f(b->insts); f(b->order); f(b->queue); f(b->stats_d);
+  delete b;
 }
 
 }  // extern "C"

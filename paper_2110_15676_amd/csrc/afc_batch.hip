@@ -1,0 +1,475 @@
+// Batched Crank-Nicolson FCT: many independent CDR instances advanced by one
+// persistent launch (Sec. 2.1.1 scheme, Sec. 2.1.3 limiter, Sec. 4 fixed-point
+// iteration with BiCGStab-Jacobi).
+//
+// All instances live in one packed device layout (SELL-64 entry order, the
+// diagonal first in every row).  Each workgroup of NT
+// threads repeatedly takes the next instance from an atomic queue (instances
+// ordered by decreasing nonzero count) and runs every time step of it: the
+// CN matrix for its dt, the low-order predictor, the limiter passes, the
+// nonlinear residual and the BiCGStab solves.  Phases are separated by
+// workgroup barriers and all reductions are LDS sums in a fixed order, so an
+// instance's result does not depend on which workgroup ran it or on what else
+// is in the batch.  The queue ends the loop of every workgroup.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "afc_batch_internal.h"
+#include "afc_device.h"
+
+namespace afc {
+namespace {
+
+constexpr int kBatchThreads = 1024;
+
+enum BatchWork { BW_UOLD = 0, BW_UT, BW_G, BW_QP, BW_QM, BW_RP, BW_RM, BW_B, BW_R, BW_X, BW_RHAT, BW_P, BW_V, BW_S,
+                 BW_T, BW_COUNT };
+
+// Sum of NV values over the workgroup; every thread receives the totals.
+template <int NT, int NV>
+__device__ void wg_sum(double (&v)[NV]) {
+  __shared__ double sh[NV][NT / 64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    const double s = wave_sum(v[q]);
+    if (lane == 0) sh[q][wv] = s;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) t += sh[q][w];
+    v[q] = t;
+  }
+  __syncthreads();
+}
+
+struct InstView {
+  int N, nsl;
+  const int* slp;
+  const int16_t* dlt;
+  const double *mij, *dp, *AL, *ml, *uD;
+  const uint8_t* isd;
+  double *Acn, *dinv;
+  double* w[BW_COUNT];
+  double* u;
+  const double* F;
+};
+
+// Row loops run in SELL order: wave w takes slices w, w + NT/64, ...; lane l
+// owns row 64 s + l and walks its slots p = 0..L-1 (p = 0 is the diagonal;
+// padding slots point at the row itself with zero values).
+#define AFC_SELL_ROWS(I, NT)                                              \
+  for (int s_ = (int)(threadIdx.x >> 6); s_ < (I).nsl; s_ += (NT) / 64)   \
+    if (const int i = s_ * 64 + (int)(threadIdx.x & 63); i < (I).N)
+
+struct RowSpan {
+  int base, L;
+};
+__device__ __forceinline__ RowSpan row_span(const InstView& I, int i) {
+  const int s = i >> 6;
+  const int b = I.slp[s];
+  return {b + (i & 63), (I.slp[s + 1] - b) >> 6};
+}
+
+// y_i = sum_j A_ij dinv_j x_j ; returns this thread's share of sum_i z_i y_i
+template <int NT>
+__device__ double wg_spmv_prec(const InstView& I, const double* A, const double* x, double* y, const double* z) {
+  double acc = 0.0;
+  AFC_SELL_ROWS(I, NT) {
+    const RowSpan rs = row_span(I, i);
+    double sacc = 0.0;
+#pragma unroll 4
+    for (int p = 0; p < rs.L; ++p) {
+      const int k = rs.base + 64 * p;
+      const int j = i + I.dlt[k];
+      sacc += A[k] * (I.dinv[j] * x[j]);
+    }
+    y[i] = sacc;
+    acc += z[i] * sacc;
+  }
+  return acc;
+}
+
+// r = b - A x over the instance, returns this thread's share of ||r||^2
+template <int NT>
+__device__ double wg_residual(const InstView& I, const double* A, const double* b, const double* x, double* r) {
+  double acc = 0.0;
+  AFC_SELL_ROWS(I, NT) {
+    const RowSpan rs = row_span(I, i);
+    double sacc = 0.0;
+#pragma unroll 4
+    for (int p = 0; p < rs.L; ++p) {
+      const int k = rs.base + 64 * p;
+      sacc += A[k] * x[i + I.dlt[k]];
+    }
+    const double ri = b[i] - sacc;
+    r[i] = ri;
+    acc += ri * ri;
+  }
+  return acc;
+}
+
+// BiCGStab (van der Vorst, right Jacobi) on A_cn x = b inside one workgroup.
+// r holds b - A x on entry (squared norm rr).  Returns the iterations done;
+// *status is 0, AFC_ENOCONV, AFC_EBREAKDOWN or AFC_ENAN; *res the final true
+// residual norm.
+template <int NT>
+__device__ int wg_bicgstab(const InstView& I, const double* b, double* x, double rr, double tol, int maxit,
+                           int* status, double* res) {
+  double* r = I.w[BW_R];
+  double* rhat = I.w[BW_RHAT];
+  double* p = I.w[BW_P];
+  double* v = I.w[BW_V];
+  double* s = I.w[BW_S];
+  double* t = I.w[BW_T];
+  const double* A = I.Acn;
+  const int N = I.N;
+  int it = 0, restarts = 0;
+  *status = 0;
+  while (true) {
+    for (int i = threadIdx.x; i < N; i += NT) {
+      rhat[i] = r[i];
+      p[i] = r[i];
+      v[i] = 0.0;
+    }
+    __syncthreads();
+    double rho = rr, alpha = 1.0, omega = 1.0;
+    double cur = sqrt(rr);
+    bool breakdown = false, converged = !(cur > tol);
+    if (!isfinite(cur)) {
+      *status = AFC_ENAN;
+      *res = cur;
+      return it;
+    }
+    while (!converged && it < maxit) {
+      double q1[1] = {wg_spmv_prec<NT>(I, A, p, v, rhat)};
+      wg_sum<NT, 1>(q1);
+      if (q1[0] == 0.0 || !isfinite(q1[0])) {
+        breakdown = true;
+        break;
+      }
+      alpha = rho / q1[0];
+      double q2[1] = {0.0};
+      for (int i = threadIdx.x; i < N; i += NT) {
+        const double si = r[i] - alpha * v[i];
+        s[i] = si;
+        q2[0] += si * si;
+      }
+      wg_sum<NT, 1>(q2);
+      ++it;
+      if (sqrt(q2[0]) <= tol) {
+        for (int i = threadIdx.x; i < N; i += NT) {
+          x[i] += alpha * (I.dinv[i] * p[i]);
+          r[i] = s[i];
+        }
+        __syncthreads();
+        converged = true;
+        break;
+      }
+      double q3[2] = {0.0, 0.0};
+      AFC_SELL_ROWS(I, NT) {
+        const RowSpan rs = row_span(I, i);
+        double a = 0.0;
+#pragma unroll 4
+        for (int pp = 0; pp < rs.L; ++pp) {
+          const int k = rs.base + 64 * pp;
+          const int j = i + I.dlt[k];
+          a += A[k] * (I.dinv[j] * s[j]);
+        }
+        t[i] = a;
+        q3[0] += a * s[i];
+        q3[1] += a * a;
+      }
+      wg_sum<NT, 2>(q3);
+      omega = q3[1] != 0.0 ? q3[0] / q3[1] : 0.0;
+      double q4[2] = {0.0, 0.0};
+      for (int i = threadIdx.x; i < N; i += NT) {
+        const double di = I.dinv[i];
+        x[i] += alpha * (di * p[i]) + omega * (di * s[i]);
+        const double ri = s[i] - omega * t[i];
+        r[i] = ri;
+        q4[0] += rhat[i] * ri;
+        q4[1] += ri * ri;
+      }
+      wg_sum<NT, 2>(q4);
+      cur = sqrt(q4[1]);
+      if (!isfinite(cur)) {
+        *status = AFC_ENAN;
+        *res = cur;
+        return it;
+      }
+      if (cur <= tol) {
+        converged = true;
+        break;
+      }
+      if (q4[0] == 0.0 || omega == 0.0) {
+        breakdown = true;
+        break;
+      }
+      const double beta = (q4[0] / rho) * (alpha / omega);
+      rho = q4[0];
+      for (int i = threadIdx.x; i < N; i += NT) p[i] = r[i] + beta * (p[i] - omega * v[i]);
+      __syncthreads();
+    }
+    // confirm on the true residual
+    double q5[1] = {wg_residual<NT>(I, A, b, x, r)};
+    wg_sum<NT, 1>(q5);
+    *res = sqrt(q5[0]);
+    if (!isfinite(*res)) {
+      *status = AFC_ENAN;
+      return it;
+    }
+    if (*res <= tol) return it;
+    if (breakdown && ++restarts > 1) {
+      *status = AFC_EBREAKDOWN;
+      return it;
+    }
+    if (it >= maxit) {
+      *status = AFC_ENOCONV;
+      return it;
+    }
+    rr = q5[0];
+  }
+}
+
+template <int NT>
+__device__ void run_instance(const BInst& in, const BatchDev& D, const BatchOpts& o, int steps, double* ug,
+                             const double* Fg, BStat* stat) {
+  InstView I;
+  I.N = in.N;
+  I.nsl = in.nsl;
+  I.slp = D.slp + in.sl_off;
+  I.dlt = D.dlt + in.slot_off;
+  I.mij = D.mij + in.slot_off;
+  I.dp = D.dp + in.slot_off;
+  I.AL = D.AL + in.slot_off;
+  I.Acn = D.Acn + in.slot_off;
+  I.ml = D.ml + in.node_off;
+  I.uD = D.uD + in.node_off;
+  I.isd = D.is_dir + in.node_off;
+  I.dinv = D.dinv + in.node_off;
+  for (int q = 0; q < BW_COUNT; ++q) I.w[q] = D.work + (size_t)q * D.total_nodes + in.node_off;
+  I.u = ug + in.node_off;
+  I.F = Fg + in.node_off;
+  const int N = in.N;
+  const double dt = in.dt, inv_dt = 1.0 / dt;
+  double* u = I.u;
+  double* uo = I.w[BW_UOLD];
+  double* ut = I.w[BW_UT];
+  double* g = I.w[BW_G];
+  double* Qp = I.w[BW_QP];
+  double* Qm = I.w[BW_QM];
+  double* Rp = I.w[BW_RP];
+  double* Rm = I.w[BW_RM];
+  double* b = I.w[BW_B];
+  double* r = I.w[BW_R];
+
+  // CN matrix M_L/dt + A_low/2 with Dirichlet identity rows, and its inverse diagonal
+  AFC_SELL_ROWS(I, NT) {
+    const RowSpan rs = row_span(I, i);
+    const bool dir = I.isd[i];
+    for (int p = 0; p < rs.L; ++p) {
+      const int k = rs.base + 64 * p;
+      double v;
+      if (dir)
+        v = (p == 0) ? 1.0 : 0.0;
+      else
+        v = 0.5 * I.AL[k] + ((p == 0) ? I.ml[i] * inv_dt : 0.0);
+      I.Acn[k] = v;
+      if (p == 0) I.dinv[i] = 1.0 / v;
+    }
+  }
+  __syncthreads();
+
+  int fp_total = 0, status = 0;
+  long long kry_total = 0;
+  double res0 = 0.0, res_last = 0.0, lin_res = 0.0;
+  for (int step = 0; step < steps && status >= 0; ++step) {
+    // predictor of eq. (14) and the right-hand side of eq. (11)
+    AFC_SELL_ROWS(I, NT) {
+      const double ui = u[i];
+      uo[i] = ui;
+      if (I.isd[i]) {
+        ut[i] = g[i] = I.uD[i];
+        continue;
+      }
+      const RowSpan rs = row_span(I, i);
+      double y = 0.0;
+#pragma unroll 4
+      for (int p = 0; p < rs.L; ++p) {
+        const int k = rs.base + 64 * p;
+        y += I.AL[k] * u[i + I.dlt[k]];
+      }
+      const double mi = I.ml[i];
+      ut[i] = ui - 0.5 * dt * (y - I.F[i]) / mi;
+      // (F^{n-1} + F^n) / 2 with the batch's time-independent load
+      g[i] = mi * inv_dt * ui - 0.5 * y + 0.5 * (I.F[i] + I.F[i]);
+    }
+    __syncthreads();
+    // Q+- from the predictor (Sec. 2.1.3 step 2)
+    AFC_SELL_ROWS(I, NT) {
+      const RowSpan rs = row_span(I, i);
+      const double uti = ut[i];
+      double qp = 0.0, qm = 0.0;
+#pragma unroll 4
+      for (int p = 1; p < rs.L; ++p) {
+        const double du = ut[i + I.dlt[rs.base + 64 * p]] - uti;
+        qp = fmax(qp, du);
+        qm = fmin(qm, du);
+      }
+      Qp[i] = qp;
+      Qm[i] = qm;
+    }
+    __syncthreads();
+    // Dirichlet values into u (after every predictor read of u)
+    AFC_SELL_ROWS(I, NT) {
+      if (I.isd[i]) u[i] = I.uD[i];
+    }
+    __syncthreads();
+    double R0 = 0.0, R_prev = 0.0, omega = o.omega;
+    bool have_prev = false;
+    int nu = 0;
+    while (true) {
+      // P+-, R+- of the prelimited CN fluxes (eqs. (12), (13))
+      AFC_SELL_ROWS(I, NT) {
+        if (I.isd[i]) {
+          Rp[i] = Rm[i] = 1.0;
+          continue;
+        }
+        const RowSpan rs = row_span(I, i);
+        const double dui = u[i] - uo[i], sui = u[i] + uo[i];
+        double pp = 0.0, pm = 0.0;
+#pragma unroll 4
+        for (int p = 1; p < rs.L; ++p) {
+          const int k = rs.base + 64 * p;
+          const int j = i + I.dlt[k];
+          const double rf = cn_flux(I.mij[k], -I.dp[k], inv_dt, dui, u[j] - uo[j], sui, u[j] + uo[j], o.prelimit);
+          pp += fmax(rf, 0.0);
+          pm += fmin(rf, 0.0);
+        }
+        Rp[i] = zalesak_R(I.ml[i], Qp[i], pp, dt);
+        Rm[i] = zalesak_R(I.ml[i], Qm[i], pm, dt);
+      }
+      __syncthreads();
+      // b = g + F*, r = b - A_cn u ; R^2 (free rows), ||b||^2, ||r||^2
+      double red[3] = {0.0, 0.0, 0.0};
+      AFC_SELL_ROWS(I, NT) {
+        if (I.isd[i]) {
+          const double bi = I.uD[i], ri = I.uD[i] - u[i];
+          b[i] = bi;
+          r[i] = ri;
+          red[1] += bi * bi;
+          red[2] += ri * ri;
+          continue;
+        }
+        const RowSpan rs = row_span(I, i);
+        const double ui = u[i];
+        const double dui = ui - uo[i], sui = ui + uo[i], rpi = Rp[i], rmi = Rm[i];
+        double fs = 0.0, au = I.Acn[rs.base] * ui;
+#pragma unroll 4
+        for (int p = 1; p < rs.L; ++p) {
+          const int k = rs.base + 64 * p;
+          const int j = i + I.dlt[k];
+          const double uj = u[j];
+          au += I.Acn[k] * uj;
+          if (o.alpha_mode == AFC_ALPHA_ZERO) continue;
+          const double rf = cn_flux(I.mij[k], -I.dp[k], inv_dt, dui, uj - uo[j], sui, uj + uo[j], o.prelimit);
+          double a = 1.0;
+          if (o.alpha_mode == AFC_ALPHA_LIMITED) a = rf > 0.0 ? fmin(rpi, Rm[j]) : fmin(rmi, Rp[j]);
+          fs += a * rf;
+        }
+        const double bi = g[i] + fs, ri = bi - au;
+        b[i] = bi;
+        r[i] = ri;
+        red[0] += ri * ri;
+        red[1] += bi * bi;
+        red[2] += ri * ri;
+      }
+      wg_sum<NT, 3>(red);
+      const double R = sqrt(red[0]), bn = sqrt(red[1]);
+      if (!isfinite(R) || !isfinite(bn)) {
+        status = AFC_ENAN;
+        break;
+      }
+      if (nu == 0) R0 = R;
+      if (step == 0 && nu == 0) res0 = R;
+      res_last = R;
+      const bool conv = (o.fp_tol_mode == AFC_TOL_ABS_SQRTN) ? (R < sqrt((double)N) * o.fp_tol) : (R <= o.fp_tol * R0);
+      if (R == 0.0 || conv) break;
+      if (nu >= o.fp_maxit) {
+        status = status > 0 ? status : AFC_WMAXIT;
+        break;
+      }
+      if (o.dynamic_damping && have_prev) omega = (R > R_prev) ? fmax(omega * 0.5, 1.0 / 64.0) : fmin(1.0, omega * 1.25);
+      const bool relax = omega != 1.0;
+      double* x = u;
+      if (relax) {
+        x = I.w[BW_X];
+        for (int i = threadIdx.x; i < N; i += NT) x[i] = u[i];
+        __syncthreads();
+      }
+      const double tol = fmax(o.lin_atol, o.lin_rtol * bn);
+      int lst = 0;
+      kry_total += wg_bicgstab<NT>(I, b, x, red[2], tol, o.lin_maxit, &lst, &lin_res);
+      if (lst == AFC_ENAN || lst == AFC_EBREAKDOWN) {
+        status = lst;
+        break;
+      }
+      if (relax) {
+        for (int i = threadIdx.x; i < N; i += NT) u[i] += omega * (x[i] - u[i]);
+      }
+      __syncthreads();
+      R_prev = R;
+      have_prev = true;
+      ++nu;
+    }
+    fp_total += nu;
+  }
+  if (threadIdx.x == 0) {
+    stat->status = status;
+    stat->fp_iters = fp_total;
+    stat->krylov_iters = kry_total;
+    stat->res0 = res0;
+    stat->res = res_last;
+    stat->lin_res = lin_res;
+  }
+  __syncthreads();
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_batch_cn(const BInst* __restrict__ insts, const int* __restrict__ order,
+                                                 int count, int* queue, int steps, BatchDev D, BatchOpts o,
+                                                 double* u, const double* F, BStat* stats) {
+  __shared__ int slot;
+  while (true) {
+    if (threadIdx.x == 0) slot = atomicAdd(queue, 1);
+    __syncthreads();
+    const int q = slot;
+    __syncthreads();
+    if (q >= count) break;
+    const int id = order[q];
+    run_instance<NT>(insts[id], D, o, steps, u, F, stats + id);
+  }
+}
+
+}  // namespace
+
+void batch_launch(afc_batch_s* b, double* u, const double* F, int steps, int grid) {
+  k_batch_cn<kBatchThreads><<<grid, kBatchThreads, 0, b->stream>>>(b->insts, b->order, b->count, b->queue, steps,
+                                                                   b->dev, b->bopt, u, F, b->stats_d);
+}
+
+int batch_work_vectors() { return BW_COUNT; }
+
+}  // namespace afc

@@ -74,7 +74,6 @@ struct afc_handle_s {
   double* ccT = nullptr;
   double* AL_mcl = nullptr;
   double* dinv_mcl = nullptr;
-  float* A32_mcl = nullptr;  // A_low D^{-1} in FP32
 
   // SELL-64 layout of the Krylov system matrices (one 64-row slice per wave,
   // entries column-major in a slice, column deltas j - i); padding entries
@@ -94,7 +93,6 @@ struct afc_handle_s {
   double cn_dt = 0.0;
   double* A_cn = nullptr;
   double* dinv_cn = nullptr;
-  float* A32_cn = nullptr;
 
   // work vectors (FP64, N each)
   std::vector<double*> w;

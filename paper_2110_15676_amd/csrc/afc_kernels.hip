@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <cmath>
 
+#include "afc_device.h"
 #include "afc_kernels.h"
 
 namespace afc {
@@ -36,37 +37,6 @@ __device__ __forceinline__ void tile_range(int ntiles, int& t0, int& t1) {
   const int per = (ntiles + nb - 1) / nb;
   t0 = min(b * per, ntiles);
   t1 = min(t0 + per, ntiles);
-}
-
-template <int G>
-__device__ __forceinline__ double gsum(double v) {
-#pragma unroll
-  for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
-  return v;
-}
-template <int G>
-__device__ __forceinline__ float gsumf(float v) {
-#pragma unroll
-  for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
-  return v;
-}
-template <int G>
-__device__ __forceinline__ double gmax(double v) {
-#pragma unroll
-  for (int o = G / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, G));
-  return v;
-}
-template <int G>
-__device__ __forceinline__ double gmin(double v) {
-#pragma unroll
-  for (int o = G / 2; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, G));
-  return v;
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
 }
 
 // Block totals of NV per-thread values for workgroups of NT threads.
@@ -217,21 +187,6 @@ __global__ __launch_bounds__(kBlock) void k_build_cn(int N, const int* __restric
   }
 }
 
-template <int G>
-__global__ __launch_bounds__(kBlock) void k_scale32(int N, const int* __restrict__ rp, const int* __restrict__ col,
-                                                    const double* __restrict__ A, const double* __restrict__ dinv,
-                                                    float* __restrict__ A32) {
-  constexpr int RPB = kBlock / G;
-  const int lane = threadIdx.x % G, sub = threadIdx.x / G;
-  int t0, t1;
-  tile_range((N + RPB - 1) / RPB, t0, t1);
-  for (int t = t0; t < t1; ++t) {
-    const int i = t * RPB + sub;
-    if (i >= N) continue;
-    const int e = rp[i + 1];
-    for (int k = rp[i] + lane; k < e; k += G) A32[k] = (float)(A[k] * dinv[col[k]]);
-  }
-}
 
 __global__ void k_cycle_start(KState* ks, int mode, int idx, double tol_abs, double tol_rel) {
   if (threadIdx.x == 0 && blockIdx.x == 0) cycle_start_dev(ks, mode, ks->red[idx], tol_abs, tol_rel);
@@ -982,10 +937,6 @@ __global__ __launch_bounds__(kBlock) void k_ssp_lowrate(int N, const int* __rest
   }
 }
 
-__device__ __forceinline__ double zalesak_R(double mi, double Q, double P, double dt) {
-  return P != 0.0 ? fmin(1.0, mi * Q / (dt * P)) : 1.0;
-}
-
 // P+-, Q+- (from ut) and R+- of the SSP fluxes r_ij = m_ij (udot_i - udot_j) + d_ij (u_j - u_i)
 template <int G>
 __global__ __launch_bounds__(kBlock) void k_ssp_limit_R(int N, const int* __restrict__ rp,
@@ -1139,20 +1090,6 @@ __global__ __launch_bounds__(kBlock) void k_zalesak_Q(int N, const int* __restri
       Qm[i] = qm;
     }
   }
-}
-
-__device__ __forceinline__ double minmod(double a, double b) {
-  if (a > 0.0 && b > 0.0) return fmin(a, b);
-  if (a < 0.0 && b < 0.0) return fmax(a, b);
-  return 0.0;
-}
-
-// CN flux r_ij of eq. (12), prelimited by eq. (13) (midpoint reading)
-__device__ __forceinline__ double cn_flux(double mij, double d, double inv_dt, double dui, double duj, double sui,
-                                          double suj, double L) {
-  double r = mij * inv_dt * (dui - duj) + 0.5 * d * (suj - sui);
-  if (L != 0.0) r = minmod(r, L * d * (0.5 * suj - 0.5 * sui));
-  return r;
 }
 
 template <int G>
@@ -1630,7 +1567,6 @@ void mcl_apply(H* h, const double* u, const double* umax, const double* umin, co
 void build_cn_matrix(H* h, double dt) {
   AFC_DISPATCH_G(h, k_build_cn, row_grid(h, false), h->N, h->row_ptr, h->col, h->AL_fct, h->ml, h->is_dir,
                  1.0 / dt, h->A_cn, h->dinv_cn);
-  AFC_DISPATCH_G(h, k_scale32, row_grid(h, false), h->N, h->row_ptr, h->col, h->A_cn, h->dinv_cn, h->A32_cn);
   to_sell64(h, h->A_cn, h->S64_cn);
   to_sell32_scaled(h, h->A_cn, h->dinv_cn, h->S32_cn);
 }
