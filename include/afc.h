@@ -219,6 +219,50 @@ const char *afc_batch_last_error(const afc_batch *b);
 /* Release the batch (NULL is ignored). */
 void afc_batch_destroy(afc_batch *b);
 
+/* ---- Request server (continuous batching) ---------------------------------
+ * Requests are copied at submission and queued; a scheduler admits them in
+ * arrival order whenever one of `slots` slots is free and the modelled device
+ * footprint (afc_footprint_bytes) of the running set stays within the HBM
+ * budget.  Each slot runs its request on its own HIP stream, so requests
+ * overlap on the device; a finished request frees its slot for the next one.
+ * A request's result is independent of the other requests. */
+enum { AFC_REQ_CN = 0, AFC_REQ_STATIONARY = 1 };
+
+typedef struct {
+  int32_t kind;          /* AFC_REQ_CN: `steps` CN-FCT steps of length dt;
+                            AFC_REQ_STATIONARY: MCL stationary solve        */
+  afc_problem problem;   /* host arrays (mem_space must be AFC_MEM_HOST)     */
+  const double *u0;      /* host [N]: CN initial state (required); stationary
+                            initial guess, NULL = the low-order solution     */
+  const double *F;       /* host [N] load vector, constant in time           */
+  double dt;             /* CN step length                                   */
+  int32_t steps;         /* CN steps                                         */
+  afc_options opt;       /* solver options; the stream field is ignored      */
+} afc_request;
+
+typedef struct afc_server_s afc_server;
+
+/* Modelled device bytes a request of this size keeps resident. */
+int64_t afc_footprint_bytes(int32_t n, int64_t nnz, int32_t kind, const afc_options *opt);
+
+/* Start a server with `slots` concurrent slots (1..64) on the current device. */
+afc_status afc_server_create(int32_t slots, int64_t hbm_budget_bytes, afc_server **out);
+
+/* Queue a request (inputs are copied; returns at once); *id identifies it. */
+afc_status afc_server_submit(afc_server *s, const afc_request *req, int64_t *id);
+
+/* Block until request id has finished.  u_out: NULL or host [N] for the
+ * result; stats: NULL or its statistics; times: NULL or 3 doubles (seconds
+ * queued, seconds in service, submit-to-completion latency).  Returns the
+ * request's status.  Each id can be waited for once. */
+afc_status afc_server_wait(afc_server *s, int64_t id, double *u_out, afc_stats *stats, double *times);
+
+/* Message of the last failed request or call (empty if none). */
+const char *afc_server_last_error(const afc_server *s);
+
+/* Stop the server: running requests finish, queued ones are dropped. */
+void afc_server_destroy(afc_server *s);
+
 /* Static description of a status code. */
 const char *afc_status_str(int32_t status);
 

@@ -47,6 +47,13 @@ class afc_options(ctypes.Structure):
     ]
 
 
+class afc_request(ctypes.Structure):
+    _fields_ = [
+        ("kind", c_int32), ("problem", afc_problem), ("u0", c_void_p), ("F", c_void_p), ("dt", c_double),
+        ("steps", c_int32), ("opt", afc_options),
+    ]
+
+
 class afc_stats(ctypes.Structure):
     _fields_ = [
         ("status", c_int32), ("fp_iters", c_int32), ("krylov_iters", c_int64), ("inner_iters", c_int64),
@@ -61,7 +68,11 @@ EXPORTS = [
     "afc_default_options", "afc_create", "afc_set_options", "afc_step_ssprk3", "afc_step_cn",
     "afc_solve_stationary", "afc_destroy", "afc_status_str", "afc_last_error", "afc_kernel_time",
     "afc_batch_create", "afc_batch_offsets", "afc_batch_step_cn", "afc_batch_last_error", "afc_batch_destroy",
+    "afc_footprint_bytes", "afc_server_create", "afc_server_submit", "afc_server_wait", "afc_server_last_error",
+    "afc_server_destroy",
 ]
+
+AFC_REQ_CN, AFC_REQ_STATIONARY = 0, 1
 
 AFC_KERNEL_SPMV32, AFC_KERNEL_SPMV64, AFC_KERNEL_DOTS, AFC_KERNEL_UPDATE = 0, 1, 2, 3
 AFC_KERNEL_RESIDUAL, AFC_KERNEL_MCL, AFC_KERNEL_FINISH, AFC_KERNEL_COUNT = 4, 5, 6, 7
@@ -101,6 +112,18 @@ def lib():
         L.afc_batch_last_error.restype = c_char_p
         L.afc_batch_destroy.argtypes = [c_void_p]
         L.afc_batch_destroy.restype = None
+        L.afc_footprint_bytes.argtypes = [c_int32, c_int64, c_int32, POINTER(afc_options)]
+        L.afc_footprint_bytes.restype = c_int64
+        L.afc_server_create.argtypes = [c_int32, c_int64, POINTER(c_void_p)]
+        L.afc_server_create.restype = c_int32
+        L.afc_server_submit.argtypes = [c_void_p, POINTER(afc_request), POINTER(c_int64)]
+        L.afc_server_submit.restype = c_int32
+        L.afc_server_wait.argtypes = [c_void_p, c_int64, c_void_p, POINTER(afc_stats), POINTER(c_double)]
+        L.afc_server_wait.restype = c_int32
+        L.afc_server_last_error.argtypes = [c_void_p]
+        L.afc_server_last_error.restype = c_char_p
+        L.afc_server_destroy.argtypes = [c_void_p]
+        L.afc_server_destroy.restype = None
         L.afc_destroy.argtypes = [c_void_p]
         L.afc_destroy.restype = None
         L.afc_status_str.argtypes = [c_int32]
@@ -303,3 +326,62 @@ def afc_batch_step_cn(b, u, F, dt, steps, raise_on_error=True):
 def afc_batch_destroy(b):
     if b is not None and b.value:
         lib().afc_batch_destroy(b)
+
+
+# ---------------------------------------------------------------------------
+# request server
+# ---------------------------------------------------------------------------
+
+
+def afc_footprint_bytes(n, nnz, kind, opts=None):
+    o = opts if opts is not None else afc_default_options()
+    return int(lib().afc_footprint_bytes(int(n), int(nnz), int(kind), ctypes.byref(o)))
+
+
+def afc_server_create(slots, hbm_budget_bytes):
+    s = c_void_p()
+    st = lib().afc_server_create(int(slots), int(hbm_budget_bytes), ctypes.byref(s))
+    if st != AFC_OK:
+        raise AFCError(st, "afc_server_create")
+    return s
+
+
+def afc_server_submit(s, kind, inst, opts, u0=None, dt=0.0, steps=0, conv=True):
+    """Queue one request built from an inputs.Instance; returns its id."""
+    keep = []
+    req = afc_request()
+    req.kind = int(kind)
+    req.problem = _host_problem(inst.row_ptr, inst.col, inst.M, inst.K, inst.dir_idx, inst.dir_val, keep)
+    if conv:
+        kc = np.ascontiguousarray(inst.K_conv, dtype=np.float64)
+        keep.append(kc)
+        req.problem.K_conv = kc.ctypes.data
+    F = np.ascontiguousarray(inst.F, dtype=np.float64)
+    keep.append(F)
+    req.F = F.ctypes.data
+    if u0 is not None:
+        u0 = np.ascontiguousarray(u0, dtype=np.float64)
+        keep.append(u0)
+        req.u0 = u0.ctypes.data
+    req.dt = float(dt)
+    req.steps = int(steps)
+    req.opt = opts
+    rid = c_int64()
+    st = lib().afc_server_submit(s, ctypes.byref(req), ctypes.byref(rid))
+    if st != AFC_OK:
+        raise AFCError(st, lib().afc_server_last_error(s).decode())
+    return rid.value
+
+
+def afc_server_wait(s, rid, n):
+    """(status, u (numpy), stats dict, (queued s, service s, latency s))."""
+    u = np.zeros(n)
+    stats = afc_stats()
+    times = (c_double * 3)()
+    st = lib().afc_server_wait(s, int(rid), u.ctypes.data, ctypes.byref(stats), times)
+    return st, u, stats.as_dict(), tuple(times)
+
+
+def afc_server_destroy(s):
+    if s is not None and s.value:
+        lib().afc_server_destroy(s)

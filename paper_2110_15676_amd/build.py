@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libafc.so")
-SOURCES = ["afc_kernels.hip", "afc_batch.hip", "afc_api.hip"]
+SOURCES = ["afc_kernels.hip", "afc_batch.hip", "afc_api.hip", "afc_server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
@@ -39,7 +39,7 @@ def build(verbose: bool = False) -> str:
     objs = []
     cmds = []
     for s in SOURCES:
-        o = os.path.join(objdir, s.replace(".hip", ".o"))
+        o = os.path.join(objdir, os.path.splitext(s)[0] + ".o")
         objs.append(o)
         cmds.append([HIPCC, *FLAGS, "-c", os.path.join(CSRC, s), "-o", o])
     with ThreadPoolExecutor(max_workers=len(cmds)) as ex:

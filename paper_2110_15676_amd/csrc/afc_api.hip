@@ -48,7 +48,7 @@ struct Fail {
   throw Fail{st, msg};
 }
 
-std::string g_create_error;  // errors of afc_create before a handle exists
+thread_local std::string g_create_error;  // errors of afc_create before a handle exists
 
 afc_status check_options(const afc_options& o, std::string& why) {
   if (o.alpha_mode < 0 || o.alpha_mode > 2) return why = "alpha_mode", AFC_EINVAL;
@@ -83,12 +83,14 @@ std::vector<T> fetch(afc_handle* h, const T* p, size_t n, int mem_space) {
   return v;
 }
 
+// Device copy of a host vector, ordered on stream st (the caller synchronizes
+// st before the host vector goes away).
 template <typename T>
-T* upload(afc_handle* h, const std::vector<T>& v) {
+T* upload(afc_handle* h, const std::vector<T>& v, hipStream_t st) {
   T* d = nullptr;
   const size_t bytes = std::max<size_t>(1, v.size()) * sizeof(T);
   if (hipMalloc(&d, bytes) != hipSuccess) fail(h, AFC_ENOMEM, "hipMalloc failed during afc_create");
-  if (!v.empty()) HIP_OK(hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  if (!v.empty()) HIP_OK(hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
   return d;
 }
 
@@ -617,18 +619,18 @@ afc_status afc_create(const afc_problem* p, const afc_options* opt, afc_handle**
     const std::vector<int>& rp = ops.rp;
     const std::vector<int>& col = ops.col;
     HIP_OK(hipGetDevice(&h->device));
-    h->row_ptr = upload(h, ops.rp);
-    h->col = upload(h, ops.col);
-    h->is_dir = upload(h, ops.is_dir);
-    h->uD = upload(h, ops.uD);
-    h->ml = upload(h, ops.ml);
-    h->mij = upload(h, ops.M);
-    h->dp_fct = upload(h, ops.dp);
-    h->AL_fct = upload(h, ops.AL);
-    h->cc = upload(h, ops.c);
-    h->ccT = upload(h, ops.cT);
-    h->AL_mcl = upload(h, ops.ALc);
-    h->dinv_mcl = upload(h, ops.dinv);
+    h->row_ptr = upload(h, ops.rp, h->stream);
+    h->col = upload(h, ops.col, h->stream);
+    h->is_dir = upload(h, ops.is_dir, h->stream);
+    h->uD = upload(h, ops.uD, h->stream);
+    h->ml = upload(h, ops.ml, h->stream);
+    h->mij = upload(h, ops.M, h->stream);
+    h->dp_fct = upload(h, ops.dp, h->stream);
+    h->AL_fct = upload(h, ops.AL, h->stream);
+    h->cc = upload(h, ops.c, h->stream);
+    h->ccT = upload(h, ops.cT, h->stream);
+    h->AL_mcl = upload(h, ops.ALc, h->stream);
+    h->dinv_mcl = upload(h, ops.dinv, h->stream);
     // CN system storage (values built per dt on the device)
     h->A_cn = dalloc<double>(h, (size_t)nnz);
     h->dinv_cn = dalloc<double>(h, (size_t)N);
@@ -666,31 +668,32 @@ afc_status afc_create(const afc_problem* p, const afc_options* opt, afc_handle**
             d32[q] = col[k] - i;
         }
       }
-      h->sl_ptr = upload(h, slp);
-      h->sell_pos = upload(h, pos);
+      h->sl_ptr = upload(h, slp, h->stream);
+      h->sell_pos = upload(h, pos, h->stream);
       if (h->dlt16)
-        h->sl_dlt = upload(h, d16);
+        h->sl_dlt = upload(h, d16, h->stream);
       else
-        h->sl_dlt = upload(h, d32);
+        h->sl_dlt = upload(h, d32, h->stream);
       h->S64_mcl = dalloc<double>(h, slots);
       h->S32_mcl = dalloc<float>(h, slots);
       h->S64_cn = dalloc<double>(h, slots);
       h->S32_cn = dalloc<float>(h, slots);
-      HIP_OK(hipMemset(h->S64_mcl, 0, slots * sizeof(double)));
-      HIP_OK(hipMemset(h->S32_mcl, 0, slots * sizeof(float)));
-      HIP_OK(hipMemset(h->S64_cn, 0, slots * sizeof(double)));
-      HIP_OK(hipMemset(h->S32_cn, 0, slots * sizeof(float)));
+      // zero the padding slots in stream order before the conversion kernels
+      HIP_OK(hipMemsetAsync(h->S64_mcl, 0, slots * sizeof(double), h->stream));
+      HIP_OK(hipMemsetAsync(h->S32_mcl, 0, slots * sizeof(float), h->stream));
+      HIP_OK(hipMemsetAsync(h->S64_cn, 0, slots * sizeof(double), h->stream));
+      HIP_OK(hipMemsetAsync(h->S32_cn, 0, slots * sizeof(float), h->stream));
       afc::to_sell64(h, h->AL_mcl, h->S64_mcl);
       afc::to_sell32_scaled(h, h->AL_mcl, h->dinv_mcl, h->S32_mcl);
     }
     // solver state
     h->partials = dalloc<double>(h, (size_t)kMaxRed * kRedBlocks);
     h->ks = dalloc<KState>(h, 1);
-    HIP_OK(hipMemset(h->ks, 0, sizeof(KState)));
+    HIP_OK(hipMemsetAsync(h->ks, 0, sizeof(KState), h->stream));
     if (hipHostMalloc((void**)&h->host_status, sizeof(KState), hipHostMallocDefault) != hipSuccess)
       fail(h, AFC_ENOMEM, "hipHostMalloc failed");
     std::memset(h->host_status, 0, sizeof(KState));
-    HIP_OK(hipDeviceSynchronize());
+    HIP_OK(hipStreamSynchronize(h->stream));
   } catch (const Fail& f) {
     g_create_error = f.msg;
     free_all(h);
@@ -882,7 +885,7 @@ afc_status afc_solve_stationary(afc_handle* h, double* u, const double* F, int32
 // batched CN-FCT
 // ---------------------------------------------------------------------------
 
-static std::string g_batch_error;
+static thread_local std::string g_batch_error;
 
 afc_status afc_batch_create(int32_t count, const afc_problem* probs, const afc_options* opt, afc_batch** out) {
   g_batch_error.clear();
@@ -972,24 +975,24 @@ afc_status afc_batch_create(int32_t count, const afc_problem* probs, const afc_o
     std::stable_sort(b->host_order.begin(), b->host_order.end(),
                      [&](int a, int c) { return b->host_insts[a].nnz > b->host_insts[c].nnz; });
     HIP_OK(hipGetDevice(&b->device));
-    b->slp = upload(h, slp);
-    b->dlt = upload(h, dlt);
-    b->mij = upload(h, mij);
-    b->dp = upload(h, dp);
-    b->AL = upload(h, AL);
-    b->ml = upload(h, ml);
-    b->uD = upload(h, uD);
-    b->is_dir = upload(h, is_dir);
+    b->slp = upload(h, slp, b->stream);
+    b->dlt = upload(h, dlt, b->stream);
+    b->mij = upload(h, mij, b->stream);
+    b->dp = upload(h, dp, b->stream);
+    b->AL = upload(h, AL, b->stream);
+    b->ml = upload(h, ml, b->stream);
+    b->uD = upload(h, uD, b->stream);
+    b->is_dir = upload(h, is_dir, b->stream);
     b->Acn = dalloc<double>(h, (size_t)slot_off);
     b->dinv = dalloc<double>(h, (size_t)node_off);
     b->work = dalloc<double>(h, (size_t)afc::batch_work_vectors() * (size_t)node_off);
-    b->insts = upload(h, b->host_insts);
-    b->order = upload(h, b->host_order);
+    b->insts = upload(h, b->host_insts, b->stream);
+    b->order = upload(h, b->host_order, b->stream);
     b->queue = dalloc<int>(h, 1);
     b->stats_d = dalloc<afc::BStat>(h, (size_t)count);
     b->dev = afc::BatchDev{b->slp, b->dlt, b->mij, b->dp, b->AL, b->ml, b->uD, b->is_dir, b->Acn, b->dinv, b->work,
                            node_off};
-    HIP_OK(hipDeviceSynchronize());
+    HIP_OK(hipStreamSynchronize(b->stream));
   } catch (const Fail& f) {
     g_batch_error = f.msg;
     afc_batch_destroy(b);

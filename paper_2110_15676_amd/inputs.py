@@ -482,3 +482,34 @@ def manufactured(elem: str, n: int, t: float | None = None):
     inst = build(elem, n, eps, affine_field(b), c, load=("fn", f), dirichlet="all",
                  dir_fn=u_star, u0_fn=u_star)
     return inst, u_star(inst.coords)
+
+
+def config5_requests(count: int, rate: float = 200.0, nmin: int = 16, nmax: int = 96):
+    """Seeded request stream of the serving workload: exponential inter-arrival
+    gaps of mean 1/rate seconds, kind ~ Bernoulli(1/2) between 'cn' (20 CN-FCT
+    steps, dt = 1e-3, u0 = 1 on [0.2,0.45]^3, inflow Dirichlet u = 0) and
+    'mcl' (stationary, f = 1 on [0.25,0.5]^3, u = 0 on the boundary), Q1 mesh
+    n = round(exp(U(ln nmin, ln nmax))), eps = 10^U(-8,-3), |b| = 1 in a
+    random direction, c ~ U(0, 1)."""
+    rng = np.random.default_rng((0, 5, 1))
+    gaps = rng.exponential(1.0 / rate, size=count)
+    t = np.cumsum(gaps) - gaps[0]
+    out = []
+    for k in range(count):
+        r = np.random.default_rng((0, 5, 2, k))
+        kind = "cn" if r.uniform() < 0.5 else "mcl"
+        n = int(round(math.exp(r.uniform(math.log(nmin), math.log(nmax)))))
+        eps = float(10.0 ** r.uniform(-8.0, -3.0))
+        g = r.standard_normal(3)
+        b = (g / np.linalg.norm(g)).tolist()
+        c = float(r.uniform(0.0, 1.0))
+        out.append(dict(arrival=float(t[k]), kind=kind, n=n, eps=eps, b=b, c=c))
+    return out
+
+
+def config5_instance(req) -> Instance:
+    if req["kind"] == "cn":
+        return build("Q1", req["n"], req["eps"], affine_field(req["b"]), req["c"], load=None, dirichlet="inflow",
+                     u0_fn=_box_indicator([0.2] * 3, [0.45] * 3), params=dict(cfg=5, dt=1e-3, steps=20))
+    return build("Q1", req["n"], req["eps"], affine_field(req["b"]), req["c"], load=("box", [0.25] * 3, [0.5] * 3),
+                 dirichlet="all", params=dict(cfg=5, fp_rtol=1e-8))

@@ -1,0 +1,94 @@
+"""Request server (continuous batching) through the C ABI: results are the
+same alone and in the mix, they match the direct entry points, and the HBM
+budget limits how many requests run at once."""
+import numpy as np
+import pytest
+
+from paper_2110_15676_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _afc():
+    from paper_2110_15676_amd import afc
+
+    return afc
+
+
+def _requests():
+    reqs = I.config5_requests(6, nmin=6, nmax=12)
+    return reqs, [I.config5_instance(r) for r in reqs]
+
+
+def _opts(afc, kind):
+    if kind == "cn":
+        return afc.afc_default_options(precision=afc.AFC_PREC_MIXED, fp_tol=1e-12, fp_maxit=50, lin_atol=1e-13)
+    return afc.afc_default_options(precision=afc.AFC_PREC_MIXED, fp_tol=1e-8, fp_tol_mode=afc.AFC_TOL_REL,
+                                   fp_maxit=500, lin_atol=0.0, lin_rtol=1e-10)
+
+
+def _run(afc, reqs, insts, slots, budget):
+    s = afc.afc_server_create(slots, budget)
+    try:
+        ids = []
+        for r, inst in zip(reqs, insts):
+            kind = afc.AFC_REQ_CN if r["kind"] == "cn" else afc.AFC_REQ_STATIONARY
+            ids.append(afc.afc_server_submit(s, kind, inst, _opts(afc, r["kind"]),
+                                             u0=inst.u0 if r["kind"] == "cn" else None, dt=1e-3, steps=3,
+                                             conv=r["kind"] == "mcl"))
+        out = [afc.afc_server_wait(s, rid, inst.N) for rid, inst in zip(ids, insts)]
+    finally:
+        afc.afc_server_destroy(s)
+    return out
+
+
+def test_server_alone_equals_mix_and_direct_calls():
+    afc = _afc()
+    reqs, insts = _requests()
+    print("server kinds", [r["kind"] for r in reqs], "n", [r["n"] for r in reqs], flush=True)
+    mix = _run(afc, reqs, insts, 3, 1 << 40)
+    for k in range(len(reqs)):
+        alone = _run(afc, reqs[k:k + 1], insts[k:k + 1], 1, 1 << 40)[0]
+        assert alone[0] >= 0 and mix[k][0] >= 0
+        assert np.array_equal(alone[1], mix[k][1]), k
+    # the same request through the direct entry points
+    for k in (0, 1):
+        r, inst = reqs[k], insts[k]
+        o = _opts(afc, r["kind"])
+        o.stream = torch.cuda.current_stream().cuda_stream
+        h = afc.afc_create_instance(inst, o, conv=r["kind"] == "mcl")
+        try:
+            F = torch.tensor(inst.F, device="cuda:0")
+            if r["kind"] == "cn":
+                u = torch.tensor(inst.u0, device="cuda:0")
+                for _ in range(3):
+                    afc.afc_step_cn(h, u, F, F, 1e-3)
+            else:
+                u = torch.zeros(inst.N, dtype=torch.float64, device="cuda:0")
+                afc.afc_solve_stationary(h, u, F, init_low_order=True)
+            assert np.array_equal(u.cpu().numpy(), mix[k][1]), k
+        finally:
+            afc.afc_destroy(h)
+
+
+def test_server_budget_serializes_requests():
+    afc = _afc()
+    reqs, insts = _requests()
+    reqs, insts = reqs[:4], insts[:4]
+    fps = [afc.afc_footprint_bytes(i.N, i.nnz, 0, _opts(afc, r["kind"])) for r, i in zip(reqs, insts)]
+    out = _run(afc, reqs, insts, 4, max(fps))  # room for one request at a time
+    spans = []
+    for st, _, _, (queued, service, latency) in out:
+        assert st >= 0
+        spans.append((queued, queued + service))
+    spans.sort()
+    for (a0, a1), (b0, b1) in zip(spans, spans[1:]):
+        assert b0 >= a1 - 1e-3  # never two requests in service together
