@@ -12,8 +12,10 @@ solution (computed before timing).  value = nodes x steps / seconds
 (DOF-iterations/s).
 
 Also reported: the plain-FP64 GMRES rate, Krylov iterations per step, the
-roofline of the dominant kernel (FP32 CSR SpMV) from HIP-event timings taken
-live in this process, and the FP64 CPU oracle timed on a bounded sample.
+roofline of the dominant kernel (FP32 SELL-64 SpMV) from HIP-event timings
+taken live in this process, batched CN-FCT solves/s (one persistent launch
+for 256 instances, against one-at-a-time solves), serving solves/s with
+p50/p99 latency, and the FP64 CPU oracle timed on a bounded sample.
 """
 import argparse
 import hashlib
@@ -101,6 +103,106 @@ def cpu_baseline(seconds):
     }
 
 
+def bench_batch(afc, torch, I, count, steps, nseq):
+    """256 seeded P1 CN-FCT instances x 20 steps in one persistent launch, and
+    the same instances one at a time through afc_step_cn (a subset, scaled)."""
+    import numpy as np
+
+    insts = [I.config4_instance(p) for p in I.config4_params(count)]
+    o = afc.afc_default_options(krylov=afc.AFC_KRYLOV_BICGSTAB, fp_tol=1e-12, fp_maxit=50, lin_atol=1e-12)
+    o.stream = torch.cuda.current_stream().cuda_stream
+    b = afc.afc_batch_create(insts, o)
+    try:
+        offs = afc.afc_batch_offsets(b, count)
+        u0 = np.zeros(offs[-1])
+        Fp = np.zeros(offs[-1])
+        for k, inst in enumerate(insts):
+            u0[offs[k]:offs[k + 1]] = inst.u0
+            Fp[offs[k]:offs[k + 1]] = inst.F
+        F = torch.tensor(Fp, device="cuda:0")
+        afc.afc_batch_step_cn(b, torch.tensor(u0, device="cuda:0"), F, [1e-3] * count, 1)  # warm-up
+        u = torch.tensor(u0, device="cuda:0")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, stats = afc.afc_batch_step_cn(b, u, F, [1e-3] * count, steps)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+    finally:
+        afc.afc_batch_destroy(b)
+    tseq = 0.0
+    for inst in insts[:nseq]:
+        h = afc.afc_create_instance(inst, o, conv=False)
+        try:
+            uk = torch.tensor(inst.u0, device="cuda:0")
+            Fk = torch.tensor(inst.F, device="cuda:0")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                afc.afc_step_cn(h, uk, Fk, Fk, 1e-3)
+            torch.cuda.synchronize()
+            tseq += time.perf_counter() - t0
+        finally:
+            afc.afc_destroy(h)
+    seq_rate = nseq / tseq
+    return {
+        "workload": "%d seeded P1 CN-FCT instances (n in 8..32, %d nodes), %d steps each, BiCGStab-Jacobi FP64"
+                    % (count, int(offs[-1]), steps),
+        "solves_per_s": count / tb, "seconds": tb, "status": st,
+        "fp_iters": int(sum(x["fp_iters"] for x in stats)), "krylov_iters": int(sum(x["krylov_iters"] for x in stats)),
+        "one_at_a_time_solves_per_s": seq_rate, "one_at_a_time_sample": nseq,
+        "speedup": (count / tb) / seq_rate,
+    }
+
+
+def bench_serve(afc, torch, I, count, slots):
+    """Poisson arrivals (200/s) of mixed CN-FCT / stationary-MCL Q1 requests."""
+    import threading
+
+    import numpy as np
+
+    reqs = I.config5_requests(count)
+    insts = [I.config5_instance(r) for r in reqs]
+
+    def opts(kind):
+        if kind == "cn":
+            return afc.afc_default_options(precision=afc.AFC_PREC_MIXED, fp_tol=1e-12, fp_maxit=50, lin_atol=1e-13)
+        return afc.afc_default_options(precision=afc.AFC_PREC_MIXED, fp_tol=1e-8, fp_tol_mode=afc.AFC_TOL_REL,
+                                       fp_maxit=300, lin_atol=0.0, lin_rtol=1e-10, lin_maxit=5000)
+
+    free, _ = torch.cuda.mem_get_info()
+    s = afc.afc_server_create(slots, int(0.8 * free))
+    ids = [None] * count
+    t0 = time.perf_counter()
+
+    def submitter():
+        for k, (r, inst) in enumerate(zip(reqs, insts)):
+            d = r["arrival"] - (time.perf_counter() - t0)
+            if d > 0:
+                time.sleep(d)
+            kind = afc.AFC_REQ_CN if r["kind"] == "cn" else afc.AFC_REQ_STATIONARY
+            ids[k] = afc.afc_server_submit(s, kind, inst, opts(r["kind"]), u0=inst.u0 if r["kind"] == "cn" else None,
+                                           dt=1e-3, steps=20, conv=r["kind"] == "mcl")
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    th.join()
+    res = []
+    for k, (rid, inst) in enumerate(zip(ids, insts)):
+        res.append(afc.afc_server_wait(s, rid, inst.N))
+        print("bench: request %d/%d done" % (k + 1, count), file=sys.stderr, flush=True)
+    wall = time.perf_counter() - t0
+    afc.afc_server_destroy(s)
+    lat = np.array([r[3][2] for r in res])
+    return {
+        "workload": "%d requests, Poisson 200/s, CN-FCT (20 steps) / stationary MCL (rel 1e-8, <= 300 its), "
+                    "Q1 n log-uniform 16..96, FP32-inner/FP64-outer" % count,
+        "slots": slots, "solves_per_s": count / wall, "seconds": wall,
+        "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
+        "statuses": sorted(set(int(r[0]) for r in res)),
+        "mean_nodes": float(np.mean([i.N for i in insts])),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,6 +212,10 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-slots", type=int, default=4)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
@@ -207,6 +313,15 @@ def main():
                 "krylov_per_step": s3["krylov_iters"] / max(1, s3["fp_iters"]), "steps": s3["fp_iters"]}
     afc.afc_destroy(h)
 
+    batch = None
+    if not args.no_batch:
+        print("bench: batched CN-FCT", file=sys.stderr, flush=True)
+        batch = bench_batch(afc, torch, I, 256, 20, 8)
+    serve = None
+    if not args.no_serve:
+        print("bench: serving", file=sys.stderr, flush=True)
+        serve = bench_serve(afc, torch, I, args.serve_requests, args.serve_slots)
+
     cpu = None
     if not args.no_cpu_baseline:
         print("bench: cpu baseline", file=sys.stderr, flush=True)
@@ -237,6 +352,8 @@ def main():
         "hbm_gbs_model": model_bytes / elapsed / 1e9,
         "nonlinear_residual": {"first": s["res0"], "last": s["res"]},
         "fp64": fp64,
+        "batch": batch,
+        "serving": serve,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
