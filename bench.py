@@ -22,6 +22,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -38,35 +39,22 @@ def kernel_source_hash():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def sell_layout(row_ptr, col):
-    """(slots, bytes per column delta) of the library's SELL-64 layout: 64-row
-    slices padded to their longest row, column deltas j - i in 16 bits when
-    every |j - i| fits."""
-    import numpy as np
-
-    N = row_ptr.shape[0] - 1
-    rl = np.diff(row_ptr).astype(np.int64)
-    nsl = (N + 63) // 64
-    pad = np.zeros(nsl * 64, dtype=np.int64)
-    pad[:N] = rl
-    slots = int(64 * pad.reshape(nsl, 64).max(axis=1).sum())
-    rows = np.repeat(np.arange(N), rl)
-    dbytes = 2 if int(np.abs(col.astype(np.int64) - rows).max()) <= 32767 else 4
-    return slots, dbytes
+def spmv32_bytes(N, info):
+    """Algorithmic bytes of one FP32 SELL-64 SpMV: the FP32 value of every
+    slot, the per-row column offsets of non-uniform slices, the shared offset
+    patterns, two 32-bit slice headers per slice, one read of x, one write of y."""
+    return (4 * info["slots"] + info["delta_bytes"] * info["lane_delta_slots"] + 4 * info["pattern_ints"]
+            + 4 * (info["slices"] + 1) + 4 * info["slices"] + 4 * N + 4 * N)
 
 
-def spmv32_bytes(N, slots, dbytes):
-    """Algorithmic bytes of one FP32 SELL-64 SpMV: FP32 values and column
-    deltas of every slot, slice offsets, one read of x and one write of y."""
-    return (4 + dbytes) * slots + 4 * ((N + 63) // 64 + 1) + 4 * N + 4 * N
-
-
-def step_model_bytes(N, nnz, slots, dbytes, krylov, sweeps, steps):
+def step_model_bytes(N, nnz, info, krylov, sweeps, steps):
     """Algorithmic HBM bytes of `steps` fixed-point iterations (model)."""
     L = krylov / max(sweeps, 1)  # mean FP32 GMRES cycle length
     kbar = (L - 1) / 2.0         # mean Arnoldi index inside a cycle
-    per_it = spmv32_bytes(N, slots, dbytes) + (kbar + 2) * 4 * N + (kbar + 3) * 4 * N
-    per_sweep = (8 + dbytes) * slots + 4 * (N // 64 + 1) + 24 * N + kbar * 4 * N + 16 * N + 12 * N
+    per_it = spmv32_bytes(N, info) + (kbar + 2) * 4 * N + (kbar + 3) * 4 * N
+    residual = (8 * info["slots"] + info["delta_bytes"] * info["lane_delta_slots"] + 4 * info["pattern_ints"]
+                + 8 * info["slices"] + 4 + 24 * N)
+    per_sweep = residual + kbar * 4 * N + 16 * N + 12 * N
     per_fp = (4 * nnz + 4 * (N + 1) + 24 * N) + (28 * nnz + 4 * (N + 1) + 57 * N)
     return krylov * per_it + sweeps * per_sweep + steps * per_fp
 
@@ -203,6 +191,93 @@ def bench_serve(afc, torch, I, count, slots):
     }
 
 
+def traffic_probe(n):
+    """Program for the two HBM counter passes (FETCH_SIZE, then WRITE_SIZE):
+    three plain 1 GiB device copies (the calibration of each counter) and then
+    one fixed-point iteration of the workload from its low-order solution."""
+    import torch
+
+    from paper_2110_15676_amd import afc
+    from paper_2110_15676_amd import inputs as I
+
+    src = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    print("traffic probe: 3 copies of %d bytes done" % (1 << 30), flush=True)
+    inst = I.config3(n)
+    o = afc.afc_default_options(precision=afc.AFC_PREC_MIXED, krylov=afc.AFC_KRYLOV_GMRES, restart=30,
+                                fp_tol=0.0, fp_tol_mode=afc.AFC_TOL_REL, fp_maxit=0, lin_atol=0.0,
+                                lin_rtol=1e-10, lin_maxit=100000)
+    o.stream = torch.cuda.current_stream().cuda_stream
+    h = afc.afc_create_instance(inst, o, conv=True)
+    u = torch.zeros(inst.N, dtype=torch.float64, device="cuda")
+    F = torch.tensor(inst.F, device="cuda")
+    afc.afc_solve_stationary(h, u, F, init_low_order=True)
+    o.fp_maxit = 1
+    afc.afc_set_options(h, o)
+    _, s = afc.afc_solve_stationary(h, u, F)
+    torch.cuda.synchronize()
+    afc.afc_destroy(h)
+    print("traffic probe: 1 fixed-point iteration, %d Krylov iterations" % s["krylov_iters"], flush=True)
+
+
+def traffic_summarize(fetch_csv, write_csv, n):
+    """Turn the two counter CSVs of `traffic_probe` into HBM bytes per launch.
+    Each counter is scaled by what it reads for the 1 GiB copies; launches that
+    moved under 1 MiB (no-op launches after a cycle converged) are left out.
+    Writes the SpMV figure, keyed by the kernel source hash, for the bench."""
+    import csv
+
+    from paper_2110_15676_amd import inputs as I
+
+    def load(path, counter):
+        out = {}
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] == counter:
+                    out.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return out
+
+    fe, wr = load(fetch_csv, "FETCH_SIZE"), load(write_csv, "WRITE_SIZE")
+
+    def series(d, name):
+        # demangled names: "void afc::(anonymous namespace)::k_sell_spmv32<short>(int, ...)"
+        return [v for k, vals in d.items() if re.search(r"(^|::)%s[<(]" % name, k) or k == name for v in vals]
+
+    gib_kib = float(1 << 20)
+    cf = [v for v in series(fe, "__amd_rocclr_copyBuffer") if v > 0.25 * gib_kib]
+    cw = [v for v in series(wr, "__amd_rocclr_copyBuffer") if v > 0.5 * gib_kib]
+    if len(cf) < 3 or len(cw) < 3:
+        raise SystemExit("traffic: the three 1 GiB calibration copies are missing from the counter files")
+    sf, sw = gib_kib / (sum(cf[:3]) / 3), gib_kib / (sum(cw[:3]) / 3)
+    table = {}
+    for name in ("k_sell_spmv32", "k_gmres_dots", "k_gmres_update", "k_sell_residual", "k_mcl_bounds", "k_mcl_apply"):
+        f = [v for v in series(fe, name) if v > 1024]
+        w = [v for v in series(wr, name) if v > 1024]
+        if f:
+            table[name] = {"launches": len(f), "fetch_bytes": 1024 * sf * sum(f) / len(f),
+                           "write_bytes": 1024 * sw * sum(w) / len(w) if w else 0.0}
+    inst = I.config3(n)
+    sp = table["k_sell_spmv32"]
+    rec = {"kernel": "k_sell_spmv32", "workload": "stationary MCL Q1 %d^3 (%d nodes, %d nnz)" % (n, inst.N, inst.nnz),
+           "nnz": inst.nnz, "bytes_per_launch": round(sp["fetch_bytes"] + sp["write_bytes"]),
+           "fetch_bytes": round(sp["fetch_bytes"]), "write_bytes": round(sp["write_bytes"]),
+           "launches_averaged": sp["launches"], "fetch_scale": sf, "write_scale": sw,
+           "kernel_source_sha": kernel_source_hash()}
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(rec, f, indent=1)
+        f.write("\n")
+    print("copy calibration: FETCH_SIZE %.1f KiB, WRITE_SIZE %.1f KiB per 1 GiB copy -> scales %.4f, %.4f"
+          % (sum(cf[:3]) / 3, sum(cw[:3]) / 3, sf, sw))
+    print("| kernel | launches | fetch MB | write MB |")
+    print("|---|---|---|---|")
+    for name, t in table.items():
+        print("| %s | %d | %.1f | %.1f |" % (name, t["launches"], t["fetch_bytes"] / 1e6, t["write_bytes"] / 1e6))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -216,10 +291,20 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="only run the program profiled by the FETCH_SIZE / WRITE_SIZE counter passes")
+    ap.add_argument("--traffic-summarize", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="turn the counter CSVs of --traffic-probe into the per-launch traffic file (no GPU)")
     args = ap.parse_args()
+    if args.traffic_summarize:
+        traffic_summarize(args.traffic_summarize[0], args.traffic_summarize[1], args.n)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
+    if args.traffic_probe:
+        traffic_probe(args.n)
+        return
 
     import numpy as np
     import torch
@@ -232,7 +317,6 @@ def main():
     print("bench: building Q1 %d^3 MCL instance" % args.n, file=sys.stderr, flush=True)
     inst = I.config3(args.n)
     N, nnz = inst.N, inst.nnz
-    slots, dbytes = sell_layout(inst.row_ptr, inst.col)
     stream = torch.cuda.current_stream().cuda_stream
 
     def opts(**kw):
@@ -243,6 +327,7 @@ def main():
         return o
 
     h = afc.afc_create_instance(inst, opts(fp_maxit=0), conv=True)
+    info = afc.afc_get_sell_info(h)
     u = torch.zeros(N, dtype=torch.float64, device=dev)
     F = torch.tensor(inst.F, device=dev)
     afc.afc_solve_stationary(h, u, F, init_low_order=True)  # low-order start, not timed
@@ -261,7 +346,7 @@ def main():
     assert s["fp_iters"] == args.steps, s
     value = N * args.steps / elapsed
     ms_per_step = 1e3 * elapsed / args.steps
-    model_bytes = step_model_bytes(N, nnz, slots, dbytes, s["krylov_iters"], s["refine_sweeps"], args.steps)
+    model_bytes = step_model_bytes(N, nnz, info, s["krylov_iters"], s["refine_sweeps"], args.steps)
     print("bench: %.1f ms/step, %d Krylov its" % (ms_per_step, s["krylov_iters"]), file=sys.stderr, flush=True)
 
     # --- the same steps again with per-kernel HIP events (roofline) ----------
@@ -279,7 +364,7 @@ def main():
         ("residual", afc.AFC_KERNEL_RESIDUAL), ("mcl", afc.AFC_KERNEL_MCL), ("finish", afc.AFC_KERNEL_FINISH))}
     # launches after convergence of a cycle are no-ops; divide by SpMVs performed
     spmv_avg_s = 1e-3 * spmv_ms / max(1, s2["krylov_iters"])
-    spmv_b = spmv32_bytes(N, slots, dbytes)
+    spmv_b = spmv32_bytes(N, info)
     achieved = spmv_b / spmv_avg_s / 1e9
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
@@ -289,7 +374,7 @@ def main():
             traffic = tr.get("bytes_per_launch")
     roofline = {
         "kernel": "k_sell_spmv32 (FP32 SELL-64 SpMV, GMRES inner)",
-        "sell_slots": slots, "delta_bytes": dbytes,
+        "sell": info,
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
         "bytes_per_launch": spmv_b, "avg_launch_us": round(spmv_avg_s * 1e6, 2),

@@ -117,13 +117,14 @@ typedef struct {
 
 /* Kernel classes timed when afc_options.profile is set. */
 enum {
-  AFC_KERNEL_SPMV32 = 0,    /* FP32 CSR SpMV of the mixed-precision GMRES      */
-  AFC_KERNEL_SPMV64 = 1,    /* FP64 CSR SpMV (Jacobi-scaled) of FP64 GMRES     */
+  AFC_KERNEL_SPMV32 = 0,    /* FP32 SELL-64 SpMV of the mixed-precision GMRES  */
+  AFC_KERNEL_SPMV64 = 1,    /* FP64 SELL-64 SpMV (Jacobi-scaled) of FP64 GMRES */
   AFC_KERNEL_DOTS = 2,      /* GMRES Gram-Schmidt projections                  */
   AFC_KERNEL_UPDATE = 3,    /* GMRES orthogonalization update + norm           */
   AFC_KERNEL_RESIDUAL = 4,  /* FP64 residual b - A x                           */
   AFC_KERNEL_MCL = 5,       /* MCL bounds + limited fluxes + residual          */
-  AFC_KERNEL_FINISH = 6,    /* reduction finish (scalar solver steps)          */
+  AFC_KERNEL_FINISH = 6,    /* reduction finishes (GMRES projections + Givens, */
+                            /* scalar solver steps)                            */
   AFC_KERNEL_COUNT = 7
 };
 
@@ -184,6 +185,41 @@ afc_status afc_solve_stationary(afc_handle *h, double *u, const double *F, int32
  * the counters after reading).  Only launches made while options.profile was
  * set are counted.  Returns EINVAL for an unknown kernel id. */
 afc_status afc_kernel_time(afc_handle *h, int32_t kernel, double *total_ms, int64_t *launches, int32_t reset);
+
+/* Storage of the SELL-64 copy of the Krylov system matrices (sizes only).
+ * Rows are taken in slices of 64 consecutive rows, each padded to its longest
+ * row; a slice whose rows all fit one shared list of column offsets j - i
+ * ("uniform") stores no per-row offsets.  Read to price the SpMV's memory
+ * traffic: per launch the FP32 SpMV reads 4 * slots value bytes,
+ * delta_bytes * lane_delta_slots offset bytes, 4 * pattern_ints pattern
+ * bytes and 8 * slices + 4 slice-header bytes, besides x and y. */
+typedef struct {
+  int64_t slices;            /* ceil(N / 64) */
+  int64_t slots;             /* value slots over all slices (64 x padded length) */
+  int64_t uniform_slices;    /* slices stored with a shared offset pattern */
+  int64_t lane_delta_slots;  /* per-row offsets stored for the other slices */
+  int64_t pattern_ints;      /* 32-bit entries of the shared pattern table */
+  int32_t delta_bytes;       /* bytes of one per-row offset: 2 or 4 */
+  int32_t reserved;
+} afc_sell_info;
+
+/* Fill *out for handle h.  Returns EINVAL if h or out is NULL. */
+afc_status afc_get_sell_info(const afc_handle *h, afc_sell_info *out);
+
+/* The same SELL-64 layout computed on the host for an n-row CSR pattern
+ * (row_ptr[n + 1], col[row_ptr[n]], 0-based, host memory); needs no GPU.
+ * Fills *info; each array pointer may be NULL (call once with NULLs to learn
+ * the sizes), else it must hold: slice_ptr info->slices + 1 slot offsets,
+ * slice_delta info->slices entries (>= 0: offset of the slice's per-row
+ * offsets in lane_deltas, slot p of row lane l at + 64 p + l; < 0: the slice
+ * is uniform and ~value is the offset of its pattern in pattern[]), pattern
+ * info->pattern_ints, pos row_ptr[n] (slot of each CSR entry; entry p of
+ * row lane l of slice s lies at slice_ptr[s] + 64 p + l), lane_deltas
+ * info->lane_delta_slots (widened to 32 bits).  Returns EINVAL for a
+ * malformed pattern or a layout beyond 2^31 slots. */
+afc_status afc_sell_layout(int32_t n, const int32_t *row_ptr, const int32_t *col, afc_sell_info *info,
+                           int32_t *slice_ptr, int32_t *slice_delta, int32_t *pattern, int32_t *pos,
+                           int32_t *lane_deltas);
 
 /* Release every device and host resource of h (NULL is ignored). */
 void afc_destroy(afc_handle *h);

@@ -69,7 +69,7 @@ EXPORTS = [
     "afc_solve_stationary", "afc_destroy", "afc_status_str", "afc_last_error", "afc_kernel_time",
     "afc_batch_create", "afc_batch_offsets", "afc_batch_step_cn", "afc_batch_last_error", "afc_batch_destroy",
     "afc_footprint_bytes", "afc_server_create", "afc_server_submit", "afc_server_wait", "afc_server_last_error",
-    "afc_server_destroy",
+    "afc_server_destroy", "afc_get_sell_info", "afc_sell_layout",
 ]
 
 AFC_REQ_CN, AFC_REQ_STATIONARY = 0, 1
@@ -101,6 +101,10 @@ def lib():
         L.afc_solve_stationary.restype = c_int32
         L.afc_kernel_time.argtypes = [c_void_p, c_int32, POINTER(c_double), POINTER(c_int64), c_int32]
         L.afc_kernel_time.restype = c_int32
+        L.afc_get_sell_info.argtypes = [c_void_p, POINTER(afc_sell_info)]
+        L.afc_get_sell_info.restype = c_int32
+        L.afc_sell_layout.argtypes = [c_int32, c_void_p, c_void_p, POINTER(afc_sell_info)] + [c_void_p] * 5
+        L.afc_sell_layout.restype = c_int32
         L.afc_batch_create.argtypes = [c_int32, POINTER(afc_problem), POINTER(afc_options), POINTER(c_void_p)]
         L.afc_batch_create.restype = c_int32
         L.afc_batch_offsets.argtypes = [c_void_p, POINTER(c_int64)]
@@ -132,6 +136,12 @@ def lib():
         L.afc_last_error.restype = c_char_p
         _lib = L
     return _lib
+
+
+class afc_sell_info(ctypes.Structure):
+    _fields_ = [("slices", c_int64), ("slots", c_int64), ("uniform_slices", c_int64),
+                ("lane_delta_slots", c_int64), ("pattern_ints", c_int64), ("delta_bytes", c_int32),
+                ("reserved", c_int32)]
 
 
 class AFCError(RuntimeError):
@@ -259,6 +269,38 @@ def afc_kernel_time(h, kernel, reset=False):
     if st != AFC_OK:
         raise AFCError(st, "afc_kernel_time")
     return ms.value, n.value
+
+
+def afc_get_sell_info(h):
+    """Sizes of the handle's SELL-64 matrix storage (dict)."""
+    info = afc_sell_info()
+    st = lib().afc_get_sell_info(h, ctypes.byref(info))
+    if st != AFC_OK:
+        raise AFCError(st, "afc_get_sell_info")
+    return {name: getattr(info, name) for name, _ in afc_sell_info._fields_ if name != "reserved"}
+
+
+def afc_sell_layout(row_ptr, col):
+    """Host SELL-64 layout of a CSR pattern (numpy int32 arrays): returns
+    (info dict, slice_ptr, slice_delta, pattern, pos, lane_deltas)."""
+    import numpy as np
+
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    cl = np.ascontiguousarray(col, dtype=np.int32)
+    n = rp.shape[0] - 1
+    info = afc_sell_info()
+    ptr = lambda a: a.ctypes.data_as(c_void_p)  # noqa: E731
+    st = lib().afc_sell_layout(n, ptr(rp), ptr(cl), ctypes.byref(info), None, None, None, None, None)
+    if st != AFC_OK:
+        raise AFCError(st, "afc_sell_layout")
+    out = [np.zeros(max(1, m), dtype=np.int32) for m in (info.slices + 1, info.slices, info.pattern_ints,
+                                                         rp[-1], info.lane_delta_slots)]
+    st = lib().afc_sell_layout(n, ptr(rp), ptr(cl), ctypes.byref(info), *[ptr(a) for a in out])
+    if st != AFC_OK:
+        raise AFCError(st, "afc_sell_layout")
+    sizes = (info.slices + 1, info.slices, info.pattern_ints, int(rp[-1]), info.lane_delta_slots)
+    d = {name: getattr(info, name) for name, _ in afc_sell_info._fields_ if name != "reserved"}
+    return (d, *[a[:m] for a, m in zip(out, sizes)])
 
 
 def afc_destroy(h):

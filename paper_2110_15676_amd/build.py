@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libafc.so")
-SOURCES = ["afc_kernels.hip", "afc_batch.hip", "afc_api.hip", "afc_server.cpp"]
+SOURCES = ["afc_kernels.hip", "afc_batch.hip", "afc_api.hip", "afc_server.cpp", "afc_layout.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -16,6 +16,7 @@
 
 #include "afc_batch_internal.h"
 #include "afc_kernels.h"
+#include "afc_layout.h"
 
 using afc::KState;
 using afc::kMaxRestart;
@@ -119,7 +120,7 @@ void free_all(afc_handle* h) {
   f(h->mij); f(h->dp_fct); f(h->AL_fct);
   f(h->cc); f(h->ccT); f(h->AL_mcl); f(h->dinv_mcl);
   f(h->A_cn); f(h->dinv_cn);
-  f(h->sl_ptr); f(h->sl_dlt); f(h->sell_pos); f(h->S64_mcl); f(h->S32_mcl); f(h->S64_cn); f(h->S32_cn);
+  f(h->sl_ptr); f(h->sl_dl); f(h->sl_pat); f(h->sl_dlt); f(h->sell_pos); f(h->S64_mcl); f(h->S32_mcl); f(h->S64_cn); f(h->S32_cn);
   for (auto*& p : h->w) f(p);
   h->w.clear();
   f(h->V64); f(h->V32);
@@ -201,11 +202,12 @@ SolveOut solve_gmres(afc_handle* h, const SysMat& S, const double* b, double* x,
   while (res > tol) {
     for (int k = 0; k < m; ++k) {
       if (mixed)
-        afc::gmres_spmv32(h, S.S32, k, m);
+        afc::gmres_spmv32(h, S.S32, k);
       else
-        afc::gmres_spmv64(h, S.S64, S.dinv, k, m);
-      afc::gmres_dots(h, mixed, k, m);
-      afc::gmres_update(h, mixed, k, m);
+        afc::gmres_spmv64(h, S.S64, S.dinv, k);
+      afc::gmres_dots(h, mixed, k);
+      afc::gmres_reduce(h, mixed, k, m);
+      afc::gmres_update(h, mixed, k);
     }
     afc::gmres_last_givens(h, mixed, m - 1, m);
     afc::gmres_solve(h, m);
@@ -634,46 +636,29 @@ afc_status afc_create(const afc_problem* p, const afc_options* opt, afc_handle**
     // CN system storage (values built per dt on the device)
     h->A_cn = dalloc<double>(h, (size_t)nnz);
     h->dinv_cn = dalloc<double>(h, (size_t)N);
-    // SELL-64 layout of the Krylov matrices: slices of 64 rows padded to the
-    // slice's longest row, column deltas j - i (16-bit when they fit)
+    // SELL-64 layout of the Krylov matrices
     {
-      const int nsl = (N + 63) / 64;
-      std::vector<int> slp(nsl + 1, 0);
-      int maxd = 0;
-      for (int sl = 0; sl < nsl; ++sl) {
-        int L = 0;
-        for (int i = sl * 64; i < std::min(N, sl * 64 + 64); ++i) {
-          L = std::max(L, rp[i + 1] - rp[i]);
-          for (int k = rp[i]; k < rp[i + 1]; ++k) maxd = std::max(maxd, std::abs(col[k] - i));
-        }
-        if ((int64_t)slp[sl] + 64LL * L >= (int64_t)std::numeric_limits<int>::max())
-          fail(h, AFC_EINVAL, "SELL layout exceeds 2^31 slots");
-        slp[sl + 1] = slp[sl] + 64 * L;
-      }
-      const size_t slots = (size_t)slp[nsl];
-      h->nslices = nsl;
+      afc::SellLayout L;
+      const std::string err = afc::build_sell_layout(N, rp.data(), col.data(), L);
+      if (!err.empty()) fail(h, AFC_EINVAL, err.c_str());
+      const size_t slots = (size_t)L.slp.back();
+      h->nslices = (int)L.dl.size();
       h->sell_slots = (int64_t)slots;
-      h->dlt16 = maxd <= 32767;
-      std::vector<int> pos((size_t)nnz);
-      std::vector<int16_t> d16(h->dlt16 ? slots : 0, 0);
-      std::vector<int32_t> d32(h->dlt16 ? 0 : slots, 0);
-      for (int i = 0; i < N; ++i) {
-        const int sl = i / 64, lane = i % 64;
-        for (int k = rp[i]; k < rp[i + 1]; ++k) {
-          const int q = slp[sl] + 64 * (k - rp[i]) + lane;
-          pos[k] = q;
-          if (h->dlt16)
-            d16[q] = (int16_t)(col[k] - i);
-          else
-            d32[q] = col[k] - i;
-        }
-      }
-      h->sl_ptr = upload(h, slp, h->stream);
-      h->sell_pos = upload(h, pos, h->stream);
+      h->sell_uniform = L.uniform;
+      h->sell_lane_deltas = (int64_t)(L.dlt16 ? L.d16.size() : L.d32.size());
+      h->sell_pat_ints = (int64_t)L.pat.size();
+      h->dlt16 = L.dlt16;
+      if (L.pat.empty()) L.pat.push_back(0);
+      if (L.d16.empty()) L.d16.push_back(0);
+      if (L.d32.empty()) L.d32.push_back(0);
+      h->sl_ptr = upload(h, L.slp, h->stream);
+      h->sl_dl = upload(h, L.dl, h->stream);
+      h->sl_pat = upload(h, L.pat, h->stream);
+      h->sell_pos = upload(h, L.pos, h->stream);
       if (h->dlt16)
-        h->sl_dlt = upload(h, d16, h->stream);
+        h->sl_dlt = upload(h, L.d16, h->stream);
       else
-        h->sl_dlt = upload(h, d32, h->stream);
+        h->sl_dlt = upload(h, L.d32, h->stream);
       h->S64_mcl = dalloc<double>(h, slots);
       h->S32_mcl = dalloc<float>(h, slots);
       h->S64_cn = dalloc<double>(h, slots);
@@ -720,6 +705,18 @@ afc_status afc_kernel_time(afc_handle* h, int32_t kernel, double* total_ms, int6
     h->prof_ms[kernel] = 0.0;
     h->prof_n[kernel] = 0;
   }
+  return AFC_OK;
+}
+
+afc_status afc_get_sell_info(const afc_handle* h, afc_sell_info* out) {
+  if (!h || !out) return AFC_EINVAL;
+  out->slices = h->nslices;
+  out->slots = h->sell_slots;
+  out->uniform_slices = h->sell_uniform;
+  out->lane_delta_slots = h->sell_lane_deltas;
+  out->pattern_ints = h->sell_pat_ints;
+  out->delta_bytes = h->dlt16 ? 2 : 4;
+  out->reserved = 0;
   return AFC_OK;
 }
 

@@ -39,6 +39,7 @@ struct KState {
   double g[kMaxRestart + 1];                  // rotated right-hand side
   double sc[kMaxRestart + 1];                 // basis scales: v_j = sc_j * V[j]
   double coef[kMaxRestart + 1];               // update coefficients y_j * sc_j
+  double proj[kMaxRestart + 1];               // running Arnoldi step: h_{q,k} sc_q
 };
 
 // bytes of KState copied back to the host: scalars + red[0..7]
@@ -77,10 +78,16 @@ struct afc_handle_s {
 
   // SELL-64 layout of the Krylov system matrices (one 64-row slice per wave,
   // entries column-major in a slice, column deltas j - i); padding entries
-  // have value 0 and delta 0.  sell_pos maps each CSR entry to its slot.
+  // have value 0 and an in-range delta.  sell_pos maps each CSR entry to its
+  // slot.
   int nslices = 0;
   int* sl_ptr = nullptr;      // [nslices + 1] slot offsets (multiples of 64)
-  void* sl_dlt = nullptr;     // int16 when every |j - i| <= 32767, else int32
+  int* sl_dl = nullptr;       // per slice: >= 0 offset of per-lane deltas, < 0 ~offset into sl_pat
+  int* sl_pat = nullptr;      // shared delta patterns of uniform slices
+  int64_t sell_uniform = 0;   // slices with one delta pattern
+  int64_t sell_lane_deltas = 0;  // per-lane deltas stored (other slices)
+  int64_t sell_pat_ints = 0;  // entries of sl_pat
+  void* sl_dlt = nullptr;     // per-lane deltas: int16 when every |j - i| <= 32767, else int32
   bool dlt16 = true;
   int* sell_pos = nullptr;    // [nnz]
   double* S64_mcl = nullptr;  // A_low (MCL) in SELL order
@@ -116,14 +123,6 @@ struct afc_handle_s {
 };
 
 namespace afc {
-// Brackets the launches of one kernel class with HIP events when profiling.
-struct ProfScope {
-  afc_handle_s* h;
-  int kid;
-  hipEvent_t b = nullptr;
-  ProfScope(afc_handle_s* h_, int kid_);
-  ~ProfScope();
-};
 void prof_collect(afc_handle_s* h);  // fold completed event pairs into the totals
 void prof_release(afc_handle_s* h);
 }  // namespace afc

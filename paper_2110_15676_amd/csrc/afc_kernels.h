@@ -30,12 +30,14 @@ void cycle_start(H* h, int mode, int red_idx, double tol_abs, double tol_rel);  
 void cast_v0(H* h, const double* r);
 
 // --- GMRES (right Jacobi), FP64 or FP32 Arnoldi --------------------------------
-// Arnoldi step k = spmv (finishes step k-1) + dots + update (finishes the
-// projections); the last step of a cycle is finished by gmres_last_givens.
-void gmres_spmv64(H* h, const double* A, const double* dinv, int k, int m);
-void gmres_spmv32(H* h, const float* A32, int k, int m);
-void gmres_dots(H* h, bool fp32, int k, int m);
-void gmres_update(H* h, bool fp32, int k, int m);
+// Arnoldi step k = spmv + dots + reduce (finalizes the projections and the
+// Givens rotation of step k-1) + update; the last step of a cycle is
+// finished by gmres_last_givens.
+void gmres_spmv64(H* h, const double* A, const double* dinv, int k);
+void gmres_spmv32(H* h, const float* A32, int k);
+void gmres_dots(H* h, bool fp32, int k);
+void gmres_reduce(H* h, bool fp32, int k, int m);
+void gmres_update(H* h, bool fp32, int k);
 void gmres_last_givens(H* h, bool fp32, int k, int m);
 void gmres_solve(H* h, int m);
 void gmres_xupdate(H* h, bool fp32, const double* dinv, double* x);

@@ -17,6 +17,8 @@
 #include <algorithm>
 #include <cmath>
 
+#include <hip/hip_ext.h>
+
 #include "afc_device.h"
 #include "afc_kernels.h"
 
@@ -37,27 +39,6 @@ __device__ __forceinline__ void tile_range(int ntiles, int& t0, int& t1) {
   const int per = (ntiles + nb - 1) / nb;
   t0 = min(b * per, ntiles);
   t1 = min(t0 + per, ntiles);
-}
-
-// Block totals of NV per-thread values for workgroups of NT threads.
-template <int NT, int NV>
-__device__ void block_partials_n(const double (&v)[NV], int nv, double* partials, int slot) {
-  __shared__ double sh[NV][NT / 64];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-  for (int q = 0; q < NV; ++q) {
-    if (q < nv) {
-      const double s = wave_sum(v[q]);
-      if (lane == 0) sh[q][wv] = s;
-    }
-  }
-  __syncthreads();
-  for (int q = threadIdx.x; q < nv; q += NT) {
-    double s = 0.0;
-#pragma unroll
-    for (int w = 0; w < NT / 64; ++w) s += sh[q][w];
-    partials[(size_t)q * kRedBlocks + slot] = s;
-  }
 }
 
 // Block totals of nv per-thread values into partials[q * kRedBlocks + slot].
@@ -81,27 +62,9 @@ __device__ void block_partials(const double (&v)[KMAX], int nv, double* partials
   }
 }
 
-// Partial rows used by the fused GMRES step: projection partials in rows
+// Partial rows of the GMRES step: projection partials in rows
 // 0..k, the squared norm of the new basis vector in the last row.
 constexpr int kNormRow = kMaxRed - 1;
-constexpr int kVecBlock = 1024;  // workgroup of the GMRES vector kernels (16 waves)
-
-// Every workgroup of the calling kernel sums the same partials in the same
-// fixed order (wave q takes rows q, q + NW, ...; lanes stride the slots), so
-// all workgroups obtain bitwise identical totals.  out is LDS.
-template <int NT>
-__device__ void sum_partial_rows(const double* __restrict__ partials, int row0, int nrows, int nb,
-                                 double* out) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int q = wv; q < nrows; q += NT / 64) {
-    double s = 0.0;
-    for (int b = lane; b < nb; b += 64) s += partials[(size_t)(row0 + q) * kRedBlocks + b];
-    s = wave_sum(s);
-    if (lane == 0) out[q] = s;
-  }
-  __syncthreads();
-}
-
 // Start of a Krylov cycle from the squared norm of its residual.
 __device__ void cycle_start_dev(KState* ks, int mode, double rr, double tol_abs, double tol_rel) {
   const double beta = sqrt(rr);
@@ -250,145 +213,124 @@ __device__ void givens_step(KState* ks, int k, int m, double hk1sq) {
   for (int q = threadIdx.x; q <= k + 1; q += blockDim.x) Hk[q] = col[q];
 }
 
-// ks->done read once per workgroup (workgroup 0 of the fused SpMV may set it
-// while other workgroups start), so the early return is workgroup-uniform.
-__device__ bool block_done(const KState* ks) {
-  __shared__ int d;
-  if (threadIdx.x == 0) d = __hip_atomic_load(&ks->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __syncthreads();
-  const bool r = d != 0;
-  __syncthreads();
-  return r;
-}
-
-// Finish of Arnoldi step k - 1 at the start of step k's projections: every
-// workgroup sums the norm partials of V[k] in the same order, workgroup 0
-// applies the Givens rotation of column k - 1 (which sets sc_k and may end the
-// cycle).  A cycle that converged at step k - 1 thus runs one redundant SpMV
-// and projection pass; later kernels see ks->done and return.
-__device__ void finish_prev_step(KState* ks, const double* __restrict__ partials, int nbu, int k, int m) {
-  if (k == 0) return;
-  __shared__ double nrm2[1];
-  sum_partial_rows<kVecBlock>(partials, kNormRow, 1, nbu, nrm2);
-  if (blockIdx.x == 0) givens_step(ks, k - 1, m, nrm2[0]);
-}
-
 // ---------------------------------------------------------------------------
-// SELL-64 SpMV: one wave per 64-row slice, one row per lane.  Entry p of
-// the slice's rows lies at slot base + 64 p + lane, so value and delta loads
-// are contiguous across the wave, and on a structured mesh the gathers
-// x[i + delta] of neighbouring lanes hit neighbouring addresses.  Rows are
-// accumulated in registers; no LDS and no shuffles.
+// SELL-64: one wave per 64-row slice, one row per lane.  Entry p of the
+// slice's rows lies at slot base + 64 p + lane, so value loads are contiguous
+// across the wave.  Column deltas j - i come in two forms:
+//   * uniform slice (sl_dl < 0): every row of the slice uses the same delta
+//     for slot p, held once in the shared pattern table at ~sl_dl; the slice
+//     index is wave-uniform, so those reads are scalar loads and a wave's
+//     gathers x[i + delta] cover 64 consecutive addresses;
+//   * other slices: one delta per slot (int16 or int32) at sl_dl + 64 p + lane.
+// Padding slots hold value 0 and an in-range delta.  Rows accumulate in
+// registers; no LDS and no shuffles.
 // ---------------------------------------------------------------------------
 
-template <typename TI>
-__global__ __launch_bounds__(kBlock) void k_sell_spmv32(int N, int nsl, const int* __restrict__ sl_ptr,
-                                                        const TI* __restrict__ dlt, const float* __restrict__ val,
-                                                        const float* __restrict__ x, KState* ks,
-                                                        const double* __restrict__ partials, int nbu, int k, int m,
-                                                        float* __restrict__ y) {
-  if (ks->done) return;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  int t0, t1;
-  tile_range((nsl + kBlock / 64 - 1) / (kBlock / 64), t0, t1);
-  for (int t = t0; t < t1; ++t) {
-    const int s = t * (kBlock / 64) + wv;
-    if (s >= nsl) continue;
-    const int i = s * 64 + lane;
-    if (i >= N) continue;
-    const int b = sl_ptr[s];
-    const int L = (sl_ptr[s + 1] - b) >> 6;
-    const TI* __restrict__ d = dlt + b + lane;
-    const float* __restrict__ v = val + b + lane;
-    float acc = 0.0f;
+struct SellView {
+  int N, nsl;
+  const int* __restrict__ sl_ptr;
+  const int* __restrict__ sl_dl;
+  const int* __restrict__ pat;
+};
+
+// slice handled by this wave in tile t (wave-uniform by construction)
+__device__ __forceinline__ int wave_slice(int t) {
+  return t * (kBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+}
+
+// sum_p val[p] * X(i + delta_p) over the row of lane i in slice s
+template <int U, typename TI, typename TA, typename XF>
+__device__ __forceinline__ TA sell_row(const SellView& S, const TI* __restrict__ dlt, const TA* __restrict__ val,
+                                       int s, int i, XF xf) {
+  const int b = S.sl_ptr[s];
+  const int L = (S.sl_ptr[s + 1] - b) >> 6;
+  const int doff = S.sl_dl[s];
+  const TA* __restrict__ v = val + b + (i & 63);
+  TA acc = TA(0);
+  if (doff < 0) {
+    const int* __restrict__ pp = S.pat + ~doff;
     int p = 0;
-    for (; p + 8 <= L; p += 8) {
-      int j[8];
-      float a[8];
+    for (; p + U <= L; p += U) {
+      TA a[U], xv[U];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < U; ++u) {
+        a[u] = v[64 * (p + u)];
+        xv[u] = xf(i + pp[p + u]);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) acc += a[u] * xv[u];
+    }
+    for (; p < L; ++p) acc += v[64 * p] * xf(i + pp[p]);
+  } else {
+    const TI* __restrict__ d = dlt + doff + (i & 63);
+    int p = 0;
+    for (; p + U <= L; p += U) {
+      int j[U];
+      TA a[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
         j[u] = i + d[64 * (p + u)];
         a[u] = v[64 * (p + u)];
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) acc += a[u] * x[j[u]];
+      for (int u = 0; u < U; ++u) acc += a[u] * xf(j[u]);
     }
-    for (; p < L; ++p) acc += v[64 * p] * x[i + d[64 * p]];
-    y[i] = acc;
+    for (; p < L; ++p) acc += v[64 * p] * xf(i + d[64 * p]);
+  }
+  return acc;
+}
+
+// FP32: y = A x (Jacobi-scaled FP32 matrix, unscaled basis vector)
+template <typename TI>
+__global__ __launch_bounds__(kBlock) void k_sell_spmv32(SellView S, const TI* __restrict__ dlt,
+                                                        const float* __restrict__ val, const float* __restrict__ x,
+                                                        const KState* __restrict__ ks, float* __restrict__ y) {
+  if (ks->done) return;
+  int t0, t1;
+  tile_range((S.nsl + kBlock / 64 - 1) / (kBlock / 64), t0, t1);
+  for (int t = t0; t < t1; ++t) {
+    const int s = wave_slice(t);
+    if (s >= S.nsl) continue;
+    const int i = s * 64 + (threadIdx.x & 63);
+    if (i >= S.N) continue;
+    y[i] = sell_row<8>(S, dlt, val, s, i, [&](int j) { return x[j]; });
   }
 }
 
-// FP64: y = mul * A (s .* x)
+// FP64: y = A (sc .* x)
 template <typename TI>
-__global__ __launch_bounds__(kBlock) void k_sell_spmv64(int N, int nsl, const int* __restrict__ sl_ptr,
-                                                        const TI* __restrict__ dlt, const double* __restrict__ val,
+__global__ __launch_bounds__(kBlock) void k_sell_spmv64(SellView S, const TI* __restrict__ dlt,
+                                                        const double* __restrict__ val,
                                                         const double* __restrict__ sc, const double* __restrict__ x,
-                                                        KState* ks, const double* __restrict__ partials, int nbu,
-                                                        int k, int m, double* __restrict__ y) {
+                                                        const KState* __restrict__ ks, double* __restrict__ y) {
   if (ks->done) return;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   int t0, t1;
-  tile_range((nsl + kBlock / 64 - 1) / (kBlock / 64), t0, t1);
+  tile_range((S.nsl + kBlock / 64 - 1) / (kBlock / 64), t0, t1);
   for (int t = t0; t < t1; ++t) {
-    const int s = t * (kBlock / 64) + wv;
-    if (s >= nsl) continue;
-    const int i = s * 64 + lane;
-    if (i >= N) continue;
-    const int b = sl_ptr[s];
-    const int L = (sl_ptr[s + 1] - b) >> 6;
-    const TI* __restrict__ d = dlt + b + lane;
-    const double* __restrict__ v = val + b + lane;
-    double acc = 0.0;
-    int p = 0;
-    for (; p + 4 <= L; p += 4) {
-      const int j0 = i + d[64 * p], j1 = i + d[64 * (p + 1)], j2 = i + d[64 * (p + 2)], j3 = i + d[64 * (p + 3)];
-      const double a0 = v[64 * p], a1 = v[64 * (p + 1)], a2 = v[64 * (p + 2)], a3 = v[64 * (p + 3)];
-      acc += a0 * (sc[j0] * x[j0]);
-      acc += a1 * (sc[j1] * x[j1]);
-      acc += a2 * (sc[j2] * x[j2]);
-      acc += a3 * (sc[j3] * x[j3]);
-    }
-    for (; p < L; ++p) {
-      const int j = i + d[64 * p];
-      acc += v[64 * p] * (sc[j] * x[j]);
-    }
-    y[i] = acc;
+    const int s = wave_slice(t);
+    if (s >= S.nsl) continue;
+    const int i = s * 64 + (threadIdx.x & 63);
+    if (i >= S.N) continue;
+    y[i] = sell_row<4>(S, dlt, val, s, i, [&](int j) { return sc[j] * x[j]; });
   }
 }
 
 // r = b - A x (FP64) with ||r||^2 partials
 template <typename TI>
-__global__ __launch_bounds__(kBlock) void k_sell_residual(int N, int nsl, const int* __restrict__ sl_ptr,
-                                                          const TI* __restrict__ dlt,
+__global__ __launch_bounds__(kBlock) void k_sell_residual(SellView S, const TI* __restrict__ dlt,
                                                           const double* __restrict__ val,
                                                           const double* __restrict__ bvec,
                                                           const double* __restrict__ x, double* __restrict__ r,
                                                           double* partials) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double nrm[1] = {0.0};
   int t0, t1;
-  tile_range((nsl + kBlock / 64 - 1) / (kBlock / 64), t0, t1);
+  tile_range((S.nsl + kBlock / 64 - 1) / (kBlock / 64), t0, t1);
   for (int t = t0; t < t1; ++t) {
-    const int s = t * (kBlock / 64) + wv;
-    if (s >= nsl) continue;
-    const int i = s * 64 + lane;
-    if (i >= N) continue;
-    const int b = sl_ptr[s];
-    const int L = (sl_ptr[s + 1] - b) >> 6;
-    const TI* __restrict__ d = dlt + b + lane;
-    const double* __restrict__ v = val + b + lane;
-    double acc = 0.0;
-    int p = 0;
-    for (; p + 4 <= L; p += 4) {
-      const int j0 = i + d[64 * p], j1 = i + d[64 * (p + 1)], j2 = i + d[64 * (p + 2)], j3 = i + d[64 * (p + 3)];
-      const double a0 = v[64 * p], a1 = v[64 * (p + 1)], a2 = v[64 * (p + 2)], a3 = v[64 * (p + 3)];
-      acc += a0 * x[j0];
-      acc += a1 * x[j1];
-      acc += a2 * x[j2];
-      acc += a3 * x[j3];
-    }
-    for (; p < L; ++p) acc += v[64 * p] * x[i + d[64 * p]];
-    const double ri = bvec[i] - acc;
+    const int s = wave_slice(t);
+    if (s >= S.nsl) continue;
+    const int i = s * 64 + (threadIdx.x & 63);
+    if (i >= S.N) continue;
+    const double ri = bvec[i] - sell_row<4>(S, dlt, val, s, i, [&](int j) { return x[j]; });
     r[i] = ri;
     nrm[0] += ri * ri;
   }
@@ -455,63 +397,60 @@ __device__ __forceinline__ void store16(T* __restrict__ p, int e, int N, const T
   }
 }
 
-// h_{q,k} = sc_q (V[q], W), q = 0..k.  Each block streams chunks of
-// 2 x 16 B per thread of W and of every basis vector (four vectors per pass
-// for memory-level parallelism); per-wave sums accumulate in LDS.
-// Raw projections (V[q], W), q = 0..k, of the unscaled SpMV output W.
+// Arnoldi step k (classical Gram-Schmidt) as four launches:
+//   SpMV      W = A V[k]                          (unscaled basis vector)
+//   dots      per-workgroup partials of (V[q], W), q = 0..k
+//   reduce    h_{q,k} = sc_q sc_k (V[q], W); workgroup 0 also finishes step
+//             k - 1 (norm of V[k] -> Givens rotation of column k - 1)
+//   update    V[k+1] = sc_k W - sum_q h_{q,k} sc_q V[q] and its squared norm
+// The vector kernels use 256-thread workgroups, one 16-byte access per
+// thread and vector per chunk, so that a launch fills every SIMD with waves.
+
+// Raw projections (V[q], W), q = 0..k: per-wave sums accumulate in LDS
+// (double), one partial per workgroup and row.
 template <typename T>
-__global__ __launch_bounds__(kVecBlock) void k_gmres_dots(int N, int ldv, const T* __restrict__ V,
-                                                       const T* __restrict__ W, int k, int m, KState* ks,
-                                                       double* partials, int nbu) {
-  if (block_done(ks)) return;
-  finish_prev_step(ks, partials, nbu, k, m);
+__global__ __launch_bounds__(kBlock) void k_gmres_dots(int N, int ldv, const T* __restrict__ V,
+                                                     const T* __restrict__ W, int k, const KState* __restrict__ ks,
+                                                     double* __restrict__ partials) {
+  if (ks->done) return;
   constexpr int VN = 16 / sizeof(T);
-  constexpr int CH = kVecBlock * VN * 2;
-  constexpr int NW = kVecBlock / 64;
+  constexpr int CH = kBlock * VN;
+  constexpr int NW = kBlock / 64;
   __shared__ double sh[kMaxRestart + 1][NW];
   const int nv = k + 1;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int q = threadIdx.x; q < nv * NW; q += kVecBlock) sh[q / NW][q % NW] = 0.0;
+  for (int q = threadIdx.x; q < nv * NW; q += kBlock) sh[q / NW][q % NW] = 0.0;
   __syncthreads();
   for (int base = blockIdx.x * CH; base < N; base += gridDim.x * CH) {
-    const int e0 = base + threadIdx.x * VN, e1 = e0 + kVecBlock * VN;
-    T w0[VN], w1[VN];
-    load16(W, e0, N, w0);
-    load16(W, e1, N, w1);
+    const int e = base + threadIdx.x * VN;
+    T w[VN];
+    load16(W, e, N, w);
     int q = 0;
     for (; q + 4 <= nv; q += 4) {
-      T a[4][VN], b[4][VN];
+      T a[4][VN];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        load16(V + (size_t)(q + u) * ldv, e0, N, a[u]);
-        load16(V + (size_t)(q + u) * ldv, e1, N, b[u]);
-      }
-      double sum[4];
+      for (int u = 0; u < 4; ++u) load16(V + (size_t)(q + u) * ldv, e, N, a[u]);
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         double t = 0.0;
 #pragma unroll
-        for (int c = 0; c < VN; ++c) t += (double)a[u][c] * (double)w0[c] + (double)b[u][c] * (double)w1[c];
-        sum[u] = wave_sum(t);
-      }
-      if (lane == 0) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) sh[q + u][wv] += sum[u];
+        for (int c = 0; c < VN; ++c) t += (double)a[u][c] * (double)w[c];
+        t = wave_sum(t);
+        if (lane == 0) sh[q + u][wv] += t;
       }
     }
     for (; q < nv; ++q) {
-      T a[VN], b[VN];
-      load16(V + (size_t)q * ldv, e0, N, a);
-      load16(V + (size_t)q * ldv, e1, N, b);
+      T a[VN];
+      load16(V + (size_t)q * ldv, e, N, a);
       double t = 0.0;
 #pragma unroll
-      for (int c = 0; c < VN; ++c) t += (double)a[c] * (double)w0[c] + (double)b[c] * (double)w1[c];
+      for (int c = 0; c < VN; ++c) t += (double)a[c] * (double)w[c];
       t = wave_sum(t);
       if (lane == 0) sh[q][wv] += t;
     }
   }
   __syncthreads();
-  for (int q = threadIdx.x; q < nv; q += kVecBlock) {
+  for (int q = threadIdx.x; q < nv; q += kBlock) {
     double t = 0.0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) t += sh[q][w];
@@ -519,79 +458,99 @@ __global__ __launch_bounds__(kVecBlock) void k_gmres_dots(int N, int ldv, const 
   }
 }
 
-// V[k+1] = W - sum_q h_{q,k} sc_q V[q], its squared norm, then the Givens step.
+// Fixed-order sum of nb partials of one row by a whole workgroup (result in
+// every thread).  Identical inputs give bitwise identical sums in every
+// workgroup.
+__device__ double block_row_sum(const double* __restrict__ row, int nb) {
+  __shared__ double sh[kBlock / 64];
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kBlock) s += row[b];
+  s = wave_sum(s);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wv] = s;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int w = 0; w < kBlock / 64; ++w) t += sh[w];
+  return t;
+}
+
+// Workgroup q (q = 0..k) finalizes h_{q,k}.  For k > 0 every workgroup first
+// derives sc_k = 1 / ||V[k]|| from the norm partials of the previous update
+// (same order everywhere, so the same value), and workgroup 0 applies the
+// Givens rotation of column k - 1, which stores sc_k and may end the cycle.
+__global__ __launch_bounds__(kBlock) void k_gmres_reduce(KState* ks, const double* __restrict__ partials, int nb,
+                                                       int k, int m) {
+  if (ks->done) return;
+  const int q = blockIdx.x;
+  double sck = ks->sc[0];
+  double nrm2 = 0.0;
+  if (k > 0) {
+    nrm2 = block_row_sum(partials + (size_t)kNormRow * kRedBlocks, nb);
+    const double hk = sqrt(nrm2);
+    sck = hk > 0.0 ? 1.0 / hk : 0.0;
+  }
+  const double t = block_row_sum(partials + (size_t)q * kRedBlocks, nb);
+  if (threadIdx.x == 0) {
+    const double scq = q == k ? sck : ks->sc[q];
+    const double h = scq * sck * t;
+    ks->H[(size_t)k * (m + 1) + q] = h;
+    ks->proj[q] = h * scq;
+  }
+  if (q == 0 && k > 0) givens_step(ks, k - 1, m, nrm2);
+}
+
+// V[k+1] = sc_k W - sum_q proj_q V[q] and the partials of its squared norm.
 template <typename T>
-__global__ __launch_bounds__(kVecBlock) void k_gmres_update(int N, int ldv, T* __restrict__ V,
-                                                         const T* __restrict__ W, int k, int m, KState* ks,
-                                                         double* partials, int nbd) {
+__global__ __launch_bounds__(kBlock) void k_gmres_update(int N, int ldv, T* __restrict__ V,
+                                                       const T* __restrict__ W, int k,
+                                                       const KState* __restrict__ ks, double* __restrict__ partials) {
   if (ks->done) return;
   constexpr int VN = 16 / sizeof(T);
-  constexpr int CH = kVecBlock * VN * 2;
+  constexpr int CH = kBlock * VN;
   __shared__ double tq[kMaxRestart + 1];
   const int nv = k + 1;
-  // projections h_{q,k} = sc_q sc_k (V[q], W): same fixed-order sums in every workgroup
-  sum_partial_rows<kVecBlock>(partials, 0, nv, nbd, tq);
+  for (int q = threadIdx.x; q < nv; q += kBlock) tq[q] = ks->proj[q];
   const double sck = ks->sc[k];
-  double* Hk = ks->H + (size_t)k * (m + 1);
-  for (int q = threadIdx.x; q < nv; q += kVecBlock) {
-    const double hq = ks->sc[q] * sck * tq[q];
-    if (blockIdx.x == 0) Hk[q] = hq;
-    tq[q] = hq * ks->sc[q];
-  }
   __syncthreads();
   T* __restrict__ out = V + (size_t)(k + 1) * ldv;
   double nrm[1] = {0.0};
   for (int base = blockIdx.x * CH; base < N; base += gridDim.x * CH) {
-    const int e0 = base + threadIdx.x * VN, e1 = e0 + kVecBlock * VN;
-    T w0[VN], w1[VN];
-    load16(W, e0, N, w0);
-    load16(W, e1, N, w1);
-    double c0[VN], c1[VN];
+    const int e = base + threadIdx.x * VN;
+    T w[VN];
+    load16(W, e, N, w);
+    double c[VN];
 #pragma unroll
-    for (int c = 0; c < VN; ++c) {
-      c0[c] = sck * (double)w0[c];
-      c1[c] = sck * (double)w1[c];
-    }
+    for (int i = 0; i < VN; ++i) c[i] = sck * (double)w[i];
     int q = 0;
     for (; q + 4 <= nv; q += 4) {
-      T a[4][VN], b[4][VN];
+      T a[4][VN];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        load16(V + (size_t)(q + u) * ldv, e0, N, a[u]);
-        load16(V + (size_t)(q + u) * ldv, e1, N, b[u]);
-      }
+      for (int u = 0; u < 4; ++u) load16(V + (size_t)(q + u) * ldv, e, N, a[u]);
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const double t = tq[q + u];
 #pragma unroll
-        for (int c = 0; c < VN; ++c) {
-          c0[c] -= t * (double)a[u][c];
-          c1[c] -= t * (double)b[u][c];
-        }
+        for (int i = 0; i < VN; ++i) c[i] -= t * (double)a[u][i];
       }
     }
     for (; q < nv; ++q) {
-      T a[VN], b[VN];
-      load16(V + (size_t)q * ldv, e0, N, a);
-      load16(V + (size_t)q * ldv, e1, N, b);
+      T a[VN];
+      load16(V + (size_t)q * ldv, e, N, a);
       const double t = tq[q];
 #pragma unroll
-      for (int c = 0; c < VN; ++c) {
-        c0[c] -= t * (double)a[c];
-        c1[c] -= t * (double)b[c];
-      }
+      for (int i = 0; i < VN; ++i) c[i] -= t * (double)a[i];
     }
-    T o0[VN], o1[VN];
+    T o[VN];
 #pragma unroll
-    for (int c = 0; c < VN; ++c) {
-      o0[c] = (T)c0[c];
-      o1[c] = (T)c1[c];
-      nrm[0] += (double)o0[c] * (double)o0[c] + (double)o1[c] * (double)o1[c];
+    for (int i = 0; i < VN; ++i) {
+      o[i] = (T)c[i];
+      nrm[0] += (double)o[i] * (double)o[i];
     }
-    store16(out, e0, N, o0);
-    store16(out, e1, N, o1);
+    store16(out, e, N, o);
   }
-  block_partials_n<kVecBlock, 1>(nrm, 1, partials + (size_t)kNormRow * kRedBlocks, blockIdx.x);
+  block_partials<1>(nrm, 1, partials + (size_t)kNormRow * kRedBlocks, blockIdx.x);
 }
 
 // back substitution R y = g over the columns completed in the cycle (one wave)
@@ -1311,25 +1270,47 @@ int vec_grid(const H* h) { return std::max(1, std::min((h->N + kBlock - 1) / kBl
 
 }  // namespace
 
-ProfScope::ProfScope(afc_handle_s* h_, int kid_) : h(h_), kid(kid_) {
-  if (!h->opt.profile) return;
-  hipEvent_t a;
+namespace {
+
+void take_events(afc_handle_s* h, hipEvent_t* a, hipEvent_t* b) {
   if (h->ev_pool.size() >= 2) {
-    a = h->ev_pool.back();
+    *a = h->ev_pool.back();
     h->ev_pool.pop_back();
-    b = h->ev_pool.back();
+    *b = h->ev_pool.back();
     h->ev_pool.pop_back();
   } else {
-    (void)hipEventCreate(&a);
-    (void)hipEventCreate(&b);
+    (void)hipEventCreate(a);
+    (void)hipEventCreate(b);
   }
-  (void)hipEventRecord(a, h->stream);
+}
+
+// Launch on the handle's stream.  With per-kernel timing on, the start and
+// stop events ride on the dispatch itself (hipExtLaunchKernel), so the time
+// folded into the totals is the kernel's own execution, with no gap from
+// separately recorded event packets.
+template <typename... KArgs, typename... Args>
+void launch(H* h, int kid, void (*kernel)(KArgs...), dim3 grid, dim3 block, Args... args) {
+  if (!h->opt.profile) {
+    kernel<<<grid, block, 0, h->stream>>>(args...);
+    return;
+  }
+  hipEvent_t a, b;
+  take_events(h, &a, &b);
+  hipExtLaunchKernelGGL(kernel, grid, block, 0, h->stream, a, b, 0, static_cast<KArgs>(args)...);
   h->ev_pending.push_back({a, b, kid});
 }
 
-ProfScope::~ProfScope() {
-  if (b) (void)hipEventRecord(b, h->stream);
-}
+}  // namespace
+
+#define AFC_DISPATCH_G_TIMED(h, KID, KERNEL, GRID, ...)                         \
+  do {                                                                          \
+    switch ((h)->G) {                                                           \
+      case 8: launch((h), (KID), KERNEL<8>, (GRID), kBlock, __VA_ARGS__); break;   \
+      case 16: launch((h), (KID), KERNEL<16>, (GRID), kBlock, __VA_ARGS__); break; \
+      case 32: launch((h), (KID), KERNEL<32>, (GRID), kBlock, __VA_ARGS__); break; \
+      default: launch((h), (KID), KERNEL<64>, (GRID), kBlock, __VA_ARGS__); break; \
+    }                                                                           \
+  } while (0)
 
 void prof_collect(afc_handle_s* h) {
   for (auto& e : h->ev_pending) {
@@ -1353,8 +1334,8 @@ void prof_release(afc_handle_s* h) {
 
 void finish(H* h, int nb, int nv, int act, int red_off = 0, int k = 0, int m = 0, int mode = 0, double p1 = 0.0,
             double p2 = 0.0, int prow = 0) {
-  ProfScope ps(h, AFC_KERNEL_FINISH);
-  k_finish<<<1, kFinish, 0, h->stream>>>(h->ks, h->partials, nb, nv, act, red_off, k, m, mode, p1, p2, prow);
+  launch(h, AFC_KERNEL_FINISH, k_finish, 1, kFinish, h->ks, (const double*)h->partials, nb, nv, act, red_off, k, m,
+         mode, p1, p2, prow);
 }
 
 void copy(H* h, double* dst, const double* src) { k_copy<<<vec_grid(h), kBlock, 0, h->stream>>>(h->N, dst, src); }
@@ -1390,20 +1371,17 @@ int sell_grid(const H* h, bool reduce) {
   return std::max(1, std::min(nt, reduce ? kRedBlocks : kRowGridCap));
 }
 
+SellView sell_view(const H* h) { return SellView{h->N, h->nslices, h->sl_ptr, h->sl_dl, h->sl_pat}; }
+
 void residual(H* h, const double* A, const double* b, const double* x, double* r, int mode, double tol_abs,
               double tol_rel) {
   const int nb = sell_grid(h, true);
-  {
-    ProfScope ps(h, AFC_KERNEL_RESIDUAL);
-    if (h->dlt16)
-      k_sell_residual<int16_t><<<nb, kBlock, 0, h->stream>>>(h->N, h->nslices, h->sl_ptr,
-                                                             static_cast<const int16_t*>(h->sl_dlt), A, b, x, r,
-                                                             h->partials);
-    else
-      k_sell_residual<int32_t><<<nb, kBlock, 0, h->stream>>>(h->N, h->nslices, h->sl_ptr,
-                                                             static_cast<const int32_t*>(h->sl_dlt), A, b, x, r,
-                                                             h->partials);
-  }
+  if (h->dlt16)
+    launch(h, AFC_KERNEL_RESIDUAL, k_sell_residual<int16_t>, nb, kBlock, sell_view(h),
+           static_cast<const int16_t*>(h->sl_dlt), A, b, x, r, h->partials);
+  else
+    launch(h, AFC_KERNEL_RESIDUAL, k_sell_residual<int32_t>, nb, kBlock, sell_view(h),
+           static_cast<const int32_t*>(h->sl_dlt), A, b, x, r, h->partials);
   finish(h, nb, 1, ACT_CYCLE, 0, 0, 0, mode, tol_abs, tol_rel);
 }
 
@@ -1421,62 +1399,58 @@ void cycle_start(H* h, int mode, int red_idx, double tol_abs, double tol_rel) {
 
 void cast_v0(H* h, const double* r) { k_cast_v0<<<vec_grid(h), kBlock, 0, h->stream>>>(h->N, r, h->V32, h->ks); }
 
-int upd_grid(const H* h, bool fp32) { return vec16_grid(h, fp32 ? kVecBlock * 8 : kVecBlock * 4); }
+// workgroups of the GMRES vector kernels: one 16-byte access per thread and
+// vector per chunk, at most kRedBlocks partials per row
+int gmres_grid(const H* h, bool fp32) { return vec16_grid(h, kBlock * (fp32 ? 4 : 2)); }
 
-void gmres_spmv64(H* h, const double* A, const double* dinv, int k, int m) {
-  ProfScope ps(h, AFC_KERNEL_SPMV64);
+void gmres_spmv64(H* h, const double* A, const double* dinv, int k) {
   const double* x = h->V64 + (size_t)k * h->ldv;
-  const int nbu = upd_grid(h, false);
   if (h->dlt16)
-    k_sell_spmv64<int16_t><<<sell_grid(h, false), kBlock, 0, h->stream>>>(
-        h->N, h->nslices, h->sl_ptr, static_cast<const int16_t*>(h->sl_dlt), A, dinv, x, h->ks, h->partials, nbu, k,
-        m, h->w[0]);
+    launch(h, AFC_KERNEL_SPMV64, k_sell_spmv64<int16_t>, sell_grid(h, false), kBlock, sell_view(h),
+           static_cast<const int16_t*>(h->sl_dlt), A, dinv, x, (const KState*)h->ks, h->w[0]);
   else
-    k_sell_spmv64<int32_t><<<sell_grid(h, false), kBlock, 0, h->stream>>>(
-        h->N, h->nslices, h->sl_ptr, static_cast<const int32_t*>(h->sl_dlt), A, dinv, x, h->ks, h->partials, nbu, k,
-        m, h->w[0]);
+    launch(h, AFC_KERNEL_SPMV64, k_sell_spmv64<int32_t>, sell_grid(h, false), kBlock, sell_view(h),
+           static_cast<const int32_t*>(h->sl_dlt), A, dinv, x, (const KState*)h->ks, h->w[0]);
 }
 
-void gmres_spmv32(H* h, const float* A32, int k, int m) {
-  ProfScope ps(h, AFC_KERNEL_SPMV32);
+void gmres_spmv32(H* h, const float* A32, int k) {
   const float* x = h->V32 + (size_t)k * h->ldv;
   float* y = reinterpret_cast<float*>(h->w[0]);
-  const int nbu = upd_grid(h, true);
   if (h->dlt16)
-    k_sell_spmv32<int16_t><<<sell_grid(h, false), kBlock, 0, h->stream>>>(
-        h->N, h->nslices, h->sl_ptr, static_cast<const int16_t*>(h->sl_dlt), A32, x, h->ks, h->partials, nbu, k, m,
-        y);
+    launch(h, AFC_KERNEL_SPMV32, k_sell_spmv32<int16_t>, sell_grid(h, false), kBlock, sell_view(h),
+           static_cast<const int16_t*>(h->sl_dlt), A32, x, (const KState*)h->ks, y);
   else
-    k_sell_spmv32<int32_t><<<sell_grid(h, false), kBlock, 0, h->stream>>>(
-        h->N, h->nslices, h->sl_ptr, static_cast<const int32_t*>(h->sl_dlt), A32, x, h->ks, h->partials, nbu, k, m,
-        y);
+    launch(h, AFC_KERNEL_SPMV32, k_sell_spmv32<int32_t>, sell_grid(h, false), kBlock, sell_view(h),
+           static_cast<const int32_t*>(h->sl_dlt), A32, x, (const KState*)h->ks, y);
 }
 
-void gmres_dots(H* h, bool fp32, int k, int m) {
-  const int nb = vec16_grid(h, fp32 ? kVecBlock * 8 : kVecBlock * 4);
-  ProfScope ps(h, AFC_KERNEL_DOTS);
+void gmres_dots(H* h, bool fp32, int k) {
+  const int nb = gmres_grid(h, fp32);
   if (fp32)
-    k_gmres_dots<float><<<nb, kVecBlock, 0, h->stream>>>(h->N, h->ldv, h->V32, reinterpret_cast<const float*>(h->w[0]),
-                                                         k, m, h->ks, h->partials, nb);
+    launch(h, AFC_KERNEL_DOTS, k_gmres_dots<float>, nb, kBlock, h->N, h->ldv, (const float*)h->V32,
+           reinterpret_cast<const float*>(h->w[0]), k, (const KState*)h->ks, h->partials);
   else
-    k_gmres_dots<double><<<nb, kVecBlock, 0, h->stream>>>(h->N, h->ldv, h->V64, h->w[0], k, m, h->ks, h->partials,
-                                                          nb);
+    launch(h, AFC_KERNEL_DOTS, k_gmres_dots<double>, nb, kBlock, h->N, h->ldv, (const double*)h->V64,
+           (const double*)h->w[0], k, (const KState*)h->ks, h->partials);
 }
 
-void gmres_update(H* h, bool fp32, int k, int m) {
-  const int nb = upd_grid(h, fp32);
-  ProfScope ps(h, AFC_KERNEL_UPDATE);
+void gmres_reduce(H* h, bool fp32, int k, int m) {
+  launch(h, AFC_KERNEL_FINISH, k_gmres_reduce, k + 1, kBlock, h->ks, (const double*)h->partials,
+         gmres_grid(h, fp32), k, m);
+}
+
+void gmres_update(H* h, bool fp32, int k) {
+  const int nb = gmres_grid(h, fp32);
   if (fp32)
-    k_gmres_update<float><<<nb, kVecBlock, 0, h->stream>>>(h->N, h->ldv, h->V32,
-                                                           reinterpret_cast<const float*>(h->w[0]), k, m, h->ks,
-                                                           h->partials, nb);
+    launch(h, AFC_KERNEL_UPDATE, k_gmres_update<float>, nb, kBlock, h->N, h->ldv, h->V32,
+           reinterpret_cast<const float*>(h->w[0]), k, (const KState*)h->ks, h->partials);
   else
-    k_gmres_update<double><<<nb, kVecBlock, 0, h->stream>>>(h->N, h->ldv, h->V64, h->w[0], k, m, h->ks, h->partials,
-                                                            nb);
+    launch(h, AFC_KERNEL_UPDATE, k_gmres_update<double>, nb, kBlock, h->N, h->ldv, h->V64,
+           (const double*)h->w[0], k, (const KState*)h->ks, h->partials);
 }
 
 void gmres_last_givens(H* h, bool fp32, int k, int m) {
-  finish(h, upd_grid(h, fp32), 1, ACT_GIVENS, 0, k, m, 0, 0.0, 0.0, kNormRow);
+  finish(h, gmres_grid(h, fp32), 1, ACT_GIVENS, 0, k, m, 0, 0.0, 0.0, kNormRow);
 }
 
 void gmres_solve(H* h, int m) { k_gmres_solve<<<1, 64, 0, h->stream>>>(h->ks, m); }
@@ -1550,17 +1524,13 @@ void cn_apply(H* h, const double* u, const double* u_old, const double* Rp, cons
 }
 
 void mcl_bounds(H* h, const double* u, double* umax, double* umin) {
-  ProfScope ps(h, AFC_KERNEL_MCL);
-  AFC_DISPATCH_G(h, k_mcl_bounds, row_grid(h, false), h->N, h->row_ptr, h->col, u, umax, umin);
+  AFC_DISPATCH_G_TIMED(h, AFC_KERNEL_MCL, k_mcl_bounds, row_grid(h, false), h->N, h->row_ptr, h->col, u, umax, umin);
 }
 
 void mcl_apply(H* h, const double* u, const double* umax, const double* umin, const double* F, double* b, double* r) {
   const int nb = row_grid(h, true);
-  {
-  ProfScope ps(h, AFC_KERNEL_MCL);
-  AFC_DISPATCH_G(h, k_mcl_apply, nb, h->N, h->row_ptr, h->col, h->cc, h->ccT, h->AL_mcl, u, umax, umin, F,
-                 h->is_dir, h->uD, h->opt.alpha_mode, b, r, h->ks, h->partials);
-  }
+  AFC_DISPATCH_G_TIMED(h, AFC_KERNEL_MCL, k_mcl_apply, nb, h->N, h->row_ptr, h->col, h->cc, h->ccT, h->AL_mcl, u,
+                       umax, umin, F, h->is_dir, h->uD, h->opt.alpha_mode, b, r, h->ks, h->partials);
   finish(h, nb, 3, ACT_STORE);
 }
 

@@ -513,3 +513,29 @@ def config5_instance(req) -> Instance:
                      u0_fn=_box_indicator([0.2] * 3, [0.45] * 3), params=dict(cfg=5, dt=1e-3, steps=20))
     return build("Q1", req["n"], req["eps"], affine_field(req["b"]), req["c"], load=("box", [0.25] * 3, [0.5] * 3),
                  dirichlet="all", params=dict(cfg=5, fp_rtol=1e-8))
+
+
+def renumbered(inst: Instance, seed=(0, 9)) -> Instance:
+    """The same problem with its nodes renamed by a seeded random permutation
+    (node i becomes perm[i]; every CSR row re-sorted by column).  Stands in for
+    the unstructured node numbering of a general mesh: neighbouring rows no
+    longer share one column-offset pattern."""
+    perm = np.random.default_rng(seed).permutation(inst.N)
+    rows = inst.row_index()
+    new_r = perm[rows]
+    new_c = perm[inst.col.astype(np.int64)]
+    order = np.lexsort((new_c, new_r))
+    counts = np.bincount(new_r, minlength=inst.N)
+    row_ptr = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+
+    def nodal(v):
+        out = np.empty_like(v)
+        out[perm] = v
+        return out
+
+    d_new = perm[inst.dir_idx.astype(np.int64)]
+    d_order = np.argsort(d_new)
+    return Instance(elem=inst.elem, n=inst.n, N=inst.N, row_ptr=row_ptr, col=new_c[order].astype(np.int32),
+                    M=inst.M[order], K=inst.K[order], K_conv=inst.K_conv[order], F=nodal(inst.F),
+                    dir_idx=d_new[d_order].astype(np.int32), dir_val=inst.dir_val[d_order], u0=nodal(inst.u0),
+                    coords=nodal(inst.coords), params=dict(inst.params, perm=perm))

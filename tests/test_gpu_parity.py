@@ -206,6 +206,41 @@ def test_mcl_stationary_parity(prec):
         afc.afc_destroy(h)
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_mcl_renumbered_parity(prec):
+    """Scrambled node numbering: the SELL slices fall back to per-row column
+    offsets (the structured numbering above uses shared offset patterns)."""
+    afc = _afc()
+    inst = I.renumbered(I.config3(12))
+    ref, rst = _mcl_ref(inst, 1e-12, 1e-14)
+    print("mcl renumbered n=12 prec=%d oracle fp its %d" % (prec, rst.iters), flush=True)
+    h = afc.afc_create_instance(inst, _opts(precision=prec, fp_tol=1e-12, fp_tol_mode=1, fp_maxit=2000,
+                                            lin_atol=0.0, lin_rtol=1e-14), conv=True)
+    try:
+        info = afc.afc_get_sell_info(h)
+        assert info["uniform_slices"] < info["slices"] and info["lane_delta_slots"] > 0
+        u = _dev(np.zeros(inst.N))
+        st, stats = afc.afc_solve_stationary(h, u, _dev(inst.F), init_low_order=True)
+        assert st == 0, stats
+        tol = 1e-10 if prec == 0 else 1e-8
+        assert _rel(u.cpu().numpy(), ref) <= tol
+    finally:
+        afc.afc_destroy(h)
+
+
+def test_sell_info_matches_host_layout():
+    afc = _afc()
+    inst = I.config3(12)
+    h = afc.afc_create_instance(inst, _opts(), conv=True)
+    try:
+        info = afc.afc_get_sell_info(h)
+    finally:
+        afc.afc_destroy(h)
+    host = afc.afc_sell_layout(inst.row_ptr, inst.col)[0]
+    assert info == host
+    assert info["uniform_slices"] > info["slices"] // 2
+
+
 def test_mcl_single_iteration_parity():
     """One fixed-point iteration from the same low-order start (fp_maxit = 1)."""
     afc = _afc()
