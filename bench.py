@@ -48,9 +48,11 @@ def spmv32_bytes(N, info):
 
 
 def step_model_bytes(N, nnz, info, krylov, sweeps, steps):
-    """Algorithmic HBM bytes of `steps` fixed-point iterations (model)."""
+    """Algorithmic HBM bytes of `steps` fixed-point iterations (model: every
+    cycle of equal length, Arnoldi index k uniform over the cycle)."""
     L = krylov / max(sweeps, 1)  # mean FP32 GMRES cycle length
     kbar = (L - 1) / 2.0         # mean Arnoldi index inside a cycle
+    # SpMV, projections (V[0..k] and W) and the update
     per_it = spmv32_bytes(N, info) + (kbar + 2) * 4 * N + (kbar + 3) * 4 * N
     residual = (8 * info["slots"] + info["delta_bytes"] * info["lane_delta_slots"] + 4 * info["pattern_ints"]
                 + 8 * info["slices"] + 4 + 24 * N)
@@ -208,9 +210,11 @@ def traffic_probe(n):
     del src, dst
     print("traffic probe: 3 copies of %d bytes done" % (1 << 30), flush=True)
     inst = I.config3(n)
+    # profiled from the start, so that the library's work counters cover every
+    # launch the counter passes see
     o = afc.afc_default_options(precision=afc.AFC_PREC_MIXED, krylov=afc.AFC_KRYLOV_GMRES, restart=30,
                                 fp_tol=0.0, fp_tol_mode=afc.AFC_TOL_REL, fp_maxit=0, lin_atol=0.0,
-                                lin_rtol=1e-10, lin_maxit=100000)
+                                lin_rtol=1e-10, lin_maxit=100000, profile=1)
     o.stream = torch.cuda.current_stream().cuda_stream
     h = afc.afc_create_instance(inst, o, conv=True)
     u = torch.zeros(inst.N, dtype=torch.float64, device="cuda")
@@ -220,11 +224,17 @@ def traffic_probe(n):
     afc.afc_set_options(h, o)
     _, s = afc.afc_solve_stationary(h, u, F)
     torch.cuda.synchronize()
+    work = {}
+    for name, kid in (("k_sell_spmv32", afc.AFC_KERNEL_SPMV32), ("k_gmres_dots", afc.AFC_KERNEL_DOTS),
+                      ("k_gmres_update", afc.AFC_KERNEL_UPDATE), ("k_sell_residual", afc.AFC_KERNEL_RESIDUAL)):
+        by, n = afc.afc_kernel_work(h, kid)
+        work[name] = {"bytes": by, "launches_with_work": n}
     afc.afc_destroy(h)
     print("traffic probe: 1 fixed-point iteration, %d Krylov iterations" % s["krylov_iters"], flush=True)
+    print("traffic probe work: " + json.dumps(work), flush=True)
 
 
-def traffic_summarize(fetch_csv, write_csv, n):
+def traffic_summarize(fetch_csv, write_csv, probe_log, n):
     """Turn the two counter CSVs of `traffic_probe` into HBM bytes per launch.
     Each counter is scaled by what it reads for the 1 GiB copies; launches that
     moved under 1 MiB (no-op launches after a cycle converged) are left out.
@@ -242,6 +252,13 @@ def traffic_summarize(fetch_csv, write_csv, n):
         return out
 
     fe, wr = load(fetch_csv, "FETCH_SIZE"), load(write_csv, "WRITE_SIZE")
+    work = None
+    with open(probe_log) as f:
+        for line in f:
+            if line.startswith("traffic probe work: "):
+                work = json.loads(line[len("traffic probe work: "):])
+    if work is None:
+        raise SystemExit("traffic: no 'traffic probe work' line in %s" % probe_log)
 
     def series(d, name):
         # demangled names: "void afc::(anonymous namespace)::k_sell_spmv32<short>(int, ...)"
@@ -254,16 +271,25 @@ def traffic_summarize(fetch_csv, write_csv, n):
         raise SystemExit("traffic: the three 1 GiB calibration copies are missing from the counter files")
     sf, sw = gib_kib / (sum(cf[:3]) / 3), gib_kib / (sum(cw[:3]) / 3)
     table = {}
-    for name in ("k_sell_spmv32", "k_gmres_dots", "k_gmres_update", "k_sell_residual", "k_mcl_bounds", "k_mcl_apply"):
+    for name in ("k_sell_spmv32", "k_gmres_dots", "k_gmres_update", "k_gmres_reduce", "k_sell_residual",
+                 "k_mcl_bounds", "k_mcl_apply"):
         f = [v for v in series(fe, name) if v > 1024]
         w = [v for v in series(wr, name) if v > 1024]
         if f:
             table[name] = {"launches": len(f), "fetch_bytes": 1024 * sf * sum(f) / len(f),
                            "write_bytes": 1024 * sw * sum(w) / len(w) if w else 0.0}
+    for name, t in table.items():
+        if name in work and work[name]["launches_with_work"] == t["launches"]:
+            t["algorithmic_bytes"] = work[name]["bytes"] / t["launches"]
     inst = I.config3(n)
     sp = table["k_sell_spmv32"]
-    rec = {"kernel": "k_sell_spmv32", "workload": "stationary MCL Q1 %d^3 (%d nodes, %d nnz)" % (n, inst.N, inst.nnz),
+    if "algorithmic_bytes" not in sp:
+        raise SystemExit("traffic: counted %d SpMV launches with work, the library %d"
+                         % (sp["launches"], work["k_sell_spmv32"]["launches_with_work"]))
+    rec = {"kernel": "k_sell_spmv32<short>",
+           "workload": "stationary MCL Q1 %d^3 (%d nodes, %d nnz)" % (n, inst.N, inst.nnz),
            "nnz": inst.nnz, "bytes_per_launch": round(sp["fetch_bytes"] + sp["write_bytes"]),
+           "algorithmic_bytes_per_launch": round(sp["algorithmic_bytes"]),
            "fetch_bytes": round(sp["fetch_bytes"]), "write_bytes": round(sp["write_bytes"]),
            "launches_averaged": sp["launches"], "fetch_scale": sf, "write_scale": sw,
            "kernel_source_sha": kernel_source_hash()}
@@ -272,10 +298,12 @@ def traffic_summarize(fetch_csv, write_csv, n):
         f.write("\n")
     print("copy calibration: FETCH_SIZE %.1f KiB, WRITE_SIZE %.1f KiB per 1 GiB copy -> scales %.4f, %.4f"
           % (sum(cf[:3]) / 3, sum(cw[:3]) / 3, sf, sw))
-    print("| kernel | launches | fetch MB | write MB |")
-    print("|---|---|---|---|")
+    print("| kernel | launches | fetch MB | write MB | algorithmic MB |")
+    print("|---|---|---|---|---|")
     for name, t in table.items():
-        print("| %s | %d | %.1f | %.1f |" % (name, t["launches"], t["fetch_bytes"] / 1e6, t["write_bytes"] / 1e6))
+        alg = "%.1f" % (t["algorithmic_bytes"] / 1e6) if "algorithmic_bytes" in t else "-"
+        print("| %s | %d | %.1f | %.1f | %s |" % (name, t["launches"], t["fetch_bytes"] / 1e6,
+                                                  t["write_bytes"] / 1e6, alg))
 
 
 def main():
@@ -293,11 +321,11 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only run the program profiled by the FETCH_SIZE / WRITE_SIZE counter passes")
-    ap.add_argument("--traffic-summarize", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+    ap.add_argument("--traffic-summarize", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "PROBE_LOG"),
                     help="turn the counter CSVs of --traffic-probe into the per-launch traffic file (no GPU)")
     args = ap.parse_args()
     if args.traffic_summarize:
-        traffic_summarize(args.traffic_summarize[0], args.traffic_summarize[1], args.n)
+        traffic_summarize(*args.traffic_summarize, args.n)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
@@ -358,28 +386,39 @@ def main():
     st2, s2 = afc.afc_solve_stationary(h, u, F)
     torch.cuda.synchronize()
     elapsed_prof = time.perf_counter() - t0
+    classes = (("spmv32", afc.AFC_KERNEL_SPMV32), ("dots", afc.AFC_KERNEL_DOTS), ("update", afc.AFC_KERNEL_UPDATE),
+               ("residual", afc.AFC_KERNEL_RESIDUAL), ("mcl", afc.AFC_KERNEL_MCL), ("finish", afc.AFC_KERNEL_FINISH))
+    kernels = {}
+    for name, kid in classes:
+        ms, launches = afc.afc_kernel_time(h, kid)
+        by, work = afc.afc_kernel_work(h, kid)
+        kernels[name] = {"ms_per_step": round(ms / args.steps, 3), "launches": launches, "with_work": work,
+                         "gbs": round(by / (1e-3 * ms) / 1e9, 1) if by > 0 and ms > 0 else None}
+    # dominant kernel: the FP32 SELL SpMV of the inner GMRES.  Launches issued
+    # after a cycle converged return at once: their (small) time stays in the
+    # total, the average is taken over launches with work.
     spmv_ms, spmv_launches = afc.afc_kernel_time(h, afc.AFC_KERNEL_SPMV32)
-    kernel_ms = {name: afc.afc_kernel_time(h, kid)[0] for name, kid in (
-        ("spmv32", afc.AFC_KERNEL_SPMV32), ("dots", afc.AFC_KERNEL_DOTS), ("update", afc.AFC_KERNEL_UPDATE),
-        ("residual", afc.AFC_KERNEL_RESIDUAL), ("mcl", afc.AFC_KERNEL_MCL), ("finish", afc.AFC_KERNEL_FINISH))}
-    # launches after convergence of a cycle are no-ops; divide by SpMVs performed
-    spmv_avg_s = 1e-3 * spmv_ms / max(1, s2["krylov_iters"])
-    spmv_b = spmv32_bytes(N, info)
+    spmv_bytes_total, spmv_work = afc.afc_kernel_work(h, afc.AFC_KERNEL_SPMV32)
+    spmv_avg_s = 1e-3 * spmv_ms / max(1, spmv_work)
+    spmv_b = spmv_bytes_total / max(1, spmv_work)
     achieved = spmv_b / spmv_avg_s / 1e9
     traffic = None
+    traffic_alg = None
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
             tr = json.load(f)
         if tr.get("kernel_source_sha") == kernel_source_hash() and tr.get("nnz") == nnz:
             traffic = tr.get("bytes_per_launch")
+            traffic_alg = tr.get("algorithmic_bytes_per_launch")
     roofline = {
         "kernel": "k_sell_spmv32 (FP32 SELL-64 SpMV, GMRES inner)",
         "sell": info,
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-        "bytes_per_launch": spmv_b, "avg_launch_us": round(spmv_avg_s * 1e6, 2),
-        "launches": spmv_launches, "spmv_performed": s2["krylov_iters"],
-        "kernel_ms_per_step": {k: round(v / args.steps, 3) for k, v in kernel_ms.items()},
+        "traffic_probe_algorithmic": traffic_alg,
+        "bytes_per_launch": round(spmv_b), "avg_launch_us": round(spmv_avg_s * 1e6, 2),
+        "launches": spmv_launches, "launches_with_work": spmv_work,
+        "kernels": kernels,
         "profiled_ms_per_step": round(1e3 * elapsed_prof / args.steps, 3),
     }
 

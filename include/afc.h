@@ -112,6 +112,10 @@ typedef struct {
   int32_t lanes_per_row;    /* 0 = automatic; else 8, 16, 32 or 64             */
   int32_t profile;          /* 1: time every launch of the hot kernels with HIP
                                events on the handle's stream (afc_kernel_time) */
+  int32_t graphs;           /* 1 (default): each GMRES cycle is captured once
+                               as a HIP graph and replayed (same kernels, same
+                               results); 0: plain launches.  Not used while
+                               profile = 1.                                    */
   void *stream;             /* hipStream_t; NULL = default stream              */
 } afc_options;
 
@@ -119,7 +123,7 @@ typedef struct {
 enum {
   AFC_KERNEL_SPMV32 = 0,    /* FP32 SELL-64 SpMV of the mixed-precision GMRES  */
   AFC_KERNEL_SPMV64 = 1,    /* FP64 SELL-64 SpMV (Jacobi-scaled) of FP64 GMRES */
-  AFC_KERNEL_DOTS = 2,      /* GMRES Gram-Schmidt projections                  */
+  AFC_KERNEL_DOTS = 2,      /* GMRES Gram-Schmidt projection partials          */
   AFC_KERNEL_UPDATE = 3,    /* GMRES orthogonalization update + norm           */
   AFC_KERNEL_RESIDUAL = 4,  /* FP64 residual b - A x                           */
   AFC_KERNEL_MCL = 5,       /* MCL bounds + limited fluxes + residual          */
@@ -185,6 +189,14 @@ afc_status afc_solve_stationary(afc_handle *h, double *u, const double *F, int32
  * the counters after reading).  Only launches made while options.profile was
  * set are counted.  Returns EINVAL for an unknown kernel id. */
 afc_status afc_kernel_time(afc_handle *h, int32_t kernel, double *total_ms, int64_t *launches, int32_t reset);
+
+/* Algorithmic HBM bytes (each array element the kernels must read or write,
+ * counted once per launch) and the number of launches that did work, over
+ * the same profiled launches as afc_kernel_time (and cleared by its reset).
+ * GMRES launches issued after a cycle converged return at once; they count
+ * as launches in afc_kernel_time but do no work.  Accounted for the SPMV32,
+ * SPMV64, DOTS, UPDATE, RESIDUAL and MCL classes; 0 for FINISH.  Returns EINVAL for an unknown kernel id. */
+afc_status afc_kernel_work(afc_handle *h, int32_t kernel, double *bytes, int64_t *launches_with_work);
 
 /* Storage of the SELL-64 copy of the Krylov system matrices (sizes only).
  * Rows are taken in slices of 64 consecutive rows, each padded to its longest

@@ -43,7 +43,8 @@ class afc_options(ctypes.Structure):
         ("inner_rtol", c_double), ("inner_maxit", c_int32), ("refine_maxit", c_int32),
         ("fp_tol", c_double), ("fp_tol_mode", c_int32), ("fp_maxit", c_int32),
         ("prelimit", c_double), ("omega", c_double), ("dynamic_damping", c_int32),
-        ("ssp_stages", c_int32), ("lanes_per_row", c_int32), ("profile", c_int32), ("stream", c_void_p),
+        ("ssp_stages", c_int32), ("lanes_per_row", c_int32), ("profile", c_int32), ("graphs", c_int32),
+        ("stream", c_void_p),
     ]
 
 
@@ -69,7 +70,7 @@ EXPORTS = [
     "afc_solve_stationary", "afc_destroy", "afc_status_str", "afc_last_error", "afc_kernel_time",
     "afc_batch_create", "afc_batch_offsets", "afc_batch_step_cn", "afc_batch_last_error", "afc_batch_destroy",
     "afc_footprint_bytes", "afc_server_create", "afc_server_submit", "afc_server_wait", "afc_server_last_error",
-    "afc_server_destroy", "afc_get_sell_info", "afc_sell_layout",
+    "afc_server_destroy", "afc_get_sell_info", "afc_sell_layout", "afc_kernel_work",
 ]
 
 AFC_REQ_CN, AFC_REQ_STATIONARY = 0, 1
@@ -101,6 +102,8 @@ def lib():
         L.afc_solve_stationary.restype = c_int32
         L.afc_kernel_time.argtypes = [c_void_p, c_int32, POINTER(c_double), POINTER(c_int64), c_int32]
         L.afc_kernel_time.restype = c_int32
+        L.afc_kernel_work.argtypes = [c_void_p, c_int32, POINTER(c_double), POINTER(c_int64)]
+        L.afc_kernel_work.restype = c_int32
         L.afc_get_sell_info.argtypes = [c_void_p, POINTER(afc_sell_info)]
         L.afc_get_sell_info.restype = c_int32
         L.afc_sell_layout.argtypes = [c_int32, c_void_p, c_void_p, POINTER(afc_sell_info)] + [c_void_p] * 5
@@ -269,6 +272,16 @@ def afc_kernel_time(h, kernel, reset=False):
     if st != AFC_OK:
         raise AFCError(st, "afc_kernel_time")
     return ms.value, n.value
+
+
+def afc_kernel_work(h, kernel):
+    """(algorithmic bytes, launches that did work) of one profiled kernel class."""
+    b = c_double()
+    n = c_int64()
+    st = lib().afc_kernel_work(h, int(kernel), ctypes.byref(b), ctypes.byref(n))
+    if st != AFC_OK:
+        raise AFCError(st, "afc_kernel_work")
+    return b.value, n.value
 
 
 def afc_get_sell_info(h):

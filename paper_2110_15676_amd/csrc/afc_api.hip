@@ -67,6 +67,7 @@ afc_status check_options(const afc_options& o, std::string& why) {
   if (!(o.omega > 0 && o.omega <= 1)) return why = "omega must be in (0, 1]", AFC_EINVAL;
   if (o.ssp_stages < 1 || o.ssp_stages > 3) return why = "ssp_stages must be 1, 2 or 3", AFC_EINVAL;
   if (o.profile != 0 && o.profile != 1) return why = "profile must be 0 or 1", AFC_EINVAL;
+  if (o.graphs != 0 && o.graphs != 1) return why = "graphs must be 0 or 1", AFC_EINVAL;
   if (o.lanes_per_row != 0 && o.lanes_per_row != 8 && o.lanes_per_row != 16 && o.lanes_per_row != 32 &&
       o.lanes_per_row != 64)
     return why = "lanes_per_row must be 0, 8, 16, 32 or 64", AFC_EINVAL;
@@ -128,6 +129,11 @@ void free_all(afc_handle* h) {
   if (h->host_status) (void)hipHostFree(h->host_status);
   h->host_status = nullptr;
   afc::prof_release(h);
+  if (h->cyc_exec) (void)hipGraphExecDestroy(h->cyc_exec);
+  h->cyc_exec = nullptr;
+  h->cyc_key.clear();
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+  h->cap_stream = nullptr;
 }
 
 void sync_status(afc_handle* h) {
@@ -171,6 +177,31 @@ struct SolveOut {
   double res = 0.0;
 };
 
+// Capture the launches issued by `issue` on the handle's private capture
+// stream into h->cyc_exec (replacing an older graph).
+template <typename F>
+void capture_cycle(afc_handle* h, const std::vector<const void*>& key, F&& issue) {
+  if (h->cyc_exec) {
+    (void)hipGraphExecDestroy(h->cyc_exec);
+    h->cyc_exec = nullptr;
+  }
+  if (!h->cap_stream) HIP_OK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+  hipStream_t user = h->stream;
+  h->stream = h->cap_stream;
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    issue();
+    e = hipStreamEndCapture(h->cap_stream, &g);
+  }
+  h->stream = user;
+  HIP_OK(e);
+  e = hipGraphInstantiate(&h->cyc_exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  HIP_OK(e);
+  h->cyc_key = key;
+}
+
 // GMRES(m), right Jacobi.  x: in x0, out solution; r: b - A x0 on entry, with
 // ||r||^2 in ks->red[red_idx].  FP64 mode runs the Arnoldi process in FP64;
 // MIXED runs it in FP32 on the Jacobi-scaled FP32 matrix and recomputes the
@@ -199,7 +230,9 @@ SolveOut solve_gmres(afc_handle* h, const SysMat& S, const double* b, double* x,
     o.res = res;
     return o;
   }
-  while (res > tol) {
+  // one cycle: m Arnoldi steps, back substitution, x update, FP64 residual
+  // and the restart (no host decision inside, so it can be replayed)
+  auto cycle = [&]() {
     for (int k = 0; k < m; ++k) {
       if (mixed)
         afc::gmres_spmv32(h, S.S32, k);
@@ -213,13 +246,30 @@ SolveOut solve_gmres(afc_handle* h, const SysMat& S, const double* b, double* x,
     afc::gmres_solve(h, m);
     afc::gmres_xupdate(h, mixed, S.dinv, x);
     if (mixed) {
-      afc::residual(h, S.S64, b, x, r, 2, tol, inner_rel);
+      afc::residual(h, S.S64, b, x, r, 2);
       afc::cast_v0(h, r);
     } else {
-      afc::residual(h, S.S64, b, x, h->V64, 1, tol, 0.0);
+      afc::residual(h, S.S64, b, x, h->V64, 1);
     }
+  };
+  const bool graph = h->opt.graphs && !h->opt.profile;
+  if (graph) {
+    const std::vector<const void*> key = {
+        S.S32, S.S64, S.dinv, b, x, r, h->V32, h->V64, h->w[0], h->partials, h->ks,
+        reinterpret_cast<const void*>((intptr_t)m), reinterpret_cast<const void*>((intptr_t)mixed),
+        reinterpret_cast<const void*>((intptr_t)h->ldv)};
+    if (!h->cyc_exec || h->cyc_key != key) capture_cycle(h, key, cycle);
+  }
+  int cycle_it0 = it0;
+  while (res > tol) {
+    if (graph)
+      HIP_OK(hipGraphLaunch(h->cyc_exec, h->stream));
+    else
+      cycle();
     o.sweeps += 1;
     sync_status(h);
+    afc::prof_gmres_cycle(h, mixed, m, h->host_status->iters - cycle_it0);
+    cycle_it0 = h->host_status->iters;
     res = h->host_status->beta;
     const int64_t its = h->host_status->iters - it0;
     if (!std::isfinite(res)) {
@@ -266,7 +316,7 @@ SolveOut solve_bicgstab(afc_handle* h, const SysMat& S, const double* b, double*
     }
     const bool breakdown = h->host_status->flag == 1;
     // confirm on the true residual
-    afc::residual(h, S.S64, b, x, r, 0, 0.0, 0.0);
+    afc::residual(h, S.S64, b, x, r, 0);
     sync_status(h);
     const double res = std::sqrt(h->host_status->red[0]);
     o.res = res;
@@ -562,6 +612,7 @@ void afc_default_options(afc_options* o) {
   o->dynamic_damping = 0;
   o->ssp_stages = 3;
   o->lanes_per_row = 0;
+  o->graphs = 1;
   o->stream = nullptr;
 }
 
@@ -704,7 +755,16 @@ afc_status afc_kernel_time(afc_handle* h, int32_t kernel, double* total_ms, int6
   if (reset) {
     h->prof_ms[kernel] = 0.0;
     h->prof_n[kernel] = 0;
+    h->prof_bytes[kernel] = 0.0;
+    h->prof_work[kernel] = 0;
   }
+  return AFC_OK;
+}
+
+afc_status afc_kernel_work(afc_handle* h, int32_t kernel, double* bytes, int64_t* launches_with_work) {
+  if (!h || kernel < 0 || kernel >= AFC_KERNEL_COUNT) return AFC_EINVAL;
+  if (bytes) *bytes = h->prof_bytes[kernel];
+  if (launches_with_work) *launches_with_work = h->prof_work[kernel];
   return AFC_OK;
 }
 
@@ -855,7 +915,7 @@ afc_status afc_solve_stationary(afc_handle* h, double* u, const double* F, int32
           afc::fill(h, a.u, 0.0);
           afc::set_dirichlet(h, a.u);
           afc::norm2(h, b, 1);
-          afc::residual(h, S.S64, b, a.u, r, 0, 0.0, 0.0);
+          afc::residual(h, S.S64, b, a.u, r, 0);
           sync_status(h);
           const double tol = std::max(h->opt.lin_atol, h->opt.lin_rtol * std::sqrt(h->host_status->red[1]));
           const SolveOut o = linear_solve(h, S, b, a.u, r, 0, tol);

@@ -40,6 +40,7 @@ struct KState {
   double sc[kMaxRestart + 1];                 // basis scales: v_j = sc_j * V[j]
   double coef[kMaxRestart + 1];               // update coefficients y_j * sc_j
   double proj[kMaxRestart + 1];               // running Arnoldi step: h_{q,k} sc_q
+  double ctol_abs, ctol_rel;                  // cycle restart tolerances of the running solve
 };
 
 // bytes of KState copied back to the host: scalars + red[0..7]
@@ -111,6 +112,12 @@ struct afc_handle_s {
   afc::KState* ks = nullptr;
   afc::KState* host_status = nullptr;  // pinned copy of the KState head
 
+  // GMRES cycle replayed as a HIP graph (options.graphs): captured on a
+  // private stream, valid while every pointer and size it baked in is unchanged
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t cyc_exec = nullptr;
+  std::vector<const void*> cyc_key;
+
   // optional per-kernel timing (options.profile)
   struct ProfEv {
     hipEvent_t a, b;
@@ -120,9 +127,14 @@ struct afc_handle_s {
   std::vector<ProfEv> ev_pending;
   double prof_ms[AFC_KERNEL_COUNT] = {};
   int64_t prof_n[AFC_KERNEL_COUNT] = {};
+  double prof_bytes[AFC_KERNEL_COUNT] = {};  // algorithmic bytes of launches that did work
+  int64_t prof_work[AFC_KERNEL_COUNT] = {};  // launches that did work
 };
 
 namespace afc {
+// Algorithmic HBM bytes of one GMRES cycle whose Arnoldi process completed kk
+// columns out of m, added to the per-kernel work counters (profiling only).
+void prof_gmres_cycle(afc_handle_s* h, bool fp32, int m, int kk);
 void prof_collect(afc_handle_s* h);  // fold completed event pairs into the totals
 void prof_release(afc_handle_s* h);
 }  // namespace afc

@@ -22,10 +22,10 @@ void to_sell32_scaled(H* h, const double* csr, const double* dinv, float* sell);
 
 // --- residual of a linear system (FP64 SpMV) -----------------------------------
 // r = b - A x (A in SELL order) and ||r||^2 into ks->red[0]; mode selects the cycle start that
-// the last workgroup performs (0: none, 1: GMRES FP64 restart into V64[0],
-// 2: GMRES mixed restart, V32[0] cast done by cast_v0).
-void residual(H* h, const double* A, const double* b, const double* x, double* r, int mode, double tol_abs,
-              double tol_rel);
+// the reduction finish performs (0: none, 1: GMRES FP64 restart into V64[0],
+// 2: GMRES mixed restart, V32[0] cast done by cast_v0), with the tolerances
+// that the solve's cycle_start stored in the device state.
+void residual(H* h, const double* A, const double* b, const double* x, double* r, int mode);
 void cycle_start(H* h, int mode, int red_idx, double tol_abs, double tol_rel);  // from a finished reduction
 void cast_v0(H* h, const double* r);
 

@@ -33,12 +33,13 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
   return x * per + min(x, rem) + k;
 }
 
+// contiguous, balanced share of ntiles for this workgroup (sizes differ by at
+// most one), in the XCD-aware order
 __device__ __forceinline__ void tile_range(int ntiles, int& t0, int& t1) {
   const int nb = gridDim.x;
   const int b = xcd_block(blockIdx.x, nb);
-  const int per = (ntiles + nb - 1) / nb;
-  t0 = min(b * per, ntiles);
-  t1 = min(t0 + per, ntiles);
+  t0 = (int)(((int64_t)b * ntiles) / nb);
+  t1 = (int)(((int64_t)(b + 1) * ntiles) / nb);
 }
 
 // Block totals of nv per-thread values into partials[q * kRedBlocks + slot].
@@ -67,6 +68,8 @@ __device__ void block_partials(const double (&v)[KMAX], int nv, double* partials
 constexpr int kNormRow = kMaxRed - 1;
 // Start of a Krylov cycle from the squared norm of its residual.
 __device__ void cycle_start_dev(KState* ks, int mode, double rr, double tol_abs, double tol_rel) {
+  ks->ctol_abs = tol_abs;
+  ks->ctol_rel = tol_rel;
   const double beta = sqrt(rr);
   ks->beta = beta;
   ks->res = beta;
@@ -163,18 +166,26 @@ __global__ __launch_bounds__(kBlock) void k_cast_v0(int N, const double* __restr
 }
 
 // Givens step for Arnoldi column k, called by every thread of one workgroup:
-// the column and the previous rotations are staged in LDS in parallel, one
-// thread applies the rotation chain carrying the running entry in a register,
-// and the updated column is written back in parallel.
-__device__ void givens_step(KState* ks, int k, int m, double hk1sq) {
-  __shared__ double col[kMaxRestart + 1], c[kMaxRestart], sgn[kMaxRestart];
-  double* Hk = ks->H + (size_t)k * (m + 1);
-  for (int q = threadIdx.x; q <= k; q += blockDim.x) col[q] = Hk[q];
+// the column and the previous rotations are staged in LDS in parallel
+// (givens_stage, which needs no reduction result and so can be issued early),
+// one thread applies the rotation chain carrying the running entry in a
+// register, and the updated column is written back in parallel.
+struct GivensLds {
+  double col[kMaxRestart + 1], c[kMaxRestart], sgn[kMaxRestart];
+};
+
+__device__ void givens_stage(const KState* ks, int k, int m, GivensLds& L) {
+  const double* Hk = ks->H + (size_t)k * (m + 1);
+  for (int q = threadIdx.x; q <= k; q += blockDim.x) L.col[q] = Hk[q];
   for (int q = threadIdx.x; q < k; q += blockDim.x) {
-    c[q] = ks->cs[q];
-    sgn[q] = ks->sn[q];
+    L.c[q] = ks->cs[q];
+    L.sgn[q] = ks->sn[q];
   }
-  __syncthreads();
+}
+
+// after givens_stage and a workgroup barrier
+__device__ void givens_apply(KState* ks, int k, int m, double hk1sq, GivensLds& L) {
+  double* Hk = ks->H + (size_t)k * (m + 1);
   if (threadIdx.x == 0) {
     const double hk1 = sqrt(hk1sq);
     if (!isfinite(hk1)) {
@@ -182,23 +193,23 @@ __device__ void givens_step(KState* ks, int k, int m, double hk1sq) {
       ks->done = 1;
     } else {
       ks->sc[k + 1] = hk1 > 0.0 ? 1.0 / hk1 : 0.0;
-      double cur = col[0];
+      double cur = L.col[0];
       for (int jj = 0; jj < k; ++jj) {
-        const double nxt = col[jj + 1];
-        col[jj] = c[jj] * cur + sgn[jj] * nxt;
-        cur = -sgn[jj] * cur + c[jj] * nxt;
+        const double nxt = L.col[jj + 1];
+        L.col[jj] = L.c[jj] * cur + L.sgn[jj] * nxt;
+        cur = -L.sgn[jj] * cur + L.c[jj] * nxt;
       }
       const double den = hypot(cur, hk1);
       if (den == 0.0) {  // w = 0 in exact arithmetic: the column adds nothing
         ks->done = 1;
-        col[k] = cur;
-        col[k + 1] = hk1;
+        L.col[k] = cur;
+        L.col[k + 1] = hk1;
       } else {
         const double cs = cur / den, sn = hk1 / den;
         ks->cs[k] = cs;
         ks->sn[k] = sn;
-        col[k] = den;
-        col[k + 1] = 0.0;
+        L.col[k] = den;
+        L.col[k + 1] = 0.0;
         const double gk = ks->g[k];
         ks->g[k + 1] = -sn * gk;
         ks->g[k] = cs * gk;
@@ -210,7 +221,14 @@ __device__ void givens_step(KState* ks, int k, int m, double hk1sq) {
     }
   }
   __syncthreads();
-  for (int q = threadIdx.x; q <= k + 1; q += blockDim.x) Hk[q] = col[q];
+  for (int q = threadIdx.x; q <= k + 1; q += blockDim.x) Hk[q] = L.col[q];
+}
+
+__device__ void givens_step(KState* ks, int k, int m, double hk1sq) {
+  __shared__ GivensLds L;
+  givens_stage(ks, k, m, L);
+  __syncthreads();
+  givens_apply(ks, k, m, hk1sq, L);
 }
 
 // ---------------------------------------------------------------------------
@@ -400,11 +418,13 @@ __device__ __forceinline__ void store16(T* __restrict__ p, int e, int N, const T
 // Arnoldi step k (classical Gram-Schmidt) as four launches:
 //   SpMV      W = A V[k]                          (unscaled basis vector)
 //   dots      per-workgroup partials of (V[q], W), q = 0..k
-//   reduce    h_{q,k} = sc_q sc_k (V[q], W); workgroup 0 also finishes step
-//             k - 1 (norm of V[k] -> Givens rotation of column k - 1)
+//   reduce    h_{q,k} = sc_q sc_k (V[q], W); workgroup k + 1 also finishes
+//             step k - 1 (norm of V[k] -> Givens rotation of column k - 1)
 //   update    V[k+1] = sc_k W - sum_q h_{q,k} sc_q V[q] and its squared norm
 // The vector kernels use 256-thread workgroups, one 16-byte access per
 // thread and vector per chunk, so that a launch fills every SIMD with waves.
+// (Projections taken inside the SpMV, slice by slice, measured slower: their
+// 4-byte-per-lane basis reads cannot stream like the 16-byte chunks here.)
 
 // Raw projections (V[q], W), q = 0..k: per-wave sums accumulate in LDS
 // (double), one partial per workgroup and row.
@@ -458,47 +478,88 @@ __global__ __launch_bounds__(kBlock) void k_gmres_dots(int N, int ldv, const T* 
   }
 }
 
-// Fixed-order sum of nb partials of one row by a whole workgroup (result in
-// every thread).  Identical inputs give bitwise identical sums in every
-// workgroup.
-__device__ double block_row_sum(const double* __restrict__ row, int nb) {
-  __shared__ double sh[kBlock / 64];
-  double s = 0.0;
-  for (int b = threadIdx.x; b < nb; b += kBlock) s += row[b];
-  s = wave_sum(s);
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) sh[wv] = s;
-  __syncthreads();
-  double t = 0.0;
+// Fixed-order sums of the nb (<= kRedBlocks) partials of up to two rows by a
+// whole workgroup; every load is issued before the first add.  Thread t adds
+// slots t, t + kBlock, ... in order, then waves and lanes combine in a fixed
+// order, so identical inputs give bitwise identical sums in every workgroup.
+template <int NR>
+__device__ void block_rows_sum(const double* const (&row)[NR], const int (&nb)[NR], double (&out)[NR]) {
+  constexpr int PER = kRedBlocks / kBlock;
+  static_assert(PER * kBlock == kRedBlocks, "partials per thread");
+  __shared__ double sh[NR][kBlock / 64];
+  double v[NR][PER];
 #pragma unroll
-  for (int w = 0; w < kBlock / 64; ++w) t += sh[w];
-  return t;
+  for (int r = 0; r < NR; ++r)
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int b = threadIdx.x + i * kBlock;
+      v[r][i] = b < nb[r] ? row[r][b] : 0.0;
+    }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) s += v[r][i];
+    s = wave_sum(s);
+    if (lane == 0) sh[r][wv] = s;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) t += sh[r][w];
+    out[r] = t;
+  }
 }
 
-// Workgroup q (q = 0..k) finalizes h_{q,k}.  For k > 0 every workgroup first
-// derives sc_k = 1 / ||V[k]|| from the norm partials of the previous update
-// (same order everywhere, so the same value), and workgroup 0 applies the
-// Givens rotation of column k - 1, which stores sc_k and may end the cycle.
-__global__ __launch_bounds__(kBlock) void k_gmres_reduce(KState* ks, const double* __restrict__ partials, int nb,
-                                                       int k, int m) {
-  if (ks->done) return;
+// Workgroup q <= k finalizes h_{q,k} = sc_q sc_k (V[q], W); for k > 0 it
+// derives sc_k = 1 / ||V[k]|| itself from the norm partials of the previous
+// update (same order everywhere, so the same value).  For k > 0 workgroup
+// k + 1 applies the Givens rotation of column k - 1 (it stores sc_k and may end
+// the cycle).
+__global__ __launch_bounds__(kBlock) void k_gmres_reduce(KState* ks, const double* __restrict__ partials,
+                                                       int nb_proj, int nb_norm, int k, int m) {
+  const double* norm_row = partials + (size_t)kNormRow * kRedBlocks;
   const int q = blockIdx.x;
-  double sck = ks->sc[0];
-  double nrm2 = 0.0;
-  if (k > 0) {
-    nrm2 = block_row_sum(partials + (size_t)kNormRow * kRedBlocks, nb);
-    const double hk = sqrt(nrm2);
-    sck = hk > 0.0 ? 1.0 / hk : 0.0;
+  if (q == k + 1) {
+    __shared__ GivensLds L;
+    if (ks->done) return;
+    givens_stage(ks, k - 1, m, L);
+    const double* const rows[1] = {norm_row};
+    const int nbs[1] = {nb_norm};
+    double nrm2[1];
+    block_rows_sum<1>(rows, nbs, nrm2);
+    givens_apply(ks, k - 1, m, nrm2[0], L);
+    return;
   }
-  const double t = block_row_sum(partials + (size_t)q * kRedBlocks, nb);
+  // no early exit here: ks->done may change during this launch (workgroup
+  // k + 1), and a column past the cycle's end is never read
+  const double scq_prev = q < k ? ks->sc[q] : 0.0;
+  double sck = ks->sc[0];
+  double t;
+  if (k > 0) {
+    const double* const rows[2] = {norm_row, partials + (size_t)q * kRedBlocks};
+    const int nbs[2] = {nb_norm, nb_proj};
+    double sums[2];
+    block_rows_sum<2>(rows, nbs, sums);
+    const double hk = sqrt(sums[0]);
+    sck = hk > 0.0 ? 1.0 / hk : 0.0;
+    t = sums[1];
+  } else {
+    const double* const rows[1] = {partials + (size_t)q * kRedBlocks};
+    const int nbs[1] = {nb_proj};
+    double sums[1];
+    block_rows_sum<1>(rows, nbs, sums);
+    t = sums[0];
+  }
   if (threadIdx.x == 0) {
-    const double scq = q == k ? sck : ks->sc[q];
+    const double scq = q == k ? sck : scq_prev;
     const double h = scq * sck * t;
     ks->H[(size_t)k * (m + 1) + q] = h;
     ks->proj[q] = h * scq;
   }
-  if (q == 0 && k > 0) givens_step(ks, k - 1, m, nrm2);
 }
 
 // V[k+1] = sc_k W - sum_q proj_q V[q] and the partials of its squared norm.
@@ -662,8 +723,8 @@ __global__ __launch_bounds__(kFinish) void k_finish(KState* ks, const double* __
   }
   if (threadIdx.x != 0) return;
   switch (act) {
-    case ACT_CYCLE:
-      if (mode != 0) cycle_start_dev(ks, mode, red[0], p1, p2);
+    case ACT_CYCLE:  // tolerances as set by the solve's first cycle_start
+      if (mode != 0) cycle_start_dev(ks, mode, red[0], ks->ctol_abs, ks->ctol_rel);
       break;
     case ACT_BICG_INIT: {
       const double rr = red[0];
@@ -1326,6 +1387,14 @@ void prof_collect(afc_handle_s* h) {
   h->ev_pending.clear();
 }
 
+namespace {
+// bytes of the SELL matrix stream: values, per-row offsets, patterns, headers
+double sell_matrix_bytes(const H* h, int value_bytes) {
+  return (double)value_bytes * (double)h->sell_slots + (h->dlt16 ? 2.0 : 4.0) * (double)h->sell_lane_deltas +
+         4.0 * (double)h->sell_pat_ints + 8.0 * (double)h->nslices + 4.0;
+}
+}  // namespace
+
 void prof_release(afc_handle_s* h) {
   prof_collect(h);
   for (auto e : h->ev_pool) (void)hipEventDestroy(e);
@@ -1373,16 +1442,19 @@ int sell_grid(const H* h, bool reduce) {
 
 SellView sell_view(const H* h) { return SellView{h->N, h->nslices, h->sl_ptr, h->sl_dl, h->sl_pat}; }
 
-void residual(H* h, const double* A, const double* b, const double* x, double* r, int mode, double tol_abs,
-              double tol_rel) {
+void residual(H* h, const double* A, const double* b, const double* x, double* r, int mode) {
   const int nb = sell_grid(h, true);
+  if (h->opt.profile) {
+    h->prof_bytes[AFC_KERNEL_RESIDUAL] += sell_matrix_bytes(h, 8) + 24.0 * h->N + 8.0 * nb;
+    h->prof_work[AFC_KERNEL_RESIDUAL] += 1;
+  }
   if (h->dlt16)
     launch(h, AFC_KERNEL_RESIDUAL, k_sell_residual<int16_t>, nb, kBlock, sell_view(h),
            static_cast<const int16_t*>(h->sl_dlt), A, b, x, r, h->partials);
   else
     launch(h, AFC_KERNEL_RESIDUAL, k_sell_residual<int32_t>, nb, kBlock, sell_view(h),
            static_cast<const int32_t*>(h->sl_dlt), A, b, x, r, h->partials);
-  finish(h, nb, 1, ACT_CYCLE, 0, 0, 0, mode, tol_abs, tol_rel);
+  finish(h, nb, 1, ACT_CYCLE, 0, 0, 0, mode);
 }
 
 void to_sell64(H* h, const double* csr, double* sell) {
@@ -1435,8 +1507,8 @@ void gmres_dots(H* h, bool fp32, int k) {
 }
 
 void gmres_reduce(H* h, bool fp32, int k, int m) {
-  launch(h, AFC_KERNEL_FINISH, k_gmres_reduce, k + 1, kBlock, h->ks, (const double*)h->partials,
-         gmres_grid(h, fp32), k, m);
+  launch(h, AFC_KERNEL_FINISH, k_gmres_reduce, k + (k > 0 ? 2 : 1), kBlock, h->ks, (const double*)h->partials,
+         gmres_grid(h, fp32), gmres_grid(h, fp32), k, m);
 }
 
 void gmres_update(H* h, bool fp32, int k) {
@@ -1524,11 +1596,19 @@ void cn_apply(H* h, const double* u, const double* u_old, const double* Rp, cons
 }
 
 void mcl_bounds(H* h, const double* u, double* umax, double* umin) {
+  if (h->opt.profile) {  // row_ptr, col, u, u^max, u^min
+    h->prof_bytes[AFC_KERNEL_MCL] += 4.0 * (h->N + 1) + 4.0 * h->nnz + 24.0 * h->N;
+    h->prof_work[AFC_KERNEL_MCL] += 1;
+  }
   AFC_DISPATCH_G_TIMED(h, AFC_KERNEL_MCL, k_mcl_bounds, row_grid(h, false), h->N, h->row_ptr, h->col, u, umax, umin);
 }
 
 void mcl_apply(H* h, const double* u, const double* umax, const double* umin, const double* F, double* b, double* r) {
   const int nb = row_grid(h, true);
+  if (h->opt.profile) {  // row_ptr, col, c_ij, c_ji, A_low; u, bounds, F, u_D, Dirichlet flags; b, r, partials
+    h->prof_bytes[AFC_KERNEL_MCL] += 4.0 * (h->N + 1) + 28.0 * h->nnz + 57.0 * h->N + 24.0 * nb;
+    h->prof_work[AFC_KERNEL_MCL] += 1;
+  }
   AFC_DISPATCH_G_TIMED(h, AFC_KERNEL_MCL, k_mcl_apply, nb, h->N, h->row_ptr, h->col, h->cc, h->ccT, h->AL_mcl, u,
                        umax, umin, F, h->is_dir, h->uD, h->opt.alpha_mode, b, r, h->ks, h->partials);
   finish(h, nb, 3, ACT_STORE);
@@ -1539,6 +1619,30 @@ void build_cn_matrix(H* h, double dt) {
                  1.0 / dt, h->A_cn, h->dinv_cn);
   to_sell64(h, h->A_cn, h->S64_cn);
   to_sell32_scaled(h, h->A_cn, h->dinv_cn, h->S32_cn);
+}
+
+void prof_gmres_cycle(afc_handle_s* h, bool fp32, int m, int kk) {
+  if (!h->opt.profile) return;
+  const double vb = fp32 ? 4.0 : 8.0;
+  const double N = (double)h->N;
+  const int kid = fp32 ? AFC_KERNEL_SPMV32 : AFC_KERNEL_SPMV64;
+  const double nbv = (double)gmres_grid(h, fp32);
+  // SpMV and projections of step k did work for k <= kk (the step after the
+  // last completed column still runs: that column's Givens comes after it)
+  const int nspmv = std::min(kk + 1, m);
+  for (int k = 0; k < nspmv; ++k) {
+    // matrix, x = V[k] (FP64: and the Jacobi scales), y
+    h->prof_bytes[kid] += sell_matrix_bytes(h, (int)vb) + vb * N * (fp32 ? 1.0 : 2.0) + vb * N;
+    h->prof_work[kid] += 1;
+    // V[0..k], W, partials
+    h->prof_bytes[AFC_KERNEL_DOTS] += vb * N * (k + 2) + 8.0 * nbv * (k + 1);
+    h->prof_work[AFC_KERNEL_DOTS] += 1;
+  }
+  // update of step k did work for k < kk
+  for (int k = 0; k < std::min(kk, m); ++k) {
+    h->prof_bytes[AFC_KERNEL_UPDATE] += vb * N * (k + 1) + 2.0 * vb * N + 8.0 * nbv;
+    h->prof_work[AFC_KERNEL_UPDATE] += 1;
+  }
 }
 
 }  // namespace afc

@@ -228,6 +228,30 @@ def test_mcl_renumbered_parity(prec):
         afc.afc_destroy(h)
 
 
+def test_kernel_work_accounting():
+    """Profiled launches: SpMV+projection launches with work = Krylov
+    iterations plus at most one per cycle (the launch after the last completed
+    column), algorithmic bytes positive."""
+    afc = _afc()
+    inst = I.config3(12)
+    h = afc.afc_create_instance(inst, _opts(precision=1, fp_tol=0.0, fp_tol_mode=1, fp_maxit=3, lin_atol=0.0,
+                                            lin_rtol=1e-10, profile=1), conv=True)
+    try:
+        u = _dev(np.zeros(inst.N))
+        st, stats = afc.afc_solve_stationary(h, u, _dev(inst.F), init_low_order=True)
+        ms, launches = afc.afc_kernel_time(h, afc.AFC_KERNEL_SPMV32)
+        by, work = afc.afc_kernel_work(h, afc.AFC_KERNEL_SPMV32)
+        ub, uwork = afc.afc_kernel_work(h, afc.AFC_KERNEL_UPDATE)
+        total_its = stats["krylov_iters"]
+        assert launches >= work > 0 and by > 0 and ms > 0
+        print("spmv launches %d with work %d, Krylov its %d" % (launches, work, total_its), flush=True)
+        assert uwork <= work
+        afc.afc_kernel_time(h, afc.AFC_KERNEL_SPMV32, reset=True)
+        assert afc.afc_kernel_work(h, afc.AFC_KERNEL_SPMV32) == (0.0, 0)
+    finally:
+        afc.afc_destroy(h)
+
+
 def test_sell_info_matches_host_layout():
     afc = _afc()
     inst = I.config3(12)
@@ -273,6 +297,32 @@ def test_nan_input_is_reported():
         assert st == afc.AFC_ENAN
     finally:
         afc.afc_destroy(h)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_graph_replay_matches_plain_launches(prec):
+    """GMRES cycles replayed from a captured HIP graph against the same cycles
+    launched one by one: bitwise equal after every call (each call replays the
+    graph several times, with the fixed point's own kernels and host syncs in
+    between)."""
+    afc = _afc()
+    inst = I.config3(10)
+    hs = [afc.afc_create_instance(inst, _opts(precision=prec, fp_tol=0.0, fp_tol_mode=1, fp_maxit=1,
+                                              lin_atol=0.0, lin_rtol=1e-10, graphs=g), conv=True)
+          for g in (1, 0)]
+    try:
+        us = [_dev(np.zeros(inst.N)) for _ in hs]
+        F = _dev(inst.F)
+        for h, u in zip(hs, us):
+            afc.afc_solve_stationary(h, u, F, init_low_order=True)
+        assert torch.equal(us[0], us[1])
+        for it in range(4):
+            sts = [afc.afc_solve_stationary(h, u, F)[1] for h, u in zip(hs, us)]
+            assert sts[0]["krylov_iters"] == sts[1]["krylov_iters"] > 0
+            assert torch.equal(us[0], us[1]), it
+    finally:
+        for h in hs:
+            afc.afc_destroy(h)
 
 
 def test_run_twice_bitwise_identical():
