@@ -110,7 +110,10 @@ def bench_batch(afc, torch, I, count, steps, nseq):
             u0[offs[k]:offs[k + 1]] = inst.u0
             Fp[offs[k]:offs[k + 1]] = inst.F
         F = torch.tensor(Fp, device="cuda:0")
-        afc.afc_batch_step_cn(b, torch.tensor(u0, device="cuda:0"), F, [1e-3] * count, 1)  # warm-up
+        # schedule from the autotuner (one trial step per candidate, not timed)
+        t0 = time.perf_counter()
+        sched, trials = afc.afc_batch_autotune(b, torch.tensor(u0, device="cuda:0"), F, [1e-3] * count, 1)
+        tune_s = time.perf_counter() - t0
         u = torch.tensor(u0, device="cuda:0")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -141,6 +144,8 @@ def bench_batch(afc, torch, I, count, steps, nseq):
         "fp_iters": int(sum(x["fp_iters"] for x in stats)), "krylov_iters": int(sum(x["krylov_iters"] for x in stats)),
         "one_at_a_time_solves_per_s": seq_rate, "one_at_a_time_sample": nseq,
         "speedup": (count / tb) / seq_rate,
+        "schedule": {"threads": sched[0], "workgroups": sched[1], "autotune_s": round(tune_s, 3),
+                     "trial_ms": [round(t, 2) for t in trials]},
     }
 
 

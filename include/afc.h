@@ -264,6 +264,30 @@ afc_status afc_batch_step_cn(afc_batch *b, double *u, const double *F, const dou
 /* Description of the last error on b (b may be NULL: last creation error). */
 const char *afc_batch_last_error(const afc_batch *b);
 
+/* Schedule of the persistent batch launch: threads per workgroup (256, 512 or
+ * 1024) and the number of workgroups pulling instances from the queue (0 =
+ * twice the compute units; never more than the instances).  Every reduction
+ * of an instance follows one fixed order whatever the schedule, so results
+ * are bitwise identical under every schedule. */
+typedef struct {
+  int32_t threads;
+  int32_t workgroups;
+} afc_batch_schedule;
+
+afc_status afc_batch_set_schedule(afc_batch *b, const afc_batch_schedule *s);
+afc_status afc_batch_get_schedule(const afc_batch *b, afc_batch_schedule *s);
+
+/* Autotuner: times trial_steps CN steps of the whole batch (from a scratch
+ * copy of u; u and the batch's results are untouched) under each candidate
+ * schedule (threads 256/512/1024 x 1, 2 or 4 workgroups per compute unit,
+ * duplicates dropped), keeps the fastest as the batch's schedule and returns
+ * it in *chosen (if not NULL).  trial_ms (if not NULL) receives up to
+ * max_trials timings in candidate order, *n_trials (if not NULL) their
+ * number.  u, F: device, packed as for afc_batch_step_cn; dt: host, one per
+ * instance.  Returns EINVAL for bad arguments, EDEVICE/ENOMEM on HIP errors. */
+afc_status afc_batch_autotune(afc_batch *b, const double *u, const double *F, const double *dt, int32_t trial_steps,
+                              afc_batch_schedule *chosen, double *trial_ms, int32_t max_trials, int32_t *n_trials);
+
 /* Release the batch (NULL is ignored). */
 void afc_batch_destroy(afc_batch *b);
 

@@ -71,6 +71,7 @@ EXPORTS = [
     "afc_batch_create", "afc_batch_offsets", "afc_batch_step_cn", "afc_batch_last_error", "afc_batch_destroy",
     "afc_footprint_bytes", "afc_server_create", "afc_server_submit", "afc_server_wait", "afc_server_last_error",
     "afc_server_destroy", "afc_get_sell_info", "afc_sell_layout", "afc_kernel_work",
+    "afc_batch_set_schedule", "afc_batch_get_schedule", "afc_batch_autotune",
 ]
 
 AFC_REQ_CN, AFC_REQ_STATIONARY = 0, 1
@@ -115,6 +116,13 @@ def lib():
         L.afc_batch_step_cn.argtypes = [c_void_p, c_void_p, c_void_p, POINTER(c_double), c_int32,
                                         POINTER(afc_stats)]
         L.afc_batch_step_cn.restype = c_int32
+        L.afc_batch_set_schedule.argtypes = [c_void_p, POINTER(afc_batch_schedule)]
+        L.afc_batch_set_schedule.restype = c_int32
+        L.afc_batch_get_schedule.argtypes = [c_void_p, POINTER(afc_batch_schedule)]
+        L.afc_batch_get_schedule.restype = c_int32
+        L.afc_batch_autotune.argtypes = [c_void_p, c_void_p, c_void_p, POINTER(c_double), c_int32,
+                                         POINTER(afc_batch_schedule), POINTER(c_double), c_int32, POINTER(c_int32)]
+        L.afc_batch_autotune.restype = c_int32
         L.afc_batch_last_error.argtypes = [c_void_p]
         L.afc_batch_last_error.restype = c_char_p
         L.afc_batch_destroy.argtypes = [c_void_p]
@@ -145,6 +153,10 @@ class afc_sell_info(ctypes.Structure):
     _fields_ = [("slices", c_int64), ("slots", c_int64), ("uniform_slices", c_int64),
                 ("lane_delta_slots", c_int64), ("pattern_ints", c_int64), ("delta_bytes", c_int32),
                 ("reserved", c_int32)]
+
+
+class afc_batch_schedule(ctypes.Structure):
+    _fields_ = [("threads", c_int32), ("workgroups", c_int32)]
 
 
 class AFCError(RuntimeError):
@@ -376,6 +388,37 @@ def afc_batch_step_cn(b, u, F, dt, steps, raise_on_error=True):
     if raise_on_error and st < 0:
         raise AFCError(st, lib().afc_batch_last_error(b).decode())
     return st, [s.as_dict() for s in stats]
+
+
+def afc_batch_set_schedule(b, threads, workgroups=0):
+    """Workgroup size (256, 512, 1024) and workgroup count (0 = automatic) of
+    the persistent launch; results do not depend on them."""
+    sch = afc_batch_schedule(int(threads), int(workgroups))
+    st = lib().afc_batch_set_schedule(b, ctypes.byref(sch))
+    if st != AFC_OK:
+        raise AFCError(st, lib().afc_batch_last_error(b).decode())
+
+
+def afc_batch_get_schedule(b):
+    sch = afc_batch_schedule()
+    st = lib().afc_batch_get_schedule(b, ctypes.byref(sch))
+    if st != AFC_OK:
+        raise AFCError(st, "afc_batch_get_schedule")
+    return sch.threads, sch.workgroups
+
+
+def afc_batch_autotune(b, u, F, dt, trial_steps=1):
+    """Time the candidate schedules on a scratch copy of u and keep the
+    fastest; returns ((threads, workgroups), [trial ms ...])."""
+    dt = np.ascontiguousarray(dt, dtype=np.float64)
+    chosen = afc_batch_schedule()
+    times = (c_double * 16)()
+    n = c_int32()
+    st = lib().afc_batch_autotune(b, u.data_ptr(), F.data_ptr(), dt.ctypes.data_as(POINTER(c_double)),
+                                  int(trial_steps), ctypes.byref(chosen), times, 16, ctypes.byref(n))
+    if st != AFC_OK:
+        raise AFCError(st, lib().afc_batch_last_error(b).decode())
+    return (chosen.threads, chosen.workgroups), [times[i] for i in range(min(n.value, 16))]
 
 
 def afc_batch_destroy(b):

@@ -129,9 +129,8 @@ void free_all(afc_handle* h) {
   if (h->host_status) (void)hipHostFree(h->host_status);
   h->host_status = nullptr;
   afc::prof_release(h);
-  if (h->cyc_exec) (void)hipGraphExecDestroy(h->cyc_exec);
-  h->cyc_exec = nullptr;
-  h->cyc_key.clear();
+  for (auto& e : h->graphs) (void)hipGraphExecDestroy(e.second);
+  h->graphs.clear();
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   h->cap_stream = nullptr;
 }
@@ -177,13 +176,18 @@ struct SolveOut {
   double res = 0.0;
 };
 
-// Capture the launches issued by `issue` on the handle's private capture
-// stream into h->cyc_exec (replacing an older graph).
+// The graph of the launches that `issue` makes on the handle's stream, keyed
+// by `key`: replayed from the handle's cache, or captured on the handle's
+// private capture stream (at most kGraphCache kept, the oldest dropped).
+constexpr size_t kGraphCache = 8;
+
 template <typename F>
-void capture_cycle(afc_handle* h, const std::vector<const void*>& key, F&& issue) {
-  if (h->cyc_exec) {
-    (void)hipGraphExecDestroy(h->cyc_exec);
-    h->cyc_exec = nullptr;
+hipGraphExec_t cached_graph(afc_handle* h, const std::vector<const void*>& key, F&& issue) {
+  for (auto& e : h->graphs)
+    if (e.first == key) return e.second;
+  if (h->graphs.size() >= kGraphCache) {
+    (void)hipGraphExecDestroy(h->graphs.front().second);
+    h->graphs.erase(h->graphs.begin());
   }
   if (!h->cap_stream) HIP_OK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
   hipStream_t user = h->stream;
@@ -196,11 +200,15 @@ void capture_cycle(afc_handle* h, const std::vector<const void*>& key, F&& issue
   }
   h->stream = user;
   HIP_OK(e);
-  e = hipGraphInstantiate(&h->cyc_exec, g, nullptr, nullptr, 0);
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   HIP_OK(e);
-  h->cyc_key = key;
+  h->graphs.emplace_back(key, exec);
+  return exec;
 }
+
+const void* key_int(int64_t v) { return reinterpret_cast<const void*>((intptr_t)v); }
 
 // GMRES(m), right Jacobi.  x: in x0, out solution; r: b - A x0 on entry, with
 // ||r||^2 in ks->red[red_idx].  FP64 mode runs the Arnoldi process in FP64;
@@ -252,18 +260,15 @@ SolveOut solve_gmres(afc_handle* h, const SysMat& S, const double* b, double* x,
       afc::residual(h, S.S64, b, x, h->V64, 1);
     }
   };
-  const bool graph = h->opt.graphs && !h->opt.profile;
-  if (graph) {
-    const std::vector<const void*> key = {
-        S.S32, S.S64, S.dinv, b, x, r, h->V32, h->V64, h->w[0], h->partials, h->ks,
-        reinterpret_cast<const void*>((intptr_t)m), reinterpret_cast<const void*>((intptr_t)mixed),
-        reinterpret_cast<const void*>((intptr_t)h->ldv)};
-    if (!h->cyc_exec || h->cyc_key != key) capture_cycle(h, key, cycle);
-  }
+  hipGraphExec_t graph = nullptr;
+  if (h->opt.graphs && !h->opt.profile)
+    graph = cached_graph(h, {key_int(1), S.S32, S.S64, S.dinv, b, x, r, h->V32, h->V64, h->w[0], key_int(m),
+                             key_int(mixed), key_int(h->ldv)},
+                         cycle);
   int cycle_it0 = it0;
   while (res > tol) {
     if (graph)
-      HIP_OK(hipGraphLaunch(h->cyc_exec, h->stream));
+      HIP_OK(hipGraphLaunch(graph, h->stream));
     else
       cycle();
     o.sweeps += 1;
@@ -305,7 +310,13 @@ SolveOut solve_bicgstab(afc_handle* h, const SysMat& S, const double* b, double*
     int chunk = 2;
     while (!h->host_status->done && h->host_status->iters - it0 < h->opt.lin_maxit) {
       const int n = std::min<int>(chunk, h->opt.lin_maxit - (h->host_status->iters - it0));
-      for (int c = 0; c < n; ++c) afc::bicg_iter(h, S.A, S.dinv, v);
+      auto iters = [&]() {
+        for (int c = 0; c < n; ++c) afc::bicg_iter(h, S.A, S.dinv, v);
+      };
+      if (h->opt.graphs && !h->opt.profile)
+        HIP_OK(hipGraphLaunch(cached_graph(h, {key_int(2), S.A, S.dinv, x, r, key_int(n), key_int(h->G)}, iters), h->stream));
+      else
+        iters();
       sync_status(h);
       chunk = std::min(chunk * 2, 16);
     }
@@ -1072,6 +1083,22 @@ afc_status afc_batch_offsets(const afc_batch* b, int64_t* offsets) {
 
 static int severity(int s) { return s < 0 ? 100 - s : s; }
 
+// per-call instance data (dt) and the work queue, in stream order
+void batch_prepare(afc_handle* h, afc_batch* b, const double* dt) {
+  for (int q = 0; q < b->count; ++q) b->host_insts[q].dt = dt[q];
+  HIP_OK(hipMemcpyAsync(b->insts, b->host_insts.data(), sizeof(afc::BInst) * b->count, hipMemcpyHostToDevice,
+                        b->stream));
+  HIP_OK(hipMemsetAsync(b->queue, 0, sizeof(int), b->stream));
+}
+
+// workgroups of the persistent launch: `want`, or twice the compute units;
+// never more than the instances
+int batch_grid(afc_handle* h, const afc_batch* b, int want) {
+  int cus = 0;
+  HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device));
+  return std::max(1, std::min(b->count, want > 0 ? want : 2 * cus));
+}
+
 afc_status afc_batch_step_cn(afc_batch* b, double* u, const double* F, const double* dt, int32_t steps,
                              afc_stats* stats) {
   if (!b) return AFC_EINVAL;
@@ -1088,14 +1115,8 @@ afc_status afc_batch_step_cn(afc_batch* b, double* u, const double* F, const dou
   afc_handle* h = nullptr;
   try {
     HIP_OK(hipSetDevice(b->device));
-    for (int q = 0; q < b->count; ++q) b->host_insts[q].dt = dt[q];
-    HIP_OK(hipMemcpyAsync(b->insts, b->host_insts.data(), sizeof(afc::BInst) * b->count, hipMemcpyHostToDevice,
-                          b->stream));
-    HIP_OK(hipMemsetAsync(b->queue, 0, sizeof(int), b->stream));
-    int cus = 0;
-    HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device));
-    const int grid = std::max(1, std::min(b->count, 2 * cus));
-    afc::batch_launch(b, u, F, steps, grid);
+    batch_prepare(h, b, dt);
+    afc::batch_launch(b, u, F, steps, b->threads, batch_grid(h, b, b->workgroups));
     HIP_OK(hipGetLastError());
     std::vector<afc::BStat> hs(b->count);
     HIP_OK(hipMemcpyAsync(hs.data(), b->stats_d, sizeof(afc::BStat) * b->count, hipMemcpyDeviceToHost, b->stream));
@@ -1117,6 +1138,96 @@ afc_status afc_batch_step_cn(afc_batch* b, double* u, const double* F, const dou
     return (afc_status)worst;
   } catch (const Fail& f) {
     b->last_error = f.msg;
+    return f.st;
+  }
+}
+
+afc_status afc_batch_set_schedule(afc_batch* b, const afc_batch_schedule* sch) {
+  if (!b || !sch) return AFC_EINVAL;
+  if ((sch->threads != 256 && sch->threads != 512 && sch->threads != 1024) || sch->workgroups < 0) {
+    b->last_error = "schedule: threads must be 256, 512 or 1024 and workgroups >= 0";
+    return AFC_EINVAL;
+  }
+  b->threads = sch->threads;
+  b->workgroups = sch->workgroups;
+  return AFC_OK;
+}
+
+afc_status afc_batch_get_schedule(const afc_batch* b, afc_batch_schedule* sch) {
+  if (!b || !sch) return AFC_EINVAL;
+  sch->threads = b->threads;
+  sch->workgroups = b->workgroups;
+  return AFC_OK;
+}
+
+afc_status afc_batch_autotune(afc_batch* b, const double* u, const double* F, const double* dt, int32_t trial_steps,
+                              afc_batch_schedule* chosen, double* trial_ms, int32_t max_trials,
+                              int32_t* n_trials) {
+  if (!b) return AFC_EINVAL;
+  b->last_error.clear();
+  if (!u || !F || !dt || trial_steps < 1 || (trial_ms && max_trials < 0)) {
+    b->last_error = "afc_batch_autotune: need device u, F, host dt and trial_steps >= 1";
+    return AFC_EINVAL;
+  }
+  for (int q = 0; q < b->count; ++q)
+    if (!(dt[q] > 0) || !std::isfinite(dt[q])) {
+      b->last_error = "dt must be positive for every instance";
+      return AFC_EINVAL;
+    }
+  afc_handle* h = nullptr;
+  double* scratch = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  try {
+    HIP_OK(hipSetDevice(b->device));
+    int cus = 0;
+    HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device));
+    HIP_OK(hipMalloc(&scratch, sizeof(double) * std::max<int64_t>(1, b->total_nodes)));
+    HIP_OK(hipEventCreate(&e0));
+    HIP_OK(hipEventCreate(&e1));
+    std::vector<afc_batch_schedule> cand;
+    for (int t : {256, 512, 1024})
+      for (int mult : {1, 2, 4}) {
+        const int g = batch_grid(h, b, mult * cus);
+        bool dup = false;
+        for (auto& c : cand) dup = dup || (c.threads == t && c.workgroups == g);
+        if (!dup) cand.push_back({t, g});
+      }
+    double best = 0.0;
+    afc_batch_schedule pick = {b->threads, b->workgroups};
+    int nt = 0;
+    for (const auto& c : cand) {
+      HIP_OK(hipMemcpyAsync(scratch, u, sizeof(double) * b->total_nodes, hipMemcpyDeviceToDevice, b->stream));
+      batch_prepare(h, b, dt);
+      HIP_OK(hipEventRecord(e0, b->stream));
+      afc::batch_launch(b, scratch, F, trial_steps, c.threads, c.workgroups);
+      HIP_OK(hipGetLastError());
+      HIP_OK(hipEventRecord(e1, b->stream));
+      HIP_OK(hipEventSynchronize(e1));
+      float ms = 0.0f;
+      HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+      if (trial_ms && nt < max_trials) trial_ms[nt] = ms;
+      ++nt;
+      if (nt == 1 || ms < best) {
+        best = ms;
+        pick = c;
+      }
+    }
+    b->threads = pick.threads;
+    b->workgroups = pick.workgroups;
+    if (chosen) *chosen = pick;
+    if (n_trials) *n_trials = nt;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(scratch);
+    return AFC_OK;
+  } catch (const Fail& f) {
+    b->last_error = f.msg;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (scratch) {
+      (void)hipStreamSynchronize(b->stream);
+      (void)hipFree(scratch);
+    }
     return f.st;
   }
 }

@@ -28,28 +28,46 @@
 namespace afc {
 namespace {
 
-constexpr int kBatchThreads = 1024;
+// Reductions follow one canonical order whatever the workgroup size: rows are
+// visited as if by kVW waves (virtual wave v takes slices v, v + kVW, ...;
+// lane l the row 64 s + l), each virtual wave accumulates per lane in slice
+// order, and the kVW wave totals are added in virtual-wave order.  A workgroup
+// of NT threads runs its NT/64 real waves over virtual waves w, w + NT/64, ...
+// with one accumulator set per virtual wave, so every schedule (workgroup size,
+// number of workgroups) gives bitwise identical results.
+constexpr int kVW = 16;
+
+template <int NT>
+struct Sched {
+  static constexpr int NW = NT / 64;
+  static constexpr int PER = kVW / NW;  // virtual waves per real wave
+  static_assert(NW * PER == kVW, "workgroup size must divide 16 waves");
+};
 
 enum BatchWork { BW_UOLD = 0, BW_UT, BW_G, BW_QP, BW_QM, BW_RP, BW_RM, BW_B, BW_R, BW_X, BW_RHAT, BW_P, BW_V, BW_S,
                  BW_T, BW_COUNT };
 
-// Sum of NV values over the workgroup; every thread receives the totals.
+// Totals of NV sums accumulated per virtual wave (acc[c] belongs to virtual
+// wave w + c NW); every thread receives them.
 template <int NT, int NV>
-__device__ void wg_sum(double (&v)[NV]) {
-  __shared__ double sh[NV][NT / 64];
+__device__ void wg_sum(const double (&acc)[Sched<NT>::PER][NV], double (&out)[NV]) {
+  constexpr int NW = Sched<NT>::NW, PER = Sched<NT>::PER;
+  __shared__ double sh[NV][kVW];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-  for (int q = 0; q < NV; ++q) {
-    const double s = wave_sum(v[q]);
-    if (lane == 0) sh[q][wv] = s;
-  }
+  for (int c = 0; c < PER; ++c)
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const double s = wave_sum(acc[c][q]);
+      if (lane == 0) sh[q][wv + c * NW] = s;
+    }
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < NV; ++q) {
     double t = 0.0;
 #pragma unroll
-    for (int w = 0; w < NT / 64; ++w) t += sh[q][w];
-    v[q] = t;
+    for (int v = 0; v < kVW; ++v) t += sh[q][v];
+    out[q] = t;
   }
   __syncthreads();
 }
@@ -66,12 +84,14 @@ struct InstView {
   const double* F;
 };
 
-// Row loops run in SELL order: wave w takes slices w, w + NT/64, ...; lane l
-// owns row 64 s + l and walks its slots p = 0..L-1 (p = 0 is the diagonal;
-// padding slots point at the row itself with zero values).
-#define AFC_SELL_ROWS(I, NT)                                              \
-  for (int s_ = (int)(threadIdx.x >> 6); s_ < (I).nsl; s_ += (NT) / 64)   \
-    if (const int i = s_ * 64 + (int)(threadIdx.x & 63); i < (I).N)
+// Row loops in the canonical order: C is the index of the running virtual
+// wave among this real wave's (accumulator set acc[C]); lane l owns row
+// 64 s + l and walks its slots p = 0..L-1 (p = 0 is the diagonal; padding
+// slots point at the row itself with zero values).
+#define AFC_ROWS(I, NT, C)                                                                          \
+  _Pragma("unroll") for (int C = 0; C < Sched<NT>::PER; ++C)                                        \
+    for (int s_ = (int)(threadIdx.x >> 6) + C * Sched<NT>::NW; s_ < (I).nsl; s_ += kVW)              \
+      if (const int i = s_ * 64 + (int)(threadIdx.x & 63); i < (I).N)
 
 struct RowSpan {
   int base, L;
@@ -82,11 +102,11 @@ __device__ __forceinline__ RowSpan row_span(const InstView& I, int i) {
   return {b + (i & 63), (I.slp[s + 1] - b) >> 6};
 }
 
-// y_i = sum_j A_ij dinv_j x_j ; returns this thread's share of sum_i z_i y_i
+// y_i = sum_j A_ij dinv_j x_j; returns sum_i z_i y_i
 template <int NT>
 __device__ double wg_spmv_prec(const InstView& I, const double* A, const double* x, double* y, const double* z) {
-  double acc = 0.0;
-  AFC_SELL_ROWS(I, NT) {
+  double acc[Sched<NT>::PER][1] = {};
+  AFC_ROWS(I, NT, c) {
     const RowSpan rs = row_span(I, i);
     double sacc = 0.0;
 #pragma unroll 4
@@ -96,16 +116,18 @@ __device__ double wg_spmv_prec(const InstView& I, const double* A, const double*
       sacc += A[k] * (I.dinv[j] * x[j]);
     }
     y[i] = sacc;
-    acc += z[i] * sacc;
+    acc[c][0] += z[i] * sacc;
   }
-  return acc;
+  double out[1];
+  wg_sum<NT, 1>(acc, out);
+  return out[0];
 }
 
-// r = b - A x over the instance, returns this thread's share of ||r||^2
+// r = b - A x over the instance; returns ||r||^2
 template <int NT>
 __device__ double wg_residual(const InstView& I, const double* A, const double* b, const double* x, double* r) {
-  double acc = 0.0;
-  AFC_SELL_ROWS(I, NT) {
+  double acc[Sched<NT>::PER][1] = {};
+  AFC_ROWS(I, NT, c) {
     const RowSpan rs = row_span(I, i);
     double sacc = 0.0;
 #pragma unroll 4
@@ -115,9 +137,11 @@ __device__ double wg_residual(const InstView& I, const double* A, const double* 
     }
     const double ri = b[i] - sacc;
     r[i] = ri;
-    acc += ri * ri;
+    acc[c][0] += ri * ri;
   }
-  return acc;
+  double out[1];
+  wg_sum<NT, 1>(acc, out);
+  return out[0];
 }
 
 // BiCGStab (van der Vorst, right Jacobi) on A_cn x = b inside one workgroup.
@@ -154,19 +178,19 @@ __device__ int wg_bicgstab(const InstView& I, const double* b, double* x, double
     }
     while (!converged && it < maxit) {
       double q1[1] = {wg_spmv_prec<NT>(I, A, p, v, rhat)};
-      wg_sum<NT, 1>(q1);
       if (q1[0] == 0.0 || !isfinite(q1[0])) {
         breakdown = true;
         break;
       }
       alpha = rho / q1[0];
-      double q2[1] = {0.0};
-      for (int i = threadIdx.x; i < N; i += NT) {
+      double a2[Sched<NT>::PER][1] = {};
+      AFC_ROWS(I, NT, c) {
         const double si = r[i] - alpha * v[i];
         s[i] = si;
-        q2[0] += si * si;
+        a2[c][0] += si * si;
       }
-      wg_sum<NT, 1>(q2);
+      double q2[1];
+      wg_sum<NT, 1>(a2, q2);
       ++it;
       if (sqrt(q2[0]) <= tol) {
         for (int i = threadIdx.x; i < N; i += NT) {
@@ -177,8 +201,8 @@ __device__ int wg_bicgstab(const InstView& I, const double* b, double* x, double
         converged = true;
         break;
       }
-      double q3[2] = {0.0, 0.0};
-      AFC_SELL_ROWS(I, NT) {
+      double a3[Sched<NT>::PER][2] = {};
+      AFC_ROWS(I, NT, c) {
         const RowSpan rs = row_span(I, i);
         double a = 0.0;
 #pragma unroll 4
@@ -188,21 +212,23 @@ __device__ int wg_bicgstab(const InstView& I, const double* b, double* x, double
           a += A[k] * (I.dinv[j] * s[j]);
         }
         t[i] = a;
-        q3[0] += a * s[i];
-        q3[1] += a * a;
+        a3[c][0] += a * s[i];
+        a3[c][1] += a * a;
       }
-      wg_sum<NT, 2>(q3);
+      double q3[2];
+      wg_sum<NT, 2>(a3, q3);
       omega = q3[1] != 0.0 ? q3[0] / q3[1] : 0.0;
-      double q4[2] = {0.0, 0.0};
-      for (int i = threadIdx.x; i < N; i += NT) {
+      double a4[Sched<NT>::PER][2] = {};
+      AFC_ROWS(I, NT, c) {
         const double di = I.dinv[i];
         x[i] += alpha * (di * p[i]) + omega * (di * s[i]);
         const double ri = s[i] - omega * t[i];
         r[i] = ri;
-        q4[0] += rhat[i] * ri;
-        q4[1] += ri * ri;
+        a4[c][0] += rhat[i] * ri;
+        a4[c][1] += ri * ri;
       }
-      wg_sum<NT, 2>(q4);
+      double q4[2];
+      wg_sum<NT, 2>(a4, q4);
       cur = sqrt(q4[1]);
       if (!isfinite(cur)) {
         *status = AFC_ENAN;
@@ -224,7 +250,6 @@ __device__ int wg_bicgstab(const InstView& I, const double* b, double* x, double
     }
     // confirm on the true residual
     double q5[1] = {wg_residual<NT>(I, A, b, x, r)};
-    wg_sum<NT, 1>(q5);
     *res = sqrt(q5[0]);
     if (!isfinite(*res)) {
       *status = AFC_ENAN;
@@ -276,7 +301,7 @@ __device__ void run_instance(const BInst& in, const BatchDev& D, const BatchOpts
   double* r = I.w[BW_R];
 
   // CN matrix M_L/dt + A_low/2 with Dirichlet identity rows, and its inverse diagonal
-  AFC_SELL_ROWS(I, NT) {
+  AFC_ROWS(I, NT, c_) {
     const RowSpan rs = row_span(I, i);
     const bool dir = I.isd[i];
     for (int p = 0; p < rs.L; ++p) {
@@ -297,7 +322,7 @@ __device__ void run_instance(const BInst& in, const BatchDev& D, const BatchOpts
   double res0 = 0.0, res_last = 0.0, lin_res = 0.0;
   for (int step = 0; step < steps && status >= 0; ++step) {
     // predictor of eq. (14) and the right-hand side of eq. (11)
-    AFC_SELL_ROWS(I, NT) {
+    AFC_ROWS(I, NT, c_) {
       const double ui = u[i];
       uo[i] = ui;
       if (I.isd[i]) {
@@ -318,7 +343,7 @@ __device__ void run_instance(const BInst& in, const BatchDev& D, const BatchOpts
     }
     __syncthreads();
     // Q+- from the predictor (Sec. 2.1.3 step 2)
-    AFC_SELL_ROWS(I, NT) {
+    AFC_ROWS(I, NT, c_) {
       const RowSpan rs = row_span(I, i);
       const double uti = ut[i];
       double qp = 0.0, qm = 0.0;
@@ -333,7 +358,7 @@ __device__ void run_instance(const BInst& in, const BatchDev& D, const BatchOpts
     }
     __syncthreads();
     // Dirichlet values into u (after every predictor read of u)
-    AFC_SELL_ROWS(I, NT) {
+    AFC_ROWS(I, NT, c_) {
       if (I.isd[i]) u[i] = I.uD[i];
     }
     __syncthreads();
@@ -342,7 +367,7 @@ __device__ void run_instance(const BInst& in, const BatchDev& D, const BatchOpts
     int nu = 0;
     while (true) {
       // P+-, R+- of the prelimited CN fluxes (eqs. (12), (13))
-      AFC_SELL_ROWS(I, NT) {
+      AFC_ROWS(I, NT, c_) {
         if (I.isd[i]) {
           Rp[i] = Rm[i] = 1.0;
           continue;
@@ -363,14 +388,14 @@ __device__ void run_instance(const BInst& in, const BatchDev& D, const BatchOpts
       }
       __syncthreads();
       // b = g + F*, r = b - A_cn u ; R^2 (free rows), ||b||^2, ||r||^2
-      double red[3] = {0.0, 0.0, 0.0};
-      AFC_SELL_ROWS(I, NT) {
+      double acc[Sched<NT>::PER][3] = {};
+      AFC_ROWS(I, NT, c) {
         if (I.isd[i]) {
           const double bi = I.uD[i], ri = I.uD[i] - u[i];
           b[i] = bi;
           r[i] = ri;
-          red[1] += bi * bi;
-          red[2] += ri * ri;
+          acc[c][1] += bi * bi;
+          acc[c][2] += ri * ri;
           continue;
         }
         const RowSpan rs = row_span(I, i);
@@ -392,11 +417,12 @@ __device__ void run_instance(const BInst& in, const BatchDev& D, const BatchOpts
         const double bi = g[i] + fs, ri = bi - au;
         b[i] = bi;
         r[i] = ri;
-        red[0] += ri * ri;
-        red[1] += bi * bi;
-        red[2] += ri * ri;
+        acc[c][0] += ri * ri;
+        acc[c][1] += bi * bi;
+        acc[c][2] += ri * ri;
       }
-      wg_sum<NT, 3>(red);
+      double red[3];
+      wg_sum<NT, 3>(acc, red);
       const double R = sqrt(red[0]), bn = sqrt(red[1]);
       if (!isfinite(R) || !isfinite(bn)) {
         status = AFC_ENAN;
@@ -465,9 +491,21 @@ __global__ __launch_bounds__(NT) void k_batch_cn(const BInst* __restrict__ insts
 
 }  // namespace
 
-void batch_launch(afc_batch_s* b, double* u, const double* F, int steps, int grid) {
-  k_batch_cn<kBatchThreads><<<grid, kBatchThreads, 0, b->stream>>>(b->insts, b->order, b->count, b->queue, steps,
-                                                                   b->dev, b->bopt, u, F, b->stats_d);
+void batch_launch(afc_batch_s* b, double* u, const double* F, int steps, int threads, int grid) {
+  switch (threads) {
+    case 256:
+      k_batch_cn<256><<<grid, 256, 0, b->stream>>>(b->insts, b->order, b->count, b->queue, steps, b->dev, b->bopt, u,
+                                                    F, b->stats_d);
+      break;
+    case 512:
+      k_batch_cn<512><<<grid, 512, 0, b->stream>>>(b->insts, b->order, b->count, b->queue, steps, b->dev, b->bopt, u,
+                                                    F, b->stats_d);
+      break;
+    default:
+      k_batch_cn<1024><<<grid, 1024, 0, b->stream>>>(b->insts, b->order, b->count, b->queue, steps, b->dev, b->bopt,
+                                                      u, F, b->stats_d);
+      break;
+  }
 }
 
 int batch_work_vectors() { return BW_COUNT; }

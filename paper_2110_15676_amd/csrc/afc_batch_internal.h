@@ -71,6 +71,8 @@ struct afc_batch_s {
   afc_options opt{};
   afc::BatchOpts bopt{};
   hipStream_t stream = nullptr;
+  int threads = 1024;   // schedule of the persistent launch (results do not depend on it)
+  int workgroups = 0;   // 0: twice the compute units, at most count
   std::string last_error;
   std::vector<afc::BInst> host_insts;
   std::vector<int> host_order;
@@ -88,5 +90,6 @@ struct afc_batch_s {
 };
 
 namespace afc {
-void batch_launch(afc_batch_s* b, double* u, const double* F, int steps, int grid);
+// one persistent launch of `grid` workgroups of `threads` (256, 512 or 1024)
+void batch_launch(afc_batch_s* b, double* u, const double* F, int steps, int threads, int grid);
 }

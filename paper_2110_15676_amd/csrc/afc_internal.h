@@ -112,11 +112,11 @@ struct afc_handle_s {
   afc::KState* ks = nullptr;
   afc::KState* host_status = nullptr;  // pinned copy of the KState head
 
-  // GMRES cycle replayed as a HIP graph (options.graphs): captured on a
-  // private stream, valid while every pointer and size it baked in is unchanged
+  // launch sequences replayed as HIP graphs (options.graphs): a GMRES cycle,
+  // a chunk of BiCGStab iterations.  Captured on a private stream, each keyed
+  // by every pointer and size it baked in; a few are kept (oldest dropped).
   hipStream_t cap_stream = nullptr;
-  hipGraphExec_t cyc_exec = nullptr;
-  std::vector<const void*> cyc_key;
+  std::vector<std::pair<std::vector<const void*>, hipGraphExec_t>> graphs;
 
   // optional per-kernel timing (options.profile)
   struct ProfEv {

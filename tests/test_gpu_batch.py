@@ -132,3 +132,60 @@ def test_batch_rejects_gmres_options():
     with pytest.raises(afc.AFCError) as e:
         afc.afc_batch_create(insts, o)
     assert e.value.status == afc.AFC_EINVAL
+
+
+def test_batch_results_identical_under_every_schedule():
+    """Workgroup size and workgroup count change only the speed: every
+    instance ends bitwise the same under each schedule, and alone (with a
+    different schedule) as in the mix."""
+    afc = _afc()
+    insts = _mixed_instances(12, 12)
+    opts = _opts(fp_tol=1e-12, fp_maxit=50, lin_atol=1e-12)
+    b = afc.afc_batch_create(insts, opts)
+    results = {}
+    try:
+        offs = afc.afc_batch_offsets(b, len(insts))
+        u0 = torch.tensor(_pack(insts, offs, "u0"), device="cuda:0")
+        F = torch.tensor(_pack(insts, offs, "F"), device="cuda:0")
+        for threads in (256, 512, 1024):
+            for wgs in (0, 1, 5):
+                print("batch schedule threads=%d workgroups=%d" % (threads, wgs), flush=True)
+                afc.afc_batch_set_schedule(b, threads, wgs)
+                assert afc.afc_batch_get_schedule(b) == (threads, wgs)
+                u = u0.clone()
+                st, _ = afc.afc_batch_step_cn(b, u, F, [1e-3] * len(insts), 3)
+                assert st >= 0
+                results[(threads, wgs)] = u.cpu().numpy()
+    finally:
+        afc.afc_batch_destroy(b)
+    ref = results[(1024, 0)]
+    for key, x in results.items():
+        assert np.array_equal(x, ref), key
+    k = 7
+    b1 = afc.afc_batch_create([insts[k]], opts)
+    try:
+        afc.afc_batch_set_schedule(b1, 256, 1)
+        u1 = torch.tensor(insts[k].u0, device="cuda:0")
+        afc.afc_batch_step_cn(b1, u1, torch.tensor(insts[k].F, device="cuda:0"), [1e-3], 3)
+        assert np.array_equal(u1.cpu().numpy(), ref[offs[k]:offs[k + 1]])
+    finally:
+        afc.afc_batch_destroy(b1)
+
+
+def test_batch_autotune_keeps_inputs_and_picks_a_candidate():
+    afc = _afc()
+    insts = _mixed_instances(20, 10)
+    b = afc.afc_batch_create(insts, _opts(fp_tol=1e-12, fp_maxit=50, lin_atol=1e-12))
+    try:
+        offs = afc.afc_batch_offsets(b, len(insts))
+        u = torch.tensor(_pack(insts, offs, "u0"), device="cuda:0")
+        F = torch.tensor(_pack(insts, offs, "F"), device="cuda:0")
+        before = u.clone()
+        chosen, times = afc.afc_batch_autotune(b, u, F, [1e-3] * len(insts), trial_steps=1)
+        print("autotune chose", chosen, "trial ms", [round(t, 3) for t in times], flush=True)
+        assert torch.equal(u, before)
+        assert chosen[0] in (256, 512, 1024) and 1 <= chosen[1] <= len(insts)
+        assert afc.afc_batch_get_schedule(b) == chosen
+        assert len(times) >= 3 and all(t > 0 for t in times)
+    finally:
+        afc.afc_batch_destroy(b)

@@ -325,6 +325,26 @@ def test_graph_replay_matches_plain_launches(prec):
             afc.afc_destroy(h)
 
 
+def test_graph_replay_bicgstab_cn_steps():
+    """CN-FCT steps with BiCGStab: chunks replayed from captured graphs against
+    plain launches, bitwise equal after every step."""
+    afc = _afc()
+    inst = I.config1()
+    dt = inst.params["dt"]
+    hs = [afc.afc_create_instance(inst, _opts(krylov=afc.AFC_KRYLOV_BICGSTAB, graphs=g, **CN_PARITY), conv=False)
+          for g in (1, 0)]
+    try:
+        us = [_dev(inst.u0) for _ in hs]
+        F = _dev(inst.F)
+        for step in range(6):
+            sts = [afc.afc_step_cn(h, u, F, F, dt)[1] for h, u in zip(hs, us)]
+            assert sts[0]["krylov_iters"] == sts[1]["krylov_iters"] > 0
+            assert torch.equal(us[0], us[1]), step
+    finally:
+        for h in hs:
+            afc.afc_destroy(h)
+
+
 def test_run_twice_bitwise_identical():
     afc = _afc()
     inst = I.config3(10)
