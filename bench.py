@@ -149,6 +149,38 @@ def bench_batch(afc, torch, I, count, steps, nseq):
     }
 
 
+def bench_cn(afc, torch, I, n, steps):
+    """Nonlinear Zal+CN (fixed point) against linear Zal+CN (one solve per
+    step) on the Q1 n^3 rotating-transport problem, BiCGStab-Jacobi FP64."""
+    inst = I.config2(n)
+    dt = 4.0 * inst.params["dt"]
+    o = afc.afc_default_options(krylov=afc.AFC_KRYLOV_BICGSTAB, fp_tol=1e-8, fp_tol_mode=afc.AFC_TOL_REL,
+                                fp_maxit=50, lin_atol=0.0, lin_rtol=1e-10)
+    o.stream = torch.cuda.current_stream().cuda_stream
+    out = {"workload": "Q1 %d^3 (%d nodes), rotating b, eps 1e-8, dt = 4 x CFL-0.2 step, %d CN steps, "
+                       "BiCGStab-Jacobi FP64 to 1e-10 ||b||, fixed point to 1e-8 R0" % (n, inst.N, steps)}
+    for name, step in (("nonlinear", afc.afc_step_cn), ("linear", afc.afc_step_cn_linear)):
+        h = afc.afc_create_instance(inst, o, conv=False)
+        try:
+            u = torch.tensor(inst.u0, device="cuda:0")
+            F = torch.tensor(inst.F, device="cuda:0")
+            step(h, u.clone(), F, F, dt)  # warm-up (matrix build, graphs)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fp = kr = 0
+            for _ in range(steps):
+                _, st = step(h, u, F, F, dt)
+                fp += st["fp_iters"]
+                kr += st["krylov_iters"]
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+        finally:
+            afc.afc_destroy(h)
+        out[name] = {"ms_per_step": 1e3 * el / steps, "dof_steps_per_s": inst.N * steps / el,
+                     "fp_iters_per_step": fp / steps, "krylov_per_step": kr / steps}
+    return out
+
+
 def bench_serve(afc, torch, I, count, slots):
     """Poisson arrivals (200/s) of mixed CN-FCT / stationary-MCL Q1 requests."""
     import threading
@@ -322,6 +354,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-cn", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--traffic-probe", action="store_true",
@@ -446,6 +479,10 @@ def main():
     if not args.no_batch:
         print("bench: batched CN-FCT", file=sys.stderr, flush=True)
         batch = bench_batch(afc, torch, I, 256, 20, 8)
+    cn = None
+    if not args.no_cn:
+        print("bench: CN (nonlinear vs linear Zal+CN)", file=sys.stderr, flush=True)
+        cn = bench_cn(afc, torch, I, 64, 10)
     serve = None
     if not args.no_serve:
         print("bench: serving", file=sys.stderr, flush=True)
@@ -482,6 +519,7 @@ def main():
         "nonlinear_residual": {"first": s["res0"], "last": s["res"]},
         "fp64": fp64,
         "batch": batch,
+        "cn": cn,
         "serving": serve,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -176,6 +176,17 @@ afc_status afc_step_ssprk3(afc_handle *h, double *u, const double *F, double dt,
 afc_status afc_step_cn(afc_handle *h, double *u, const double *F_old, const double *F_new, double dt,
                        afc_stats *stats);
 
+/* One linear Zal+CN step (Sec. 2.1.1, the linearized variant of eq. (11)):
+ * u^n in the fluxes of eq. (12) is replaced by u* = 2 u~ - u^{n-1}, with u~
+ * the predictor of eq. (14) and u_D at Dirichlet nodes.  The fluxes
+ * (prelimited by eq. (13)), Zalesak's limiter and F* are then evaluated once,
+ * and eq. (11) is one linear system, solved from x0 = u* with the handle's
+ * Krylov options.  Same arguments and ownership as afc_step_cn; stats report
+ * fp_iters = 1 and res0 = res = the residual of eq. (11) at u*.  Returns the
+ * linear solver's status (ENOCONV, EBREAKDOWN, ENAN) or EINVAL. */
+afc_status afc_step_cn_linear(afc_handle *h, double *u, const double *F_old, const double *F_new, double dt,
+                              afc_stats *stats);
+
 /* Stationary MCL scheme (Sec. 3.1): fixed-point iteration of Sec. 4 for
  * A_low u = F + F*(u), where F* sums the fluxes r^ss_ij = d_ij (u_j - u_i)
  * of eq. (25) limited by eq. (22).  u: in initial guess, out solution

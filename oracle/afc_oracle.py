@@ -515,6 +515,44 @@ def cn_fct_step(P: AFCProblem, u_old, F_old, F_new, dt, *, alpha_mode="limited",
     return u, st
 
 
+def cn_linear_step(P: AFCProblem, u_old, F_old, F_new, dt, *, alpha_mode="limited", prelimit=2.0,
+                   lin="bicgstab", lin_atol=1e-12, lin_rtol=0.0, lin_maxit=10000, restart=30):
+    """Linear Zal+CN (Sec. 2.1.1, the linearized variant): u^n in the fluxes of
+    eq. (12) is approximated by 2 u~ - u^{n-1}, with u~ the predictor of
+    eq. (14) (u_D at Dirichlet nodes), so the correction F* is known before the
+    solve and eq. (11) becomes one linear system, solved from that same
+    approximation.  Returns (u^n, stats); stats.iters = 1 solve."""
+    d = artificial_diffusion(P, P.a)
+    AL = low_order_operator(P, P.a, d)
+    y = P.matvec(AL, u_old)
+    ut = cn_predictor(P, u_old, F_old, dt)
+    Qp, Qm = zalesak_Q(P, ut)
+    g = P.m / dt * u_old - 0.5 * y + 0.5 * (F_old + F_new)  # right-hand side of eq. (11)
+    g[P.is_dir] = P.uD[P.is_dir]
+    Acn = 0.5 * AL
+    Acn[P.diag_pos] += P.m / dt
+    Acn = P.with_dirichlet_rows(Acn)
+    u_star = 2.0 * ut - u_old
+    u_star[P.is_dir] = P.uD[P.is_dir]
+    r = cn_fluxes(P, u_star, u_old, d, dt, prelimit)
+    if alpha_mode == "limited":
+        alpha = zalesak_alpha(P, r, Qp, Qm, dt)[0]
+    elif alpha_mode == "one":
+        alpha = np.where(r != 0.0, 1.0, 0.0)
+    else:
+        alpha = np.zeros_like(r)
+    b = g + P.row_sum(alpha * r)
+    b[P.is_dir] = P.uD[P.is_dir]
+    st = FixedPointStats()
+    st.residuals.append(float(np.linalg.norm((b - P.matvec(Acn, u_star))[~P.is_dir])))
+    kr = krylov(P, Acn, b, u_star, lin, lin_atol, lin_rtol, lin_maxit, restart)
+    st.krylov_iters.append(kr.iters)
+    st.iters = 1
+    if kr.status < 0:
+        st.status = kr.status
+    return kr.x, st
+
+
 # ----------------------------------------------------------------------------
 # Stationary problem with the monolithic convex limiter (Sec. 3.1, Sec. 4)
 # ----------------------------------------------------------------------------

@@ -71,7 +71,7 @@ EXPORTS = [
     "afc_batch_create", "afc_batch_offsets", "afc_batch_step_cn", "afc_batch_last_error", "afc_batch_destroy",
     "afc_footprint_bytes", "afc_server_create", "afc_server_submit", "afc_server_wait", "afc_server_last_error",
     "afc_server_destroy", "afc_get_sell_info", "afc_sell_layout", "afc_kernel_work",
-    "afc_batch_set_schedule", "afc_batch_get_schedule", "afc_batch_autotune",
+    "afc_batch_set_schedule", "afc_batch_get_schedule", "afc_batch_autotune", "afc_step_cn_linear",
 ]
 
 AFC_REQ_CN, AFC_REQ_STATIONARY = 0, 1
@@ -99,6 +99,8 @@ def lib():
         L.afc_step_ssprk3.restype = c_int32
         L.afc_step_cn.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_double, POINTER(afc_stats)]
         L.afc_step_cn.restype = c_int32
+        L.afc_step_cn_linear.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_double, POINTER(afc_stats)]
+        L.afc_step_cn_linear.restype = c_int32
         L.afc_solve_stationary.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, POINTER(afc_stats)]
         L.afc_solve_stationary.restype = c_int32
         L.afc_kernel_time.argtypes = [c_void_p, c_int32, POINTER(c_double), POINTER(c_int64), c_int32]
@@ -267,6 +269,14 @@ def afc_step_ssprk3(h, u, F, dt, raise_on_error=True):
 def afc_step_cn(h, u, F_old, F_new, dt, raise_on_error=True):
     stats = afc_stats()
     st = lib().afc_step_cn(h, u.data_ptr(), F_old.data_ptr(), F_new.data_ptr(), float(dt), ctypes.byref(stats))
+    return _finish(h, st, stats, raise_on_error)
+
+
+def afc_step_cn_linear(h, u, F_old, F_new, dt, raise_on_error=True):
+    """One linear Zal+CN step (fluxes at u* = 2 u~ - u^{n-1}, one linear solve)."""
+    stats = afc_stats()
+    st = lib().afc_step_cn_linear(h, u.data_ptr(), F_old.data_ptr(), F_new.data_ptr(), float(dt),
+                                  ctypes.byref(stats))
     return _finish(h, st, stats, raise_on_error)
 
 

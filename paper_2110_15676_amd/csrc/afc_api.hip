@@ -899,6 +899,60 @@ afc_status afc_step_cn(afc_handle* h, double* u, const double* F_old, const doub
       &a);
 }
 
+afc_status afc_step_cn_linear(afc_handle* h, double* u, const double* F_old, const double* F_new, double dt,
+                              afc_stats* st) {
+  if (!h) return AFC_EINVAL;
+  if (!u || !F_old || !F_new || !(dt > 0) || !std::isfinite(dt)) {
+    h->last_error = "afc_step_cn_linear: need device u, F_old, F_new and dt > 0";
+    return AFC_EINVAL;
+  }
+  CnArgs a{u, F_old, F_new, dt, st};
+  return guard(
+      h, st,
+      [](afc_handle* h, void* ctx) -> afc_status {
+        const CnArgs& a = *static_cast<CnArgs*>(ctx);
+        if (h->cn_dt != a.dt) {
+          afc::build_cn_matrix(h, a.dt);
+          h->cn_dt = a.dt;
+        }
+        double* uo = h->w[W_UOLD];
+        double* ut = h->w[W_UT];
+        double* g = h->w[W_G];
+        double* Qp = h->w[W_A];
+        double* Qm = h->w[W_B2];
+        double* Rp = h->w[W_RP];
+        double* Rm = h->w[W_RM];
+        double* b = h->w[W_B];
+        double* r = h->w[W_R];
+        afc::copy(h, uo, a.u);
+        afc::cn_predict(h, uo, a.Fo, a.Fn, a.dt, ut, g);  // eq. (14) and the right-hand side of eq. (11)
+        afc::zalesak_Q(h, ut, Qp, Qm);
+        afc::cn_extrapolate(h, ut, uo, a.u);  // u <- u* = 2 u~ - u^{n-1}
+        afc::cn_limit_R(h, a.u, uo, Qp, Qm, a.dt, Rp, Rm);
+        afc::cn_apply(h, a.u, uo, Rp, Rm, g, a.dt, b, r);  // b = g + F*(u*), r = b - A_cn u*
+        sync_status(h);
+        const double R = std::sqrt(h->host_status->red[0]);
+        const double bn = std::sqrt(h->host_status->red[1]);
+        if (a.st) {
+          a.st->res0 = R;
+          a.st->res = R;
+          a.st->fp_iters = 1;
+        }
+        if (!std::isfinite(R) || !std::isfinite(bn)) {
+          h->last_error = "non-finite residual";
+          return AFC_ENAN;
+        }
+        const SysMat S{h->A_cn, h->dinv_cn, h->S64_cn, h->S32_cn};
+        const double tol = std::max(h->opt.lin_atol, h->opt.lin_rtol * bn);
+        const SolveOut o = linear_solve(h, S, b, a.u, r, 2, tol);
+        add_solve(a.st, o);
+        if (o.st == AFC_ENAN) h->last_error = "non-finite linear residual";
+        if (o.st == AFC_EBREAKDOWN) h->last_error = "BiCGStab breakdown";
+        return o.st;
+      },
+      &a);
+}
+
 struct StatArgs {
   double* u;
   const double* F;

@@ -59,6 +59,7 @@ void cn_predict(H* h, const double* u_old, const double* F_old, const double* F_
 void zalesak_Q(H* h, const double* ut, double* Qp, double* Qm);
 void cn_limit_R(H* h, const double* u, const double* u_old, const double* Qp, const double* Qm, double dt,
                 double* Rp, double* Rm);
+void cn_extrapolate(H* h, const double* ut, const double* uo, double* us);  // u* = 2 u~ - u_old (linear Zal+CN)
 void cn_apply(H* h, const double* u, const double* u_old, const double* Rp, const double* Rm, const double* g,
               double dt, double* b, double* r);
 

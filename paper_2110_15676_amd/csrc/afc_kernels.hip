@@ -1049,6 +1049,16 @@ __global__ __launch_bounds__(kBlock) void k_ssp_apply(
 // ---------------------------------------------------------------------------
 
 // ut = u_old - dt/2 M_L^{-1} (A_low u_old - F_old) ; g = (M_L/dt - A_low/2) u_old + (F_old + F_new)/2
+// Linear Zal+CN (Sec. 2.1.1): u* = 2 u~ - u^{n-1} stands for u^n in the
+// fluxes of eq. (12); u_D at Dirichlet nodes.
+__global__ __launch_bounds__(kBlock) void k_cn_extrapolate(int N, const double* __restrict__ ut,
+                                                           const double* __restrict__ uo,
+                                                           const uint8_t* __restrict__ is_dir,
+                                                           const double* __restrict__ uD, double* __restrict__ us) {
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock)
+    us[i] = is_dir[i] ? uD[i] : 2.0 * ut[i] - uo[i];
+}
+
 template <int G>
 __global__ __launch_bounds__(kBlock) void k_cn_predict(int N, const int* __restrict__ rp,
                                                        const int* __restrict__ col, const double* __restrict__ AL,
@@ -1575,6 +1585,10 @@ void cn_predict(H* h, const double* u_old, const double* F_old, const double* F_
                 double* g) {
   AFC_DISPATCH_G(h, k_cn_predict, row_grid(h, false), h->N, h->row_ptr, h->col, h->AL_fct, u_old, F_old, F_new,
                  h->ml, h->is_dir, h->uD, dt, ut, g);
+}
+
+void cn_extrapolate(H* h, const double* ut, const double* uo, double* us) {
+  k_cn_extrapolate<<<vec_grid(h), kBlock, 0, h->stream>>>(h->N, ut, uo, h->is_dir, h->uD, us);
 }
 
 void zalesak_Q(H* h, const double* ut, double* Qp, double* Qm) {

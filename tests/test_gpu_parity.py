@@ -156,6 +156,48 @@ def test_cn_config1_parity(krylov, prec):
         afc.afc_destroy(h)
 
 
+@pytest.mark.parametrize("krylov,prec", [(0, 0), (1, 0), (1, 1)])
+def test_cn_linear_parity(krylov, prec):
+    """Linear Zal+CN on the CN workload (P1 8^3): 10 steps against the oracle."""
+    afc = _afc()
+    inst = I.config1()
+    P = O.problem_from_instance(inst, conv=False)
+    dt = inst.params["dt"]
+    print("cn linear config1 krylov=%d prec=%d" % (krylov, prec), flush=True)
+    h = afc.afc_create_instance(inst, _opts(krylov=krylov, precision=prec, **CN_PARITY), conv=False)
+    try:
+        u = _dev(inst.u0)
+        F = _dev(inst.F)
+        ref = inst.u0.copy()
+        for s in range(10):
+            st, stats = afc.afc_step_cn_linear(h, u, F, F, dt)
+            assert st == 0 and stats["fp_iters"] == 1, stats
+            lin = "bicgstab" if krylov == 0 else "gmres"
+            ref, rst = O.cn_linear_step(P, ref, inst.F, inst.F, dt, lin=lin, lin_atol=1e-15)
+            assert rst.status == 0
+        tol = 1e-10 if prec == 0 else 1e-8
+        assert _rel(u.cpu().numpy(), ref) <= tol
+    finally:
+        afc.afc_destroy(h)
+
+
+@pytest.mark.parametrize("mode,name", [(1, "one"), (2, "zero")])
+def test_cn_linear_alpha_modes(mode, name):
+    afc = _afc()
+    inst = I.build("Q1", 9, 1e-3, I.affine_field([0.8, 0.3, -0.5]), 0.2, dirichlet="inflow",
+                   u0_fn=lambda X: np.exp(-30 * np.sum((X - 0.35) ** 2, axis=1)))
+    P = O.problem_from_instance(inst, conv=False)
+    h = afc.afc_create_instance(inst, _opts(alpha_mode=mode, **CN_PARITY), conv=False)
+    try:
+        u = _dev(inst.u0)
+        F = _dev(inst.F)
+        afc.afc_step_cn_linear(h, u, F, F, 5e-3)
+        ref, _ = O.cn_linear_step(P, inst.u0, inst.F, inst.F, 5e-3, alpha_mode=name, lin="gmres", lin_atol=1e-15)
+        assert _rel(u.cpu().numpy(), ref) <= 1e-10
+    finally:
+        afc.afc_destroy(h)
+
+
 @pytest.mark.parametrize("mode,name", [(1, "one"), (2, "zero")])
 def test_cn_alpha_modes(mode, name):
     afc = _afc()

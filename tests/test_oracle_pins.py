@@ -204,6 +204,75 @@ def test_cn_alpha_one_is_cn_galerkin_and_zero_is_low_order(elem, lin):
     np.testing.assert_allclose(u0, ref0, rtol=0, atol=1e-12 * np.abs(ref0).max())
 
 
+@pytest.mark.parametrize("elem,lin", [("P1", "bicgstab"), ("Q1", "gmres")])
+def test_cn_linear_alpha_one_and_zero_closed_forms(elem, lin):
+    """Linear Zal+CN (Sec. 2.1.1): with alpha = 1 and no prelimiting the
+    correction is F* = (M_L - M_C)(u* - u^{n-1})/dt + D u~ (the row sums of
+    eq. (12) at u^n = u* = 2u~ - u^{n-1}, whose midpoint is u~), so one dense
+    solve of eq. (11) gives the step; with alpha = 0 it is the low-order CN
+    step."""
+    inst = I.build(elem, 4, 0.05, I.affine_field([1.0, -0.5, 0.25]), 0.5, dirichlet="inflow",
+                   u0_fn=lambda X: np.exp(-20 * np.sum((X - 0.4) ** 2, axis=1)))
+    P = O.problem_from_instance(inst, conv=False)
+    Md, Ad = _dense_ops(inst)
+    dt = 0.02
+    Fo = np.full(inst.N, 0.1)
+    Fn = np.full(inst.N, 0.3)
+    dirs = inst.dir_idx
+    u = inst.u0.copy()
+    u[dirs] = inst.dir_val  # an admissible u^{n-1}
+    mL = Md.sum(axis=1)
+    Dd = np.zeros_like(Ad)
+    for i in range(inst.N):
+        for j in range(inst.N):
+            if i != j and Md[i, j] != 0.0:
+                Dd[i, j] = -max(Ad[i, j], 0.0, Ad[j, i])
+        Dd[i, i] = -Dd[i].sum()
+    AL = Ad + Dd
+    ut = u - 0.5 * dt * (AL @ u - Fo) / mL
+    ut[dirs] = inst.dir_val
+    us = 2.0 * ut - u
+    Fstar = (np.diag(mL) - Md) @ (us - u) / dt + Dd @ ut
+    L = np.diag(mL) / dt + 0.5 * AL
+    rhs1 = (np.diag(mL) / dt - 0.5 * AL) @ u + 0.5 * (Fo + Fn) + Fstar
+    rhs0 = (np.diag(mL) / dt - 0.5 * AL) @ u + 0.5 * (Fo + Fn)
+    L[dirs, :] = 0.0
+    L[dirs, dirs] = 1.0
+    rhs1[dirs] = inst.dir_val
+    rhs0[dirs] = inst.dir_val
+    ref1 = np.linalg.solve(L, rhs1)
+    ref0 = np.linalg.solve(L, rhs0)
+    u1, st = O.cn_linear_step(P, u, Fo, Fn, dt, alpha_mode="one", prelimit=0.0, lin=lin, lin_atol=0.0,
+                              lin_rtol=1e-15)
+    assert st.status == O.STATUS_OK and st.iters == 1
+    np.testing.assert_allclose(u1, ref1, rtol=0, atol=1e-12 * np.abs(ref1).max())
+    u0, st0 = O.cn_linear_step(P, u, Fo, Fn, dt, alpha_mode="zero", lin=lin, lin_atol=0.0, lin_rtol=1e-15)
+    np.testing.assert_allclose(u0, ref0, rtol=0, atol=1e-12 * np.abs(ref0).max())
+    # the limited step is neither: its correction lies between (alpha in [0, 1])
+    ul, _ = O.cn_linear_step(P, u, Fo, Fn, dt, lin=lin, lin_atol=0.0, lin_rtol=1e-15)
+    assert not np.allclose(ul, ref1, atol=1e-9) and not np.allclose(ul, ref0, atol=1e-9)
+
+
+def test_cn_linear_conserves_mass_without_dirichlet_nodes():
+    """No Dirichlet nodes: the limited fluxes are antisymmetric (alpha_ij =
+    alpha_ji, r_ji = -r_ij), so sum_i m_i u^n_i changes only by the
+    low-order terms: 1^T M_L u^n = 1^T M_L u^{n-1} + dt/2 1^T (F^n + F^{n-1})
+    - dt/2 1^T A_low (u^n + u^{n-1}), with the columns of A_low summing to
+    those of A."""
+    inst = I.build("Q1", 4, 0.02, I.affine_field([0.7, 0.2, -0.4]), 0.0, dirichlet="none",
+                   u0_fn=lambda X: np.exp(-15 * np.sum((X - 0.5) ** 2, axis=1)))
+    P = O.problem_from_instance(inst, conv=False)
+    Md, Ad = _dense_ops(inst)
+    dt = 0.01
+    F = np.zeros(inst.N)
+    u = inst.u0
+    un, st = O.cn_linear_step(P, u, F, F, dt, lin="gmres", lin_atol=0.0, lin_rtol=1e-15)
+    lhs = Md.sum(axis=1) @ un
+    rhs = Md.sum(axis=1) @ u - 0.5 * dt * np.ones(inst.N) @ Ad @ (un + u)
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+
 @pytest.mark.parametrize("elem", ["P1", "Q1"])
 def test_stationary_alpha_one_is_galerkin_zero_is_low_order(elem):
     # MCL scheme with r*_ij = r_ij reduces to A u = F; with r* = 0 to A_low u = F
