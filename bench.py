@@ -181,6 +181,53 @@ def bench_cn(afc, torch, I, n, steps):
     return out
 
 
+def bench_time_dependent(afc, torch, I, n, ssp_steps, cn_steps):
+    """Explicit SSP-RK3 (Zalesak FCT vs MC limiter) and implicit CN (MC) on the
+    Q1 n^3 rotating-transport problem (CFL 0.2 for SSP, 4x that step for CN)."""
+    inst = I.config2(n)
+    dt = inst.params["dt"]
+    out = {"workload": "Q1 %d^3 (%d nodes), rotating b, eps 1e-8, ball indicator u0" % (n, inst.N)}
+    o = afc.afc_default_options()
+    o.stream = torch.cuda.current_stream().cuda_stream
+    for name, step in (("fct_ssprk3", afc.afc_step_ssprk3), ("mc_ssprk3", afc.afc_step_mc_ssprk3)):
+        h = afc.afc_create_instance(inst, o, conv=True)
+        try:
+            u = torch.tensor(inst.u0, device="cuda:0")
+            F = torch.tensor(inst.F, device="cuda:0")
+            step(h, u.clone(), F, dt)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(ssp_steps):
+                step(h, u, F, dt)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+        finally:
+            afc.afc_destroy(h)
+        out[name] = {"ms_per_step": 1e3 * el / ssp_steps, "dof_stages_per_s": 3 * inst.N * ssp_steps / el,
+                     "steps": ssp_steps}
+    oc = afc.afc_default_options(krylov=afc.AFC_KRYLOV_BICGSTAB, fp_tol=1e-8, fp_tol_mode=afc.AFC_TOL_REL,
+                                 fp_maxit=50, lin_atol=0.0, lin_rtol=1e-10)
+    oc.stream = o.stream
+    h = afc.afc_create_instance(inst, oc, conv=True)
+    try:
+        u = torch.tensor(inst.u0, device="cuda:0")
+        F = torch.tensor(inst.F, device="cuda:0")
+        afc.afc_step_mc_cn(h, u.clone(), F, F, 4 * dt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fp = 0
+        for _ in range(cn_steps):
+            _, st = afc.afc_step_mc_cn(h, u, F, F, 4 * dt)
+            fp += st["fp_iters"]
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+    finally:
+        afc.afc_destroy(h)
+    out["mc_cn"] = {"ms_per_step": 1e3 * el / cn_steps, "dof_iterations_per_s": inst.N * fp / el,
+                    "fp_iters_per_step": fp / cn_steps, "steps": cn_steps}
+    return out
+
+
 def bench_serve(afc, torch, I, count, slots):
     """Poisson arrivals (200/s) of mixed CN-FCT / stationary-MCL Q1 requests."""
     import threading
@@ -483,6 +530,7 @@ def main():
     if not args.no_cn:
         print("bench: CN (nonlinear vs linear Zal+CN)", file=sys.stderr, flush=True)
         cn = bench_cn(afc, torch, I, 64, 10)
+        cn["time_dependent"] = bench_time_dependent(afc, torch, I, 64, 20, 5)
     serve = None
     if not args.no_serve:
         print("bench: serving", file=sys.stderr, flush=True)

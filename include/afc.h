@@ -187,6 +187,25 @@ afc_status afc_step_cn(afc_handle *h, double *u, const double *F_old, const doub
 afc_status afc_step_cn_linear(afc_handle *h, double *u, const double *F_old, const double *F_new, double dt,
                               afc_stats *stats);
 
+/* Time-dependent monolithic convex limiting (Sec. 2.2).  Both use the
+ * semi-discrete fluxes of eq. (20), r_ij = m_ij (udot_i - udot_j) +
+ * d_ij (u_j - u_i) with udot the low-order rate of eq. (21), limited by
+ * eq. (22) with the bar states and local bounds of the state the fluxes are
+ * evaluated at.  As for afc_solve_stationary, D and the bar states come from
+ * the convective matrix K_conv (Remark 1) and A_low = A + D^conv.
+ *
+ * afc_step_mc_ssprk3: forward-Euler stages of eq. (18) with F* = sum_j r*_ij,
+ * composed as options.ssp_stages (3 Shu-Osher, 2 Heun, 1 single stage); same
+ * arguments as afc_step_ssprk3.
+ *
+ * afc_step_mc_cn: eq. (11) with A_low^conv and the correction
+ * F* = (F*(u^n) + F*(u^{n-1}))/2 (each with udot at its own time level, from
+ * F_new resp. F_old), solved by the fixed point of Sec. 4 from u^{n-1}; same
+ * arguments, options and statuses as afc_step_cn. */
+afc_status afc_step_mc_ssprk3(afc_handle *h, double *u, const double *F, double dt, afc_stats *stats);
+afc_status afc_step_mc_cn(afc_handle *h, double *u, const double *F_old, const double *F_new, double dt,
+                          afc_stats *stats);
+
 /* Stationary MCL scheme (Sec. 3.1): fixed-point iteration of Sec. 4 for
  * A_low u = F + F*(u), where F* sums the fluxes r^ss_ij = d_ij (u_j - u_i)
  * of eq. (25) limited by eq. (22).  u: in initial guess, out solution

@@ -182,8 +182,9 @@ def zalesak_alpha(P: AFCProblem, r: np.ndarray, Qp, Qm, dt: float):
     return alpha, Rp, Rm, Pp, Pm
 
 
-def mcl_limited_fluxes(P: AFCProblem, u: np.ndarray, c: np.ndarray, d: np.ndarray):
-    """Monolithic convex limiting of r_ij = d_ij (u_j - u_i) (eqs. (22), (23), (25)).
+def mcl_limited_fluxes(P: AFCProblem, u: np.ndarray, c: np.ndarray, d: np.ndarray, r=None):
+    """Monolithic convex limiting (eqs. (22), (23)) of the fluxes r (default:
+    the stationary r^ss_ij = d_ij (u_j - u_i) of eq. (25)).
 
     Bar states 2 d_ij ubar_ij = d_ij (u_i + u_j) + c_ij (u_j - u_i), with c the
     convective a_ij (Remark 1); u_i^max/min over N_i including i.  Returns
@@ -191,7 +192,8 @@ def mcl_limited_fluxes(P: AFCProblem, u: np.ndarray, c: np.ndarray, d: np.ndarra
     i, j = P.rows, P.col
     umax = P.row_max(u[j])
     umin = P.row_min(u[j])
-    r = d * (u[j] - u[i])
+    if r is None:
+        r = d * (u[j] - u[i])
     S_ij = d * (u[i] + u[j]) + c * (u[j] - u[i])  # 2 d_ij ubar_ij
     S_ji = d * (u[i] + u[j]) + c[P.tpos] * (u[i] - u[j])  # 2 d_ji ubar_ji
     two_d = 2.0 * d
@@ -611,6 +613,107 @@ def stationary_mcl(P: AFCProblem, F, u0, *, alpha_mode="limited", tol=1e-8, tol_
             break
         w_omega = _next_omega(w_omega, R, R_prev, dynamic_damping)
         kr = krylov(P, As, b, u, lin, lin_atol, lin_rtol, lin_maxit, restart)
+        st.krylov_iters.append(kr.iters)
+        if kr.status < 0:
+            st.status = kr.status
+            u = kr.x
+            break
+        u = u + w_omega * (kr.x - u)
+        R_prev = R
+        nu += 1
+    st.iters = nu
+    return u, st
+
+
+# ----------------------------------------------------------------------------
+# Time-dependent monolithic convex limiting (Sec. 2.2): MC+SSP and MC+CN
+# ----------------------------------------------------------------------------
+
+
+def mc_operators(P: AFCProblem):
+    """(d^conv, A_low) of the MC schemes: D from the convective part only
+    (Remark 1), A_low = A + D^conv (no Dirichlet rows)."""
+    d = artificial_diffusion(P, P.c)
+    return d, low_order_operator(P, P.a, d)
+
+
+def mc_rate(P: AFCProblem, AL, u, F):
+    """Low-order time derivative of eq. (21) for the MC operator, zero at
+    Dirichlet nodes."""
+    udot = (F - P.matvec(AL, u)) / P.m
+    udot[P.is_dir] = 0.0
+    return udot
+
+
+def mc_correction(P: AFCProblem, u, udot, d, alpha_mode="limited"):
+    """F*_i = sum_j r*_ij: the semi-discrete fluxes of eq. (20),
+    r_ij = m_ij (udot_i - udot_j) + d_ij (u_j - u_i), limited by eq. (22)."""
+    i, j = P.rows, P.col
+    r = np.where(P.offd & ~P.is_dir[i], P.m_ij * (udot[i] - udot[j]) + d * (u[j] - u[i]), 0.0)
+    if alpha_mode == "limited":
+        rstar = mcl_limited_fluxes(P, u, P.c, d, r=r)[0]
+    elif alpha_mode == "one":
+        rstar = r
+    else:
+        rstar = np.zeros_like(r)
+    return P.row_sum(rstar)
+
+
+def mc_ssp_stage(P: AFCProblem, u, F, dt, alpha_mode="limited"):
+    """Forward-Euler update of eq. (18) with the MC correction F*(u) of Sec. 2.2:
+    u_new = u + dt M_L^{-1} (F + F*(u) - A_low u), u_D at Dirichlet nodes."""
+    d, AL = mc_operators(P)
+    udot = mc_rate(P, AL, u, F)
+    un = u + dt * (udot + mc_correction(P, u, udot, d, alpha_mode) / P.m)
+    un[P.is_dir] = P.uD[P.is_dir]
+    return un
+
+
+def mc_ssp_rk3_step(P: AFCProblem, u, F, dt, alpha_mode="limited"):
+    """Shu-Osher SSP-RK3 composed of three MC forward-Euler stages."""
+    u1 = mc_ssp_stage(P, u, F, dt, alpha_mode)
+    u2 = 0.75 * u + 0.25 * mc_ssp_stage(P, u1, F, dt, alpha_mode)
+    return (1.0 / 3.0) * u + (2.0 / 3.0) * mc_ssp_stage(P, u2, F, dt, alpha_mode)
+
+
+def mc_cn_step(P: AFCProblem, u_old, F_old, F_new, dt, *, alpha_mode="limited", tol=1e-12, tol_mode="abs",
+               maxit=50, lin="bicgstab", lin_atol=1e-12, lin_rtol=0.0, lin_maxit=10000, omega=1.0,
+               dynamic_damping=False, restart=30):
+    """MC+CN (Sec. 2.2): eq. (11) with 𝔸 = A + D^conv and the correction
+    F* = 1/2 [F*(u^n) + F*(u^{n-1})], each evaluated with the low-order rate
+    at its own time level (F^n resp. F^{n-1}); fixed point of Sec. 4 from
+    u^{n-1}.  Returns (u^n, stats)."""
+    d, AL = mc_operators(P)
+    udot_old = mc_rate(P, AL, u_old, F_old)
+    g = P.m / dt * u_old - 0.5 * P.matvec(AL, u_old) + 0.5 * (F_old + F_new) \
+        + 0.5 * mc_correction(P, u_old, udot_old, d, alpha_mode)
+    g[P.is_dir] = P.uD[P.is_dir]
+    Acn = 0.5 * AL
+    Acn[P.diag_pos] += P.m / dt
+    Acn = P.with_dirichlet_rows(Acn)
+    u = u_old.copy()
+    u[P.is_dir] = P.uD[P.is_dir]
+    st = FixedPointStats()
+    R0 = None
+    R_prev = None
+    w_omega = omega
+    nu = 0
+    while True:
+        udot = mc_rate(P, AL, u, F_new)
+        b = g + 0.5 * mc_correction(P, u, udot, d, alpha_mode)
+        b[P.is_dir] = P.uD[P.is_dir]
+        res = b - P.matvec(Acn, u)
+        R = float(np.linalg.norm(res[~P.is_dir]))
+        if R0 is None:
+            R0 = R
+        st.residuals.append(R)
+        if R == 0.0 or _fp_converged(R, R0, P.N, tol, tol_mode):
+            break
+        if nu >= maxit:
+            st.status = STATUS_WMAXIT
+            break
+        w_omega = _next_omega(w_omega, R, R_prev, dynamic_damping)
+        kr = krylov(P, Acn, b, u, lin, lin_atol, lin_rtol, lin_maxit, restart)
         st.krylov_iters.append(kr.iters)
         if kr.status < 0:
             st.status = kr.status

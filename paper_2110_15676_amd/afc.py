@@ -72,6 +72,7 @@ EXPORTS = [
     "afc_footprint_bytes", "afc_server_create", "afc_server_submit", "afc_server_wait", "afc_server_last_error",
     "afc_server_destroy", "afc_get_sell_info", "afc_sell_layout", "afc_kernel_work",
     "afc_batch_set_schedule", "afc_batch_get_schedule", "afc_batch_autotune", "afc_step_cn_linear",
+    "afc_step_mc_ssprk3", "afc_step_mc_cn",
 ]
 
 AFC_REQ_CN, AFC_REQ_STATIONARY = 0, 1
@@ -101,6 +102,10 @@ def lib():
         L.afc_step_cn.restype = c_int32
         L.afc_step_cn_linear.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_double, POINTER(afc_stats)]
         L.afc_step_cn_linear.restype = c_int32
+        L.afc_step_mc_cn.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_double, POINTER(afc_stats)]
+        L.afc_step_mc_cn.restype = c_int32
+        L.afc_step_mc_ssprk3.argtypes = [c_void_p, c_void_p, c_void_p, c_double, POINTER(afc_stats)]
+        L.afc_step_mc_ssprk3.restype = c_int32
         L.afc_solve_stationary.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, POINTER(afc_stats)]
         L.afc_solve_stationary.restype = c_int32
         L.afc_kernel_time.argtypes = [c_void_p, c_int32, POINTER(c_double), POINTER(c_int64), c_int32]
@@ -277,6 +282,20 @@ def afc_step_cn_linear(h, u, F_old, F_new, dt, raise_on_error=True):
     stats = afc_stats()
     st = lib().afc_step_cn_linear(h, u.data_ptr(), F_old.data_ptr(), F_new.data_ptr(), float(dt),
                                   ctypes.byref(stats))
+    return _finish(h, st, stats, raise_on_error)
+
+
+def afc_step_mc_ssprk3(h, u, F, dt, raise_on_error=True):
+    """One SSP step (options.ssp_stages) with the time-dependent MC limiter."""
+    stats = afc_stats()
+    st = lib().afc_step_mc_ssprk3(h, u.data_ptr(), F.data_ptr(), float(dt), ctypes.byref(stats))
+    return _finish(h, st, stats, raise_on_error)
+
+
+def afc_step_mc_cn(h, u, F_old, F_new, dt, raise_on_error=True):
+    """One MC+CN step (fixed point of Sec. 4)."""
+    stats = afc_stats()
+    st = lib().afc_step_mc_cn(h, u.data_ptr(), F_old.data_ptr(), F_new.data_ptr(), float(dt), ctypes.byref(stats))
     return _finish(h, st, stats, raise_on_error)
 
 

@@ -853,6 +853,15 @@ afc_status afc_step_ssprk3(afc_handle* h, double* u, const double* F, double dt,
       &a);
 }
 
+// CN system matrix M_L/dt + AL/2 for the scheme's low-order operator AL,
+// rebuilt when dt or the operator changes
+void ensure_cn_matrix(afc_handle* h, const double* AL, double dt) {
+  if (h->cn_dt == dt && h->cn_src == AL) return;
+  afc::build_cn_matrix(h, AL, dt);
+  h->cn_dt = dt;
+  h->cn_src = AL;
+}
+
 struct CnArgs {
   double* u;
   const double* Fo;
@@ -873,10 +882,7 @@ afc_status afc_step_cn(afc_handle* h, double* u, const double* F_old, const doub
       h, st,
       [](afc_handle* h, void* ctx) -> afc_status {
         const CnArgs& a = *static_cast<CnArgs*>(ctx);
-        if (h->cn_dt != a.dt) {
-          afc::build_cn_matrix(h, a.dt);
-          h->cn_dt = a.dt;
-        }
+        ensure_cn_matrix(h, h->AL_fct, a.dt);
         double* uo = h->w[W_UOLD];
         double* ut = h->w[W_UT];
         double* g = h->w[W_G];
@@ -911,10 +917,7 @@ afc_status afc_step_cn_linear(afc_handle* h, double* u, const double* F_old, con
       h, st,
       [](afc_handle* h, void* ctx) -> afc_status {
         const CnArgs& a = *static_cast<CnArgs*>(ctx);
-        if (h->cn_dt != a.dt) {
-          afc::build_cn_matrix(h, a.dt);
-          h->cn_dt = a.dt;
-        }
+        ensure_cn_matrix(h, h->AL_fct, a.dt);
         double* uo = h->w[W_UOLD];
         double* ut = h->w[W_UT];
         double* g = h->w[W_G];
@@ -949,6 +952,89 @@ afc_status afc_step_cn_linear(afc_handle* h, double* u, const double* F_old, con
         if (o.st == AFC_ENAN) h->last_error = "non-finite linear residual";
         if (o.st == AFC_EBREAKDOWN) h->last_error = "BiCGStab breakdown";
         return o.st;
+      },
+      &a);
+}
+
+afc_status afc_step_mc_ssprk3(afc_handle* h, double* u, const double* F, double dt, afc_stats* st) {
+  if (!h) return AFC_EINVAL;
+  if (!u || !F || !(dt > 0) || !std::isfinite(dt)) {
+    h->last_error = "afc_step_mc_ssprk3: need device u, F and dt > 0";
+    return AFC_EINVAL;
+  }
+  SspArgs a{u, F, dt};
+  return guard(
+      h, st,
+      [](afc_handle* h, void* ctx) -> afc_status {
+        const SspArgs& a = *static_cast<SspArgs*>(ctx);
+        double* s1 = h->w[W_S1];
+        double* s2 = h->w[W_S2];
+        double* udot = h->w[W_G];
+        double* scratch = h->w[W_UT];
+        double* umax = h->w[W_A];
+        double* umin = h->w[W_B2];
+        struct Stage {
+          const double* in;
+          double* out;
+          double c0, c1;
+        };
+        Stage stages[3];
+        int ns = 0;
+        if (h->opt.ssp_stages == 3) {  // Shu-Osher SSP-RK3
+          stages[ns++] = {a.u, s1, 0.0, 1.0};
+          stages[ns++] = {s1, s2, 0.75, 0.25};
+          stages[ns++] = {s2, a.u, 1.0 / 3.0, 2.0 / 3.0};
+        } else if (h->opt.ssp_stages == 2) {  // Heun
+          stages[ns++] = {a.u, s1, 0.0, 1.0};
+          stages[ns++] = {s1, a.u, 0.5, 0.5};
+        } else {
+          stages[ns++] = {a.u, s1, 0.0, 1.0};
+        }
+        for (int s = 0; s < ns; ++s) {
+          afc::mc_lowrate(h, stages[s].in, a.F, udot, scratch);
+          afc::mcl_bounds(h, stages[s].in, umax, umin);
+          afc::mc_stage(h, stages[s].in, udot, umax, umin, a.dt, a.u, stages[s].c0, stages[s].c1, stages[s].out);
+        }
+        if (ns == 1) afc::copy(h, a.u, s1);
+        HIP_OK(hipGetLastError());
+        HIP_OK(hipStreamSynchronize(h->stream));
+        afc::prof_collect(h);
+        return AFC_OK;
+      },
+      &a);
+}
+
+afc_status afc_step_mc_cn(afc_handle* h, double* u, const double* F_old, const double* F_new, double dt,
+                          afc_stats* st) {
+  if (!h) return AFC_EINVAL;
+  if (!u || !F_old || !F_new || !(dt > 0) || !std::isfinite(dt)) {
+    h->last_error = "afc_step_mc_cn: need device u, F_old, F_new and dt > 0";
+    return AFC_EINVAL;
+  }
+  CnArgs a{u, F_old, F_new, dt, st};
+  return guard(
+      h, st,
+      [](afc_handle* h, void* ctx) -> afc_status {
+        const CnArgs& a = *static_cast<CnArgs*>(ctx);
+        ensure_cn_matrix(h, h->AL_mcl, a.dt);
+        double* uo = h->w[W_UOLD];
+        double* g = h->w[W_G];
+        double* udot = h->w[W_S1];
+        double* scratch = h->w[W_UT];
+        double* umax = h->w[W_A];
+        double* umin = h->w[W_B2];
+        afc::copy(h, uo, a.u);
+        afc::mc_lowrate(h, uo, a.Fo, udot, scratch);
+        afc::mcl_bounds(h, uo, umax, umin);
+        afc::mc_cn_g(h, uo, udot, umax, umin, a.Fn, a.dt, g);
+        afc::set_dirichlet(h, a.u);
+        const SysMat S{h->A_cn, h->dinv_cn, h->S64_cn, h->S32_cn};
+        auto eval = [&](double* u, double* b, double* r) {
+          afc::mc_lowrate(h, u, a.Fn, udot, scratch);
+          afc::mcl_bounds(h, u, umax, umin);
+          afc::mc_cn_apply(h, u, udot, umax, umin, g, b, r);
+        };
+        return fixed_point(h, a.u, S, eval, a.st);
       },
       &a);
 }

@@ -99,6 +99,7 @@ struct afc_handle_s {
 
   // CN system M_L/dt + A_low/2 (built for the last dt used)
   double cn_dt = 0.0;
+  const double* cn_src = nullptr;  // A_low the CN matrix was built from (AL_fct or AL_mcl)
   double* A_cn = nullptr;
   double* dinv_cn = nullptr;
 

@@ -16,7 +16,9 @@ void fill(H* h, double* u, double v);
 void norm2(H* h, const double* x, int red_idx);             // ||x||^2 into ks->red[red_idx]
 
 // --- setup --------------------------------------------------------------------
-void build_cn_matrix(H* h, double dt);  // A_cn = M_L/dt + A_low/2 (+ dinv, SELL FP64 and scaled FP32 copies)
+// A_cn = M_L/dt + AL/2 for AL = A_low of the FCT (AL_fct) or MC (AL_mcl) scheme
+// (+ dinv, SELL FP64 and scaled FP32 copies)
+void build_cn_matrix(H* h, const double* AL, double dt);
 void to_sell64(H* h, const double* csr, double* sell);                       // CSR values -> SELL slots
 void to_sell32_scaled(H* h, const double* csr, const double* dinv, float* sell);  // (a_ij dinv_j) in FP32
 
@@ -49,6 +51,15 @@ void bicg_iter(H* h, const double* A, const double* dinv, const BicgVec& b);
 
 // --- Zalesak FCT, explicit SSP stage -------------------------------------------
 void ssp_lowrate(H* h, const double* u, const double* F, double dt, double* udot, double* ut);
+
+// --- time-dependent MC limiting (Sec. 2.2) ----------------------------------------
+void mc_lowrate(H* h, const double* u, const double* F, double* udot, double* scratch);  // udot = (F - A_low^mc u)/m
+void mc_stage(H* h, const double* u, const double* udot, const double* umax, const double* umin, double dt,
+              const double* u0, double c0, double c1, double* out);
+void mc_cn_g(H* h, const double* uo, const double* udot, const double* umax, const double* umin, const double* Fn,
+             double dt, double* g);
+void mc_cn_apply(H* h, const double* u, const double* udot, const double* umax, const double* umin, const double* g,
+                 double* b, double* r);
 void ssp_limit_R(H* h, const double* u, const double* udot, const double* ut, double dt, double* Rp, double* Rm);
 void ssp_apply(H* h, const double* u, const double* udot, const double* ut, const double* Rp, const double* Rm,
                double dt, const double* base, double c0, double c1, double* out);

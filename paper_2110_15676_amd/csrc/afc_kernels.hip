@@ -1318,6 +1318,149 @@ __global__ __launch_bounds__(kBlock) void k_mcl_apply(
 }
 
 // ---------------------------------------------------------------------------
+// Time-dependent monolithic convex limiting (Sec. 2.2): the fluxes of eq. (20),
+// r_ij = m_ij (udot_i - udot_j) + d_ij (u_j - u_i), d_ij = -max(c_ij, 0, c_ji)
+// from the convective part (Remark 1), clipped by eq. (22) with the bar states
+// of the current state u (r* = 0 where d_ij = 0)
+// ---------------------------------------------------------------------------
+
+// this lane's share of F*_i = sum_j r*_ij (caller sums over the G lanes)
+template <int G>
+__device__ __forceinline__ double mc_row_fstar(int i, int lane, const int* __restrict__ rp,
+                                               const int* __restrict__ col, const double* __restrict__ mij,
+                                               const double* __restrict__ cc, const double* __restrict__ ccT,
+                                               const double* __restrict__ u, const double* __restrict__ udot,
+                                               const double* __restrict__ umax, const double* __restrict__ umin,
+                                               int alpha_mode) {
+  if (alpha_mode == AFC_ALPHA_ZERO) return 0.0;
+  const double ui = u[i], udi = udot[i], umaxi = umax[i], umini = umin[i];
+  double fs = 0.0;
+  const int e = rp[i + 1];
+  for (int k = rp[i] + lane; k < e; k += G) {
+    const int j = col[k];
+    if (j == i) continue;
+    const double uj = u[j];
+    const double c = cc[k], ct = ccT[k];
+    const double d = -fmax(fmax(c, 0.0), ct);
+    const double rf = mij[k] * (udi - udot[j]) + d * (uj - ui);
+    if (alpha_mode == AFC_ALPHA_ONE) {
+      fs += rf;
+      continue;
+    }
+    if (d == 0.0) continue;
+    const double sij = d * (ui + uj) + c * (uj - ui);
+    const double sji = d * (ui + uj) + ct * (ui - uj);
+    const double two_d = 2.0 * d;
+    if (rf > 0.0)
+      fs += fmin(rf, fmin(sij - two_d * umaxi, two_d * umin[j] - sji));
+    else
+      fs += fmax(rf, fmax(sij - two_d * umini, two_d * umax[j] - sji));
+  }
+  return fs;
+}
+
+// MC forward-Euler stage of eq. (18): out = c0 u0 + c1 (u + dt (udot + F*/m)),
+// u_D at Dirichlet nodes (udot from the MC low-order operator)
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_mc_stage(
+    int N, const int* __restrict__ rp, const int* __restrict__ col, const double* __restrict__ mij,
+    const double* __restrict__ cc, const double* __restrict__ ccT, const double* __restrict__ ml,
+    const uint8_t* __restrict__ is_dir, const double* __restrict__ uD, const double* __restrict__ u,
+    const double* __restrict__ udot, const double* __restrict__ umax, const double* __restrict__ umin, double dt,
+    const double* __restrict__ u0, double c0, double c1, int alpha_mode, double* __restrict__ out) {
+  constexpr int RPB = kBlock / G;
+  const int lane = threadIdx.x % G, sub = threadIdx.x / G;
+  int t0, t1;
+  tile_range((N + RPB - 1) / RPB, t0, t1);
+  for (int t = t0; t < t1; ++t) {
+    const int i = t * RPB + sub;
+    if (i >= N) continue;
+    if (is_dir[i]) {
+      if (lane == 0) out[i] = c0 * u0[i] + c1 * uD[i];
+      continue;
+    }
+    double fs = mc_row_fstar<G>(i, lane, rp, col, mij, cc, ccT, u, udot, umax, umin, alpha_mode);
+    fs = gsum<G>(fs);
+    if (lane == 0) out[i] = c0 * u0[i] + c1 * (u[i] + dt * (udot[i] + fs / ml[i]));
+  }
+}
+
+// MC+CN right-hand side without the new-level correction:
+// g = M_L/dt u^{n-1} - A_low u^{n-1}/2 + (F^{n-1} + F^n)/2 + F*(u^{n-1})/2, with
+// A_low u^{n-1} = F^{n-1} - M_L udot^{n-1} on free rows; u_D on Dirichlet rows
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_mc_cn_g(
+    int N, const int* __restrict__ rp, const int* __restrict__ col, const double* __restrict__ mij,
+    const double* __restrict__ cc, const double* __restrict__ ccT, const double* __restrict__ ml,
+    const uint8_t* __restrict__ is_dir, const double* __restrict__ uD, const double* __restrict__ uo,
+    const double* __restrict__ udot, const double* __restrict__ umax, const double* __restrict__ umin,
+    const double* __restrict__ Fn, double inv_dt, int alpha_mode, double* __restrict__ g) {
+  constexpr int RPB = kBlock / G;
+  const int lane = threadIdx.x % G, sub = threadIdx.x / G;
+  int t0, t1;
+  tile_range((N + RPB - 1) / RPB, t0, t1);
+  for (int t = t0; t < t1; ++t) {
+    const int i = t * RPB + sub;
+    if (i >= N) continue;
+    if (is_dir[i]) {
+      if (lane == 0) g[i] = uD[i];
+      continue;
+    }
+    double fs = mc_row_fstar<G>(i, lane, rp, col, mij, cc, ccT, uo, udot, umax, umin, alpha_mode);
+    fs = gsum<G>(fs);
+    if (lane == 0) {
+      const double mi = ml[i];
+      g[i] = mi * inv_dt * uo[i] + 0.5 * mi * udot[i] + 0.5 * Fn[i] + 0.5 * fs;
+    }
+  }
+}
+
+// MC+CN fixed-point residual: b = g + F*(u)/2, r = b - A_cn u;
+// reductions R^2 (free rows), ||b||^2, ||r||^2
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_mc_cn_apply(
+    int N, const int* __restrict__ rp, const int* __restrict__ col, const double* __restrict__ mij,
+    const double* __restrict__ cc, const double* __restrict__ ccT, const double* __restrict__ Acn,
+    const double* __restrict__ u, const double* __restrict__ udot, const double* __restrict__ umax,
+    const double* __restrict__ umin, const double* __restrict__ g, const uint8_t* __restrict__ is_dir,
+    const double* __restrict__ uD, int alpha_mode, double* __restrict__ b, double* __restrict__ r, double* partials) {
+  constexpr int RPB = kBlock / G;
+  const int lane = threadIdx.x % G, sub = threadIdx.x / G;
+  double acc[3] = {0.0, 0.0, 0.0};
+  int t0, t1;
+  tile_range((N + RPB - 1) / RPB, t0, t1);
+  for (int t = t0; t < t1; ++t) {
+    const int i = t * RPB + sub;
+    if (i >= N) continue;
+    if (is_dir[i]) {
+      if (lane == 0) {
+        const double bi = uD[i], ri = uD[i] - u[i];
+        b[i] = bi;
+        r[i] = ri;
+        acc[1] += bi * bi;
+        acc[2] += ri * ri;
+      }
+      continue;
+    }
+    double fs = mc_row_fstar<G>(i, lane, rp, col, mij, cc, ccT, u, udot, umax, umin, alpha_mode);
+    double au = 0.0;
+    const int e = rp[i + 1];
+    for (int k = rp[i] + lane; k < e; k += G) au += Acn[k] * u[col[k]];
+    fs = gsum<G>(fs);
+    au = gsum<G>(au);
+    if (lane == 0) {
+      const double bi = g[i] + 0.5 * fs, ri = bi - au;
+      b[i] = bi;
+      r[i] = ri;
+      acc[0] += ri * ri;
+      acc[1] += bi * bi;
+      acc[2] += ri * ri;
+    }
+  }
+  block_partials<3>(acc, 3, partials, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
 // launch helpers
 // ---------------------------------------------------------------------------
 
@@ -1565,6 +1708,31 @@ void bicg_iter(H* h, const double* A, const double* dinv, const BicgVec& b) {
   k_bicg_p<<<nv, kBlock, 0, h->stream>>>(h->N, b.r, b.v, b.p, h->ks);
 }
 
+void mc_lowrate(H* h, const double* u, const double* F, double* udot, double* scratch) {
+  AFC_DISPATCH_G(h, k_ssp_lowrate, row_grid(h, false), h->N, h->row_ptr, h->col, h->AL_mcl, u, F, h->ml, h->is_dir,
+                 h->uD, 0.0, udot, scratch);
+}
+
+void mc_stage(H* h, const double* u, const double* udot, const double* umax, const double* umin, double dt,
+              const double* u0, double c0, double c1, double* out) {
+  AFC_DISPATCH_G(h, k_mc_stage, row_grid(h, false), h->N, h->row_ptr, h->col, h->mij, h->cc, h->ccT, h->ml,
+                 h->is_dir, h->uD, u, udot, umax, umin, dt, u0, c0, c1, h->opt.alpha_mode, out);
+}
+
+void mc_cn_g(H* h, const double* uo, const double* udot, const double* umax, const double* umin, const double* Fn,
+             double dt, double* g) {
+  AFC_DISPATCH_G(h, k_mc_cn_g, row_grid(h, false), h->N, h->row_ptr, h->col, h->mij, h->cc, h->ccT, h->ml,
+                 h->is_dir, h->uD, uo, udot, umax, umin, Fn, 1.0 / dt, h->opt.alpha_mode, g);
+}
+
+void mc_cn_apply(H* h, const double* u, const double* udot, const double* umax, const double* umin, const double* g,
+                 double* b, double* r) {
+  const int nb = row_grid(h, true);
+  AFC_DISPATCH_G(h, k_mc_cn_apply, nb, h->N, h->row_ptr, h->col, h->mij, h->cc, h->ccT, h->A_cn, u, udot, umax, umin,
+                 g, h->is_dir, h->uD, h->opt.alpha_mode, b, r, h->partials);
+  finish(h, nb, 3, ACT_STORE);
+}
+
 void ssp_lowrate(H* h, const double* u, const double* F, double dt, double* udot, double* ut) {
   AFC_DISPATCH_G(h, k_ssp_lowrate, row_grid(h, false), h->N, h->row_ptr, h->col, h->AL_fct, u, F, h->ml, h->is_dir,
                  h->uD, dt, udot, ut);
@@ -1628,9 +1796,9 @@ void mcl_apply(H* h, const double* u, const double* umax, const double* umin, co
   finish(h, nb, 3, ACT_STORE);
 }
 
-void build_cn_matrix(H* h, double dt) {
-  AFC_DISPATCH_G(h, k_build_cn, row_grid(h, false), h->N, h->row_ptr, h->col, h->AL_fct, h->ml, h->is_dir,
-                 1.0 / dt, h->A_cn, h->dinv_cn);
+void build_cn_matrix(H* h, const double* AL, double dt) {
+  AFC_DISPATCH_G(h, k_build_cn, row_grid(h, false), h->N, h->row_ptr, h->col, AL, h->ml, h->is_dir, 1.0 / dt,
+                 h->A_cn, h->dinv_cn);
   to_sell64(h, h->A_cn, h->S64_cn);
   to_sell32_scaled(h, h->A_cn, h->dinv_cn, h->S32_cn);
 }

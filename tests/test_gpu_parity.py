@@ -307,6 +307,82 @@ def test_sell_info_matches_host_layout():
     assert info["uniform_slices"] > info["slices"] // 2
 
 
+@pytest.mark.parametrize("stages", [1, 2, 3])
+def test_mc_ssp_parity(stages):
+    """Time-dependent MC limiter with SSP stages (Sec. 2.2) on the SSP workload
+    geometry at 12^3: 5 steps against the oracle."""
+    afc = _afc()
+    inst = I.config2(12)
+    P = O.problem_from_instance(inst, conv=True)
+    dt = inst.params["dt"]
+    print("mc ssp stages=%d" % stages, flush=True)
+    h = afc.afc_create_instance(inst, _opts(ssp_stages=stages), conv=True)
+    try:
+        u = _dev(inst.u0)
+        F = _dev(inst.F)
+        ref = inst.u0.copy()
+        for _ in range(5):
+            afc.afc_step_mc_ssprk3(h, u, F, dt)
+            if stages == 3:
+                ref = O.mc_ssp_rk3_step(P, ref, inst.F, dt)
+            elif stages == 2:
+                ref = 0.5 * (ref + O.mc_ssp_stage(P, O.mc_ssp_stage(P, ref, inst.F, dt), inst.F, dt))
+            else:
+                ref = O.mc_ssp_stage(P, ref, inst.F, dt)
+        assert _rel(u.cpu().numpy(), ref) <= 1e-12
+    finally:
+        afc.afc_destroy(h)
+
+
+@pytest.mark.parametrize("mode,name", [(1, "one"), (2, "zero")])
+def test_mc_ssp_alpha_modes(mode, name):
+    afc = _afc()
+    inst = I.config2(10)
+    P = O.problem_from_instance(inst, conv=True)
+    dt = inst.params["dt"]
+    h = afc.afc_create_instance(inst, _opts(ssp_stages=1, alpha_mode=mode), conv=True)
+    try:
+        u = _dev(inst.u0)
+        afc.afc_step_mc_ssprk3(h, u, _dev(inst.F), dt)
+        ref = O.mc_ssp_stage(P, inst.u0, inst.F, dt, alpha_mode=name)
+        assert _rel(u.cpu().numpy(), ref) <= 1e-12
+    finally:
+        afc.afc_destroy(h)
+
+
+@pytest.mark.parametrize("krylov,prec", [(0, 0), (1, 0), (1, 1)])
+def test_mc_cn_parity(krylov, prec):
+    """MC+CN on the CN workload (P1 8^3): 5 steps against the oracle."""
+    afc = _afc()
+    inst = I.config1()
+    P = O.problem_from_instance(inst, conv=True)
+    dt = inst.params["dt"]
+    print("mc cn krylov=%d prec=%d" % (krylov, prec), flush=True)
+    h = afc.afc_create_instance(inst, _opts(krylov=krylov, precision=prec, **CN_PARITY), conv=True)
+    try:
+        u = _dev(inst.u0)
+        F = _dev(inst.F)
+        ref = inst.u0.copy()
+        lin = "bicgstab" if krylov == 0 else "gmres"
+        for _ in range(5):
+            st, stats = afc.afc_step_mc_cn(h, u, F, F, dt)
+            assert st == 0, stats
+            ref, rst = O.mc_cn_step(P, ref, inst.F, inst.F, dt, tol=1e-14, tol_mode="abs", maxit=100, lin=lin,
+                                    lin_atol=1e-15)
+            assert rst.status == 0
+        tol = 1e-10 if prec == 0 else 1e-8
+        assert _rel(u.cpu().numpy(), ref) <= tol
+        # the FCT CN step on the same handle rebuilds its own CN matrix
+        u2 = _dev(inst.u0)
+        afc.afc_step_cn(h, u2, F, F, dt)
+        P2 = O.problem_from_instance(inst, conv=True)
+        ref2, _ = O.cn_fct_step(P2, inst.u0, inst.F, inst.F, dt, tol=1e-14, tol_mode="abs", maxit=100, lin=lin,
+                                lin_atol=1e-15)
+        assert _rel(u2.cpu().numpy(), ref2) <= (1e-10 if prec == 0 else 1e-8)
+    finally:
+        afc.afc_destroy(h)
+
+
 def test_mcl_single_iteration_parity():
     """One fixed-point iteration from the same low-order start (fp_maxit = 1)."""
     afc = _afc()

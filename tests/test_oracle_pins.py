@@ -457,3 +457,115 @@ def test_second_order_convergence_on_smooth_solution():
     for k, e in errs.items():
         rate = math.log2(e[-2] / e[-1])
         assert rate >= 1.8, (k, e, rate)
+
+
+def _dense_mc(inst):
+    """Dense M_C, A, D^conv (paper sign, from the convective part, Remark 1)."""
+    Md, Ad = _dense_ops(inst)
+    C = np.zeros_like(Ad)
+    C[inst.row_index(), inst.col] = -inst.K_conv
+    Dd = np.zeros_like(Ad)
+    for i in range(inst.N):
+        for j in range(inst.N):
+            if i != j and Md[i, j] != 0.0:
+                Dd[i, j] = -max(C[i, j], 0.0, C[j, i])
+        Dd[i, i] = -Dd[i].sum()
+    return Md, Ad, Dd
+
+
+@pytest.mark.parametrize("elem", ["P1", "Q1"])
+def test_mc_ssp_stage_alpha_one_and_zero_closed_forms(elem):
+    """MC forward-Euler stage (Sec. 2.2 with eqs. (18), (20), (21)): alpha = 1
+    gives u + dt M_L^{-1} (F - A u + (M_L - M_C) udot) with udot = M_L^{-1}
+    (F - (A + D^conv) u); alpha = 0 the low-order update."""
+    inst = I.build(elem, 4, 0.02, I.affine_field([1.0, -0.5, 0.25], [[0.2, 0, 0], [0, -0.1, 0], [0, 0, 0.3]]),
+                   0.4, dirichlet="inflow", u0_fn=lambda X: np.sin(3 * X[:, 0]) * np.cos(2 * X[:, 1]) + X[:, 2])
+    P = O.problem_from_instance(inst, conv=True)
+    Md, Ad, Dd = _dense_mc(inst)
+    mL = Md.sum(axis=1)
+    free = np.ones(inst.N, dtype=bool)
+    free[inst.dir_idx] = False
+    dt = 1e-3
+    F = np.linspace(0.0, 1.0, inst.N)
+    u = inst.u0.copy()
+    u[inst.dir_idx] = inst.dir_val
+    udot = (F - (Ad + Dd) @ u) / mL
+    udot[~free] = 0.0
+    ref1 = u + dt * (F - Ad @ u + (np.diag(mL) - Md) @ udot) / mL
+    ref0 = u + dt * udot
+    for ref in (ref1, ref0):
+        ref[~free] = inst.dir_val
+    got1 = O.mc_ssp_stage(P, u, F, dt, alpha_mode="one")
+    got0 = O.mc_ssp_stage(P, u, F, dt, alpha_mode="zero")
+    np.testing.assert_allclose(got1, ref1, rtol=0, atol=1e-13 * np.abs(ref1).max())
+    np.testing.assert_allclose(got0, ref0, rtol=0, atol=1e-13 * np.abs(ref0).max())
+
+
+def test_mc_ssp_stage_keeps_local_bounds_for_pure_convection():
+    """Pure convection with a constant velocity, no Dirichlet nodes, F = 0 and
+    dt below m_i / (2 sum_j |d_ij|).  At an interior node the convection
+    entries are skew (a_ji = -a_ij, so |a_ij| <= d_ij and the bar states lie
+    between u_i and u_j), and the MC stage is a convex combination of bar
+    states clipped to [u^min, u^max]: each new value lies in the range of its
+    neighbourhood (Sec. 2.2, eq. (22)).  Boundary rows carry the boundary
+    integral of b.n and are not covered."""
+    inst = I.build("Q1", 6, 0.0, I.affine_field([0.8, -0.45, 0.3]), 0.0, dirichlet="none",
+                   u0_fn=lambda X: (np.sum((X - 0.5) ** 2, axis=1) < 0.09).astype(float) + 0.3 * X[:, 0])
+    P = O.problem_from_instance(inst, conv=True)
+    d, _ = O.mc_operators(P)
+    dsum = P.row_sum(np.where(P.offd, np.abs(d), 0.0))
+    dt = 0.9 * float(np.min(P.m / (2.0 * dsum)))
+    u = inst.u0
+    un = O.mc_ssp_stage(P, u, np.zeros(inst.N), dt)
+    umax = P.row_max(u[P.col])
+    umin = P.row_min(u[P.col])
+    span = float(u.max() - u.min())
+    inner = np.all((inst.coords > 1e-12) & (inst.coords < 1 - 1e-12), axis=1)
+    assert np.all(un[inner] <= umax[inner] + 1e-13 * span) and np.all(un[inner] >= umin[inner] - 1e-13 * span)
+    # the unlimited (alpha = 1) stage leaves the bounds on the same data
+    u1 = O.mc_ssp_stage(P, u, np.zeros(inst.N), dt, alpha_mode="one")
+    assert np.any(u1[inner] > umax[inner] + 1e-6 * span) or np.any(u1[inner] < umin[inner] - 1e-6 * span)
+
+
+@pytest.mark.parametrize("elem,lin", [("P1", "bicgstab"), ("Q1", "gmres")])
+def test_mc_cn_alpha_one_and_zero_dense(elem, lin):
+    """MC+CN (Sec. 2.2): with alpha = 1 the correction is linear,
+    F*(u) = (M_L - M_C) M_L^{-1} (F - A_low u) + D u at each time level, so the
+    converged fixed point solves one dense system; alpha = 0 is low-order CN."""
+    inst = I.build(elem, 4, 0.05, I.affine_field([1.0, -0.5, 0.25]), 0.5, dirichlet="inflow",
+                   u0_fn=lambda X: np.exp(-20 * np.sum((X - 0.4) ** 2, axis=1)))
+    P = O.problem_from_instance(inst, conv=True)
+    Md, Ad, Dd = _dense_mc(inst)
+    mL = Md.sum(axis=1)
+    AL = Ad + Dd
+    dirs = inst.dir_idx
+    free = np.ones(inst.N, dtype=bool)
+    free[dirs] = False
+    dt = 0.02
+    Fo = np.full(inst.N, 0.1)
+    Fn = np.full(inst.N, 0.3)
+    u = inst.u0.copy()
+    u[dirs] = inst.dir_val
+    # udot(v, F) = Z (F - AL v) on free rows (0 on Dirichlet rows)
+    Z = np.diag(np.where(free, 1.0 / mL, 0.0))
+    Q = np.diag(mL) - Md
+    # (M_L/dt + AL/2) u^n - 1/2 [Q Z (Fn - AL u^n) + D u^n] = (M_L/dt - AL/2) u + (Fo + Fn)/2
+    #                                                        + 1/2 [Q Z (Fo - AL u) + D u]
+    L1 = np.diag(mL) / dt + 0.5 * AL + 0.5 * (Q @ Z @ AL) - 0.5 * Dd
+    rhs1 = (np.diag(mL) / dt - 0.5 * AL) @ u + 0.5 * (Fo + Fn) + 0.5 * (Q @ Z @ Fn) \
+        + 0.5 * (Q @ Z @ (Fo - AL @ u) + Dd @ u)
+    L0 = np.diag(mL) / dt + 0.5 * AL
+    rhs0 = (np.diag(mL) / dt - 0.5 * AL) @ u + 0.5 * (Fo + Fn)
+    for L, rhs in ((L1, rhs1), (L0, rhs0)):
+        L[dirs, :] = 0.0
+        L[dirs, dirs] = 1.0
+        rhs[dirs] = inst.dir_val
+    ref1 = np.linalg.solve(L1, rhs1)
+    ref0 = np.linalg.solve(L0, rhs0)
+    u1, st = O.mc_cn_step(P, u, Fo, Fn, dt, alpha_mode="one", tol=1e-14, tol_mode="rel", maxit=2000, lin=lin,
+                          lin_atol=0.0, lin_rtol=1e-15)
+    assert st.status == O.STATUS_OK
+    np.testing.assert_allclose(u1, ref1, rtol=0, atol=1e-10 * np.abs(ref1).max())
+    u0, _ = O.mc_cn_step(P, u, Fo, Fn, dt, alpha_mode="zero", tol=1e-15, tol_mode="rel", maxit=5, lin=lin,
+                         lin_atol=0.0, lin_rtol=1e-15)
+    np.testing.assert_allclose(u0, ref0, rtol=0, atol=1e-12 * np.abs(ref0).max())
