@@ -397,6 +397,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=128, help="cells per direction (128 is the workload)")
     ap.add_argument("--fp64-steps", type=int, default=5)
+    ap.add_argument("--mu-steps", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
@@ -520,6 +521,22 @@ def main():
         e3 = time.perf_counter() - t0
         fp64 = {"value": N * s3["fp_iters"] / e3, "ms_per_step": 1e3 * e3 / max(1, s3["fp_iters"]),
                 "krylov_per_step": s3["krylov_iters"] / max(1, s3["fp_iters"]), "steps": s3["fp_iters"]}
+    # --- the MU limiter (Sec. 3.2) on the same problem (secondary) ----------
+    mu = None
+    if args.mu_steps > 0:
+        o = opts(fp_maxit=0, limiter=afc.AFC_LIMITER_MU)
+        afc.afc_set_options(h, o)
+        umu = torch.zeros(N, dtype=torch.float64, device=dev)
+        afc.afc_solve_stationary(h, umu, F, init_low_order=True)
+        afc.afc_set_options(h, opts(fp_maxit=args.mu_steps, limiter=afc.AFC_LIMITER_MU))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, s4 = afc.afc_solve_stationary(h, umu, F)
+        torch.cuda.synchronize()
+        e4 = time.perf_counter() - t0
+        mu = {"value": N * s4["fp_iters"] / e4, "ms_per_step": 1e3 * e4 / max(1, s4["fp_iters"]),
+              "krylov_per_step": s4["krylov_iters"] / max(1, s4["fp_iters"]), "steps": s4["fp_iters"],
+              "nonlinear_residual": {"first": s4["res0"], "last": s4["res"]}}
     afc.afc_destroy(h)
 
     batch = None
@@ -566,6 +583,7 @@ def main():
         "hbm_gbs_model": model_bytes / elapsed / 1e9,
         "nonlinear_residual": {"first": s["res0"], "last": s["res"]},
         "fp64": fp64,
+        "mu_limiter": mu,
         "batch": batch,
         "cn": cn,
         "serving": serve,

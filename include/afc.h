@@ -71,6 +71,12 @@ enum { AFC_PREC_FP64 = 0, AFC_PREC_MIXED = 1 };
  * residual over non-Dirichlet rows. */
 enum { AFC_TOL_ABS_SQRTN = 0, AFC_TOL_REL = 1 };
 
+/* Limiter of the stationary scheme (afc_solve_stationary). */
+enum { AFC_LIMITER_MCL = 0, /* monolithic convex limiter, Sec. 3.1 (D, bar states from K_conv)   */
+       AFC_LIMITER_MU = 1   /* monolithic upwind limiter, Sec. 3.2 (D and the edge orientation
+                               a_ji <= a_ij from the full matrix A = -K)                       */
+};
+
 typedef struct {
   int32_t n;                /* number of nodes N (> 0)                         */
   int64_t nnz;              /* number of stored entries (< 2^31)               */
@@ -112,6 +118,7 @@ typedef struct {
   int32_t lanes_per_row;    /* 0 = automatic; else 8, 16, 32 or 64             */
   int32_t profile;          /* 1: time every launch of the hot kernels with HIP
                                events on the handle's stream (afc_kernel_time) */
+  int32_t limiter;          /* AFC_LIMITER_* of afc_solve_stationary          */
   int32_t graphs;           /* 1 (default): each GMRES cycle is captured once
                                as a HIP graph and replayed (same kernels, same
                                results); 0: plain launches.  Not used while
@@ -206,11 +213,15 @@ afc_status afc_step_mc_ssprk3(afc_handle *h, double *u, const double *F, double 
 afc_status afc_step_mc_cn(afc_handle *h, double *u, const double *F_old, const double *F_new, double dt,
                           afc_stats *stats);
 
-/* Stationary MCL scheme (Sec. 3.1): fixed-point iteration of Sec. 4 for
+/* Stationary AFC scheme: fixed-point iteration of Sec. 4 for
  * A_low u = F + F*(u), where F* sums the fluxes r^ss_ij = d_ij (u_j - u_i)
- * of eq. (25) limited by eq. (22).  u: in initial guess, out solution
- * (device).  If init_low_order is nonzero the guess is first replaced by the
- * low-order solution A_low u = F.  F: load vector (device). */
+ * of eq. (25) limited by options.limiter: the MC limiter of eq. (22)
+ * (Sec. 3.1; D and the bar states from K_conv, Remark 1) or the MU limiter
+ * of Sec. 3.2 (D from A = -K; node i owns edge (i, j) when a_ji <= a_ij,
+ * and when a_ji = a_ij the smaller of both nodes' factors is used).
+ * u: in initial guess, out solution (device).  If init_low_order is nonzero
+ * the guess is first replaced by the low-order solution A_low u = F.
+ * F: load vector (device). */
 afc_status afc_solve_stationary(afc_handle *h, double *u, const double *F, int32_t init_low_order,
                                 afc_stats *stats);
 

@@ -626,6 +626,88 @@ def stationary_mcl(P: AFCProblem, F, u0, *, alpha_mode="limited", tol=1e-8, tol_
 
 
 # ----------------------------------------------------------------------------
+# Stationary problem with the monolithic upwind (MU) limiter (Sec. 3.2)
+# ----------------------------------------------------------------------------
+
+
+def mu_limited_fluxes(P: AFCProblem, u, d, a, alpha_mode="limited"):
+    """MU limiter (Sec. 3.2, steps 1-4) for r^ss_ij = d_ij (u_j - u_i) of
+    eq. (25), with a the matrix a_ij of eq. (4).  Node i counts the edge (i, j)
+    in P_i when a_ji <= a_ij (steps 1, 4); Q_i sums every flux of row i
+    (step 2).  alpha_ij = alpha_ji is taken from the node that owns the edge;
+    when a_ji = a_ij both nodes own it and the smaller value is taken.
+    Returns (r*_ij, alpha_ij, R+, R-); no flux is formed on Dirichlet rows."""
+    i, j = P.rows, P.col
+    r = np.where(P.offd & ~P.is_dir[i], d * (u[j] - u[i]), 0.0)
+    rp = np.maximum(r, 0.0)
+    rm = np.minimum(r, 0.0)
+    aT = a[P.tpos]  # a_ji at entry (i, j)
+    owns = P.offd & (aT <= a)
+    Pp = P.row_sum(np.where(owns, rp, 0.0))
+    Pm = P.row_sum(np.where(owns, rm, 0.0))
+    Qp = -P.row_sum(rm)
+    Qm = -P.row_sum(rp)
+    Rp = np.ones(P.N)
+    Rm = np.ones(P.N)
+    nz = Pp != 0.0
+    Rp[nz] = np.minimum(1.0, Qp[nz] / Pp[nz])
+    nz = Pm != 0.0
+    Rm[nz] = np.minimum(1.0, Qm[nz] / Pm[nz])
+    Rp[P.is_dir] = 1.0
+    Rm[P.is_dir] = 1.0
+    abar = np.where(r > 0.0, Rp[i], np.where(r < 0.0, Rm[i], 1.0))  # step 4, from node i
+    abarT = abar[P.tpos]  # the same edge seen from node j
+    alpha = np.where(aT < a, abar, np.where(aT > a, abarT, np.minimum(abar, abarT)))
+    if alpha_mode == "one":
+        alpha = np.ones_like(alpha)
+    elif alpha_mode == "zero":
+        alpha = np.zeros_like(alpha)
+    return alpha * r, alpha, Rp, Rm
+
+
+def stationary_mu(P: AFCProblem, F, u0, *, alpha_mode="limited", tol=1e-8, tol_mode="rel", maxit=500,
+                  lin="gmres", lin_atol=0.0, lin_rtol=1e-10, lin_maxit=20000, restart=30, omega=1.0,
+                  dynamic_damping=False):
+    """Fixed-point iteration (Sec. 4) for A_low u = F + F*(u) with the MU
+    limiter of Sec. 3.2; D and A_low = A + D from the matrix A of eq. (4)."""
+    d = artificial_diffusion(P, P.a)
+    As = P.with_dirichlet_rows(low_order_operator(P, P.a, d))
+    u = np.asarray(u0, dtype=np.float64).copy()
+    u[P.is_dir] = P.uD[P.is_dir]
+    st = FixedPointStats()
+    R0 = None
+    R_prev = None
+    w_omega = omega
+    nu = 0
+    while True:
+        rstar = mu_limited_fluxes(P, u, d, P.a, alpha_mode)[0]
+        b = F + P.row_sum(rstar)
+        b[P.is_dir] = P.uD[P.is_dir]
+        res = b - P.matvec(As, u)
+        R = float(np.linalg.norm(res[~P.is_dir]))
+        if R0 is None:
+            R0 = R
+        st.residuals.append(R)
+        if R == 0.0 or _fp_converged(R, R0, P.N, tol, tol_mode):
+            break
+        if nu >= maxit:
+            st.status = STATUS_WMAXIT
+            break
+        w_omega = _next_omega(w_omega, R, R_prev, dynamic_damping)
+        kr = krylov(P, As, b, u, lin, lin_atol, lin_rtol, lin_maxit, restart)
+        st.krylov_iters.append(kr.iters)
+        if kr.status < 0:
+            st.status = kr.status
+            u = kr.x
+            break
+        u = u + w_omega * (kr.x - u)
+        R_prev = R
+        nu += 1
+    st.iters = nu
+    return u, st
+
+
+# ----------------------------------------------------------------------------
 # Time-dependent monolithic convex limiting (Sec. 2.2): MC+SSP and MC+CN
 # ----------------------------------------------------------------------------
 

@@ -26,6 +26,7 @@ AFC_ALPHA_LIMITED, AFC_ALPHA_ONE, AFC_ALPHA_ZERO = 0, 1, 2
 AFC_KRYLOV_BICGSTAB, AFC_KRYLOV_GMRES = 0, 1
 AFC_PREC_FP64, AFC_PREC_MIXED = 0, 1
 AFC_TOL_ABS_SQRTN, AFC_TOL_REL = 0, 1
+AFC_LIMITER_MCL, AFC_LIMITER_MU = 0, 1
 
 
 class afc_problem(ctypes.Structure):
@@ -43,7 +44,8 @@ class afc_options(ctypes.Structure):
         ("inner_rtol", c_double), ("inner_maxit", c_int32), ("refine_maxit", c_int32),
         ("fp_tol", c_double), ("fp_tol_mode", c_int32), ("fp_maxit", c_int32),
         ("prelimit", c_double), ("omega", c_double), ("dynamic_damping", c_int32),
-        ("ssp_stages", c_int32), ("lanes_per_row", c_int32), ("profile", c_int32), ("graphs", c_int32),
+        ("ssp_stages", c_int32), ("lanes_per_row", c_int32), ("profile", c_int32), ("limiter", c_int32),
+        ("graphs", c_int32),
         ("stream", c_void_p),
     ]
 

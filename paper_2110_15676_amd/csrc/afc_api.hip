@@ -68,6 +68,7 @@ afc_status check_options(const afc_options& o, std::string& why) {
   if (o.ssp_stages < 1 || o.ssp_stages > 3) return why = "ssp_stages must be 1, 2 or 3", AFC_EINVAL;
   if (o.profile != 0 && o.profile != 1) return why = "profile must be 0 or 1", AFC_EINVAL;
   if (o.graphs != 0 && o.graphs != 1) return why = "graphs must be 0 or 1", AFC_EINVAL;
+  if (o.limiter != AFC_LIMITER_MCL && o.limiter != AFC_LIMITER_MU) return why = "limiter", AFC_EINVAL;
   if (o.lanes_per_row != 0 && o.lanes_per_row != 8 && o.lanes_per_row != 16 && o.lanes_per_row != 32 &&
       o.lanes_per_row != 64)
     return why = "lanes_per_row must be 0, 8, 16, 32 or 64", AFC_EINVAL;
@@ -118,7 +119,7 @@ void free_all(afc_handle* h) {
     p = nullptr;
   };
   f(h->row_ptr); f(h->col); f(h->is_dir); f(h->uD); f(h->ml);
-  f(h->mij); f(h->dp_fct); f(h->AL_fct);
+  f(h->mij); f(h->dp_fct); f(h->AL_fct); f(h->mu_own);
   f(h->cc); f(h->ccT); f(h->AL_mcl); f(h->dinv_mcl);
   f(h->A_cn); f(h->dinv_cn);
   f(h->sl_ptr); f(h->sl_dl); f(h->sl_pat); f(h->sl_dlt); f(h->sell_pos); f(h->S64_mcl); f(h->S32_mcl); f(h->S64_cn); f(h->S32_cn);
@@ -449,6 +450,7 @@ struct HostOps {
   std::vector<uint8_t> is_dir;
   std::vector<double> dp, AL;              // FCT: d+ from K, A_low (Dirichlet rows identity)
   std::vector<double> c, cT, ALc, dinv;    // MCL: convective c, c^T, A_low from it, 1/diag
+  std::vector<uint8_t> mu_own;             // MU: 1 if a_ji < a_ij, 2 if a_ji > a_ij, 0 if equal
 };
 
 void check_problem(const afc_problem* p) {
@@ -555,6 +557,12 @@ void prepare_ops(afc_handle* h, const afc_problem* p, HostOps& o) {
   std::vector<double> a((size_t)nnz);
   for (int64_t k = 0; k < nnz; ++k) a[k] = -K[k];
   build_low(a, o.dp, o.AL);
+  // MU (Sec. 3.2): which node of the edge counts it in P_i (a_ji <= a_ij)
+  o.mu_own.assign((size_t)nnz, 0);
+  for (int64_t k = 0; k < nnz; ++k) {
+    const double aij = a[k], aji = a[tpos[k]];
+    o.mu_own[k] = aji < aij ? 1 : (aji > aij ? 2 : 0);
+  }
   // MCL: c = -K_conv (or a), c^T in CSR order, A_low from the convective D (Remark 1)
   std::vector<double>& c = o.c;
   c = a;
@@ -691,6 +699,7 @@ afc_status afc_create(const afc_problem* p, const afc_options* opt, afc_handle**
     h->mij = upload(h, ops.M, h->stream);
     h->dp_fct = upload(h, ops.dp, h->stream);
     h->AL_fct = upload(h, ops.AL, h->stream);
+    h->mu_own = upload(h, ops.mu_own, h->stream);
     h->cc = upload(h, ops.c, h->stream);
     h->ccT = upload(h, ops.cT, h->stream);
     h->AL_mcl = upload(h, ops.ALc, h->stream);
@@ -853,8 +862,9 @@ afc_status afc_step_ssprk3(afc_handle* h, double* u, const double* F, double dt,
       &a);
 }
 
-// CN system matrix M_L/dt + AL/2 for the scheme's low-order operator AL,
-// rebuilt when dt or the operator changes
+// System matrix kept in the handle's CN storage: M_L/dt + AL/2 for a CN step
+// (dt > 0), or AL itself for a stationary solve (dt = 0); rebuilt when dt or
+// the low-order operator changes
 void ensure_cn_matrix(afc_handle* h, const double* AL, double dt) {
   if (h->cn_dt == dt && h->cn_src == AL) return;
   afc::build_cn_matrix(h, AL, dt);
@@ -1058,7 +1068,12 @@ afc_status afc_solve_stationary(afc_handle* h, double* u, const double* F, int32
       h, st,
       [](afc_handle* h, void* ctx) -> afc_status {
         const StatArgs& a = *static_cast<StatArgs*>(ctx);
-        const SysMat S{h->AL_mcl, h->dinv_mcl, h->S64_mcl, h->S32_mcl};
+        const bool mu = h->opt.limiter == AFC_LIMITER_MU;
+        // MCL: A_low from the convective D (Remark 1); MU: A_low = A + D from A,
+        // assembled into the handle's CN storage
+        if (mu) ensure_cn_matrix(h, h->AL_fct, 0.0);
+        const SysMat S = mu ? SysMat{h->A_cn, h->dinv_cn, h->S64_cn, h->S32_cn}
+                            : SysMat{h->AL_mcl, h->dinv_mcl, h->S64_mcl, h->S32_mcl};
         double* b = h->w[W_B];
         double* r = h->w[W_R];
         if (a.init_low) {  // low-order solution A_low u = F (alpha = 0), from zero
@@ -1080,8 +1095,13 @@ afc_status afc_solve_stationary(afc_handle* h, double* u, const double* F, int32
         double* umax = h->w[W_A];
         double* umin = h->w[W_B2];
         auto eval = [&](double* u, double* bb, double* rr) {
-          afc::mcl_bounds(h, u, umax, umin);
-          afc::mcl_apply(h, u, umax, umin, a.F, bb, rr);
+          if (mu) {
+            afc::mu_R(h, u, umax, umin);  // R+ and R- of Sec. 3.2 in the same two vectors
+            afc::mu_apply(h, u, umax, umin, a.F, bb, rr);
+          } else {
+            afc::mcl_bounds(h, u, umax, umin);
+            afc::mcl_apply(h, u, umax, umin, a.F, bb, rr);
+          }
         };
         return fixed_point(h, a.u, S, eval, a.st);
       },

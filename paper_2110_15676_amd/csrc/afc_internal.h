@@ -70,6 +70,7 @@ struct afc_handle_s {
   double* mij = nullptr;
   double* dp_fct = nullptr;
   double* AL_fct = nullptr;
+  uint8_t* mu_own = nullptr;  // MU edge orientation per CSR entry (1: a_ji < a_ij, 2: a_ji > a_ij, 0: equal)
 
   // MCL data: convective c_ij, c_ji (transposed, CSR order), A_low from K_conv
   double* cc = nullptr;

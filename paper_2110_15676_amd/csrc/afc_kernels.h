@@ -52,6 +52,10 @@ void bicg_iter(H* h, const double* A, const double* dinv, const BicgVec& b);
 // --- Zalesak FCT, explicit SSP stage -------------------------------------------
 void ssp_lowrate(H* h, const double* u, const double* F, double dt, double* udot, double* ut);
 
+// --- MU limiter (Sec. 3.2); the system matrix is in the CN storage (A_cn = A_low) ---
+void mu_R(H* h, const double* u, double* Rp, double* Rm);
+void mu_apply(H* h, const double* u, const double* Rp, const double* Rm, const double* F, double* b, double* r);
+
 // --- time-dependent MC limiting (Sec. 2.2) ----------------------------------------
 void mc_lowrate(H* h, const double* u, const double* F, double* udot, double* scratch);  // udot = (F - A_low^mc u)/m
 void mc_stage(H* h, const double* u, const double* udot, const double* umax, const double* umin, double dt,

@@ -120,15 +120,16 @@ __global__ __launch_bounds__(kBlock) void k_relax(int N, double* __restrict__ u,
 }
 
 // ---------------------------------------------------------------------------
-// CN system matrix M_L/dt + A_low/2 (Dirichlet rows identity) and its FP32
-// Jacobi-scaled copy
+// System matrix scale A_low + M_L/dt (Dirichlet rows identity): the CN matrix
+// M_L/dt + A_low/2, or A_low itself (scale 1, no mass term)
 // ---------------------------------------------------------------------------
 
 template <int G>
 __global__ __launch_bounds__(kBlock) void k_build_cn(int N, const int* __restrict__ rp, const int* __restrict__ col,
                                                      const double* __restrict__ AL, const double* __restrict__ ml,
-                                                     const uint8_t* __restrict__ is_dir, double inv_dt,
-                                                     double* __restrict__ Acn, double* __restrict__ dinv) {
+                                                     const uint8_t* __restrict__ is_dir, double scale,
+                                                     double inv_dt, double* __restrict__ Acn,
+                                                     double* __restrict__ dinv) {
   constexpr int RPB = kBlock / G;
   const int lane = threadIdx.x % G, sub = threadIdx.x / G;
   int t0, t1;
@@ -144,7 +145,7 @@ __global__ __launch_bounds__(kBlock) void k_build_cn(int N, const int* __restric
       if (dir) {
         v = (j == i) ? 1.0 : 0.0;
       } else {
-        v = 0.5 * AL[k];
+        v = scale * AL[k];
         if (j == i) v += ml[i] * inv_dt;
       }
       Acn[k] = v;
@@ -1461,6 +1462,115 @@ __global__ __launch_bounds__(kBlock) void k_mc_cn_apply(
 }
 
 // ---------------------------------------------------------------------------
+// Monolithic upwind limiter (Sec. 3.2) of r^ss_ij = d_ij (u_j - u_i),
+// d_ij = -d+_ij from the matrix A (eq. (5)); own[k] orients each edge
+// (1: a_ji < a_ij, node i; 2: a_ji > a_ij, node j; 0: both)
+// ---------------------------------------------------------------------------
+
+// P+-_i over the edges node i owns, Q+-_i over all its fluxes, R+-_i
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_mu_R(int N, const int* __restrict__ rp, const int* __restrict__ col,
+                                                 const double* __restrict__ dp, const uint8_t* __restrict__ own,
+                                                 const double* __restrict__ u, const uint8_t* __restrict__ is_dir,
+                                                 double* __restrict__ Rp, double* __restrict__ Rm) {
+  constexpr int RPB = kBlock / G;
+  const int lane = threadIdx.x % G, sub = threadIdx.x / G;
+  int t0, t1;
+  tile_range((N + RPB - 1) / RPB, t0, t1);
+  for (int t = t0; t < t1; ++t) {
+    const int i = t * RPB + sub;
+    if (i >= N) continue;
+    if (is_dir[i]) {
+      if (lane == 0) Rp[i] = Rm[i] = 1.0;
+      continue;
+    }
+    const double ui = u[i];
+    double pp = 0.0, pm = 0.0, qp = 0.0, qm = 0.0;
+    const int e = rp[i + 1];
+    for (int k = rp[i] + lane; k < e; k += G) {
+      const int j = col[k];
+      if (j == i) continue;
+      const double rf = -dp[k] * (u[j] - ui);
+      const double rpos = fmax(rf, 0.0), rneg = fmin(rf, 0.0);
+      if (own[k] != 2) {
+        pp += rpos;
+        pm += rneg;
+      }
+      qp -= rneg;
+      qm -= rpos;
+    }
+    pp = gsum<G>(pp);
+    pm = gsum<G>(pm);
+    qp = gsum<G>(qp);
+    qm = gsum<G>(qm);
+    if (lane == 0) {
+      Rp[i] = pp != 0.0 ? fmin(1.0, qp / pp) : 1.0;
+      Rm[i] = pm != 0.0 ? fmin(1.0, qm / pm) : 1.0;
+    }
+  }
+}
+
+// alpha_ij = alpha_ji from the owning node (the smaller of both when equal),
+// F*_i = sum_j alpha_ij r_ij; b = F + F*, r = b - A u ; reductions R^2 (free
+// rows), ||b||^2, ||r||^2
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_mu_apply(
+    int N, const int* __restrict__ rp, const int* __restrict__ col, const double* __restrict__ dp,
+    const uint8_t* __restrict__ own, const double* __restrict__ As, const double* __restrict__ u,
+    const double* __restrict__ Rp, const double* __restrict__ Rm, const double* __restrict__ F,
+    const uint8_t* __restrict__ is_dir, const double* __restrict__ uD, int alpha_mode, double* __restrict__ b,
+    double* __restrict__ r, double* partials) {
+  constexpr int RPB = kBlock / G;
+  const int lane = threadIdx.x % G, sub = threadIdx.x / G;
+  double acc[3] = {0.0, 0.0, 0.0};
+  int t0, t1;
+  tile_range((N + RPB - 1) / RPB, t0, t1);
+  for (int t = t0; t < t1; ++t) {
+    const int i = t * RPB + sub;
+    if (i >= N) continue;
+    if (is_dir[i]) {
+      if (lane == 0) {
+        const double bi = uD[i], ri = uD[i] - u[i];
+        b[i] = bi;
+        r[i] = ri;
+        acc[1] += bi * bi;
+        acc[2] += ri * ri;
+      }
+      continue;
+    }
+    const double ui = u[i], rpi = Rp[i], rmi = Rm[i];
+    double fs = 0.0, au = 0.0;
+    const int e = rp[i + 1];
+    for (int k = rp[i] + lane; k < e; k += G) {
+      const int j = col[k];
+      const double uj = u[j];
+      au += As[k] * uj;
+      if (j == i || alpha_mode == AFC_ALPHA_ZERO) continue;
+      const double rf = -dp[k] * (uj - ui);
+      double a = 1.0;
+      if (alpha_mode == AFC_ALPHA_LIMITED) {
+        const double ai = rf > 0.0 ? rpi : (rf < 0.0 ? rmi : 1.0);         // node i, flux r_ij
+        const double aj = rf < 0.0 ? Rp[j] : (rf > 0.0 ? Rm[j] : 1.0);     // node j, flux r_ji = -r_ij
+        const int o = own[k];
+        a = o == 1 ? ai : (o == 2 ? aj : fmin(ai, aj));
+      }
+      fs += a * rf;
+    }
+    fs = gsum<G>(fs);
+    au = gsum<G>(au);
+    if (lane == 0) {
+      const double bi = F[i] + fs, ri = bi - au;
+      b[i] = bi;
+      r[i] = ri;
+      acc[0] += ri * ri;
+      acc[1] += bi * bi;
+      acc[2] += ri * ri;
+    }
+  }
+  block_partials<3>(acc, 3, partials, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
 // launch helpers
 // ---------------------------------------------------------------------------
 
@@ -1708,6 +1818,18 @@ void bicg_iter(H* h, const double* A, const double* dinv, const BicgVec& b) {
   k_bicg_p<<<nv, kBlock, 0, h->stream>>>(h->N, b.r, b.v, b.p, h->ks);
 }
 
+void mu_R(H* h, const double* u, double* Rp, double* Rm) {
+  AFC_DISPATCH_G_TIMED(h, AFC_KERNEL_MCL, k_mu_R, row_grid(h, false), h->N, h->row_ptr, h->col, h->dp_fct,
+                       h->mu_own, u, h->is_dir, Rp, Rm);
+}
+
+void mu_apply(H* h, const double* u, const double* Rp, const double* Rm, const double* F, double* b, double* r) {
+  const int nb = row_grid(h, true);
+  AFC_DISPATCH_G_TIMED(h, AFC_KERNEL_MCL, k_mu_apply, nb, h->N, h->row_ptr, h->col, h->dp_fct, h->mu_own, h->A_cn, u,
+                       Rp, Rm, F, h->is_dir, h->uD, h->opt.alpha_mode, b, r, h->partials);
+  finish(h, nb, 3, ACT_STORE);
+}
+
 void mc_lowrate(H* h, const double* u, const double* F, double* udot, double* scratch) {
   AFC_DISPATCH_G(h, k_ssp_lowrate, row_grid(h, false), h->N, h->row_ptr, h->col, h->AL_mcl, u, F, h->ml, h->is_dir,
                  h->uD, 0.0, udot, scratch);
@@ -1797,7 +1919,8 @@ void mcl_apply(H* h, const double* u, const double* umax, const double* umin, co
 }
 
 void build_cn_matrix(H* h, const double* AL, double dt) {
-  AFC_DISPATCH_G(h, k_build_cn, row_grid(h, false), h->N, h->row_ptr, h->col, AL, h->ml, h->is_dir, 1.0 / dt,
+  const double scale = dt > 0.0 ? 0.5 : 1.0, inv_dt = dt > 0.0 ? 1.0 / dt : 0.0;
+  AFC_DISPATCH_G(h, k_build_cn, row_grid(h, false), h->N, h->row_ptr, h->col, AL, h->ml, h->is_dir, scale, inv_dt,
                  h->A_cn, h->dinv_cn);
   to_sell64(h, h->A_cn, h->S64_cn);
   to_sell32_scaled(h, h->A_cn, h->dinv_cn, h->S32_cn);

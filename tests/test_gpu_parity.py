@@ -383,6 +383,54 @@ def test_mc_cn_parity(krylov, prec):
         afc.afc_destroy(h)
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_mu_stationary_parity(prec):
+    """Stationary MU limiter (Sec. 3.2) on the stationary workload at 12^3,
+    solved to convergence on both sides."""
+    afc = _afc()
+    inst = I.config3(12)
+    P = O.problem_from_instance(inst, conv=True)
+    ref, rst = O.stationary_mu(P, inst.F, np.zeros(inst.N), tol=1e-12, tol_mode="rel", maxit=3000, lin_rtol=1e-14)
+    assert rst.status == 0
+    print("mu n=12 prec=%d oracle fp its %d" % (prec, rst.iters), flush=True)
+    h = afc.afc_create_instance(inst, _opts(precision=prec, limiter=afc.AFC_LIMITER_MU, fp_tol=1e-12, fp_tol_mode=1,
+                                            fp_maxit=3000, lin_atol=0.0, lin_rtol=1e-14), conv=True)
+    try:
+        u = _dev(np.zeros(inst.N))
+        st, stats = afc.afc_solve_stationary(h, u, _dev(inst.F))
+        assert st == 0, stats
+        tol = 1e-10 if prec == 0 else 1e-8
+        assert _rel(u.cpu().numpy(), ref) <= tol
+    finally:
+        afc.afc_destroy(h)
+
+
+@pytest.mark.parametrize("mode,name", [(1, "one"), (2, "zero")])
+def test_mu_alpha_modes_and_renumbered(mode, name):
+    afc = _afc()
+    inst = I.renumbered(I.config3(8))
+    P = O.problem_from_instance(inst, conv=True)
+    ref, _ = O.stationary_mu(P, inst.F, np.zeros(inst.N), alpha_mode=name, tol=1e-13, tol_mode="rel", maxit=50,
+                             lin_rtol=1e-14)
+    h = afc.afc_create_instance(inst, _opts(limiter=afc.AFC_LIMITER_MU, alpha_mode=mode, fp_tol=1e-13, fp_tol_mode=1,
+                                            fp_maxit=50, lin_atol=0.0, lin_rtol=1e-14), conv=True)
+    try:
+        u = _dev(np.zeros(inst.N))
+        afc.afc_solve_stationary(h, u, _dev(inst.F))
+        assert _rel(u.cpu().numpy(), ref) <= 1e-10
+        # the same handle switched back to MCL solves the MCL scheme
+        o = _opts(limiter=afc.AFC_LIMITER_MCL, alpha_mode=mode, fp_tol=1e-13, fp_tol_mode=1, fp_maxit=50,
+                  lin_atol=0.0, lin_rtol=1e-14)
+        afc.afc_set_options(h, o)
+        u2 = _dev(np.zeros(inst.N))
+        afc.afc_solve_stationary(h, u2, _dev(inst.F))
+        ref2, _ = O.stationary_mcl(P, inst.F, np.zeros(inst.N), alpha_mode=name, tol=1e-13, tol_mode="rel",
+                                   maxit=50, lin_rtol=1e-14)
+        assert _rel(u2.cpu().numpy(), ref2) <= 1e-10
+    finally:
+        afc.afc_destroy(h)
+
+
 def test_mcl_single_iteration_parity():
     """One fixed-point iteration from the same low-order start (fp_maxit = 1)."""
     afc = _afc()

@@ -569,3 +569,138 @@ def test_mc_cn_alpha_one_and_zero_dense(elem, lin):
     u0, _ = O.mc_cn_step(P, u, Fo, Fn, dt, alpha_mode="zero", tol=1e-15, tol_mode="rel", maxit=5, lin=lin,
                          lin_atol=0.0, lin_rtol=1e-15)
     np.testing.assert_allclose(u0, ref0, rtol=0, atol=1e-12 * np.abs(ref0).max())
+
+
+def _mu_chain3():
+    g = json.load(open(os.path.join(GOLDEN, "mu_chain3.json")))
+    rp = np.array(g["pattern"]["row_ptr"])
+    col = np.array(g["pattern"]["col"])
+    a = np.zeros(col.shape[0])
+    for i in range(3):
+        for k in range(rp[i], rp[i + 1]):
+            a[k] = g["a"]["%d,%d" % (i, col[k])]
+    P = O.AFCProblem(rp, col, np.zeros(col.shape[0]), -a, None, np.ones(3), None, None)
+    return g, P
+
+
+def test_mu_hand_worked_chain():
+    """MU limiter, Sec. 3.2 steps 1-4, against a hand-worked 3-node example."""
+    g, P = _mu_chain3()
+    d = O.artificial_diffusion(P, P.a)
+    rstar, alpha, Rp, Rm = O.mu_limited_fluxes(P, np.array(g["u"]), d, P.a)
+    np.testing.assert_allclose(Rp, g["R_plus"], rtol=1e-14, atol=1e-15)
+    np.testing.assert_allclose(Rm, g["R_minus"], rtol=1e-14)
+    for key, v in g["alpha_offdiag"].items():
+        i, j = map(int, key.split(","))
+        k = P.row_ptr[i] + list(P.col[P.row_ptr[i]:P.row_ptr[i + 1]]).index(j)
+        assert alpha[k] == pytest.approx(v, rel=1e-14, abs=1e-15)
+    np.testing.assert_allclose(P.row_sum(rstar), g["F_star"], rtol=1e-14, atol=1e-15)
+
+
+def _mu_edge_list(P, u, d, a):
+    """Brute-force coding of Sec. 3.2 with explicit loops over node pairs."""
+    N = P.N
+    ent = {}
+    for i in range(N):
+        for k in range(P.row_ptr[i], P.row_ptr[i + 1]):
+            ent[(i, int(P.col[k]))] = k
+    r = {}
+    for (i, j), k in ent.items():
+        r[(i, j)] = 0.0 if (i == j or P.is_dir[i]) else d[k] * (u[j] - u[i])
+    Rp, Rm = [1.0] * N, [1.0] * N
+    for i in range(N):
+        pp = pm = qp = qm = 0.0
+        for (ii, j), k in ent.items():
+            if ii != i or j == i:
+                continue
+            if a[ent[(j, i)]] <= a[k]:
+                pp += max(r[(i, j)], 0.0)
+                pm += min(r[(i, j)], 0.0)
+            qp -= min(r[(i, j)], 0.0)
+            qm -= max(r[(i, j)], 0.0)
+        if not P.is_dir[i]:
+            Rp[i] = 1.0 if pp == 0 else min(1.0, qp / pp)
+            Rm[i] = 1.0 if pm == 0 else min(1.0, qm / pm)
+    alpha = {}
+    for (i, j), k in ent.items():
+        if i == j:
+            continue
+        cand = []
+        for (p, q) in ((i, j), (j, i)):  # node p owns the edge when a_qp <= a_pq
+            if a[ent[(q, p)]] <= a[ent[(p, q)]]:
+                rr = r[(p, q)]
+                cand.append(Rp[p] if rr > 0 else (Rm[p] if rr < 0 else 1.0))
+        alpha[(i, j)] = min(cand)
+    Fs = np.zeros(N)
+    for (i, j), k in ent.items():
+        if i != j:
+            Fs[i] += alpha[(i, j)] * r[(i, j)]
+    return Fs
+
+
+@pytest.mark.parametrize("dirichlet", ["none", "inflow"])
+def test_mu_row_coding_matches_edge_list_and_is_conservative(dirichlet):
+    inst = I.build("P1", 3, 1e-3, I.affine_field([1.0, -0.5, 0.25], [[0, 0.3, 0], [0, 0, 0], [0.2, 0, 0]]), 0.3,
+                   dirichlet=dirichlet)
+    P = O.problem_from_instance(inst, conv=False)
+    d = O.artificial_diffusion(P, P.a)
+    u = np.random.default_rng((0, 7)).standard_normal(inst.N)
+    u[P.is_dir] = P.uD[P.is_dir]
+    rstar, alpha, Rp, Rm = O.mu_limited_fluxes(P, u, d, P.a)
+    np.testing.assert_allclose(P.row_sum(rstar), _mu_edge_list(P, u, d, P.a), rtol=1e-13, atol=1e-15)
+    off = P.offd
+    assert np.all(alpha[off] >= 0.0) and np.all(alpha[off] <= 1.0)
+    assert np.array_equal(alpha[off], alpha[P.tpos][off])
+    assert 0.0 < np.mean(alpha[off & (rstar != 0)]) < 1.0 or np.all(alpha[off] == 1.0)
+    if dirichlet == "none":
+        assert abs(P.row_sum(rstar).sum()) <= 1e-14 * np.abs(rstar).sum()
+
+
+@pytest.mark.parametrize("elem", ["P1", "Q1"])
+def test_stationary_mu_alpha_one_is_galerkin_zero_is_low_order(elem):
+    # MU scheme: r* = r gives A u = F; r* = 0 gives (A + D) u = F with D from A (eq. (5))
+    inst = I.build(elem, 4, 0.1, I.affine_field([1.0, 0.5, 0.25]), 1.0, load=("box", [0.25] * 3, [0.75] * 3),
+                   dirichlet="all", dir_fn=lambda X: X[:, 0])
+    P = O.problem_from_instance(inst, conv=False)
+    Md, Ad = _dense_ops(inst)
+    dirs = inst.dir_idx
+    rhs = inst.F.copy()
+    rhs[dirs] = inst.dir_val
+    L = Ad.copy()
+    L[dirs, :] = 0.0
+    L[dirs, dirs] = 1.0
+    ref = np.linalg.solve(L, rhs)
+    u, st = O.stationary_mu(P, inst.F, np.zeros(inst.N), alpha_mode="one", tol=1e-12, tol_mode="rel", maxit=500,
+                            lin_rtol=1e-15)
+    assert st.status == O.STATUS_OK
+    np.testing.assert_allclose(u, ref, rtol=0, atol=1e-10 * np.abs(ref).max())
+    Dd = np.zeros_like(Ad)
+    for i in range(inst.N):
+        for j in range(inst.N):
+            if i != j and Md[i, j] != 0.0:
+                Dd[i, j] = -max(Ad[i, j], 0.0, Ad[j, i])
+        Dd[i, i] = -Dd[i].sum()
+    L0 = Ad + Dd
+    L0[dirs, :] = 0.0
+    L0[dirs, dirs] = 1.0
+    ref0 = np.linalg.solve(L0, rhs)
+    u0, _ = O.stationary_mu(P, inst.F, np.zeros(inst.N), alpha_mode="zero", tol=1e-14, tol_mode="rel", maxit=3,
+                            lin_rtol=1e-15)
+    np.testing.assert_allclose(u0, ref0, rtol=0, atol=1e-11 * np.abs(ref0).max())
+
+
+def test_mu_pure_convection_steady_state_obeys_dmp():
+    # eps = c = 0, inflow data in [0, 1], f = 0: converged MU solution stays in [0, 1];
+    # the Galerkin solution (alpha = 1) of the same problem does not
+    def u_in(X):
+        return (X[:, 1] > 0.5).astype(float)
+
+    inst = I.build("Q1", 8, 0.0, I.affine_field([1.0, 0.3, 0.2]), 0.0, dirichlet="inflow", dir_fn=u_in)
+    P = O.problem_from_instance(inst, conv=False)
+    u0 = np.zeros(inst.N)
+    u, st = O.stationary_mu(P, inst.F, u0, tol=1e-10, tol_mode="rel", maxit=3000, lin_rtol=1e-14)
+    assert st.status == O.STATUS_OK
+    ulp = 4 * np.finfo(float).eps
+    assert u.min() >= -ulp and u.max() <= 1.0 + ulp
+    ug, _ = O.stationary_mu(P, inst.F, u0, alpha_mode="one", tol=1e-10, tol_mode="rel", maxit=50, lin_rtol=1e-14)
+    assert ug.min() < -1e-3 or ug.max() > 1.0 + 1e-3
