@@ -189,3 +189,36 @@ def test_batch_autotune_keeps_inputs_and_picks_a_candidate():
         assert len(times) >= 3 and all(t > 0 for t in times)
     finally:
         afc.afc_batch_destroy(b)
+
+
+def test_batch_full_size_sampled_instances():
+    """The batched CN workload at full size (256 P1 instances, n in 8..32,
+    20 steps, one launch, autotuned schedule): the smallest, a median and the
+    largest instance against the oracle."""
+    afc = _afc()
+    ps = I.config4_params(256)
+    insts = [I.config4_instance(p) for p in ps]
+    opts = _opts(fp_tol=1e-12, fp_maxit=50, lin_atol=1e-12)
+    b = afc.afc_batch_create(insts, opts)
+    try:
+        offs = afc.afc_batch_offsets(b, len(insts))
+        u = torch.tensor(_pack(insts, offs, "u0"), device="cuda:0")
+        F = torch.tensor(_pack(insts, offs, "F"), device="cuda:0")
+        afc.afc_batch_autotune(b, u, F, [1e-3] * len(insts), 1)
+        st, stats = afc.afc_batch_step_cn(b, u, F, [1e-3] * len(insts), 20)
+        assert st >= 0
+        x = u.cpu().numpy()
+    finally:
+        afc.afc_batch_destroy(b)
+    sizes = np.array([inst.N for inst in insts])
+    order = np.argsort(sizes, kind="stable")
+    for k in (int(order[0]), int(order[len(order) // 2]), int(order[-1])):
+        inst = insts[k]
+        print("batch full size: instance %d, N=%d" % (k, inst.N), flush=True)
+        P = O.problem_from_instance(inst, conv=False)
+        ref = inst.u0.copy()
+        for _ in range(20):
+            ref, _ = O.cn_fct_step(P, ref, inst.F, inst.F, 1e-3, tol=1e-12, tol_mode="abs", maxit=50,
+                                   lin="bicgstab", lin_atol=1e-12)
+        got = x[offs[k]:offs[k + 1]]
+        assert np.linalg.norm(got - ref) <= 1e-9 * np.linalg.norm(ref), k

@@ -431,6 +431,44 @@ def test_mu_alpha_modes_and_renumbered(mode, name):
         afc.afc_destroy(h)
 
 
+def test_mcl_full_size_iteration_in_bench_configuration():
+    """Q1 128^3 (the stationary MCL workload) in the configuration bench.py
+    times (FP32 GMRES(30)-Jacobi inside FP64 refinement, 1e-10 ||b||): the
+    low-order start and one fixed-point iteration, checked with the oracle's
+    FP64 operators at full size: the nonlinear residual the GPU reports, and
+    the linear residual of the iterate against b = F + F*(u) assembled by the
+    oracle from the GPU's own starting state."""
+    afc = _afc()
+    inst = I.config3(128)
+    print("full size: N=%d nnz=%d" % (inst.N, inst.nnz), flush=True)
+    o = dict(precision=1, krylov=1, restart=30, fp_tol=0.0, fp_tol_mode=1, lin_atol=0.0, lin_rtol=1e-10,
+             lin_maxit=100000)
+    h = afc.afc_create_instance(inst, _opts(fp_maxit=0, **o), conv=True)
+    try:
+        u = _dev(np.zeros(inst.N))
+        F = _dev(inst.F)
+        afc.afc_solve_stationary(h, u, F, init_low_order=True)
+        u0 = u.cpu().numpy()
+        afc.afc_set_options(h, _opts(fp_maxit=1, **o))
+        st, stats = afc.afc_solve_stationary(h, u, F)
+        assert st == 1 and stats["fp_iters"] == 1, stats
+        u1 = u.cpu().numpy()
+    finally:
+        afc.afc_destroy(h)
+    print("full size: GPU done, oracle operators", flush=True)
+    P = O.problem_from_instance(inst, conv=True)
+    d, As = O.stationary_matrix(P)
+    b0 = inst.F.copy()
+    b0[P.is_dir] = P.uD[P.is_dir]
+    assert np.linalg.norm(b0 - P.matvec(As, u0)) <= 1.01e-10 * np.linalg.norm(b0)
+    rstar = O.mcl_limited_fluxes(P, u0, P.c, d)[0]
+    b = inst.F + P.row_sum(rstar)
+    b[P.is_dir] = P.uD[P.is_dir]
+    R = float(np.linalg.norm((b - P.matvec(As, u0))[~P.is_dir]))
+    assert abs(stats["res0"] - R) <= 1e-9 * R
+    assert np.linalg.norm(b - P.matvec(As, u1)) <= 1.01e-10 * np.linalg.norm(b)
+
+
 def test_mcl_single_iteration_parity():
     """One fixed-point iteration from the same low-order start (fp_maxit = 1)."""
     afc = _afc()
