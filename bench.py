@@ -390,6 +390,94 @@ def traffic_summarize(fetch_csv, write_csv, probe_log, n):
                                                   t["write_bytes"] / 1e6, alg))
 
 
+def accuracy_examples(n_rot, n_circ):
+    """The paper's analytic accuracy examples on this package's meshes, run
+    through the GPU library: rotating shapes (one full rotation, five schemes)
+    and circular convection (stationary MC and MU limiters).  Errors use the
+    lumped-mass nodal quadrature: L1 = sum_i m_i |e_i|, L2 = sqrt(sum_i m_i e_i^2)."""
+    import numpy as np
+    import torch
+
+    from paper_2110_15676_amd import afc
+    from paper_2110_15676_amd import inputs as I
+
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def mk_opts(**kw):
+        o = afc.afc_default_options(**kw)
+        o.stream = stream
+        return o
+
+    def lumped(inst):
+        m = np.zeros(inst.N)
+        np.add.at(m, inst.row_index(), inst.M)
+        return m
+
+    out = {}
+    inst = I.rotating_shapes(n_rot)
+    m = lumped(inst)
+    dt, steps = inst.params["dt"], inst.params["steps"]
+    # nonlinear loops as in the paper: stop at R < 1e-20 or after 50 iterations
+    fp = dict(fp_tol=1e-20 / math.sqrt(inst.N), fp_tol_mode=afc.AFC_TOL_ABS_SQRTN, fp_maxit=50,
+              krylov=afc.AFC_KRYLOV_BICGSTAB, lin_atol=0.0, lin_rtol=1e-12)
+    schemes = (("MC+SSP", afc.afc_step_mc_ssprk3, dict(ssp_stages=2), False),
+               ("MC+CN", afc.afc_step_mc_cn, fp, True),
+               ("Zal+CN linear", afc.afc_step_cn_linear, fp, True),
+               ("Zal+CN nonlinear", afc.afc_step_cn, fp, True),
+               ("Zal+SSP", afc.afc_step_ssprk3, dict(ssp_stages=2), False))
+    rot = {"mesh": "Q1 %d^3 (%d nodes), dt = %.4g, %d steps (T = 2 pi)" % (n_rot, inst.N, dt, steps)}
+    for name, step, kw, implicit in schemes:
+        print("accuracy: rotating shapes, %s" % name, file=sys.stderr, flush=True)
+        h = afc.afc_create_instance(inst, mk_opts(**kw), conv=True)
+        try:
+            u = torch.tensor(inst.u0, device="cuda:0")
+            F = torch.tensor(inst.F, device="cuda:0")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                if implicit:
+                    step(h, u, F, F, dt, raise_on_error=False)
+                else:
+                    step(h, u, F, dt, raise_on_error=False)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+        finally:
+            afc.afc_destroy(h)
+        x = u.cpu().numpy()
+        e = x - inst.u0
+        rot[name] = {"L2_error": float(np.sqrt(np.sum(m * e * e))), "min": float(x.min()), "max": float(x.max()),
+                     "seconds": round(el, 3)}
+    out["rotating_shapes"] = rot
+    circ = {}
+    for n in n_circ:
+        inst = I.circular_convection(n)
+        m = lumped(inst)
+        ex = I.circular_convection_exact(inst.coords)
+        row = {"mesh": "P1 %d^3 x 6 tetrahedra (%d nodes)" % (n, inst.N)}
+        for name, lim in (("MC", afc.AFC_LIMITER_MCL), ("MU", afc.AFC_LIMITER_MU)):
+            print("accuracy: circular convection n=%d, %s" % (n, name), file=sys.stderr, flush=True)
+            o = mk_opts(limiter=lim, fp_tol=1e-8, fp_tol_mode=afc.AFC_TOL_REL, fp_maxit=3000, lin_atol=0.0,
+                        lin_rtol=1e-12)
+            h = afc.afc_create_instance(inst, o, conv=True)
+            try:
+                u = torch.zeros(inst.N, dtype=torch.float64, device="cuda:0")
+                t0 = time.perf_counter()
+                st, stats = afc.afc_solve_stationary(h, u, torch.tensor(inst.F, device="cuda:0"), init_low_order=True,
+                                                     raise_on_error=False)
+                torch.cuda.synchronize()
+                el = time.perf_counter() - t0
+            finally:
+                afc.afc_destroy(h)
+            x = u.cpu().numpy()
+            e = x - ex
+            row[name] = {"L1_error": float(np.sum(m * np.abs(e))), "L2_error": float(np.sqrt(np.sum(m * e * e))),
+                         "min": float(x.min()), "max": float(x.max()), "fp_iters": stats["fp_iters"],
+                         "status": st, "seconds": round(el, 3)}
+        circ[str(n)] = row
+    out["circular_convection"] = circ
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -405,6 +493,9 @@ def main():
     ap.add_argument("--no-cn", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--accuracy", action="store_true",
+                    help="only run the paper's analytic accuracy examples (rotating shapes, circular convection)")
+    ap.add_argument("--accuracy-n", type=int, default=64, help="cells per direction of the rotating-shapes mesh")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only run the program profiled by the FETCH_SIZE / WRITE_SIZE counter passes")
     ap.add_argument("--traffic-summarize", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "PROBE_LOG"),
@@ -418,6 +509,9 @@ def main():
         sys.exit(2)
     if args.traffic_probe:
         traffic_probe(args.n)
+        return
+    if args.accuracy:
+        print(json.dumps(accuracy_examples(args.accuracy_n, (16, 32, 64))))
         return
 
     import numpy as np

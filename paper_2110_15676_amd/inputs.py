@@ -539,3 +539,56 @@ def renumbered(inst: Instance, seed=(0, 9)) -> Instance:
                     M=inst.M[order], K=inst.K[order], K_conv=inst.K_conv[order], F=nodal(inst.F),
                     dir_idx=d_new[d_order].astype(np.int32), dir_val=inst.dir_val[d_order], u0=nodal(inst.u0),
                     coords=nodal(inst.coords), params=dict(inst.params, perm=perm))
+
+
+# ----------------------------------------------------------------------------
+# The paper's analytic accuracy examples, on this package's meshes
+# ----------------------------------------------------------------------------
+
+
+def rotating_shapes_u0(X):
+    """Indicator of the three bodies of the rotating-shapes example: a cube
+    (edge 0.25, centre (0.5, 0.25, 0.5)), a cone (height 0.5, base radius
+    0.125, base centre (0.75, 0.5, 0.25)) and a hollow cylinder (radii 0.0625
+    and 0.125, height 0.5, base centre (0.5, 0.75, 0.25))."""
+    x, y, z = X[:, 0], X[:, 1], X[:, 2]
+    cube = (np.abs(x - 0.5) <= 0.125) & (np.abs(y - 0.25) <= 0.125) & (np.abs(z - 0.5) <= 0.125)
+    zc = z - 0.25
+    tall = (zc >= 0.0) & (zc <= 0.5)
+    cone = tall & (np.hypot(x - 0.75, y - 0.5) <= 0.125 * (1.0 - zc / 0.5))
+    rh = np.hypot(x - 0.5, y - 0.75)
+    hollow = tall & (rh >= 0.0625) & (rh <= 0.125)
+    return (cube | cone | hollow).astype(np.float64)
+
+
+def rotating_shapes(n: int = 64) -> Instance:
+    """Rotating bodies (the paper's first time-dependent example): eps = 0,
+    b = (0.5 - y, x - 0.5, 0), c = 0, f = 0, u = 0 on the whole boundary, one
+    full rotation T = 2 pi.  Q1 on n^3 cubes; dt = 1e-3 * 256 / n keeps the
+    paper's ratio dt / h (h = 2^-8, dt = 1e-3)."""
+    dt = 1e-3 * 256.0 / n
+    steps = int(round(2.0 * math.pi / dt))
+    b = affine_field([0.5, -0.5, 0.0], [[0.0, -1.0, 0.0], [1.0, 0.0, 0.0], [0.0, 0.0, 0.0]])
+    return build("Q1", n, 0.0, b, 0.0, dirichlet="all", u0_fn=rotating_shapes_u0,
+                 params=dict(example="rotating_shapes", dt=dt, steps=steps, T=steps * dt))
+
+
+def circular_convection_exact(X):
+    """Exact solution of the circular-convection example, r = sqrt(x^2 + y^2):
+    1 on 0.15 <= r <= 0.45, cos^2(10 pi (r - 0.7) / 3) on 0.55 <= r <= 0.85,
+    0 elsewhere."""
+    r = np.hypot(X[:, 0], X[:, 1])
+    u = np.zeros(X.shape[0])
+    u[(r >= 0.15) & (r <= 0.45)] = 1.0
+    m = (r >= 0.55) & (r <= 0.85)
+    u[m] = np.cos(10.0 * math.pi * (r[m] - 0.7) / 3.0) ** 2
+    return u
+
+
+def circular_convection(n: int = 32, elem: str = "P1") -> Instance:
+    """Circular convection (the paper's stationary accuracy example): eps = 0,
+    b = (y, -x, 0), c = 0, f = 0, Dirichlet data from the exact solution on
+    the faces y = 1, x = 0 and x = 1, natural conditions elsewhere."""
+    b = affine_field([0.0, 0.0, 0.0], [[0.0, 1.0, 0.0], [-1.0, 0.0, 0.0], [0.0, 0.0, 0.0]])
+    return build(elem, n, 0.0, b, 0.0, dirichlet=[("y", 1), ("x", 0), ("x", 1)], dir_fn=circular_convection_exact,
+                 params=dict(example="circular_convection"))
