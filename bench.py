@@ -7,11 +7,13 @@ c = 1, f = 1 on [0.25, 0.5]^3, u = 0 on the boundary.  One step is one
 fixed-point iteration of the paper's scheme (Sec. 4): MCL bounds, limited
 fluxes and the FP64 nonlinear residual, then the linear solve of the
 low-order matrix to ||b - A x|| <= 1e-10 ||b|| with GMRES(30)-Jacobi, FP32
-Arnoldi inside FP64 iterative refinement.  Steps continue from the low-order
+Arnoldi (s-step blocks of 8 basis vectors unless --sstep says otherwise)
+inside FP64 iterative refinement.  Steps continue from the low-order
 solution (computed before timing).  value = nodes x steps / seconds
 (DOF-iterations/s).
 
-Also reported: the plain-FP64 GMRES rate, Krylov iterations per step, the
+Also reported: the rate with one basis vector per Arnoldi step, the
+plain-FP64 GMRES rate, Krylov iterations per step, the
 roofline of the dominant kernel (FP32 SELL-64 SpMV) from HIP-event timings
 taken live in this process, batched CN-FCT solves/s (one persistent launch
 for 256 instances, against one-at-a-time solves), serving solves/s with
@@ -47,13 +49,19 @@ def spmv32_bytes(N, info):
             + 4 * (info["slices"] + 1) + 4 * info["slices"] + 4 * N + 4 * N)
 
 
-def step_model_bytes(N, nnz, info, krylov, sweeps, steps):
+def step_model_bytes(N, nnz, info, krylov, sweeps, steps, sstep=0):
     """Algorithmic HBM bytes of `steps` fixed-point iterations (model: every
-    cycle of equal length, Arnoldi index k uniform over the cycle)."""
+    cycle of equal length, Arnoldi index k uniform over the cycle).  With
+    s-step blocks the projections and the update read the old basis once per
+    block of `sstep` vectors."""
     L = krylov / max(sweeps, 1)  # mean FP32 GMRES cycle length
     kbar = (L - 1) / 2.0         # mean Arnoldi index inside a cycle
-    # SpMV, projections (V[0..k] and W) and the update
-    per_it = spmv32_bytes(N, info) + (kbar + 2) * 4 * N + (kbar + 3) * 4 * N
+    if sstep > 0:
+        kb = max(0.0, (L - sstep) / 2.0)  # mean block start
+        per_it = spmv32_bytes(N, info) + ((kb + 1) / sstep + 1) * 4 * N + ((kb + 1) / sstep + 2) * 4 * N
+    else:
+        # SpMV, projections (V[0..k] and W) and the update
+        per_it = spmv32_bytes(N, info) + (kbar + 2) * 4 * N + (kbar + 3) * 4 * N
     residual = (8 * info["slots"] + info["delta_bytes"] * info["lane_delta_slots"] + 4 * info["pattern_ints"]
                 + 8 * info["slices"] + 4 + 24 * N)
     per_sweep = residual + kbar * 4 * N + 16 * N + 12 * N
@@ -277,10 +285,11 @@ def bench_serve(afc, torch, I, count, slots):
     }
 
 
-def traffic_probe(n):
+def traffic_probe(n, sstep):
     """Program for the two HBM counter passes (FETCH_SIZE, then WRITE_SIZE):
-    three plain 1 GiB device copies (the calibration of each counter) and then
-    one fixed-point iteration of the workload from its low-order solution."""
+    three plain 1 GiB device copies (the calibration of each counter), then
+    one fixed-point iteration of the workload from its low-order solution with
+    one basis vector per Arnoldi step, and one with s-step blocks."""
     import torch
 
     from paper_2110_15676_amd import afc
@@ -294,27 +303,38 @@ def traffic_probe(n):
     del src, dst
     print("traffic probe: 3 copies of %d bytes done" % (1 << 30), flush=True)
     inst = I.config3(n)
-    # profiled from the start, so that the library's work counters cover every
-    # launch the counter passes see
-    o = afc.afc_default_options(precision=afc.AFC_PREC_MIXED, krylov=afc.AFC_KRYLOV_GMRES, restart=30,
-                                fp_tol=0.0, fp_tol_mode=afc.AFC_TOL_REL, fp_maxit=0, lin_atol=0.0,
-                                lin_rtol=1e-10, lin_maxit=100000, profile=1)
-    o.stream = torch.cuda.current_stream().cuda_stream
-    h = afc.afc_create_instance(inst, o, conv=True)
-    u = torch.zeros(inst.N, dtype=torch.float64, device="cuda")
     F = torch.tensor(inst.F, device="cuda")
-    afc.afc_solve_stationary(h, u, F, init_low_order=True)
-    o.fp_maxit = 1
-    afc.afc_set_options(h, o)
-    _, s = afc.afc_solve_stationary(h, u, F)
-    torch.cuda.synchronize()
     work = {}
-    for name, kid in (("k_sell_spmv32", afc.AFC_KERNEL_SPMV32), ("k_gmres_dots", afc.AFC_KERNEL_DOTS),
-                      ("k_gmres_update", afc.AFC_KERNEL_UPDATE), ("k_sell_residual", afc.AFC_KERNEL_RESIDUAL)):
-        by, n = afc.afc_kernel_work(h, kid)
-        work[name] = {"bytes": by, "launches_with_work": n}
-    afc.afc_destroy(h)
-    print("traffic probe: 1 fixed-point iteration, %d Krylov iterations" % s["krylov_iters"], flush=True)
+
+    def add(name, kid, h):
+        by, cnt = afc.afc_kernel_work(h, kid)
+        w = work.setdefault(name, {"bytes": 0.0, "launches_with_work": 0})
+        w["bytes"] += by
+        w["launches_with_work"] += cnt
+
+    for ss in (0, sstep):
+        # profiled from the start, so that the library's work counters cover
+        # every launch the counter passes see
+        o = afc.afc_default_options(precision=afc.AFC_PREC_MIXED, krylov=afc.AFC_KRYLOV_GMRES, restart=30,
+                                    fp_tol=0.0, fp_tol_mode=afc.AFC_TOL_REL, fp_maxit=0, lin_atol=0.0,
+                                    lin_rtol=1e-10, lin_maxit=100000, profile=1, sstep=ss)
+        o.stream = torch.cuda.current_stream().cuda_stream
+        h = afc.afc_create_instance(inst, o, conv=True)
+        u = torch.zeros(inst.N, dtype=torch.float64, device="cuda")
+        afc.afc_solve_stationary(h, u, F, init_low_order=True)
+        o.fp_maxit = 1
+        afc.afc_set_options(h, o)
+        _, st = afc.afc_solve_stationary(h, u, F)
+        torch.cuda.synchronize()
+        pre = "k_sstep" if ss else "k_gmres"
+        add("k_sell_spmv32", afc.AFC_KERNEL_SPMV32, h)
+        add(pre + "_dots", afc.AFC_KERNEL_DOTS, h)
+        add(pre + "_update", afc.AFC_KERNEL_UPDATE, h)
+        add("k_sell_residual", afc.AFC_KERNEL_RESIDUAL, h)
+        afc.afc_destroy(h)
+        del u
+        print("traffic probe: s=%d, 1 fixed-point iteration, %d Krylov iterations" % (ss, st["krylov_iters"]),
+              flush=True)
     print("traffic probe work: " + json.dumps(work), flush=True)
 
 
@@ -355,8 +375,8 @@ def traffic_summarize(fetch_csv, write_csv, probe_log, n):
         raise SystemExit("traffic: the three 1 GiB calibration copies are missing from the counter files")
     sf, sw = gib_kib / (sum(cf[:3]) / 3), gib_kib / (sum(cw[:3]) / 3)
     table = {}
-    for name in ("k_sell_spmv32", "k_gmres_dots", "k_gmres_update", "k_gmres_reduce", "k_sell_residual",
-                 "k_mcl_bounds", "k_mcl_apply"):
+    for name in ("k_sell_spmv32", "k_gmres_dots", "k_gmres_update", "k_gmres_reduce", "k_sstep_dots",
+                 "k_sstep_update", "k_sstep_sums", "k_sell_residual", "k_mcl_bounds", "k_mcl_apply"):
         f = [v for v in series(fe, name) if v > 1024]
         w = [v for v in series(wr, name) if v > 1024]
         if f:
@@ -486,6 +506,10 @@ def main():
     ap.add_argument("--n", type=int, default=128, help="cells per direction (128 is the workload)")
     ap.add_argument("--fp64-steps", type=int, default=5)
     ap.add_argument("--mu-steps", type=int, default=5)
+    ap.add_argument("--sstep", type=int, default=8,
+                    help="GMRES basis block size s (0: one vector per step; 2..8: s-step blocks)")
+    ap.add_argument("--classical-steps", type=int, default=5,
+                    help="steps timed again with one basis vector per Arnoldi step (secondary)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
@@ -508,7 +532,7 @@ def main():
         print("bench.py measures one GPU: this build has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
     if args.traffic_probe:
-        traffic_probe(args.n)
+        traffic_probe(args.n, args.sstep)
         return
     if args.accuracy:
         print(json.dumps(accuracy_examples(args.accuracy_n, (16, 32, 64))))
@@ -528,6 +552,7 @@ def main():
     stream = torch.cuda.current_stream().cuda_stream
 
     def opts(**kw):
+        kw.setdefault("sstep", args.sstep)
         o = afc.afc_default_options(precision=afc.AFC_PREC_MIXED, krylov=afc.AFC_KRYLOV_GMRES, restart=30,
                                     fp_tol=0.0, fp_tol_mode=afc.AFC_TOL_REL, lin_atol=0.0, lin_rtol=1e-10,
                                     lin_maxit=100000, **kw)
@@ -554,7 +579,7 @@ def main():
     assert s["fp_iters"] == args.steps, s
     value = N * args.steps / elapsed
     ms_per_step = 1e3 * elapsed / args.steps
-    model_bytes = step_model_bytes(N, nnz, info, s["krylov_iters"], s["refine_sweeps"], args.steps)
+    model_bytes = step_model_bytes(N, nnz, info, s["krylov_iters"], s["refine_sweeps"], args.steps, args.sstep)
     print("bench: %.1f ms/step, %d Krylov its" % (ms_per_step, s["krylov_iters"]), file=sys.stderr, flush=True)
 
     # --- the same steps again with per-kernel HIP events (roofline) ----------
@@ -602,6 +627,17 @@ def main():
         "profiled_ms_per_step": round(1e3 * elapsed_prof / args.steps, 3),
     }
 
+    # --- the same GMRES with one basis vector per Arnoldi step (secondary) ---
+    classical = None
+    if args.classical_steps > 0 and args.sstep > 0:
+        afc.afc_set_options(h, opts(fp_maxit=args.classical_steps, sstep=0))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, s5 = afc.afc_solve_stationary(h, u, F)
+        torch.cuda.synchronize()
+        e5 = time.perf_counter() - t0
+        classical = {"value": N * s5["fp_iters"] / e5, "ms_per_step": 1e3 * e5 / max(1, s5["fp_iters"]),
+                     "krylov_per_step": s5["krylov_iters"] / max(1, s5["fp_iters"]), "steps": s5["fp_iters"]}
     # --- plain FP64 GMRES for comparison (secondary) ------------------------
     fp64 = None
     if args.fp64_steps > 0:
@@ -668,8 +704,9 @@ def main():
         "config": {
             "workload": "stationary MCL, Q1 %d^3 (%d nodes, %d nnz), eps=1e-6, b=(1,1,1)/sqrt3, c=1, "
                         "f=1 on [0.25,0.5]^3, u=0 on the boundary; fixed-point iterations from the low-order "
-                        "solution, GMRES(30)-Jacobi FP32 inner + FP64 refinement to 1e-10 ||b||" % (args.n, N, nnz),
-            "nodes": N, "nnz": nnz, "parallelism": "1 GPU",
+                        "solution, GMRES(30)-Jacobi FP32 inner (%s) + FP64 refinement to 1e-10 ||b||"
+                        % (args.n, N, nnz, "s-step blocks of %d" % args.sstep if args.sstep else "one vector per step"),
+            "nodes": N, "nnz": nnz, "gmres_sstep": args.sstep, "parallelism": "1 GPU",
         },
         "krylov_per_step": s["krylov_iters"] / args.steps,
         "refine_sweeps_per_step": s["refine_sweeps"] / args.steps,
@@ -677,6 +714,7 @@ def main():
         "hbm_gbs_model": model_bytes / elapsed / 1e9,
         "nonlinear_residual": {"first": s["res0"], "last": s["res"]},
         "fp64": fp64,
+        "classical_arnoldi": classical,
         "mu_limiter": mu,
         "batch": batch,
         "cn": cn,

@@ -119,6 +119,16 @@ typedef struct {
   int32_t profile;          /* 1: time every launch of the hot kernels with HIP
                                events on the handle's stream (afc_kernel_time) */
   int32_t limiter;          /* AFC_LIMITER_* of afc_solve_stationary          */
+  int32_t sstep;            /* mixed-precision GMRES: 0 = one basis vector per
+                               step (classical Gram-Schmidt); s = 2..8 = blocks
+                               of s vectors from shifted matrix powers
+                               (A - I)^j v, orthonormalized together (block
+                               Gram-Schmidt + Cholesky QR).  Same Krylov space
+                               and minimal-residual iterate as GMRES in exact
+                               arithmetic; a block whose QR fails makes the rest
+                               of the solve use s = 0.                         */
+  double sstep_shift;       /* theta of the shifted powers (default 1: the
+                               Jacobi-scaled matrix has unit diagonal)         */
   int32_t graphs;           /* 1 (default): each GMRES cycle is captured once
                                as a HIP graph and replayed (same kernels, same
                                results); 0: plain launches.  Not used while

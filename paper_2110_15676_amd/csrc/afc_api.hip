@@ -69,6 +69,8 @@ afc_status check_options(const afc_options& o, std::string& why) {
   if (o.profile != 0 && o.profile != 1) return why = "profile must be 0 or 1", AFC_EINVAL;
   if (o.graphs != 0 && o.graphs != 1) return why = "graphs must be 0 or 1", AFC_EINVAL;
   if (o.limiter != AFC_LIMITER_MCL && o.limiter != AFC_LIMITER_MU) return why = "limiter", AFC_EINVAL;
+  if (o.sstep != 0 && (o.sstep < 2 || o.sstep > afc::kSMax)) return why = "sstep must be 0 or 2..8", AFC_EINVAL;
+  if (!std::isfinite(o.sstep_shift)) return why = "sstep_shift must be finite", AFC_EINVAL;
   if (o.lanes_per_row != 0 && o.lanes_per_row != 8 && o.lanes_per_row != 16 && o.lanes_per_row != 32 &&
       o.lanes_per_row != 64)
     return why = "lanes_per_row must be 0, 8, 16, 32 or 64", AFC_EINVAL;
@@ -126,7 +128,7 @@ void free_all(afc_handle* h) {
   for (auto*& p : h->w) f(p);
   h->w.clear();
   f(h->V64); f(h->V32);
-  f(h->partials); f(h->ks);
+  f(h->partials); f(h->partials_blk); f(h->ks);
   if (h->host_status) (void)hipHostFree(h->host_status);
   h->host_status = nullptr;
   afc::prof_release(h);
@@ -261,20 +263,63 @@ SolveOut solve_gmres(afc_handle* h, const SysMat& S, const double* b, double* x,
       afc::residual(h, S.S64, b, x, h->V64, 1);
     }
   };
-  hipGraphExec_t graph = nullptr;
-  if (h->opt.graphs && !h->opt.profile)
+  // s-step variant (mixed precision): blocks of s basis vectors from the
+  // shifted powers (A - theta I)^j (default theta = 1, the centre of the
+  // Gershgorin discs of the Jacobi-scaled matrix)
+  const int s = mixed ? h->opt.sstep : 0;
+  const double theta = h->opt.sstep_shift;
+  auto cycle_sstep = [&]() {
+    for (int k = 0; k < m; k += s) {
+      const int sb = std::min(s, m - k);
+      for (int j = 1; j <= sb; ++j)
+        afc::spmv32(h, S.S32, h->V32 + (size_t)(k + j - 1) * h->ldv, (float)theta, h->V32 + (size_t)(k + j) * h->ldv);
+      afc::sstep_dots(h, k, sb);
+      afc::sstep_reduce(h, k, sb, m, theta);
+      afc::sstep_update(h, k, sb);
+    }
+    afc::gmres_solve(h, m);
+    afc::gmres_xupdate(h, true, S.dinv, x);
+    afc::residual(h, S.S64, b, x, r, 2);
+    afc::cast_v0(h, r);
+  };
+  bool use_s = s >= 2;
+  if (use_s && !h->partials_blk) {
+    h->partials_blk = dalloc<double>(h, (size_t)afc::kBlkRows * afc::kRedBlocks);
+    HIP_OK(hipMemsetAsync(h->partials_blk, 0, sizeof(double) * afc::kBlkRows * afc::kRedBlocks, h->stream));
+  }
+  const int fails0 = h->host_status->pad_i[0];
+  uint64_t theta_bits = 0;
+  std::memcpy(&theta_bits, &theta, sizeof(theta_bits));
+  hipGraphExec_t graph = nullptr, graph_s = nullptr;
+  if (h->opt.graphs && !h->opt.profile) {
     graph = cached_graph(h, {key_int(1), S.S32, S.S64, S.dinv, b, x, r, h->V32, h->V64, h->w[0], key_int(m),
                              key_int(mixed), key_int(h->ldv)},
                          cycle);
+    if (use_s)
+      graph_s = cached_graph(h, {key_int(3), S.S32, S.S64, S.dinv, b, x, r, h->V32, key_int(m), key_int(s),
+                                 key_int(h->ldv), key_int((int64_t)theta_bits)},
+                             cycle_sstep);
+  }
   int cycle_it0 = it0;
   while (res > tol) {
-    if (graph)
+    if (use_s) {
+      if (graph_s)
+        HIP_OK(hipGraphLaunch(graph_s, h->stream));
+      else
+        cycle_sstep();
+    } else if (graph) {
       HIP_OK(hipGraphLaunch(graph, h->stream));
-    else
+    } else {
       cycle();
+    }
     o.sweeps += 1;
     sync_status(h);
-    afc::prof_gmres_cycle(h, mixed, m, h->host_status->iters - cycle_it0);
+    if (use_s) {
+      afc::prof_sstep_cycle(h, m, s, h->host_status->iters - cycle_it0);
+      if (h->host_status->pad_i[0] != fails0) use_s = false;  // a block's QR failed: one-vector steps from here
+    } else {
+      afc::prof_gmres_cycle(h, mixed, m, h->host_status->iters - cycle_it0);
+    }
     cycle_it0 = h->host_status->iters;
     res = h->host_status->beta;
     const int64_t its = h->host_status->iters - it0;
@@ -632,6 +677,8 @@ void afc_default_options(afc_options* o) {
   o->ssp_stages = 3;
   o->lanes_per_row = 0;
   o->graphs = 1;
+  o->sstep = 0;
+  o->sstep_shift = 1.0;
   o->stream = nullptr;
 }
 

@@ -31,10 +31,29 @@ static __device__ __forceinline__ double gmin(double v) {
   return v;
 }
 
+// Lane move of a double with one DPP control (both 32-bit halves).
+template <int CTRL>
+static __device__ __forceinline__ double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a wave (every lane active), returned to every lane.
+// DPP lane moves build it in lane 63: pairs and quads (quad permutes), rows
+// of 16 (row rotates by 4 and 8), then rows 0+1 and 2+3 (broadcast of lane
+// 15 into the next row) and all four rows (broadcast of lane 31 into rows 2
+// and 3).  A fixed pattern, so the result is deterministic.
 static __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_move<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  v += dpp_move<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  v += dpp_move<0x124>(v);  // row_ror 4
+  v += dpp_move<0x128>(v);  // row_ror 8
+  v += dpp_move<0x142>(v);  // row_bcast 15
+  v += dpp_move<0x143>(v);  // row_bcast 31
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
 }
 
 // Zalesak's R = min(1, m Q / (dt P)), 1 when P = 0 (Sec. 2.1.3, step 3).

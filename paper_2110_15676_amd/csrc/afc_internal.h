@@ -15,6 +15,9 @@ constexpr int kBlock = 256;        // threads per workgroup (4 wave64)
 constexpr int kMaxRestart = 64;    // GMRES restart cap (Hessenberg lives on device)
 constexpr int kMaxRed = 72;        // values a single fused reduction may produce
 constexpr int kRedBlocks = 2048;   // cap on workgroups of reduction kernels
+constexpr int kSMax = 8;           // largest s-step GMRES block
+// values of one s-step block reduction: C = V^T W ((m+1) x s) and the Gram W^T W (s(s+1)/2)
+constexpr int kBlkRows = (kMaxRestart + 1) * kSMax + kSMax * (kSMax + 1) / 2;
 
 // Device-resident scalars of the Krylov solvers (one per handle).  Every
 // scalar decision (step lengths, Givens rotations, convergence) is taken on
@@ -29,7 +32,7 @@ struct KState {
   int m;            // restart length of the running cycle
   int k;            // Arnoldi columns completed in the cycle
   int done;         // converged or stopped: kernels of the chunk become no-ops
-  int flag;         // 1 breakdown, 2 non-finite
+  int flag;         // 1 breakdown, 2 non-finite, 3 s-step block QR failed
   int iters;        // Krylov iterations, cumulative over the handle's life
   int half;         // BiCGStab: ||s|| already below tol in this iteration
   int pad_i[2];
@@ -41,6 +44,13 @@ struct KState {
   double coef[kMaxRestart + 1];               // update coefficients y_j * sc_j
   double proj[kMaxRestart + 1];               // running Arnoldi step: h_{q,k} sc_q
   double ctol_abs, ctol_rel;                  // cycle restart tolerances of the running solve
+  // s-step GMRES (mixed precision): Arnoldi Hessenberg before rotation, block sums,
+  // update coefficients D = C R^{-1} and R^{-1} of the running block
+  double Hraw[(kMaxRestart + 1) * kMaxRestart];
+  double blk[kBlkRows];
+  double dco[(kMaxRestart + 1) * kSMax];
+  double rinv[kSMax * kSMax];
+  int blk_ok;                                 // the running block's QR succeeded
 };
 
 // bytes of KState copied back to the host: scalars + red[0..7]
@@ -111,6 +121,7 @@ struct afc_handle_s {
   int Vm = 0;
   int ldv = 0;  // basis / work vector stride: N rounded up to 64 (16-byte aligned rows)
   double* partials = nullptr;  // kMaxRed * kRedBlocks
+  double* partials_blk = nullptr;  // kBlkRows * kRedBlocks (s-step GMRES, allocated on first use)
   afc::KState* ks = nullptr;
   afc::KState* host_status = nullptr;  // pinned copy of the KState head
 
@@ -137,6 +148,7 @@ namespace afc {
 // Algorithmic HBM bytes of one GMRES cycle whose Arnoldi process completed kk
 // columns out of m, added to the per-kernel work counters (profiling only).
 void prof_gmres_cycle(afc_handle_s* h, bool fp32, int m, int kk);
+void prof_sstep_cycle(afc_handle_s* h, int m, int s, int kk);  // the same for an s-step cycle
 void prof_collect(afc_handle_s* h);  // fold completed event pairs into the totals
 void prof_release(afc_handle_s* h);
 }  // namespace afc

@@ -300,10 +300,12 @@ __device__ __forceinline__ TA sell_row(const SellView& S, const TI* __restrict__
 }
 
 // FP32: y = A x (Jacobi-scaled FP32 matrix, unscaled basis vector)
+// y = A x - theta x (theta != 0: the shifted powers of s-step GMRES)
 template <typename TI>
 __global__ __launch_bounds__(kBlock) void k_sell_spmv32(SellView S, const TI* __restrict__ dlt,
                                                         const float* __restrict__ val, const float* __restrict__ x,
-                                                        const KState* __restrict__ ks, float* __restrict__ y) {
+                                                        const KState* __restrict__ ks, float theta,
+                                                        float* __restrict__ y) {
   if (ks->done) return;
   int t0, t1;
   tile_range((S.nsl + kBlock / 64 - 1) / (kBlock / 64), t0, t1);
@@ -312,7 +314,9 @@ __global__ __launch_bounds__(kBlock) void k_sell_spmv32(SellView S, const TI* __
     if (s >= S.nsl) continue;
     const int i = s * 64 + (threadIdx.x & 63);
     if (i >= S.N) continue;
-    y[i] = sell_row<8>(S, dlt, val, s, i, [&](int j) { return x[j]; });
+    float acc = sell_row<8>(S, dlt, val, s, i, [&](int j) { return x[j]; });
+    if (theta != 0.0f) acc -= theta * x[i];
+    y[i] = acc;
   }
 }
 
@@ -613,6 +617,337 @@ __global__ __launch_bounds__(kBlock) void k_gmres_update(int N, int ldv, T* __re
     store16(out, e, N, o);
   }
   block_partials<1>(nrm, 1, partials + (size_t)kNormRow * kRedBlocks, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// s-step GMRES (mixed precision).  A block of s basis vectors comes from the
+// shifted powers W_j = (A - theta I) W_{j-1}, W_0 = V[k] (stored at
+// V[k+1..k+s]).  One pass over V[0..k] and the block forms C = V^T W and the
+// Gram matrix W^T W; G = W^T W - C^T C is the Gram matrix of the projected
+// block, whose Cholesky factor R gives the new orthonormal vectors
+// Q = (W - V C) R^{-1} in one more pass.  The Hessenberg columns of the
+// Arnoldi relation A [V_k, Q_1..Q_{s-1}] = [V, Q] H follow from the change of
+// basis.  In exact arithmetic the iterates are those of GMRES.
+// ---------------------------------------------------------------------------
+
+// row of the Gram entry (i, j), i <= j < s, after the (k+1) s rows of C
+__device__ __forceinline__ int gram_row(int nv, int s, int i, int j) {
+  return nv * s + i * s - i * (i - 1) / 2 + (j - i);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_sstep_dots(int N, int ldv, const T* __restrict__ V, int k, int s,
+                                                     const KState* __restrict__ ks, double* __restrict__ partials) {
+  if (ks->done) return;
+  constexpr int VN = 16 / sizeof(T);
+  constexpr int CH = kBlock * VN;
+  constexpr int NW = kBlock / 64;
+  constexpr int QU = 4;  // basis vectors loaded together (loads in flight)
+  __shared__ double sh[kBlkRows][NW];
+  const int nv = k + 1;
+  const int nrows = nv * s + s * (s + 1) / 2;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int q = threadIdx.x; q < nrows * NW; q += kBlock) sh[q / NW][q % NW] = 0.0;
+  __syncthreads();
+  const T* __restrict__ W = V + (size_t)(k + 1) * ldv;
+  for (int base = blockIdx.x * CH; base < N; base += gridDim.x * CH) {
+    const int e = base + threadIdx.x * VN;
+    T w[kSMax][VN];
+#pragma unroll
+    for (int j = 0; j < kSMax; ++j)
+      if (j < s) load16(W + (size_t)j * ldv, e, N, w[j]);
+    for (int q0 = 0; q0 < nv; q0 += QU) {
+      T a[QU][VN];
+#pragma unroll
+      for (int u = 0; u < QU; ++u)
+        if (q0 + u < nv) load16(V + (size_t)(q0 + u) * ldv, e, N, a[u]);
+#pragma unroll
+      for (int u = 0; u < QU; ++u) {
+        if (q0 + u < nv) {
+#pragma unroll
+          for (int j = 0; j < kSMax; ++j) {
+            if (j < s) {
+              double t = 0.0;
+#pragma unroll
+              for (int c = 0; c < VN; ++c) t += (double)a[u][c] * (double)w[j][c];
+              t = wave_sum(t);
+              if (lane == 0) sh[(q0 + u) * s + j][wv] += t;
+            }
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kSMax; ++i) {
+#pragma unroll
+      for (int j = 0; j < kSMax; ++j) {
+        if (i < s && j >= i && j < s) {
+          double t = 0.0;
+#pragma unroll
+          for (int c = 0; c < VN; ++c) t += (double)w[i][c] * (double)w[j][c];
+          t = wave_sum(t);
+          if (lane == 0) sh[gram_row(nv, s, i, j)][wv] += t;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int r = threadIdx.x; r < nrows; r += kBlock) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) t += sh[r][w];
+    partials[(size_t)r * kRedBlocks + blockIdx.x] = t;
+  }
+}
+
+// workgroup r sums partial row r of the block reduction into ks->blk[r]
+__global__ __launch_bounds__(kBlock) void k_sstep_sums(KState* ks, const double* __restrict__ partials, int nb) {
+  if (ks->done) return;
+  const double* const rows[1] = {partials + (size_t)blockIdx.x * kRedBlocks};
+  const int nbs[1] = {nb};
+  double t[1];
+  block_rows_sum<1>(rows, nbs, t);
+  if (threadIdx.x == 0) ks->blk[blockIdx.x] = t[0];
+}
+
+// Cholesky QR of the projected block, update coefficients, Hessenberg
+// columns k..k+s-1 and their Givens rotations (one workgroup).
+__global__ __launch_bounds__(kBlock) void k_sstep_small(KState* ks, int k, int s, int m, double theta) {
+  constexpr int kRows = kMaxRestart + 1 + kSMax;
+  __shared__ double C[(kMaxRestart + 1) * kSMax];  // C[q s + j] = (V_q, W_{j+1})
+  __shared__ double G[kSMax * kSMax], R[kSMax * kSMax], Ri[kSMax * kSMax];
+  __shared__ double Z[kRows * (kSMax + 1)];  // coordinates of W_0..W_s in [V_0..V_k, Q_1..Q_s]
+  __shared__ double M1[kRows * kSMax];
+  __shared__ double Hn[kRows * kSMax];       // new Hessenberg columns k..k+s-1
+  __shared__ double colw[kMaxRestart + 2];
+  __shared__ double gcs[kMaxRestart], gsn[kMaxRestart], gg[kMaxRestart + 1];  // rotations and rhs, staged
+  __shared__ int ok;
+  const int was_done = ks->done;
+  __syncthreads();  // every thread has read done before thread 0 may set it below
+  if (was_done) {
+    if (threadIdx.x == 0) ks->blk_ok = 0;
+    return;
+  }
+  const int nv = k + 1, nr = nv + s;
+  for (int i = threadIdx.x; i < nv * s; i += blockDim.x) C[i] = ks->blk[i];
+  for (int i = threadIdx.x; i < k; i += blockDim.x) {
+    gcs[i] = ks->cs[i];
+    gsn[i] = ks->sn[i];
+  }
+  for (int i = threadIdx.x; i <= k; i += blockDim.x) gg[i] = ks->g[i];
+  __syncthreads();
+  for (int t = threadIdx.x; t < s * s; t += blockDim.x) {  // G = W^T W - C^T C
+    const int i = t / s, j = t % s;
+    double g = ks->blk[gram_row(nv, s, min(i, j), max(i, j))];
+    for (int q = 0; q < nv; ++q) g -= C[q * s + i] * C[q * s + j];
+    G[t] = g;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    bool good = true;
+    for (int j = 0; j < s && good; ++j) {  // G = R^T R, R upper triangular
+      double d = G[j * s + j];
+      for (int p = 0; p < j; ++p) d -= R[p * s + j] * R[p * s + j];
+      if (!(d > 0.0) || !isfinite(d)) {
+        good = false;
+        break;
+      }
+      const double rjj = sqrt(d);
+      R[j * s + j] = rjj;
+      for (int i = j + 1; i < s; ++i) {
+        double v = G[j * s + i];
+        for (int p = 0; p < j; ++p) v -= R[p * s + j] * R[p * s + i];
+        R[j * s + i] = v / rjj;
+      }
+      for (int i = 0; i < j; ++i) R[j * s + i] = 0.0;
+    }
+    if (good) {
+      for (int j = 0; j < s; ++j) {  // R^{-1}, column by column
+        for (int i = 0; i < s; ++i) Ri[i * s + j] = 0.0;
+        Ri[j * s + j] = 1.0 / R[j * s + j];
+        for (int i = j - 1; i >= 0; --i) {
+          double v = 0.0;
+          for (int p = i + 1; p <= j; ++p) v += R[i * s + p] * Ri[p * s + j];
+          Ri[i * s + j] = -v / R[i * s + i];
+        }
+      }
+    }
+    ok = good;
+  }
+  __syncthreads();
+  if (!ok) {
+    if (threadIdx.x == 0) {
+      ks->blk_ok = 0;
+      ks->pad_i[0] += 1;  // sticky count of failed blocks (the host falls back to one-vector steps)
+      ks->done = 1;
+    }
+    return;
+  }
+  // update coefficients: Q = W R^{-1} - V (C R^{-1})
+  for (int t = threadIdx.x; t < nv * s; t += blockDim.x) {
+    const int q = t / s, j = t % s;
+    double v = 0.0;
+    for (int i = 0; i <= j; ++i) v += C[q * s + i] * Ri[i * s + j];
+    ks->dco[t] = v;
+  }
+  for (int t = threadIdx.x; t < s * s; t += blockDim.x) ks->rinv[t] = Ri[t];
+  for (int t = threadIdx.x; t < nr * (s + 1); t += blockDim.x) {
+    const int r = t / (s + 1), c = t % (s + 1);
+    double v;
+    if (c == 0)
+      v = r == k ? 1.0 : 0.0;
+    else if (r < nv)
+      v = C[r * s + (c - 1)];
+    else
+      v = R[(r - nv) * s + (c - 1)];
+    Z[t] = v;
+  }
+  __syncthreads();
+  // A W_{j} = W_{j+1} + theta W_j: A [V Z_{:, 0..s-1}] = V (Z B); split the
+  // left side into A V_{0..k-1} E (known: the raw Hessenberg) and A X T with
+  // X = [V_k, Q_1..Q_{s-1}], T = Z[k..k+s-1, 0..s-1] upper triangular
+  for (int t = threadIdx.x; t < nr * s; t += blockDim.x) {
+    const int r = t / s, j = t % s;
+    double v = theta * Z[r * (s + 1) + j] + Z[r * (s + 1) + j + 1];
+    if (r <= k)
+      for (int c = max(r - 1, 0); c < k; ++c) v -= ks->Hraw[(size_t)c * (m + 1) + r] * Z[c * (s + 1) + j];
+    M1[t] = v;
+  }
+  __syncthreads();
+  for (int r = threadIdx.x; r < nr; r += blockDim.x) {  // Hn = M1 T^{-1}
+    for (int j = 0; j < s; ++j) {
+      double v = M1[r * s + j];
+      for (int i = 0; i < j; ++i) v -= Hn[r * s + i] * Z[(k + i) * (s + 1) + j];
+      Hn[r * s + j] = v / Z[(k + j) * (s + 1) + j];
+    }
+  }
+  __syncthreads();
+  const int ns = min(s, m - k);
+  for (int t = threadIdx.x; t < ns * nr; t += blockDim.x) {
+    const int j = t / nr, r = t % nr;
+    if (r <= k + j + 1) ks->Hraw[(size_t)(k + j) * (m + 1) + r] = Hn[r * s + j];
+  }
+  __shared__ int ncols, stop, nonfinite;
+  if (threadIdx.x == 0) {  // Givens rotations of the new columns, in LDS
+    const double tol = ks->tol;
+    int j = 0;
+    stop = 0;
+    nonfinite = 0;
+    for (; j < ns; ++j) {
+      const int c = k + j;
+      double* col = Hn + j;  // column j of Hn, stride s
+      double cur = col[0];
+      for (int jj = 0; jj < c; ++jj) {
+        const double nxt = col[(jj + 1) * s];
+        col[jj * s] = gcs[jj] * cur + gsn[jj] * nxt;
+        cur = -gsn[jj] * cur + gcs[jj] * nxt;
+      }
+      const double hk1 = col[(c + 1) * s];
+      const double den = hypot(cur, hk1);
+      if (!isfinite(den)) {
+        nonfinite = 1;
+        stop = 1;
+        break;
+      }
+      if (den == 0.0) {  // the new direction adds nothing: keep the column as rotated
+        col[c * s] = cur;
+        stop = 1;
+        break;
+      }
+      const double cs = cur / den, sn = hk1 / den;
+      gcs[c] = cs;
+      gsn[c] = sn;
+      col[c * s] = den;
+      col[(c + 1) * s] = 0.0;
+      const double gk = gg[c];
+      gg[c + 1] = -sn * gk;
+      gg[c] = cs * gk;
+      if (fabs(gg[c + 1]) <= tol) {
+        ++j;
+        stop = 1;
+        break;
+      }
+    }
+    ncols = j;  // columns completed by this block
+  }
+  __syncthreads();
+  // write back the rotated columns, rotations and right-hand side
+  const int nc = ncols;
+  for (int t = threadIdx.x; t < nc * nr; t += blockDim.x) {
+    const int j = t / nr, r = t % nr;
+    if (r <= k + j + 1) ks->H[(size_t)(k + j) * (m + 1) + r] = Hn[r * s + j];
+  }
+  for (int j = threadIdx.x; j < nc; j += blockDim.x) {
+    ks->cs[k + j] = gcs[k + j];
+    ks->sn[k + j] = gsn[k + j];
+    ks->sc[k + j + 1] = 1.0;
+  }
+  for (int i = threadIdx.x; i <= k + nc; i += blockDim.x) ks->g[i] = gg[i];
+  if (threadIdx.x == 0) {
+    ks->blk_ok = 1;
+    ks->k = k + nc;
+    ks->iters += nc;
+    ks->res = fabs(gg[k + nc]);
+    if (nonfinite) ks->flag = 2;
+    if (stop) ks->done = 1;
+  }
+}
+
+// Q = W R^{-1} - V (C R^{-1}), in place over the block V[k+1..k+s]
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_sstep_update(int N, int ldv, T* __restrict__ V, int k, int s,
+                                                       const KState* __restrict__ ks) {
+  constexpr int VN = 16 / sizeof(T);
+  constexpr int CH = kBlock * VN;
+  __shared__ double D[(kMaxRestart + 1) * kSMax], Ri[kSMax * kSMax];
+  __shared__ int okb;
+  if (threadIdx.x == 0) okb = ks->blk_ok;
+  __syncthreads();
+  if (!okb) return;
+  const int nv = k + 1;
+  for (int t = threadIdx.x; t < nv * s; t += kBlock) D[t] = ks->dco[t];
+  for (int t = threadIdx.x; t < s * s; t += kBlock) Ri[t] = ks->rinv[t];
+  __syncthreads();
+  T* __restrict__ W = V + (size_t)(k + 1) * ldv;
+  for (int base = blockIdx.x * CH; base < N; base += gridDim.x * CH) {
+    const int e = base + threadIdx.x * VN;
+    T w[kSMax][VN];
+#pragma unroll
+    for (int j = 0; j < kSMax; ++j)
+      if (j < s) load16(W + (size_t)j * ldv, e, N, w[j]);
+    double acc[kSMax][VN];
+#pragma unroll
+    for (int j = 0; j < kSMax; ++j) {
+#pragma unroll
+      for (int c = 0; c < VN; ++c) acc[j][c] = 0.0;
+#pragma unroll
+      for (int i = 0; i < kSMax; ++i)
+        if (i <= j && j < s) {
+          const double r = Ri[i * s + j];
+#pragma unroll
+          for (int c = 0; c < VN; ++c) acc[j][c] += r * (double)w[i][c];
+        }
+    }
+    for (int q = 0; q < nv; ++q) {
+      T a[VN];
+      load16(V + (size_t)q * ldv, e, N, a);
+#pragma unroll
+      for (int j = 0; j < kSMax; ++j)
+        if (j < s) {
+          const double d = D[q * s + j];
+#pragma unroll
+          for (int c = 0; c < VN; ++c) acc[j][c] -= d * (double)a[c];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kSMax; ++j)
+      if (j < s) {
+        T o[VN];
+#pragma unroll
+        for (int c = 0; c < VN; ++c) o[c] = (T)acc[j][c];
+        store16(W + (size_t)j * ldv, e, N, o);
+      }
+  }
 }
 
 // back substitution R y = g over the columns completed in the cycle (one wave)
@@ -1748,15 +2083,17 @@ void gmres_spmv64(H* h, const double* A, const double* dinv, int k) {
            static_cast<const int32_t*>(h->sl_dlt), A, dinv, x, (const KState*)h->ks, h->w[0]);
 }
 
-void gmres_spmv32(H* h, const float* A32, int k) {
-  const float* x = h->V32 + (size_t)k * h->ldv;
-  float* y = reinterpret_cast<float*>(h->w[0]);
+void spmv32(H* h, const float* A32, const float* x, float theta, float* y) {
   if (h->dlt16)
     launch(h, AFC_KERNEL_SPMV32, k_sell_spmv32<int16_t>, sell_grid(h, false), kBlock, sell_view(h),
-           static_cast<const int16_t*>(h->sl_dlt), A32, x, (const KState*)h->ks, y);
+           static_cast<const int16_t*>(h->sl_dlt), A32, x, (const KState*)h->ks, theta, y);
   else
     launch(h, AFC_KERNEL_SPMV32, k_sell_spmv32<int32_t>, sell_grid(h, false), kBlock, sell_view(h),
-           static_cast<const int32_t*>(h->sl_dlt), A32, x, (const KState*)h->ks, y);
+           static_cast<const int32_t*>(h->sl_dlt), A32, x, (const KState*)h->ks, theta, y);
+}
+
+void gmres_spmv32(H* h, const float* A32, int k) {
+  spmv32(h, A32, h->V32 + (size_t)k * h->ldv, 0.0f, reinterpret_cast<float*>(h->w[0]));
 }
 
 void gmres_dots(H* h, bool fp32, int k) {
@@ -1786,6 +2123,25 @@ void gmres_update(H* h, bool fp32, int k) {
 
 void gmres_last_givens(H* h, bool fp32, int k, int m) {
   finish(h, gmres_grid(h, fp32), 1, ACT_GIVENS, 0, k, m, 0, 0.0, 0.0, kNormRow);
+}
+
+// workgroups of the s-step projections (one 16-byte chunk per thread and vector)
+int sstep_grid(const H* h) { return vec16_grid(h, kBlock * 4); }
+
+void sstep_dots(H* h, int k, int s) {
+  launch(h, AFC_KERNEL_DOTS, k_sstep_dots<float>, sstep_grid(h), kBlock, h->N, h->ldv, (const float*)h->V32, k, s,
+         (const KState*)h->ks, h->partials_blk);
+}
+
+void sstep_reduce(H* h, int k, int s, int m, double theta) {
+  const int nrows = (k + 1) * s + s * (s + 1) / 2;
+  launch(h, AFC_KERNEL_FINISH, k_sstep_sums, nrows, kBlock, h->ks, (const double*)h->partials_blk, sstep_grid(h));
+  launch(h, AFC_KERNEL_FINISH, k_sstep_small, 1, kBlock, h->ks, k, s, m, theta);
+}
+
+void sstep_update(H* h, int k, int s) {
+  launch(h, AFC_KERNEL_UPDATE, k_sstep_update<float>, gmres_grid(h, true), kBlock, h->N, h->ldv, h->V32, k, s,
+         (const KState*)h->ks);
 }
 
 void gmres_solve(H* h, int m) { k_gmres_solve<<<1, 64, 0, h->stream>>>(h->ks, m); }
@@ -1947,6 +2303,25 @@ void prof_gmres_cycle(afc_handle_s* h, bool fp32, int m, int kk) {
   for (int k = 0; k < std::min(kk, m); ++k) {
     h->prof_bytes[AFC_KERNEL_UPDATE] += vb * N * (k + 1) + 2.0 * vb * N + 8.0 * nbv;
     h->prof_work[AFC_KERNEL_UPDATE] += 1;
+  }
+}
+
+void prof_sstep_cycle(afc_handle_s* h, int m, int s, int kk) {
+  if (!h->opt.profile) return;
+  const double N = (double)h->N;
+  const double nbv = (double)sstep_grid(h);
+  // blocks that ran: up to the one holding column kk (a converged block still
+  // orthonormalizes its vectors)
+  for (int k = 0; k < m && k <= kk; k += s) {
+    const int sb = std::min(s, m - k);
+    // matrix, x = V[k+j] (its diagonal term feeds the shift too), y
+    h->prof_bytes[AFC_KERNEL_SPMV32] += sb * (sell_matrix_bytes(h, 4) + 2.0 * 4.0 * N);
+    h->prof_work[AFC_KERNEL_SPMV32] += sb;
+    h->prof_bytes[AFC_KERNEL_DOTS] += 4.0 * N * (k + 1 + sb) + 8.0 * nbv * ((k + 1) * sb + sb * (sb + 1) / 2);
+    h->prof_work[AFC_KERNEL_DOTS] += 1;
+    h->prof_bytes[AFC_KERNEL_UPDATE] += 4.0 * N * (k + 1 + 2 * sb);
+    h->prof_work[AFC_KERNEL_UPDATE] += 1;
+    if (k + sb >= kk && kk < m) break;
   }
 }
 

@@ -270,14 +270,16 @@ def test_mcl_renumbered_parity(prec):
         afc.afc_destroy(h)
 
 
-def test_kernel_work_accounting():
-    """Profiled launches: SpMV+projection launches with work = Krylov
-    iterations plus at most one per cycle (the launch after the last completed
-    column), algorithmic bytes positive."""
+@pytest.mark.parametrize("sstep", [0, 8])
+def test_kernel_work_accounting(sstep):
+    """Profiled launches: SpMV launches with work = Krylov iterations plus, per
+    cycle, at most one (one vector per step: the launch after the last
+    completed column) or s (s-step: the rest of the last block); algorithmic
+    bytes positive."""
     afc = _afc()
     inst = I.config3(12)
     h = afc.afc_create_instance(inst, _opts(precision=1, fp_tol=0.0, fp_tol_mode=1, fp_maxit=3, lin_atol=0.0,
-                                            lin_rtol=1e-10, profile=1), conv=True)
+                                            lin_rtol=1e-10, profile=1, sstep=sstep), conv=True)
     try:
         u = _dev(np.zeros(inst.N))
         st, stats = afc.afc_solve_stationary(h, u, _dev(inst.F), init_low_order=True)
@@ -285,8 +287,11 @@ def test_kernel_work_accounting():
         by, work = afc.afc_kernel_work(h, afc.AFC_KERNEL_SPMV32)
         ub, uwork = afc.afc_kernel_work(h, afc.AFC_KERNEL_UPDATE)
         total_its = stats["krylov_iters"]
+        cycles = stats["refine_sweeps"]
         assert launches >= work > 0 and by > 0 and ms > 0
-        print("spmv launches %d with work %d, Krylov its %d" % (launches, work, total_its), flush=True)
+        print("s=%d: spmv launches %d with work %d, Krylov its %d, cycles %d"
+              % (sstep, launches, work, total_its, cycles), flush=True)
+        assert total_its <= work <= total_its + cycles * max(1, sstep)
         assert uwork <= work
         afc.afc_kernel_time(h, afc.AFC_KERNEL_SPMV32, reset=True)
         assert afc.afc_kernel_work(h, afc.AFC_KERNEL_SPMV32) == (0.0, 0)
@@ -467,6 +472,72 @@ def test_mcl_full_size_iteration_in_bench_configuration():
     R = float(np.linalg.norm((b - P.matvec(As, u0))[~P.is_dir]))
     assert abs(stats["res0"] - R) <= 1e-9 * R
     assert np.linalg.norm(b - P.matvec(As, u1)) <= 1.01e-10 * np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("sstep", [2, 5, 8])
+def test_sstep_gmres_parity(sstep):
+    """s-step GMRES (blocks of s basis vectors) in the mixed-precision solve of
+    the stationary MCL workload at 12^3: same solution as the oracle, Krylov
+    iterations close to the one-vector method's."""
+    afc = _afc()
+    inst = I.config3(12)
+    ref, rst = _mcl_ref(inst, 1e-12, 1e-14)
+    its = {}
+    for s in (0, sstep):
+        print("sstep=%d" % s, flush=True)
+        h = afc.afc_create_instance(inst, _opts(precision=1, sstep=s, fp_tol=1e-12, fp_tol_mode=1, fp_maxit=2000,
+                                                lin_atol=0.0, lin_rtol=1e-14), conv=True)
+        try:
+            u = _dev(np.zeros(inst.N))
+            st, stats = afc.afc_solve_stationary(h, u, _dev(inst.F), init_low_order=True)
+            assert st == 0, stats
+            assert _rel(u.cpu().numpy(), ref) <= 1e-8
+            its[s] = stats["krylov_iters"]
+        finally:
+            afc.afc_destroy(h)
+    print("krylov iterations", its, flush=True)
+    assert its[sstep] <= 1.25 * its[0] + 8 * stats["fp_iters"]
+
+
+def test_sstep_renumbered_and_graph_replay():
+    afc = _afc()
+    inst = I.renumbered(I.config3(10))
+    outs = []
+    for g in (1, 0):
+        h = afc.afc_create_instance(inst, _opts(precision=1, sstep=5, graphs=g, fp_tol=0.0, fp_tol_mode=1, fp_maxit=1,
+                                                lin_atol=0.0, lin_rtol=1e-10), conv=True)
+        try:
+            u = _dev(np.zeros(inst.N))
+            F = _dev(inst.F)
+            afc.afc_solve_stationary(h, u, F, init_low_order=True)
+            for _ in range(3):
+                afc.afc_solve_stationary(h, u, F)
+            outs.append(u.cpu().numpy())
+        finally:
+            afc.afc_destroy(h)
+    assert np.array_equal(outs[0], outs[1])
+    P = O.problem_from_instance(inst, conv=True)
+    lo = O.low_order_solution(P, inst.F, lin_rtol=1e-14)
+    # the first call already takes one fixed-point iteration after the low-order start
+    ref, _ = O.stationary_mcl(P, inst.F, lo.x, tol=0.0, tol_mode="rel", maxit=4, lin_rtol=1e-14)
+    assert _rel(outs[0], ref) <= 1e-8
+
+
+def test_sstep_failed_block_falls_back():
+    """A shift that overflows the FP32 powers makes the first block's Cholesky
+    QR fail; the solve continues with one-vector steps and converges."""
+    afc = _afc()
+    inst = I.config3(10)
+    ref, _ = _mcl_ref(inst, 1e-12, 1e-14)
+    h = afc.afc_create_instance(inst, _opts(precision=1, sstep=5, sstep_shift=1e30, fp_tol=1e-12, fp_tol_mode=1,
+                                            fp_maxit=2000, lin_atol=0.0, lin_rtol=1e-14), conv=True)
+    try:
+        u = _dev(np.zeros(inst.N))
+        st, stats = afc.afc_solve_stationary(h, u, _dev(inst.F), init_low_order=True)
+        assert st == 0, stats
+        assert _rel(u.cpu().numpy(), ref) <= 1e-8
+    finally:
+        afc.afc_destroy(h)
 
 
 def test_mcl_single_iteration_parity():
