@@ -131,6 +131,12 @@ void free_all(afc_handle* h) {
   f(h->partials); f(h->partials_blk); f(h->ks);
   if (h->host_status) (void)hipHostFree(h->host_status);
   h->host_status = nullptr;
+  if (h->ring) (void)hipHostFree(h->ring);
+  h->ring = nullptr;
+  for (auto& e : h->ring_ev) {
+    if (e) (void)hipEventDestroy(e);
+    e = nullptr;
+  }
   afc::prof_release(h);
   for (auto& e : h->graphs) (void)hipGraphExecDestroy(e.second);
   h->graphs.clear();
@@ -143,6 +149,12 @@ void sync_status(afc_handle* h) {
   HIP_OK(hipMemcpyAsync(h->host_status, h->ks, afc::kStatusBytes, hipMemcpyDeviceToHost, h->stream));
   HIP_OK(hipStreamSynchronize(h->stream));
   if (!h->ev_pending.empty()) afc::prof_collect(h);
+}
+
+void ensure_ring(afc_handle* h) {
+  if (h->ring) return;
+  HIP_OK(hipHostMalloc((void**)&h->ring, 2 * afc::kStatusBytes, hipHostMallocDefault));
+  for (auto& e : h->ring_ev) HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
 }
 
 void ensure_basis(afc_handle* h, int m, bool fp32) {
@@ -271,8 +283,9 @@ SolveOut solve_gmres(afc_handle* h, const SysMat& S, const double* b, double* x,
   auto cycle_sstep = [&]() {
     for (int k = 0; k < m; k += s) {
       const int sb = std::min(s, m - k);
-      for (int j = 1; j <= sb; ++j)
-        afc::spmv32(h, S.S32, h->V32 + (size_t)(k + j - 1) * h->ldv, (float)theta, h->V32 + (size_t)(k + j) * h->ldv);
+      for (int j = 1; j <= sb; ++j)  // alternating sweep directions (cache reuse between the SpMVs)
+        afc::spmv32(h, S.S32, h->V32 + (size_t)(k + j - 1) * h->ldv, (float)theta, (j + 1) & 1,
+                    h->V32 + (size_t)(k + j) * h->ldv);
       afc::sstep_dots(h, k, sb);
       afc::sstep_reduce(h, k, sb, m, theta);
       afc::sstep_update(h, k, sb);
@@ -287,7 +300,7 @@ SolveOut solve_gmres(afc_handle* h, const SysMat& S, const double* b, double* x,
     h->partials_blk = dalloc<double>(h, (size_t)afc::kBlkRows * afc::kRedBlocks);
     HIP_OK(hipMemsetAsync(h->partials_blk, 0, sizeof(double) * afc::kBlkRows * afc::kRedBlocks, h->stream));
   }
-  const int fails0 = h->host_status->pad_i[0];
+  const int fails0 = h->host_status->sfail;
   uint64_t theta_bits = 0;
   std::memcpy(&theta_bits, &theta, sizeof(theta_bits));
   hipGraphExec_t graph = nullptr, graph_s = nullptr;
@@ -300,9 +313,8 @@ SolveOut solve_gmres(afc_handle* h, const SysMat& S, const double* b, double* x,
                                  key_int(h->ldv), key_int((int64_t)theta_bits)},
                              cycle_sstep);
   }
-  int cycle_it0 = it0;
-  while (res > tol) {
-    if (use_s) {
+  auto issue = [&](bool sstep) {
+    if (sstep) {
       if (graph_s)
         HIP_OK(hipGraphLaunch(graph_s, h->stream));
       else
@@ -312,25 +324,78 @@ SolveOut solve_gmres(afc_handle* h, const SysMat& S, const double* b, double* x,
     } else {
       cycle();
     }
-    o.sweeps += 1;
-    sync_status(h);
-    if (use_s) {
-      afc::prof_sstep_cycle(h, m, s, h->host_status->iters - cycle_it0);
-      if (h->host_status->pad_i[0] != fails0) use_s = false;  // a block's QR failed: one-vector steps from here
-    } else {
-      afc::prof_gmres_cycle(h, mixed, m, h->host_status->iters - cycle_it0);
+  };
+  if (!graph) {  // one cycle at a time (profiling, or graphs switched off)
+    int cycle_it0 = it0;
+    while (res > tol) {
+      issue(use_s);
+      o.sweeps += 1;
+      sync_status(h);
+      if (use_s) {
+        afc::prof_sstep_cycle(h, m, s, h->host_status->iters - cycle_it0);
+        if (h->host_status->sfail != fails0) use_s = false;  // a block's QR failed: one-vector steps from here
+      } else {
+        afc::prof_gmres_cycle(h, mixed, m, h->host_status->iters - cycle_it0);
+      }
+      cycle_it0 = h->host_status->iters;
+      res = h->host_status->beta;
+      const int64_t its = h->host_status->iters - it0;
+      if (!std::isfinite(res)) {
+        o.st = AFC_ENAN;
+        break;
+      }
+      if (its >= cap || (mixed && o.sweeps >= h->opt.refine_maxit)) {
+        if (res > tol) o.st = AFC_ENOCONV;
+        break;
+      }
     }
-    cycle_it0 = h->host_status->iters;
-    res = h->host_status->beta;
-    const int64_t its = h->host_status->iters - it0;
-    if (!std::isfinite(res)) {
-      o.st = AFC_ENAN;
-      break;
+  } else if (res > tol) {
+    // Replayed cycles are kept one ahead: the next cycle is queued before the
+    // host waits for the status of the one in flight, when that cycle is not
+    // expected to converge and the next one stays within the iteration and
+    // sweep caps.  This hides the host's round trip between cycles.  A cycle
+    // that starts after the solve converged finds ks->solved set, and every
+    // kernel of it returns at once.
+    ensure_ring(h);
+    int queued = 0, seen = 0;  // cycles issued; cycles whose status was read
+    int64_t its = 0;
+    // residual factor expected of one cycle: the inner tolerance bounds a
+    // mixed-precision sweep; unknown (no look-ahead) before the first FP64 cycle
+    double rate = mixed ? inner_rel : 0.0;
+    auto queue = [&]() {
+      issue(use_s);
+      const int slot = queued & 1;
+      HIP_OK(hipMemcpyAsync(h->ring + slot * afc::kStatusBytes, h->ks, afc::kStatusBytes, hipMemcpyDeviceToHost,
+                            h->stream));
+      HIP_OK(hipEventRecord(h->ring_ev[slot], h->stream));
+      ++queued;
+    };
+    queue();
+    for (;;) {
+      const bool allowed = its + 2 * (int64_t)m <= cap && (!mixed || seen + 2 <= h->opt.refine_maxit);
+      if (queued - seen == 1 && allowed && res * rate > 2.0 * tol) queue();
+      const int slot = seen & 1;
+      HIP_OK(hipEventSynchronize(h->ring_ev[slot]));
+      const afc::KState* st = reinterpret_cast<const afc::KState*>(h->ring + slot * afc::kStatusBytes);
+      ++seen;
+      o.sweeps += 1;
+      if (use_s && st->sfail != fails0) use_s = false;  // a block's QR failed: one-vector steps from here
+      const double prev = res;
+      res = st->beta;
+      its = st->iters - it0;
+      if (!std::isfinite(res)) {
+        o.st = AFC_ENAN;
+        break;
+      }
+      if (res <= tol) break;
+      if (its >= cap || (mixed && o.sweeps >= h->opt.refine_maxit)) {
+        o.st = AFC_ENOCONV;
+        break;
+      }
+      if (prev > 0.0) rate = res / prev;
+      if (queued == seen) queue();
     }
-    if (its >= cap || (mixed && o.sweeps >= h->opt.refine_maxit)) {
-      if (res > tol) o.st = AFC_ENOCONV;
-      break;
-    }
+    sync_status(h);  // drains the queue: host_status holds the final state
   }
   o.iters = h->host_status->iters - it0;
   if (mixed) o.inner = o.iters;

@@ -56,6 +56,42 @@ static __device__ __forceinline__ double wave_sum(double v) {
   return __hiloint2double(hi, lo);
 }
 
+// a + b after an exchange of halves between lanes l and l ^ 32: lanes 0..31
+// return a(l) + a(l + 32), lanes 32..63 return b(l - 32) + b(l)
+// (v_permlane32_swap, both 32-bit halves)
+static __device__ __forceinline__ double swap32_sum(double a, double b) {
+  const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(a), __double2loint(b), false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(a), __double2hiint(b), false, false);
+  return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+}
+
+// the same between lanes l and l ^ 16: even rows of 16 lanes sum a, odd rows b
+static __device__ __forceinline__ double swap16_sum(double a, double b) {
+  const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(a), __double2loint(b), false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(a), __double2hiint(b), false, false);
+  return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+}
+
+// Eight sums over the 64 lanes of a wave (every lane active): lane l returns
+// the wave total of v[l >> 3].  Three exchange steps (partners l ^ 32, l ^ 16,
+// l ^ 8) each keep half of the values a lane holds, summed with its partner's
+// copy of the same values; then the eight lanes holding one value add up
+// (quad permutes, half-row mirror).  About a fifth of the lane moves of eight
+// wave_sum calls.  A fixed pattern, so the result is deterministic.
+static __device__ __forceinline__ double wave_sum8(const double (&v)[8]) {
+  double u[4], w[2];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) u[m] = swap32_sum(v[m], v[m + 4]);  // lanes with bit 5 set hold v[4..7]
+#pragma unroll
+  for (int m = 0; m < 2; ++m) w[m] = swap16_sum(u[m], u[m + 2]);  // bit 4: the upper pair
+  const bool b3 = (threadIdx.x & 8) != 0;                          // bit 3: the upper one
+  double x = (b3 ? w[1] : w[0]) + dpp_move<0x128>(b3 ? w[0] : w[1]);  // row_ror 8 = lane ^ 8
+  x += dpp_move<0xB1>(x);   // quad_perm [1, 0, 3, 2]
+  x += dpp_move<0x4E>(x);   // quad_perm [2, 3, 0, 1]
+  x += dpp_move<0x141>(x);  // row_half_mirror: lane ^ 7 inside each group of 8
+  return x;
+}
+
 // Zalesak's R = min(1, m Q / (dt P)), 1 when P = 0 (Sec. 2.1.3, step 3).
 static __device__ __forceinline__ double zalesak_R(double mi, double Q, double P, double dt) {
   return P != 0.0 ? fmin(1.0, mi * Q / (dt * P)) : 1.0;

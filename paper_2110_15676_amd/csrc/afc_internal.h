@@ -35,7 +35,8 @@ struct KState {
   int flag;         // 1 breakdown, 2 non-finite, 3 s-step block QR failed
   int iters;        // Krylov iterations, cumulative over the handle's life
   int half;         // BiCGStab: ||s|| already below tol in this iteration
-  int pad_i[2];
+  int sfail;        // s-step blocks whose QR failed (sticky count)
+  int solved;       // the solve's own tolerance holds: every kernel of a cycle queued after it returns at once
   double red[kMaxRed];                        // last finalized reduction
   double H[(kMaxRestart + 1) * kMaxRestart];  // Hessenberg, column k at H[k*(m+1)]
   double cs[kMaxRestart], sn[kMaxRestart];    // Givens rotations
@@ -124,6 +125,8 @@ struct afc_handle_s {
   double* partials_blk = nullptr;  // kBlkRows * kRedBlocks (s-step GMRES, allocated on first use)
   afc::KState* ks = nullptr;
   afc::KState* host_status = nullptr;  // pinned copy of the KState head
+  char* ring = nullptr;                // pinned status copies of the two cycles a GMRES solve keeps queued
+  hipEvent_t ring_ev[2] = {nullptr, nullptr};
 
   // launch sequences replayed as HIP graphs (options.graphs): a GMRES cycle,
   // a chunk of BiCGStab iterations.  Captured on a private stream, each keyed

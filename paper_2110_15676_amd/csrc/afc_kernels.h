@@ -44,7 +44,7 @@ void gmres_last_givens(H* h, bool fp32, int k, int m);
 // s-step GMRES block (FP32 basis): the shifted powers are spmv32 calls into
 // V[k+1..k+s]; then projections + Gram, the block reduction (Cholesky QR,
 // Hessenberg columns, Givens) and the in-place orthonormalization
-void spmv32(H* h, const float* A32, const float* x, float theta, float* y);
+void spmv32(H* h, const float* A32, const float* x, float theta, int rev, float* y);
 void sstep_dots(H* h, int k, int s);
 void sstep_reduce(H* h, int k, int s, int m, double theta);
 void sstep_update(H* h, int k, int s);

@@ -42,6 +42,18 @@ __device__ __forceinline__ void tile_range(int ntiles, int& t0, int& t1) {
   t1 = (int)(((int64_t)(b + 1) * ntiles) / nb);
 }
 
+// the same shares, each XCD's slab taken from its end: workgroups dispatched
+// first get the slab's last tiles
+__device__ __forceinline__ void tile_range_rev(int ntiles, int& t0, int& t1) {
+  const int nb = gridDim.x;
+  const int x = blockIdx.x & 7, k = blockIdx.x >> 3;
+  const int per = nb >> 3, rem = nb & 7;
+  const int cnt = per + (x < rem ? 1 : 0);
+  const int b = x * per + min(x, rem) + (cnt - 1 - k);
+  t0 = (int)(((int64_t)b * ntiles) / nb);
+  t1 = (int)(((int64_t)(b + 1) * ntiles) / nb);
+}
+
 // Block totals of nv per-thread values into partials[q * kRedBlocks + slot].
 template <int KMAX>
 __device__ void block_partials(const double (&v)[KMAX], int nv, double* partials, int slot) {
@@ -78,6 +90,7 @@ __device__ void cycle_start_dev(KState* ks, int mode, double rr, double tol_abs,
   ks->tol = fmax(tol_abs, tol_rel * beta);
   ks->flag = isfinite(beta) ? 0 : 2;
   ks->done = (!isfinite(beta) || beta <= ks->tol) ? 1 : 0;
+  ks->solved = (!isfinite(beta) || beta <= tol_abs) ? 1 : 0;
   if (mode == 1) ks->sc[0] = beta > 0.0 ? 1.0 / beta : 0.0;
   if (mode == 2) ks->sc[0] = 1.0;
 }
@@ -161,6 +174,7 @@ __global__ void k_cycle_start(KState* ks, int mode, int idx, double tol_abs, dou
 
 __global__ __launch_bounds__(kBlock) void k_cast_v0(int N, const double* __restrict__ r, float* __restrict__ V0,
                                                     const KState* __restrict__ ks) {
+  if (ks->solved) return;
   const double beta = ks->beta;
   const double inv = beta > 0.0 ? 1.0 / beta : 0.0;
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) V0[i] = (float)(r[i] * inv);
@@ -300,16 +314,24 @@ __device__ __forceinline__ TA sell_row(const SellView& S, const TI* __restrict__
 }
 
 // FP32: y = A x (Jacobi-scaled FP32 matrix, unscaled basis vector)
-// y = A x - theta x (theta != 0: the shifted powers of s-step GMRES)
+// y = A x - theta x (theta != 0: the shifted powers of s-step GMRES).
+// rev = 1 sweeps every XCD's slab backwards: back-to-back SpMVs that
+// alternate direction start on the matrix tiles the previous one read last,
+// which the memory-side cache still holds.
 template <typename TI>
 __global__ __launch_bounds__(kBlock) void k_sell_spmv32(SellView S, const TI* __restrict__ dlt,
                                                         const float* __restrict__ val, const float* __restrict__ x,
-                                                        const KState* __restrict__ ks, float theta,
+                                                        const KState* __restrict__ ks, float theta, int rev,
                                                         float* __restrict__ y) {
   if (ks->done) return;
+  const int nt = (S.nsl + kBlock / 64 - 1) / (kBlock / 64);
   int t0, t1;
-  tile_range((S.nsl + kBlock / 64 - 1) / (kBlock / 64), t0, t1);
-  for (int t = t0; t < t1; ++t) {
+  if (rev)
+    tile_range_rev(nt, t0, t1);
+  else
+    tile_range(nt, t0, t1);
+  for (int tt = t0; tt < t1; ++tt) {
+    const int t = rev ? t1 - 1 - (tt - t0) : tt;
     const int s = wave_slice(t);
     if (s >= S.nsl) continue;
     const int i = s * 64 + (threadIdx.x & 63);
@@ -334,7 +356,7 @@ __global__ __launch_bounds__(kBlock) void k_sell_spmv64(SellView S, const TI* __
     if (s >= S.nsl) continue;
     const int i = s * 64 + (threadIdx.x & 63);
     if (i >= S.N) continue;
-    y[i] = sell_row<4>(S, dlt, val, s, i, [&](int j) { return sc[j] * x[j]; });
+    y[i] = sell_row<8>(S, dlt, val, s, i, [&](int j) { return sc[j] * x[j]; });
   }
 }
 
@@ -344,7 +366,8 @@ __global__ __launch_bounds__(kBlock) void k_sell_residual(SellView S, const TI* 
                                                           const double* __restrict__ val,
                                                           const double* __restrict__ bvec,
                                                           const double* __restrict__ x, double* __restrict__ r,
-                                                          double* partials) {
+                                                          double* partials, const int* __restrict__ skip) {
+  if (skip && *skip) return;  // a cycle queued after the solve converged
   double nrm[1] = {0.0};
   int t0, t1;
   tile_range((S.nsl + kBlock / 64 - 1) / (kBlock / 64), t0, t1);
@@ -353,7 +376,7 @@ __global__ __launch_bounds__(kBlock) void k_sell_residual(SellView S, const TI* 
     if (s >= S.nsl) continue;
     const int i = s * 64 + (threadIdx.x & 63);
     if (i >= S.N) continue;
-    const double ri = bvec[i] - sell_row<4>(S, dlt, val, s, i, [&](int j) { return x[j]; });
+    const double ri = bvec[i] - sell_row<8>(S, dlt, val, s, i, [&](int j) { return x[j]; });
     r[i] = ri;
     nrm[0] += ri * ri;
   }
@@ -432,7 +455,8 @@ __device__ __forceinline__ void store16(T* __restrict__ p, int e, int N, const T
 // 4-byte-per-lane basis reads cannot stream like the 16-byte chunks here.)
 
 // Raw projections (V[q], W), q = 0..k: per-wave sums accumulate in LDS
-// (double), one partial per workgroup and row.
+// (double), one partial per workgroup and row.  Eight basis vectors are
+// loaded together and their eight products reduced over the wave at once.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_gmres_dots(int N, int ldv, const T* __restrict__ V,
                                                      const T* __restrict__ W, int k, const KState* __restrict__ ks,
@@ -441,37 +465,35 @@ __global__ __launch_bounds__(kBlock) void k_gmres_dots(int N, int ldv, const T* 
   constexpr int VN = 16 / sizeof(T);
   constexpr int CH = kBlock * VN;
   constexpr int NW = kBlock / 64;
+  constexpr int QU = 8;  // one eight-value wave reduction per group of basis vectors
   __shared__ double sh[kMaxRestart + 1][NW];
   const int nv = k + 1;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int p = lane >> 3;  // the vector of the group whose wave total this lane receives
   for (int q = threadIdx.x; q < nv * NW; q += kBlock) sh[q / NW][q % NW] = 0.0;
   __syncthreads();
   for (int base = blockIdx.x * CH; base < N; base += gridDim.x * CH) {
     const int e = base + threadIdx.x * VN;
     T w[VN];
     load16(W, e, N, w);
-    int q = 0;
-    for (; q + 4 <= nv; q += 4) {
-      T a[4][VN];
+    for (int q = 0; q < nv; q += QU) {
+      T a[QU][VN];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) load16(V + (size_t)(q + u) * ldv, e, N, a[u]);
+      for (int u = 0; u < QU; ++u) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+        for (int c = 0; c < VN; ++c) a[u][c] = T(0);
+        if (q + u < nv) load16(V + (size_t)(q + u) * ldv, e, N, a[u]);
+      }
+      double v[QU];
+#pragma unroll
+      for (int u = 0; u < QU; ++u) {
         double t = 0.0;
 #pragma unroll
         for (int c = 0; c < VN; ++c) t += (double)a[u][c] * (double)w[c];
-        t = wave_sum(t);
-        if (lane == 0) sh[q + u][wv] += t;
+        v[u] = t;
       }
-    }
-    for (; q < nv; ++q) {
-      T a[VN];
-      load16(V + (size_t)q * ldv, e, N, a);
-      double t = 0.0;
-#pragma unroll
-      for (int c = 0; c < VN; ++c) t += (double)a[c] * (double)w[c];
-      t = wave_sum(t);
-      if (lane == 0) sh[q][wv] += t;
+      const double x = wave_sum8(v);
+      if ((lane & 7) == 0 && q + p < nv) sh[q + p][wv] += x;
     }
   }
   __syncthreads();
@@ -643,19 +665,29 @@ __global__ __launch_bounds__(kBlock) void k_sstep_dots(int N, int ldv, const T* 
   constexpr int CH = kBlock * VN;
   constexpr int NW = kBlock / 64;
   constexpr int QU = 4;  // basis vectors loaded together (loads in flight)
+  static_assert(kSMax == 8, "one eight-value wave reduction per basis vector");
   __shared__ double sh[kBlkRows][NW];
   const int nv = k + 1;
   const int nrows = nv * s + s * (s + 1) / 2;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int p = lane >> 3;  // the product whose wave total this lane receives
+  const bool writer = (lane & 7) == 0 && p < s;
   for (int q = threadIdx.x; q < nrows * NW; q += kBlock) sh[q / NW][q % NW] = 0.0;
   __syncthreads();
   const T* __restrict__ W = V + (size_t)(k + 1) * ldv;
   for (int base = blockIdx.x * CH; base < N; base += gridDim.x * CH) {
     const int e = base + threadIdx.x * VN;
-    T w[kSMax][VN];
+    double w[kSMax][VN];
 #pragma unroll
-    for (int j = 0; j < kSMax; ++j)
-      if (j < s) load16(W + (size_t)j * ldv, e, N, w[j]);
+    for (int j = 0; j < kSMax; ++j) {
+      T t[VN];
+#pragma unroll
+      for (int c = 0; c < VN; ++c) t[c] = T(0);
+      if (j < s) load16(W + (size_t)j * ldv, e, N, t);
+#pragma unroll
+      for (int c = 0; c < VN; ++c) w[j][c] = (double)t[c];
+    }
+    // (V_q, W_j), j < s, for every q: one eight-value reduction per q
     for (int q0 = 0; q0 < nv; q0 += QU) {
       T a[QU][VN];
 #pragma unroll
@@ -664,30 +696,35 @@ __global__ __launch_bounds__(kBlock) void k_sstep_dots(int N, int ldv, const T* 
 #pragma unroll
       for (int u = 0; u < QU; ++u) {
         if (q0 + u < nv) {
+          double v[kSMax];
 #pragma unroll
           for (int j = 0; j < kSMax; ++j) {
-            if (j < s) {
-              double t = 0.0;
+            double t = 0.0;
 #pragma unroll
-              for (int c = 0; c < VN; ++c) t += (double)a[u][c] * (double)w[j][c];
-              t = wave_sum(t);
-              if (lane == 0) sh[(q0 + u) * s + j][wv] += t;
-            }
+            for (int c = 0; c < VN; ++c) t += (double)a[u][c] * w[j][c];
+            v[j] = t;
           }
+          const double x = wave_sum8(v);
+          if (writer) sh[(q0 + u) * s + p][wv] += x;
         }
       }
     }
+    // Gram entries (W_i, W_j), i <= j < s: one reduction per i
 #pragma unroll
     for (int i = 0; i < kSMax; ++i) {
+      if (i < s) {
+        double v[kSMax];
 #pragma unroll
-      for (int j = 0; j < kSMax; ++j) {
-        if (i < s && j >= i && j < s) {
+        for (int j = 0; j < kSMax; ++j) {
           double t = 0.0;
+          if (j >= i) {
 #pragma unroll
-          for (int c = 0; c < VN; ++c) t += (double)w[i][c] * (double)w[j][c];
-          t = wave_sum(t);
-          if (lane == 0) sh[gram_row(nv, s, i, j)][wv] += t;
+            for (int c = 0; c < VN; ++c) t += w[i][c] * w[j][c];
+          }
+          v[j] = t;
         }
+        const double x = wave_sum8(v);
+        if (writer && p >= i) sh[gram_row(nv, s, i, p)][wv] += x;
       }
     }
   }
@@ -719,9 +756,9 @@ __global__ __launch_bounds__(kBlock) void k_sstep_small(KState* ks, int k, int s
   __shared__ double Z[kRows * (kSMax + 1)];  // coordinates of W_0..W_s in [V_0..V_k, Q_1..Q_s]
   __shared__ double M1[kRows * kSMax];
   __shared__ double Hn[kRows * kSMax];       // new Hessenberg columns k..k+s-1
-  __shared__ double colw[kMaxRestart + 2];
+  __shared__ double HL[kMaxRestart * (kMaxRestart + 1)];  // raw Hessenberg columns 0..k-1
   __shared__ double gcs[kMaxRestart], gsn[kMaxRestart], gg[kMaxRestart + 1];  // rotations and rhs, staged
-  __shared__ int ok;
+  __shared__ int ok, ncols, stop, nonfinite;
   const int was_done = ks->done;
   __syncthreads();  // every thread has read done before thread 0 may set it below
   if (was_done) {
@@ -735,6 +772,10 @@ __global__ __launch_bounds__(kBlock) void k_sstep_small(KState* ks, int k, int s
     gsn[i] = ks->sn[i];
   }
   for (int i = threadIdx.x; i <= k; i += blockDim.x) gg[i] = ks->g[i];
+  for (int t = threadIdx.x; t < k * (k + 1); t += blockDim.x) {  // column c, rows 0..k
+    const int c = t / (k + 1), r = t % (k + 1);
+    HL[t] = r <= c + 1 ? ks->Hraw[(size_t)c * (m + 1) + r] : 0.0;
+  }
   __syncthreads();
   for (int t = threadIdx.x; t < s * s; t += blockDim.x) {  // G = W^T W - C^T C
     const int i = t / s, j = t % s;
@@ -743,34 +784,62 @@ __global__ __launch_bounds__(kBlock) void k_sstep_small(KState* ks, int k, int s
     G[t] = g;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0) {  // G = R^T R (R upper triangular) and R^{-1}, in registers
+    double g[kSMax][kSMax], r[kSMax][kSMax], ri[kSMax][kSMax];
+#pragma unroll
+    for (int i = 0; i < kSMax; ++i)
+#pragma unroll
+      for (int j = 0; j < kSMax; ++j) {
+        g[i][j] = (i < s && j < s) ? G[i * s + j] : 0.0;
+        r[i][j] = 0.0;
+        ri[i][j] = 0.0;
+      }
     bool good = true;
-    for (int j = 0; j < s && good; ++j) {  // G = R^T R, R upper triangular
-      double d = G[j * s + j];
-      for (int p = 0; p < j; ++p) d -= R[p * s + j] * R[p * s + j];
-      if (!(d > 0.0) || !isfinite(d)) {
-        good = false;
-        break;
-      }
-      const double rjj = sqrt(d);
-      R[j * s + j] = rjj;
-      for (int i = j + 1; i < s; ++i) {
-        double v = G[j * s + i];
-        for (int p = 0; p < j; ++p) v -= R[p * s + j] * R[p * s + i];
-        R[j * s + i] = v / rjj;
-      }
-      for (int i = 0; i < j; ++i) R[j * s + i] = 0.0;
-    }
-    if (good) {
-      for (int j = 0; j < s; ++j) {  // R^{-1}, column by column
-        for (int i = 0; i < s; ++i) Ri[i * s + j] = 0.0;
-        Ri[j * s + j] = 1.0 / R[j * s + j];
-        for (int i = j - 1; i >= 0; --i) {
-          double v = 0.0;
-          for (int p = i + 1; p <= j; ++p) v += R[i * s + p] * Ri[p * s + j];
-          Ri[i * s + j] = -v / R[i * s + i];
+#pragma unroll
+    for (int j = 0; j < kSMax; ++j) {
+      if (j < s && good) {
+        double d = g[j][j];
+#pragma unroll
+        for (int p = 0; p < j; ++p) d -= r[p][j] * r[p][j];
+        if (!(d > 0.0) || !isfinite(d)) {
+          good = false;
+        } else {
+          const double rjj = sqrt(d);
+          r[j][j] = rjj;
+#pragma unroll
+          for (int i = j + 1; i < kSMax; ++i) {
+            if (i < s) {
+              double v = g[j][i];
+#pragma unroll
+              for (int p = 0; p < j; ++p) v -= r[p][j] * r[p][i];
+              r[j][i] = v / rjj;
+            }
+          }
         }
       }
+    }
+    if (good) {
+#pragma unroll
+      for (int j = 0; j < kSMax; ++j) {  // R^{-1}, column by column
+        if (j < s) {
+          ri[j][j] = 1.0 / r[j][j];
+#pragma unroll
+          for (int i = j - 1; i >= 0; --i) {
+            double v = 0.0;
+#pragma unroll
+            for (int p = i + 1; p <= j; ++p) v += r[i][p] * ri[p][j];
+            ri[i][j] = -v / r[i][i];
+          }
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < kSMax; ++i)
+#pragma unroll
+        for (int j = 0; j < kSMax; ++j)
+          if (i < s && j < s) {
+            R[i * s + j] = r[i][j];
+            Ri[i * s + j] = ri[i][j];
+          }
     }
     ok = good;
   }
@@ -778,7 +847,7 @@ __global__ __launch_bounds__(kBlock) void k_sstep_small(KState* ks, int k, int s
   if (!ok) {
     if (threadIdx.x == 0) {
       ks->blk_ok = 0;
-      ks->pad_i[0] += 1;  // sticky count of failed blocks (the host falls back to one-vector steps)
+      ks->sfail += 1;  // sticky count of failed blocks (the host falls back to one-vector steps)
       ks->done = 1;
     }
     return;
@@ -810,7 +879,7 @@ __global__ __launch_bounds__(kBlock) void k_sstep_small(KState* ks, int k, int s
     const int r = t / s, j = t % s;
     double v = theta * Z[r * (s + 1) + j] + Z[r * (s + 1) + j + 1];
     if (r <= k)
-      for (int c = max(r - 1, 0); c < k; ++c) v -= ks->Hraw[(size_t)c * (m + 1) + r] * Z[c * (s + 1) + j];
+      for (int c = max(r - 1, 0); c < k; ++c) v -= HL[c * (k + 1) + r] * Z[c * (s + 1) + j];
     M1[t] = v;
   }
   __syncthreads();
@@ -827,17 +896,29 @@ __global__ __launch_bounds__(kBlock) void k_sstep_small(KState* ks, int k, int s
     const int j = t / nr, r = t % nr;
     if (r <= k + j + 1) ks->Hraw[(size_t)(k + j) * (m + 1) + r] = Hn[r * s + j];
   }
-  __shared__ int ncols, stop, nonfinite;
-  if (threadIdx.x == 0) {  // Givens rotations of the new columns, in LDS
+  __syncthreads();  // the raw columns are stored before the rotations change Hn
+  // rotations 0..k-1 of earlier blocks, one thread per new column
+  for (int j = threadIdx.x; j < ns; j += blockDim.x) {
+    double* col = Hn + j;  // column j of Hn, stride s
+    double cur = col[0];
+    for (int jj = 0; jj < k; ++jj) {
+      const double nxt = col[(jj + 1) * s];
+      col[jj * s] = gcs[jj] * cur + gsn[jj] * nxt;
+      cur = -gsn[jj] * cur + gcs[jj] * nxt;
+    }
+    col[k * s] = cur;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {  // rotations of this block, column by column
     const double tol = ks->tol;
     int j = 0;
     stop = 0;
     nonfinite = 0;
     for (; j < ns; ++j) {
       const int c = k + j;
-      double* col = Hn + j;  // column j of Hn, stride s
-      double cur = col[0];
-      for (int jj = 0; jj < c; ++jj) {
+      double* col = Hn + j;
+      double cur = col[k * s];
+      for (int jj = k; jj < c; ++jj) {
         const double nxt = col[(jj + 1) * s];
         col[jj * s] = gcs[jj] * cur + gsn[jj] * nxt;
         cur = -gsn[jj] * cur + gcs[jj] * nxt;
@@ -893,12 +974,15 @@ __global__ __launch_bounds__(kBlock) void k_sstep_small(KState* ks, int k, int s
   }
 }
 
-// Q = W R^{-1} - V (C R^{-1}), in place over the block V[k+1..k+s]
+// Q = W R^{-1} - V (C R^{-1}), in place over the block V[k+1..k+s].  The
+// basis part is summed first and W read last, so that W and the
+// accumulators are not live together.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_sstep_update(int N, int ldv, T* __restrict__ V, int k, int s,
                                                        const KState* __restrict__ ks) {
   constexpr int VN = 16 / sizeof(T);
   constexpr int CH = kBlock * VN;
+  constexpr int QU = 4;  // basis vectors loaded together
   __shared__ double D[(kMaxRestart + 1) * kSMax], Ri[kSMax * kSMax];
   __shared__ int okb;
   if (threadIdx.x == 0) okb = ks->blk_ok;
@@ -911,34 +995,42 @@ __global__ __launch_bounds__(kBlock) void k_sstep_update(int N, int ldv, T* __re
   T* __restrict__ W = V + (size_t)(k + 1) * ldv;
   for (int base = blockIdx.x * CH; base < N; base += gridDim.x * CH) {
     const int e = base + threadIdx.x * VN;
-    T w[kSMax][VN];
-#pragma unroll
-    for (int j = 0; j < kSMax; ++j)
-      if (j < s) load16(W + (size_t)j * ldv, e, N, w[j]);
     double acc[kSMax][VN];
 #pragma unroll
-    for (int j = 0; j < kSMax; ++j) {
+    for (int j = 0; j < kSMax; ++j)
 #pragma unroll
       for (int c = 0; c < VN; ++c) acc[j][c] = 0.0;
+    for (int q0 = 0; q0 < nv; q0 += QU) {
+      T a[QU][VN];
 #pragma unroll
-      for (int i = 0; i < kSMax; ++i)
-        if (i <= j && j < s) {
-          const double r = Ri[i * s + j];
+      for (int u = 0; u < QU; ++u)
+        if (q0 + u < nv) load16(V + (size_t)(q0 + u) * ldv, e, N, a[u]);
 #pragma unroll
-          for (int c = 0; c < VN; ++c) acc[j][c] += r * (double)w[i][c];
+      for (int u = 0; u < QU; ++u) {
+        if (q0 + u < nv) {
+#pragma unroll
+          for (int j = 0; j < kSMax; ++j)
+            if (j < s) {
+              const double d = D[(q0 + u) * s + j];
+#pragma unroll
+              for (int c = 0; c < VN; ++c) acc[j][c] -= d * (double)a[u][c];
+            }
         }
+      }
     }
-    for (int q = 0; q < nv; ++q) {
-      T a[VN];
-      load16(V + (size_t)q * ldv, e, N, a);
 #pragma unroll
-      for (int j = 0; j < kSMax; ++j)
-        if (j < s) {
-          const double d = D[q * s + j];
+    for (int i = 0; i < kSMax; ++i)
+      if (i < s) {
+        T w[VN];
+        load16(W + (size_t)i * ldv, e, N, w);
 #pragma unroll
-          for (int c = 0; c < VN; ++c) acc[j][c] -= d * (double)a[c];
-        }
-    }
+        for (int j = 0; j < kSMax; ++j)
+          if (i <= j && j < s) {
+            const double r = Ri[i * s + j];
+#pragma unroll
+            for (int c = 0; c < VN; ++c) acc[j][c] += r * (double)w[c];
+          }
+      }
 #pragma unroll
     for (int j = 0; j < kSMax; ++j)
       if (j < s) {
@@ -954,6 +1046,7 @@ __global__ __launch_bounds__(kBlock) void k_sstep_update(int N, int ldv, T* __re
 __global__ __launch_bounds__(64) void k_gmres_solve(KState* ks, int m) {
   __shared__ double R[kMaxRestart][kMaxRestart + 1];
   __shared__ double g[kMaxRestart];
+  if (ks->solved) return;
   const int kk = ks->k;
   for (int e = threadIdx.x; e < kk * kk; e += 64) {
     const int c = e / kk, row = e % kk;
@@ -976,6 +1069,7 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_gmres_xupdate(int N, int ldv, const T* __restrict__ V,
                                                           const double* __restrict__ dinv, double* __restrict__ x,
                                                           const KState* __restrict__ ks) {
+  if (ks->solved) return;
   constexpr int VN = 16 / sizeof(T);
   constexpr int CH = kBlock * VN;
   __shared__ double coef[kMaxRestart + 1];
@@ -1025,6 +1119,7 @@ constexpr int kFinish = 1024;
 __global__ __launch_bounds__(kFinish) void k_finish(KState* ks, const double* __restrict__ partials, int nb, int nv,
                                                     int act, int red_off, int k, int m, int mode, double p1,
                                                     double p2, int prow) {
+  if (act == ACT_CYCLE && mode != 0 && ks->solved) return;  // restart of a cycle queued after convergence
   switch (act) {
     case ACT_DOTS:
     case ACT_GIVENS:
@@ -2046,12 +2141,15 @@ void residual(H* h, const double* A, const double* b, const double* x, double* r
     h->prof_bytes[AFC_KERNEL_RESIDUAL] += sell_matrix_bytes(h, 8) + 24.0 * h->N + 8.0 * nb;
     h->prof_work[AFC_KERNEL_RESIDUAL] += 1;
   }
+  // inside a Krylov cycle (mode 1 / 2) the residual and its restart are
+  // skipped once the solve has converged
+  const int* skip = mode != 0 ? &h->ks->solved : nullptr;
   if (h->dlt16)
     launch(h, AFC_KERNEL_RESIDUAL, k_sell_residual<int16_t>, nb, kBlock, sell_view(h),
-           static_cast<const int16_t*>(h->sl_dlt), A, b, x, r, h->partials);
+           static_cast<const int16_t*>(h->sl_dlt), A, b, x, r, h->partials, skip);
   else
     launch(h, AFC_KERNEL_RESIDUAL, k_sell_residual<int32_t>, nb, kBlock, sell_view(h),
-           static_cast<const int32_t*>(h->sl_dlt), A, b, x, r, h->partials);
+           static_cast<const int32_t*>(h->sl_dlt), A, b, x, r, h->partials, skip);
   finish(h, nb, 1, ACT_CYCLE, 0, 0, 0, mode);
 }
 
@@ -2083,17 +2181,17 @@ void gmres_spmv64(H* h, const double* A, const double* dinv, int k) {
            static_cast<const int32_t*>(h->sl_dlt), A, dinv, x, (const KState*)h->ks, h->w[0]);
 }
 
-void spmv32(H* h, const float* A32, const float* x, float theta, float* y) {
+void spmv32(H* h, const float* A32, const float* x, float theta, int rev, float* y) {
   if (h->dlt16)
     launch(h, AFC_KERNEL_SPMV32, k_sell_spmv32<int16_t>, sell_grid(h, false), kBlock, sell_view(h),
-           static_cast<const int16_t*>(h->sl_dlt), A32, x, (const KState*)h->ks, theta, y);
+           static_cast<const int16_t*>(h->sl_dlt), A32, x, (const KState*)h->ks, theta, rev, y);
   else
     launch(h, AFC_KERNEL_SPMV32, k_sell_spmv32<int32_t>, sell_grid(h, false), kBlock, sell_view(h),
-           static_cast<const int32_t*>(h->sl_dlt), A32, x, (const KState*)h->ks, theta, y);
+           static_cast<const int32_t*>(h->sl_dlt), A32, x, (const KState*)h->ks, theta, rev, y);
 }
 
 void gmres_spmv32(H* h, const float* A32, int k) {
-  spmv32(h, A32, h->V32 + (size_t)k * h->ldv, 0.0f, reinterpret_cast<float*>(h->w[0]));
+  spmv32(h, A32, h->V32 + (size_t)k * h->ldv, 0.0f, 0, reinterpret_cast<float*>(h->w[0]));
 }
 
 void gmres_dots(H* h, bool fp32, int k) {

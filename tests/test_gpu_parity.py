@@ -594,7 +594,36 @@ def test_graph_replay_matches_plain_launches(prec):
         for it in range(4):
             sts = [afc.afc_solve_stationary(h, u, F)[1] for h, u in zip(hs, us)]
             assert sts[0]["krylov_iters"] == sts[1]["krylov_iters"] > 0
+            assert sts[0]["refine_sweeps"] == sts[1]["refine_sweeps"]
             assert torch.equal(us[0], us[1]), it
+    finally:
+        for h in hs:
+            afc.afc_destroy(h)
+
+
+@pytest.mark.parametrize("cap", [dict(lin_maxit=70), dict(refine_maxit=2)])
+def test_graph_queue_stops_at_caps(cap):
+    """Replayed GMRES cycles are queued one ahead of the host; at an
+    iteration or sweep cap the solve must stop exactly where cycles launched one
+    at a time stop: same status, iterations, sweeps and bitwise result."""
+    afc = _afc()
+    inst = I.config3(10)
+    hs = [afc.afc_create_instance(inst, _opts(precision=1, fp_tol=0.0, fp_tol_mode=1, fp_maxit=0, lin_atol=0.0,
+                                              lin_rtol=1e-12, graphs=g), conv=True)
+          for g in (1, 0)]
+    try:
+        us = [_dev(np.zeros(inst.N)) for _ in hs]
+        F = _dev(inst.F)
+        for h, u in zip(hs, us):
+            afc.afc_solve_stationary(h, u, F, init_low_order=True)
+            afc.afc_set_options(h, _opts(precision=1, fp_tol=0.0, fp_tol_mode=1, fp_maxit=2, lin_atol=0.0,
+                                         lin_rtol=1e-12, graphs=int(h is hs[0]), **cap))
+        outs = [afc.afc_solve_stationary(h, u, F, raise_on_error=False) for h, u in zip(hs, us)]
+        print("cap %s: %s" % (cap, [(st, s["krylov_iters"], s["refine_sweeps"]) for st, s in outs]), flush=True)
+        assert outs[0][0] == outs[1][0]
+        assert outs[0][1]["krylov_iters"] == outs[1][1]["krylov_iters"]
+        assert outs[0][1]["refine_sweeps"] == outs[1][1]["refine_sweeps"]
+        assert torch.equal(us[0], us[1])
     finally:
         for h in hs:
             afc.afc_destroy(h)
