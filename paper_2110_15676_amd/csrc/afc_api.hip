@@ -124,7 +124,7 @@ void free_all(afc_handle* h) {
   f(h->mij); f(h->dp_fct); f(h->AL_fct); f(h->mu_own);
   f(h->cc); f(h->ccT); f(h->AL_mcl); f(h->dinv_mcl);
   f(h->A_cn); f(h->dinv_cn);
-  f(h->sl_ptr); f(h->sl_dl); f(h->sl_pat); f(h->sl_dlt); f(h->sell_pos); f(h->S64_mcl); f(h->S32_mcl); f(h->S64_cn); f(h->S32_cn);
+  f(h->sl_ptr); f(h->sl_dl); f(h->sl_pat); f(h->sl_dlt); f(h->sell_pos); f(h->sl_mask); f(h->Scc); f(h->SccT); f(h->S64_mcl); f(h->S32_mcl); f(h->S64_cn); f(h->S32_cn);
   for (auto*& p : h->w) f(p);
   h->w.clear();
   f(h->V64); f(h->V32);
@@ -853,6 +853,22 @@ afc_status afc_create(const afc_problem* p, const afc_options* opt, afc_handle**
       HIP_OK(hipMemsetAsync(h->S32_cn, 0, slots * sizeof(float), h->stream));
       afc::to_sell64(h, h->AL_mcl, h->S64_mcl);
       afc::to_sell32_scaled(h, h->AL_mcl, h->dinv_mcl, h->S32_mcl);
+      // MCL bounds and fluxes over the SELL rows: masks of the stored slots and
+      // c_ij, c_ji in slot order (rows of up to 32 slots; longer rows keep CSR)
+      int maxlen = 0;
+      for (size_t sl = 0; sl + 1 < L.slp.size(); ++sl) maxlen = std::max(maxlen, (L.slp[sl + 1] - L.slp[sl]) / 64);
+      if (maxlen <= 32) {
+        std::vector<uint32_t> mask(N, 0u);
+        for (int i = 0; i < N; ++i)
+          for (int k = rp[i]; k < rp[i + 1]; ++k) mask[i] |= 1u << ((L.pos[k] - L.slp[i / 64]) / 64);
+        h->sl_mask = upload(h, mask, h->stream);
+        h->Scc = dalloc<double>(h, slots);
+        h->SccT = dalloc<double>(h, slots);
+        HIP_OK(hipMemsetAsync(h->Scc, 0, slots * sizeof(double), h->stream));
+        HIP_OK(hipMemsetAsync(h->SccT, 0, slots * sizeof(double), h->stream));
+        afc::to_sell64(h, h->cc, h->Scc);
+        afc::to_sell64(h, h->ccT, h->SccT);
+      }
     }
     // solver state
     h->partials = dalloc<double>(h, (size_t)kMaxRed * kRedBlocks);

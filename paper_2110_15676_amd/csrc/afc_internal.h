@@ -101,6 +101,9 @@ struct afc_handle_s {
   int64_t sell_lane_deltas = 0;  // per-lane deltas stored (other slices)
   int64_t sell_pat_ints = 0;  // entries of sl_pat
   void* sl_dlt = nullptr;     // per-lane deltas: int16 when every |j - i| <= 32767, else int32
+  uint32_t* sl_mask = nullptr;  // per row: bit p set when slot p holds a stored entry (rows of <= 32 slots)
+  double* Scc = nullptr;        // c_ij in SELL slot order (MCL)
+  double* SccT = nullptr;       // c_ji in SELL slot order (MCL)
   bool dlt16 = true;
   int* sell_pos = nullptr;    // [nnz]
   double* S64_mcl = nullptr;  // A_low (MCL) in SELL order

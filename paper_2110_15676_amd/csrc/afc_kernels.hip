@@ -1748,6 +1748,113 @@ __global__ __launch_bounds__(kBlock) void k_mcl_apply(
   block_partials<3>(acc, 3, partials, blockIdx.x);
 }
 
+// The same two passes over the SELL-64 rows (one row per lane, no column
+// array, no cross-lane sums).  mask[i] marks the slots of row i that hold a
+// stored entry: padding slots of a uniform slice can point at nodes outside
+// N_i, so they must not enter u^max / u^min.
+__device__ __forceinline__ int sell_delta(const SellView& S, const void* dlt, bool d16, int doff, int p, int lane) {
+  if (doff < 0) return S.pat[~doff + p];
+  return d16 ? (int)static_cast<const int16_t*>(dlt)[doff + 64 * p + lane]
+             : static_cast<const int*>(dlt)[doff + 64 * p + lane];
+}
+
+__global__ __launch_bounds__(kBlock) void k_mcl_bounds_sell(SellView S, const void* __restrict__ dlt, int d16,
+                                                            const uint32_t* __restrict__ mask,
+                                                            const double* __restrict__ u, double* __restrict__ umax,
+                                                            double* __restrict__ umin) {
+  int t0, t1;
+  tile_range((S.nsl + kBlock / 64 - 1) / (kBlock / 64), t0, t1);
+  for (int t = t0; t < t1; ++t) {
+    const int s = wave_slice(t);
+    if (s >= S.nsl) continue;
+    const int lane = threadIdx.x & 63;
+    const int i = s * 64 + lane;
+    if (i >= S.N) continue;
+    const int L = (S.sl_ptr[s + 1] - S.sl_ptr[s]) >> 6;
+    const int doff = S.sl_dl[s];
+    const uint32_t msk = mask[i];
+    double mx = -INFINITY, mn = INFINITY;
+#pragma unroll 4
+    for (int p = 0; p < L; ++p) {
+      const int j = i + sell_delta(S, dlt, d16, doff, p, lane);
+      if ((msk >> p) & 1u) {
+        const double uj = u[j];
+        mx = fmax(mx, uj);
+        mn = fmin(mn, uj);
+      }
+    }
+    umax[i] = mx;
+    umin[i] = mn;
+  }
+}
+
+// A_low, c_ij and c_ji in SELL slot order (Sal, Scc, SccT)
+__global__ __launch_bounds__(kBlock) void k_mcl_apply_sell(
+    SellView S, const void* __restrict__ dlt, int d16, const uint32_t* __restrict__ mask,
+    const double* __restrict__ Scc, const double* __restrict__ SccT, const double* __restrict__ Sal,
+    const double* __restrict__ u, const double* __restrict__ umax, const double* __restrict__ umin,
+    const double* __restrict__ F, const uint8_t* __restrict__ is_dir, const double* __restrict__ uD, int alpha_mode,
+    double* __restrict__ b, double* __restrict__ r, double* partials) {
+  double acc[3] = {0.0, 0.0, 0.0};
+  int t0, t1;
+  tile_range((S.nsl + kBlock / 64 - 1) / (kBlock / 64), t0, t1);
+  for (int t = t0; t < t1; ++t) {
+    const int s = wave_slice(t);
+    if (s >= S.nsl) continue;
+    const int lane = threadIdx.x & 63;
+    const int i = s * 64 + lane;
+    if (i >= S.N) continue;
+    if (is_dir[i]) {
+      const double bi = uD[i], ri = uD[i] - u[i];
+      b[i] = bi;
+      r[i] = ri;
+      acc[1] += bi * bi;
+      acc[2] += ri * ri;
+      continue;
+    }
+    const int base = S.sl_ptr[s];
+    const int L = (S.sl_ptr[s + 1] - base) >> 6;
+    const int doff = S.sl_dl[s];
+    const uint32_t msk = mask[i];
+    const double ui = u[i], umaxi = umax[i], umini = umin[i];
+    double fs = 0.0, au = 0.0;
+#pragma unroll 2
+    for (int p = 0; p < L; ++p) {
+      if (!((msk >> p) & 1u)) continue;
+      const int dj = sell_delta(S, dlt, d16, doff, p, lane);
+      const int j = i + dj;
+      const size_t v = (size_t)base + 64 * p + lane;
+      const double uj = u[j];
+      au += Sal[v] * uj;
+      if (dj == 0 || alpha_mode == AFC_ALPHA_ZERO) continue;
+      const double c = Scc[v], ct = SccT[v];
+      const double d = -fmax(fmax(c, 0.0), ct);
+      if (d == 0.0) continue;
+      const double rf = d * (uj - ui);
+      if (alpha_mode == AFC_ALPHA_ONE) {
+        fs += rf;
+        continue;
+      }
+      const double sij = d * (ui + uj) + c * (uj - ui);
+      const double sji = d * (ui + uj) + ct * (ui - uj);
+      const double two_d = 2.0 * d;
+      double rs;
+      if (rf > 0.0)
+        rs = fmin(rf, fmin(sij - two_d * umaxi, two_d * umin[j] - sji));
+      else
+        rs = fmax(rf, fmax(sij - two_d * umini, two_d * umax[j] - sji));
+      fs += rs;
+    }
+    const double bi = F[i] + fs, ri = bi - au;
+    b[i] = bi;
+    r[i] = ri;
+    acc[0] += ri * ri;
+    acc[1] += bi * bi;
+    acc[2] += ri * ri;
+  }
+  block_partials<3>(acc, 3, partials, blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // Time-dependent monolithic convex limiting (Sec. 2.2): the fluxes of eq. (20),
 // r_ij = m_ij (udot_i - udot_j) + d_ij (u_j - u_i), d_ij = -max(c_ij, 0, c_ji)
@@ -2353,7 +2460,22 @@ void cn_apply(H* h, const double* u, const double* u_old, const double* Rp, cons
   finish(h, nb, 3, ACT_STORE);
 }
 
+// bytes of the SELL slice headers, patterns and per-lane deltas
+static double sell_index_bytes(const H* h) {
+  return (double)h->sell_pat_ints * 4.0 + (double)h->sell_lane_deltas * (h->dlt16 ? 2.0 : 4.0) +
+         8.0 * h->nslices + 4.0;
+}
+
 void mcl_bounds(H* h, const double* u, double* umax, double* umin) {
+  if (h->sl_mask) {
+    if (h->opt.profile) {  // slice index, masks, u, u^max, u^min
+      h->prof_bytes[AFC_KERNEL_MCL] += sell_index_bytes(h) + 4.0 * h->N + 24.0 * h->N;
+      h->prof_work[AFC_KERNEL_MCL] += 1;
+    }
+    launch(h, AFC_KERNEL_MCL, k_mcl_bounds_sell, sell_grid(h, false), kBlock, sell_view(h),
+           (const void*)h->sl_dlt, (int)h->dlt16, (const uint32_t*)h->sl_mask, u, umax, umin);
+    return;
+  }
   if (h->opt.profile) {  // row_ptr, col, u, u^max, u^min
     h->prof_bytes[AFC_KERNEL_MCL] += 4.0 * (h->N + 1) + 4.0 * h->nnz + 24.0 * h->N;
     h->prof_work[AFC_KERNEL_MCL] += 1;
@@ -2362,6 +2484,18 @@ void mcl_bounds(H* h, const double* u, double* umax, double* umin) {
 }
 
 void mcl_apply(H* h, const double* u, const double* umax, const double* umin, const double* F, double* b, double* r) {
+  if (h->sl_mask) {
+    const int nb = sell_grid(h, true);
+    if (h->opt.profile) {  // slice index, masks, A_low, c_ij, c_ji slots; u, bounds, F, u_D, flags; b, r, partials
+      h->prof_bytes[AFC_KERNEL_MCL] += sell_index_bytes(h) + 24.0 * h->sell_slots + 4.0 * h->N + 57.0 * h->N + 24.0 * nb;
+      h->prof_work[AFC_KERNEL_MCL] += 1;
+    }
+    launch(h, AFC_KERNEL_MCL, k_mcl_apply_sell, nb, kBlock, sell_view(h), (const void*)h->sl_dlt, (int)h->dlt16,
+           (const uint32_t*)h->sl_mask, (const double*)h->Scc, (const double*)h->SccT, (const double*)h->S64_mcl, u,
+           umax, umin, F, (const uint8_t*)h->is_dir, (const double*)h->uD, h->opt.alpha_mode, b, r, h->partials);
+    finish(h, nb, 3, ACT_STORE);
+    return;
+  }
   const int nb = row_grid(h, true);
   if (h->opt.profile) {  // row_ptr, col, c_ij, c_ji, A_low; u, bounds, F, u_D, Dirichlet flags; b, r, partials
     h->prof_bytes[AFC_KERNEL_MCL] += 4.0 * (h->N + 1) + 28.0 * h->nnz + 57.0 * h->N + 24.0 * nb;
