@@ -376,7 +376,7 @@ def traffic_summarize(fetch_csv, write_csv, probe_log, n):
     sf, sw = gib_kib / (sum(cf[:3]) / 3), gib_kib / (sum(cw[:3]) / 3)
     table = {}
     for name in ("k_sell_spmv32", "k_gmres_dots", "k_gmres_update", "k_gmres_reduce", "k_sstep_dots",
-                 "k_sstep_update", "k_sstep_sums", "k_sell_residual", "k_mcl_bounds", "k_mcl_apply"):
+                 "k_sstep_update", "k_sstep_sums", "k_sell_residual", "k_mcl_bounds_sell", "k_mcl_apply_sell"):
         f = [v for v in series(fe, name) if v > 1024]
         w = [v for v in series(wr, name) if v > 1024]
         if f:

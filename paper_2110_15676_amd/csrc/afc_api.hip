@@ -128,7 +128,7 @@ void free_all(afc_handle* h) {
   for (auto*& p : h->w) f(p);
   h->w.clear();
   f(h->V64); f(h->V32);
-  f(h->partials); f(h->partials_blk); f(h->ks);
+  f(h->partials); f(h->partials_res); f(h->partials_blk); f(h->ks);
   if (h->host_status) (void)hipHostFree(h->host_status);
   h->host_status = nullptr;
   if (h->ring) (void)hipHostFree(h->ring);
@@ -854,24 +854,27 @@ afc_status afc_create(const afc_problem* p, const afc_options* opt, afc_handle**
       afc::to_sell64(h, h->AL_mcl, h->S64_mcl);
       afc::to_sell32_scaled(h, h->AL_mcl, h->dinv_mcl, h->S32_mcl);
       // MCL bounds and fluxes over the SELL rows: masks of the stored slots and
-      // c_ij, c_ji in slot order (rows of up to 32 slots; longer rows keep CSR)
-      int maxlen = 0;
+      // c_ij, c_ji in slot order
+      int maxlen = 1;
       for (size_t sl = 0; sl + 1 < L.slp.size(); ++sl) maxlen = std::max(maxlen, (L.slp[sl + 1] - L.slp[sl]) / 64);
-      if (maxlen <= 32) {
-        std::vector<uint32_t> mask(N, 0u);
-        for (int i = 0; i < N; ++i)
-          for (int k = rp[i]; k < rp[i + 1]; ++k) mask[i] |= 1u << ((L.pos[k] - L.slp[i / 64]) / 64);
-        h->sl_mask = upload(h, mask, h->stream);
-        h->Scc = dalloc<double>(h, slots);
-        h->SccT = dalloc<double>(h, slots);
-        HIP_OK(hipMemsetAsync(h->Scc, 0, slots * sizeof(double), h->stream));
-        HIP_OK(hipMemsetAsync(h->SccT, 0, slots * sizeof(double), h->stream));
-        afc::to_sell64(h, h->cc, h->Scc);
-        afc::to_sell64(h, h->ccT, h->SccT);
-      }
+      h->mask_words = (maxlen + 31) / 32;
+      std::vector<uint32_t> mask((size_t)h->mask_words * N, 0u);
+      for (int i = 0; i < N; ++i)
+        for (int k = rp[i]; k < rp[i + 1]; ++k) {
+          const int p = (L.pos[k] - L.slp[i / 64]) / 64;
+          mask[(size_t)(p / 32) * N + i] |= 1u << (p % 32);
+        }
+      h->sl_mask = upload(h, mask, h->stream);
+      h->Scc = dalloc<double>(h, slots);
+      h->SccT = dalloc<double>(h, slots);
+      HIP_OK(hipMemsetAsync(h->Scc, 0, slots * sizeof(double), h->stream));
+      HIP_OK(hipMemsetAsync(h->SccT, 0, slots * sizeof(double), h->stream));
+      afc::to_sell64(h, h->cc, h->Scc);
+      afc::to_sell64(h, h->ccT, h->SccT);
     }
     // solver state
     h->partials = dalloc<double>(h, (size_t)kMaxRed * kRedBlocks);
+    h->partials_res = dalloc<double>(h, (size_t)std::max(1, afc::sell_grid(h, false)));
     h->ks = dalloc<KState>(h, 1);
     HIP_OK(hipMemsetAsync(h->ks, 0, sizeof(KState), h->stream));
     if (hipHostMalloc((void**)&h->host_status, sizeof(KState), hipHostMallocDefault) != hipSuccess)

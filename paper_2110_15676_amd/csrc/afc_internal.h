@@ -101,7 +101,8 @@ struct afc_handle_s {
   int64_t sell_lane_deltas = 0;  // per-lane deltas stored (other slices)
   int64_t sell_pat_ints = 0;  // entries of sl_pat
   void* sl_dlt = nullptr;     // per-lane deltas: int16 when every |j - i| <= 32767, else int32
-  uint32_t* sl_mask = nullptr;  // per row: bit p set when slot p holds a stored entry (rows of <= 32 slots)
+  uint32_t* sl_mask = nullptr;  // bit p % 32 of word [p / 32][row]: slot p of the row holds a stored entry
+  int mask_words = 1;           // 32-slot words per row
   double* Scc = nullptr;        // c_ij in SELL slot order (MCL)
   double* SccT = nullptr;       // c_ji in SELL slot order (MCL)
   bool dlt16 = true;
@@ -125,6 +126,7 @@ struct afc_handle_s {
   int Vm = 0;
   int ldv = 0;  // basis / work vector stride: N rounded up to 64 (16-byte aligned rows)
   double* partials = nullptr;  // kMaxRed * kRedBlocks
+  double* partials_res = nullptr;  // one per workgroup of the FP64 SELL residual
   double* partials_blk = nullptr;  // kBlkRows * kRedBlocks (s-step GMRES, allocated on first use)
   afc::KState* ks = nullptr;
   afc::KState* host_status = nullptr;  // pinned copy of the KState head

@@ -22,6 +22,9 @@ void build_cn_matrix(H* h, const double* AL, double dt);
 void to_sell64(H* h, const double* csr, double* sell);                       // CSR values -> SELL slots
 void to_sell32_scaled(H* h, const double* csr, const double* dinv, float* sell);  // (a_ij dinv_j) in FP32
 
+// workgroups of a launch over the SELL tiles (reduce: capped at the partial slots)
+int sell_grid(const H* h, bool reduce);
+
 // --- residual of a linear system (FP64 SpMV) -----------------------------------
 // r = b - A x (A in SELL order) and ||r||^2 into ks->red[0]; mode selects the cycle start that
 // the reduction finish performs (0: none, 1: GMRES FP64 restart into V64[0],

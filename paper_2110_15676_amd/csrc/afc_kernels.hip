@@ -1136,11 +1136,25 @@ __global__ __launch_bounds__(kFinish) void k_finish(KState* ks, const double* __
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double* red = ks->red + red_off;
-  for (int q = wv; q < nv; q += kFinish / 64) {
+  if (nv == 1) {  // one row: every wave takes a strided share, then the wave totals in order
+    __shared__ double sw[kFinish / 64];
     double s = 0.0;
-    for (int b = lane; b < nb; b += 64) s += partials[(size_t)(prow + q) * kRedBlocks + b];
+    for (int b = threadIdx.x; b < nb; b += kFinish) s += partials[(size_t)prow * kRedBlocks + b];
     s = wave_sum(s);
-    if (lane == 0) red[q] = s;
+    if (lane == 0) sw[wv] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int w = 0; w < kFinish / 64; ++w) t += sw[w];
+      red[0] = t;
+    }
+  } else {
+    for (int q = wv; q < nv; q += kFinish / 64) {
+      double s = 0.0;
+      for (int b = lane; b < nb; b += 64) s += partials[(size_t)(prow + q) * kRedBlocks + b];
+      s = wave_sum(s);
+      if (lane == 0) red[q] = s;
+    }
   }
   __syncthreads();
   if (act == ACT_DOTS) {
@@ -1653,105 +1667,12 @@ __global__ __launch_bounds__(kBlock) void k_cn_apply(
 // Monolithic convex limiter (eqs. (22)-(23), (25), Remark 1)
 // ---------------------------------------------------------------------------
 
-template <int G>
-__global__ __launch_bounds__(kBlock) void k_mcl_bounds(int N, const int* __restrict__ rp,
-                                                       const int* __restrict__ col, const double* __restrict__ u,
-                                                       double* __restrict__ umax, double* __restrict__ umin) {
-  constexpr int RPB = kBlock / G;
-  const int lane = threadIdx.x % G, sub = threadIdx.x / G;
-  int t0, t1;
-  tile_range((N + RPB - 1) / RPB, t0, t1);
-  for (int t = t0; t < t1; ++t) {
-    const int i = t * RPB + sub;
-    if (i >= N) continue;
-    double mx = -INFINITY, mn = INFINITY;
-    const int e = rp[i + 1];
-    for (int k = rp[i] + lane; k < e; k += G) {
-      const double uj = u[col[k]];
-      mx = fmax(mx, uj);
-      mn = fmin(mn, uj);
-    }
-    mx = gmax<G>(mx);
-    mn = gmin<G>(mn);
-    if (lane == 0) {
-      umax[i] = mx;
-      umin[i] = mn;
-    }
-  }
-}
+// Both passes run over the SELL-64 rows: one row per lane, no column array,
+// no cross-lane sums.  Bit p % 32 of mask[(p / 32) N + i] marks slot p of
+// row i as a stored entry: padding slots of a uniform slice can point at
+// nodes outside N_i, so they must not enter u^max / u^min or the fluxes.
 
-// r*_ij from d_ij = -max(c_ij, 0, c_ji) and the bar states in product form
-// 2 d_ij ubar_ij = d_ij (u_i + u_j) + c_ij (u_j - u_i); F*_i = sum_j r*_ij;
-// b = F + F*, r = b - A_low u ; reductions: R^2 (free rows), ||b||^2, ||r||^2
-template <int G>
-__global__ __launch_bounds__(kBlock) void k_mcl_apply(
-    int N, const int* __restrict__ rp, const int* __restrict__ col, const double* __restrict__ cc,
-    const double* __restrict__ ccT, const double* __restrict__ AL, const double* __restrict__ u,
-    const double* __restrict__ umax, const double* __restrict__ umin, const double* __restrict__ F,
-    const uint8_t* __restrict__ is_dir, const double* __restrict__ uD, int alpha_mode, double* __restrict__ b,
-    double* __restrict__ r, KState* ks, double* partials) {
-  constexpr int RPB = kBlock / G;
-  const int lane = threadIdx.x % G, sub = threadIdx.x / G;
-  double acc[3] = {0.0, 0.0, 0.0};
-  int t0, t1;
-  tile_range((N + RPB - 1) / RPB, t0, t1);
-  for (int t = t0; t < t1; ++t) {
-    const int i = t * RPB + sub;
-    if (i >= N) continue;
-    if (is_dir[i]) {
-      if (lane == 0) {
-        const double bi = uD[i], ri = uD[i] - u[i];
-        b[i] = bi;
-        r[i] = ri;
-        acc[1] += bi * bi;
-        acc[2] += ri * ri;
-      }
-      continue;
-    }
-    const double ui = u[i], umaxi = umax[i], umini = umin[i];
-    double fs = 0.0, au = 0.0;
-    const int e = rp[i + 1];
-    for (int k = rp[i] + lane; k < e; k += G) {
-      const int j = col[k];
-      const double uj = u[j];
-      au += AL[k] * uj;
-      if (j == i || alpha_mode == AFC_ALPHA_ZERO) continue;
-      const double c = cc[k], ct = ccT[k];
-      const double d = -fmax(fmax(c, 0.0), ct);
-      if (d == 0.0) continue;
-      const double rf = d * (uj - ui);
-      if (alpha_mode == AFC_ALPHA_ONE) {
-        fs += rf;
-        continue;
-      }
-      const double sij = d * (ui + uj) + c * (uj - ui);
-      const double sji = d * (ui + uj) + ct * (ui - uj);
-      const double two_d = 2.0 * d;
-      double rs;
-      if (rf > 0.0)
-        rs = fmin(rf, fmin(sij - two_d * umaxi, two_d * umin[j] - sji));
-      else
-        rs = fmax(rf, fmax(sij - two_d * umini, two_d * umax[j] - sji));
-      fs += rs;
-    }
-    fs = gsum<G>(fs);
-    au = gsum<G>(au);
-    if (lane == 0) {
-      const double bi = F[i] + fs, ri = bi - au;
-      b[i] = bi;
-      r[i] = ri;
-      acc[0] += ri * ri;
-      acc[1] += bi * bi;
-      acc[2] += ri * ri;
-    }
-  }
-  block_partials<3>(acc, 3, partials, blockIdx.x);
-}
-
-// The same two passes over the SELL-64 rows (one row per lane, no column
-// array, no cross-lane sums).  mask[i] marks the slots of row i that hold a
-// stored entry: padding slots of a uniform slice can point at nodes outside
-// N_i, so they must not enter u^max / u^min.
+// u^max_i, u^min_i: extremes of u over N_i (i included)
 __device__ __forceinline__ int sell_delta(const SellView& S, const void* dlt, bool d16, int doff, int p, int lane) {
   if (doff < 0) return S.pat[~doff + p];
   return d16 ? (int)static_cast<const int16_t*>(dlt)[doff + 64 * p + lane]
@@ -1772,12 +1693,13 @@ __global__ __launch_bounds__(kBlock) void k_mcl_bounds_sell(SellView S, const vo
     if (i >= S.N) continue;
     const int L = (S.sl_ptr[s + 1] - S.sl_ptr[s]) >> 6;
     const int doff = S.sl_dl[s];
-    const uint32_t msk = mask[i];
+    uint32_t msk = 0u;
     double mx = -INFINITY, mn = INFINITY;
 #pragma unroll 4
     for (int p = 0; p < L; ++p) {
+      if ((p & 31) == 0) msk = mask[(size_t)(p >> 5) * S.N + i];
       const int j = i + sell_delta(S, dlt, d16, doff, p, lane);
-      if ((msk >> p) & 1u) {
+      if ((msk >> (p & 31)) & 1u) {
         const double uj = u[j];
         mx = fmax(mx, uj);
         mn = fmin(mn, uj);
@@ -1788,7 +1710,10 @@ __global__ __launch_bounds__(kBlock) void k_mcl_bounds_sell(SellView S, const vo
   }
 }
 
-// A_low, c_ij and c_ji in SELL slot order (Sal, Scc, SccT)
+// r*_ij from d_ij = -max(c_ij, 0, c_ji) and the bar states in product form
+// 2 d_ij ubar_ij = d_ij (u_i + u_j) + c_ij (u_j - u_i); F*_i = sum_j r*_ij;
+// b = F + F*, r = b - A_low u; reductions: R^2 (free rows), ||b||^2, ||r||^2.
+// A_low, c_ij and c_ji come in SELL slot order (Sal, Scc, SccT).
 __global__ __launch_bounds__(kBlock) void k_mcl_apply_sell(
     SellView S, const void* __restrict__ dlt, int d16, const uint32_t* __restrict__ mask,
     const double* __restrict__ Scc, const double* __restrict__ SccT, const double* __restrict__ Sal,
@@ -1815,12 +1740,13 @@ __global__ __launch_bounds__(kBlock) void k_mcl_apply_sell(
     const int base = S.sl_ptr[s];
     const int L = (S.sl_ptr[s + 1] - base) >> 6;
     const int doff = S.sl_dl[s];
-    const uint32_t msk = mask[i];
+    uint32_t msk = 0u;
     const double ui = u[i], umaxi = umax[i], umini = umin[i];
     double fs = 0.0, au = 0.0;
 #pragma unroll 2
     for (int p = 0; p < L; ++p) {
-      if (!((msk >> p) & 1u)) continue;
+      if ((p & 31) == 0) msk = mask[(size_t)(p >> 5) * S.N + i];
+      if (!((msk >> (p & 31)) & 1u)) continue;
       const int dj = sell_delta(S, dlt, d16, doff, p, lane);
       const int j = i + dj;
       const size_t v = (size_t)base + 64 * p + lane;
@@ -2201,10 +2127,14 @@ void prof_release(afc_handle_s* h) {
   h->ev_pool.clear();
 }
 
+void finish_from(H* h, const double* partials, int nb, int nv, int act, int red_off = 0, int k = 0, int m = 0,
+                 int mode = 0, double p1 = 0.0, double p2 = 0.0, int prow = 0) {
+  launch(h, AFC_KERNEL_FINISH, k_finish, 1, kFinish, h->ks, partials, nb, nv, act, red_off, k, m, mode, p1, p2, prow);
+}
+
 void finish(H* h, int nb, int nv, int act, int red_off = 0, int k = 0, int m = 0, int mode = 0, double p1 = 0.0,
             double p2 = 0.0, int prow = 0) {
-  launch(h, AFC_KERNEL_FINISH, k_finish, 1, kFinish, h->ks, (const double*)h->partials, nb, nv, act, red_off, k, m,
-         mode, p1, p2, prow);
+  finish_from(h, h->partials, nb, nv, act, red_off, k, m, mode, p1, p2, prow);
 }
 
 void copy(H* h, double* dst, const double* src) { k_copy<<<vec_grid(h), kBlock, 0, h->stream>>>(h->N, dst, src); }
@@ -2242,8 +2172,9 @@ int sell_grid(const H* h, bool reduce) {
 
 SellView sell_view(const H* h) { return SellView{h->N, h->nslices, h->sl_ptr, h->sl_dl, h->sl_pat}; }
 
+// one workgroup per tile of slices, with partials of its own (one per workgroup)
 void residual(H* h, const double* A, const double* b, const double* x, double* r, int mode) {
-  const int nb = sell_grid(h, true);
+  const int nb = sell_grid(h, false);
   if (h->opt.profile) {
     h->prof_bytes[AFC_KERNEL_RESIDUAL] += sell_matrix_bytes(h, 8) + 24.0 * h->N + 8.0 * nb;
     h->prof_work[AFC_KERNEL_RESIDUAL] += 1;
@@ -2253,11 +2184,11 @@ void residual(H* h, const double* A, const double* b, const double* x, double* r
   const int* skip = mode != 0 ? &h->ks->solved : nullptr;
   if (h->dlt16)
     launch(h, AFC_KERNEL_RESIDUAL, k_sell_residual<int16_t>, nb, kBlock, sell_view(h),
-           static_cast<const int16_t*>(h->sl_dlt), A, b, x, r, h->partials, skip);
+           static_cast<const int16_t*>(h->sl_dlt), A, b, x, r, h->partials_res, skip);
   else
     launch(h, AFC_KERNEL_RESIDUAL, k_sell_residual<int32_t>, nb, kBlock, sell_view(h),
-           static_cast<const int32_t*>(h->sl_dlt), A, b, x, r, h->partials, skip);
-  finish(h, nb, 1, ACT_CYCLE, 0, 0, 0, mode);
+           static_cast<const int32_t*>(h->sl_dlt), A, b, x, r, h->partials_res, skip);
+  finish_from(h, h->partials_res, nb, 1, ACT_CYCLE, 0, 0, 0, mode);
 }
 
 void to_sell64(H* h, const double* csr, double* sell) {
@@ -2467,42 +2398,24 @@ static double sell_index_bytes(const H* h) {
 }
 
 void mcl_bounds(H* h, const double* u, double* umax, double* umin) {
-  if (h->sl_mask) {
-    if (h->opt.profile) {  // slice index, masks, u, u^max, u^min
-      h->prof_bytes[AFC_KERNEL_MCL] += sell_index_bytes(h) + 4.0 * h->N + 24.0 * h->N;
-      h->prof_work[AFC_KERNEL_MCL] += 1;
-    }
-    launch(h, AFC_KERNEL_MCL, k_mcl_bounds_sell, sell_grid(h, false), kBlock, sell_view(h),
-           (const void*)h->sl_dlt, (int)h->dlt16, (const uint32_t*)h->sl_mask, u, umax, umin);
-    return;
-  }
-  if (h->opt.profile) {  // row_ptr, col, u, u^max, u^min
-    h->prof_bytes[AFC_KERNEL_MCL] += 4.0 * (h->N + 1) + 4.0 * h->nnz + 24.0 * h->N;
+  if (h->opt.profile) {  // slice index, masks, u, u^max, u^min
+    h->prof_bytes[AFC_KERNEL_MCL] += sell_index_bytes(h) + 4.0 * h->mask_words * h->N + 24.0 * h->N;
     h->prof_work[AFC_KERNEL_MCL] += 1;
   }
-  AFC_DISPATCH_G_TIMED(h, AFC_KERNEL_MCL, k_mcl_bounds, row_grid(h, false), h->N, h->row_ptr, h->col, u, umax, umin);
+  launch(h, AFC_KERNEL_MCL, k_mcl_bounds_sell, sell_grid(h, false), kBlock, sell_view(h), (const void*)h->sl_dlt,
+         (int)h->dlt16, (const uint32_t*)h->sl_mask, u, umax, umin);
 }
 
 void mcl_apply(H* h, const double* u, const double* umax, const double* umin, const double* F, double* b, double* r) {
-  if (h->sl_mask) {
-    const int nb = sell_grid(h, true);
-    if (h->opt.profile) {  // slice index, masks, A_low, c_ij, c_ji slots; u, bounds, F, u_D, flags; b, r, partials
-      h->prof_bytes[AFC_KERNEL_MCL] += sell_index_bytes(h) + 24.0 * h->sell_slots + 4.0 * h->N + 57.0 * h->N + 24.0 * nb;
-      h->prof_work[AFC_KERNEL_MCL] += 1;
-    }
-    launch(h, AFC_KERNEL_MCL, k_mcl_apply_sell, nb, kBlock, sell_view(h), (const void*)h->sl_dlt, (int)h->dlt16,
-           (const uint32_t*)h->sl_mask, (const double*)h->Scc, (const double*)h->SccT, (const double*)h->S64_mcl, u,
-           umax, umin, F, (const uint8_t*)h->is_dir, (const double*)h->uD, h->opt.alpha_mode, b, r, h->partials);
-    finish(h, nb, 3, ACT_STORE);
-    return;
-  }
-  const int nb = row_grid(h, true);
-  if (h->opt.profile) {  // row_ptr, col, c_ij, c_ji, A_low; u, bounds, F, u_D, Dirichlet flags; b, r, partials
-    h->prof_bytes[AFC_KERNEL_MCL] += 4.0 * (h->N + 1) + 28.0 * h->nnz + 57.0 * h->N + 24.0 * nb;
+  const int nb = sell_grid(h, true);
+  if (h->opt.profile) {  // slice index, masks, A_low, c_ij, c_ji slots; u, bounds, F, u_D, flags; b, r, partials
+    h->prof_bytes[AFC_KERNEL_MCL] +=
+        sell_index_bytes(h) + 4.0 * h->mask_words * h->N + 24.0 * h->sell_slots + 57.0 * h->N + 24.0 * nb;
     h->prof_work[AFC_KERNEL_MCL] += 1;
   }
-  AFC_DISPATCH_G_TIMED(h, AFC_KERNEL_MCL, k_mcl_apply, nb, h->N, h->row_ptr, h->col, h->cc, h->ccT, h->AL_mcl, u,
-                       umax, umin, F, h->is_dir, h->uD, h->opt.alpha_mode, b, r, h->ks, h->partials);
+  launch(h, AFC_KERNEL_MCL, k_mcl_apply_sell, nb, kBlock, sell_view(h), (const void*)h->sl_dlt, (int)h->dlt16,
+         (const uint32_t*)h->sl_mask, (const double*)h->Scc, (const double*)h->SccT, (const double*)h->S64_mcl, u,
+         umax, umin, F, (const uint8_t*)h->is_dir, (const double*)h->uD, h->opt.alpha_mode, b, r, h->partials);
   finish(h, nb, 3, ACT_STORE);
 }
 

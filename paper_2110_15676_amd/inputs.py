@@ -541,6 +541,46 @@ def renumbered(inst: Instance, seed=(0, 9)) -> Instance:
                     coords=nodal(inst.coords), params=dict(inst.params, perm=perm))
 
 
+def with_long_row(inst: Instance, extra: int = 40, seed=(0, 11)) -> Instance:
+    """The same problem with its middle node coupled to `extra` further nodes,
+    a row longer than any mesh stencil.  The new entries are structurally
+    symmetric, carry zero mass and small antisymmetric convective values
+    (k_ij = -k_ji in K and K_conv), and the diagonals absorb them so that every
+    row of K and K_conv keeps its sum."""
+    rng = np.random.default_rng(seed)
+    N = inst.N
+    node = N // 2
+    rows = inst.row_index()
+    cols = inst.col.astype(np.int64)
+    near = set(cols[inst.row_ptr[node]:inst.row_ptr[node + 1]].tolist())
+    cand = np.array([j for j in range(N) if j not in near], dtype=np.int64)
+    js = np.sort(rng.choice(cand, size=extra, replace=False))
+    a = rng.uniform(-0.01, 0.01, size=extra)
+    r_all = np.concatenate([rows, np.full(extra, node), js])
+    c_all = np.concatenate([cols, js, np.full(extra, node)])
+    order = np.lexsort((c_all, r_all))
+    counts = np.bincount(r_all, minlength=N)
+    row_ptr = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+    col = c_all[order].astype(np.int32)
+
+    def coupled(v):
+        out = np.concatenate([v, a, -a])[order]
+        # diagonal entries absorb the new couplings (row sums unchanged)
+        diag = np.empty(N, dtype=np.int64)
+        for i in range(N):
+            k = row_ptr[i] + np.searchsorted(col[row_ptr[i]:row_ptr[i + 1]], i)
+            diag[i] = k
+        out[diag[node]] -= a.sum()
+        np.add.at(out, diag[js], a)
+        return out
+
+    return Instance(elem=inst.elem, n=inst.n, N=N, row_ptr=row_ptr, col=col,
+                    M=np.concatenate([inst.M, np.zeros(2 * extra)])[order], K=coupled(inst.K),
+                    K_conv=coupled(inst.K_conv), F=inst.F.copy(), dir_idx=inst.dir_idx.copy(),
+                    dir_val=inst.dir_val.copy(), u0=inst.u0.copy(), coords=inst.coords.copy(),
+                    params=dict(inst.params, long_row=node))
+
+
 # ----------------------------------------------------------------------------
 # The paper's analytic accuracy examples, on this package's meshes
 # ----------------------------------------------------------------------------

@@ -270,6 +270,32 @@ def test_mcl_renumbered_parity(prec):
         afc.afc_destroy(h)
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_mcl_long_row_parity(prec):
+    """A node coupled to 40 extra nodes (a row of 67 stored entries, three
+    32-slot mask words; the other rows of its slice padded to 67 slots): five
+    MCL fixed-point iterations from the low-order solution against the oracle."""
+    afc = _afc()
+    inst = I.with_long_row(I.config3(6), extra=40)
+    P = O.problem_from_instance(inst, conv=True)
+    lo = O.low_order_solution(P, inst.F, lin_rtol=1e-14)
+    ref, rst = O.stationary_mcl(P, inst.F, lo.x, tol=0.0, tol_mode="rel", maxit=5, lin_rtol=1e-14)
+    print("mcl long row prec=%d" % prec, flush=True)
+    o = dict(precision=prec, fp_tol=0.0, fp_tol_mode=1, lin_atol=0.0, lin_rtol=1e-14)
+    h = afc.afc_create_instance(inst, _opts(fp_maxit=0, **o), conv=True)
+    try:
+        u = _dev(np.zeros(inst.N))
+        F = _dev(inst.F)
+        afc.afc_solve_stationary(h, u, F, init_low_order=True)
+        assert _rel(u.cpu().numpy(), lo.x) <= (1e-10 if prec == 0 else 1e-8)
+        afc.afc_set_options(h, _opts(fp_maxit=5, **o))
+        st, stats = afc.afc_solve_stationary(h, u, F, raise_on_error=False)
+        assert st >= 0 and stats["fp_iters"] == 5, stats
+        assert _rel(u.cpu().numpy(), ref) <= (1e-10 if prec == 0 else 1e-8)
+    finally:
+        afc.afc_destroy(h)
+
+
 @pytest.mark.parametrize("sstep", [0, 8])
 def test_kernel_work_accounting(sstep):
     """Profiled launches: SpMV launches with work = Krylov iterations plus, per

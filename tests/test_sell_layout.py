@@ -89,6 +89,13 @@ def test_renumbered_falls_back_to_lane_offsets():
     assert info["lane_delta_slots"] > 0
 
 
+def test_long_row_layout():
+    # one row of 67 entries: its slice pads every lane to 67 slots
+    inst = I.with_long_row(I.config3(6), extra=40)
+    info = _check_layout(inst.row_ptr, inst.col)
+    assert info["slots"] >= 64 * 67
+
+
 def test_ragged_rows_empty_rows_and_tiny_sizes():
     rng = np.random.default_rng(3)
     for N in (1, 63, 64, 65, 200):
