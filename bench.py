@@ -641,6 +641,7 @@ def main():
     # --- plain FP64 GMRES for comparison (secondary) ------------------------
     fp64 = None
     if args.fp64_steps > 0:
+        u_start = u.clone()
         o = opts(fp_maxit=args.fp64_steps)
         o.precision = afc.AFC_PREC_FP64
         afc.afc_set_options(h, o)
@@ -649,8 +650,15 @@ def main():
         _, s3 = afc.afc_solve_stationary(h, u, F)
         torch.cuda.synchronize()
         e3 = time.perf_counter() - t0
+        # the same steps from the same state with the mixed-precision solve:
+        # relative L2 distance of the two iterates
+        u_mixed = u_start.clone()
+        afc.afc_set_options(h, opts(fp_maxit=args.fp64_steps))
+        afc.afc_solve_stationary(h, u_mixed, F)
+        diff = float(torch.linalg.vector_norm(u_mixed - u) / torch.linalg.vector_norm(u))
         fp64 = {"value": N * s3["fp_iters"] / e3, "ms_per_step": 1e3 * e3 / max(1, s3["fp_iters"]),
-                "krylov_per_step": s3["krylov_iters"] / max(1, s3["fp_iters"]), "steps": s3["fp_iters"]}
+                "krylov_per_step": s3["krylov_iters"] / max(1, s3["fp_iters"]), "steps": s3["fp_iters"],
+                "mixed_vs_fp64_rel_l2": diff}
     # --- the MU limiter (Sec. 3.2) on the same problem (secondary) ----------
     mu = None
     if args.mu_steps > 0:
