@@ -42,30 +42,33 @@ def kernel_source_hash():
 
 
 def spmv32_bytes(N, info):
-    """Algorithmic bytes of one FP32 SELL-64 SpMV: the FP32 value of every
-    slot, the per-row column offsets of non-uniform slices, the shared offset
-    patterns, two 32-bit slice headers per slice, one read of x, one write of y."""
+    """Algorithmic bytes of one FP32 SELL-64 SpMV (`info`: the Krylov layout,
+    the pattern without its diagonal): the FP32 value of every slot, the
+    per-row column offsets of non-uniform slices, the shared offset patterns,
+    two 32-bit slice headers per slice, one read of x, one write of y."""
     return (4 * info["slots"] + info["delta_bytes"] * info["lane_delta_slots"] + 4 * info["pattern_ints"]
             + 4 * (info["slices"] + 1) + 4 * info["slices"] + 4 * N + 4 * N)
 
 
-def step_model_bytes(N, nnz, info, krylov, sweeps, steps, sstep=0):
+def step_model_bytes(N, info, kinfo, krylov, sweeps, steps, sstep=0):
     """Algorithmic HBM bytes of `steps` fixed-point iterations (model: every
-    cycle of equal length, Arnoldi index k uniform over the cycle).  With
-    s-step blocks the projections and the update read the old basis once per
-    block of `sstep` vectors."""
+    cycle of equal length, Arnoldi index k uniform over the cycle).  `info`:
+    the system layout (FP64 residual, MCL passes), `kinfo`: the FP32 Krylov
+    layout.  With s-step blocks the projections and the update read the old
+    basis once per block of `sstep` vectors."""
     L = krylov / max(sweeps, 1)  # mean FP32 GMRES cycle length
     kbar = (L - 1) / 2.0         # mean Arnoldi index inside a cycle
     if sstep > 0:
         kb = max(0.0, (L - sstep) / 2.0)  # mean block start
-        per_it = spmv32_bytes(N, info) + ((kb + 1) / sstep + 1) * 4 * N + ((kb + 1) / sstep + 2) * 4 * N
+        per_it = spmv32_bytes(N, kinfo) + ((kb + 1) / sstep + 1) * 4 * N + ((kb + 1) / sstep + 2) * 4 * N
     else:
         # SpMV, projections (V[0..k] and W) and the update
-        per_it = spmv32_bytes(N, info) + (kbar + 2) * 4 * N + (kbar + 3) * 4 * N
-    residual = (8 * info["slots"] + info["delta_bytes"] * info["lane_delta_slots"] + 4 * info["pattern_ints"]
-                + 8 * info["slices"] + 4 + 24 * N)
+        per_it = spmv32_bytes(N, kinfo) + (kbar + 2) * 4 * N + (kbar + 3) * 4 * N
+    index = info["delta_bytes"] * info["lane_delta_slots"] + 4 * info["pattern_ints"] + 8 * info["slices"] + 4
+    residual = 8 * info["slots"] + index + 24 * N
     per_sweep = residual + kbar * 4 * N + 16 * N + 12 * N
-    per_fp = (4 * nnz + 4 * (N + 1) + 24 * N) + (28 * nnz + 4 * (N + 1) + 57 * N)
+    # MCL bounds (slot masks, u, u^max, u^min) and flux pass (A_low, c_ij, c_ji slots + node vectors)
+    per_fp = (index + 4 * N + 24 * N) + (index + 24 * info["slots"] + 4 * N + 57 * N)
     return krylov * per_it + sweeps * per_sweep + steps * per_fp
 
 
@@ -561,6 +564,7 @@ def main():
 
     h = afc.afc_create_instance(inst, opts(fp_maxit=0), conv=True)
     info = afc.afc_get_sell_info(h)
+    kinfo = afc.afc_get_krylov_sell_info(h)
     u = torch.zeros(N, dtype=torch.float64, device=dev)
     F = torch.tensor(inst.F, device=dev)
     afc.afc_solve_stationary(h, u, F, init_low_order=True)  # low-order start, not timed
@@ -579,7 +583,7 @@ def main():
     assert s["fp_iters"] == args.steps, s
     value = N * args.steps / elapsed
     ms_per_step = 1e3 * elapsed / args.steps
-    model_bytes = step_model_bytes(N, nnz, info, s["krylov_iters"], s["refine_sweeps"], args.steps, args.sstep)
+    model_bytes = step_model_bytes(N, info, kinfo, s["krylov_iters"], s["refine_sweeps"], args.steps, args.sstep)
     print("bench: %.1f ms/step, %d Krylov its" % (ms_per_step, s["krylov_iters"]), file=sys.stderr, flush=True)
 
     # --- the same steps again with per-kernel HIP events (roofline) ----------
@@ -617,7 +621,7 @@ def main():
             traffic_alg = tr.get("algorithmic_bytes_per_launch")
     roofline = {
         "kernel": "k_sell_spmv32 (FP32 SELL-64 SpMV, GMRES inner)",
-        "sell": info,
+        "sell": kinfo,
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
         "traffic_probe_algorithmic": traffic_alg,

@@ -269,6 +269,13 @@ typedef struct {
 /* Fill *out for handle h.  Returns EINVAL if h or out is NULL. */
 afc_status afc_get_sell_info(const afc_handle *h, afc_sell_info *out);
 
+/* The same for the FP32 Jacobi-scaled Krylov matrices of the mixed-precision
+ * solve (GMRES inner iterations, Sec. 4): their layout holds the system
+ * pattern without its diagonal, because every scaled diagonal entry is 1 and
+ * the SpMV applies it as x_i.  Equal to afc_sell_layout of the pattern with
+ * the diagonal entries removed.  Returns EINVAL if h or out is NULL. */
+afc_status afc_get_krylov_sell_info(const afc_handle *h, afc_sell_info *out);
+
 /* The same SELL-64 layout computed on the host for an n-row CSR pattern
  * (row_ptr[n + 1], col[row_ptr[n]], 0-based, host memory); needs no GPU.
  * Fills *info; each array pointer may be NULL (call once with NULLs to learn

@@ -72,7 +72,7 @@ EXPORTS = [
     "afc_solve_stationary", "afc_destroy", "afc_status_str", "afc_last_error", "afc_kernel_time",
     "afc_batch_create", "afc_batch_offsets", "afc_batch_step_cn", "afc_batch_last_error", "afc_batch_destroy",
     "afc_footprint_bytes", "afc_server_create", "afc_server_submit", "afc_server_wait", "afc_server_last_error",
-    "afc_server_destroy", "afc_get_sell_info", "afc_sell_layout", "afc_kernel_work",
+    "afc_server_destroy", "afc_get_sell_info", "afc_get_krylov_sell_info", "afc_sell_layout", "afc_kernel_work",
     "afc_batch_set_schedule", "afc_batch_get_schedule", "afc_batch_autotune", "afc_step_cn_linear",
     "afc_step_mc_ssprk3", "afc_step_mc_cn",
 ]
@@ -116,6 +116,8 @@ def lib():
         L.afc_kernel_work.restype = c_int32
         L.afc_get_sell_info.argtypes = [c_void_p, POINTER(afc_sell_info)]
         L.afc_get_sell_info.restype = c_int32
+        L.afc_get_krylov_sell_info.argtypes = [c_void_p, POINTER(afc_sell_info)]
+        L.afc_get_krylov_sell_info.restype = c_int32
         L.afc_sell_layout.argtypes = [c_int32, c_void_p, c_void_p, POINTER(afc_sell_info)] + [c_void_p] * 5
         L.afc_sell_layout.restype = c_int32
         L.afc_batch_create.argtypes = [c_int32, POINTER(afc_problem), POINTER(afc_options), POINTER(c_void_p)]
@@ -333,6 +335,16 @@ def afc_get_sell_info(h):
     st = lib().afc_get_sell_info(h, ctypes.byref(info))
     if st != AFC_OK:
         raise AFCError(st, "afc_get_sell_info")
+    return {name: getattr(info, name) for name, _ in afc_sell_info._fields_ if name != "reserved"}
+
+
+def afc_get_krylov_sell_info(h):
+    """Sizes of the SELL-64 storage of the handle's FP32 Krylov matrices (the
+    pattern without its diagonal), as a dict."""
+    info = afc_sell_info()
+    st = lib().afc_get_krylov_sell_info(h, ctypes.byref(info))
+    if st != AFC_OK:
+        raise AFCError(st, "afc_get_krylov_sell_info")
     return {name: getattr(info, name) for name, _ in afc_sell_info._fields_ if name != "reserved"}
 
 

@@ -125,6 +125,7 @@ void free_all(afc_handle* h) {
   f(h->cc); f(h->ccT); f(h->AL_mcl); f(h->dinv_mcl);
   f(h->A_cn); f(h->dinv_cn);
   f(h->sl_ptr); f(h->sl_dl); f(h->sl_pat); f(h->sl_dlt); f(h->sell_pos); f(h->sl_mask); f(h->Scc); f(h->SccT); f(h->S64_mcl); f(h->S32_mcl); f(h->S64_cn); f(h->S32_cn);
+  f(h->ks_ptr); f(h->ks_dl); f(h->ks_pat); f(h->ks_dlt); f(h->kpos);
   for (auto*& p : h->w) f(p);
   h->w.clear();
   f(h->V64); f(h->V32);
@@ -843,15 +844,52 @@ afc_status afc_create(const afc_problem* p, const afc_options* opt, afc_handle**
       else
         h->sl_dlt = upload(h, L.d32, h->stream);
       h->S64_mcl = dalloc<double>(h, slots);
-      h->S32_mcl = dalloc<float>(h, slots);
       h->S64_cn = dalloc<double>(h, slots);
-      h->S32_cn = dalloc<float>(h, slots);
       // zero the padding slots in stream order before the conversion kernels
       HIP_OK(hipMemsetAsync(h->S64_mcl, 0, slots * sizeof(double), h->stream));
-      HIP_OK(hipMemsetAsync(h->S32_mcl, 0, slots * sizeof(float), h->stream));
       HIP_OK(hipMemsetAsync(h->S64_cn, 0, slots * sizeof(double), h->stream));
-      HIP_OK(hipMemsetAsync(h->S32_cn, 0, slots * sizeof(float), h->stream));
       afc::to_sell64(h, h->AL_mcl, h->S64_mcl);
+      // FP32 Krylov layout: the pattern without its diagonal (every row stores
+      // one, checked above)
+      {
+        std::vector<int> rpo(N + 1, 0), colo, kmap(nnz, -1);
+        colo.reserve((size_t)(nnz - N));
+        for (int i = 0; i < N; ++i) {
+          for (int k = rp[i]; k < rp[i + 1]; ++k)
+            if (col[k] != i) {
+              kmap[k] = (int)colo.size();
+              colo.push_back(col[k]);
+            }
+          rpo[i + 1] = (int)colo.size();
+        }
+        afc::SellLayout Lk;
+        const std::string e2 = afc::build_sell_layout(N, rpo.data(), colo.data(), Lk);
+        if (!e2.empty()) fail(h, AFC_EINVAL, e2.c_str());
+        std::vector<int> kpos(nnz, -1);
+        for (int64_t k = 0; k < nnz; ++k)
+          if (kmap[k] >= 0) kpos[k] = Lk.pos[kmap[k]];
+        const size_t kslots = (size_t)Lk.slp.back();
+        h->ks_slots = (int64_t)kslots;
+        h->ks_uniform = Lk.uniform;
+        h->ks_lane_deltas = (int64_t)(Lk.dlt16 ? Lk.d16.size() : Lk.d32.size());
+        h->ks_pat_ints = (int64_t)Lk.pat.size();
+        h->ks_dlt16 = Lk.dlt16;
+        if (Lk.pat.empty()) Lk.pat.push_back(0);
+        if (Lk.d16.empty()) Lk.d16.push_back(0);
+        if (Lk.d32.empty()) Lk.d32.push_back(0);
+        h->ks_ptr = upload(h, Lk.slp, h->stream);
+        h->ks_dl = upload(h, Lk.dl, h->stream);
+        h->ks_pat = upload(h, Lk.pat, h->stream);
+        h->kpos = upload(h, kpos, h->stream);
+        if (h->ks_dlt16)
+          h->ks_dlt = upload(h, Lk.d16, h->stream);
+        else
+          h->ks_dlt = upload(h, Lk.d32, h->stream);
+        h->S32_mcl = dalloc<float>(h, std::max<size_t>(kslots, 1));
+        h->S32_cn = dalloc<float>(h, std::max<size_t>(kslots, 1));
+        HIP_OK(hipMemsetAsync(h->S32_mcl, 0, std::max<size_t>(kslots, 1) * sizeof(float), h->stream));
+        HIP_OK(hipMemsetAsync(h->S32_cn, 0, std::max<size_t>(kslots, 1) * sizeof(float), h->stream));
+      }
       afc::to_sell32_scaled(h, h->AL_mcl, h->dinv_mcl, h->S32_mcl);
       // MCL bounds and fluxes over the SELL rows: masks of the stored slots and
       // c_ij, c_ji in slot order
@@ -916,6 +954,18 @@ afc_status afc_kernel_work(afc_handle* h, int32_t kernel, double* bytes, int64_t
   if (!h || kernel < 0 || kernel >= AFC_KERNEL_COUNT) return AFC_EINVAL;
   if (bytes) *bytes = h->prof_bytes[kernel];
   if (launches_with_work) *launches_with_work = h->prof_work[kernel];
+  return AFC_OK;
+}
+
+afc_status afc_get_krylov_sell_info(const afc_handle* h, afc_sell_info* out) {
+  if (!h || !out) return AFC_EINVAL;
+  out->slices = h->nslices;
+  out->slots = h->ks_slots;
+  out->uniform_slices = h->ks_uniform;
+  out->lane_delta_slots = h->ks_lane_deltas;
+  out->pattern_ints = h->ks_pat_ints;
+  out->delta_bytes = h->ks_dlt16 ? 2 : 4;
+  out->reserved = 0;
   return AFC_OK;
 }
 

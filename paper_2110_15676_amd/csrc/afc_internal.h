@@ -108,10 +108,22 @@ struct afc_handle_s {
   bool dlt16 = true;
   int* sell_pos = nullptr;    // [nnz]
   double* S64_mcl = nullptr;  // A_low (MCL) in SELL order
-  float* S32_mcl = nullptr;   // A_low D^{-1} (MCL) in SELL order, FP32
   double* S64_cn = nullptr;
-  float* S32_cn = nullptr;
   int64_t sell_slots = 0;
+
+  // The FP32 Jacobi-scaled Krylov matrices A D^{-1} in a SELL-64 layout of
+  // their own: the same pattern without the diagonal, whose scaled value is 1
+  // (the SpMV applies it as x_i).  kpos maps each CSR entry to its slot, -1
+  // for the diagonal.
+  int* ks_ptr = nullptr;
+  int* ks_dl = nullptr;
+  int* ks_pat = nullptr;
+  void* ks_dlt = nullptr;
+  bool ks_dlt16 = true;
+  int* kpos = nullptr;        // [nnz]
+  int64_t ks_slots = 0, ks_uniform = 0, ks_lane_deltas = 0, ks_pat_ints = 0;
+  float* S32_mcl = nullptr;   // A_low D^{-1} (MCL), off-diagonal slots, FP32
+  float* S32_cn = nullptr;
 
   // CN system M_L/dt + A_low/2 (built for the last dt used)
   double cn_dt = 0.0;

@@ -314,10 +314,11 @@ __device__ __forceinline__ TA sell_row(const SellView& S, const TI* __restrict__
 }
 
 // FP32: y = A x (Jacobi-scaled FP32 matrix, unscaled basis vector)
-// y = A x - theta x (theta != 0: the shifted powers of s-step GMRES).
-// rev = 1 sweeps every XCD's slab backwards: back-to-back SpMVs that
-// alternate direction start on the matrix tiles the previous one read last,
-// which the memory-side cache still holds.
+// y = A x - theta x (theta != 0: the shifted powers of s-step GMRES), A the
+// Jacobi-scaled matrix stored without its diagonal (all ones): the diagonal
+// term is (1 - theta) x_i.  rev = 1 sweeps every XCD's slab backwards:
+// back-to-back SpMVs that alternate direction start on the matrix tiles the
+// previous one read last, which the memory-side cache still holds.
 template <typename TI>
 __global__ __launch_bounds__(kBlock) void k_sell_spmv32(SellView S, const TI* __restrict__ dlt,
                                                         const float* __restrict__ val, const float* __restrict__ x,
@@ -337,7 +338,7 @@ __global__ __launch_bounds__(kBlock) void k_sell_spmv32(SellView S, const TI* __
     const int i = s * 64 + (threadIdx.x & 63);
     if (i >= S.N) continue;
     float acc = sell_row<8>(S, dlt, val, s, i, [&](int j) { return x[j]; });
-    if (theta != 0.0f) acc -= theta * x[i];
+    if (theta != 1.0f) acc += (1.0f - theta) * x[i];
     y[i] = acc;
   }
 }
@@ -396,7 +397,7 @@ __global__ __launch_bounds__(kBlock) void k_to_sell_scaled32(int nnz, const int*
                                                              const double* __restrict__ dinv,
                                                              float* __restrict__ dst) {
   for (int k = blockIdx.x * kBlock + threadIdx.x; k < nnz; k += gridDim.x * kBlock)
-    dst[pos[k]] = (float)(src[k] * dinv[col[k]]);
+    if (pos[k] >= 0) dst[pos[k]] = (float)(src[k] * dinv[col[k]]);
 }
 
 // ---------------------------------------------------------------------------
@@ -2119,6 +2120,12 @@ double sell_matrix_bytes(const H* h, int value_bytes) {
   return (double)value_bytes * (double)h->sell_slots + (h->dlt16 ? 2.0 : 4.0) * (double)h->sell_lane_deltas +
          4.0 * (double)h->sell_pat_ints + 8.0 * (double)h->nslices + 4.0;
 }
+
+// the FP32 Krylov matrix (off-diagonal layout)
+double krylov_matrix_bytes(const H* h) {
+  return 4.0 * (double)h->ks_slots + (h->ks_dlt16 ? 2.0 : 4.0) * (double)h->ks_lane_deltas +
+         4.0 * (double)h->ks_pat_ints + 8.0 * (double)h->nslices + 4.0;
+}
 }  // namespace
 
 void prof_release(afc_handle_s* h) {
@@ -2196,7 +2203,7 @@ void to_sell64(H* h, const double* csr, double* sell) {
 }
 
 void to_sell32_scaled(H* h, const double* csr, const double* dinv, float* sell) {
-  k_to_sell_scaled32<<<vec_grid(h), kBlock, 0, h->stream>>>((int)h->nnz, h->sell_pos, h->col, csr, dinv, sell);
+  k_to_sell_scaled32<<<vec_grid(h), kBlock, 0, h->stream>>>((int)h->nnz, h->kpos, h->col, csr, dinv, sell);
 }
 
 void cycle_start(H* h, int mode, int red_idx, double tol_abs, double tol_rel) {
@@ -2220,12 +2227,13 @@ void gmres_spmv64(H* h, const double* A, const double* dinv, int k) {
 }
 
 void spmv32(H* h, const float* A32, const float* x, float theta, int rev, float* y) {
-  if (h->dlt16)
-    launch(h, AFC_KERNEL_SPMV32, k_sell_spmv32<int16_t>, sell_grid(h, false), kBlock, sell_view(h),
-           static_cast<const int16_t*>(h->sl_dlt), A32, x, (const KState*)h->ks, theta, rev, y);
+  const SellView S{h->N, h->nslices, h->ks_ptr, h->ks_dl, h->ks_pat};
+  if (h->ks_dlt16)
+    launch(h, AFC_KERNEL_SPMV32, k_sell_spmv32<int16_t>, sell_grid(h, false), kBlock, S,
+           static_cast<const int16_t*>(h->ks_dlt), A32, x, (const KState*)h->ks, theta, rev, y);
   else
-    launch(h, AFC_KERNEL_SPMV32, k_sell_spmv32<int32_t>, sell_grid(h, false), kBlock, sell_view(h),
-           static_cast<const int32_t*>(h->sl_dlt), A32, x, (const KState*)h->ks, theta, rev, y);
+    launch(h, AFC_KERNEL_SPMV32, k_sell_spmv32<int32_t>, sell_grid(h, false), kBlock, S,
+           static_cast<const int32_t*>(h->ks_dlt), A32, x, (const KState*)h->ks, theta, rev, y);
 }
 
 void gmres_spmv32(H* h, const float* A32, int k) {
@@ -2438,7 +2446,7 @@ void prof_gmres_cycle(afc_handle_s* h, bool fp32, int m, int kk) {
   const int nspmv = std::min(kk + 1, m);
   for (int k = 0; k < nspmv; ++k) {
     // matrix, x = V[k] (FP64: and the Jacobi scales), y
-    h->prof_bytes[kid] += sell_matrix_bytes(h, (int)vb) + vb * N * (fp32 ? 1.0 : 2.0) + vb * N;
+    h->prof_bytes[kid] += (fp32 ? krylov_matrix_bytes(h) : sell_matrix_bytes(h, 8)) + vb * N * (fp32 ? 1.0 : 2.0) + vb * N;
     h->prof_work[kid] += 1;
     // V[0..k], W, partials
     h->prof_bytes[AFC_KERNEL_DOTS] += vb * N * (k + 2) + 8.0 * nbv * (k + 1);
@@ -2460,7 +2468,7 @@ void prof_sstep_cycle(afc_handle_s* h, int m, int s, int kk) {
   for (int k = 0; k < m && k <= kk; k += s) {
     const int sb = std::min(s, m - k);
     // matrix, x = V[k+j] (its diagonal term feeds the shift too), y
-    h->prof_bytes[AFC_KERNEL_SPMV32] += sb * (sell_matrix_bytes(h, 4) + 2.0 * 4.0 * N);
+    h->prof_bytes[AFC_KERNEL_SPMV32] += sb * (krylov_matrix_bytes(h) + 2.0 * 4.0 * N);
     h->prof_work[AFC_KERNEL_SPMV32] += sb;
     h->prof_bytes[AFC_KERNEL_DOTS] += 4.0 * N * (k + 1 + sb) + 8.0 * nbv * ((k + 1) * sb + sb * (sb + 1) / 2);
     h->prof_work[AFC_KERNEL_DOTS] += 1;

@@ -331,11 +331,18 @@ def test_sell_info_matches_host_layout():
     h = afc.afc_create_instance(inst, _opts(), conv=True)
     try:
         info = afc.afc_get_sell_info(h)
+        kinfo = afc.afc_get_krylov_sell_info(h)
     finally:
         afc.afc_destroy(h)
     host = afc.afc_sell_layout(inst.row_ptr, inst.col)[0]
     assert info == host
     assert info["uniform_slices"] > info["slices"] // 2
+    # FP32 Krylov matrices: the same pattern without the diagonal
+    rows = inst.row_index()
+    off = inst.col != rows
+    rp = np.concatenate([[0], np.cumsum(np.bincount(rows[off], minlength=inst.N))]).astype(np.int32)
+    assert kinfo == afc.afc_sell_layout(rp, inst.col[off])[0]
+    assert kinfo["slots"] < info["slots"]
 
 
 @pytest.mark.parametrize("stages", [1, 2, 3])
@@ -523,6 +530,27 @@ def test_sstep_gmres_parity(sstep):
             afc.afc_destroy(h)
     print("krylov iterations", its, flush=True)
     assert its[sstep] <= 1.25 * its[0] + 8 * stats["fp_iters"]
+
+
+@pytest.mark.parametrize("n", [2, 3, 4])
+def test_sstep_tiny_and_ragged_sizes(n):
+    """s-step blocks of 8 on meshes of 27, 64 and 125 nodes (below one slice,
+    exactly one, a ragged second): Krylov spaces smaller than a block, the
+    Gram matrix of a block rank-deficient; the solution still matches the
+    oracle."""
+    afc = _afc()
+    inst = I.config3(n)
+    ref, rst = _mcl_ref(inst, 1e-12, 1e-14)
+    print("sstep tiny n=%d N=%d" % (n, inst.N), flush=True)
+    h = afc.afc_create_instance(inst, _opts(precision=1, sstep=8, fp_tol=1e-12, fp_tol_mode=1, fp_maxit=2000,
+                                            lin_atol=0.0, lin_rtol=1e-14), conv=True)
+    try:
+        u = _dev(np.zeros(inst.N))
+        st, stats = afc.afc_solve_stationary(h, u, _dev(inst.F), init_low_order=True)
+        assert st == 0, stats
+        assert _rel(u.cpu().numpy(), ref) <= 1e-8
+    finally:
+        afc.afc_destroy(h)
 
 
 def test_sstep_renumbered_and_graph_replay():
