@@ -45,7 +45,7 @@ struct Sched {
 };
 
 enum BatchWork { BW_UOLD = 0, BW_UT, BW_G, BW_QP, BW_QM, BW_RP, BW_RM, BW_B, BW_R, BW_X, BW_RHAT, BW_P, BW_V, BW_S,
-                 BW_T, BW_COUNT };
+                 BW_T, BW_PH, BW_SH, BW_COUNT };
 
 // Totals of NV sums accumulated per virtual wave (acc[c] belongs to virtual
 // wave w + c NW); every thread receives them.
@@ -102,9 +102,9 @@ __device__ __forceinline__ RowSpan row_span(const InstView& I, int i) {
   return {b + (i & 63), (I.slp[s + 1] - b) >> 6};
 }
 
-// y_i = sum_j A_ij dinv_j x_j; returns sum_i z_i y_i
+// y_i = sum_j A_ij xh_j with xh = D^{-1} x already formed; returns sum_i z_i y_i
 template <int NT>
-__device__ double wg_spmv_prec(const InstView& I, const double* A, const double* x, double* y, const double* z) {
+__device__ double wg_spmv_prec(const InstView& I, const double* A, const double* xh, double* y, const double* z) {
   double acc[Sched<NT>::PER][1] = {};
   AFC_ROWS(I, NT, c) {
     const RowSpan rs = row_span(I, i);
@@ -112,8 +112,7 @@ __device__ double wg_spmv_prec(const InstView& I, const double* A, const double*
 #pragma unroll 4
     for (int p = 0; p < rs.L; ++p) {
       const int k = rs.base + 64 * p;
-      const int j = i + I.dlt[k];
-      sacc += A[k] * (I.dinv[j] * x[j]);
+      sacc += A[k] * xh[i + I.dlt[k]];
     }
     y[i] = sacc;
     acc[c][0] += z[i] * sacc;
@@ -157,6 +156,8 @@ __device__ int wg_bicgstab(const InstView& I, const double* b, double* x, double
   double* v = I.w[BW_V];
   double* s = I.w[BW_S];
   double* t = I.w[BW_T];
+  double* ph = I.w[BW_PH];  // D^{-1} p and D^{-1} s, formed where p and s are
+  double* sh = I.w[BW_SH];
   const double* A = I.Acn;
   const int N = I.N;
   int it = 0, restarts = 0;
@@ -165,6 +166,7 @@ __device__ int wg_bicgstab(const InstView& I, const double* b, double* x, double
     for (int i = threadIdx.x; i < N; i += NT) {
       rhat[i] = r[i];
       p[i] = r[i];
+      ph[i] = I.dinv[i] * r[i];
       v[i] = 0.0;
     }
     __syncthreads();
@@ -177,7 +179,7 @@ __device__ int wg_bicgstab(const InstView& I, const double* b, double* x, double
       return it;
     }
     while (!converged && it < maxit) {
-      double q1[1] = {wg_spmv_prec<NT>(I, A, p, v, rhat)};
+      double q1[1] = {wg_spmv_prec<NT>(I, A, ph, v, rhat)};
       if (q1[0] == 0.0 || !isfinite(q1[0])) {
         breakdown = true;
         break;
@@ -187,6 +189,7 @@ __device__ int wg_bicgstab(const InstView& I, const double* b, double* x, double
       AFC_ROWS(I, NT, c) {
         const double si = r[i] - alpha * v[i];
         s[i] = si;
+        sh[i] = I.dinv[i] * si;
         a2[c][0] += si * si;
       }
       double q2[1];
@@ -194,7 +197,7 @@ __device__ int wg_bicgstab(const InstView& I, const double* b, double* x, double
       ++it;
       if (sqrt(q2[0]) <= tol) {
         for (int i = threadIdx.x; i < N; i += NT) {
-          x[i] += alpha * (I.dinv[i] * p[i]);
+          x[i] += alpha * ph[i];
           r[i] = s[i];
         }
         __syncthreads();
@@ -208,8 +211,7 @@ __device__ int wg_bicgstab(const InstView& I, const double* b, double* x, double
 #pragma unroll 4
         for (int pp = 0; pp < rs.L; ++pp) {
           const int k = rs.base + 64 * pp;
-          const int j = i + I.dlt[k];
-          a += A[k] * (I.dinv[j] * s[j]);
+          a += A[k] * sh[i + I.dlt[k]];
         }
         t[i] = a;
         a3[c][0] += a * s[i];
@@ -220,8 +222,7 @@ __device__ int wg_bicgstab(const InstView& I, const double* b, double* x, double
       omega = q3[1] != 0.0 ? q3[0] / q3[1] : 0.0;
       double a4[Sched<NT>::PER][2] = {};
       AFC_ROWS(I, NT, c) {
-        const double di = I.dinv[i];
-        x[i] += alpha * (di * p[i]) + omega * (di * s[i]);
+        x[i] += alpha * ph[i] + omega * sh[i];
         const double ri = s[i] - omega * t[i];
         r[i] = ri;
         a4[c][0] += rhat[i] * ri;
@@ -245,7 +246,11 @@ __device__ int wg_bicgstab(const InstView& I, const double* b, double* x, double
       }
       const double beta = (q4[0] / rho) * (alpha / omega);
       rho = q4[0];
-      for (int i = threadIdx.x; i < N; i += NT) p[i] = r[i] + beta * (p[i] - omega * v[i]);
+      for (int i = threadIdx.x; i < N; i += NT) {
+        const double pi = r[i] + beta * (p[i] - omega * v[i]);
+        p[i] = pi;
+        ph[i] = I.dinv[i] * pi;
+      }
       __syncthreads();
     }
     // confirm on the true residual
@@ -406,12 +411,12 @@ __device__ void run_instance(const BInst& in, const BatchDev& D, const BatchOpts
         for (int p = 1; p < rs.L; ++p) {
           const int k = rs.base + 64 * p;
           const int j = i + I.dlt[k];
-          const double uj = u[j];
+          const double uj = u[j], uoj = uo[j], rpj = Rp[j], rmj = Rm[j];  // every gather issued at once
           au += I.Acn[k] * uj;
           if (o.alpha_mode == AFC_ALPHA_ZERO) continue;
-          const double rf = cn_flux(I.mij[k], -I.dp[k], inv_dt, dui, uj - uo[j], sui, uj + uo[j], o.prelimit);
+          const double rf = cn_flux(I.mij[k], -I.dp[k], inv_dt, dui, uj - uoj, sui, uj + uoj, o.prelimit);
           double a = 1.0;
-          if (o.alpha_mode == AFC_ALPHA_LIMITED) a = rf > 0.0 ? fmin(rpi, Rm[j]) : fmin(rmi, Rp[j]);
+          if (o.alpha_mode == AFC_ALPHA_LIMITED) a = rf > 0.0 ? fmin(rpi, rmj) : fmin(rmi, rpj);
           fs += a * rf;
         }
         const double bi = g[i] + fs, ri = bi - au;
