@@ -281,7 +281,10 @@ SolveOut solve_gmres(afc_handle* h, const SysMat& S, const double* b, double* x,
   // Gershgorin discs of the Jacobi-scaled matrix)
   const int s = mixed ? h->opt.sstep : 0;
   const double theta = h->opt.sstep_shift;
+  // The last block is not orthogonalized in place: no later step reads its
+  // vectors, and the x update takes them raw with their coefficients.
   auto cycle_sstep = [&]() {
+    int kb = 0, sbl = 0;
     for (int k = 0; k < m; k += s) {
       const int sb = std::min(s, m - k);
       for (int j = 1; j <= sb; ++j)  // alternating sweep directions (cache reuse between the SpMVs)
@@ -289,10 +292,12 @@ SolveOut solve_gmres(afc_handle* h, const SysMat& S, const double* b, double* x,
                     h->V32 + (size_t)(k + j) * h->ldv);
       afc::sstep_dots(h, k, sb);
       afc::sstep_reduce(h, k, sb, m, theta);
-      afc::sstep_update(h, k, sb);
+      if (k + sb < m) afc::sstep_update(h, k, sb);
+      kb = k;
+      sbl = sb;
     }
     afc::gmres_solve(h, m);
-    afc::gmres_xupdate(h, true, S.dinv, x);
+    afc::sstep_xupdate(h, kb, sbl, S.dinv, x);
     afc::residual(h, S.S64, b, x, r, 2);
     afc::cast_v0(h, r);
   };

@@ -53,6 +53,8 @@ void sstep_reduce(H* h, int k, int s, int m, double theta);
 void sstep_update(H* h, int k, int s);
 void gmres_solve(H* h, int m);
 void gmres_xupdate(H* h, bool fp32, const double* dinv, double* x);
+// end of an s-step cycle whose last block (start kb, sb vectors) was not orthogonalized in place
+void sstep_xupdate(H* h, int kb, int sb, const double* dinv, double* x);
 
 // --- BiCGStab (right Jacobi, FP64) ----------------------------------------------
 struct BicgVec { double *x, *r, *rhat, *p, *v, *s, *t; };

@@ -1065,6 +1065,65 @@ __global__ __launch_bounds__(64) void k_gmres_solve(KState* ks, int m) {
   for (int i = threadIdx.x; i < kk; i += 64) ks->coef[i] = g[i] * ks->sc[i];
 }
 
+// End of an s-step cycle whose last block starts at kb with sb vectors: the
+// block is left unorthogonalized (V[kb+1..kb+sb] hold the raw powers W), and
+// x += D^{-1} sum_{q < kk} y_q V_q is taken with the block's basis vectors
+// written out, Q = W R^{-1} - V_{0..kb} (C R^{-1}):
+//   x += D^{-1} (sum_{q <= kb} a_q V_q + sum_{i < sb} b_i W_i),
+//   a_q = y_q - sum_{j < J} y_{kb+1+j} (C R^{-1})_{qj},  b_i = sum_{i <= j < J} y_{kb+1+j} (R^{-1})_{ij},
+// J = kk - kb - 1 block vectors used by the solution (none: W is not read).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_sstep_xupdate(int N, int ldv, const T* __restrict__ V,
+                                                        const double* __restrict__ dinv, double* __restrict__ x,
+                                                        const KState* __restrict__ ks, int kb, int sb) {
+  if (ks->solved) return;
+  constexpr int VN = 16 / sizeof(T);
+  constexpr int CH = kBlock * VN;
+  constexpr int QU = 4;
+  __shared__ double a[kMaxRestart + 1 + kSMax];
+  const int kk = ks->k;
+  const int J = min(kk - kb - 1, sb);
+  const int nq = J > 0 ? kb + 1 : kk;  // basis vectors V_0.. with coefficients
+  const int nw = J > 0 ? sb : 0;       // raw block vectors with coefficients
+  for (int q = threadIdx.x; q < nq; q += kBlock) {
+    double v = ks->coef[q];
+    for (int j = 0; j < J; ++j) v -= ks->coef[kb + 1 + j] * ks->dco[q * sb + j];
+    a[q] = v;
+  }
+  for (int i = threadIdx.x; i < nw; i += kBlock) {
+    double v = 0.0;
+    for (int j = i; j < J; ++j) v += ks->coef[kb + 1 + j] * ks->rinv[i * sb + j];
+    a[nq + i] = v;
+  }
+  __syncthreads();
+  const int nt = nq + nw;  // V_0..V_{nq-1}, then V_{kb+1..kb+nw} (the raw W)
+  for (int base = blockIdx.x * CH; base < N; base += gridDim.x * CH) {
+    const int e = base + threadIdx.x * VN;
+    double acc[VN];
+#pragma unroll
+    for (int c = 0; c < VN; ++c) acc[c] = 0.0;
+    for (int t0 = 0; t0 < nt; t0 += QU) {
+      T v[QU][VN];
+#pragma unroll
+      for (int u = 0; u < QU; ++u) {
+        const int t = t0 + u;
+        if (t < nt) load16(V + (size_t)(t < nq ? t : kb + 1 + (t - nq)) * ldv, e, N, v[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < QU; ++u) {
+        if (t0 + u < nt) {
+          const double cq = a[t0 + u];
+#pragma unroll
+          for (int c = 0; c < VN; ++c) acc[c] += cq * (double)v[u][c];
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < VN; ++c)
+      if (e + c < N) x[e + c] += dinv[e + c] * acc[c];
+  }
+}
+
 // x += D^{-1} sum_q coef_q V[q]
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_gmres_xupdate(int N, int ldv, const T* __restrict__ V,
@@ -2290,6 +2349,11 @@ void sstep_update(H* h, int k, int s) {
 
 void gmres_solve(H* h, int m) { k_gmres_solve<<<1, 64, 0, h->stream>>>(h->ks, m); }
 
+void sstep_xupdate(H* h, int kb, int sb, const double* dinv, double* x) {
+  k_sstep_xupdate<float><<<vec16_grid(h, kBlock * 4), kBlock, 0, h->stream>>>(h->N, h->ldv, h->V32, dinv, x, h->ks,
+                                                                               kb, sb);
+}
+
 void gmres_xupdate(H* h, bool fp32, const double* dinv, double* x) {
   if (fp32)
     k_gmres_xupdate<float><<<vec16_grid(h, kBlock * 4), kBlock, 0, h->stream>>>(h->N, h->ldv, h->V32, dinv, x,
@@ -2472,8 +2536,10 @@ void prof_sstep_cycle(afc_handle_s* h, int m, int s, int kk) {
     h->prof_work[AFC_KERNEL_SPMV32] += sb;
     h->prof_bytes[AFC_KERNEL_DOTS] += 4.0 * N * (k + 1 + sb) + 8.0 * nbv * ((k + 1) * sb + sb * (sb + 1) / 2);
     h->prof_work[AFC_KERNEL_DOTS] += 1;
-    h->prof_bytes[AFC_KERNEL_UPDATE] += 4.0 * N * (k + 1 + 2 * sb);
-    h->prof_work[AFC_KERNEL_UPDATE] += 1;
+    if (k + sb < m) {  // the last block is not orthogonalized in place (sstep_xupdate reads it raw)
+      h->prof_bytes[AFC_KERNEL_UPDATE] += 4.0 * N * (k + 1 + 2 * sb);
+      h->prof_work[AFC_KERNEL_UPDATE] += 1;
+    }
     if (k + sb >= kk && kk < m) break;
   }
 }
