@@ -469,18 +469,20 @@ def test_mu_alpha_modes_and_renumbered(mode, name):
         afc.afc_destroy(h)
 
 
-def test_mcl_full_size_iteration_in_bench_configuration():
+@pytest.mark.parametrize("sstep", [8, 0])
+def test_mcl_full_size_iteration_in_bench_configuration(sstep):
     """Q1 128^3 (the stationary MCL workload) in the configuration bench.py
-    times (FP32 GMRES(30)-Jacobi inside FP64 refinement, 1e-10 ||b||): the
+    times (FP32 GMRES(30)-Jacobi in s-step blocks of 8 inside FP64
+    refinement, 1e-10 ||b||; and with one basis vector per step): the
     low-order start and one fixed-point iteration, checked with the oracle's
     FP64 operators at full size: the nonlinear residual the GPU reports, and
     the linear residual of the iterate against b = F + F*(u) assembled by the
     oracle from the GPU's own starting state."""
     afc = _afc()
     inst = I.config3(128)
-    print("full size: N=%d nnz=%d" % (inst.N, inst.nnz), flush=True)
+    print("full size: N=%d nnz=%d sstep=%d" % (inst.N, inst.nnz, sstep), flush=True)
     o = dict(precision=1, krylov=1, restart=30, fp_tol=0.0, fp_tol_mode=1, lin_atol=0.0, lin_rtol=1e-10,
-             lin_maxit=100000)
+             lin_maxit=100000, sstep=sstep)
     h = afc.afc_create_instance(inst, _opts(fp_maxit=0, **o), conv=True)
     try:
         u = _dev(np.zeros(inst.N))
