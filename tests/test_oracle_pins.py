@@ -656,6 +656,26 @@ def test_mu_row_coding_matches_edge_list_and_is_conservative(dirichlet):
         assert abs(P.row_sum(rstar).sum()) <= 1e-14 * np.abs(rstar).sum()
 
 
+def test_mu_ties_take_the_smaller_factor():
+    # b = 0 and a reaction term: a_ij = a_ji on every edge (both nodes own it) and
+    # the consistent mass makes the off-diagonal a_ij > 0, so d_ij > 0 and the
+    # fluxes are nonzero (Sec. 3.2 with reading: alpha_ij = min of the two nodes')
+    inst = I.build("P1", 3, 1e-4, I.affine_field([0.0, 0.0, 0.0]), 5.0, dirichlet="none")
+    P = O.problem_from_instance(inst, conv=False)
+    assert np.array_equal(P.a, P.a[P.tpos])
+    d = O.artificial_diffusion(P, P.a)
+    u = np.random.default_rng((0, 8)).standard_normal(inst.N)
+    rstar, alpha, Rp, Rm = O.mu_limited_fluxes(P, u, d, P.a)
+    np.testing.assert_allclose(P.row_sum(rstar), _mu_edge_list(P, u, d, P.a), rtol=1e-13, atol=1e-15)
+    i, j = P.rows, P.col
+    r = np.where(P.offd, d * (u[j] - u[i]), 0.0)
+    abar_i = np.where(r > 0, Rp[i], np.where(r < 0, Rm[i], 1.0))
+    abar_j = np.where(-r > 0, Rp[j], np.where(-r < 0, Rm[j], 1.0))
+    differ = P.offd & (abar_i != abar_j)
+    assert differ.sum() > 10  # the rule decides something here
+    np.testing.assert_array_equal(alpha[P.offd], np.minimum(abar_i, abar_j)[P.offd])
+
+
 @pytest.mark.parametrize("elem", ["P1", "Q1"])
 def test_stationary_mu_alpha_one_is_galerkin_zero_is_low_order(elem):
     # MU scheme: r* = r gives A u = F; r* = 0 gives (A + D) u = F with D from A (eq. (5))
