@@ -124,7 +124,7 @@ void free_all(afc_handle* h) {
   f(h->mij); f(h->dp_fct); f(h->AL_fct); f(h->mu_own);
   f(h->cc); f(h->ccT); f(h->AL_mcl); f(h->dinv_mcl);
   f(h->A_cn); f(h->dinv_cn);
-  f(h->sl_ptr); f(h->sl_dl); f(h->sl_pat); f(h->sl_dlt); f(h->sell_pos); f(h->sl_mask); f(h->Scc); f(h->SccT); f(h->S64_mcl); f(h->S32_mcl); f(h->S64_cn); f(h->S32_cn);
+  f(h->sl_ptr); f(h->sl_dl); f(h->sl_pat); f(h->sl_dlt); f(h->sell_pos); f(h->sl_mask); f(h->Scc); f(h->SccT); f(h->S_mij); f(h->S_dp); f(h->S_alf); f(h->S64_mcl); f(h->S32_mcl); f(h->S64_cn); f(h->S32_cn);
   f(h->ks_ptr); f(h->ks_dl); f(h->ks_pat); f(h->ks_dlt); f(h->kpos);
   for (auto*& p : h->w) f(p);
   h->w.clear();
@@ -1033,6 +1033,18 @@ afc_status afc_step_ssprk3(afc_handle* h, double* u, const double* F, double dt,
           stages[ns++] = {s1, a.u, 0.5, 0.5};
         } else {
           stages[ns++] = {a.u, s1, 0.0, 1.0};
+        }
+        if (!h->S_mij) {  // FCT coefficients in SELL slot order, on first use
+          const size_t slots = (size_t)h->sell_slots;
+          h->S_mij = dalloc<double>(h, slots);
+          h->S_dp = dalloc<double>(h, slots);
+          h->S_alf = dalloc<double>(h, slots);
+          HIP_OK(hipMemsetAsync(h->S_mij, 0, slots * sizeof(double), h->stream));
+          HIP_OK(hipMemsetAsync(h->S_dp, 0, slots * sizeof(double), h->stream));
+          HIP_OK(hipMemsetAsync(h->S_alf, 0, slots * sizeof(double), h->stream));
+          afc::to_sell64(h, h->mij, h->S_mij);
+          afc::to_sell64(h, h->dp_fct, h->S_dp);
+          afc::to_sell64(h, h->AL_fct, h->S_alf);
         }
         for (int s = 0; s < ns; ++s) {
           afc::ssp_lowrate(h, stages[s].in, a.F, a.dt, udot, ut);

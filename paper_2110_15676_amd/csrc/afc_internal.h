@@ -105,6 +105,9 @@ struct afc_handle_s {
   int mask_words = 1;           // 32-slot words per row
   double* Scc = nullptr;        // c_ij in SELL slot order (MCL)
   double* SccT = nullptr;       // c_ji in SELL slot order (MCL)
+  double* S_mij = nullptr;      // m_ij, d+_ij and A_low (FCT) in SELL slot order (SSP stages; built on first use)
+  double* S_dp = nullptr;
+  double* S_alf = nullptr;
   bool dlt16 = true;
   int* sell_pos = nullptr;    // [nnz]
   double* S64_mcl = nullptr;  // A_low (MCL) in SELL order

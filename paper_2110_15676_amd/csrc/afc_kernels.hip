@@ -1427,125 +1427,148 @@ __global__ __launch_bounds__(kBlock) void k_bicg_p(int N, const double* __restri
 // Zalesak FCT, explicit SSP stage (eqs. (18)-(21), limiter steps 1-4)
 // ---------------------------------------------------------------------------
 
-// udot = M_L^{-1} (F - A_low u) (0 on Dirichlet nodes), ut = u + dt udot (u_D)
-template <int G>
-__global__ __launch_bounds__(kBlock) void k_ssp_lowrate(int N, const int* __restrict__ rp,
-                                                        const int* __restrict__ col, const double* __restrict__ AL,
-                                                        const double* __restrict__ u, const double* __restrict__ F,
-                                                        const double* __restrict__ ml,
-                                                        const uint8_t* __restrict__ is_dir,
-                                                        const double* __restrict__ uD, double dt,
-                                                        double* __restrict__ udot, double* __restrict__ ut) {
-  constexpr int RPB = kBlock / G;
-  const int lane = threadIdx.x % G, sub = threadIdx.x / G;
+// Three passes per stage over the SELL-64 rows (one row per lane, values in
+// slot order, stored slots marked in `mask`; see the MCL passes below):
+//   lowrate  udot = M_L^{-1} (F - A_low u) (0 on Dirichlet nodes), ut = u + dt udot (u_D)
+//   limit_R  P+-, Q+- (from ut) and R+- of r_ij = m_ij (udot_i - udot_j) + d_ij (u_j - u_i)
+//   apply    F*_i = sum_j alpha_ij r_ij ; out = c0 * base + c1 * (ut + dt F* / m)
+__device__ __forceinline__ int sell_delta_any(const SellView& S, const void* dlt, bool d16, int doff, int p,
+                                              int lane) {
+  if (doff < 0) return S.pat[~doff + p];
+  return d16 ? (int)static_cast<const int16_t*>(dlt)[doff + 64 * p + lane]
+             : static_cast<const int*>(dlt)[doff + 64 * p + lane];
+}
+
+__global__ __launch_bounds__(kBlock) void k_ssp_lowrate_sell(SellView S, const void* __restrict__ dlt, int d16,
+                                                             const uint32_t* __restrict__ mask,
+                                                             const double* __restrict__ Sal,
+                                                             const double* __restrict__ u,
+                                                             const double* __restrict__ F,
+                                                             const double* __restrict__ ml,
+                                                             const uint8_t* __restrict__ is_dir,
+                                                             const double* __restrict__ uD, double dt,
+                                                             double* __restrict__ udot, double* __restrict__ ut) {
   int t0, t1;
-  tile_range((N + RPB - 1) / RPB, t0, t1);
+  tile_range((S.nsl + kBlock / 64 - 1) / (kBlock / 64), t0, t1);
   for (int t = t0; t < t1; ++t) {
-    const int i = t * RPB + sub;
-    if (i >= N) continue;
+    const int s = wave_slice(t);
+    if (s >= S.nsl) continue;
+    const int lane = threadIdx.x & 63;
+    const int i = s * 64 + lane;
+    if (i >= S.N) continue;
     if (is_dir[i]) {
-      if (lane == 0) {
-        udot[i] = 0.0;
-        ut[i] = uD[i];
-      }
+      udot[i] = 0.0;
+      ut[i] = uD[i];
       continue;
     }
+    const int base = S.sl_ptr[s];
+    const int L = (S.sl_ptr[s + 1] - base) >> 6;
+    const int doff = S.sl_dl[s];
+    uint32_t msk = 0u;
     double acc = 0.0;
-    const int e = rp[i + 1];
-    for (int k = rp[i] + lane; k < e; k += G) acc += AL[k] * u[col[k]];
-    acc = gsum<G>(acc);
-    if (lane == 0) {
-      const double ud = (F[i] - acc) / ml[i];
-      udot[i] = ud;
-      ut[i] = u[i] + dt * ud;
+#pragma unroll 4
+    for (int p = 0; p < L; ++p) {
+      if ((p & 31) == 0) msk = mask[(size_t)(p >> 5) * S.N + i];
+      if (!((msk >> (p & 31)) & 1u)) continue;
+      acc += Sal[(size_t)base + 64 * p + lane] * u[i + sell_delta_any(S, dlt, d16, doff, p, lane)];
     }
+    const double ud = (F[i] - acc) / ml[i];
+    udot[i] = ud;
+    ut[i] = u[i] + dt * ud;
   }
 }
 
-// P+-, Q+- (from ut) and R+- of the SSP fluxes r_ij = m_ij (udot_i - udot_j) + d_ij (u_j - u_i)
-template <int G>
-__global__ __launch_bounds__(kBlock) void k_ssp_limit_R(int N, const int* __restrict__ rp,
-                                                        const int* __restrict__ col,
-                                                        const double* __restrict__ mij,
-                                                        const double* __restrict__ dp, const double* __restrict__ u,
-                                                        const double* __restrict__ udot,
-                                                        const double* __restrict__ ut, const double* __restrict__ ml,
-                                                        const uint8_t* __restrict__ is_dir, double dt,
-                                                        double* __restrict__ Rp, double* __restrict__ Rm) {
-  constexpr int RPB = kBlock / G;
-  const int lane = threadIdx.x % G, sub = threadIdx.x / G;
+__global__ __launch_bounds__(kBlock) void k_ssp_limit_R_sell(SellView S, const void* __restrict__ dlt, int d16,
+                                                             const uint32_t* __restrict__ mask,
+                                                             const double* __restrict__ Smij,
+                                                             const double* __restrict__ Sdp,
+                                                             const double* __restrict__ u,
+                                                             const double* __restrict__ udot,
+                                                             const double* __restrict__ ut,
+                                                             const double* __restrict__ ml,
+                                                             const uint8_t* __restrict__ is_dir, double dt,
+                                                             double* __restrict__ Rp, double* __restrict__ Rm) {
   int t0, t1;
-  tile_range((N + RPB - 1) / RPB, t0, t1);
+  tile_range((S.nsl + kBlock / 64 - 1) / (kBlock / 64), t0, t1);
   for (int t = t0; t < t1; ++t) {
-    const int i = t * RPB + sub;
-    if (i >= N) continue;
+    const int s = wave_slice(t);
+    if (s >= S.nsl) continue;
+    const int lane = threadIdx.x & 63;
+    const int i = s * 64 + lane;
+    if (i >= S.N) continue;
     if (is_dir[i]) {
-      if (lane == 0) Rp[i] = Rm[i] = 1.0;
+      Rp[i] = Rm[i] = 1.0;
       continue;
     }
+    const int base = S.sl_ptr[s];
+    const int L = (S.sl_ptr[s + 1] - base) >> 6;
+    const int doff = S.sl_dl[s];
     const double ui = u[i], udi = udot[i], uti = ut[i];
+    uint32_t msk = 0u;
     double pp = 0.0, pm = 0.0, qp = 0.0, qm = 0.0;
-    const int e = rp[i + 1];
-    for (int k = rp[i] + lane; k < e; k += G) {
-      const int j = col[k];
-      if (j == i) continue;
-      const double d = -dp[k];
-      const double r = mij[k] * (udi - udot[j]) + d * (u[j] - ui);
+#pragma unroll 2
+    for (int p = 0; p < L; ++p) {
+      if ((p & 31) == 0) msk = mask[(size_t)(p >> 5) * S.N + i];
+      if (!((msk >> (p & 31)) & 1u)) continue;
+      const int dj = sell_delta_any(S, dlt, d16, doff, p, lane);
+      if (dj == 0) continue;
+      const int j = i + dj;
+      const size_t v = (size_t)base + 64 * p + lane;
+      const double r = Smij[v] * (udi - udot[j]) - Sdp[v] * (u[j] - ui);
       pp += fmax(r, 0.0);
       pm += fmin(r, 0.0);
       const double du = ut[j] - uti;
       qp = fmax(qp, du);
       qm = fmin(qm, du);
     }
-    pp = gsum<G>(pp);
-    pm = gsum<G>(pm);
-    qp = gmax<G>(qp);
-    qm = gmin<G>(qm);
-    if (lane == 0) {
-      Rp[i] = zalesak_R(ml[i], qp, pp, dt);
-      Rm[i] = zalesak_R(ml[i], qm, pm, dt);
-    }
+    Rp[i] = zalesak_R(ml[i], qp, pp, dt);
+    Rm[i] = zalesak_R(ml[i], qm, pm, dt);
   }
 }
 
-// F*_i = sum_j alpha_ij r_ij ; out = c0 * base + c1 * (ut + dt F* / m)
-template <int G>
-__global__ __launch_bounds__(kBlock) void k_ssp_apply(
-    int N, const int* __restrict__ rp, const int* __restrict__ col, const double* __restrict__ mij,
-    const double* __restrict__ dp, const double* __restrict__ u, const double* __restrict__ udot,
-    const double* __restrict__ ut, const double* __restrict__ Rp, const double* __restrict__ Rm,
-    const double* __restrict__ ml, const uint8_t* __restrict__ is_dir, const double* __restrict__ uD, double dt,
-    int alpha_mode, const double* __restrict__ base, double c0, double c1, double* __restrict__ out) {
-  constexpr int RPB = kBlock / G;
-  const int lane = threadIdx.x % G, sub = threadIdx.x / G;
+__global__ __launch_bounds__(kBlock) void k_ssp_apply_sell(
+    SellView S, const void* __restrict__ dlt, int d16, const uint32_t* __restrict__ mask,
+    const double* __restrict__ Smij, const double* __restrict__ Sdp, const double* __restrict__ u,
+    const double* __restrict__ udot, const double* __restrict__ ut, const double* __restrict__ Rp,
+    const double* __restrict__ Rm, const double* __restrict__ ml, const uint8_t* __restrict__ is_dir,
+    const double* __restrict__ uD, double dt, int alpha_mode, const double* __restrict__ base_v, double c0, double c1,
+    double* __restrict__ out) {
   int t0, t1;
-  tile_range((N + RPB - 1) / RPB, t0, t1);
+  tile_range((S.nsl + kBlock / 64 - 1) / (kBlock / 64), t0, t1);
   for (int t = t0; t < t1; ++t) {
-    const int i = t * RPB + sub;
-    if (i >= N) continue;
+    const int s = wave_slice(t);
+    if (s >= S.nsl) continue;
+    const int lane = threadIdx.x & 63;
+    const int i = s * 64 + lane;
+    if (i >= S.N) continue;
     if (is_dir[i]) {
-      if (lane == 0) out[i] = uD[i];
+      out[i] = uD[i];
       continue;
     }
     double fs = 0.0;
     if (alpha_mode != AFC_ALPHA_ZERO) {
+      const int base = S.sl_ptr[s];
+      const int L = (S.sl_ptr[s + 1] - base) >> 6;
+      const int doff = S.sl_dl[s];
       const double ui = u[i], udi = udot[i], rpi = Rp[i], rmi = Rm[i];
-      const int e = rp[i + 1];
-      for (int k = rp[i] + lane; k < e; k += G) {
-        const int j = col[k];
-        if (j == i) continue;
-        const double d = -dp[k];
-        const double r = mij[k] * (udi - udot[j]) + d * (u[j] - ui);
+      uint32_t msk = 0u;
+#pragma unroll 2
+      for (int p = 0; p < L; ++p) {
+        if ((p & 31) == 0) msk = mask[(size_t)(p >> 5) * S.N + i];
+        if (!((msk >> (p & 31)) & 1u)) continue;
+        const int dj = sell_delta_any(S, dlt, d16, doff, p, lane);
+        if (dj == 0) continue;
+        const int j = i + dj;
+        const size_t v = (size_t)base + 64 * p + lane;
+        const double uj = u[j], udj = udot[j], rpj = Rp[j], rmj = Rm[j];  // every gather issued at once
+        const double r = Smij[v] * (udi - udj) - Sdp[v] * (uj - ui);
         double a = 1.0;
-        if (alpha_mode == AFC_ALPHA_LIMITED) a = r > 0.0 ? fmin(rpi, Rm[j]) : fmin(rmi, Rp[j]);
+        if (alpha_mode == AFC_ALPHA_LIMITED) a = r > 0.0 ? fmin(rpi, rmj) : fmin(rmi, rpj);
         fs += a * r;
       }
-      fs = gsum<G>(fs);
     }
-    if (lane == 0) {
-      const double unew = ut[i] + dt * fs / ml[i];
-      out[i] = (c0 == 0.0) ? c1 * unew : c0 * base[i] + c1 * unew;
-    }
+    const double unew = ut[i] + dt * fs / ml[i];
+    out[i] = (c0 == 0.0) ? c1 * unew : c0 * base_v[i] + c1 * unew;
   }
 }
 
@@ -2395,8 +2418,9 @@ void mu_apply(H* h, const double* u, const double* Rp, const double* Rm, const d
 }
 
 void mc_lowrate(H* h, const double* u, const double* F, double* udot, double* scratch) {
-  AFC_DISPATCH_G(h, k_ssp_lowrate, row_grid(h, false), h->N, h->row_ptr, h->col, h->AL_mcl, u, F, h->ml, h->is_dir,
-                 h->uD, 0.0, udot, scratch);
+  k_ssp_lowrate_sell<<<sell_grid(h, false), kBlock, 0, h->stream>>>(sell_view(h), (const void*)h->sl_dlt, (int)h->dlt16,
+         (const uint32_t*)h->sl_mask, (const double*)h->S64_mcl, u, F, (const double*)h->ml,
+         (const uint8_t*)h->is_dir, (const double*)h->uD, 0.0, udot, scratch);
 }
 
 void mc_stage(H* h, const double* u, const double* udot, const double* umax, const double* umin, double dt,
@@ -2420,19 +2444,23 @@ void mc_cn_apply(H* h, const double* u, const double* udot, const double* umax, 
 }
 
 void ssp_lowrate(H* h, const double* u, const double* F, double dt, double* udot, double* ut) {
-  AFC_DISPATCH_G(h, k_ssp_lowrate, row_grid(h, false), h->N, h->row_ptr, h->col, h->AL_fct, u, F, h->ml, h->is_dir,
-                 h->uD, dt, udot, ut);
+  k_ssp_lowrate_sell<<<sell_grid(h, false), kBlock, 0, h->stream>>>(sell_view(h), (const void*)h->sl_dlt, (int)h->dlt16,
+         (const uint32_t*)h->sl_mask, (const double*)h->S_alf, u, F, (const double*)h->ml, (const uint8_t*)h->is_dir,
+         (const double*)h->uD, dt, udot, ut);
 }
 
 void ssp_limit_R(H* h, const double* u, const double* udot, const double* ut, double dt, double* Rp, double* Rm) {
-  AFC_DISPATCH_G(h, k_ssp_limit_R, row_grid(h, false), h->N, h->row_ptr, h->col, h->mij, h->dp_fct, u, udot, ut,
-                 h->ml, h->is_dir, dt, Rp, Rm);
+  k_ssp_limit_R_sell<<<sell_grid(h, false), kBlock, 0, h->stream>>>(sell_view(h), (const void*)h->sl_dlt, (int)h->dlt16,
+         (const uint32_t*)h->sl_mask, (const double*)h->S_mij, (const double*)h->S_dp, u, udot, ut,
+         (const double*)h->ml, (const uint8_t*)h->is_dir, dt, Rp, Rm);
 }
 
 void ssp_apply(H* h, const double* u, const double* udot, const double* ut, const double* Rp, const double* Rm,
                double dt, const double* base, double c0, double c1, double* out) {
-  AFC_DISPATCH_G(h, k_ssp_apply, row_grid(h, false), h->N, h->row_ptr, h->col, h->mij, h->dp_fct, u, udot, ut, Rp,
-                 Rm, h->ml, h->is_dir, h->uD, dt, h->opt.alpha_mode, base, c0, c1, out);
+  k_ssp_apply_sell<<<sell_grid(h, false), kBlock, 0, h->stream>>>(sell_view(h), (const void*)h->sl_dlt, (int)h->dlt16,
+         (const uint32_t*)h->sl_mask, (const double*)h->S_mij, (const double*)h->S_dp, u, udot, ut, Rp, Rm,
+         (const double*)h->ml, (const uint8_t*)h->is_dir, (const double*)h->uD, dt, h->opt.alpha_mode, base, c0, c1,
+         out);
 }
 
 void cn_predict(H* h, const double* u_old, const double* F_old, const double* F_new, double dt, double* ut,

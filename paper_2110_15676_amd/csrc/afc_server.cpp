@@ -25,6 +25,7 @@
 #include <vector>
 
 #include "../../include/afc.h"
+#include "afc_internal.h"
 
 namespace {
 
@@ -192,12 +193,19 @@ int64_t afc_footprint_bytes(int32_t n, int64_t nnz, int32_t kind, const afc_opti
   if (opt) o = *opt;
   const int64_t N = n, Z = nnz;
   const int64_t ldv = (N + 63) / 64 * 64;
-  // resident operators: col, 6 FP64 value arrays, SELL (deltas, map, 2 x FP64, 2 x FP32), CN values
-  int64_t b = Z * 4 + Z * 8 * 6 + Z * (2 + 4 + 8 + 8 + 4 + 4) + Z * 8;
+  // resident operators: col, 6 FP64 CSR value arrays and the CN values
+  int64_t b = Z * 4 + Z * 8 * 6 + Z * 8;
+  // SELL-64 system layout (slot map, offsets, A_low and CN values, c_ij and
+  // c_ji in slot order, slot masks) and the FP32 Krylov layout without the
+  // diagonal (slot map, offsets, two FP32 matrices); padding ~1 %
+  b += (Z * (4 + 4 + 8 + 8 + 8 + 8) + N * 8) * 101 / 100;
+  b += (Z * (4 + 4 + 4 + 4)) * 101 / 100;
   b += N * (4 + 8 * 4 + 1) + ldv * 8 * 18;  // row pointers, node vectors, work vectors
   const int64_t m = o.restart + 1;
   b += (o.precision == AFC_PREC_MIXED ? 4 : 8) * m * ldv;  // Krylov basis
+  b += 8 * (int64_t)(afc::kMaxRed + afc::kBlkRows) * afc::kRedBlocks + 8 * (N / 256 + 1);  // reduction partials
   b += N * 8 * 2;                                          // request u and F
+  b += 32 << 20;  // allocation granularity of ~60 device buffers, graphs and small state
   (void)kind;
   return b;
 }
