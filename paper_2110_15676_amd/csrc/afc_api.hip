@@ -152,6 +152,22 @@ void sync_status(afc_handle* h) {
   if (!h->ev_pending.empty()) afc::prof_collect(h);
 }
 
+// m_ij, d+_ij and A_low (FCT) in SELL slot order, for the explicit stages and
+// the MC passes over the SELL rows; built on first use
+void ensure_fct_sell(afc_handle* h) {
+  if (h->S_mij) return;
+  const size_t slots = (size_t)h->sell_slots;
+  h->S_mij = dalloc<double>(h, slots);
+  h->S_dp = dalloc<double>(h, slots);
+  h->S_alf = dalloc<double>(h, slots);
+  HIP_OK(hipMemsetAsync(h->S_mij, 0, slots * sizeof(double), h->stream));
+  HIP_OK(hipMemsetAsync(h->S_dp, 0, slots * sizeof(double), h->stream));
+  HIP_OK(hipMemsetAsync(h->S_alf, 0, slots * sizeof(double), h->stream));
+  afc::to_sell64(h, h->mij, h->S_mij);
+  afc::to_sell64(h, h->dp_fct, h->S_dp);
+  afc::to_sell64(h, h->AL_fct, h->S_alf);
+}
+
 void ensure_ring(afc_handle* h) {
   if (h->ring) return;
   HIP_OK(hipHostMalloc((void**)&h->ring, 2 * afc::kStatusBytes, hipHostMallocDefault));
@@ -1034,18 +1050,7 @@ afc_status afc_step_ssprk3(afc_handle* h, double* u, const double* F, double dt,
         } else {
           stages[ns++] = {a.u, s1, 0.0, 1.0};
         }
-        if (!h->S_mij) {  // FCT coefficients in SELL slot order, on first use
-          const size_t slots = (size_t)h->sell_slots;
-          h->S_mij = dalloc<double>(h, slots);
-          h->S_dp = dalloc<double>(h, slots);
-          h->S_alf = dalloc<double>(h, slots);
-          HIP_OK(hipMemsetAsync(h->S_mij, 0, slots * sizeof(double), h->stream));
-          HIP_OK(hipMemsetAsync(h->S_dp, 0, slots * sizeof(double), h->stream));
-          HIP_OK(hipMemsetAsync(h->S_alf, 0, slots * sizeof(double), h->stream));
-          afc::to_sell64(h, h->mij, h->S_mij);
-          afc::to_sell64(h, h->dp_fct, h->S_dp);
-          afc::to_sell64(h, h->AL_fct, h->S_alf);
-        }
+        ensure_fct_sell(h);
         for (int s = 0; s < ns; ++s) {
           afc::ssp_lowrate(h, stages[s].in, a.F, a.dt, udot, ut);
           afc::ssp_limit_R(h, stages[s].in, udot, ut, a.dt, Rp, Rm);
@@ -1198,6 +1203,7 @@ afc_status afc_step_mc_ssprk3(afc_handle* h, double* u, const double* F, double 
         } else {
           stages[ns++] = {a.u, s1, 0.0, 1.0};
         }
+        ensure_fct_sell(h);
         for (int s = 0; s < ns; ++s) {
           afc::mc_lowrate(h, stages[s].in, a.F, udot, scratch);
           afc::mcl_bounds(h, stages[s].in, umax, umin);
@@ -1225,6 +1231,7 @@ afc_status afc_step_mc_cn(afc_handle* h, double* u, const double* F_old, const d
       [](afc_handle* h, void* ctx) -> afc_status {
         const CnArgs& a = *static_cast<CnArgs*>(ctx);
         ensure_cn_matrix(h, h->AL_mcl, a.dt);
+        ensure_fct_sell(h);
         double* uo = h->w[W_UOLD];
         double* g = h->w[W_G];
         double* udot = h->w[W_S1];

@@ -1756,11 +1756,6 @@ __global__ __launch_bounds__(kBlock) void k_cn_apply(
 // nodes outside N_i, so they must not enter u^max / u^min or the fluxes.
 
 // u^max_i, u^min_i: extremes of u over N_i (i included)
-__device__ __forceinline__ int sell_delta(const SellView& S, const void* dlt, bool d16, int doff, int p, int lane) {
-  if (doff < 0) return S.pat[~doff + p];
-  return d16 ? (int)static_cast<const int16_t*>(dlt)[doff + 64 * p + lane]
-             : static_cast<const int*>(dlt)[doff + 64 * p + lane];
-}
 
 __global__ __launch_bounds__(kBlock) void k_mcl_bounds_sell(SellView S, const void* __restrict__ dlt, int d16,
                                                             const uint32_t* __restrict__ mask,
@@ -1781,7 +1776,7 @@ __global__ __launch_bounds__(kBlock) void k_mcl_bounds_sell(SellView S, const vo
 #pragma unroll 4
     for (int p = 0; p < L; ++p) {
       if ((p & 31) == 0) msk = mask[(size_t)(p >> 5) * S.N + i];
-      const int j = i + sell_delta(S, dlt, d16, doff, p, lane);
+      const int j = i + sell_delta_any(S, dlt, d16, doff, p, lane);
       if ((msk >> (p & 31)) & 1u) {
         const double uj = u[j];
         mx = fmax(mx, uj);
@@ -1830,7 +1825,7 @@ __global__ __launch_bounds__(kBlock) void k_mcl_apply_sell(
     for (int p = 0; p < L; ++p) {
       if ((p & 31) == 0) msk = mask[(size_t)(p >> 5) * S.N + i];
       if (!((msk >> (p & 31)) & 1u)) continue;
-      const int dj = sell_delta(S, dlt, d16, doff, p, lane);
+      const int dj = sell_delta_any(S, dlt, d16, doff, p, lane);
       const int j = i + dj;
       const size_t v = (size_t)base + 64 * p + lane;
       const double uj = u[j];
@@ -1872,24 +1867,37 @@ __global__ __launch_bounds__(kBlock) void k_mcl_apply_sell(
 // ---------------------------------------------------------------------------
 
 // this lane's share of F*_i = sum_j r*_ij (caller sums over the G lanes)
-template <int G>
-__device__ __forceinline__ double mc_row_fstar(int i, int lane, const int* __restrict__ rp,
-                                               const int* __restrict__ col, const double* __restrict__ mij,
-                                               const double* __restrict__ cc, const double* __restrict__ ccT,
-                                               const double* __restrict__ u, const double* __restrict__ udot,
-                                               const double* __restrict__ umax, const double* __restrict__ umin,
-                                               int alpha_mode) {
+struct McSell {
+  SellView S;
+  const void* dlt;
+  int d16;
+  const uint32_t* mask;
+  const double *Smij, *Scc, *SccT;
+};
+
+// F*_i = sum_j r*_ij over the SELL row of lane i in slice s (slot order)
+__device__ __forceinline__ double mc_row_fstar(const McSell& M, int s, int i, const double* __restrict__ u,
+                                               const double* __restrict__ udot, const double* __restrict__ umax,
+                                               const double* __restrict__ umin, int alpha_mode) {
   if (alpha_mode == AFC_ALPHA_ZERO) return 0.0;
+  const int lane = i & 63;
+  const int base = M.S.sl_ptr[s];
+  const int L = (M.S.sl_ptr[s + 1] - base) >> 6;
+  const int doff = M.S.sl_dl[s];
   const double ui = u[i], udi = udot[i], umaxi = umax[i], umini = umin[i];
+  uint32_t msk = 0u;
   double fs = 0.0;
-  const int e = rp[i + 1];
-  for (int k = rp[i] + lane; k < e; k += G) {
-    const int j = col[k];
-    if (j == i) continue;
-    const double uj = u[j];
-    const double c = cc[k], ct = ccT[k];
+  for (int p = 0; p < L; ++p) {
+    if ((p & 31) == 0) msk = M.mask[(size_t)(p >> 5) * M.S.N + i];
+    if (!((msk >> (p & 31)) & 1u)) continue;
+    const int dj = sell_delta_any(M.S, M.dlt, M.d16, doff, p, lane);
+    if (dj == 0) continue;
+    const int j = i + dj;
+    const size_t v = (size_t)base + 64 * p + lane;
+    const double uj = u[j], udj = udot[j], umaxj = umax[j], uminj = umin[j];  // gathers issued together
+    const double c = M.Scc[v], ct = M.SccT[v];
     const double d = -fmax(fmax(c, 0.0), ct);
-    const double rf = mij[k] * (udi - udot[j]) + d * (uj - ui);
+    const double rf = M.Smij[v] * (udi - udj) + d * (uj - ui);
     if (alpha_mode == AFC_ALPHA_ONE) {
       fs += rf;
       continue;
@@ -1899,110 +1907,101 @@ __device__ __forceinline__ double mc_row_fstar(int i, int lane, const int* __res
     const double sji = d * (ui + uj) + ct * (ui - uj);
     const double two_d = 2.0 * d;
     if (rf > 0.0)
-      fs += fmin(rf, fmin(sij - two_d * umaxi, two_d * umin[j] - sji));
+      fs += fmin(rf, fmin(sij - two_d * umaxi, two_d * uminj - sji));
     else
-      fs += fmax(rf, fmax(sij - two_d * umini, two_d * umax[j] - sji));
+      fs += fmax(rf, fmax(sij - two_d * umini, two_d * umaxj - sji));
   }
   return fs;
 }
 
+#define AFC_SELL_ROWS(S, s, i)                                                        \
+  int t0_, t1_;                                                                       \
+  tile_range(((S).nsl + kBlock / 64 - 1) / (kBlock / 64), t0_, t1_);                  \
+  for (int t_ = t0_; t_ < t1_; ++t_)                                                  \
+    if (const int s = wave_slice(t_); s < (S).nsl)                                    \
+      if (const int i = s * 64 + (int)(threadIdx.x & 63); i < (S).N)
+
 // MC forward-Euler stage of eq. (18): out = c0 u0 + c1 (u + dt (udot + F*/m)),
 // u_D at Dirichlet nodes (udot from the MC low-order operator)
-template <int G>
-__global__ __launch_bounds__(kBlock) void k_mc_stage(
-    int N, const int* __restrict__ rp, const int* __restrict__ col, const double* __restrict__ mij,
-    const double* __restrict__ cc, const double* __restrict__ ccT, const double* __restrict__ ml,
-    const uint8_t* __restrict__ is_dir, const double* __restrict__ uD, const double* __restrict__ u,
-    const double* __restrict__ udot, const double* __restrict__ umax, const double* __restrict__ umin, double dt,
-    const double* __restrict__ u0, double c0, double c1, int alpha_mode, double* __restrict__ out) {
-  constexpr int RPB = kBlock / G;
-  const int lane = threadIdx.x % G, sub = threadIdx.x / G;
-  int t0, t1;
-  tile_range((N + RPB - 1) / RPB, t0, t1);
-  for (int t = t0; t < t1; ++t) {
-    const int i = t * RPB + sub;
-    if (i >= N) continue;
+__global__ __launch_bounds__(kBlock) void k_mc_stage(McSell M, const double* __restrict__ ml,
+                                                     const uint8_t* __restrict__ is_dir,
+                                                     const double* __restrict__ uD, const double* __restrict__ u,
+                                                     const double* __restrict__ udot,
+                                                     const double* __restrict__ umax,
+                                                     const double* __restrict__ umin, double dt,
+                                                     const double* __restrict__ u0, double c0, double c1,
+                                                     int alpha_mode, double* __restrict__ out) {
+  AFC_SELL_ROWS(M.S, s, i) {
     if (is_dir[i]) {
-      if (lane == 0) out[i] = c0 * u0[i] + c1 * uD[i];
+      out[i] = c0 * u0[i] + c1 * uD[i];
       continue;
     }
-    double fs = mc_row_fstar<G>(i, lane, rp, col, mij, cc, ccT, u, udot, umax, umin, alpha_mode);
-    fs = gsum<G>(fs);
-    if (lane == 0) out[i] = c0 * u0[i] + c1 * (u[i] + dt * (udot[i] + fs / ml[i]));
+    const double fs = mc_row_fstar(M, s, i, u, udot, umax, umin, alpha_mode);
+    out[i] = c0 * u0[i] + c1 * (u[i] + dt * (udot[i] + fs / ml[i]));
   }
 }
 
 // MC+CN right-hand side without the new-level correction:
 // g = M_L/dt u^{n-1} - A_low u^{n-1}/2 + (F^{n-1} + F^n)/2 + F*(u^{n-1})/2, with
 // A_low u^{n-1} = F^{n-1} - M_L udot^{n-1} on free rows; u_D on Dirichlet rows
-template <int G>
-__global__ __launch_bounds__(kBlock) void k_mc_cn_g(
-    int N, const int* __restrict__ rp, const int* __restrict__ col, const double* __restrict__ mij,
-    const double* __restrict__ cc, const double* __restrict__ ccT, const double* __restrict__ ml,
-    const uint8_t* __restrict__ is_dir, const double* __restrict__ uD, const double* __restrict__ uo,
-    const double* __restrict__ udot, const double* __restrict__ umax, const double* __restrict__ umin,
-    const double* __restrict__ Fn, double inv_dt, int alpha_mode, double* __restrict__ g) {
-  constexpr int RPB = kBlock / G;
-  const int lane = threadIdx.x % G, sub = threadIdx.x / G;
-  int t0, t1;
-  tile_range((N + RPB - 1) / RPB, t0, t1);
-  for (int t = t0; t < t1; ++t) {
-    const int i = t * RPB + sub;
-    if (i >= N) continue;
+__global__ __launch_bounds__(kBlock) void k_mc_cn_g(McSell M, const double* __restrict__ ml,
+                                                    const uint8_t* __restrict__ is_dir,
+                                                    const double* __restrict__ uD, const double* __restrict__ uo,
+                                                    const double* __restrict__ udot,
+                                                    const double* __restrict__ umax,
+                                                    const double* __restrict__ umin, const double* __restrict__ Fn,
+                                                    double inv_dt, int alpha_mode, double* __restrict__ g) {
+  AFC_SELL_ROWS(M.S, s, i) {
     if (is_dir[i]) {
-      if (lane == 0) g[i] = uD[i];
+      g[i] = uD[i];
       continue;
     }
-    double fs = mc_row_fstar<G>(i, lane, rp, col, mij, cc, ccT, uo, udot, umax, umin, alpha_mode);
-    fs = gsum<G>(fs);
-    if (lane == 0) {
-      const double mi = ml[i];
-      g[i] = mi * inv_dt * uo[i] + 0.5 * mi * udot[i] + 0.5 * Fn[i] + 0.5 * fs;
-    }
+    const double fs = mc_row_fstar(M, s, i, uo, udot, umax, umin, alpha_mode);
+    const double mi = ml[i];
+    g[i] = mi * inv_dt * uo[i] + 0.5 * mi * udot[i] + 0.5 * Fn[i] + 0.5 * fs;
   }
 }
 
-// MC+CN fixed-point residual: b = g + F*(u)/2, r = b - A_cn u;
-// reductions R^2 (free rows), ||b||^2, ||r||^2
-template <int G>
-__global__ __launch_bounds__(kBlock) void k_mc_cn_apply(
-    int N, const int* __restrict__ rp, const int* __restrict__ col, const double* __restrict__ mij,
-    const double* __restrict__ cc, const double* __restrict__ ccT, const double* __restrict__ Acn,
-    const double* __restrict__ u, const double* __restrict__ udot, const double* __restrict__ umax,
-    const double* __restrict__ umin, const double* __restrict__ g, const uint8_t* __restrict__ is_dir,
-    const double* __restrict__ uD, int alpha_mode, double* __restrict__ b, double* __restrict__ r, double* partials) {
-  constexpr int RPB = kBlock / G;
-  const int lane = threadIdx.x % G, sub = threadIdx.x / G;
+// MC+CN fixed-point residual: b = g + F*(u)/2, r = b - A_cn u (A_cn in SELL
+// slot order); reductions R^2 (free rows), ||b||^2, ||r||^2
+__global__ __launch_bounds__(kBlock) void k_mc_cn_apply(McSell M, const double* __restrict__ Scn,
+                                                        const double* __restrict__ u,
+                                                        const double* __restrict__ udot,
+                                                        const double* __restrict__ umax,
+                                                        const double* __restrict__ umin,
+                                                        const double* __restrict__ g,
+                                                        const uint8_t* __restrict__ is_dir,
+                                                        const double* __restrict__ uD, int alpha_mode,
+                                                        double* __restrict__ b, double* __restrict__ r,
+                                                        double* partials) {
   double acc[3] = {0.0, 0.0, 0.0};
-  int t0, t1;
-  tile_range((N + RPB - 1) / RPB, t0, t1);
-  for (int t = t0; t < t1; ++t) {
-    const int i = t * RPB + sub;
-    if (i >= N) continue;
+  AFC_SELL_ROWS(M.S, s, i) {
     if (is_dir[i]) {
-      if (lane == 0) {
-        const double bi = uD[i], ri = uD[i] - u[i];
-        b[i] = bi;
-        r[i] = ri;
-        acc[1] += bi * bi;
-        acc[2] += ri * ri;
-      }
-      continue;
-    }
-    double fs = mc_row_fstar<G>(i, lane, rp, col, mij, cc, ccT, u, udot, umax, umin, alpha_mode);
-    double au = 0.0;
-    const int e = rp[i + 1];
-    for (int k = rp[i] + lane; k < e; k += G) au += Acn[k] * u[col[k]];
-    fs = gsum<G>(fs);
-    au = gsum<G>(au);
-    if (lane == 0) {
-      const double bi = g[i] + 0.5 * fs, ri = bi - au;
+      const double bi = uD[i], ri = uD[i] - u[i];
       b[i] = bi;
       r[i] = ri;
-      acc[0] += ri * ri;
       acc[1] += bi * bi;
       acc[2] += ri * ri;
+      continue;
     }
+    const double fs = mc_row_fstar(M, s, i, u, udot, umax, umin, alpha_mode);
+    const int lane = i & 63;
+    const int base = M.S.sl_ptr[s];
+    const int L = (M.S.sl_ptr[s + 1] - base) >> 6;
+    const int doff = M.S.sl_dl[s];
+    uint32_t msk = 0u;
+    double au = 0.0;
+    for (int p = 0; p < L; ++p) {
+      if ((p & 31) == 0) msk = M.mask[(size_t)(p >> 5) * M.S.N + i];
+      if (!((msk >> (p & 31)) & 1u)) continue;
+      au += Scn[(size_t)base + 64 * p + lane] * u[i + sell_delta_any(M.S, M.dlt, M.d16, doff, p, lane)];
+    }
+    const double bi = g[i] + 0.5 * fs, ri = bi - au;
+    b[i] = bi;
+    r[i] = ri;
+    acc[0] += ri * ri;
+    acc[1] += bi * bi;
+    acc[2] += ri * ri;
   }
   block_partials<3>(acc, 3, partials, blockIdx.x);
 }
@@ -2423,23 +2422,27 @@ void mc_lowrate(H* h, const double* u, const double* F, double* udot, double* sc
          (const uint8_t*)h->is_dir, (const double*)h->uD, 0.0, udot, scratch);
 }
 
+static McSell mc_sell(const H* h) {
+  return McSell{sell_view(h), h->sl_dlt, (int)h->dlt16, h->sl_mask, h->S_mij, h->Scc, h->SccT};
+}
+
 void mc_stage(H* h, const double* u, const double* udot, const double* umax, const double* umin, double dt,
               const double* u0, double c0, double c1, double* out) {
-  AFC_DISPATCH_G(h, k_mc_stage, row_grid(h, false), h->N, h->row_ptr, h->col, h->mij, h->cc, h->ccT, h->ml,
-                 h->is_dir, h->uD, u, udot, umax, umin, dt, u0, c0, c1, h->opt.alpha_mode, out);
+  k_mc_stage<<<sell_grid(h, false), kBlock, 0, h->stream>>>(mc_sell(h), h->ml, h->is_dir, h->uD, u, udot, umax, umin,
+                                                             dt, u0, c0, c1, h->opt.alpha_mode, out);
 }
 
 void mc_cn_g(H* h, const double* uo, const double* udot, const double* umax, const double* umin, const double* Fn,
              double dt, double* g) {
-  AFC_DISPATCH_G(h, k_mc_cn_g, row_grid(h, false), h->N, h->row_ptr, h->col, h->mij, h->cc, h->ccT, h->ml,
-                 h->is_dir, h->uD, uo, udot, umax, umin, Fn, 1.0 / dt, h->opt.alpha_mode, g);
+  k_mc_cn_g<<<sell_grid(h, false), kBlock, 0, h->stream>>>(mc_sell(h), h->ml, h->is_dir, h->uD, uo, udot, umax, umin,
+                                                            Fn, 1.0 / dt, h->opt.alpha_mode, g);
 }
 
 void mc_cn_apply(H* h, const double* u, const double* udot, const double* umax, const double* umin, const double* g,
                  double* b, double* r) {
-  const int nb = row_grid(h, true);
-  AFC_DISPATCH_G(h, k_mc_cn_apply, nb, h->N, h->row_ptr, h->col, h->mij, h->cc, h->ccT, h->A_cn, u, udot, umax, umin,
-                 g, h->is_dir, h->uD, h->opt.alpha_mode, b, r, h->partials);
+  const int nb = sell_grid(h, true);
+  k_mc_cn_apply<<<nb, kBlock, 0, h->stream>>>(mc_sell(h), h->S64_cn, u, udot, umax, umin, g, h->is_dir, h->uD,
+                                               h->opt.alpha_mode, b, r, h->partials);
   finish(h, nb, 3, ACT_STORE);
 }
 
