@@ -1096,6 +1096,7 @@ afc_status afc_step_cn(afc_handle* h, double* u, const double* F_old, const doub
       [](afc_handle* h, void* ctx) -> afc_status {
         const CnArgs& a = *static_cast<CnArgs*>(ctx);
         ensure_cn_matrix(h, h->AL_fct, a.dt);
+        ensure_fct_sell(h);
         double* uo = h->w[W_UOLD];
         double* ut = h->w[W_UT];
         double* g = h->w[W_G];
@@ -1131,6 +1132,7 @@ afc_status afc_step_cn_linear(afc_handle* h, double* u, const double* F_old, con
       [](afc_handle* h, void* ctx) -> afc_status {
         const CnArgs& a = *static_cast<CnArgs*>(ctx);
         ensure_cn_matrix(h, h->AL_fct, a.dt);
+        ensure_fct_sell(h);
         double* uo = h->w[W_UOLD];
         double* ut = h->w[W_UT];
         double* g = h->w[W_G];

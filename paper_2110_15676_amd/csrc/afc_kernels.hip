@@ -1439,6 +1439,14 @@ __device__ __forceinline__ int sell_delta_any(const SellView& S, const void* dlt
              : static_cast<const int*>(dlt)[doff + 64 * p + lane];
 }
 
+// rows of a SELL launch: slice s of this wave, row i of this lane
+#define AFC_SELL_ROWS(S, s, i)                                                        \
+  int t0_, t1_;                                                                       \
+  tile_range(((S).nsl + kBlock / 64 - 1) / (kBlock / 64), t0_, t1_);                  \
+  for (int t_ = t0_; t_ < t1_; ++t_)                                                  \
+    if (const int s = wave_slice(t_); s < (S).nsl)                                    \
+      if (const int i = s * 64 + (int)(threadIdx.x & 63); i < (S).N)
+
 __global__ __launch_bounds__(kBlock) void k_ssp_lowrate_sell(SellView S, const void* __restrict__ dlt, int d16,
                                                              const uint32_t* __restrict__ mask,
                                                              const double* __restrict__ Sal,
@@ -1587,161 +1595,137 @@ __global__ __launch_bounds__(kBlock) void k_cn_extrapolate(int N, const double* 
     us[i] = is_dir[i] ? uD[i] : 2.0 * ut[i] - uo[i];
 }
 
-template <int G>
-__global__ __launch_bounds__(kBlock) void k_cn_predict(int N, const int* __restrict__ rp,
-                                                       const int* __restrict__ col, const double* __restrict__ AL,
-                                                       const double* __restrict__ uo,
+
+// Q+-_i = max/min(0, ext_{j != i} (ut_j - ut_i))
+
+
+// b = g + F*(u), r = b - A_cn u ; reductions: R^2 (free rows), ||b||^2, ||r||^2
+
+// The Crank-Nicolson passes over the SELL-64 rows (one row per lane, values
+// in slot order, stored slots marked in `mask`).
+struct FctSell {
+  SellView S;
+  const void* dlt;
+  int d16;
+  const uint32_t* mask;
+  const double *Smij, *Sdp, *Sal;
+};
+
+#define AFC_FCT_SLOTS(F, s, i, p, dj, v)                                                  \
+  const int base_ = (F).S.sl_ptr[s];                                                      \
+  const int L_ = ((F).S.sl_ptr[s + 1] - base_) >> 6;                                      \
+  const int doff_ = (F).S.sl_dl[s];                                                       \
+  uint32_t msk_ = 0u;                                                                     \
+  for (int p = 0; p < L_; ++p)                                                            \
+    if (((p & 31) == 0 ? (msk_ = (F).mask[(size_t)(p >> 5) * (F).S.N + i]) : msk_),       \
+        ((msk_ >> (p & 31)) & 1u))                                                        \
+      if (const int dj = sell_delta_any((F).S, (F).dlt, (F).d16, doff_, p, i & 63); true) \
+        if (const size_t v = (size_t)base_ + 64 * p + (i & 63); true)
+
+// ut = u_old - dt/2 M_L^{-1} (A_low u_old - F_old) (eq. (14));
+// g = (M_L/dt - A_low/2) u_old + (F_old + F_new)/2 (right-hand side of eq. (11))
+__global__ __launch_bounds__(kBlock) void k_cn_predict(FctSell F, const double* __restrict__ uo,
                                                        const double* __restrict__ Fo, const double* __restrict__ Fn,
                                                        const double* __restrict__ ml,
                                                        const uint8_t* __restrict__ is_dir,
                                                        const double* __restrict__ uD, double dt,
                                                        double* __restrict__ ut, double* __restrict__ g) {
-  constexpr int RPB = kBlock / G;
-  const int lane = threadIdx.x % G, sub = threadIdx.x / G;
-  int t0, t1;
-  tile_range((N + RPB - 1) / RPB, t0, t1);
-  for (int t = t0; t < t1; ++t) {
-    const int i = t * RPB + sub;
-    if (i >= N) continue;
+  AFC_SELL_ROWS(F.S, s, i) {
     if (is_dir[i]) {
-      if (lane == 0) ut[i] = g[i] = uD[i];
+      ut[i] = g[i] = uD[i];
       continue;
     }
     double y = 0.0;
-    const int e = rp[i + 1];
-    for (int k = rp[i] + lane; k < e; k += G) y += AL[k] * uo[col[k]];
-    y = gsum<G>(y);
-    if (lane == 0) {
-      const double mi = ml[i];
-      ut[i] = uo[i] - 0.5 * dt * (y - Fo[i]) / mi;
-      g[i] = mi / dt * uo[i] - 0.5 * y + 0.5 * (Fo[i] + Fn[i]);
-    }
+    AFC_FCT_SLOTS(F, s, i, p, dj, v) y += F.Sal[v] * uo[i + dj];
+    const double mi = ml[i];
+    ut[i] = uo[i] - 0.5 * dt * (y - Fo[i]) / mi;
+    g[i] = mi / dt * uo[i] - 0.5 * y + 0.5 * (Fo[i] + Fn[i]);
   }
 }
 
 // Q+-_i = max/min(0, ext_{j != i} (ut_j - ut_i))
-template <int G>
-__global__ __launch_bounds__(kBlock) void k_zalesak_Q(int N, const int* __restrict__ rp, const int* __restrict__ col,
-                                                      const double* __restrict__ ut, double* __restrict__ Qp,
-                                                      double* __restrict__ Qm) {
-  constexpr int RPB = kBlock / G;
-  const int lane = threadIdx.x % G, sub = threadIdx.x / G;
-  int t0, t1;
-  tile_range((N + RPB - 1) / RPB, t0, t1);
-  for (int t = t0; t < t1; ++t) {
-    const int i = t * RPB + sub;
-    if (i >= N) continue;
+__global__ __launch_bounds__(kBlock) void k_zalesak_Q(FctSell F, const double* __restrict__ ut,
+                                                      double* __restrict__ Qp, double* __restrict__ Qm) {
+  AFC_SELL_ROWS(F.S, s, i) {
     const double uti = ut[i];
     double qp = 0.0, qm = 0.0;
-    const int e = rp[i + 1];
-    for (int k = rp[i] + lane; k < e; k += G) {
-      const int j = col[k];
-      if (j == i) continue;
-      const double du = ut[j] - uti;
+    AFC_FCT_SLOTS(F, s, i, p, dj, v) {
+      if (dj == 0) continue;
+      const double du = ut[i + dj] - uti;
       qp = fmax(qp, du);
       qm = fmin(qm, du);
     }
-    qp = gmax<G>(qp);
-    qm = gmin<G>(qm);
-    if (lane == 0) {
-      Qp[i] = qp;
-      Qm[i] = qm;
-    }
+    Qp[i] = qp;
+    Qm[i] = qm;
   }
 }
 
-template <int G>
-__global__ __launch_bounds__(kBlock) void k_cn_limit_R(int N, const int* __restrict__ rp,
-                                                       const int* __restrict__ col,
-                                                       const double* __restrict__ mij, const double* __restrict__ dp,
-                                                       const double* __restrict__ u,
+// P+- of the (prelimited) CN fluxes of eqs. (12), (13) and R+-
+__global__ __launch_bounds__(kBlock) void k_cn_limit_R(FctSell F, const double* __restrict__ u,
                                                        const double* __restrict__ uo, const double* __restrict__ Qp,
                                                        const double* __restrict__ Qm, const double* __restrict__ ml,
                                                        const uint8_t* __restrict__ is_dir, double dt, double L,
                                                        double* __restrict__ Rp, double* __restrict__ Rm) {
-  constexpr int RPB = kBlock / G;
-  const int lane = threadIdx.x % G, sub = threadIdx.x / G;
   const double inv_dt = 1.0 / dt;
-  int t0, t1;
-  tile_range((N + RPB - 1) / RPB, t0, t1);
-  for (int t = t0; t < t1; ++t) {
-    const int i = t * RPB + sub;
-    if (i >= N) continue;
+  AFC_SELL_ROWS(F.S, s, i) {
     if (is_dir[i]) {
-      if (lane == 0) Rp[i] = Rm[i] = 1.0;
+      Rp[i] = Rm[i] = 1.0;
       continue;
     }
     const double dui = u[i] - uo[i], sui = u[i] + uo[i];
     double pp = 0.0, pm = 0.0;
-    const int e = rp[i + 1];
-    for (int k = rp[i] + lane; k < e; k += G) {
-      const int j = col[k];
-      if (j == i) continue;
+    AFC_FCT_SLOTS(F, s, i, p, dj, v) {
+      if (dj == 0) continue;
+      const int j = i + dj;
       const double uj = u[j], uoj = uo[j];
-      const double r = cn_flux(mij[k], -dp[k], inv_dt, dui, uj - uoj, sui, uj + uoj, L);
+      const double r = cn_flux(F.Smij[v], -F.Sdp[v], inv_dt, dui, uj - uoj, sui, uj + uoj, L);
       pp += fmax(r, 0.0);
       pm += fmin(r, 0.0);
     }
-    pp = gsum<G>(pp);
-    pm = gsum<G>(pm);
-    if (lane == 0) {
-      Rp[i] = zalesak_R(ml[i], Qp[i], pp, dt);
-      Rm[i] = zalesak_R(ml[i], Qm[i], pm, dt);
-    }
+    Rp[i] = zalesak_R(ml[i], Qp[i], pp, dt);
+    Rm[i] = zalesak_R(ml[i], Qm[i], pm, dt);
   }
 }
 
-// b = g + F*(u), r = b - A_cn u ; reductions: R^2 (free rows), ||b||^2, ||r||^2
-template <int G>
-__global__ __launch_bounds__(kBlock) void k_cn_apply(
-    int N, const int* __restrict__ rp, const int* __restrict__ col, const double* __restrict__ mij,
-    const double* __restrict__ dp, const double* __restrict__ Acn, const double* __restrict__ u,
-    const double* __restrict__ uo, const double* __restrict__ Rp, const double* __restrict__ Rm,
-    const double* __restrict__ g, const uint8_t* __restrict__ is_dir, const double* __restrict__ uD, double dt,
-    double L, int alpha_mode, double* __restrict__ b, double* __restrict__ r, KState* ks, double* partials) {
-  constexpr int RPB = kBlock / G;
-  const int lane = threadIdx.x % G, sub = threadIdx.x / G;
+// b = g + F*(u), r = b - A_cn u (A_cn in slot order); reductions: R^2 (free rows), ||b||^2, ||r||^2
+__global__ __launch_bounds__(kBlock) void k_cn_apply(FctSell F, const double* __restrict__ Scn,
+                                                     const double* __restrict__ u, const double* __restrict__ uo,
+                                                     const double* __restrict__ Rp, const double* __restrict__ Rm,
+                                                     const double* __restrict__ g,
+                                                     const uint8_t* __restrict__ is_dir,
+                                                     const double* __restrict__ uD, double dt, double L,
+                                                     int alpha_mode, double* __restrict__ b, double* __restrict__ r,
+                                                     double* partials) {
   const double inv_dt = 1.0 / dt;
   double acc[3] = {0.0, 0.0, 0.0};
-  int t0, t1;
-  tile_range((N + RPB - 1) / RPB, t0, t1);
-  for (int t = t0; t < t1; ++t) {
-    const int i = t * RPB + sub;
-    if (i >= N) continue;
+  AFC_SELL_ROWS(F.S, s, i) {
     if (is_dir[i]) {
-      if (lane == 0) {
-        const double bi = uD[i], ri = uD[i] - u[i];
-        b[i] = bi;
-        r[i] = ri;
-        acc[1] += bi * bi;
-        acc[2] += ri * ri;
-      }
+      const double bi = uD[i], ri = uD[i] - u[i];
+      b[i] = bi;
+      r[i] = ri;
+      acc[1] += bi * bi;
+      acc[2] += ri * ri;
       continue;
     }
     const double dui = u[i] - uo[i], sui = u[i] + uo[i], rpi = Rp[i], rmi = Rm[i];
     double fs = 0.0, au = 0.0;
-    const int e = rp[i + 1];
-    for (int k = rp[i] + lane; k < e; k += G) {
-      const int j = col[k];
+    AFC_FCT_SLOTS(F, s, i, p, dj, v) {
+      const int j = i + dj;
       const double uj = u[j];
-      au += Acn[k] * uj;
-      if (j == i || alpha_mode == AFC_ALPHA_ZERO) continue;
-      const double uoj = uo[j];
-      const double rf = cn_flux(mij[k], -dp[k], inv_dt, dui, uj - uoj, sui, uj + uoj, L);
+      au += Scn[v] * uj;
+      if (dj == 0 || alpha_mode == AFC_ALPHA_ZERO) continue;
+      const double uoj = uo[j], rpj = Rp[j], rmj = Rm[j];  // every gather issued at once
+      const double rf = cn_flux(F.Smij[v], -F.Sdp[v], inv_dt, dui, uj - uoj, sui, uj + uoj, L);
       double a = 1.0;
-      if (alpha_mode == AFC_ALPHA_LIMITED) a = rf > 0.0 ? fmin(rpi, Rm[j]) : fmin(rmi, Rp[j]);
+      if (alpha_mode == AFC_ALPHA_LIMITED) a = rf > 0.0 ? fmin(rpi, rmj) : fmin(rmi, rpj);
       fs += a * rf;
     }
-    fs = gsum<G>(fs);
-    au = gsum<G>(au);
-    if (lane == 0) {
-      const double bi = g[i] + fs, ri = bi - au;
-      b[i] = bi;
-      r[i] = ri;
-      acc[0] += ri * ri;
-      acc[1] += bi * bi;
-      acc[2] += ri * ri;
-    }
+    const double bi = g[i] + fs, ri = bi - au;
+    b[i] = bi;
+    r[i] = ri;
+    acc[0] += ri * ri;
+    acc[1] += bi * bi;
+    acc[2] += ri * ri;
   }
   block_partials<3>(acc, 3, partials, blockIdx.x);
 }
@@ -1913,13 +1897,6 @@ __device__ __forceinline__ double mc_row_fstar(const McSell& M, int s, int i, co
   }
   return fs;
 }
-
-#define AFC_SELL_ROWS(S, s, i)                                                        \
-  int t0_, t1_;                                                                       \
-  tile_range(((S).nsl + kBlock / 64 - 1) / (kBlock / 64), t0_, t1_);                  \
-  for (int t_ = t0_; t_ < t1_; ++t_)                                                  \
-    if (const int s = wave_slice(t_); s < (S).nsl)                                    \
-      if (const int i = s * 64 + (int)(threadIdx.x & 63); i < (S).N)
 
 // MC forward-Euler stage of eq. (18): out = c0 u0 + c1 (u + dt (udot + F*/m)),
 // u_D at Dirichlet nodes (udot from the MC low-order operator)
@@ -2466,10 +2443,14 @@ void ssp_apply(H* h, const double* u, const double* udot, const double* ut, cons
          out);
 }
 
+static FctSell fct_sell(const H* h) {
+  return FctSell{sell_view(h), h->sl_dlt, (int)h->dlt16, h->sl_mask, h->S_mij, h->S_dp, h->S_alf};
+}
+
 void cn_predict(H* h, const double* u_old, const double* F_old, const double* F_new, double dt, double* ut,
                 double* g) {
-  AFC_DISPATCH_G(h, k_cn_predict, row_grid(h, false), h->N, h->row_ptr, h->col, h->AL_fct, u_old, F_old, F_new,
-                 h->ml, h->is_dir, h->uD, dt, ut, g);
+  k_cn_predict<<<sell_grid(h, false), kBlock, 0, h->stream>>>(fct_sell(h), u_old, F_old, F_new, h->ml, h->is_dir,
+                                                               h->uD, dt, ut, g);
 }
 
 void cn_extrapolate(H* h, const double* ut, const double* uo, double* us) {
@@ -2477,20 +2458,20 @@ void cn_extrapolate(H* h, const double* ut, const double* uo, double* us) {
 }
 
 void zalesak_Q(H* h, const double* ut, double* Qp, double* Qm) {
-  AFC_DISPATCH_G(h, k_zalesak_Q, row_grid(h, false), h->N, h->row_ptr, h->col, ut, Qp, Qm);
+  k_zalesak_Q<<<sell_grid(h, false), kBlock, 0, h->stream>>>(fct_sell(h), ut, Qp, Qm);
 }
 
 void cn_limit_R(H* h, const double* u, const double* u_old, const double* Qp, const double* Qm, double dt,
                 double* Rp, double* Rm) {
-  AFC_DISPATCH_G(h, k_cn_limit_R, row_grid(h, false), h->N, h->row_ptr, h->col, h->mij, h->dp_fct, u, u_old, Qp,
-                 Qm, h->ml, h->is_dir, dt, h->opt.prelimit, Rp, Rm);
+  k_cn_limit_R<<<sell_grid(h, false), kBlock, 0, h->stream>>>(fct_sell(h), u, u_old, Qp, Qm, h->ml, h->is_dir, dt,
+                                                               h->opt.prelimit, Rp, Rm);
 }
 
 void cn_apply(H* h, const double* u, const double* u_old, const double* Rp, const double* Rm, const double* g,
               double dt, double* b, double* r) {
-  const int nb = row_grid(h, true);
-  AFC_DISPATCH_G(h, k_cn_apply, nb, h->N, h->row_ptr, h->col, h->mij, h->dp_fct, h->A_cn, u, u_old, Rp, Rm, g,
-                 h->is_dir, h->uD, dt, h->opt.prelimit, h->opt.alpha_mode, b, r, h->ks, h->partials);
+  const int nb = sell_grid(h, true);
+  k_cn_apply<<<nb, kBlock, 0, h->stream>>>(fct_sell(h), h->S64_cn, u, u_old, Rp, Rm, g, h->is_dir, h->uD, dt,
+                                           h->opt.prelimit, h->opt.alpha_mode, b, r, h->partials);
   finish(h, nb, 3, ACT_STORE);
 }
 

@@ -206,7 +206,7 @@ int64_t afc_footprint_bytes(int32_t n, int64_t nnz, int32_t kind, const afc_opti
   b += 8 * (int64_t)(afc::kMaxRed + afc::kBlkRows) * afc::kRedBlocks + 8 * (N / 256 + 1);  // reduction partials
   b += N * 8 * 2;                                          // request u and F
   b += 32 << 20;  // allocation granularity of ~60 device buffers, graphs and small state
-  (void)kind;
+  if (kind == AFC_REQ_CN) b += Z * 24 * 101 / 100;  // m_ij, d+_ij and A_low in slot order (CN passes)
   return b;
 }
 

@@ -94,28 +94,32 @@ def test_server_budget_serializes_requests():
         assert b0 >= a1 - 1e-3  # never two requests in service together
 
 
-@pytest.mark.parametrize("sstep", [0, 8])
-def test_footprint_bounds_handle_memory(sstep):
+@pytest.mark.parametrize("kind,sstep", [(1, 0), (1, 8), (0, 0)])
+def test_footprint_bounds_handle_memory(kind, sstep):
     """The admission model (afc_footprint_bytes) covers what a handle really
-    allocates on the device after a stationary mixed-precision solve (the
-    Krylov basis, the s-step partials and the status ring included), and is not
-    more than twice that."""
+    allocates on the device after a stationary mixed-precision solve or CN
+    steps (the Krylov basis, the s-step partials, the status ring and the
+    coefficient copies built on first use included), and is not more than twice
+    that."""
     afc = _afc()
-    inst = I.config3(40)
+    inst = I.config3(40) if kind == 1 else I.config2(40)
     o = afc.afc_default_options(precision=afc.AFC_PREC_MIXED, fp_tol=0.0, fp_tol_mode=afc.AFC_TOL_REL, fp_maxit=1,
                                 lin_atol=0.0, lin_rtol=1e-8, sstep=sstep)
     o.stream = torch.cuda.current_stream().cuda_stream
-    u = torch.zeros(inst.N, dtype=torch.float64, device="cuda:0")
+    u = torch.tensor(inst.u0 if kind == 0 else np.zeros(inst.N), device="cuda:0")
     F = torch.tensor(inst.F, device="cuda:0")
     torch.cuda.synchronize()
     free0 = torch.cuda.mem_get_info()[0]
-    h = afc.afc_create_instance(inst, o, conv=True)
+    h = afc.afc_create_instance(inst, o, conv=kind == 1)
     try:
-        afc.afc_solve_stationary(h, u, F, init_low_order=True)
+        if kind == 1:
+            afc.afc_solve_stationary(h, u, F, init_low_order=True)
+        else:
+            afc.afc_step_cn(h, u, F, F, 1e-3, raise_on_error=False)
         torch.cuda.synchronize()
         used = free0 - torch.cuda.mem_get_info()[0]
     finally:
         afc.afc_destroy(h)
-    fp = afc.afc_footprint_bytes(inst.N, inst.nnz, 1, o) - 16 * inst.N  # less the request's own u and F
+    fp = afc.afc_footprint_bytes(inst.N, inst.nnz, kind, o) - 16 * inst.N  # less the request's own u and F
     print("N=%d nnz=%d used %.1f MB model %.1f MB" % (inst.N, inst.nnz, used / 1e6, fp / 1e6), flush=True)
     assert used <= fp <= 2 * used + (64 << 20)
