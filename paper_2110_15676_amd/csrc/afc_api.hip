@@ -124,7 +124,7 @@ void free_all(afc_handle* h) {
   f(h->mij); f(h->dp_fct); f(h->AL_fct); f(h->mu_own);
   f(h->cc); f(h->ccT); f(h->AL_mcl); f(h->dinv_mcl);
   f(h->A_cn); f(h->dinv_cn);
-  f(h->sl_ptr); f(h->sl_dl); f(h->sl_pat); f(h->sl_dlt); f(h->sell_pos); f(h->sl_mask); f(h->Scc); f(h->SccT); f(h->S_mij); f(h->S_dp); f(h->S_alf); f(h->S64_mcl); f(h->S32_mcl); f(h->S64_cn); f(h->S32_cn);
+  f(h->sl_ptr); f(h->sl_dl); f(h->sl_pat); f(h->sl_dlt); f(h->sell_pos); f(h->sl_mask); f(h->Scc); f(h->SccT); f(h->S_mij); f(h->S_dp); f(h->S_alf); f(h->S_own); f(h->S64_mcl); f(h->S32_mcl); f(h->S64_cn); f(h->S32_cn);
   f(h->ks_ptr); f(h->ks_dl); f(h->ks_pat); f(h->ks_dlt); f(h->kpos);
   for (auto*& p : h->w) f(p);
   h->w.clear();
@@ -166,6 +166,9 @@ void ensure_fct_sell(afc_handle* h) {
   afc::to_sell64(h, h->mij, h->S_mij);
   afc::to_sell64(h, h->dp_fct, h->S_dp);
   afc::to_sell64(h, h->AL_fct, h->S_alf);
+  h->S_own = dalloc<uint8_t>(h, slots);
+  HIP_OK(hipMemsetAsync(h->S_own, 0, slots, h->stream));
+  afc::to_sell8(h, h->mu_own, h->S_own);
 }
 
 void ensure_ring(afc_handle* h) {
@@ -1278,7 +1281,10 @@ afc_status afc_solve_stationary(afc_handle* h, double* u, const double* F, int32
         const bool mu = h->opt.limiter == AFC_LIMITER_MU;
         // MCL: A_low from the convective D (Remark 1); MU: A_low = A + D from A,
         // assembled into the handle's CN storage
-        if (mu) ensure_cn_matrix(h, h->AL_fct, 0.0);
+        if (mu) {
+          ensure_cn_matrix(h, h->AL_fct, 0.0);
+          ensure_fct_sell(h);
+        }
         const SysMat S = mu ? SysMat{h->A_cn, h->dinv_cn, h->S64_cn, h->S32_cn}
                             : SysMat{h->AL_mcl, h->dinv_mcl, h->S64_mcl, h->S32_mcl};
         double* b = h->w[W_B];

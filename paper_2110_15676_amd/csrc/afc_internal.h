@@ -108,6 +108,7 @@ struct afc_handle_s {
   double* S_mij = nullptr;      // m_ij, d+_ij and A_low (FCT) in SELL slot order (SSP stages; built on first use)
   double* S_dp = nullptr;
   double* S_alf = nullptr;
+  uint8_t* S_own = nullptr;     // MU edge owner in slot order
   bool dlt16 = true;
   int* sell_pos = nullptr;    // [nnz]
   double* S64_mcl = nullptr;  // A_low (MCL) in SELL order

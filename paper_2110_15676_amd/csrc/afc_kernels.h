@@ -19,7 +19,8 @@ void norm2(H* h, const double* x, int red_idx);             // ||x||^2 into ks->
 // A_cn = M_L/dt + AL/2 for AL = A_low of the FCT (AL_fct) or MC (AL_mcl) scheme
 // (+ dinv, SELL FP64 and scaled FP32 copies)
 void build_cn_matrix(H* h, const double* AL, double dt);
-void to_sell64(H* h, const double* csr, double* sell);                       // CSR values -> SELL slots
+void to_sell64(H* h, const double* csr, double* sell);
+void to_sell8(H* h, const uint8_t* csr, uint8_t* sell);                      // uint8 CSR values -> SELL slots                       // CSR values -> SELL slots
 void to_sell32_scaled(H* h, const double* csr, const double* dinv, float* sell);  // (a_ij dinv_j) in FP32
 
 // workgroups of a launch over the SELL tiles (reduce: capped at the partial slots)

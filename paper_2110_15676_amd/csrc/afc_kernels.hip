@@ -1989,105 +1989,79 @@ __global__ __launch_bounds__(kBlock) void k_mc_cn_apply(McSell M, const double* 
 // (1: a_ji < a_ij, node i; 2: a_ji > a_ij, node j; 0: both)
 // ---------------------------------------------------------------------------
 
-// P+-_i over the edges node i owns, Q+-_i over all its fluxes, R+-_i
-template <int G>
-__global__ __launch_bounds__(kBlock) void k_mu_R(int N, const int* __restrict__ rp, const int* __restrict__ col,
-                                                 const double* __restrict__ dp, const uint8_t* __restrict__ own,
+// P+-_i over the edges node i owns, Q+-_i over all its fluxes, R+-_i (SELL rows;
+// Sown: own[k] in slot order)
+__global__ __launch_bounds__(kBlock) void k_mu_R(FctSell F, const uint8_t* __restrict__ Sown,
                                                  const double* __restrict__ u, const uint8_t* __restrict__ is_dir,
                                                  double* __restrict__ Rp, double* __restrict__ Rm) {
-  constexpr int RPB = kBlock / G;
-  const int lane = threadIdx.x % G, sub = threadIdx.x / G;
-  int t0, t1;
-  tile_range((N + RPB - 1) / RPB, t0, t1);
-  for (int t = t0; t < t1; ++t) {
-    const int i = t * RPB + sub;
-    if (i >= N) continue;
+  AFC_SELL_ROWS(F.S, s, i) {
     if (is_dir[i]) {
-      if (lane == 0) Rp[i] = Rm[i] = 1.0;
+      Rp[i] = Rm[i] = 1.0;
       continue;
     }
     const double ui = u[i];
     double pp = 0.0, pm = 0.0, qp = 0.0, qm = 0.0;
-    const int e = rp[i + 1];
-    for (int k = rp[i] + lane; k < e; k += G) {
-      const int j = col[k];
-      if (j == i) continue;
-      const double rf = -dp[k] * (u[j] - ui);
+    AFC_FCT_SLOTS(F, s, i, p, dj, v) {
+      if (dj == 0) continue;
+      const double rf = -F.Sdp[v] * (u[i + dj] - ui);
       const double rpos = fmax(rf, 0.0), rneg = fmin(rf, 0.0);
-      if (own[k] != 2) {
+      if (Sown[v] != 2) {
         pp += rpos;
         pm += rneg;
       }
       qp -= rneg;
       qm -= rpos;
     }
-    pp = gsum<G>(pp);
-    pm = gsum<G>(pm);
-    qp = gsum<G>(qp);
-    qm = gsum<G>(qm);
-    if (lane == 0) {
-      Rp[i] = pp != 0.0 ? fmin(1.0, qp / pp) : 1.0;
-      Rm[i] = pm != 0.0 ? fmin(1.0, qm / pm) : 1.0;
-    }
+    Rp[i] = pp != 0.0 ? fmin(1.0, qp / pp) : 1.0;
+    Rm[i] = pm != 0.0 ? fmin(1.0, qm / pm) : 1.0;
   }
 }
 
 // alpha_ij = alpha_ji from the owning node (the smaller of both when equal),
-// F*_i = sum_j alpha_ij r_ij; b = F + F*, r = b - A u ; reductions R^2 (free
-// rows), ||b||^2, ||r||^2
-template <int G>
-__global__ __launch_bounds__(kBlock) void k_mu_apply(
-    int N, const int* __restrict__ rp, const int* __restrict__ col, const double* __restrict__ dp,
-    const uint8_t* __restrict__ own, const double* __restrict__ As, const double* __restrict__ u,
-    const double* __restrict__ Rp, const double* __restrict__ Rm, const double* __restrict__ F,
-    const uint8_t* __restrict__ is_dir, const double* __restrict__ uD, int alpha_mode, double* __restrict__ b,
-    double* __restrict__ r, double* partials) {
-  constexpr int RPB = kBlock / G;
-  const int lane = threadIdx.x % G, sub = threadIdx.x / G;
+// F*_i = sum_j alpha_ij r_ij; b = F + F*, r = b - A u (A in slot order);
+// reductions R^2 (free rows), ||b||^2, ||r||^2
+__global__ __launch_bounds__(kBlock) void k_mu_apply(FctSell F, const uint8_t* __restrict__ Sown,
+                                                     const double* __restrict__ Sa, const double* __restrict__ u,
+                                                     const double* __restrict__ Rp, const double* __restrict__ Rm,
+                                                     const double* __restrict__ Fv,
+                                                     const uint8_t* __restrict__ is_dir,
+                                                     const double* __restrict__ uD, int alpha_mode,
+                                                     double* __restrict__ b, double* __restrict__ r,
+                                                     double* partials) {
   double acc[3] = {0.0, 0.0, 0.0};
-  int t0, t1;
-  tile_range((N + RPB - 1) / RPB, t0, t1);
-  for (int t = t0; t < t1; ++t) {
-    const int i = t * RPB + sub;
-    if (i >= N) continue;
+  AFC_SELL_ROWS(F.S, s, i) {
     if (is_dir[i]) {
-      if (lane == 0) {
-        const double bi = uD[i], ri = uD[i] - u[i];
-        b[i] = bi;
-        r[i] = ri;
-        acc[1] += bi * bi;
-        acc[2] += ri * ri;
-      }
+      const double bi = uD[i], ri = uD[i] - u[i];
+      b[i] = bi;
+      r[i] = ri;
+      acc[1] += bi * bi;
+      acc[2] += ri * ri;
       continue;
     }
     const double ui = u[i], rpi = Rp[i], rmi = Rm[i];
     double fs = 0.0, au = 0.0;
-    const int e = rp[i + 1];
-    for (int k = rp[i] + lane; k < e; k += G) {
-      const int j = col[k];
+    AFC_FCT_SLOTS(F, s, i, p, dj, v) {
+      const int j = i + dj;
       const double uj = u[j];
-      au += As[k] * uj;
-      if (j == i || alpha_mode == AFC_ALPHA_ZERO) continue;
-      const double rf = -dp[k] * (uj - ui);
+      au += Sa[v] * uj;
+      if (dj == 0 || alpha_mode == AFC_ALPHA_ZERO) continue;
+      const double rf = -F.Sdp[v] * (uj - ui);
       double a = 1.0;
       if (alpha_mode == AFC_ALPHA_LIMITED) {
-        const double ai = rf > 0.0 ? rpi : (rf < 0.0 ? rmi : 1.0);         // node i, flux r_ij
-        const double aj = rf < 0.0 ? Rp[j] : (rf > 0.0 ? Rm[j] : 1.0);     // node j, flux r_ji = -r_ij
-        const int o = own[k];
+        const double rpj = Rp[j], rmj = Rm[j];
+        const double ai = rf > 0.0 ? rpi : (rf < 0.0 ? rmi : 1.0);  // node i, flux r_ij
+        const double aj = rf < 0.0 ? rpj : (rf > 0.0 ? rmj : 1.0);  // node j, flux r_ji = -r_ij
+        const int o = Sown[v];
         a = o == 1 ? ai : (o == 2 ? aj : fmin(ai, aj));
       }
       fs += a * rf;
     }
-    fs = gsum<G>(fs);
-    au = gsum<G>(au);
-    if (lane == 0) {
-      const double bi = F[i] + fs, ri = bi - au;
-      b[i] = bi;
-      r[i] = ri;
-      acc[0] += ri * ri;
-      acc[1] += bi * bi;
-      acc[2] += ri * ri;
-    }
+    const double bi = Fv[i] + fs, ri = bi - au;
+    b[i] = bi;
+    r[i] = ri;
+    acc[0] += ri * ri;
+    acc[1] += bi * bi;
+    acc[2] += ri * ri;
   }
   block_partials<3>(acc, 3, partials, blockIdx.x);
 }
@@ -2256,6 +2230,10 @@ void residual(H* h, const double* A, const double* b, const double* x, double* r
   finish_from(h, h->partials_res, nb, 1, ACT_CYCLE, 0, 0, 0, mode);
 }
 
+void to_sell8(H* h, const uint8_t* csr, uint8_t* sell) {
+  k_to_sell<uint8_t><<<vec_grid(h), kBlock, 0, h->stream>>>((int)h->nnz, h->sell_pos, csr, sell);
+}
+
 void to_sell64(H* h, const double* csr, double* sell) {
   k_to_sell<double><<<vec_grid(h), kBlock, 0, h->stream>>>((int)h->nnz, h->sell_pos, csr, sell);
 }
@@ -2381,22 +2359,26 @@ void bicg_iter(H* h, const double* A, const double* dinv, const BicgVec& b) {
   k_bicg_p<<<nv, kBlock, 0, h->stream>>>(h->N, b.r, b.v, b.p, h->ks);
 }
 
+static FctSell fct_sell(const H* h) {
+  return FctSell{sell_view(h), h->sl_dlt, (int)h->dlt16, h->sl_mask, h->S_mij, h->S_dp, h->S_alf};
+}
+
 void mu_R(H* h, const double* u, double* Rp, double* Rm) {
-  AFC_DISPATCH_G_TIMED(h, AFC_KERNEL_MCL, k_mu_R, row_grid(h, false), h->N, h->row_ptr, h->col, h->dp_fct,
-                       h->mu_own, u, h->is_dir, Rp, Rm);
+  launch(h, AFC_KERNEL_MCL, k_mu_R, sell_grid(h, false), kBlock, fct_sell(h), (const uint8_t*)h->S_own, u,
+         (const uint8_t*)h->is_dir, Rp, Rm);
 }
 
 void mu_apply(H* h, const double* u, const double* Rp, const double* Rm, const double* F, double* b, double* r) {
-  const int nb = row_grid(h, true);
-  AFC_DISPATCH_G_TIMED(h, AFC_KERNEL_MCL, k_mu_apply, nb, h->N, h->row_ptr, h->col, h->dp_fct, h->mu_own, h->A_cn, u,
-                       Rp, Rm, F, h->is_dir, h->uD, h->opt.alpha_mode, b, r, h->partials);
+  const int nb = sell_grid(h, true);
+  launch(h, AFC_KERNEL_MCL, k_mu_apply, nb, kBlock, fct_sell(h), (const uint8_t*)h->S_own, (const double*)h->S64_cn,
+         u, Rp, Rm, F, (const uint8_t*)h->is_dir, (const double*)h->uD, h->opt.alpha_mode, b, r, h->partials);
   finish(h, nb, 3, ACT_STORE);
 }
 
 void mc_lowrate(H* h, const double* u, const double* F, double* udot, double* scratch) {
-  k_ssp_lowrate_sell<<<sell_grid(h, false), kBlock, 0, h->stream>>>(sell_view(h), (const void*)h->sl_dlt, (int)h->dlt16,
-         (const uint32_t*)h->sl_mask, (const double*)h->S64_mcl, u, F, (const double*)h->ml,
-         (const uint8_t*)h->is_dir, (const double*)h->uD, 0.0, udot, scratch);
+  k_ssp_lowrate_sell<<<sell_grid(h, false), kBlock, 0, h->stream>>>(
+      sell_view(h), (const void*)h->sl_dlt, (int)h->dlt16, (const uint32_t*)h->sl_mask, (const double*)h->S64_mcl, u, F,
+      (const double*)h->ml, (const uint8_t*)h->is_dir, (const double*)h->uD, 0.0, udot, scratch);
 }
 
 static McSell mc_sell(const H* h) {
@@ -2443,9 +2425,6 @@ void ssp_apply(H* h, const double* u, const double* udot, const double* ut, cons
          out);
 }
 
-static FctSell fct_sell(const H* h) {
-  return FctSell{sell_view(h), h->sl_dlt, (int)h->dlt16, h->sl_mask, h->S_mij, h->S_dp, h->S_alf};
-}
 
 void cn_predict(H* h, const double* u_old, const double* F_old, const double* F_new, double dt, double* ut,
                 double* g) {
