@@ -447,10 +447,10 @@ SolveOut solve_bicgstab(afc_handle* h, const SysMat& S, const double* b, double*
     while (!h->host_status->done && h->host_status->iters - it0 < h->opt.lin_maxit) {
       const int n = std::min<int>(chunk, h->opt.lin_maxit - (h->host_status->iters - it0));
       auto iters = [&]() {
-        for (int c = 0; c < n; ++c) afc::bicg_iter(h, S.A, S.dinv, v);
+        for (int c = 0; c < n; ++c) afc::bicg_iter(h, S.S64, S.dinv, v);
       };
       if (h->opt.graphs && !h->opt.profile)
-        HIP_OK(hipGraphLaunch(cached_graph(h, {key_int(2), S.A, S.dinv, x, r, key_int(n), key_int(h->G)}, iters), h->stream));
+        HIP_OK(hipGraphLaunch(cached_graph(h, {key_int(2), S.S64, S.dinv, x, r, key_int(n)}, iters), h->stream));
       else
         iters();
       sync_status(h);

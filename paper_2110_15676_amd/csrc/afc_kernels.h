@@ -60,7 +60,7 @@ void sstep_xupdate(H* h, int kb, int sb, const double* dinv, double* x);
 // --- BiCGStab (right Jacobi, FP64) ----------------------------------------------
 struct BicgVec { double *x, *r, *rhat, *p, *v, *s, *t; };
 void bicg_init(H* h, const BicgVec& b, double tol);
-void bicg_iter(H* h, const double* A, const double* dinv, const BicgVec& b);
+void bicg_iter(H* h, const double* A_sell, const double* dinv, const BicgVec& b);  // A in SELL order
 
 // --- Zalesak FCT, explicit SSP stage -------------------------------------------
 void ssp_lowrate(H* h, const double* u, const double* F, double dt, double* udot, double* ut);

@@ -1312,32 +1312,24 @@ __global__ __launch_bounds__(kBlock) void k_bicg_init(int N, const double* __res
   block_partials<1>(acc, 1, partials, blockIdx.x);
 }
 
-// v = A D^{-1} p ; alpha = rho / (rhat, v)
-template <int G>
-__global__ __launch_bounds__(kBlock) void k_bicg_v(int N, const int* __restrict__ rp, const int* __restrict__ col,
+// v = A D^{-1} p ; alpha = rho / (rhat, v)   (A in SELL order)
+template <typename TI>
+__global__ __launch_bounds__(kBlock) void k_bicg_v(SellView S, const TI* __restrict__ dlt,
                                                    const double* __restrict__ A, const double* __restrict__ dinv,
                                                    const double* __restrict__ p, const double* __restrict__ rhat,
                                                    double* __restrict__ v, KState* ks, double* partials) {
   if (ks->done) return;
-  constexpr int RPB = kBlock / G;
-  const int lane = threadIdx.x % G, sub = threadIdx.x / G;
   double acc[1] = {0.0};
   int t0, t1;
-  tile_range((N + RPB - 1) / RPB, t0, t1);
+  tile_range((S.nsl + kBlock / 64 - 1) / (kBlock / 64), t0, t1);
   for (int t = t0; t < t1; ++t) {
-    const int i = t * RPB + sub;
-    if (i >= N) continue;
-    double s = 0.0;
-    const int e = rp[i + 1];
-    for (int k = rp[i] + lane; k < e; k += G) {
-      const int j = col[k];
-      s += A[k] * (dinv[j] * p[j]);
-    }
-    s = gsum<G>(s);
-    if (lane == 0) {
-      v[i] = s;
-      acc[0] += rhat[i] * s;
-    }
+    const int s = wave_slice(t);
+    if (s >= S.nsl) continue;
+    const int i = s * 64 + (threadIdx.x & 63);
+    if (i >= S.N) continue;
+    const double q = sell_row<8>(S, dlt, A, s, i, [&](int j) { return dinv[j] * p[j]; });
+    v[i] = q;
+    acc[0] += rhat[i] * q;
   }
   block_partials<1>(acc, 1, partials, blockIdx.x);
 }
@@ -1356,33 +1348,25 @@ __global__ __launch_bounds__(kBlock) void k_bicg_s(int N, const double* __restri
   block_partials<1>(acc, 1, partials, blockIdx.x);
 }
 
-// t = A D^{-1} s ; omega = (t, s) / (t, t)
-template <int G>
-__global__ __launch_bounds__(kBlock) void k_bicg_t(int N, const int* __restrict__ rp, const int* __restrict__ col,
+// t = A D^{-1} s ; omega = (t, s) / (t, t)   (A in SELL order)
+template <typename TI>
+__global__ __launch_bounds__(kBlock) void k_bicg_t(SellView S, const TI* __restrict__ dlt,
                                                    const double* __restrict__ A, const double* __restrict__ dinv,
-                                                   const double* __restrict__ s, double* __restrict__ tv, KState* ks,
+                                                   const double* __restrict__ sv, double* __restrict__ tv, KState* ks,
                                                    double* partials) {
   if (ks->done || ks->half) return;
-  constexpr int RPB = kBlock / G;
-  const int lane = threadIdx.x % G, sub = threadIdx.x / G;
   double acc[2] = {0.0, 0.0};
   int t0, t1;
-  tile_range((N + RPB - 1) / RPB, t0, t1);
+  tile_range((S.nsl + kBlock / 64 - 1) / (kBlock / 64), t0, t1);
   for (int t = t0; t < t1; ++t) {
-    const int i = t * RPB + sub;
-    if (i >= N) continue;
-    double q = 0.0;
-    const int e = rp[i + 1];
-    for (int k = rp[i] + lane; k < e; k += G) {
-      const int j = col[k];
-      q += A[k] * (dinv[j] * s[j]);
-    }
-    q = gsum<G>(q);
-    if (lane == 0) {
-      tv[i] = q;
-      acc[0] += q * s[i];
-      acc[1] += q * q;
-    }
+    const int s = wave_slice(t);
+    if (s >= S.nsl) continue;
+    const int i = s * 64 + (threadIdx.x & 63);
+    if (i >= S.N) continue;
+    const double q = sell_row<8>(S, dlt, A, s, i, [&](int j) { return dinv[j] * sv[j]; });
+    tv[i] = q;
+    acc[0] += q * sv[i];
+    acc[1] += q * q;
   }
   block_partials<2>(acc, 2, partials, blockIdx.x);
 }
@@ -2347,12 +2331,22 @@ void bicg_init(H* h, const BicgVec& b, double tol) {
 }
 
 void bicg_iter(H* h, const double* A, const double* dinv, const BicgVec& b) {
-  const int nr = row_grid(h, true), nv = vec_grid(h);
-  AFC_DISPATCH_G(h, k_bicg_v, nr, h->N, h->row_ptr, h->col, A, dinv, b.p, b.rhat, b.v, h->ks, h->partials);
+  const int nr = sell_grid(h, true), nv = vec_grid(h);
+  if (h->dlt16)
+    k_bicg_v<int16_t><<<nr, kBlock, 0, h->stream>>>(sell_view(h), static_cast<const int16_t*>(h->sl_dlt), A, dinv,
+                                                     b.p, b.rhat, b.v, h->ks, h->partials);
+  else
+    k_bicg_v<int32_t><<<nr, kBlock, 0, h->stream>>>(sell_view(h), static_cast<const int32_t*>(h->sl_dlt), A, dinv,
+                                                     b.p, b.rhat, b.v, h->ks, h->partials);
   finish(h, nr, 1, ACT_BICG_ALPHA);
   k_bicg_s<<<nv, kBlock, 0, h->stream>>>(h->N, b.r, b.v, b.s, h->ks, h->partials);
   finish(h, nv, 1, ACT_BICG_S);
-  AFC_DISPATCH_G(h, k_bicg_t, nr, h->N, h->row_ptr, h->col, A, dinv, b.s, b.t, h->ks, h->partials);
+  if (h->dlt16)
+    k_bicg_t<int16_t><<<nr, kBlock, 0, h->stream>>>(sell_view(h), static_cast<const int16_t*>(h->sl_dlt), A, dinv,
+                                                     b.s, b.t, h->ks, h->partials);
+  else
+    k_bicg_t<int32_t><<<nr, kBlock, 0, h->stream>>>(sell_view(h), static_cast<const int32_t*>(h->sl_dlt), A, dinv,
+                                                     b.s, b.t, h->ks, h->partials);
   finish(h, nr, 2, ACT_BICG_OMEGA);
   k_bicg_xr<<<nv, kBlock, 0, h->stream>>>(h->N, dinv, b.p, b.s, b.t, b.rhat, b.x, b.r, h->ks, h->partials);
   finish(h, nv, 2, ACT_BICG_RHO);
