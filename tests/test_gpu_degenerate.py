@@ -1,0 +1,162 @@
+"""Degenerate cases of the method on the GPU path (libafc through the C ABI),
+checked against the oracle and against what the mathematics fixes.
+
+- Every node a Dirichlet node: each system row is an identity row, the limiters
+  have no free row, and every scheme returns u_D.
+- A constant state with no source, no reaction and no Dirichlet node: the row
+  sums of K and D vanish (the shape functions sum to one), so the low-order
+  rate is zero up to rounding, every u_j - u_i is exactly zero, and the limited
+  schemes keep the state: explicit and Crank-Nicolson, FCT (Sec. 2.1) and MC
+  (Sec. 2.2).
+- Zero data: the stationary solve starts from a zero residual and stops at
+  once with u = 0, with no 0/0 in the Krylov start (beta = 0).
+"""
+import numpy as np
+import pytest
+
+from oracle import afc_oracle as O
+from paper_2110_15676_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+B = [0.8, 0.3, -0.5]
+CN_OPTS = dict(fp_tol=1e-14, fp_tol_mode=0, fp_maxit=100, lin_atol=1e-15, lin_rtol=0.0)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _afc():
+    from paper_2110_15676_amd import afc
+
+    return afc
+
+
+def _dev(x):
+    return torch.tensor(np.asarray(x, dtype=np.float64), device="cuda:0")
+
+
+def _opts(**kw):
+    o = _afc().afc_default_options(**kw)
+    o.stream = torch.cuda.current_stream().cuda_stream
+    return o
+
+
+def _all_dirichlet(n):
+    N = (n + 1) ** 3
+    return I.build("Q1", n, 1e-3, I.affine_field(B), 0.2, dirichlet=np.arange(N),
+                   dir_fn=lambda X: np.sin(3 * X[:, 0]) + X[:, 1] * X[:, 2])
+
+
+@pytest.mark.parametrize("prec,sstep", [(0, 0), (1, 0), (1, 8)])
+def test_every_node_dirichlet(prec, sstep):
+    """Q1 5^3 (216 nodes), all of them Dirichlet nodes."""
+    afc = _afc()
+    inst = _all_dirichlet(5)
+    uD = inst.u0
+    scale = np.abs(uD).max()
+    print("all-Dirichlet prec=%d sstep=%d N=%d" % (prec, sstep, inst.N), flush=True)
+    # stationary MCL from zero (the low-order start already lands on u_D)
+    h = afc.afc_create_instance(inst, _opts(precision=prec, sstep=sstep, fp_tol=1e-12, fp_tol_mode=1,
+                                            fp_maxit=50, lin_atol=0.0, lin_rtol=1e-14), conv=True)
+    try:
+        u = _dev(np.zeros(inst.N))
+        st, stats = afc.afc_solve_stationary(h, u, _dev(inst.F), init_low_order=True)
+        assert st == 0, stats
+        assert np.abs(u.cpu().numpy() - uD).max() <= 1e-12 * scale
+    finally:
+        afc.afc_destroy(h)
+    # one SSP-RK3 FCT step and one nonlinear CN-FCT step from u_D
+    P = O.problem_from_instance(inst, conv=False)
+    dt = 1e-3
+    h = afc.afc_create_instance(inst, _opts(precision=prec, sstep=sstep, krylov=1 if prec else 0, **CN_OPTS),
+                                conv=False)
+    try:
+        u = _dev(uD)
+        F = _dev(inst.F)
+        afc.afc_step_ssprk3(h, u, F, dt)
+        ref = O.ssp_rk3_step(P, uD, inst.F, dt)
+        assert np.abs(u.cpu().numpy() - ref).max() <= 1e-14 * scale
+        assert np.abs(u.cpu().numpy() - uD).max() <= 1e-14 * scale
+        u = _dev(uD)
+        st, stats = afc.afc_step_cn(h, u, F, F, dt)
+        assert st == 0, stats
+        assert np.abs(u.cpu().numpy() - uD).max() <= 1e-12 * scale
+    finally:
+        afc.afc_destroy(h)
+
+
+def _constant(n, c0=0.7):
+    return I.build("Q1", n, 1e-3, I.affine_field(B), 0.0, dirichlet="none", u0_fn=lambda X: c0 + 0.0 * X[:, 0])
+
+
+def test_constant_state_is_kept_by_explicit_schemes():
+    """Q1 8^3 (729 nodes), u = 0.7: SSP-RK3 with Zalesak's FCT and with the MC
+    limiter, ten steps each, against the oracle and the constant."""
+    afc = _afc()
+    inst = _constant(8)
+    dt = 2e-3
+    for conv, step, ref_step in ((False, "afc_step_ssprk3", O.ssp_rk3_step),
+                                 (True, "afc_step_mc_ssprk3", O.mc_ssp_rk3_step)):
+        P = O.problem_from_instance(inst, conv=conv)
+        print("constant state %s" % step, flush=True)
+        h = afc.afc_create_instance(inst, _opts(), conv=conv)
+        try:
+            u = _dev(inst.u0)
+            F = _dev(inst.F)
+            ref = inst.u0.copy()
+            for _ in range(10):
+                getattr(afc, step)(h, u, F, dt)
+                ref = ref_step(P, ref, inst.F, dt)
+            got = u.cpu().numpy()
+            assert np.abs(ref - 0.7).max() <= 1e-13
+            assert np.abs(got - ref).max() <= 1e-13
+        finally:
+            afc.afc_destroy(h)
+
+
+@pytest.mark.parametrize("krylov,prec,sstep", [(0, 0, 0), (1, 1, 8)])
+def test_constant_state_is_kept_by_crank_nicolson(krylov, prec, sstep):
+    """The same constant state through the nonlinear CN-FCT and MC+CN steps."""
+    afc = _afc()
+    inst = _constant(8)
+    dt = 2e-3
+    print("constant state CN krylov=%d prec=%d sstep=%d" % (krylov, prec, sstep), flush=True)
+    h = afc.afc_create_instance(inst, _opts(krylov=krylov, precision=prec, sstep=sstep, **CN_OPTS), conv=True)
+    try:
+        F = _dev(inst.F)
+        for name in ("afc_step_cn", "afc_step_mc_cn"):
+            u = _dev(inst.u0)
+            for _ in range(3):
+                st, stats = getattr(afc, name)(h, u, F, F, dt)
+                assert st == 0, (name, stats)
+            assert np.abs(u.cpu().numpy() - 0.7).max() <= 1e-12, name
+    finally:
+        afc.afc_destroy(h)
+
+
+@pytest.mark.parametrize("prec,sstep", [(0, 0), (1, 8)])
+def test_zero_data_stops_at_once(prec, sstep):
+    """F = 0 and u_D = 0 on Q1 6^3: the solution is zero, reached with no
+    Krylov iteration and no NaN."""
+    afc = _afc()
+    inst = I.build("Q1", 6, 1e-3, I.affine_field(B), 1.0, dirichlet="all")
+    assert not inst.F.any() and not inst.dir_val.any()
+    print("zero data prec=%d sstep=%d" % (prec, sstep), flush=True)
+    h = afc.afc_create_instance(inst, _opts(precision=prec, sstep=sstep, fp_tol=1e-12, fp_tol_mode=1, fp_maxit=20,
+                                            lin_atol=0.0, lin_rtol=1e-12), conv=True)
+    try:
+        u = _dev(np.zeros(inst.N))
+        st, stats = afc.afc_solve_stationary(h, u, _dev(inst.F), init_low_order=True)
+        assert st == 0, stats
+        got = u.cpu().numpy()
+        assert np.isfinite(got).all()
+        assert not got.any()
+        assert stats["krylov_iters"] == 0
+    finally:
+        afc.afc_destroy(h)
