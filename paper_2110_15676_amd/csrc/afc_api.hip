@@ -213,13 +213,21 @@ struct SolveOut {
 
 // The graph of the launches that `issue` makes on the handle's stream, keyed
 // by `key`: replayed from the handle's cache, or captured on the handle's
-// private capture stream (at most kGraphCache kept, the oldest dropped).
+// private capture stream.  At most kGraphCache are kept; a hit moves its entry
+// to the back and a capture drops the least recently used one, so the graphs
+// that one solve looks up back to back (GMRES holds two) stay alive.
 constexpr size_t kGraphCache = 8;
+static_assert(kGraphCache >= 2, "a GMRES solve holds two cached graphs at once");
 
 template <typename F>
 hipGraphExec_t cached_graph(afc_handle* h, const std::vector<const void*>& key, F&& issue) {
-  for (auto& e : h->graphs)
-    if (e.first == key) return e.second;
+  for (size_t k = 0; k < h->graphs.size(); ++k)
+    if (h->graphs[k].first == key) {
+      auto e = std::move(h->graphs[k]);
+      h->graphs.erase(h->graphs.begin() + (std::ptrdiff_t)k);
+      h->graphs.push_back(std::move(e));
+      return h->graphs.back().second;
+    }
   if (h->graphs.size() >= kGraphCache) {
     (void)hipGraphExecDestroy(h->graphs.front().second);
     h->graphs.erase(h->graphs.begin());

@@ -596,6 +596,33 @@ def test_sstep_failed_block_falls_back():
         afc.afc_destroy(h)
 
 
+def test_graph_cache_keeps_both_graphs_of_a_solve():
+    """A full graph cache (eight entries) with the one-vector cycle's graph the
+    oldest: the next s-step solve captures a new block graph, which must not
+    drop the one-vector graph that the fallback after a failed block replays."""
+    afc = _afc()
+    inst = I.config3(10)
+    ref, _ = _mcl_ref(inst, 1e-12, 1e-14)
+    base = dict(precision=1, fp_tol=1e-12, fp_tol_mode=1, fp_maxit=2000, lin_atol=0.0, lin_rtol=1e-14)
+    h = afc.afc_create_instance(inst, _opts(sstep=2, **base), conv=True)
+    try:
+        F = _dev(inst.F)
+        for s in range(2, 9):  # one block graph per s, next to the one-vector cycle graph
+            afc.afc_set_options(h, _opts(sstep=s, **base))
+            u = _dev(np.zeros(inst.N))
+            st, stats = afc.afc_solve_stationary(h, u, F, init_low_order=True)
+            assert st == 0, stats
+            assert _rel(u.cpu().numpy(), ref) <= 1e-8
+        # a shift that makes every block fail: one more block graph, then the fallback
+        afc.afc_set_options(h, _opts(sstep=5, sstep_shift=1e30, **base))
+        u = _dev(np.zeros(inst.N))
+        st, stats = afc.afc_solve_stationary(h, u, F, init_low_order=True)
+        assert st == 0, stats
+        assert _rel(u.cpu().numpy(), ref) <= 1e-8
+    finally:
+        afc.afc_destroy(h)
+
+
 def test_mcl_single_iteration_parity():
     """One fixed-point iteration from the same low-order start (fp_maxit = 1)."""
     afc = _afc()
