@@ -390,7 +390,9 @@ afc_status afc_server_wait(afc_server *s, int64_t id, double *u_out, afc_stats *
 /* Message of the last failed request or call (empty if none). */
 const char *afc_server_last_error(const afc_server *s);
 
-/* Stop the server: running requests finish, queued ones are dropped. */
+/* Stop the server: running requests finish, queued ones are dropped (their
+ * ids can no longer be waited for).  Call it once every other thread's
+ * submit and wait calls on s have returned; s is freed. */
 void afc_server_destroy(afc_server *s);
 
 /* Static description of a status code. */
