@@ -56,6 +56,13 @@ static __device__ __forceinline__ double wave_sum(double v) {
   return __hiloint2double(hi, lo);
 }
 
+// v of lane src (src the same for the whole wave)
+static __device__ __forceinline__ double lane_value(double v, int src) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+  return __hiloint2double(hi, lo);
+}
+
 // a + b after an exchange of halves between lanes l and l ^ 32: lanes 0..31
 // return a(l) + a(l + 32), lanes 32..63 return b(l - 32) + b(l)
 // (v_permlane32_swap, both 32-bit halves)

@@ -749,15 +749,22 @@ __global__ __launch_bounds__(kBlock) void k_sstep_sums(KState* ks, const double*
 }
 
 // Cholesky QR of the projected block, update coefficients, Hessenberg
-// columns k..k+s-1 and their Givens rotations (one workgroup).
+// columns k..k+s-1 and their Givens rotations (one workgroup).  The three
+// chains of the block (Cholesky factor, its inverse, the block's rotations)
+// run one column per lane of the first wave, with the pivots broadcast by
+// readlane; every entry is formed by the same operations in the same order as
+// a column-by-column loop on one thread would use.
 __global__ __launch_bounds__(kBlock) void k_sstep_small(KState* ks, int k, int s, int m, double theta) {
   constexpr int kRows = kMaxRestart + 1 + kSMax;
-  __shared__ double C[(kMaxRestart + 1) * kSMax];  // C[q s + j] = (V_q, W_{j+1})
+  constexpr int kHL = kMaxRestart * (kMaxRestart + 1);
+  constexpr int kHLU = (kHL + kBlock - 1) / kBlock;
+  constexpr int kBU = (kBlkRows + kBlock - 1) / kBlock;
+  __shared__ double B[kBlkRows];  // the block's reduced rows: C[q s + j] = (V_q, W_{j+1}), then W^T W
   __shared__ double G[kSMax * kSMax], R[kSMax * kSMax], Ri[kSMax * kSMax];
   __shared__ double Z[kRows * (kSMax + 1)];  // coordinates of W_0..W_s in [V_0..V_k, Q_1..Q_s]
   __shared__ double M1[kRows * kSMax];
   __shared__ double Hn[kRows * kSMax];       // new Hessenberg columns k..k+s-1
-  __shared__ double HL[kMaxRestart * (kMaxRestart + 1)];  // raw Hessenberg columns 0..k-1
+  __shared__ double HL[kHL];                 // raw Hessenberg columns 0..k-1
   __shared__ double gcs[kMaxRestart], gsn[kMaxRestart], gg[kMaxRestart + 1];  // rotations and rhs, staged
   __shared__ int ok, ncols, stop, nonfinite;
   const int was_done = ks->done;
@@ -767,82 +774,93 @@ __global__ __launch_bounds__(kBlock) void k_sstep_small(KState* ks, int k, int s
     return;
   }
   const int nv = k + 1, nr = nv + s;
-  for (int i = threadIdx.x; i < nv * s; i += blockDim.x) C[i] = ks->blk[i];
-  for (int i = threadIdx.x; i < k; i += blockDim.x) {
-    gcs[i] = ks->cs[i];
-    gsn[i] = ks->sn[i];
-  }
-  for (int i = threadIdx.x; i <= k; i += blockDim.x) gg[i] = ks->g[i];
-  for (int t = threadIdx.x; t < k * (k + 1); t += blockDim.x) {  // column c, rows 0..k
-    const int c = t / (k + 1), r = t % (k + 1);
-    HL[t] = r <= c + 1 ? ks->Hraw[(size_t)c * (m + 1) + r] : 0.0;
+  const int nrows = nv * s + s * (s + 1) / 2;
+  const double* C = B;
+  {  // every global read of the kernel in flight at once
+    double hv[kHLU], bv[kBU];
+#pragma unroll
+    for (int u = 0; u < kHLU; ++u) {
+      const int t = threadIdx.x + u * kBlock;
+      hv[u] = 0.0;
+      if (t < k * (k + 1)) {  // column c, rows 0..k
+        const int c = t / (k + 1), r = t % (k + 1);
+        if (r <= c + 1) hv[u] = ks->Hraw[(size_t)c * (m + 1) + r];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kBU; ++u) {
+      const int t = threadIdx.x + u * kBlock;
+      bv[u] = t < nrows ? ks->blk[t] : 0.0;
+    }
+    const int t = threadIdx.x;
+    double cs0 = 0.0, sn0 = 0.0, g0 = 0.0;
+    if (t < k) {
+      cs0 = ks->cs[t];
+      sn0 = ks->sn[t];
+    }
+    if (t <= k) g0 = ks->g[t];
+#pragma unroll
+    for (int u = 0; u < kHLU; ++u)
+      if (threadIdx.x + u * kBlock < k * (k + 1)) HL[threadIdx.x + u * kBlock] = hv[u];
+#pragma unroll
+    for (int u = 0; u < kBU; ++u)
+      if (threadIdx.x + u * kBlock < nrows) B[threadIdx.x + u * kBlock] = bv[u];
+    if (t < k) {
+      gcs[t] = cs0;
+      gsn[t] = sn0;
+    }
+    if (t <= k) gg[t] = g0;
   }
   __syncthreads();
   for (int t = threadIdx.x; t < s * s; t += blockDim.x) {  // G = W^T W - C^T C
     const int i = t / s, j = t % s;
-    double g = ks->blk[gram_row(nv, s, min(i, j), max(i, j))];
+    double g = B[gram_row(nv, s, min(i, j), max(i, j))];
     for (int q = 0; q < nv; ++q) g -= C[q * s + i] * C[q * s + j];
     G[t] = g;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {  // G = R^T R (R upper triangular) and R^{-1}, in registers
-    double g[kSMax][kSMax], r[kSMax][kSMax], ri[kSMax][kSMax];
+  // G = R^T R, R upper triangular: lane i holds column i of R; column j's
+  // pivot and entries are broadcast from lane j
+  if (threadIdx.x < 64) {
+    const int i = threadIdx.x;
+    double gc[kSMax], rc[kSMax];
 #pragma unroll
-    for (int i = 0; i < kSMax; ++i)
-#pragma unroll
-      for (int j = 0; j < kSMax; ++j) {
-        g[i][j] = (i < s && j < s) ? G[i * s + j] : 0.0;
-        r[i][j] = 0.0;
-        ri[i][j] = 0.0;
-      }
+    for (int p = 0; p < kSMax; ++p) {
+      gc[p] = (i < s && p < s) ? G[p * s + i] : 0.0;
+      rc[p] = 0.0;
+    }
     bool good = true;
 #pragma unroll
     for (int j = 0; j < kSMax; ++j) {
       if (j < s && good) {
-        double d = g[j][j];
+        double d = gc[j];
 #pragma unroll
-        for (int p = 0; p < j; ++p) d -= r[p][j] * r[p][j];
-        if (!(d > 0.0) || !isfinite(d)) {
+        for (int p = 0; p < j; ++p) d -= rc[p] * rc[p];
+        const double dj = lane_value(d, j);
+        if (!(dj > 0.0) || !isfinite(dj)) {
           good = false;
         } else {
-          const double rjj = sqrt(d);
-          r[j][j] = rjj;
+          const double rjj = sqrt(dj);
+          double rpj[kSMax];
 #pragma unroll
-          for (int i = j + 1; i < kSMax; ++i) {
-            if (i < s) {
-              double v = g[j][i];
+          for (int p = 0; p < j; ++p) rpj[p] = lane_value(rc[p], j);
+          if (i == j) {
+            rc[j] = rjj;
+          } else if (i > j && i < s) {
+            double v = gc[j];
 #pragma unroll
-              for (int p = 0; p < j; ++p) v -= r[p][j] * r[p][i];
-              r[j][i] = v / rjj;
-            }
+            for (int p = 0; p < j; ++p) v -= rpj[p] * rc[p];
+            rc[j] = v / rjj;
           }
         }
       }
     }
-    if (good) {
+    if (good && i < s) {
 #pragma unroll
-      for (int j = 0; j < kSMax; ++j) {  // R^{-1}, column by column
-        if (j < s) {
-          ri[j][j] = 1.0 / r[j][j];
-#pragma unroll
-          for (int i = j - 1; i >= 0; --i) {
-            double v = 0.0;
-#pragma unroll
-            for (int p = i + 1; p <= j; ++p) v += r[i][p] * ri[p][j];
-            ri[i][j] = -v / r[i][i];
-          }
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < kSMax; ++i)
-#pragma unroll
-        for (int j = 0; j < kSMax; ++j)
-          if (i < s && j < s) {
-            R[i * s + j] = r[i][j];
-            Ri[i * s + j] = ri[i][j];
-          }
+      for (int p = 0; p < kSMax; ++p)
+        if (p < s) R[p * s + i] = rc[p];
     }
-    ok = good;
+    if (i == 0) ok = good;
   }
   __syncthreads();
   if (!ok) {
@@ -853,6 +871,27 @@ __global__ __launch_bounds__(kBlock) void k_sstep_small(KState* ks, int k, int s
     }
     return;
   }
+  if (threadIdx.x < s) {  // R^{-1}: lane j solves for its column by back substitution
+    const int j = threadIdx.x;
+    const double djj = 1.0 / R[j * s + j];
+    double ric[kSMax];
+#pragma unroll
+    for (int p = 0; p < kSMax; ++p) ric[p] = p == j ? djj : 0.0;
+#pragma unroll
+    for (int i = kSMax - 2; i >= 0; --i) {
+      if (i < j) {
+        double v = 0.0;
+#pragma unroll
+        for (int p = i + 1; p < kSMax; ++p)
+          if (p <= j) v += R[i * s + p] * ric[p];
+        ric[i] = -v / R[i * s + i];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kSMax; ++i)
+      if (i < s) Ri[i * s + j] = ric[i];
+  }
+  __syncthreads();
   // update coefficients: Q = W R^{-1} - V (C R^{-1})
   for (int t = threadIdx.x; t < nv * s; t += blockDim.x) {
     const int q = t / s, j = t % s;
@@ -884,11 +923,18 @@ __global__ __launch_bounds__(kBlock) void k_sstep_small(KState* ks, int k, int s
     M1[t] = v;
   }
   __syncthreads();
-  for (int r = threadIdx.x; r < nr; r += blockDim.x) {  // Hn = M1 T^{-1}
-    for (int j = 0; j < s; ++j) {
-      double v = M1[r * s + j];
-      for (int i = 0; i < j; ++i) v -= Hn[r * s + i] * Z[(k + i) * (s + 1) + j];
-      Hn[r * s + j] = v / Z[(k + j) * (s + 1) + j];
+  if (threadIdx.x < nr) {  // Hn = M1 T^{-1}, one row per thread, the row in registers
+    const int r = threadIdx.x;
+    double h[kSMax];
+#pragma unroll
+    for (int j = 0; j < kSMax; ++j) {
+      if (j < s) {
+        double v = M1[r * s + j];
+#pragma unroll
+        for (int i = 0; i < j; ++i) v -= h[i] * Z[(k + i) * (s + 1) + j];
+        h[j] = v / Z[(k + j) * (s + 1) + j];
+        Hn[r * s + j] = h[j];
+      }
     }
   }
   __syncthreads();
@@ -898,11 +944,26 @@ __global__ __launch_bounds__(kBlock) void k_sstep_small(KState* ks, int k, int s
     if (r <= k + j + 1) ks->Hraw[(size_t)(k + j) * (m + 1) + r] = Hn[r * s + j];
   }
   __syncthreads();  // the raw columns are stored before the rotations change Hn
-  // rotations 0..k-1 of earlier blocks, one thread per new column
+  // rotations 0..k-1 of earlier blocks, one thread per new column, eight at a time
   for (int j = threadIdx.x; j < ns; j += blockDim.x) {
     double* col = Hn + j;  // column j of Hn, stride s
     double cur = col[0];
-    for (int jj = 0; jj < k; ++jj) {
+    int jj = 0;
+    for (; jj + 8 <= k; jj += 8) {
+      double nx[8], c8[8], s8[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        nx[u] = col[(jj + u + 1) * s];
+        c8[u] = gcs[jj + u];
+        s8[u] = gsn[jj + u];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        col[(jj + u) * s] = c8[u] * cur + s8[u] * nx[u];
+        cur = -s8[u] * cur + c8[u] * nx[u];
+      }
+    }
+    for (; jj < k; ++jj) {
       const double nxt = col[(jj + 1) * s];
       col[jj * s] = gcs[jj] * cur + gsn[jj] * nxt;
       cur = -gsn[jj] * cur + gcs[jj] * nxt;
@@ -910,47 +971,60 @@ __global__ __launch_bounds__(kBlock) void k_sstep_small(KState* ks, int k, int s
     col[k * s] = cur;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {  // rotations of this block, column by column
+  // rotations of this block: lane j holds rows k..k+s of new column j; at
+  // step t the rotation of column t (lane t's two leading rows, broadcast)
+  // is formed, stored, and applied to every later column
+  if (threadIdx.x < 64) {
+    const int j = threadIdx.x;
+    const bool mine = j < ns;
+    double v[kSMax + 1];
+#pragma unroll
+    for (int r = 0; r <= kSMax; ++r) v[r] = (mine && k + r < nr) ? Hn[(k + r) * s + j] : 0.0;
     const double tol = ks->tol;
-    int j = 0;
-    stop = 0;
-    nonfinite = 0;
-    for (; j < ns; ++j) {
-      const int c = k + j;
-      double* col = Hn + j;
-      double cur = col[k * s];
-      for (int jj = k; jj < c; ++jj) {
-        const double nxt = col[(jj + 1) * s];
-        col[jj * s] = gcs[jj] * cur + gsn[jj] * nxt;
-        cur = -gsn[jj] * cur + gcs[jj] * nxt;
-      }
-      const double hk1 = col[(c + 1) * s];
-      const double den = hypot(cur, hk1);
-      if (!isfinite(den)) {
-        nonfinite = 1;
-        stop = 1;
-        break;
-      }
-      if (den == 0.0) {  // the new direction adds nothing: keep the column as rotated
-        col[c * s] = cur;
-        stop = 1;
-        break;
-      }
-      const double cs = cur / den, sn = hk1 / den;
-      gcs[c] = cs;
-      gsn[c] = sn;
-      col[c * s] = den;
-      col[(c + 1) * s] = 0.0;
-      const double gk = gg[c];
-      gg[c + 1] = -sn * gk;
-      gg[c] = cs * gk;
-      if (fabs(gg[c + 1]) <= tol) {
-        ++j;
-        stop = 1;
-        break;
+    double gk = gg[k];
+    int st = 0, nf = 0, nc = 0;
+#pragma unroll
+    for (int t = 0; t < kSMax; ++t) {
+      if (t < ns && !st) {
+        const double cur = lane_value(v[t], t);
+        const double hk1 = lane_value(v[t + 1], t);
+        const double den = hypot(cur, hk1);
+        if (!isfinite(den)) {
+          nf = 1;
+          st = 1;
+        } else if (den == 0.0) {  // the new direction adds nothing: the column stays as rotated
+          st = 1;
+        } else {
+          const double cs = cur / den, sn = hk1 / den;
+          if (j == t) {
+            v[t] = den;
+            v[t + 1] = 0.0;
+          } else if (j > t && mine) {
+            const double a = v[t], b = v[t + 1];
+            v[t] = cs * a + sn * b;
+            v[t + 1] = -sn * a + cs * b;
+          }
+          const double gn = -sn * gk;
+          if (j == 0) {
+            gcs[k + t] = cs;
+            gsn[k + t] = sn;
+            gg[k + t + 1] = gn;
+            gg[k + t] = cs * gk;
+          }
+          gk = gn;
+          nc = t + 1;
+          if (fabs(gn) <= tol) st = 1;
+        }
       }
     }
-    ncols = j;  // columns completed by this block
+#pragma unroll
+    for (int r = 0; r <= kSMax; ++r)
+      if (mine && k + r < nr) Hn[(k + r) * s + j] = v[r];
+    if (j == 0) {
+      ncols = nc;  // columns completed by this block
+      stop = st;
+      nonfinite = nf;
+    }
   }
   __syncthreads();
   // write back the rotated columns, rotations and right-hand side
