@@ -1117,26 +1117,28 @@ __global__ __launch_bounds__(kBlock) void k_sstep_update(int N, int ldv, T* __re
   }
 }
 
-// back substitution R y = g over the columns completed in the cycle (one wave)
+// back substitution R y = g over the columns completed in the cycle (one
+// wave): lane j holds row j of R and g_j; y_i = g_i / R_ii, broadcast from
+// lane i, then g_j -= R_ji y_i on the rows above, for i from the last row up
 __global__ __launch_bounds__(64) void k_gmres_solve(KState* ks, int m) {
-  __shared__ double R[kMaxRestart][kMaxRestart + 1];
-  __shared__ double g[kMaxRestart];
+  static_assert(kMaxRestart <= 64, "one row of R per lane");
   if (ks->solved) return;
   const int kk = ks->k;
-  for (int e = threadIdx.x; e < kk * kk; e += 64) {
-    const int c = e / kk, row = e % kk;
-    R[row][c] = row <= c ? ks->H[(size_t)c * (m + 1) + row] : 0.0;
+  const int j = threadIdx.x;
+  double row[kMaxRestart];
+#pragma unroll
+  for (int c = 0; c < kMaxRestart; ++c)
+    row[c] = (j < kk && c < kk && c >= j) ? ks->H[(size_t)c * (m + 1) + j] : 0.0;
+  double gj = j < kk ? ks->g[j] : 0.0;
+#pragma unroll
+  for (int i = kMaxRestart - 1; i >= 0; --i) {
+    if (i < kk) {
+      const double yi = lane_value(gj, i) / lane_value(row[i], i);
+      if (j < i) gj -= row[i] * yi;
+      if (j == i) gj = yi;
+    }
   }
-  for (int i = threadIdx.x; i < kk; i += 64) g[i] = ks->g[i];
-  __syncthreads();
-  for (int i = kk - 1; i >= 0; --i) {
-    const double yi = g[i] / R[i][i];
-    __syncthreads();
-    for (int j = threadIdx.x; j < i; j += 64) g[j] -= R[j][i] * yi;
-    if (threadIdx.x == 0) g[i] = yi;
-    __syncthreads();
-  }
-  for (int i = threadIdx.x; i < kk; i += 64) ks->coef[i] = g[i] * ks->sc[i];
+  if (j < kk) ks->coef[j] = gj * ks->sc[j];
 }
 
 // End of an s-step cycle whose last block starts at kb with sb vectors: the
