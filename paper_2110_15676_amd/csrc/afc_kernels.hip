@@ -2365,8 +2365,10 @@ void gmres_last_givens(H* h, bool fp32, int k, int m) {
   finish(h, gmres_grid(h, fp32), 1, ACT_GIVENS, 0, k, m, 0, 0.0, 0.0, kNormRow);
 }
 
-// workgroups of the s-step projections (one 16-byte chunk per thread and vector)
-int sstep_grid(const H* h) { return vec16_grid(h, kBlock * 4); }
+// workgroups of the s-step projections (one 16-byte chunk per thread and
+// vector per pass): at most 1024, as many as stay resident at four waves per
+// SIMD, so that no workgroup starts late and runs its chunk alone at the end
+int sstep_grid(const H* h) { return std::min(vec16_grid(h, kBlock * 4), 1024); }
 
 void sstep_dots(H* h, int k, int s) {
   launch(h, AFC_KERNEL_DOTS, k_sstep_dots<float>, sstep_grid(h), kBlock, h->N, h->ldv, (const float*)h->V32, k, s,
