@@ -387,6 +387,11 @@ afc_status afc_server_submit(afc_server *s, const afc_request *req, int64_t *id)
  * request's status.  Each id can be waited for once. */
 afc_status afc_server_wait(afc_server *s, int64_t id, double *u_out, afc_stats *stats, double *times);
 
+/* Non-blocking completion check: *done = 1 once request id has finished
+ * (afc_server_wait then returns at once), 0 while it is queued or running.
+ * AFC_EINVAL for an unknown id or one already waited for. */
+afc_status afc_server_poll(afc_server *s, int64_t id, int32_t *done);
+
 /* Message of the last failed request or call (empty if none). */
 const char *afc_server_last_error(const afc_server *s);
 

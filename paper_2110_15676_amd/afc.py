@@ -71,7 +71,7 @@ EXPORTS = [
     "afc_default_options", "afc_create", "afc_set_options", "afc_step_ssprk3", "afc_step_cn",
     "afc_solve_stationary", "afc_destroy", "afc_status_str", "afc_last_error", "afc_kernel_time",
     "afc_batch_create", "afc_batch_offsets", "afc_batch_step_cn", "afc_batch_last_error", "afc_batch_destroy",
-    "afc_footprint_bytes", "afc_server_create", "afc_server_submit", "afc_server_wait", "afc_server_last_error",
+    "afc_footprint_bytes", "afc_server_create", "afc_server_submit", "afc_server_wait", "afc_server_poll", "afc_server_last_error",
     "afc_server_destroy", "afc_get_sell_info", "afc_get_krylov_sell_info", "afc_sell_layout", "afc_kernel_work",
     "afc_batch_set_schedule", "afc_batch_get_schedule", "afc_batch_autotune", "afc_step_cn_linear",
     "afc_step_mc_ssprk3", "afc_step_mc_cn",
@@ -146,6 +146,8 @@ def lib():
         L.afc_server_submit.restype = c_int32
         L.afc_server_wait.argtypes = [c_void_p, c_int64, c_void_p, POINTER(afc_stats), POINTER(c_double)]
         L.afc_server_wait.restype = c_int32
+        L.afc_server_poll.argtypes = [c_void_p, c_int64, POINTER(c_int32)]
+        L.afc_server_poll.restype = c_int32
         L.afc_server_last_error.argtypes = [c_void_p]
         L.afc_server_last_error.restype = c_char_p
         L.afc_server_destroy.argtypes = [c_void_p]
@@ -521,6 +523,15 @@ def afc_server_wait(s, rid, n):
     times = (c_double * 3)()
     st = lib().afc_server_wait(s, int(rid), u.ctypes.data, ctypes.byref(stats), times)
     return st, u, stats.as_dict(), tuple(times)
+
+
+def afc_server_poll(s, rid):
+    """True once request rid has finished (non-blocking)."""
+    done = c_int32()
+    st = lib().afc_server_poll(s, int(rid), ctypes.byref(done))
+    if st != AFC_OK:
+        raise AFCError(st, "unknown request id %d" % int(rid))
+    return bool(done.value)
 
 
 def afc_server_destroy(s):

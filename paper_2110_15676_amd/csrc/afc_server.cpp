@@ -303,6 +303,15 @@ afc_status afc_server_wait(afc_server* s, int64_t id, double* u_out, afc_stats* 
   return r->status;
 }
 
+afc_status afc_server_poll(afc_server* s, int64_t id, int32_t* done) {
+  if (!s || !done) return AFC_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->all.find(id);
+  if (it == s->all.end()) return AFC_EINVAL;
+  *done = it->second->done ? 1 : 0;
+  return AFC_OK;
+}
+
 const char* afc_server_last_error(const afc_server* s) { return s ? s->last_error.c_str() : ""; }
 
 void afc_server_destroy(afc_server* s) {

@@ -79,6 +79,36 @@ def test_server_alone_equals_mix_and_direct_calls():
             afc.afc_destroy(h)
 
 
+def test_server_poll_reports_completion_without_blocking():
+    """Two requests in one slot: polling the second returns at once until it
+    reports completion; by then the first (ahead of it in the one slot) has
+    finished too; an id already waited for is rejected."""
+    import time
+
+    afc = _afc()
+    reqs, insts = _requests()
+    s = afc.afc_server_create(1, 1 << 40)
+    try:
+        ids = []
+        for r, inst in zip(reqs[:2], insts[:2]):
+            kind = afc.AFC_REQ_CN if r["kind"] == "cn" else afc.AFC_REQ_STATIONARY
+            ids.append(afc.afc_server_submit(s, kind, inst, _opts(afc, r["kind"]),
+                                             u0=inst.u0 if r["kind"] == "cn" else None, dt=1e-3, steps=3,
+                                             conv=r["kind"] == "mcl"))
+        deadline = time.time() + 100.0
+        while not afc.afc_server_poll(s, ids[1]):
+            assert time.time() < deadline
+            time.sleep(0.01)
+        assert afc.afc_server_poll(s, ids[0])  # one slot, arrival order: the first finished before
+        for rid, inst in zip(ids, insts[:2]):
+            st, u, _, _ = afc.afc_server_wait(s, rid, inst.N)
+            assert st >= 0 and np.isfinite(u).all()
+        with pytest.raises(afc.AFCError):
+            afc.afc_server_poll(s, ids[0])
+    finally:
+        afc.afc_server_destroy(s)
+
+
 def test_server_budget_serializes_requests():
     afc = _afc()
     reqs, insts = _requests()
