@@ -596,6 +596,35 @@ def test_sstep_failed_block_falls_back():
         afc.afc_destroy(h)
 
 
+@pytest.mark.parametrize("restart,inner,sstep,prec", [
+    (64, 300, 0, 0),  # the longest cycle the device state holds, FP64
+    (64, 300, 0, 1),  # the same in FP32 inner / FP64 outer
+    (64, 300, 8, 1),  # eight full s-step blocks
+    (64, 300, 5, 1),  # twelve blocks of 5 and a last block of 4
+    (5, 300, 8, 1),   # a block cut to the cycle: one block of 5
+    (12, 300, 8, 1),  # blocks of 8 and 4
+    (30, 10, 8, 1),   # the inner step cap shortens the cycle to 10: blocks of 8 and 2
+])
+def test_gmres_restart_lengths(restart, inner, sstep, prec):
+    """GMRES cycles from 5 to the 64-vector limit, with and without s-step
+    blocks, on the stationary MCL workload at 10^3: the same solution as the
+    oracle."""
+    afc = _afc()
+    inst = I.config3(10)
+    ref, _ = _mcl_ref(inst, 1e-12, 1e-14)
+    print("restart=%d inner=%d sstep=%d prec=%d" % (restart, inner, sstep, prec), flush=True)
+    h = afc.afc_create_instance(inst, _opts(precision=prec, restart=restart, inner_maxit=inner, sstep=sstep,
+                                            fp_tol=1e-12, fp_tol_mode=1, fp_maxit=2000, lin_atol=0.0,
+                                            lin_rtol=1e-14), conv=True)
+    try:
+        u = _dev(np.zeros(inst.N))
+        st, stats = afc.afc_solve_stationary(h, u, _dev(inst.F), init_low_order=True)
+        assert st == 0, stats
+        assert _rel(u.cpu().numpy(), ref) <= (1e-10 if prec == 0 else 1e-8)
+    finally:
+        afc.afc_destroy(h)
+
+
 def test_graph_cache_keeps_both_graphs_of_a_solve():
     """A full graph cache (eight entries) with the one-vector cycle's graph the
     oldest: the next s-step solve captures a new block graph, which must not
