@@ -670,6 +670,78 @@ def test_mcl_single_iteration_parity():
         afc.afc_destroy(h)
 
 
+def test_int32_delta_layouts():
+    """Renumbered meshes of 35937 nodes put column offsets beyond 16 bits, so
+    every SELL kernel runs its 32-bit-delta form: one MCL fixed-point iteration
+    (FP64, and mixed with s-step blocks), two MU iterations, one SSP-RK3 step
+    with Zalesak's FCT and with MC, and three CN-FCT and MC+CN fixed-point
+    iterations with BiCGStab, each against the oracle."""
+    afc = _afc()
+    inst = I.renumbered(I.config3(32))
+    P = O.problem_from_instance(inst, conv=True)
+    lo = O.low_order_solution(P, inst.F, lin_rtol=1e-14)
+    ref, _ = O.stationary_mcl(P, inst.F, lo.x, tol=0.0, tol_mode="rel", maxit=1, lin_rtol=1e-14)
+    for prec, sstep in ((0, 0), (1, 8)):
+        print("int32 deltas: mcl prec=%d sstep=%d N=%d" % (prec, sstep, inst.N), flush=True)
+        h = afc.afc_create_instance(inst, _opts(precision=prec, sstep=sstep, fp_tol=0.0, fp_tol_mode=1, fp_maxit=1,
+                                                lin_atol=0.0, lin_rtol=1e-14), conv=True)
+        try:
+            assert afc.afc_get_sell_info(h)["delta_bytes"] == 4
+            assert afc.afc_get_krylov_sell_info(h)["delta_bytes"] == 4
+            u = _dev(lo.x)
+            st, stats = afc.afc_solve_stationary(h, u, _dev(inst.F), raise_on_error=False)
+            assert st >= 0 and stats["fp_iters"] == 1, stats
+            assert _rel(u.cpu().numpy(), ref) <= (1e-10 if prec == 0 else 1e-8)
+        finally:
+            afc.afc_destroy(h)
+    ref, _ = O.stationary_mu(P, inst.F, np.zeros(inst.N), tol=0.0, tol_mode="rel", maxit=2, lin_rtol=1e-14)
+    print("int32 deltas: mu N=%d" % inst.N, flush=True)
+    h = afc.afc_create_instance(inst, _opts(limiter=afc.AFC_LIMITER_MU, fp_tol=0.0, fp_tol_mode=1, fp_maxit=2,
+                                            lin_atol=0.0, lin_rtol=1e-14), conv=True)
+    try:
+        u = _dev(np.zeros(inst.N))
+        st, stats = afc.afc_solve_stationary(h, u, _dev(inst.F), raise_on_error=False)
+        assert st >= 0 and stats["fp_iters"] == 2, stats
+        assert _rel(u.cpu().numpy(), ref) <= 1e-10
+    finally:
+        afc.afc_destroy(h)
+    inst = I.renumbered(I.config2(32))
+    dt = inst.params["dt"]
+    for conv, step, ref_step in ((False, "afc_step_ssprk3", O.ssp_rk3_step),
+                                 (True, "afc_step_mc_ssprk3", O.mc_ssp_rk3_step)):
+        print("int32 deltas: %s" % step, flush=True)
+        P = O.problem_from_instance(inst, conv=conv)
+        h = afc.afc_create_instance(inst, _opts(), conv=conv)
+        try:
+            assert afc.afc_get_sell_info(h)["delta_bytes"] == 4
+            u = _dev(inst.u0)
+            getattr(afc, step)(h, u, _dev(inst.F), dt)
+            assert _rel(u.cpu().numpy(), ref_step(P, inst.u0, inst.F, dt)) <= 1e-12
+        finally:
+            afc.afc_destroy(h)
+    inst = I.renumbered(I.config1(32))
+    P = O.problem_from_instance(inst, conv=False)
+    dt = inst.params["dt"]
+    ref, _ = O.cn_fct_step(P, inst.u0, inst.F, inst.F, dt, tol=0.0, tol_mode="abs", maxit=3, lin="bicgstab",
+                           lin_atol=1e-15)
+    Pc = O.problem_from_instance(inst, conv=True)
+    ref_mc, _ = O.mc_cn_step(Pc, inst.u0, inst.F, inst.F, dt, tol=0.0, tol_mode="abs", maxit=3, lin="bicgstab",
+                             lin_atol=1e-15)
+    print("int32 deltas: cn and mc+cn bicgstab N=%d" % inst.N, flush=True)
+    h = afc.afc_create_instance(inst, _opts(krylov=0, precision=0, fp_tol=0.0, fp_tol_mode=0, fp_maxit=3,
+                                            lin_atol=1e-15, lin_rtol=0.0), conv=True)
+    try:
+        assert afc.afc_get_sell_info(h)["delta_bytes"] == 4
+        F = _dev(inst.F)
+        for name, r in (("afc_step_cn", ref), ("afc_step_mc_cn", ref_mc)):
+            u = _dev(inst.u0)
+            st, stats = getattr(afc, name)(h, u, F, F, dt, raise_on_error=False)
+            assert st >= 0 and stats["fp_iters"] == 3, (name, stats)
+            assert _rel(u.cpu().numpy(), r) <= 1e-10, name
+    finally:
+        afc.afc_destroy(h)
+
+
 def test_nan_input_is_reported():
     afc = _afc()
     inst = I.config3(6)
