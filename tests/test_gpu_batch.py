@@ -134,6 +134,20 @@ def test_batch_rejects_gmres_options():
     assert e.value.status == afc.AFC_EINVAL
 
 
+def test_batch_rejects_offsets_beyond_16_bits():
+    """The batch stores 16-bit column offsets; an instance whose renumbered
+    pattern needs more is refused with EINVAL and a message naming it, before
+    any launch."""
+    afc = _afc()
+    big = I.renumbered(I.config4_instance(I.config4_params(1, 32, 32)[0]))
+    assert big.N > 32768
+    insts = _mixed_instances(2, 5) + [big]
+    with pytest.raises(afc.AFCError) as e:
+        afc.afc_batch_create(insts, _opts())
+    assert e.value.status == afc.AFC_EINVAL
+    assert "instance 2" in str(e.value) or "16-bit" in str(e.value)
+
+
 def test_batch_results_identical_under_every_schedule():
     """Workgroup size and workgroup count change only the speed: every
     instance ends bitwise the same under each schedule, and alone (with a

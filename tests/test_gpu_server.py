@@ -1,6 +1,8 @@
 """Request server (continuous batching) through the C ABI: results are the
 same alone and in the mix, they match the direct entry points, and the HBM
 budget limits how many requests run at once."""
+import copy
+
 import numpy as np
 import pytest
 
@@ -105,6 +107,35 @@ def test_server_poll_reports_completion_without_blocking():
             assert st >= 0 and np.isfinite(u).all()
         with pytest.raises(afc.AFCError):
             afc.afc_server_poll(s, ids[0])
+    finally:
+        afc.afc_server_destroy(s)
+
+
+def test_server_failed_request_reports_and_others_run():
+    """A request whose mass matrix holds a NaN fails in its worker: its wait
+    returns the error status with a message, and the requests around it in
+    the same slot still finish with the results they get alone."""
+    afc = _afc()
+    reqs, insts = _requests()
+    bad = copy.deepcopy(insts[1])
+    bad.M = bad.M.copy()
+    bad.M[3] = np.nan
+    order = [(reqs[0], insts[0]), (reqs[1], bad), (reqs[2], insts[2])]
+    s = afc.afc_server_create(1, 1 << 40)
+    try:
+        ids = []
+        for r, inst in order:
+            kind = afc.AFC_REQ_CN if r["kind"] == "cn" else afc.AFC_REQ_STATIONARY
+            ids.append(afc.afc_server_submit(s, kind, inst, _opts(afc, r["kind"]),
+                                             u0=inst.u0 if r["kind"] == "cn" else None, dt=1e-3, steps=3,
+                                             conv=r["kind"] == "mcl"))
+        out = [afc.afc_server_wait(s, rid, inst.N) for rid, (_, inst) in zip(ids, order)]
+        assert out[1][0] < 0
+        assert afc.lib().afc_server_last_error(s).decode() != ""
+        alone = _run(afc, [reqs[0], reqs[2]], [insts[0], insts[2]], 1, 1 << 40)
+        for k, a in ((0, alone[0]), (2, alone[1])):
+            assert out[k][0] >= 0
+            assert np.array_equal(out[k][1], a[1]), k
     finally:
         afc.afc_server_destroy(s)
 
