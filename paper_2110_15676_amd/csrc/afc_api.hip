@@ -443,37 +443,40 @@ SolveOut solve_bicgstab(afc_handle* h, const SysMat& S, const double* b, double*
   sync_status(h);
   const int it0 = h->host_status->iters;
   int restarts = 0;
+  // iterations of the first chunk: about what the previous solve on this
+  // handle took (a power of two in 2..16); iterations past convergence find
+  // the state done and return at once
+  int first = 2;
+  while (first < std::min(h->bicg_last, 16)) first *= 2;
   while (true) {
+    // no wait after the start: a non-finite start marks the state done, so
+    // the chunk's iterations return at once and the status read after the
+    // chunk reports it
     afc::bicg_init(h, v, tol);
-    sync_status(h);
-    if (h->host_status->flag == 2) {
-      o.st = AFC_ENAN;
-      o.res = h->host_status->res;
-      break;
-    }
-    int chunk = 2;
-    while (!h->host_status->done && h->host_status->iters - it0 < h->opt.lin_maxit) {
+    int chunk = first;
+    do {
       const int n = std::min<int>(chunk, h->opt.lin_maxit - (h->host_status->iters - it0));
+      // the chunk's iterations, then the true residual b - A x of its iterate
+      // into t (every iteration writes t before reading it) with its norm
       auto iters = [&]() {
         for (int c = 0; c < n; ++c) afc::bicg_iter(h, S.S64, S.dinv, v);
+        afc::residual(h, S.S64, b, x, v.t, 0);
       };
       if (h->opt.graphs && !h->opt.profile)
-        HIP_OK(hipGraphLaunch(cached_graph(h, {key_int(2), S.S64, S.dinv, x, r, key_int(n)}, iters), h->stream));
+        HIP_OK(hipGraphLaunch(cached_graph(h, {key_int(4), S.S64, S.dinv, b, x, r, key_int(n)}, iters), h->stream));
       else
         iters();
       sync_status(h);
       chunk = std::min(chunk * 2, 16);
-    }
+    } while (!h->host_status->done && h->host_status->iters - it0 < h->opt.lin_maxit);
+    h->bicg_last = h->host_status->iters - it0;
     if (h->host_status->flag == 2) {
       o.st = AFC_ENAN;
       o.res = h->host_status->res;
       break;
     }
     const bool breakdown = h->host_status->flag == 1;
-    // confirm on the true residual
-    afc::residual(h, S.S64, b, x, r, 0);
-    sync_status(h);
-    const double res = std::sqrt(h->host_status->red[0]);
+    const double res = std::sqrt(h->host_status->red[0]);  // the true residual of the last iterate
     o.res = res;
     if (!std::isfinite(res)) {
       o.st = AFC_ENAN;
@@ -488,6 +491,7 @@ SolveOut solve_bicgstab(afc_handle* h, const SysMat& S, const double* b, double*
       o.st = AFC_ENOCONV;
       break;
     }
+    afc::residual(h, S.S64, b, x, r, 0);  // restart from the true residual
   }
   o.iters = h->host_status->iters - it0;
   return o;

@@ -141,6 +141,7 @@ struct afc_handle_s {
   float* V32 = nullptr;   // (m+1) x N
   int Vm = 0;
   int ldv = 0;  // basis / work vector stride: N rounded up to 64 (16-byte aligned rows)
+  int bicg_last = 2;  // BiCGStab iterations of the handle's last solve (first chunk size)
   double* partials = nullptr;  // kMaxRed * kRedBlocks
   double* partials_res = nullptr;  // one per workgroup of the FP64 SELL residual
   double* partials_blk = nullptr;  // kBlkRows * kRedBlocks (s-step GMRES, allocated on first use)
