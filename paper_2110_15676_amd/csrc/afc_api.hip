@@ -440,7 +440,8 @@ SolveOut solve_gmres(afc_handle* h, const SysMat& S, const double* b, double* x,
 SolveOut solve_bicgstab(afc_handle* h, const SysMat& S, const double* b, double* x, double* r, double tol) {
   SolveOut o;
   afc::BicgVec v{x, r, h->w[W_RHAT], h->w[W_P], h->w[W_V], h->w[W_S], h->w[W_T]};
-  sync_status(h);
+  // no status read here: only Krylov kernels change the device's iteration
+  // count and every solve ends with a status read, so the host copy is current
   const int it0 = h->host_status->iters;
   int restarts = 0;
   // iterations of the first chunk: about what the previous solve on this
