@@ -132,15 +132,15 @@ def test_ssp_full_size_step_and_invariants():
 CN_PARITY = dict(fp_tol=1e-14, fp_tol_mode=0, fp_maxit=100, lin_atol=1e-15, lin_rtol=0.0)
 
 
-@pytest.mark.parametrize("krylov,prec", [(0, 0), (1, 0), (1, 1)])
-def test_cn_config1_parity(krylov, prec):
+@pytest.mark.parametrize("krylov,prec,sstep", [(0, 0, 0), (1, 0, 0), (1, 1, 0), (1, 1, 8)])
+def test_cn_config1_parity(krylov, prec, sstep):
     """The CN workload (P1 8^3, 729 nodes): 10 steps against the oracle."""
     afc = _afc()
     inst = I.config1()
     P = O.problem_from_instance(inst, conv=False)
     dt = inst.params["dt"]
-    print("cn config1 krylov=%d prec=%d" % (krylov, prec), flush=True)
-    h = afc.afc_create_instance(inst, _opts(krylov=krylov, precision=prec, **CN_PARITY), conv=False)
+    print("cn config1 krylov=%d prec=%d sstep=%d" % (krylov, prec, sstep), flush=True)
+    h = afc.afc_create_instance(inst, _opts(krylov=krylov, precision=prec, sstep=sstep, **CN_PARITY), conv=False)
     try:
         u = _dev(inst.u0)
         F = _dev(inst.F)
@@ -156,15 +156,15 @@ def test_cn_config1_parity(krylov, prec):
         afc.afc_destroy(h)
 
 
-@pytest.mark.parametrize("krylov,prec", [(0, 0), (1, 0), (1, 1)])
-def test_cn_linear_parity(krylov, prec):
+@pytest.mark.parametrize("krylov,prec,sstep", [(0, 0, 0), (1, 0, 0), (1, 1, 0), (1, 1, 8)])
+def test_cn_linear_parity(krylov, prec, sstep):
     """Linear Zal+CN on the CN workload (P1 8^3): 10 steps against the oracle."""
     afc = _afc()
     inst = I.config1()
     P = O.problem_from_instance(inst, conv=False)
     dt = inst.params["dt"]
-    print("cn linear config1 krylov=%d prec=%d" % (krylov, prec), flush=True)
-    h = afc.afc_create_instance(inst, _opts(krylov=krylov, precision=prec, **CN_PARITY), conv=False)
+    print("cn linear config1 krylov=%d prec=%d sstep=%d" % (krylov, prec, sstep), flush=True)
+    h = afc.afc_create_instance(inst, _opts(krylov=krylov, precision=prec, sstep=sstep, **CN_PARITY), conv=False)
     try:
         u = _dev(inst.u0)
         F = _dev(inst.F)
@@ -388,15 +388,15 @@ def test_mc_ssp_alpha_modes(mode, name):
         afc.afc_destroy(h)
 
 
-@pytest.mark.parametrize("krylov,prec", [(0, 0), (1, 0), (1, 1)])
-def test_mc_cn_parity(krylov, prec):
+@pytest.mark.parametrize("krylov,prec,sstep", [(0, 0, 0), (1, 0, 0), (1, 1, 0), (1, 1, 8)])
+def test_mc_cn_parity(krylov, prec, sstep):
     """MC+CN on the CN workload (P1 8^3): 5 steps against the oracle."""
     afc = _afc()
     inst = I.config1()
     P = O.problem_from_instance(inst, conv=True)
     dt = inst.params["dt"]
-    print("mc cn krylov=%d prec=%d" % (krylov, prec), flush=True)
-    h = afc.afc_create_instance(inst, _opts(krylov=krylov, precision=prec, **CN_PARITY), conv=True)
+    print("mc cn krylov=%d prec=%d sstep=%d" % (krylov, prec, sstep), flush=True)
+    h = afc.afc_create_instance(inst, _opts(krylov=krylov, precision=prec, sstep=sstep, **CN_PARITY), conv=True)
     try:
         u = _dev(inst.u0)
         F = _dev(inst.F)
@@ -421,8 +421,8 @@ def test_mc_cn_parity(krylov, prec):
         afc.afc_destroy(h)
 
 
-@pytest.mark.parametrize("prec", [0, 1])
-def test_mu_stationary_parity(prec):
+@pytest.mark.parametrize("prec,sstep", [(0, 0), (1, 0), (1, 8)])
+def test_mu_stationary_parity(prec, sstep):
     """Stationary MU limiter (Sec. 3.2) on the stationary workload at 12^3,
     solved to convergence on both sides."""
     afc = _afc()
@@ -430,9 +430,9 @@ def test_mu_stationary_parity(prec):
     P = O.problem_from_instance(inst, conv=True)
     ref, rst = O.stationary_mu(P, inst.F, np.zeros(inst.N), tol=1e-12, tol_mode="rel", maxit=3000, lin_rtol=1e-14)
     assert rst.status == 0
-    print("mu n=12 prec=%d oracle fp its %d" % (prec, rst.iters), flush=True)
-    h = afc.afc_create_instance(inst, _opts(precision=prec, limiter=afc.AFC_LIMITER_MU, fp_tol=1e-12, fp_tol_mode=1,
-                                            fp_maxit=3000, lin_atol=0.0, lin_rtol=1e-14), conv=True)
+    print("mu n=12 prec=%d sstep=%d oracle fp its %d" % (prec, sstep, rst.iters), flush=True)
+    h = afc.afc_create_instance(inst, _opts(precision=prec, sstep=sstep, limiter=afc.AFC_LIMITER_MU, fp_tol=1e-12,
+                                            fp_tol_mode=1, fp_maxit=3000, lin_atol=0.0, lin_rtol=1e-14), conv=True)
     try:
         u = _dev(np.zeros(inst.N))
         st, stats = afc.afc_solve_stationary(h, u, _dev(inst.F))
