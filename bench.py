@@ -214,8 +214,9 @@ def bench_time_dependent(afc, torch, I, n, ssp_steps, cn_steps):
             el = time.perf_counter() - t0
         finally:
             afc.afc_destroy(h)
+        # u0 lies in [0, 1]; the limited explicit schemes keep the iterate there
         out[name] = {"ms_per_step": 1e3 * el / ssp_steps, "dof_stages_per_s": 3 * inst.N * ssp_steps / el,
-                     "steps": ssp_steps}
+                     "steps": ssp_steps, "range": [float(u.min()), float(u.max())]}
     oc = afc.afc_default_options(krylov=afc.AFC_KRYLOV_BICGSTAB, fp_tol=1e-8, fp_tol_mode=afc.AFC_TOL_REL,
                                  fp_maxit=50, lin_atol=0.0, lin_rtol=1e-10)
     oc.stream = o.stream
@@ -235,7 +236,7 @@ def bench_time_dependent(afc, torch, I, n, ssp_steps, cn_steps):
     finally:
         afc.afc_destroy(h)
     out["mc_cn"] = {"ms_per_step": 1e3 * el / cn_steps, "dof_iterations_per_s": inst.N * fp / el,
-                    "fp_iters_per_step": fp / cn_steps, "steps": cn_steps}
+                    "fp_iters_per_step": fp / cn_steps, "steps": cn_steps, "range": [float(u.min()), float(u.max())]}
     return out
 
 
@@ -585,6 +586,10 @@ def main():
     ms_per_step = 1e3 * elapsed / args.steps
     model_bytes = step_model_bytes(N, info, kinfo, s["krylov_iters"], s["refine_sweeps"], args.steps, args.sstep)
     print("bench: %.1f ms/step, %d Krylov its" % (ms_per_step, s["krylov_iters"]), file=sys.stderr, flush=True)
+    # extremes of the iterate after the timed steps (reported, not asserted:
+    # with c = 1 the discrete maximum principle of the eps = 0, c = 0 steady
+    # state does not apply)
+    u_range = {"min": float(u.min()), "max": float(u.max())}
 
     # --- the same steps again with per-kernel HIP events (roofline) ----------
     afc.afc_set_options(h, opts(fp_maxit=args.steps, profile=1))
@@ -725,6 +730,7 @@ def main():
         "dof_krylov_its_per_s": N * s["krylov_iters"] / elapsed,
         "hbm_gbs_model": model_bytes / elapsed / 1e9,
         "nonlinear_residual": {"first": s["res0"], "last": s["res"]},
+        "solution_range": u_range,
         "fp64": fp64,
         "classical_arnoldi": classical,
         "mu_limiter": mu,
