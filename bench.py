@@ -533,7 +533,7 @@ def main():
         traffic_summarize(*args.traffic_summarize, args.n)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
     if args.traffic_probe:
         traffic_probe(args.n, args.sstep)
