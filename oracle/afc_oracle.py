@@ -424,11 +424,21 @@ def _fp_converged(R, R0, N, tol, tol_mode):
 
 
 def _next_omega(omega, R, R_prev, dynamic):
+    """Dynamic damping of the Sec. 4 fixed point (the rule itself is only cited
+    there; reading): halve omega, not below 1/64, when the residual grew since
+    the previous iteration, otherwise omega <- min(1, 1.25 omega).  Fixed omega
+    without the dynamic rule and at the first iteration."""
     if not dynamic or R_prev is None:
         return omega
     if R > R_prev:
         return max(omega * 0.5, 1.0 / 64.0)
     return min(1.0, omega * 1.25)
+
+
+def _relax(u, w, omega):
+    """Damped fixed-point update u^{nu+1} = u^nu + omega (w - u^nu), with w the
+    solution of the fixed-point matrix system (Sec. 4; relaxation reading)."""
+    return u + omega * (w - u)
 
 
 # ----------------------------------------------------------------------------
@@ -510,7 +520,7 @@ def cn_fct_step(P: AFCProblem, u_old, F_old, F_new, dt, *, alpha_mode="limited",
             st.status = kr.status
             u = kr.x
             break
-        u = u + w_omega * (kr.x - u)
+        u = _relax(u, kr.x, w_omega)
         R_prev = R
         nu += 1
     st.iters = nu
@@ -618,7 +628,7 @@ def stationary_mcl(P: AFCProblem, F, u0, *, alpha_mode="limited", tol=1e-8, tol_
             st.status = kr.status
             u = kr.x
             break
-        u = u + w_omega * (kr.x - u)
+        u = _relax(u, kr.x, w_omega)
         R_prev = R
         nu += 1
     st.iters = nu
@@ -700,7 +710,7 @@ def stationary_mu(P: AFCProblem, F, u0, *, alpha_mode="limited", tol=1e-8, tol_m
             st.status = kr.status
             u = kr.x
             break
-        u = u + w_omega * (kr.x - u)
+        u = _relax(u, kr.x, w_omega)
         R_prev = R
         nu += 1
     st.iters = nu
@@ -801,7 +811,7 @@ def mc_cn_step(P: AFCProblem, u_old, F_old, F_new, dt, *, alpha_mode="limited", 
             st.status = kr.status
             u = kr.x
             break
-        u = u + w_omega * (kr.x - u)
+        u = _relax(u, kr.x, w_omega)
         R_prev = R
         nu += 1
     st.iters = nu

@@ -67,6 +67,25 @@ MUTATIONS = {
     # MC+CN: the old level's correction without its factor 1/2
     "mc_cn_old_half": ("        + 0.5 * mc_correction(P, u_old, udot_old, d, alpha_mode)",
                        "        + mc_correction(P, u_old, udot_old, d, alpha_mode)"),
+    # Shu-Osher SSP-RK3: second-stage weights swapped
+    "rk3_stage2_weights": ("u2 = 0.75 * u + 0.25 * fe_ssp_stage(P, u1, F, dt, alpha_mode)",
+                           "u2 = 0.25 * u + 0.75 * fe_ssp_stage(P, u1, F, dt, alpha_mode)"),
+    # Shu-Osher SSP-RK3: final weights swapped
+    "rk3_final_weights": ("return (1.0 / 3.0) * u + (2.0 / 3.0) * fe_ssp_stage(P, u2, F, dt, alpha_mode)",
+                          "return (2.0 / 3.0) * u + (1.0 / 3.0) * fe_ssp_stage(P, u2, F, dt, alpha_mode)"),
+    # Heun's form of Sec. 2.1.2: not the plain average of u^{n,0} and u^{n,2}
+    "heun_average_weights": ("return 0.5 * (u + u2)", "return 0.4 * u + 0.6 * u2"),
+    # MC SSP-RK3: second-stage weights swapped
+    "mc_rk3_stage2_weights": ("u2 = 0.75 * u + 0.25 * mc_ssp_stage(P, u1, F, dt, alpha_mode)",
+                              "u2 = 0.25 * u + 0.75 * mc_ssp_stage(P, u1, F, dt, alpha_mode)"),
+    # dynamic damping: a different floor
+    "damping_floor": ("return max(omega * 0.5, 1.0 / 64.0)", "return max(omega * 0.5, 1.0 / 32.0)"),
+    # dynamic damping: a different growth factor
+    "damping_growth": ("return min(1.0, omega * 1.25)", "return min(1.0, omega * 1.5)"),
+    # dynamic damping: growth when the residual grew
+    "damping_direction": ("    if R > R_prev:\n        return max(", "    if R < R_prev:\n        return max("),
+    # relaxation applied to the wrong iterate
+    "relaxation_form": ("return u + omega * (w - u)", "return w + omega * (w - u)"),
 }
 
 

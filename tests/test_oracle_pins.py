@@ -724,3 +724,151 @@ def test_mu_pure_convection_steady_state_obeys_dmp():
     assert u.min() >= -ulp and u.max() <= 1.0 + ulp
     ug, _ = O.stationary_mu(P, inst.F, u0, alpha_mode="one", tol=1e-10, tol_mode="rel", maxit=50, lin_rtol=1e-14)
     assert ug.min() < -1e-3 or ug.max() > 1.0 + 1e-3
+
+
+# ---------------------------------------------------------------------------
+# time integrators and the damped fixed point
+# ---------------------------------------------------------------------------
+
+
+def _dense_diffusion(Md, Xd):
+    """Dense D of eq. (5) from a dense a_ij (pattern of M_C): d_ij = -max(a_ij, 0, a_ji)."""
+    N = Md.shape[0]
+    Dd = np.zeros_like(Xd)
+    for i in range(N):
+        for j in range(N):
+            if i != j and Md[i, j] != 0.0:
+                Dd[i, j] = -max(Xd[i, j], 0.0, Xd[j, i])
+        Dd[i, i] = -Dd[i].sum()
+    return Dd
+
+
+def _fe_affine_map(Md, Ad, Dd, F):
+    """With alpha = 1 and no Dirichlet node the forward-Euler stage of eq. (18)
+    is affine: FE(u) = u + h (L u + c), where the stage's closed form
+    u + h M_L^-1 (F - A u + (M_L - M_C) udot), udot = M_L^-1 (F - (A + D) u)
+    gives L = M_L^-1 (-A - (M_L - M_C) M_L^-1 (A + D)) and
+    c = M_L^-1 (F + (M_L - M_C) M_L^-1 F)."""
+    mL = Md.sum(axis=1)
+    E = np.diag(mL) - Md
+    L = (-Ad - E @ ((Ad + Dd) / mL[:, None])) / mL[:, None]
+    c = (F + E @ (F / mL)) / mL
+    return L, c
+
+
+def _integrator_case(elem):
+    inst = I.build(elem, 3, 1e-2, I.ROTATING_B, 0.3, dirichlet="none",
+                   u0_fn=lambda X: np.sin(3 * X[:, 0]) + X[:, 1] * X[:, 2])
+    F = np.linspace(-1.0, 1.0, inst.N)
+    Md, Ad = _dense_ops(inst)
+    return inst, F, Md, Ad
+
+
+@pytest.mark.parametrize("elem", ["P1", "Q1"])
+@pytest.mark.parametrize("scheme", ["fct", "mc"])
+def test_ssp_compositions_are_the_taylor_polynomials(elem, scheme):
+    """For the linear ODE u' = L u + c, one step of Shu-Osher SSP-RK3 is the
+    cubic Taylor polynomial u + h f + h^2/2 L f + h^3/6 L^2 f (f = L u + c),
+    and Heun's form of Sec. 2.1.2, (u + FE(FE(u)))/2, the quadratic one.  The
+    limited stages with alpha = 1 are such an affine map, built densely here
+    from the closed form; FCT takes D from the full A (eq. (5)), MC from the
+    convective part (Remark 1).  h is large enough (|hL| about 1/2) that each
+    power of hL is far above rounding."""
+    inst, F, Md, Ad = _integrator_case(elem)
+    if scheme == "fct":
+        P = O.problem_from_instance(inst, conv=False)
+        Dd = _dense_diffusion(Md, Ad)
+    else:
+        P = O.problem_from_instance(inst, conv=True)
+        C = np.zeros_like(Ad)
+        C[inst.row_index(), inst.col] = -inst.K_conv
+        Dd = _dense_diffusion(Md, C)
+    L, c = _fe_affine_map(Md, Ad, Dd, F)
+    h = 0.5 / np.abs(np.linalg.eigvals(L)).max()
+    u = inst.u0.copy()
+    f = L @ u + c
+    t1, t2, t3 = h * f, h * h / 2 * (L @ f), h ** 3 / 6 * (L @ (L @ f))
+    assert np.abs(t3).max() > 1e-4 * np.abs(u).max()  # the cubic term is visible
+    scale = np.abs(u).max()
+    stage = O.fe_ssp_stage if scheme == "fct" else O.mc_ssp_stage
+    np.testing.assert_allclose(stage(P, u, F, h, alpha_mode="one"), u + t1, rtol=0, atol=1e-12 * scale)
+    rk3 = O.ssp_rk3_step if scheme == "fct" else O.mc_ssp_rk3_step
+    np.testing.assert_allclose(rk3(P, u, F, h, alpha_mode="one"), u + t1 + t2 + t3, rtol=0, atol=1e-12 * scale)
+    if scheme == "fct":
+        np.testing.assert_allclose(O.ssp_rk2_step(P, u, F, h, alpha_mode="one"), u + t1 + t2, rtol=0,
+                                   atol=1e-12 * scale)
+
+
+def test_dynamic_damping_rule_truth_table():
+    """The damping rule (reading of Sec. 4): unchanged without the dynamic rule
+    or before a previous residual exists; halved with a floor of 1/64 when the
+    residual grew; times 1.25 with a cap of 1 when it did not."""
+    f = O._next_omega
+    assert f(0.7, 2.0, 1.0, False) == 0.7
+    assert f(0.7, 2.0, None, True) == 0.7
+    assert f(1.0, 2.0, 1.0, True) == 0.5
+    assert f(1.0 / 32, 2.0, 1.0, True) == 1.0 / 64
+    assert f(1.0 / 64, 2.0, 1.0, True) == 1.0 / 64
+    assert f(0.02, 2.0, 1.0, True) == 1.0 / 64
+    assert f(0.5, 1.0, 2.0, True) == 0.625
+    assert f(0.5, 1.0, 1.0, True) == 0.625  # equal residual: not a growth
+    assert f(0.9, 1.0, 2.0, True) == 1.0
+    assert f(1.0, 1.0, 2.0, True) == 1.0
+
+
+def test_relaxed_step_is_the_convex_combination_with_the_dense_solve():
+    """One damped iteration from u0 (Sec. 4, relaxation reading) with omega =
+    0.5 and the unlimited correction F* = D u (alpha = 1, D from the convective
+    part): u1 = u0 + omega (w - u0), with w from a dense solve of
+    A_low w = F + D u0 (Dirichlet rows: identity, u_D)."""
+    inst = I.build("Q1", 4, 0.05, I.affine_field([1.0, 0.5, 0.25]), 1.0, load=("box", [0.25] * 3, [0.75] * 3),
+                   dirichlet="all", dir_fn=lambda X: X[:, 0])
+    P = O.problem_from_instance(inst, conv=True)
+    Md, Ad = _dense_ops(inst)
+    C = np.zeros_like(Ad)
+    C[inst.row_index(), inst.col] = -inst.K_conv
+    Dc = _dense_diffusion(Md, C)
+    dirs = inst.dir_idx
+    u0 = np.cos(np.arange(inst.N) * 0.7)
+    u0[dirs] = inst.dir_val
+    L0 = Ad + Dc
+    L0[dirs, :] = 0.0
+    L0[dirs, dirs] = 1.0
+    rhs = inst.F + Dc @ u0
+    rhs[dirs] = inst.dir_val
+    w = np.linalg.solve(L0, rhs)
+    u1, st = O.stationary_mcl(P, inst.F, u0, alpha_mode="one", tol=0.0, tol_mode="rel", maxit=1, omega=0.5,
+                              lin_rtol=1e-15)
+    assert st.iters == 1
+    ref = u0 + 0.5 * (w - u0)
+    np.testing.assert_allclose(u1, ref, rtol=0, atol=1e-11 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("kind", ["mcl", "cn"])
+def test_damped_fixed_points_reach_the_undamped_solution(kind):
+    """omega = 0.5 and the dynamic rule change the path of the Sec. 4 fixed
+    point but not its fixed point: all three runs end at the same solution of
+    the limited scheme (stationary MCL; CN-FCT step)."""
+    if kind == "mcl":
+        inst = I.config3(6)
+        P = O.problem_from_instance(inst, conv=True)
+        lo = O.low_order_solution(P, inst.F, lin_rtol=1e-14)
+
+        def run(**kw):
+            return O.stationary_mcl(P, inst.F, lo.x, tol=1e-13, tol_mode="rel", maxit=5000, lin_rtol=1e-14, **kw)
+    else:
+        inst = I.config1(5)
+        P = O.problem_from_instance(inst, conv=False)
+
+        def run(**kw):
+            return O.cn_fct_step(P, inst.u0, inst.F, inst.F, 1e-3, tol=1e-11, tol_mode="rel", maxit=500,
+                                 lin_atol=0.0, lin_rtol=1e-15, **kw)
+    u1, s1 = run()
+    uh, sh = run(omega=0.5)
+    ud, sd = run(omega=0.5, dynamic_damping=True)
+    for s in (s1, sh, sd):
+        assert s.status == O.STATUS_OK
+    assert sh.iters > s1.iters  # the damped path is a different (slower) one
+    scale = np.abs(u1).max()
+    np.testing.assert_allclose(uh, u1, rtol=0, atol=1e-10 * scale)
+    np.testing.assert_allclose(ud, u1, rtol=0, atol=1e-10 * scale)
