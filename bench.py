@@ -104,6 +104,69 @@ def cpu_baseline(seconds):
     }
 
 
+def solve_to_tolerance(afc, torch, inst, make_opts, rel_tol, cap, chunk, lin_eta=0.0, label=""):
+    """The stationary problem solved to its own stopping rule, R <= rel_tol R_0
+    (R_0: the nonlinear residual at the low-order start), as one user would
+    run it: the low-order solve, then fixed-point iterations until the rule
+    holds or `cap` iterations have run.  The iterations run in calls of
+    `chunk` (each stops early once the rule holds, through the equivalent
+    absolute test R < sqrt(N) tol), so that the residual is recorded every
+    `chunk` iterations; each call adds one residual evaluation (~0.5 ms at
+    128^3) to the time.  Returns counts, seconds and the residual curve."""
+    N = inst.N
+    dev = torch.device("cuda:0")
+    h = afc.afc_create_instance(inst, make_opts(fp_maxit=0, lin_eta=lin_eta), conv=True)
+    try:
+        u = torch.zeros(N, dtype=torch.float64, device=dev)
+        F = torch.tensor(inst.F, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, s0 = afc.afc_solve_stationary(h, u, F, init_low_order=True, raise_on_error=False)
+        torch.cuda.synchronize()
+        t_low = time.perf_counter() - t0
+        R0 = s0["res0"]
+        curve = [[0, 1.0]]
+        fp = kr = 0
+        status = 1
+        t_fp = 0.0
+        o = make_opts(fp_maxit=chunk, fp_tol=rel_tol * R0 / math.sqrt(N), fp_tol_mode=afc.AFC_TOL_ABS_SQRTN,
+                      lin_eta=lin_eta)
+        afc.afc_set_options(h, o)
+        while fp < cap:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, s = afc.afc_solve_stationary(h, u, F, raise_on_error=False)
+            torch.cuda.synchronize()
+            t_fp += time.perf_counter() - t0
+            fp += s["fp_iters"]
+            kr += s["krylov_iters"]
+            curve.append([fp, s["res"] / R0])
+            if st < 0:
+                status = st
+                break
+            if st == 0:
+                status = 0
+                break
+            if len(curve) % 10 == 0:
+                print("bench: %s solve: %d iterations, R/R0 = %.3e, %.1f s" % (label, fp, s["res"] / R0, t_fp),
+                      file=sys.stderr, flush=True)
+        x_min, x_max = float(u.min()), float(u.max())
+    finally:
+        afc.afc_destroy(h)
+    tail = [c for c in curve if c[0] >= curve[-1][0] // 2 and c[1] > 0]
+    contraction = None
+    if len(tail) >= 2 and tail[-1][0] > tail[0][0]:
+        contraction = (tail[-1][1] / tail[0][1]) ** (1.0 / (tail[-1][0] - tail[0][0]))
+    return {
+        "status": status, "reached": status == 0, "fp_iters": fp, "krylov_iters": kr,
+        "krylov_per_fp_iter": kr / max(1, fp), "seconds": t_fp, "low_order_seconds": t_low,
+        "low_order_krylov_iters": s0["krylov_iters"], "R0": R0, "final_rel_residual": curve[-1][1],
+        "contraction_last_half": contraction, "ms_per_iteration": 1e3 * t_fp / max(1, fp),
+        "solution_range": [x_min, x_max], "lin_eta": lin_eta,
+        "residual_curve": [[c[0], float("%.4g" % c[1])] for c in curve],
+    }
+
+
 def bench_batch(afc, torch, I, count, steps, nseq):
     """256 seeded P1 CN-FCT instances x 20 steps in one persistent launch, and
     the same instances one at a time through afc_step_cn (a subset, scaled)."""

@@ -133,6 +133,14 @@ typedef struct {
                                as a HIP graph and replayed (same kernels, same
                                results); 0: plain launches.  Not used while
                                profile = 1.                                    */
+  double lin_eta;           /* inexact fixed point (not in the paper): each
+                               linear solve of the Sec. 4 iteration may also
+                               stop once ||b - A x|| <= lin_eta * R, where R is
+                               the current nonlinear residual (the solve starts
+                               from u^nu, so R is its initial residual).  The
+                               iterates change, the fixed point does not.
+                               0 (default) = off; must lie in [0, 1).  The
+                               batched launch requires 0.                      */
   void *stream;             /* hipStream_t; NULL = default stream              */
 } afc_options;
 

@@ -472,9 +472,11 @@ def cn_fluxes(P: AFCProblem, u, u_old, d, dt, prelimit):
 
 def cn_fct_step(P: AFCProblem, u_old, F_old, F_new, dt, *, alpha_mode="limited", prelimit=2.0,
                 tol=1e-12, tol_mode="abs", maxit=50, lin="bicgstab", lin_atol=1e-12, lin_rtol=0.0,
-                lin_maxit=10000, omega=1.0, dynamic_damping=False, restart=30):
+                lin_maxit=10000, omega=1.0, dynamic_damping=False, restart=30, lin_eta=0.0):
     """One step of eq. (11) with the fluxes of eq. (12), prelimiting eq. (13) and
-    Zalesak's limiter with the predictor of eq. (14).  Returns (u^n, stats)."""
+    Zalesak's limiter with the predictor of eq. (14).  Returns (u^n, stats).
+    lin_eta > 0 lets each linear solve stop once its residual is below
+    lin_eta times the current nonlinear residual (inexact fixed point)."""
     d = artificial_diffusion(P, P.a)
     AL = low_order_operator(P, P.a, d)
     y = P.matvec(AL, u_old)
@@ -514,7 +516,7 @@ def cn_fct_step(P: AFCProblem, u_old, F_old, F_new, dt, *, alpha_mode="limited",
             st.status = STATUS_WMAXIT
             break
         w_omega = _next_omega(w_omega, R, R_prev, dynamic_damping)
-        kr = krylov(P, Acn, b, u, lin, lin_atol, lin_rtol, lin_maxit, restart)
+        kr = krylov(P, Acn, b, u, lin, max(lin_atol, lin_eta * R), lin_rtol, lin_maxit, restart)
         st.krylov_iters.append(kr.iters)
         if kr.status < 0:
             st.status = kr.status
@@ -590,9 +592,10 @@ def low_order_solution(P: AFCProblem, F, *, lin="gmres", lin_atol=0.0, lin_rtol=
 
 def stationary_mcl(P: AFCProblem, F, u0, *, alpha_mode="limited", tol=1e-8, tol_mode="rel", maxit=500,
                    lin="gmres", lin_atol=0.0, lin_rtol=1e-10, lin_maxit=20000, restart=30, omega=1.0,
-                   dynamic_damping=False):
+                   dynamic_damping=False, lin_eta=0.0):
     """Fixed-point iteration for A_low u = F + F*(u) (Sec. 4) with F* from the
-    monolithic convex limiter applied to r^ss_ij = d_ij (u_j - u_i) (Sec. 3.1)."""
+    monolithic convex limiter applied to r^ss_ij = d_ij (u_j - u_i) (Sec. 3.1).
+    lin_eta as in cn_fct_step."""
     d, As = stationary_matrix(P)
     u = np.asarray(u0, dtype=np.float64).copy()
     u[P.is_dir] = P.uD[P.is_dir]
@@ -622,7 +625,7 @@ def stationary_mcl(P: AFCProblem, F, u0, *, alpha_mode="limited", tol=1e-8, tol_
             st.status = STATUS_WMAXIT
             break
         w_omega = _next_omega(w_omega, R, R_prev, dynamic_damping)
-        kr = krylov(P, As, b, u, lin, lin_atol, lin_rtol, lin_maxit, restart)
+        kr = krylov(P, As, b, u, lin, max(lin_atol, lin_eta * R), lin_rtol, lin_maxit, restart)
         st.krylov_iters.append(kr.iters)
         if kr.status < 0:
             st.status = kr.status
@@ -677,7 +680,7 @@ def mu_limited_fluxes(P: AFCProblem, u, d, a, alpha_mode="limited"):
 
 def stationary_mu(P: AFCProblem, F, u0, *, alpha_mode="limited", tol=1e-8, tol_mode="rel", maxit=500,
                   lin="gmres", lin_atol=0.0, lin_rtol=1e-10, lin_maxit=20000, restart=30, omega=1.0,
-                  dynamic_damping=False):
+                  dynamic_damping=False, lin_eta=0.0):
     """Fixed-point iteration (Sec. 4) for A_low u = F + F*(u) with the MU
     limiter of Sec. 3.2; D and A_low = A + D from the matrix A of eq. (4)."""
     d = artificial_diffusion(P, P.a)
@@ -704,7 +707,7 @@ def stationary_mu(P: AFCProblem, F, u0, *, alpha_mode="limited", tol=1e-8, tol_m
             st.status = STATUS_WMAXIT
             break
         w_omega = _next_omega(w_omega, R, R_prev, dynamic_damping)
-        kr = krylov(P, As, b, u, lin, lin_atol, lin_rtol, lin_maxit, restart)
+        kr = krylov(P, As, b, u, lin, max(lin_atol, lin_eta * R), lin_rtol, lin_maxit, restart)
         st.krylov_iters.append(kr.iters)
         if kr.status < 0:
             st.status = kr.status
@@ -770,7 +773,7 @@ def mc_ssp_rk3_step(P: AFCProblem, u, F, dt, alpha_mode="limited"):
 
 def mc_cn_step(P: AFCProblem, u_old, F_old, F_new, dt, *, alpha_mode="limited", tol=1e-12, tol_mode="abs",
                maxit=50, lin="bicgstab", lin_atol=1e-12, lin_rtol=0.0, lin_maxit=10000, omega=1.0,
-               dynamic_damping=False, restart=30):
+               dynamic_damping=False, restart=30, lin_eta=0.0):
     """MC+CN (Sec. 2.2): eq. (11) with 𝔸 = A + D^conv and the correction
     F* = 1/2 [F*(u^n) + F*(u^{n-1})], each evaluated with the low-order rate
     at its own time level (F^n resp. F^{n-1}); fixed point of Sec. 4 from
@@ -805,7 +808,7 @@ def mc_cn_step(P: AFCProblem, u_old, F_old, F_new, dt, *, alpha_mode="limited", 
             st.status = STATUS_WMAXIT
             break
         w_omega = _next_omega(w_omega, R, R_prev, dynamic_damping)
-        kr = krylov(P, Acn, b, u, lin, lin_atol, lin_rtol, lin_maxit, restart)
+        kr = krylov(P, Acn, b, u, lin, max(lin_atol, lin_eta * R), lin_rtol, lin_maxit, restart)
         st.krylov_iters.append(kr.iters)
         if kr.status < 0:
             st.status = kr.status

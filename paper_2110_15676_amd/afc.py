@@ -45,7 +45,7 @@ class afc_options(ctypes.Structure):
         ("fp_tol", c_double), ("fp_tol_mode", c_int32), ("fp_maxit", c_int32),
         ("prelimit", c_double), ("omega", c_double), ("dynamic_damping", c_int32),
         ("ssp_stages", c_int32), ("lanes_per_row", c_int32), ("profile", c_int32), ("limiter", c_int32),
-        ("sstep", c_int32), ("sstep_shift", c_double), ("graphs", c_int32),
+        ("sstep", c_int32), ("sstep_shift", c_double), ("graphs", c_int32), ("lin_eta", c_double),
         ("stream", c_void_p),
     ]
 

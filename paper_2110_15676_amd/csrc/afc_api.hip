@@ -71,6 +71,7 @@ afc_status check_options(const afc_options& o, std::string& why) {
   if (o.limiter != AFC_LIMITER_MCL && o.limiter != AFC_LIMITER_MU) return why = "limiter", AFC_EINVAL;
   if (o.sstep != 0 && (o.sstep < 2 || o.sstep > afc::kSMax)) return why = "sstep must be 0 or 2..8", AFC_EINVAL;
   if (!std::isfinite(o.sstep_shift)) return why = "sstep_shift must be finite", AFC_EINVAL;
+  if (!(o.lin_eta >= 0 && o.lin_eta < 1)) return why = "lin_eta must be in [0, 1)", AFC_EINVAL;
   if (o.lanes_per_row != 0 && o.lanes_per_row != 8 && o.lanes_per_row != 16 && o.lanes_per_row != 32 &&
       o.lanes_per_row != 64)
     return why = "lanes_per_row must be 0, 8, 16, 32 or 64", AFC_EINVAL;
@@ -562,7 +563,7 @@ afc_status fixed_point(afc_handle* h, double* u, const SysMat& S, Eval eval, afc
       x = h->w[W_X];
       afc::copy(h, x, u);
     }
-    const double tol = std::max(h->opt.lin_atol, h->opt.lin_rtol * bn);
+    const double tol = std::max(std::max(h->opt.lin_atol, h->opt.lin_rtol * bn), h->opt.lin_eta * R);
     const SolveOut o = linear_solve(h, S, b, x, r, 2, tol);
     add_solve(st, o);
     if (o.st == AFC_ENAN || o.st == AFC_EBREAKDOWN) {
@@ -1352,6 +1353,7 @@ afc_status afc_batch_create(int32_t count, const afc_problem* probs, const afc_o
   if (check_options(o, why) != AFC_OK) return g_batch_error = "invalid options: " + why, AFC_EINVAL;
   if (o.krylov != AFC_KRYLOV_BICGSTAB || o.precision != AFC_PREC_FP64)
     return g_batch_error = "the batched launch runs BiCGStab in FP64", AFC_EINVAL;
+  if (o.lin_eta != 0.0) return g_batch_error = "the batched launch has no inexact solves (lin_eta = 0)", AFC_EINVAL;
   afc_batch* b = new afc_batch();
   afc_handle* h = nullptr;  // HIP_OK / fail record messages only in the thrown Fail
   try {

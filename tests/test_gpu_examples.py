@@ -94,6 +94,7 @@ def test_rotating_shapes_steps_match_oracle():
         for u, r in ((u1, r1), (u2, r2)):
             x = u.cpu().numpy()
             assert np.linalg.norm(x - r) <= 1e-10 * np.linalg.norm(r)
+            assert np.abs(x - r).max() <= 1e-10 * np.abs(r).max()
     finally:
         afc.afc_destroy(h1)
         afc.afc_destroy(h2)

@@ -26,7 +26,14 @@ def _dev(x):
 
 
 def _rel(a, b):
-    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+    """Larger of the relative L2 distance and the element-wise distance
+    max_i |a_i - b_i| / max_i |b_i|, so that a wrong value at a single node
+    fails the same bar as a wrong vector."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    l2 = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+    mx = np.abs(a - b).max() / max(np.abs(b).max(), 1e-300) if b.size else 0.0
+    return float(max(l2, mx))
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -125,6 +132,71 @@ def test_ssp_full_size_step_and_invariants():
         afc.afc_destroy(h)
 
 
+@pytest.mark.parametrize("n", [16, 33])
+def test_ssp_stage_keeps_local_fct_bounds(n):
+    """Sec. 2.1.3: Zalesak's factors keep every limited forward-Euler update
+    inside the range of the low-order predictor over the node's neighbourhood,
+    u_new_i in [min_{j in N_i} u~_j, max_{j in N_i} u~_j].  Checked node by
+    node on the GPU's output (the predictor from the oracle), within 4 ulp of
+    the data's scale."""
+    afc = _afc()
+    inst = I.config2(n)
+    P = O.problem_from_instance(inst, conv=False)
+    dt = inst.params["dt"]
+    h = afc.afc_create_instance(inst, _opts(ssp_stages=1), conv=False)
+    try:
+        u = _dev(inst.u0)
+        F = _dev(inst.F)
+        for stage in range(3):
+            before = u.cpu().numpy()
+            afc.afc_step_ssprk3(h, u, F, dt)
+            got = u.cpu().numpy()
+            _, info = O.fe_ssp_stage(P, before, inst.F, dt, info=True)
+            lo = P.row_min(info.ut[P.col])
+            hi = P.row_max(info.ut[P.col])
+            slack = 4 * np.finfo(float).eps * max(1.0, np.abs(info.ut).max())
+            assert np.all(got >= lo - slack) and np.all(got <= hi + slack), stage
+    finally:
+        afc.afc_destroy(h)
+
+
+def test_cn_step_keeps_local_fct_bounds():
+    """Sec. 2.1.1 with Zalesak's limiter: at the converged CN step the limited
+    correction F* = A_CN u^n - g satisfies u~_i + dt F*_i / m_i in
+    [u~_i + Q-_i, u~_i + Q+_i] at every non-Dirichlet node (u~ the half-step
+    predictor of eq. (14)).  F* is recovered from the GPU's u^n with FP64 CPU
+    arithmetic; the slack is the fixed-point residual's share plus a few ulp."""
+    afc = _afc()
+    inst = I.config1()
+    P = O.problem_from_instance(inst, conv=False)
+    dt = inst.params["dt"]
+    h = afc.afc_create_instance(inst, _opts(krylov=0, **CN_PARITY), conv=False)
+    try:
+        u = _dev(inst.u0)
+        F = _dev(inst.F)
+        u_old = inst.u0.copy()
+        for step in range(5):
+            st, stats = afc.afc_step_cn(h, u, F, F, dt)
+            assert st == 0, stats
+            un = u.cpu().numpy()
+            d = O.artificial_diffusion(P, P.a)
+            AL = O.low_order_operator(P, P.a, d)
+            ut = O.cn_predictor(P, u_old, inst.F, dt)
+            Qp, Qm = O.zalesak_Q(P, ut)
+            g = P.m / dt * u_old - 0.5 * P.matvec(AL, u_old) + inst.F
+            Acn = 0.5 * AL
+            Acn[P.diag_pos] += P.m / dt
+            Fstar = P.matvec(Acn, un) - g
+            free = ~P.is_dir
+            x = ut + dt * Fstar / P.m
+            slack = dt / P.m * stats["res"] + 8 * np.finfo(float).eps * max(1.0, np.abs(un).max())
+            assert np.all((x >= ut + Qm - slack)[free]), step
+            assert np.all((x <= ut + Qp + slack)[free]), step
+            u_old = un
+    finally:
+        afc.afc_destroy(h)
+
+
 # ---------------------------------------------------------------------------
 # Crank-Nicolson + Zalesak (nonlinear, fixed point)
 # ---------------------------------------------------------------------------
@@ -134,7 +206,7 @@ CN_PARITY = dict(fp_tol=1e-14, fp_tol_mode=0, fp_maxit=100, lin_atol=1e-15, lin_
 
 @pytest.mark.parametrize("krylov,prec,sstep", [(0, 0, 0), (1, 0, 0), (1, 1, 0), (1, 1, 8)])
 def test_cn_config1_parity(krylov, prec, sstep):
-    """The CN workload (P1 8^3, 729 nodes): 10 steps against the oracle."""
+    """The CN workload (P1 8^3, 729 nodes): all 50 steps against the oracle."""
     afc = _afc()
     inst = I.config1()
     P = O.problem_from_instance(inst, conv=False)
@@ -145,7 +217,7 @@ def test_cn_config1_parity(krylov, prec, sstep):
         u = _dev(inst.u0)
         F = _dev(inst.F)
         ref = inst.u0.copy()
-        for s in range(10):
+        for s in range(inst.params["steps"]):
             st, stats = afc.afc_step_cn(h, u, F, F, dt)
             assert st == 0, stats
             ref, rst = O.cn_fct_step(P, ref, inst.F, inst.F, dt, tol=1e-14, tol_mode="abs", maxit=100,
@@ -221,10 +293,10 @@ def test_cn_alpha_modes(mode, name):
 # ---------------------------------------------------------------------------
 
 
-def _mcl_ref(inst, tol, lin_rtol, maxit=2000):
+def _mcl_ref(inst, tol, lin_rtol, maxit=2000, **kw):
     P = O.problem_from_instance(inst, conv=True)
     lo = O.low_order_solution(P, inst.F, lin_rtol=1e-14)
-    u, st = O.stationary_mcl(P, inst.F, lo.x, tol=tol, tol_mode="rel", maxit=maxit, lin_rtol=lin_rtol)
+    u, st = O.stationary_mcl(P, inst.F, lo.x, tol=tol, tol_mode="rel", maxit=maxit, lin_rtol=lin_rtol, **kw)
     return u, st
 
 
@@ -292,6 +364,88 @@ def test_mcl_long_row_parity(prec):
         st, stats = afc.afc_solve_stationary(h, u, F, raise_on_error=False)
         assert st >= 0 and stats["fp_iters"] == 5, stats
         assert _rel(u.cpu().numpy(), ref) <= (1e-10 if prec == 0 else 1e-8)
+    finally:
+        afc.afc_destroy(h)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("omega,dyn", [(0.5, 0), (1.0, 1), (0.5, 1)])
+def test_mcl_damped_fixed_point_parity(prec, omega, dyn):
+    """The damped fixed point of Sec. 4 (relaxation u + omega (w - u), with
+    and without the dynamic rule) on the stationary MCL workload at 12^3:
+    same iteration count and same converged solution as the oracle run with
+    the same options."""
+    afc = _afc()
+    inst = I.config3(12)
+    ref, rst = _mcl_ref(inst, 1e-12, 1e-14, maxit=4000, omega=omega, dynamic_damping=bool(dyn))
+    print("mcl damped n=12 prec=%d omega=%g dyn=%d oracle fp its %d" % (prec, omega, dyn, rst.iters), flush=True)
+    assert rst.status == O.STATUS_OK
+    h = afc.afc_create_instance(inst, _opts(precision=prec, fp_tol=1e-12, fp_tol_mode=1, fp_maxit=4000,
+                                            lin_atol=0.0, lin_rtol=1e-14, omega=omega, dynamic_damping=dyn),
+                                conv=True)
+    try:
+        u = _dev(np.zeros(inst.N))
+        st, stats = afc.afc_solve_stationary(h, u, _dev(inst.F), init_low_order=True)
+        assert st == 0, stats
+        if prec == 0:
+            assert abs(stats["fp_iters"] - rst.iters) <= 2, (stats["fp_iters"], rst.iters)
+        tol = 1e-10 if prec == 0 else 1e-8
+        assert _rel(u.cpu().numpy(), ref) <= tol
+    finally:
+        afc.afc_destroy(h)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_mcl_inexact_fixed_point_parity(prec):
+    """Inexact linear solves (each to 1e-2 of the current nonlinear residual)
+    on the stationary MCL workload at 12^3: the oracle run with the same
+    option takes the same fixed-point iterations, and both reach the strict
+    run's solution."""
+    afc = _afc()
+    inst = I.config3(12)
+    ref, rst = _mcl_ref(inst, 1e-12, 1e-14, maxit=4000, lin_eta=1e-2)
+    strict, _ = _mcl_ref(inst, 1e-12, 1e-14, maxit=4000)
+    print("mcl inexact n=12 prec=%d oracle fp its %d" % (prec, rst.iters), flush=True)
+    h = afc.afc_create_instance(inst, _opts(precision=prec, fp_tol=1e-12, fp_tol_mode=1, fp_maxit=4000,
+                                            lin_atol=0.0, lin_rtol=1e-14, lin_eta=1e-2), conv=True)
+    try:
+        u = _dev(np.zeros(inst.N))
+        st, stats = afc.afc_solve_stationary(h, u, _dev(inst.F), init_low_order=True)
+        assert st == 0, stats
+        if prec == 0:
+            assert abs(stats["fp_iters"] - rst.iters) <= 2, (stats["fp_iters"], rst.iters)
+        tol = 1e-10 if prec == 0 else 1e-8
+        x = u.cpu().numpy()
+        assert _rel(x, ref) <= tol
+        assert _rel(x, strict) <= tol
+    finally:
+        afc.afc_destroy(h)
+
+
+@pytest.mark.parametrize("omega,dyn", [(0.5, 0), (0.5, 1)])
+def test_cn_damped_fixed_point_parity(omega, dyn):
+    """CN-FCT on the P1 8^3 workload with the damped fixed point: 10 steps
+    against the oracle with the same omega and damping rule."""
+    afc = _afc()
+    inst = I.config1()
+    P = O.problem_from_instance(inst, conv=False)
+    dt = inst.params["dt"]
+    print("cn damped omega=%g dyn=%d" % (omega, dyn), flush=True)
+    h = afc.afc_create_instance(inst, _opts(krylov=0, omega=omega, dynamic_damping=dyn, fp_tol=1e-11,
+                                            fp_tol_mode=1, fp_maxit=400, lin_atol=0.0, lin_rtol=1e-15),
+                                conv=False)
+    try:
+        u = _dev(inst.u0)
+        F = _dev(inst.F)
+        ref = inst.u0.copy()
+        for s in range(10):
+            st, stats = afc.afc_step_cn(h, u, F, F, dt)
+            assert st == 0, stats
+            ref, rst = O.cn_fct_step(P, ref, inst.F, inst.F, dt, tol=1e-11, tol_mode="rel", maxit=400,
+                                     lin="bicgstab", lin_atol=0.0, lin_rtol=1e-15, omega=omega,
+                                     dynamic_damping=bool(dyn))
+            assert rst.status == O.STATUS_OK
+        assert _rel(u.cpu().numpy(), ref) <= 1e-10
     finally:
         afc.afc_destroy(h)
 

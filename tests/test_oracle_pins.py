@@ -846,9 +846,9 @@ def test_relaxed_step_is_the_convex_combination_with_the_dense_solve():
 
 @pytest.mark.parametrize("kind", ["mcl", "cn"])
 def test_damped_fixed_points_reach_the_undamped_solution(kind):
-    """omega = 0.5 and the dynamic rule change the path of the Sec. 4 fixed
-    point but not its fixed point: all three runs end at the same solution of
-    the limited scheme (stationary MCL; CN-FCT step)."""
+    """omega = 0.5, the dynamic rule and inexact linear solves change the path
+    of the Sec. 4 fixed point but not its fixed point: all runs end at the
+    same solution of the limited scheme (stationary MCL; CN-FCT step)."""
     if kind == "mcl":
         inst = I.config3(6)
         P = O.problem_from_instance(inst, conv=True)
@@ -866,9 +866,14 @@ def test_damped_fixed_points_reach_the_undamped_solution(kind):
     u1, s1 = run()
     uh, sh = run(omega=0.5)
     ud, sd = run(omega=0.5, dynamic_damping=True)
-    for s in (s1, sh, sd):
+    ue, se = run(lin_eta=1e-2)
+    for s in (s1, sh, sd, se):
         assert s.status == O.STATUS_OK
     assert sh.iters > s1.iters  # the damped path is a different (slower) one
+    # inexact solves (each to 1e-2 of the current nonlinear residual) take
+    # fewer Krylov iterations to the same fixed point
+    assert sum(se.krylov_iters) < sum(s1.krylov_iters)
     scale = np.abs(u1).max()
     np.testing.assert_allclose(uh, u1, rtol=0, atol=1e-10 * scale)
     np.testing.assert_allclose(ud, u1, rtol=0, atol=1e-10 * scale)
+    np.testing.assert_allclose(ue, u1, rtol=0, atol=1e-10 * scale)
