@@ -193,6 +193,29 @@ afc_status afc_set_options(afc_handle *h, const afc_options *opt);
  * step.  stats may be NULL. */
 afc_status afc_step_ssprk3(afc_handle *h, double *u, const double *F, double dt, afc_stats *stats);
 
+/* Size of the fixed device array behind afc_step_ssprk3_noalloc: 64 MiB on
+ * every GPU the library is loaded on, held until the process ends. */
+#define AFC_NOALLOC_SCRATCH_BYTES (64ull << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the step of
+ * afc_step_ssprk3, with the same arguments, kernels and results, whose six
+ * per-call work vectors (two stage states, the low-order rate, the predictor,
+ * Zalesak's R+ and R-) live in a fixed device array of
+ * AFC_NOALLOC_SCRATCH_BYTES instead of memory the handle allocates on first
+ * use.  It calls no hipMalloc, hipFree or other allocating routine.
+ * Limits and errors (EINVAL, u unchanged, afc_last_error says which):
+ *   - 6 * ceil(N / 64) * 64 * 8 bytes must fit the array (N <= 1,398,080);
+ *   - the handle's slot-order explicit-stage coefficients must exist: they are
+ *     built by the first afc_step_ssprk3, afc_step_mc_ssprk3 or CN call on the
+ *     handle, which this entry point never makes for the caller;
+ *   - options.profile must be 0.
+ * Every call on one GPU shares that GPU's array, which keeps the last call's
+ * contents (each call writes every element it reads, so nothing needs
+ * clearing): calls that overlap on one GPU (several host threads or streams)
+ * race and must be serialized by the caller. */
+afc_status afc_step_ssprk3_noalloc(afc_handle *h, double *u, const double *F, double dt, afc_stats *stats);
+
 /* One Crank-Nicolson FCT step, eq. (11) with fluxes eq. (12), prelimiting
  * eq. (13) and the predictor eq. (14), solved by the fixed-point iteration of
  * Sec. 4 with matrix M_L/dt + A_low/2.  u: in u^{n-1}, out u^n (device).

@@ -27,6 +27,7 @@ AFC_KRYLOV_BICGSTAB, AFC_KRYLOV_GMRES = 0, 1
 AFC_PREC_FP64, AFC_PREC_MIXED = 0, 1
 AFC_TOL_ABS_SQRTN, AFC_TOL_REL = 0, 1
 AFC_LIMITER_MCL, AFC_LIMITER_MU = 0, 1
+AFC_NOALLOC_SCRATCH_BYTES = 64 << 20  # include/afc.h
 
 
 class afc_problem(ctypes.Structure):
@@ -74,7 +75,7 @@ EXPORTS = [
     "afc_footprint_bytes", "afc_server_create", "afc_server_submit", "afc_server_wait", "afc_server_poll", "afc_server_last_error",
     "afc_server_destroy", "afc_get_sell_info", "afc_get_krylov_sell_info", "afc_sell_layout", "afc_kernel_work",
     "afc_batch_set_schedule", "afc_batch_get_schedule", "afc_batch_autotune", "afc_step_cn_linear",
-    "afc_step_mc_ssprk3", "afc_step_mc_cn",
+    "afc_step_mc_ssprk3", "afc_step_mc_cn", "afc_step_ssprk3_noalloc",
 ]
 
 AFC_REQ_CN, AFC_REQ_STATIONARY = 0, 1
@@ -100,6 +101,8 @@ def lib():
         L.afc_set_options.restype = c_int32
         L.afc_step_ssprk3.argtypes = [c_void_p, c_void_p, c_void_p, c_double, POINTER(afc_stats)]
         L.afc_step_ssprk3.restype = c_int32
+        L.afc_step_ssprk3_noalloc.argtypes = [c_void_p, c_void_p, c_void_p, c_double, POINTER(afc_stats)]
+        L.afc_step_ssprk3_noalloc.restype = c_int32
         L.afc_step_cn.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_double, POINTER(afc_stats)]
         L.afc_step_cn.restype = c_int32
         L.afc_step_cn_linear.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_double, POINTER(afc_stats)]
@@ -274,6 +277,14 @@ def _finish(h, st, stats, raise_on_error):
 def afc_step_ssprk3(h, u, F, dt, raise_on_error=True):
     stats = afc_stats()
     st = lib().afc_step_ssprk3(h, u.data_ptr(), F.data_ptr(), float(dt), ctypes.byref(stats))
+    return _finish(h, st, stats, raise_on_error)
+
+
+def afc_step_ssprk3_noalloc(h, u, F, dt, raise_on_error=True):
+    """afc_step_ssprk3 with its work vectors in the library's fixed per-GPU
+    array (allocates nothing; see include/afc.h for the limits)."""
+    stats = afc_stats()
+    st = lib().afc_step_ssprk3_noalloc(h, u.data_ptr(), F.data_ptr(), float(dt), ctypes.byref(stats))
     return _finish(h, st, stats, raise_on_error)
 
 

@@ -10,6 +10,7 @@
 #include <cstddef>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -751,7 +752,83 @@ afc_status guard(afc_handle* h, afc_stats* st, afc_status (*body)(afc_handle*, v
   return s;
 }
 
+struct SspArgs {
+  double* u;
+  const double* F;
+  double dt;
+};
+
+// The stages of one explicit step (Shu-Osher RK3, Heun or one forward-Euler
+// stage of eq. (18), Zalesak-limited), with the six per-call work vectors
+// given by the caller: s1, s2 (stage states), udot, ut (low-order rate and
+// predictor), Rp, Rm (Zalesak's R+-).  Needs the slot-order coefficients.
+void ssp_stages(afc_handle* h, const SspArgs& a, double* s1, double* s2, double* udot, double* ut, double* Rp,
+                double* Rm) {
+  struct Stage {
+    const double* in;
+    double* out;
+    double c0, c1;
+  };
+  Stage stages[3];
+  int ns = 0;
+  if (h->opt.ssp_stages == 3) {  // Shu-Osher SSP-RK3
+    stages[ns++] = {a.u, s1, 0.0, 1.0};
+    stages[ns++] = {s1, s2, 0.75, 0.25};
+    stages[ns++] = {s2, a.u, 1.0 / 3.0, 2.0 / 3.0};
+  } else if (h->opt.ssp_stages == 2) {  // Heun, u^n = (u^{n,0} + u^{n,2}) / 2
+    stages[ns++] = {a.u, s1, 0.0, 1.0};
+    stages[ns++] = {s1, a.u, 0.5, 0.5};
+  } else {
+    stages[ns++] = {a.u, s1, 0.0, 1.0};
+  }
+  for (int s = 0; s < ns; ++s) {
+    afc::ssp_lowrate(h, stages[s].in, a.F, a.dt, udot, ut);
+    afc::ssp_limit_R(h, stages[s].in, udot, ut, a.dt, Rp, Rm);
+    afc::ssp_apply(h, stages[s].in, udot, ut, Rp, Rm, a.dt, a.u, stages[s].c0, stages[s].c1, stages[s].out);
+  }
+  if (ns == 1) afc::copy(h, a.u, s1);
+  HIP_OK(hipGetLastError());
+  HIP_OK(hipStreamSynchronize(h->stream));
+}
+
+// ---------------------------------------------------------------------------
+// afc_step_ssprk3_noalloc: the explicit step with its work vectors in a fixed
+// per-device array instead of the handle's lazily allocated ones.
+// ---------------------------------------------------------------------------
+
+constexpr size_t kNoallocScratchBytes = size_t(AFC_NOALLOC_SCRATCH_BYTES);
+constexpr int kNoallocVectors = 6;
+constexpr int kMaxDevices = 64;
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
 }  // namespace
+
+// The array of the allocation-free entry point.  In host code this name is
+// only a stand-in: its device address comes from hipGetSymbolAddress, once
+// per device (noalloc_scratch), and only that address is ever used.
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+namespace {
+
+// Device address of `scratch` on the current device `dev` (looked up on the
+// first call per device and kept).
+void* noalloc_scratch(afc_handle* h, int dev) {
+  if (dev < 0 || dev >= kMaxDevices) fail(h, AFC_EDEVICE, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    HIP_OK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) fail(h, AFC_EDEVICE, "hipGetSymbolAddress returned no address for the scratch array");
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+
 
 // ===========================================================================
 // C ABI
@@ -1027,12 +1104,6 @@ void afc_destroy(afc_handle* h) {
   delete h;
 }
 
-struct SspArgs {
-  double* u;
-  const double* F;
-  double dt;
-};
-
 afc_status afc_step_ssprk3(afc_handle* h, double* u, const double* F, double dt, afc_stats* st) {
   if (!h) return AFC_EINVAL;
   if (!u || !F || !(dt > 0) || !std::isfinite(dt)) {
@@ -1044,42 +1115,51 @@ afc_status afc_step_ssprk3(afc_handle* h, double* u, const double* F, double dt,
       h, st,
       [](afc_handle* h, void* ctx) -> afc_status {
         const SspArgs& a = *static_cast<SspArgs*>(ctx);
-        double* s1 = h->w[W_S1];
-        double* s2 = h->w[W_S2];
-        double* udot = h->w[W_G];
-        double* ut = h->w[W_UT];
-        double* Rp = h->w[W_RP];
-        double* Rm = h->w[W_RM];
-        struct Stage {
-          const double* in;
-          double* out;
-          double c0, c1;
-        };
-        Stage stages[3];
-        int ns = 0;
-        if (h->opt.ssp_stages == 3) {  // Shu-Osher SSP-RK3
-          stages[ns++] = {a.u, s1, 0.0, 1.0};
-          stages[ns++] = {s1, s2, 0.75, 0.25};
-          stages[ns++] = {s2, a.u, 1.0 / 3.0, 2.0 / 3.0};
-        } else if (h->opt.ssp_stages == 2) {  // Heun, u^n = (u^{n,0} + u^{n,2}) / 2
-          stages[ns++] = {a.u, s1, 0.0, 1.0};
-          stages[ns++] = {s1, a.u, 0.5, 0.5};
-        } else {
-          stages[ns++] = {a.u, s1, 0.0, 1.0};
-        }
         ensure_fct_sell(h);
-        for (int s = 0; s < ns; ++s) {
-          afc::ssp_lowrate(h, stages[s].in, a.F, a.dt, udot, ut);
-          afc::ssp_limit_R(h, stages[s].in, udot, ut, a.dt, Rp, Rm);
-          afc::ssp_apply(h, stages[s].in, udot, ut, Rp, Rm, a.dt, a.u, stages[s].c0, stages[s].c1, stages[s].out);
-        }
-        if (ns == 1) afc::copy(h, a.u, s1);
-        HIP_OK(hipGetLastError());
-        HIP_OK(hipStreamSynchronize(h->stream));
+        ssp_stages(h, a, h->w[W_S1], h->w[W_S2], h->w[W_G], h->w[W_UT], h->w[W_RP], h->w[W_RM]);
         afc::prof_collect(h);
         return AFC_OK;
       },
       &a);
+}
+
+afc_status afc_step_ssprk3_noalloc(afc_handle* h, double* u, const double* F, double dt, afc_stats* st) {
+  if (!h) return AFC_EINVAL;
+  h->last_error.clear();
+  if (st) std::memset(st, 0, sizeof(*st));
+  afc_status s = AFC_OK;
+  if (!u || !F || !(dt > 0) || !std::isfinite(dt)) {
+    h->last_error = "afc_step_ssprk3_noalloc: need device u, F and dt > 0";
+    s = AFC_EINVAL;
+  } else if ((size_t)kNoallocVectors * (size_t)h->ldv * sizeof(double) > kNoallocScratchBytes) {
+    h->last_error = "afc_step_ssprk3_noalloc: N = " + std::to_string(h->N) + " needs " +
+                    std::to_string((size_t)kNoallocVectors * (size_t)h->ldv * sizeof(double)) +
+                    " bytes of work space, above the fixed " + std::to_string(kNoallocScratchBytes);
+    s = AFC_EINVAL;
+  } else if (!h->S_mij) {
+    h->last_error = "afc_step_ssprk3_noalloc: the handle's explicit-stage coefficients are not built yet "
+                    "(one afc_step_ssprk3, afc_step_mc_ssprk3 or CN call on the handle builds them)";
+    s = AFC_EINVAL;
+  } else if (h->opt.profile) {
+    h->last_error = "afc_step_ssprk3_noalloc: profiling (options.profile) is not available here";
+    s = AFC_EINVAL;
+  }
+  if (s == AFC_OK) {
+    try {
+      HIP_OK(hipSetDevice(h->device));
+      double* base = static_cast<double*>(noalloc_scratch(h, h->device));
+      const size_t ld = (size_t)h->ldv;
+      SspArgs a{u, F, dt};
+      ssp_stages(h, a, base, base + ld, base + 2 * ld, base + 3 * ld, base + 4 * ld, base + 5 * ld);
+    } catch (const Fail& f) {
+      s = f.st;
+    } catch (...) {
+      h->last_error = "unexpected host exception";
+      s = AFC_EDEVICE;
+    }
+  }
+  if (st) st->status = s;
+  return s;
 }
 
 // System matrix kept in the handle's CN storage: M_L/dt + AL/2 for a CN step
