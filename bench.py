@@ -72,47 +72,136 @@ def step_model_bytes(N, info, kinfo, krylov, sweeps, steps, sstep=0):
     return krylov * per_it + sweeps * per_sweep + steps * per_fp
 
 
-def cpu_baseline(seconds):
-    """The FP64 oracle on a bounded sample: fixed-point iterations of the same
-    problem on the 32^3 mesh, from its low-order solution, single thread."""
-    import numpy as np  # noqa: F401
+def _oracle_first_iteration(n):
+    """The oracle's first fixed-point iteration of the MCL workload on Q1 n^3
+    from its low-order solution (one thread).  Returns (nodes, seconds,
+    Krylov iterations, seconds of the untimed low-order solve)."""
     from threadpoolctl import threadpool_limits
 
     from oracle import afc_oracle as O
     from paper_2110_15676_amd import inputs as I
 
-    n = 32
     inst = I.config3(n)
     with threadpool_limits(1):
         P = O.problem_from_instance(inst, conv=True)
-        lo = O.low_order_solution(P, inst.F, lin_rtol=1e-12)
         t = time.perf_counter()
-        O.stationary_mcl(P, inst.F, lo.x, tol=0.0, tol_mode="rel", maxit=1, lin_rtol=1e-10)
-        t1 = time.perf_counter() - t
-        its = max(1, min(200, int(seconds / max(t1, 1e-3))))
+        lo = O.low_order_solution(P, inst.F, lin_rtol=1e-10)
+        t_lo = time.perf_counter() - t
         t = time.perf_counter()
-        _, st = O.stationary_mcl(P, inst.F, lo.x, tol=0.0, tol_mode="rel", maxit=its, lin_rtol=1e-10)
-        dt = time.perf_counter() - t
-    return {
-        "value": inst.N * st.iters / dt,
+        _, st = O.stationary_mcl(P, inst.F, lo.x, tol=0.0, tol_mode="rel", maxit=1, lin_rtol=1e-10)
+        el = time.perf_counter() - t
+    return inst.N, el, int(sum(st.krylov_iters)), t_lo
+
+
+def _oracle_cn_instance(k):
+    """20 CN-FCT steps of batch instance k with the oracle (one process per
+    instance, one thread), at the batch's tolerances."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import afc_oracle as O
+    from paper_2110_15676_amd import inputs as I
+
+    with threadpool_limits(1):
+        inst = I.config4_instance(I.config4_params(k + 1)[k])
+        P = O.problem_from_instance(inst, conv=False)
+        u = inst.u0.copy()
+        t = time.perf_counter()
+        for _ in range(20):
+            u, _ = O.cn_fct_step(P, u, inst.F, inst.F, 1e-3, tol=1e-12, tol_mode="abs", maxit=50,
+                                 lin="bicgstab", lin_atol=1e-12)
+        return inst.N, time.perf_counter() - t
+
+
+def gpu_first_iteration(afc, torch, I, n, sstep):
+    """The GPU on the oracle's sample: the first fixed-point iteration of the
+    MCL workload on Q1 n^3 from its low-order solution, with the bench's
+    mixed-precision solver and with plain FP64 GMRES (the oracle's
+    arithmetic)."""
+    inst = I.config3(n)
+    out = {"nodes": inst.N}
+    for name, prec, ss in (("mixed", afc.AFC_PREC_MIXED, sstep), ("fp64", afc.AFC_PREC_FP64, 0)):
+        o = afc.afc_default_options(precision=prec, krylov=afc.AFC_KRYLOV_GMRES, restart=30, fp_tol=0.0,
+                                    fp_tol_mode=afc.AFC_TOL_REL, fp_maxit=0, lin_atol=0.0, lin_rtol=1e-10,
+                                    lin_maxit=100000, sstep=ss)
+        o.stream = torch.cuda.current_stream().cuda_stream
+        h = afc.afc_create_instance(inst, o, conv=True)
+        try:
+            u = torch.zeros(inst.N, dtype=torch.float64, device="cuda:0")
+            F = torch.tensor(inst.F, device="cuda:0")
+            afc.afc_solve_stationary(h, u, F, init_low_order=True)
+            o.fp_maxit = 1
+            afc.afc_set_options(h, o)
+            u1 = u.clone()
+            afc.afc_solve_stationary(h, u1, F)  # warm-up (graphs, coefficient layouts)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, s = afc.afc_solve_stationary(h, u, F)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+        finally:
+            afc.afc_destroy(h)
+        out[name] = {"seconds": el, "krylov_iters": s["krylov_iters"], "dof_its_per_s": inst.N / el,
+                     "dof_krylov_its_per_s": inst.N * s["krylov_iters"] / el}
+    return out
+
+
+def host_cores():
+    """Host cores this process may use (affinity), at most the 16 of a one-GPU
+    share."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_baseline(n, gpu_sample, batch_sample):
+    """The FP64 oracle on bounded samples of the workloads, on the host cores.
+    (1) The first fixed-point iteration of the MCL workload on Q1 n^3 from its
+    low-order solution, one thread, beside the GPU's time for the same
+    iteration (`gpu_sample`).  (2) Every 8th of the 256 batched CN-FCT
+    instances, 20 steps each, one process per instance over the host cores."""
+    import multiprocessing as mp
+
+    N, el, kr, t_lo = _oracle_first_iteration(n)
+    out = {
+        "value": N / el,
         "unit": "DOF-iterations/s",
         "cores": 1,
+        "host_cores": host_cores(),
+        "nproc": os.cpu_count(),
         "kind": "oracle",
-        "sample": "%d fixed-point iterations (%d GMRES(30) iterations) of the same MCL problem on Q1 %d^3 "
-                  "(%d nodes) from its low-order solution, numpy FP64, one thread; %.1f s"
-                  % (st.iters, sum(st.krylov_iters), n, inst.N, dt),
+        "sample": "first fixed-point iteration of the same MCL problem on Q1 %d^3 (%d nodes) from its low-order "
+                  "solution: %d GMRES(30)-Jacobi iterations to 1e-10 ||b||, numpy FP64, one thread; %.1f s "
+                  "(low-order start %.1f s, not timed)" % (n, N, kr, el, t_lo),
+        "krylov_iters": kr,
+        "dof_krylov_its_per_s": N * kr / el,
+        "gpu_same_sample": gpu_sample,
     }
+    if batch_sample:
+        ids = list(range(0, 256, 8))
+        workers = host_cores()
+        ctx = mp.get_context("spawn")
+        t = time.perf_counter()
+        with ctx.Pool(workers) as pool:
+            res = pool.map(_oracle_cn_instance, ids, chunksize=1)
+        wall = time.perf_counter() - t
+        out["batch_oracle"] = {
+            "solves_per_s": len(ids) / wall, "seconds": wall, "processes": workers,
+            "sample": "every 8th of the 256 batched CN-FCT instances (%d instances, %d nodes), 20 steps each, "
+                      "one process per instance, numpy FP64" % (len(ids), sum(r[0] for r in res)),
+            "cpu_seconds": sum(r[1] for r in res),
+        }
+    return out
 
 
-def solve_to_tolerance(afc, torch, inst, make_opts, rel_tol, cap, chunk, lin_eta=0.0, label=""):
+def solve_to_tolerance(afc, torch, inst, make_opts, rel_tol, cap, lin_eta=0.0, dynamic_damping=1, label=""):
     """The stationary problem solved to its own stopping rule, R <= rel_tol R_0
-    (R_0: the nonlinear residual at the low-order start), as one user would
-    run it: the low-order solve, then fixed-point iterations until the rule
-    holds or `cap` iterations have run.  The iterations run in calls of
-    `chunk` (each stops early once the rule holds, through the equivalent
-    absolute test R < sqrt(N) tol), so that the residual is recorded every
-    `chunk` iterations; each call adds one residual evaluation (~0.5 ms at
-    128^3) to the time.  Returns counts, seconds and the residual curve."""
+    (R_0: the nonlinear residual at the low-order start), as a user runs it:
+    the low-order solve, then one afc_solve_stationary call that iterates
+    until the rule holds or `cap` iterations have run.  The residual curve
+    comes from the library's residual history of that call.  Returns counts,
+    seconds and the curve (R / R_0 every 10 iterations)."""
     N = inst.N
     dev = torch.device("cuda:0")
     h = afc.afc_create_instance(inst, make_opts(fp_maxit=0, lin_eta=lin_eta), conv=True)
@@ -124,46 +213,36 @@ def solve_to_tolerance(afc, torch, inst, make_opts, rel_tol, cap, chunk, lin_eta
         _, s0 = afc.afc_solve_stationary(h, u, F, init_low_order=True, raise_on_error=False)
         torch.cuda.synchronize()
         t_low = time.perf_counter() - t0
-        R0 = s0["res0"]
-        curve = [[0, 1.0]]
-        fp = kr = 0
-        status = 1
-        t_fp = 0.0
-        o = make_opts(fp_maxit=chunk, fp_tol=rel_tol * R0 / math.sqrt(N), fp_tol_mode=afc.AFC_TOL_ABS_SQRTN,
-                      lin_eta=lin_eta)
-        afc.afc_set_options(h, o)
-        while fp < cap:
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            st, s = afc.afc_solve_stationary(h, u, F, raise_on_error=False)
-            torch.cuda.synchronize()
-            t_fp += time.perf_counter() - t0
-            fp += s["fp_iters"]
-            kr += s["krylov_iters"]
-            curve.append([fp, s["res"] / R0])
-            if st < 0:
-                status = st
-                break
-            if st == 0:
-                status = 0
-                break
-            if len(curve) % 10 == 0:
-                print("bench: %s solve: %d iterations, R/R0 = %.3e, %.1f s" % (label, fp, s["res"] / R0, t_fp),
-                      file=sys.stderr, flush=True)
+        afc.afc_set_options(h, make_opts(fp_maxit=cap, fp_tol=rel_tol, fp_tol_mode=afc.AFC_TOL_REL,
+                                         lin_eta=lin_eta, dynamic_damping=dynamic_damping))
+        print("bench: %s solve to R <= %g R0 (cap %d)" % (label, rel_tol, cap), file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, s = afc.afc_solve_stationary(h, u, F, raise_on_error=False)
+        torch.cuda.synchronize()
+        t_fp = time.perf_counter() - t0
+        hist = afc.afc_residual_history(h)
         x_min, x_max = float(u.min()), float(u.max())
     finally:
         afc.afc_destroy(h)
-    tail = [c for c in curve if c[0] >= curve[-1][0] // 2 and c[1] > 0]
+    R0 = float(hist[0])
+    rel = hist / R0
+    fp = s["fp_iters"]
+    half = fp // 2
     contraction = None
-    if len(tail) >= 2 and tail[-1][0] > tail[0][0]:
-        contraction = (tail[-1][1] / tail[0][1]) ** (1.0 / (tail[-1][0] - tail[0][0]))
+    if fp >= 2 and rel[half] > 0 and rel[fp] > 0:
+        contraction = float((rel[fp] / rel[half]) ** (1.0 / (fp - half)))
+    curve = [[k, float("%.4g" % rel[k])] for k in range(0, len(rel), 10)]
+    if curve[-1][0] != len(rel) - 1:
+        curve.append([len(rel) - 1, float("%.4g" % rel[-1])])
     return {
-        "status": status, "reached": status == 0, "fp_iters": fp, "krylov_iters": kr,
-        "krylov_per_fp_iter": kr / max(1, fp), "seconds": t_fp, "low_order_seconds": t_low,
-        "low_order_krylov_iters": s0["krylov_iters"], "R0": R0, "final_rel_residual": curve[-1][1],
-        "contraction_last_half": contraction, "ms_per_iteration": 1e3 * t_fp / max(1, fp),
-        "solution_range": [x_min, x_max], "lin_eta": lin_eta,
-        "residual_curve": [[c[0], float("%.4g" % c[1])] for c in curve],
+        "status": st, "reached": st == 0, "fp_iters": fp, "krylov_iters": s["krylov_iters"],
+        "krylov_per_fp_iter": s["krylov_iters"] / max(1, fp), "seconds": t_fp,
+        "low_order_seconds": t_low, "low_order_krylov_iters": s0["krylov_iters"], "R0": R0,
+        "final_rel_residual": float(rel[-1]), "contraction_last_half": contraction,
+        "ms_per_iteration": 1e3 * t_fp / max(1, fp), "solution_range": [x_min, x_max],
+        "lin_eta": lin_eta, "dynamic_damping": dynamic_damping,
+        "residual_curve": curve,
     }
 
 
@@ -577,8 +656,17 @@ def main():
                     help="GMRES basis block size s (0: one vector per step; 2..8: s-step blocks)")
     ap.add_argument("--classical-steps", type=int, default=5,
                     help="steps timed again with one basis vector per Arnoldi step (secondary)")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-n", type=int, default=64,
+                    help="mesh of the oracle's first-iteration sample (cells per direction)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch-oracle", action="store_true", help="leave out the batched-CN oracle sample")
+    ap.add_argument("--cpu-baseline-only", action="store_true",
+                    help="only time the oracle's first iteration on --cpu-n (and the GPU on the same sample)")
+    ap.add_argument("--solve-cap", type=int, default=8000,
+                    help="fixed-point cap of the solves run to the stopping rule R <= 1e-8 R0")
+    ap.add_argument("--no-solve", action="store_true", help="leave out the solves run to the stopping rule")
+    ap.add_argument("--no-strict-solve", action="store_true",
+                    help="run the stopping-rule solve with inexact linear solves only")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cn", action="store_true")
@@ -613,6 +701,9 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.cpu_baseline_only:
+        print(json.dumps(cpu_baseline(args.cpu_n, gpu_first_iteration(afc, torch, I, args.cpu_n, args.sstep), False)))
+        return
     print("bench: building Q1 %d^3 MCL instance" % args.n, file=sys.stderr, flush=True)
     inst = I.config3(args.n)
     N, nnz = inst.N, inst.nnz
@@ -763,10 +854,27 @@ def main():
         print("bench: serving", file=sys.stderr, flush=True)
         serve = bench_serve(afc, torch, I, args.serve_requests, args.serve_slots)
 
+    solve = None
+    if not args.no_solve:
+        def solve_opts(**kw):
+            o = opts(**{k: v for k, v in kw.items() if k in ("fp_maxit", "sstep")})
+            for k, v in kw.items():
+                setattr(o, k, v)
+            return o
+
+        solve = {"rule": "R <= 1e-8 R0 from the low-order solution, dynamic damping (Sec. 4), cap %d"
+                         % args.solve_cap}
+        solve["inexact"] = solve_to_tolerance(afc, torch, inst, solve_opts, 1e-8, args.solve_cap, lin_eta=1e-2,
+                                              label="inexact (lin_eta 1e-2)")
+        if not args.no_strict_solve:
+            solve["strict"] = solve_to_tolerance(afc, torch, inst, solve_opts, 1e-8, args.solve_cap,
+                                                 label="strict (1e-10 ||b||)")
+
     cpu = None
     if not args.no_cpu_baseline:
         print("bench: cpu baseline", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(args.cpu_seconds)
+        cpu = cpu_baseline(args.cpu_n, gpu_first_iteration(afc, torch, I, args.cpu_n, args.sstep),
+                           not args.no_batch_oracle)
 
     line = {
         "metric": "AFC DOF-iterations/s at 128^3 Q1 (stationary MCL fixed-point iterations)",
@@ -800,6 +908,7 @@ def main():
         "batch": batch,
         "cn": cn,
         "serving": serve,
+        "solve_to_tolerance": solve,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

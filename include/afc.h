@@ -322,6 +322,15 @@ afc_status afc_sell_layout(int32_t n, const int32_t *row_ptr, const int32_t *col
                            int32_t *slice_ptr, int32_t *slice_delta, int32_t *pattern, int32_t *pos,
                            int32_t *lane_deltas);
 
+/* Nonlinear residuals R (Euclidean norm over non-Dirichlet rows, Sec. 4 and
+ * eq. (28)) of the last fixed-point call on h (afc_step_cn, afc_step_mc_cn,
+ * afc_solve_stationary): one value per evaluation, R_0 first, the value that
+ * ended the loop last.  Copies min(count, cap) values into out (host memory,
+ * may be NULL when cap = 0) and stores the full count in *count.  The history
+ * is kept until the next fixed-point call on h.  EINVAL on a NULL h or count,
+ * or cap < 0. */
+afc_status afc_residual_history(const afc_handle *h, double *out, int32_t cap, int32_t *count);
+
 /* Release every device and host resource of h (NULL is ignored). */
 void afc_destroy(afc_handle *h);
 

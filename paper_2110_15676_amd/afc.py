@@ -75,7 +75,7 @@ EXPORTS = [
     "afc_footprint_bytes", "afc_server_create", "afc_server_submit", "afc_server_wait", "afc_server_poll", "afc_server_last_error",
     "afc_server_destroy", "afc_get_sell_info", "afc_get_krylov_sell_info", "afc_sell_layout", "afc_kernel_work",
     "afc_batch_set_schedule", "afc_batch_get_schedule", "afc_batch_autotune", "afc_step_cn_linear",
-    "afc_step_mc_ssprk3", "afc_step_mc_cn", "afc_step_ssprk3_noalloc",
+    "afc_step_mc_ssprk3", "afc_step_mc_cn", "afc_step_ssprk3_noalloc", "afc_residual_history",
 ]
 
 AFC_REQ_CN, AFC_REQ_STATIONARY = 0, 1
@@ -155,6 +155,8 @@ def lib():
         L.afc_server_last_error.restype = c_char_p
         L.afc_server_destroy.argtypes = [c_void_p]
         L.afc_server_destroy.restype = None
+        L.afc_residual_history.argtypes = [c_void_p, POINTER(c_double), c_int32, POINTER(c_int32)]
+        L.afc_residual_history.restype = c_int32
         L.afc_destroy.argtypes = [c_void_p]
         L.afc_destroy.restype = None
         L.afc_status_str.argtypes = [c_int32]
@@ -320,6 +322,19 @@ def afc_solve_stationary(h, u, F, init_low_order=False, raise_on_error=True):
     stats = afc_stats()
     st = lib().afc_solve_stationary(h, u.data_ptr(), F.data_ptr(), int(bool(init_low_order)), ctypes.byref(stats))
     return _finish(h, st, stats, raise_on_error)
+
+
+def afc_residual_history(h):
+    """Nonlinear residuals of the last fixed-point call on h (numpy array)."""
+    n = c_int32()
+    st = lib().afc_residual_history(h, None, 0, ctypes.byref(n))
+    if st != AFC_OK:
+        raise AFCError(st, "afc_residual_history")
+    out = np.zeros(max(1, n.value))
+    st = lib().afc_residual_history(h, out.ctypes.data_as(POINTER(c_double)), n.value, ctypes.byref(n))
+    if st != AFC_OK:
+        raise AFCError(st, "afc_residual_history")
+    return out[:n.value]
 
 
 def afc_kernel_time(h, kernel, reset=False):

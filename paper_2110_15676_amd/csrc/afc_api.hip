@@ -537,10 +537,12 @@ afc_status fixed_point(afc_handle* h, double* u, const SysMat& S, Eval eval, afc
   double omega = h->opt.omega;
   afc_status status = AFC_OK;
   int nu = 0;
+  h->res_hist.clear();
   while (true) {
     eval(u, b, r);
     sync_status(h);
     const double R = std::sqrt(h->host_status->red[0]);
+    h->res_hist.push_back(R);
     const double bn = std::sqrt(h->host_status->red[1]);
     if (!std::isfinite(R) || !std::isfinite(bn)) {
       status = AFC_ENAN;
@@ -1093,6 +1095,15 @@ afc_status afc_get_sell_info(const afc_handle* h, afc_sell_info* out) {
   out->pattern_ints = h->sell_pat_ints;
   out->delta_bytes = h->dlt16 ? 2 : 4;
   out->reserved = 0;
+  return AFC_OK;
+}
+
+afc_status afc_residual_history(const afc_handle* h, double* out, int32_t cap, int32_t* count) {
+  if (!h || !count || cap < 0 || (cap > 0 && !out)) return AFC_EINVAL;
+  const size_t n = h->res_hist.size();
+  *count = (int32_t)std::min<size_t>(n, (size_t)std::numeric_limits<int32_t>::max());
+  const size_t m = std::min<size_t>(n, (size_t)cap);
+  if (m) std::memcpy(out, h->res_hist.data(), m * sizeof(double));
   return AFC_OK;
 }
 

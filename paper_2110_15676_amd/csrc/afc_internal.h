@@ -69,6 +69,7 @@ struct afc_handle_s {
   hipStream_t stream = nullptr;
   int device = 0;
   std::string last_error;
+  std::vector<double> res_hist;  // nonlinear residuals of the last fixed-point call
 
   // pattern and node data (device)
   int* row_ptr = nullptr;

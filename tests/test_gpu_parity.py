@@ -391,6 +391,11 @@ def test_mcl_damped_fixed_point_parity(prec, omega, dyn):
             assert abs(stats["fp_iters"] - rst.iters) <= 2, (stats["fp_iters"], rst.iters)
         tol = 1e-10 if prec == 0 else 1e-8
         assert _rel(u.cpu().numpy(), ref) <= tol
+        # the residual history of the call: one value per evaluation, R_0 first
+        hist = afc.afc_residual_history(h)
+        assert hist.shape[0] == stats["fp_iters"] + 1
+        assert hist[-1] == stats["res"] and hist[0] == stats["res0"]
+        np.testing.assert_allclose(hist[:6], rst.residuals[:6], rtol=1e-6)
     finally:
         afc.afc_destroy(h)
 
