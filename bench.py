@@ -382,34 +382,38 @@ def bench_time_dependent(afc, torch, I, n, ssp_steps, cn_steps):
     return out
 
 
-def bench_serve(afc, torch, I, count, slots):
-    """Poisson arrivals (200/s) of mixed CN-FCT / stationary-MCL Q1 requests."""
+def serve_opts(afc, kind):
+    """Solver options of the serving workload: FP32-inner / FP64-outer GMRES;
+    CN to R < sqrt(N) 1e-12 per step, the stationary MCL solve to R <= 1e-8 R0
+    with the dynamic damping of Sec. 4 and inexact linear solves."""
+    if kind == "cn":
+        return afc.afc_default_options(precision=afc.AFC_PREC_MIXED, fp_tol=1e-12, fp_maxit=50, lin_atol=1e-13)
+    return afc.afc_default_options(precision=afc.AFC_PREC_MIXED, fp_tol=1e-8, fp_tol_mode=afc.AFC_TOL_REL,
+                                   fp_maxit=20000, lin_atol=0.0, lin_rtol=1e-10, lin_maxit=5000, dynamic_damping=1,
+                                   lin_eta=1e-2)
+
+
+def serve_run(afc, reqs, insts, rate, cfg):
+    """Submit the requests at their arrival times (scaled to `rate`), wait for
+    all; returns latencies, wall time, statuses and the server's round counts."""
     import threading
 
     import numpy as np
 
-    reqs = I.config5_requests(count)
-    insts = [I.config5_instance(r) for r in reqs]
-
-    def opts(kind):
-        if kind == "cn":
-            return afc.afc_default_options(precision=afc.AFC_PREC_MIXED, fp_tol=1e-12, fp_maxit=50, lin_atol=1e-13)
-        return afc.afc_default_options(precision=afc.AFC_PREC_MIXED, fp_tol=1e-8, fp_tol_mode=afc.AFC_TOL_REL,
-                                       fp_maxit=300, lin_atol=0.0, lin_rtol=1e-10, lin_maxit=5000)
-
-    free, _ = torch.cuda.mem_get_info()
-    s = afc.afc_server_create(slots, int(0.8 * free))
-    ids = [None] * count
+    s = afc.afc_server_create_cfg(cfg)
+    ids = [None] * len(reqs)
+    scale = 200.0 / rate  # the seeded arrival times are for 200 requests/s
     t0 = time.perf_counter()
 
     def submitter():
         for k, (r, inst) in enumerate(zip(reqs, insts)):
-            d = r["arrival"] - (time.perf_counter() - t0)
+            d = scale * r["arrival"] - (time.perf_counter() - t0)
             if d > 0:
                 time.sleep(d)
             kind = afc.AFC_REQ_CN if r["kind"] == "cn" else afc.AFC_REQ_STATIONARY
-            ids[k] = afc.afc_server_submit(s, kind, inst, opts(r["kind"]), u0=inst.u0 if r["kind"] == "cn" else None,
-                                           dt=1e-3, steps=20, conv=r["kind"] == "mcl")
+            ids[k] = afc.afc_server_submit(s, kind, inst, serve_opts(afc, r["kind"]),
+                                           u0=inst.u0 if r["kind"] == "cn" else None, dt=1e-3, steps=20,
+                                           conv=r["kind"] == "mcl")
 
     th = threading.Thread(target=submitter)
     th.start()
@@ -417,17 +421,86 @@ def bench_serve(afc, torch, I, count, slots):
     res = []
     for k, (rid, inst) in enumerate(zip(ids, insts)):
         res.append(afc.afc_server_wait(s, rid, inst.N))
-        print("bench: request %d/%d done" % (k + 1, count), file=sys.stderr, flush=True)
+        if (k + 1) % 25 == 0:
+            print("bench: serving at %.3g/s: %d/%d done" % (rate, k + 1, len(reqs)), file=sys.stderr, flush=True)
     wall = time.perf_counter() - t0
+    rounds, carried, _ = afc.afc_server_info(s)
     afc.afc_server_destroy(s)
     lat = np.array([r[3][2] for r in res])
+    mcl = [r for r, q in zip(res, reqs) if q["kind"] == "mcl"]
     return {
-        "workload": "%d requests, Poisson 200/s, CN-FCT (20 steps) / stationary MCL (rel 1e-8, <= 300 its), "
-                    "Q1 n log-uniform 16..96, FP32-inner/FP64-outer" % count,
-        "slots": slots, "solves_per_s": count / wall, "seconds": wall,
+        "requests": len(reqs), "arrival_rate": rate, "solves_per_s": len(reqs) / wall, "seconds": wall,
         "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
-        "statuses": sorted(set(int(r[0]) for r in res)),
-        "mean_nodes": float(np.mean([i.N for i in insts])),
+        "statuses": {str(k): int(v) for k, v in zip(*np.unique([r[0] for r in res], return_counts=True))},
+        "mcl_reached_1e-8": sum(1 for r in mcl if r[0] == 0), "mcl_requests": len(mcl),
+        "fused_rounds": rounds, "requests_per_round": carried / max(1, rounds),
+    }, [r[1] for r in res]
+
+
+def one_at_a_time(afc, torch, reqs, insts):
+    """The same requests solved one after another on their own handle with the
+    same options (setup included, as a served request's is)."""
+    t0 = time.perf_counter()
+    out = []
+    for r, inst in zip(reqs, insts):
+        o = serve_opts(afc, r["kind"])
+        o.stream = torch.cuda.current_stream().cuda_stream
+        h = afc.afc_create_instance(inst, o, conv=r["kind"] == "mcl")
+        try:
+            F = torch.tensor(inst.F, device="cuda:0")
+            if r["kind"] == "cn":
+                u = torch.tensor(inst.u0, device="cuda:0")
+                for _ in range(20):
+                    afc.afc_step_cn(h, u, F, F, 1e-3, raise_on_error=False)
+            else:
+                u = torch.zeros(inst.N, dtype=torch.float64, device="cuda:0")
+                afc.afc_solve_stationary(h, u, F, init_low_order=True, raise_on_error=False)
+            out.append(u.cpu().numpy())
+        finally:
+            afc.afc_destroy(h)
+    wall = time.perf_counter() - t0
+    return {"solves_per_s": len(reqs) / wall, "seconds": wall, "requests": len(reqs)}, out
+
+
+def bench_serve(afc, torch, I, count, sample_every):
+    """Serving workload (Q1 n log-uniform 16..96, CN-FCT 20 steps or
+    stationary MCL to 1e-8 R0): `count` Poisson arrivals at 200/s; half as
+    many at 0.8 x the saturation rate measured there; and every
+    `sample_every`-th request, served at 200/s and solved one at a time (the
+    same requests both ways)."""
+    import numpy as np
+
+    reqs = I.config5_requests(count)
+    insts = [I.config5_instance(r) for r in reqs]
+    cfg = afc.afc_server_default_config()
+    print("bench: serving %d requests at 200/s" % count, file=sys.stderr, flush=True)
+    at200, _ = serve_run(afc, reqs, insts, 200.0, cfg)
+    sat = at200["solves_per_s"]
+    half = max(1, count // 2)
+    print("bench: serving %d requests at %.3g/s" % (half, 0.8 * sat), file=sys.stderr, flush=True)
+    sustainable, _ = serve_run(afc, reqs[:half], insts[:half], 0.8 * sat, cfg)
+    pick = list(range(0, count, sample_every))
+    sub_r, sub_i = [reqs[k] for k in pick], [insts[k] for k in pick]
+    print("bench: %d requests served and one at a time" % len(pick), file=sys.stderr, flush=True)
+    served_sub, u_srv = serve_run(afc, sub_r, sub_i, 200.0, cfg)
+    seq, u_seq = one_at_a_time(afc, torch, sub_r, sub_i)
+    diff = max(float(np.abs(a - b).max() / max(np.abs(a).max(), 1e-300)) for a, b in zip(u_seq, u_srv))
+    nodes = np.array([i.N for i in insts])
+    return {
+        "workload": "%d requests, Poisson arrivals, CN-FCT (20 steps, dt 1e-3) / stationary MCL (R <= 1e-8 R0, "
+                    "dynamic damping, lin_eta 1e-2), Q1 n log-uniform 16..96, FP32-inner/FP64-outer options" % count,
+        "config": {"slots": cfg.slots, "fuse_max_nodes": cfg.fuse_max_nodes, "loop_threads": cfg.loop_threads,
+                   "quantum_ms": cfg.quantum_ms},
+        "fused_lane_requests": int(np.sum(nodes <= cfg.fuse_max_nodes)),
+        "mean_nodes": float(nodes.mean()),
+        "at_200_per_s": at200,
+        "at_0.8x_saturation": sustainable,
+        "same_requests": {
+            "sample": "every %d-th request (%d requests)" % (sample_every, len(pick)),
+            "served_at_200_per_s": served_sub, "one_at_a_time": seq,
+            "served_vs_one_at_a_time": served_sub["solves_per_s"] / seq["solves_per_s"],
+            "max_rel_diff": diff,
+        },
     }
 
 
@@ -670,8 +743,10 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cn", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=24)
-    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-sample", type=int, default=4,
+                    help="every k-th served request is also solved one at a time")
+    ap.add_argument("--serve-only", action="store_true", help="only run the serving workload")
     ap.add_argument("--accuracy", action="store_true",
                     help="only run the paper's analytic accuracy examples (rotating shapes, circular convection)")
     ap.add_argument("--accuracy-n", type=int, default=64, help="cells per direction of the rotating-shapes mesh")
@@ -701,6 +776,9 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.serve_only:
+        print(json.dumps(bench_serve(afc, torch, I, args.serve_requests, args.serve_sample)))
+        return
     if args.cpu_baseline_only:
         print(json.dumps(cpu_baseline(args.cpu_n, gpu_first_iteration(afc, torch, I, args.cpu_n, args.sstep), False)))
         return
@@ -852,7 +930,7 @@ def main():
     serve = None
     if not args.no_serve:
         print("bench: serving", file=sys.stderr, flush=True)
-        serve = bench_serve(afc, torch, I, args.serve_requests, args.serve_slots)
+        serve = bench_serve(afc, torch, I, args.serve_requests, args.serve_sample)
 
     solve = None
     if not args.no_solve:

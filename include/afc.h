@@ -55,7 +55,8 @@ typedef enum {
   AFC_ENOCONV = -3,      /* linear solver did not converge within its cap     */
   AFC_EBREAKDOWN = -4,   /* BiCGStab breakdown (rho or omega = 0) twice       */
   AFC_ENAN = -5,         /* a norm became non-finite                          */
-  AFC_EDEVICE = -6       /* HIP runtime error                                 */
+  AFC_EDEVICE = -6,      /* HIP runtime error                                 */
+  AFC_ECANCELED = -7     /* request dropped by afc_server_destroy             */
 } afc_status;
 
 enum { AFC_MEM_HOST = 0, AFC_MEM_DEVICE = 1 };
@@ -390,17 +391,32 @@ afc_status afc_batch_autotune(afc_batch *b, const double *u, const double *F, co
 void afc_batch_destroy(afc_batch *b);
 
 /* ---- Request server (continuous batching) ---------------------------------
- * Requests are copied at submission and queued; a scheduler admits them in
- * arrival order whenever one of `slots` slots is free and the modelled device
- * footprint (afc_footprint_bytes) of the running set stays within the HBM
- * budget.  Each slot runs its request on its own HIP stream, so requests
- * overlap on the device; a finished request frees its slot for the next one.
- * A request's result is independent of the other requests. */
+ * Requests are copied at submission and served on the current device by two
+ * lanes that run concurrently.
+ *   Fused lane (N <= fuse_max_nodes; CN, or stationary MCL): host setup
+ *   threads build the request's operators (eqs. (4)-(6)) and SELL layout and
+ *   upload them into a device block of its own.  A round thread then runs the
+ *   active requests in rounds: each round is one launch in which every active
+ *   request advances by up to quantum_ms (at least one fixed-point iteration)
+ *   in a workgroup of its own, resuming from the state it left in device
+ *   memory.  Requests that become ready join the next round; finished ones
+ *   leave.  This lane runs BiCGStab-Jacobi in FP64 whatever options.krylov
+ *   and options.precision say; tolerances, iteration caps, alpha_mode,
+ *   prelimit, omega, dynamic_damping and lin_eta are honoured.
+ *   Dedicated lane (larger requests, and the MU limiter): `slots` worker
+ *   threads, each with its own stream, run one request at a time end to end
+ *   on a handle of its own with the request's options.
+ * Admission is per lane in arrival order while the device footprint of the
+ * admitted requests fits hbm_budget_bytes (and, for the dedicated lane, a slot
+ * is free).  A request's result does not depend on the other requests in
+ * flight, on the quantum or on the workgroup that ran it (fixed reduction
+ * orders). */
 enum { AFC_REQ_CN = 0, AFC_REQ_STATIONARY = 1 };
 
 typedef struct {
   int32_t kind;          /* AFC_REQ_CN: `steps` CN-FCT steps of length dt;
-                            AFC_REQ_STATIONARY: MCL stationary solve        */
+                            AFC_REQ_STATIONARY: stationary solve (options.
+                            limiter: MCL or MU)                              */
   afc_problem problem;   /* host arrays (mem_space must be AFC_MEM_HOST)     */
   const double *u0;      /* host [N]: CN initial state (required); stationary
                             initial guess, NULL = the low-order solution     */
@@ -412,19 +428,43 @@ typedef struct {
 
 typedef struct afc_server_s afc_server;
 
-/* Modelled device bytes a request of this size keeps resident. */
-int64_t afc_footprint_bytes(int32_t n, int64_t nnz, int32_t kind, const afc_options *opt);
+typedef struct {
+  int32_t slots;            /* dedicated-lane slots (streams), 1..64         */
+  int64_t hbm_budget_bytes; /* admission budget over both lanes (> 0)        */
+  int32_t fuse_max_nodes;   /* requests with N <= this use the fused lane;
+                               0 = every request is dedicated               */
+  int32_t loop_threads;     /* fused-lane workgroup size: 256, 512 or 1024   */
+  int32_t loop_workgroups;  /* workgroups per round; 0 = one per compute unit */
+  int32_t setup_threads;    /* host threads preparing fused requests, 1..32  */
+  int32_t max_active;       /* fused requests in flight at most, 1..65536    */
+  double quantum_ms;        /* time slice of a request in one round (>= 0;
+                               0 = run each request to completion)          */
+} afc_server_config;
 
-/* Start a server with `slots` concurrent slots (1..64) on the current device. */
+/* Defaults: 4 slots, 64 GiB budget, fuse_max_nodes 20000, 1024 threads, one
+ * workgroup per compute unit, 4 setup threads, 512 active, 2 ms quantum. */
+void afc_server_default_config(afc_server_config *cfg);
+
+/* Start a server with the given configuration on the current device.
+ * EINVAL for a configuration outside the ranges above. */
+afc_status afc_server_create_cfg(const afc_server_config *cfg, afc_server **out);
+
+/* Start a server with the default configuration and `slots` dedicated slots
+ * (1..64) within hbm_budget_bytes. */
 afc_status afc_server_create(int32_t slots, int64_t hbm_budget_bytes, afc_server **out);
+
+/* Modelled device bytes a dedicated-lane request of this size keeps resident. */
+int64_t afc_footprint_bytes(int32_t n, int64_t nnz, int32_t kind, const afc_options *opt);
 
 /* Queue a request (inputs are copied; returns at once); *id identifies it. */
 afc_status afc_server_submit(afc_server *s, const afc_request *req, int64_t *id);
 
 /* Block until request id has finished.  u_out: NULL or host [N] for the
  * result; stats: NULL or its statistics; times: NULL or 3 doubles (seconds
- * queued, seconds in service, submit-to-completion latency).  Returns the
- * request's status.  Each id can be waited for once. */
+ * from submission to admission, seconds of setup and service, submit-to-
+ * completion latency).  Returns the request's status (AFC_ECANCELED if
+ * afc_server_destroy dropped it).  Each id can be waited for once; a second
+ * wait or poll on it returns AFC_EINVAL. */
 afc_status afc_server_wait(afc_server *s, int64_t id, double *u_out, afc_stats *stats, double *times);
 
 /* Non-blocking completion check: *done = 1 once request id has finished
@@ -432,12 +472,17 @@ afc_status afc_server_wait(afc_server *s, int64_t id, double *u_out, afc_stats *
  * AFC_EINVAL for an unknown id or one already waited for. */
 afc_status afc_server_poll(afc_server *s, int64_t id, int32_t *done);
 
+/* Rounds run by the fused lane so far, the requests those rounds carried
+ * (summed over rounds: divided by the rounds, the mean number of requests
+ * per fused launch) and the footprint admitted now.  Any pointer may be NULL. */
+afc_status afc_server_info(const afc_server *s, int64_t *rounds, int64_t *request_rounds, int64_t *in_use_bytes);
+
 /* Message of the last failed request or call (empty if none). */
 const char *afc_server_last_error(const afc_server *s);
 
-/* Stop the server: running requests finish, queued ones are dropped (their
- * ids can no longer be waited for).  Call it once every other thread's
- * submit and wait calls on s have returned; s is freed. */
+/* Stop the server: admitted requests finish, requests not yet admitted end
+ * with AFC_ECANCELED, threads blocked in afc_server_wait return, then s is
+ * freed.  No submit, wait or poll may start once this call has begun. */
 void afc_server_destroy(afc_server *s);
 
 /* Static description of a status code. */

@@ -20,7 +20,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libafc.so")
 
 AFC_OK, AFC_WMAXIT = 0, 1
-AFC_EINVAL, AFC_ENOMEM, AFC_ENOCONV, AFC_EBREAKDOWN, AFC_ENAN, AFC_EDEVICE = -1, -2, -3, -4, -5, -6
+AFC_EINVAL, AFC_ENOMEM, AFC_ENOCONV, AFC_EBREAKDOWN, AFC_ENAN, AFC_EDEVICE, AFC_ECANCELED = -1, -2, -3, -4, -5, -6, -7
 AFC_MEM_HOST, AFC_MEM_DEVICE = 0, 1
 AFC_ALPHA_LIMITED, AFC_ALPHA_ONE, AFC_ALPHA_ZERO = 0, 1, 2
 AFC_KRYLOV_BICGSTAB, AFC_KRYLOV_GMRES = 0, 1
@@ -58,6 +58,13 @@ class afc_request(ctypes.Structure):
     ]
 
 
+class afc_server_config(ctypes.Structure):
+    _fields_ = [
+        ("slots", c_int32), ("hbm_budget_bytes", c_int64), ("fuse_max_nodes", c_int32), ("loop_threads", c_int32),
+        ("loop_workgroups", c_int32), ("setup_threads", c_int32), ("max_active", c_int32), ("quantum_ms", c_double),
+    ]
+
+
 class afc_stats(ctypes.Structure):
     _fields_ = [
         ("status", c_int32), ("fp_iters", c_int32), ("krylov_iters", c_int64), ("inner_iters", c_int64),
@@ -76,6 +83,7 @@ EXPORTS = [
     "afc_server_destroy", "afc_get_sell_info", "afc_get_krylov_sell_info", "afc_sell_layout", "afc_kernel_work",
     "afc_batch_set_schedule", "afc_batch_get_schedule", "afc_batch_autotune", "afc_step_cn_linear",
     "afc_step_mc_ssprk3", "afc_step_mc_cn", "afc_step_ssprk3_noalloc", "afc_residual_history",
+    "afc_server_default_config", "afc_server_create_cfg", "afc_server_info",
 ]
 
 AFC_REQ_CN, AFC_REQ_STATIONARY = 0, 1
@@ -145,6 +153,12 @@ def lib():
         L.afc_footprint_bytes.restype = c_int64
         L.afc_server_create.argtypes = [c_int32, c_int64, POINTER(c_void_p)]
         L.afc_server_create.restype = c_int32
+        L.afc_server_default_config.argtypes = [POINTER(afc_server_config)]
+        L.afc_server_default_config.restype = None
+        L.afc_server_create_cfg.argtypes = [POINTER(afc_server_config), POINTER(c_void_p)]
+        L.afc_server_create_cfg.restype = c_int32
+        L.afc_server_info.argtypes = [c_void_p, POINTER(c_int64), POINTER(c_int64), POINTER(c_int64)]
+        L.afc_server_info.restype = c_int32
         L.afc_server_submit.argtypes = [c_void_p, POINTER(afc_request), POINTER(c_int64)]
         L.afc_server_submit.restype = c_int32
         L.afc_server_wait.argtypes = [c_void_p, c_int64, c_void_p, POINTER(afc_stats), POINTER(c_double)]
@@ -505,6 +519,34 @@ def afc_batch_destroy(b):
 def afc_footprint_bytes(n, nnz, kind, opts=None):
     o = opts if opts is not None else afc_default_options()
     return int(lib().afc_footprint_bytes(int(n), int(nnz), int(kind), ctypes.byref(o)))
+
+
+def afc_server_default_config(**overrides):
+    c = afc_server_config()
+    lib().afc_server_default_config(ctypes.byref(c))
+    for k, v in overrides.items():
+        setattr(c, k, v)
+    return c
+
+
+def afc_server_create_cfg(cfg):
+    s = c_void_p()
+    st = lib().afc_server_create_cfg(ctypes.byref(cfg), ctypes.byref(s))
+    if st != AFC_OK:
+        raise AFCError(st, "afc_server_create_cfg")
+    return s
+
+
+def afc_server_info(s):
+    """(rounds run by the fused lane, requests carried summed over rounds,
+    admitted footprint in bytes)."""
+    rounds = c_int64()
+    carried = c_int64()
+    used = c_int64()
+    st = lib().afc_server_info(s, ctypes.byref(rounds), ctypes.byref(carried), ctypes.byref(used))
+    if st != AFC_OK:
+        raise AFCError(st, "afc_server_info")
+    return rounds.value, carried.value, used.value
 
 
 def afc_server_create(slots, hbm_budget_bytes):

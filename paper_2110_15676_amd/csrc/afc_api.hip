@@ -832,6 +832,164 @@ void* noalloc_scratch(afc_handle* h, int dev) {
 
 
 
+// ---------------------------------------------------------------------------
+// Host setup of a request of the served loop (see afc_batch_internal.h)
+// ---------------------------------------------------------------------------
+
+namespace afc {
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+struct BlockLayout {
+  int64_t slots = 0, ldw = 0;
+  size_t off[15] = {};
+  size_t upload = 0, total = 0;
+};
+
+// Offsets of the arrays inside a request block, in upload order.
+BlockLayout block_layout(int N, int64_t slots, int kind) {
+  BlockLayout L;
+  L.slots = slots;
+  L.ldw = (N + 31) / 32 * 32;
+  const int nsl = (N + 63) / 64;
+  const bool cn = kind == AFC_REQ_CN;
+  size_t at = 0;
+  auto put = [&](int idx, size_t bytes) {
+    L.off[idx] = at;
+    at = align256(at + std::max<size_t>(bytes, 1));
+  };
+  put(0, sizeof(int) * (size_t)(nsl + 1));         // slp
+  put(1, sizeof(int16_t) * (size_t)slots);         // dlt
+  if (cn) {
+    put(2, 8 * (size_t)slots);                     // mij
+    put(3, 8 * (size_t)slots);                     // dp
+    put(4, 8 * (size_t)slots);                     // AL
+    put(5, 8 * (size_t)N);                         // ml
+  } else {
+    put(6, 8 * (size_t)slots);                     // cc
+    put(7, 8 * (size_t)slots);                     // ccT
+    put(8, 8 * (size_t)slots);                     // A (A_low of MCL)
+    put(9, 8 * (size_t)N);                         // dinv
+  }
+  put(10, 8 * (size_t)N);                          // uD
+  put(11, (size_t)N);                              // isd
+  put(12, 8 * (size_t)N);                          // F
+  put(13, 8 * (size_t)N);                          // u
+  L.upload = at;
+  if (cn) {
+    put(8, 8 * (size_t)slots);                     // A: CN matrix, built on the device
+    put(9, 8 * (size_t)N);                         // dinv
+  }
+  put(14, 8 * (size_t)L.ldw * (size_t)serve_work_vectors());  // work vectors
+  L.total = at;
+  return L;
+}
+
+int64_t sell_slots(int N, const int32_t* rp) {
+  int64_t slots = 0;
+  for (int s0 = 0; s0 < N; s0 += 64) {
+    int L = 0;
+    for (int i = s0; i < std::min(N, s0 + 64); ++i) L = std::max(L, rp[i + 1] - rp[i]);
+    slots += 64 * (int64_t)L;
+  }
+  return slots;
+}
+
+}  // namespace
+
+size_t serve_block_bytes(int N, const int32_t* rp, int kind) {
+  return block_layout(N, sell_slots(N, rp), kind).total;
+}
+
+afc_status serve_prepare(const afc_problem* p, int kind, const double* u0, const double* F, ServeImage& img,
+                         std::string* err) {
+  afc_handle* h = nullptr;  // fail() records messages only in the thrown Fail
+  try {
+    HostOps ops;
+    prepare_ops(h, p, ops);
+    const int N = ops.N;
+    const int nsl = (N + 63) / 64;
+    const bool cn = kind == AFC_REQ_CN;
+    const BlockLayout L = block_layout(N, sell_slots(N, ops.rp.data()), kind);
+    img.N = N;
+    img.nsl = nsl;
+    img.slots = L.slots;
+    img.ldw = L.ldw;
+    img.upload_bytes = L.upload;
+    img.block_bytes = L.total;
+    img.off_slp = L.off[0];
+    img.off_dlt = L.off[1];
+    img.off_mij = L.off[2];
+    img.off_dp = L.off[3];
+    img.off_AL = L.off[4];
+    img.off_ml = L.off[5];
+    img.off_cc = L.off[6];
+    img.off_ccT = L.off[7];
+    img.off_A = L.off[8];
+    img.off_dinv = L.off[9];
+    img.off_uD = L.off[10];
+    img.off_isd = L.off[11];
+    img.off_F = L.off[12];
+    img.off_u = L.off[13];
+    img.off_work = L.off[14];
+    img.bytes.assign(L.upload, 0);
+    unsigned char* base = img.bytes.data();
+    auto arr = [&](size_t off) { return base + off; };
+    int* slp = reinterpret_cast<int*>(arr(L.off[0]));
+    int16_t* dlt = reinterpret_cast<int16_t*>(arr(L.off[1]));
+    slp[0] = 0;
+    for (int sl = 0; sl < nsl; ++sl) {
+      int Lr = 0;
+      for (int i = sl * 64; i < std::min(N, sl * 64 + 64); ++i) Lr = std::max(Lr, ops.rp[i + 1] - ops.rp[i]);
+      slp[sl + 1] = slp[sl] + 64 * Lr;
+    }
+    double* v0 = reinterpret_cast<double*>(arr(cn ? L.off[2] : L.off[6]));  // mij | cc
+    double* v1 = reinterpret_cast<double*>(arr(cn ? L.off[3] : L.off[7]));  // dp  | ccT
+    double* v2 = reinterpret_cast<double*>(arr(cn ? L.off[4] : L.off[8]));  // AL  | A_low (MCL)
+    for (int i = 0; i < N; ++i) {
+      const int sl = i / 64, lane = i % 64;
+      int pcount = 1;
+      for (int k = ops.rp[i]; k < ops.rp[i + 1]; ++k) {
+        const int j = ops.col[k];
+        const int pos = (j == i) ? 0 : pcount++;
+        const size_t slot = (size_t)slp[sl] + 64 * (size_t)pos + lane;
+        if (std::abs(j - i) > 32767) throw Fail{AFC_EINVAL, "request bandwidth exceeds 16-bit column deltas"};
+        dlt[slot] = (int16_t)(j - i);
+        if (cn) {
+          v0[slot] = ops.M[k];
+          v1[slot] = ops.dp[k];
+          v2[slot] = ops.AL[k];
+        } else {
+          v0[slot] = ops.c[k];
+          v1[slot] = ops.cT[k];
+          v2[slot] = ops.ALc[k];
+        }
+      }
+    }
+    if (cn)
+      std::memcpy(arr(L.off[5]), ops.ml.data(), 8 * (size_t)N);
+    else
+      std::memcpy(arr(L.off[9]), ops.dinv.data(), 8 * (size_t)N);
+    std::memcpy(arr(L.off[10]), ops.uD.data(), 8 * (size_t)N);
+    std::memcpy(arr(L.off[11]), ops.is_dir.data(), (size_t)N);
+    for (int i = 0; i < N; ++i)
+      if (!std::isfinite(F[i]) || (u0 && !std::isfinite(u0[i]))) throw Fail{AFC_ENAN, "non-finite F or u0"};
+    std::memcpy(arr(L.off[12]), F, 8 * (size_t)N);
+    if (u0) std::memcpy(arr(L.off[13]), u0, 8 * (size_t)N);
+  } catch (const Fail& f) {
+    if (err) *err = f.msg;
+    return f.st;
+  } catch (...) {
+    if (err) *err = "host allocation failed";
+    return AFC_ENOMEM;
+  }
+  return AFC_OK;
+}
+
+}  // namespace afc
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -875,6 +1033,7 @@ const char* afc_status_str(int32_t s) {
     case AFC_EBREAKDOWN: return "BiCGStab breakdown";
     case AFC_ENAN: return "non-finite value";
     case AFC_EDEVICE: return "HIP runtime error";
+    case AFC_ECANCELED: return "request cancelled";
     default: return "unknown status";
   }
 }
@@ -1452,7 +1611,7 @@ afc_status afc_batch_create(int32_t count, const afc_problem* probs, const afc_o
     b->opt = o;
     b->stream = static_cast<hipStream_t>(o.stream);
     b->bopt = afc::BatchOpts{o.alpha_mode, o.fp_tol_mode, o.fp_maxit, o.lin_maxit, o.dynamic_damping,
-                             o.fp_tol, o.lin_atol, o.lin_rtol, o.prelimit, o.omega};
+                             o.fp_tol, o.lin_atol, o.lin_rtol, o.prelimit, o.omega, o.lin_eta};
     std::vector<int> slp;
     std::vector<int16_t> dlt;
     std::vector<double> mij, dp, AL, ml, uD;

@@ -273,27 +273,85 @@ __device__ int wg_bicgstab(const InstView& I, const double* b, double* x, double
   }
 }
 
+// True once the wall clock has passed `deadline` (< 0: never); the same
+// answer for every thread of the workgroup.
+__device__ bool past_deadline(int64_t deadline) {
+  __shared__ int flag;
+  if (deadline < 0) return false;
+  if (threadIdx.x == 0) flag = (int64_t)wall_clock64() > deadline ? 1 : 0;
+  __syncthreads();
+  const bool r = flag != 0;
+  __syncthreads();
+  return r;
+}
+
+// Damping rule of the fixed point (reading of Sec. 4): halve omega (not below
+// 1/64) when the residual grew, else omega <- min(1, 1.25 omega).
+__device__ __forceinline__ double next_omega(const BatchOpts& o, const SState& st, double R) {
+  if (!o.dynamic_damping || !st.have_prev) return st.omega;
+  return (R > st.R_prev) ? fmax(st.omega * 0.5, 1.0 / 64.0) : fmin(1.0, st.omega * 1.25);
+}
+
+// One fixed-point update of Sec. 4 after the residual R of the current
+// iterate: linear solve of A x = b from x = u (BiCGStab-Jacobi, stopping at
+// max(atol, rtol ||b||, lin_eta R)), then u <- u + omega (x - u).  r holds
+// b - A u (squared norm rr).  Returns false on a solver error (in st.status).
 template <int NT>
-__device__ void run_instance(const BInst& in, const BatchDev& D, const BatchOpts& o, int steps, double* ug,
-                             const double* Fg, BStat* stat) {
-  InstView I;
-  I.N = in.N;
-  I.nsl = in.nsl;
-  I.slp = D.slp + in.sl_off;
-  I.dlt = D.dlt + in.slot_off;
-  I.mij = D.mij + in.slot_off;
-  I.dp = D.dp + in.slot_off;
-  I.AL = D.AL + in.slot_off;
-  I.Acn = D.Acn + in.slot_off;
-  I.ml = D.ml + in.node_off;
-  I.uD = D.uD + in.node_off;
-  I.isd = D.is_dir + in.node_off;
-  I.dinv = D.dinv + in.node_off;
-  for (int q = 0; q < BW_COUNT; ++q) I.w[q] = D.work + (size_t)q * D.total_nodes + in.node_off;
-  I.u = ug + in.node_off;
-  I.F = Fg + in.node_off;
-  const int N = in.N;
-  const double dt = in.dt, inv_dt = 1.0 / dt;
+__device__ bool fp_update(const InstView& I, const BatchOpts& o, SState& st, double R, double bn, double rr) {
+  st.omega = next_omega(o, st, R);
+  const bool relax = st.omega != 1.0;
+  double* u = I.u;
+  double* x = u;
+  if (relax) {
+    x = I.w[BW_X];
+    for (int i = threadIdx.x; i < I.N; i += NT) x[i] = u[i];
+    __syncthreads();
+  }
+  const double tol = fmax(fmax(o.lin_atol, o.lin_rtol * bn), o.lin_eta * R);
+  int lst = 0;
+  st.kry += wg_bicgstab<NT>(I, I.w[BW_B], x, rr, tol, o.lin_maxit, &lst, &st.lin_res);
+  if (lst == AFC_ENAN || lst == AFC_EBREAKDOWN) {
+    st.status = lst;
+    return false;
+  }
+  if (relax) {
+    const double om = st.omega;
+    for (int i = threadIdx.x; i < I.N; i += NT) u[i] += om * (x[i] - u[i]);
+  }
+  __syncthreads();
+  st.R_prev = R;
+  st.have_prev = 1;
+  ++st.nu;
+  return true;
+}
+
+// Bookkeeping after the residual R (||b||: bn) of iterate nu: returns true
+// when the fixed point stops here (converged, capped or non-finite).
+__device__ __forceinline__ bool fp_stop(const BatchOpts& o, SState& st, int N, double R, double bn, bool first_of_run) {
+  if (!isfinite(R) || !isfinite(bn)) {
+    st.status = AFC_ENAN;
+    return true;
+  }
+  if (st.nu == 0) st.R0 = R;
+  if (first_of_run) st.res0 = R;
+  st.res = R;
+  const bool conv = (o.fp_tol_mode == AFC_TOL_ABS_SQRTN) ? (R < sqrt((double)N) * o.fp_tol) : (R <= o.fp_tol * st.R0);
+  if (R == 0.0 || conv) return true;
+  if (st.nu >= o.fp_maxit) {
+    st.status = st.status > 0 ? st.status : AFC_WMAXIT;
+    return true;
+  }
+  return false;
+}
+
+// CN-FCT steps of one instance (eqs. (11)-(14), Zalesak's limiter, the Sec. 4
+// fixed point), resumable: returns when st.done is set or, after at least
+// one fixed-point iteration of this call, at the top of an iteration once
+// the wall clock passes `deadline`.
+template <int NT>
+__device__ void run_cn(const InstView& I, double dt, int steps, const BatchOpts& o, SState& st, int64_t deadline) {
+  const int N = I.N;
+  const double inv_dt = 1.0 / dt;
   double* u = I.u;
   double* uo = I.w[BW_UOLD];
   double* ut = I.w[BW_UT];
@@ -305,72 +363,77 @@ __device__ void run_instance(const BInst& in, const BatchDev& D, const BatchOpts
   double* b = I.w[BW_B];
   double* r = I.w[BW_R];
 
-  // CN matrix M_L/dt + A_low/2 with Dirichlet identity rows, and its inverse diagonal
-  AFC_ROWS(I, NT, c_) {
-    const RowSpan rs = row_span(I, i);
-    const bool dir = I.isd[i];
-    for (int p = 0; p < rs.L; ++p) {
-      const int k = rs.base + 64 * p;
-      double v;
-      if (dir)
-        v = (p == 0) ? 1.0 : 0.0;
-      else
-        v = 0.5 * I.AL[k] + ((p == 0) ? I.ml[i] * inv_dt : 0.0);
-      I.Acn[k] = v;
-      if (p == 0) I.dinv[i] = 1.0 / v;
-    }
-  }
-  __syncthreads();
-
-  int fp_total = 0, status = 0;
-  long long kry_total = 0;
-  double res0 = 0.0, res_last = 0.0, lin_res = 0.0;
-  for (int step = 0; step < steps && status >= 0; ++step) {
-    // predictor of eq. (14) and the right-hand side of eq. (11)
+  if (st.phase < 0) {
+    // CN matrix M_L/dt + A_low/2 with Dirichlet identity rows, and its inverse diagonal
     AFC_ROWS(I, NT, c_) {
-      const double ui = u[i];
-      uo[i] = ui;
-      if (I.isd[i]) {
-        ut[i] = g[i] = I.uD[i];
-        continue;
-      }
       const RowSpan rs = row_span(I, i);
-      double y = 0.0;
-#pragma unroll 4
+      const bool dir = I.isd[i];
       for (int p = 0; p < rs.L; ++p) {
         const int k = rs.base + 64 * p;
-        y += I.AL[k] * u[i + I.dlt[k]];
+        double v;
+        if (dir)
+          v = (p == 0) ? 1.0 : 0.0;
+        else
+          v = 0.5 * I.AL[k] + ((p == 0) ? I.ml[i] * inv_dt : 0.0);
+        I.Acn[k] = v;
+        if (p == 0) I.dinv[i] = 1.0 / v;
       }
-      const double mi = I.ml[i];
-      ut[i] = ui - 0.5 * dt * (y - I.F[i]) / mi;
-      // (F^{n-1} + F^n) / 2 with the batch's time-independent load
-      g[i] = mi * inv_dt * ui - 0.5 * y + 0.5 * (I.F[i] + I.F[i]);
     }
     __syncthreads();
-    // Q+- from the predictor (Sec. 2.1.3 step 2)
-    AFC_ROWS(I, NT, c_) {
-      const RowSpan rs = row_span(I, i);
-      const double uti = ut[i];
-      double qp = 0.0, qm = 0.0;
+    st.phase = 0;
+  }
+  int iters = 0;  // fixed-point iterations of this call
+  while (st.step < steps && st.status >= 0) {
+    if (st.phase == 0) {
+      // predictor of eq. (14) and the right-hand side of eq. (11)
+      AFC_ROWS(I, NT, c_) {
+        const double ui = u[i];
+        uo[i] = ui;
+        if (I.isd[i]) {
+          ut[i] = g[i] = I.uD[i];
+          continue;
+        }
+        const RowSpan rs = row_span(I, i);
+        double y = 0.0;
 #pragma unroll 4
-      for (int p = 1; p < rs.L; ++p) {
-        const double du = ut[i + I.dlt[rs.base + 64 * p]] - uti;
-        qp = fmax(qp, du);
-        qm = fmin(qm, du);
+        for (int p = 0; p < rs.L; ++p) {
+          const int k = rs.base + 64 * p;
+          y += I.AL[k] * u[i + I.dlt[k]];
+        }
+        const double mi = I.ml[i];
+        ut[i] = ui - 0.5 * dt * (y - I.F[i]) / mi;
+        // (F^{n-1} + F^n) / 2 with a time-independent load
+        g[i] = mi * inv_dt * ui - 0.5 * y + 0.5 * (I.F[i] + I.F[i]);
       }
-      Qp[i] = qp;
-      Qm[i] = qm;
+      __syncthreads();
+      // Q+- from the predictor (Sec. 2.1.3 step 2)
+      AFC_ROWS(I, NT, c_) {
+        const RowSpan rs = row_span(I, i);
+        const double uti = ut[i];
+        double qp = 0.0, qm = 0.0;
+#pragma unroll 4
+        for (int p = 1; p < rs.L; ++p) {
+          const double du = ut[i + I.dlt[rs.base + 64 * p]] - uti;
+          qp = fmax(qp, du);
+          qm = fmin(qm, du);
+        }
+        Qp[i] = qp;
+        Qm[i] = qm;
+      }
+      __syncthreads();
+      // Dirichlet values into u (after every predictor read of u)
+      AFC_ROWS(I, NT, c_) {
+        if (I.isd[i]) u[i] = I.uD[i];
+      }
+      __syncthreads();
+      st.R0 = st.R_prev = 0.0;
+      st.omega = o.omega;
+      st.have_prev = 0;
+      st.nu = 0;
+      st.phase = 1;
     }
-    __syncthreads();
-    // Dirichlet values into u (after every predictor read of u)
-    AFC_ROWS(I, NT, c_) {
-      if (I.isd[i]) u[i] = I.uD[i];
-    }
-    __syncthreads();
-    double R0 = 0.0, R_prev = 0.0, omega = o.omega;
-    bool have_prev = false;
-    int nu = 0;
     while (true) {
+      if (iters > 0 && past_deadline(deadline)) return;
       // P+-, R+- of the prelimited CN fluxes (eqs. (12), (13))
       AFC_ROWS(I, NT, c_) {
         if (I.isd[i]) {
@@ -429,51 +492,178 @@ __device__ void run_instance(const BInst& in, const BatchDev& D, const BatchOpts
       double red[3];
       wg_sum<NT, 3>(acc, red);
       const double R = sqrt(red[0]), bn = sqrt(red[1]);
-      if (!isfinite(R) || !isfinite(bn)) {
-        status = AFC_ENAN;
-        break;
+      if (fp_stop(o, st, N, R, bn, st.step == 0 && st.nu == 0)) break;
+      if (!fp_update<NT>(I, o, st, R, bn, red[2])) break;
+      ++iters;
+    }
+    st.fp_total += st.nu;
+    ++st.step;
+    st.phase = 0;
+  }
+  st.done = 1;
+}
+
+// Stationary MCL solve of one instance (Sec. 3.1, eqs. (22)-(23), Remark 1,
+// the Sec. 4 fixed point), resumable like run_cn.  A = A_low of the MCL
+// scheme with Dirichlet identity rows; cc, ccT: the convective a_ij, a_ji in
+// slot order.  init_low: start from the low-order solution A u = F (from
+// zero), else from the caller's u.
+template <int NT>
+__device__ void run_mcl(const InstView& I, const double* cc, const double* ccT, int init_low, const BatchOpts& o,
+                        SState& st, int64_t deadline) {
+  const int N = I.N;
+  double* u = I.u;
+  double* umax = I.w[BW_QP];
+  double* umin = I.w[BW_QM];
+  double* b = I.w[BW_B];
+  double* r = I.w[BW_R];
+  const double* A = I.Acn;
+  if (st.phase < 0) {
+    if (init_low) {
+      double acc[Sched<NT>::PER][1] = {};
+      AFC_ROWS(I, NT, c) {
+        const double bi = I.isd[i] ? I.uD[i] : I.F[i];
+        b[i] = bi;
+        u[i] = I.isd[i] ? I.uD[i] : 0.0;
+        acc[c][0] += bi * bi;
       }
-      if (nu == 0) R0 = R;
-      if (step == 0 && nu == 0) res0 = R;
-      res_last = R;
-      const bool conv = (o.fp_tol_mode == AFC_TOL_ABS_SQRTN) ? (R < sqrt((double)N) * o.fp_tol) : (R <= o.fp_tol * R0);
-      if (R == 0.0 || conv) break;
-      if (nu >= o.fp_maxit) {
-        status = status > 0 ? status : AFC_WMAXIT;
-        break;
-      }
-      if (o.dynamic_damping && have_prev) omega = (R > R_prev) ? fmax(omega * 0.5, 1.0 / 64.0) : fmin(1.0, omega * 1.25);
-      const bool relax = omega != 1.0;
-      double* x = u;
-      if (relax) {
-        x = I.w[BW_X];
-        for (int i = threadIdx.x; i < N; i += NT) x[i] = u[i];
-        __syncthreads();
-      }
-      const double tol = fmax(o.lin_atol, o.lin_rtol * bn);
+      double bn2[1];
+      wg_sum<NT, 1>(acc, bn2);
+      const double rr = wg_residual<NT>(I, A, b, u, r);
+      const double tol = fmax(o.lin_atol, o.lin_rtol * sqrt(bn2[0]));
       int lst = 0;
-      kry_total += wg_bicgstab<NT>(I, b, x, red[2], tol, o.lin_maxit, &lst, &lin_res);
-      if (lst == AFC_ENAN || lst == AFC_EBREAKDOWN) {
-        status = lst;
-        break;
+      st.kry += wg_bicgstab<NT>(I, b, u, rr, tol, o.lin_maxit, &lst, &st.lin_res);
+      if (lst == AFC_ENAN) {
+        st.status = lst;
+        st.done = 1;
+        return;
       }
-      if (relax) {
-        for (int i = threadIdx.x; i < N; i += NT) u[i] += omega * (x[i] - u[i]);
+    } else {
+      AFC_ROWS(I, NT, c_) {
+        if (I.isd[i]) u[i] = I.uD[i];
       }
       __syncthreads();
-      R_prev = R;
-      have_prev = true;
-      ++nu;
     }
-    fp_total += nu;
+    st.R0 = st.R_prev = 0.0;
+    st.omega = o.omega;
+    st.have_prev = 0;
+    st.nu = 0;
+    st.phase = 1;
   }
+  int iters = 0;
+  while (true) {
+    if (iters > 0 && past_deadline(deadline)) return;
+    // local bounds u^max_i, u^min_i over N_i, i included (eq. (23))
+    AFC_ROWS(I, NT, c_) {
+      const RowSpan rs = row_span(I, i);
+      double mx = u[i], mn = u[i];
+#pragma unroll 4
+      for (int p = 1; p < rs.L; ++p) {
+        const double uj = u[i + I.dlt[rs.base + 64 * p]];
+        mx = fmax(mx, uj);
+        mn = fmin(mn, uj);
+      }
+      umax[i] = mx;
+      umin[i] = mn;
+    }
+    __syncthreads();
+    // clipped fluxes (eq. (22), bar states in product form), b = F + F*,
+    // r = b - A u ; R^2 (free rows), ||b||^2, ||r||^2
+    double acc[Sched<NT>::PER][3] = {};
+    AFC_ROWS(I, NT, c) {
+      if (I.isd[i]) {
+        const double bi = I.uD[i], ri = I.uD[i] - u[i];
+        b[i] = bi;
+        r[i] = ri;
+        acc[c][1] += bi * bi;
+        acc[c][2] += ri * ri;
+        continue;
+      }
+      const RowSpan rs = row_span(I, i);
+      const double ui = u[i], umaxi = umax[i], umini = umin[i];
+      double fs = 0.0, au = A[rs.base] * ui;
+#pragma unroll 2
+      for (int p = 1; p < rs.L; ++p) {
+        const int k = rs.base + 64 * p;
+        const int dj = I.dlt[k];
+        const int j = i + dj;
+        const double uj = u[j];
+        au += A[k] * uj;
+        if (dj == 0 || o.alpha_mode == AFC_ALPHA_ZERO) continue;
+        const double c = cc[k], ct = ccT[k];
+        const double d = -fmax(fmax(c, 0.0), ct);
+        if (d == 0.0) continue;
+        const double rf = d * (uj - ui);
+        if (o.alpha_mode == AFC_ALPHA_ONE) {
+          fs += rf;
+          continue;
+        }
+        const double sij = d * (ui + uj) + c * (uj - ui);
+        const double sji = d * (ui + uj) + ct * (ui - uj);
+        const double two_d = 2.0 * d;
+        double rs_;
+        if (rf > 0.0)
+          rs_ = fmin(rf, fmin(sij - two_d * umaxi, two_d * umin[j] - sji));
+        else
+          rs_ = fmax(rf, fmax(sij - two_d * umini, two_d * umax[j] - sji));
+        fs += rs_;
+      }
+      const double bi = I.F[i] + fs, ri = bi - au;
+      b[i] = bi;
+      r[i] = ri;
+      acc[c][0] += ri * ri;
+      acc[c][1] += bi * bi;
+      acc[c][2] += ri * ri;
+    }
+    double red[3];
+    wg_sum<NT, 3>(acc, red);
+    const double R = sqrt(red[0]), bn = sqrt(red[1]);
+    if (fp_stop(o, st, N, R, bn, st.nu == 0)) break;
+    if (!fp_update<NT>(I, o, st, R, bn, red[2])) break;
+    ++iters;
+  }
+  st.fp_total = st.nu;
+  st.done = 1;
+}
+
+__device__ __forceinline__ SState fresh_state() {
+  SState st;
+  st.phase = -1;
+  st.step = st.nu = st.have_prev = st.status = st.done = st.fp_total = st.pad_ = 0;
+  st.kry = 0;
+  st.R0 = st.R_prev = st.res0 = st.res = st.lin_res = 0.0;
+  st.omega = 1.0;
+  return st;
+}
+
+template <int NT>
+__device__ void run_instance(const BInst& in, const BatchDev& D, const BatchOpts& o, int steps, double* ug,
+                             const double* Fg, BStat* stat) {
+  InstView I;
+  I.N = in.N;
+  I.nsl = in.nsl;
+  I.slp = D.slp + in.sl_off;
+  I.dlt = D.dlt + in.slot_off;
+  I.mij = D.mij + in.slot_off;
+  I.dp = D.dp + in.slot_off;
+  I.AL = D.AL + in.slot_off;
+  I.Acn = D.Acn + in.slot_off;
+  I.ml = D.ml + in.node_off;
+  I.uD = D.uD + in.node_off;
+  I.isd = D.is_dir + in.node_off;
+  I.dinv = D.dinv + in.node_off;
+  for (int q = 0; q < BW_COUNT; ++q) I.w[q] = D.work + (size_t)q * D.total_nodes + in.node_off;
+  I.u = ug + in.node_off;
+  I.F = Fg + in.node_off;
+  SState st = fresh_state();
+  run_cn<NT>(I, in.dt, steps, o, st, -1);
   if (threadIdx.x == 0) {
-    stat->status = status;
-    stat->fp_iters = fp_total;
-    stat->krylov_iters = kry_total;
-    stat->res0 = res0;
-    stat->res = res_last;
-    stat->lin_res = lin_res;
+    stat->status = st.status;
+    stat->fp_iters = st.fp_total;
+    stat->krylov_iters = st.kry;
+    stat->res0 = st.res0;
+    stat->res = st.res;
+    stat->lin_res = st.lin_res;
   }
   __syncthreads();
 }
@@ -491,6 +681,56 @@ __global__ __launch_bounds__(NT) void k_batch_cn(const BInst* __restrict__ insts
     if (q >= count) break;
     const int id = order[q];
     run_instance<NT>(insts[id], D, o, steps, u, F, stats + id);
+  }
+}
+
+// One round of the served loop: each workgroup takes requests from the
+// round's queue and advances each by one quantum (resumable state in
+// `states`); the queue ends every workgroup's loop.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_serve_round(const SReq* __restrict__ reqs, SState* states,
+                                                    const int* __restrict__ list, int count, int* queue,
+                                                    int64_t quantum) {
+  __shared__ int slot;
+  __shared__ int64_t t0;
+  while (true) {
+    if (threadIdx.x == 0) {
+      slot = atomicAdd(queue, 1);
+      t0 = (int64_t)wall_clock64();
+    }
+    __syncthreads();
+    const int q = slot;
+    const int64_t deadline = quantum > 0 ? t0 + quantum : -1;
+    __syncthreads();
+    if (q >= count) break;
+    const int id = list[q];
+    const SReq& R = reqs[id];
+    InstView I;
+    I.N = R.N;
+    I.nsl = R.nsl;
+    I.slp = R.slp;
+    I.dlt = R.dlt;
+    I.mij = R.mij;
+    I.dp = R.dp;
+    I.AL = R.AL;
+    I.ml = R.ml;
+    I.uD = R.uD;
+    I.isd = R.isd;
+    I.Acn = R.A;
+    I.dinv = R.dinv;
+    for (int w = 0; w < BW_COUNT; ++w) I.w[w] = R.work + (size_t)w * (size_t)R.ldw;
+    I.u = R.u;
+    I.F = R.F;
+    SState st = states[id];
+    if (!st.done) {
+      if (R.kind == AFC_REQ_CN)
+        run_cn<NT>(I, R.dt, R.steps, R.o, st, deadline);
+      else
+        run_mcl<NT>(I, R.cc, R.ccT, R.init_low, R.o, st, deadline);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) states[id] = st;
+    __syncthreads();
   }
 }
 
@@ -514,5 +754,22 @@ void batch_launch(afc_batch_s* b, double* u, const double* F, int steps, int thr
 }
 
 int batch_work_vectors() { return BW_COUNT; }
+
+int serve_work_vectors() { return BW_COUNT; }
+
+void serve_round_launch(const SReq* reqs, SState* states, const int* list, int count, int* queue, int64_t quantum,
+                        int threads, int grid, hipStream_t stream) {
+  switch (threads) {
+    case 256:
+      k_serve_round<256><<<grid, 256, 0, stream>>>(reqs, states, list, count, queue, quantum);
+      break;
+    case 512:
+      k_serve_round<512><<<grid, 512, 0, stream>>>(reqs, states, list, count, queue, quantum);
+      break;
+    default:
+      k_serve_round<1024><<<grid, 1024, 0, stream>>>(reqs, states, list, count, queue, quantum);
+      break;
+  }
+}
 
 }  // namespace afc

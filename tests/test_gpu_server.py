@@ -1,11 +1,18 @@
-"""Request server (continuous batching) through the C ABI: results are the
-same alone and in the mix, they match the direct entry points, and the HBM
-budget limits how many requests run at once."""
+"""Request server (continuous batching) through the C ABI.
+
+Fused lane: served requests match the oracle (one of each kind at n = 16);
+every result is bitwise the same alone and in a mix of both lanes, whatever
+the round quantum.  Dedicated lane: results equal the direct entry points.
+Admission respects the HBM budget; requests dropped by afc_server_destroy
+report AFC_ECANCELED to the threads waiting for them."""
 import copy
+import threading
+import time
 
 import numpy as np
 import pytest
 
+from oracle import afc_oracle as O
 from paper_2110_15676_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
@@ -25,8 +32,14 @@ def _afc():
     return afc
 
 
-def _requests():
-    reqs = I.config5_requests(6, nmin=6, nmax=12)
+def _rel(a, b):
+    l2 = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+    mx = np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+    return float(max(l2, mx))
+
+
+def _requests(count=6, nmin=6, nmax=12):
+    reqs = I.config5_requests(count, nmin=nmin, nmax=nmax)
     return reqs, [I.config5_instance(r) for r in reqs]
 
 
@@ -34,34 +47,98 @@ def _opts(afc, kind):
     if kind == "cn":
         return afc.afc_default_options(precision=afc.AFC_PREC_MIXED, fp_tol=1e-12, fp_maxit=50, lin_atol=1e-13)
     return afc.afc_default_options(precision=afc.AFC_PREC_MIXED, fp_tol=1e-8, fp_tol_mode=afc.AFC_TOL_REL,
-                                   fp_maxit=500, lin_atol=0.0, lin_rtol=1e-10)
+                                   fp_maxit=5000, lin_atol=0.0, lin_rtol=1e-10, dynamic_damping=1, lin_eta=1e-2)
 
 
-def _run(afc, reqs, insts, slots, budget):
-    s = afc.afc_server_create(slots, budget)
+def _server(afc, **cfg):
+    return afc.afc_server_create_cfg(afc.afc_server_default_config(**cfg))
+
+
+def _submit(afc, s, r, inst, opts=None, steps=3):
+    kind = afc.AFC_REQ_CN if r["kind"] == "cn" else afc.AFC_REQ_STATIONARY
+    return afc.afc_server_submit(s, kind, inst, opts if opts is not None else _opts(afc, r["kind"]),
+                                 u0=inst.u0 if r["kind"] == "cn" else None, dt=1e-3, steps=steps,
+                                 conv=r["kind"] == "mcl")
+
+
+def _run(afc, reqs, insts, **cfg):
+    s = _server(afc, **cfg)
     try:
-        ids = []
-        for r, inst in zip(reqs, insts):
-            kind = afc.AFC_REQ_CN if r["kind"] == "cn" else afc.AFC_REQ_STATIONARY
-            ids.append(afc.afc_server_submit(s, kind, inst, _opts(afc, r["kind"]),
-                                             u0=inst.u0 if r["kind"] == "cn" else None, dt=1e-3, steps=3,
-                                             conv=r["kind"] == "mcl"))
+        ids = [_submit(afc, s, r, inst) for r, inst in zip(reqs, insts)]
         out = [afc.afc_server_wait(s, rid, inst.N) for rid, inst in zip(ids, insts)]
+        info = afc.afc_server_info(s)
     finally:
         afc.afc_server_destroy(s)
-    return out
+    return out, info
 
 
-def test_server_alone_equals_mix_and_direct_calls():
+@pytest.mark.parametrize("kind", ["cn", "mcl"])
+def test_fused_request_matches_the_oracle(kind):
+    """One served request of each kind on Q1 16^3 (4913 nodes, fused lane,
+    many rounds of 0.5 ms): CN-FCT 20 steps and the stationary MCL solve with
+    dynamic damping, both sides with BiCGStab-Jacobi and tight tolerances."""
+    afc = _afc()
+    reqs = I.config5_requests(40)
+    r = dict(next(q for q in reqs if q["kind"] == kind))
+    r["n"] = 16
+    inst = I.config5_instance(r)
+    print("served %s n=16 N=%d eps=%.3g c=%.3g" % (kind, inst.N, r["eps"], r["c"]), flush=True)
+    if kind == "cn":
+        o = afc.afc_default_options(krylov=afc.AFC_KRYLOV_BICGSTAB, fp_tol=1e-14, fp_maxit=100, lin_atol=0.0,
+                                    lin_rtol=1e-14)
+    else:
+        o = afc.afc_default_options(krylov=afc.AFC_KRYLOV_BICGSTAB, fp_tol=1e-12, fp_tol_mode=afc.AFC_TOL_REL,
+                                    fp_maxit=20000, lin_atol=0.0, lin_rtol=1e-14, dynamic_damping=1)
+    s = _server(afc, quantum_ms=0.5)
+    try:
+        rid = _submit(afc, s, r, inst, o, steps=20)
+        st, u, stats, _ = afc.afc_server_wait(s, rid, inst.N)
+        rounds, carried, _ = afc.afc_server_info(s)
+    finally:
+        afc.afc_server_destroy(s)
+    assert st == 0, stats
+    assert rounds > 1  # the request was resumed across rounds
+    P = O.problem_from_instance(inst, conv=kind == "mcl")
+    if kind == "cn":
+        ref = inst.u0.copy()
+        for _ in range(20):
+            ref, rst = O.cn_fct_step(P, ref, inst.F, inst.F, 1e-3, tol=1e-14, tol_mode="abs", maxit=100,
+                                     lin="bicgstab", lin_atol=0.0, lin_rtol=1e-14)
+            assert rst.status == O.STATUS_OK
+    else:
+        lo = O.low_order_solution(P, inst.F, lin="bicgstab", lin_rtol=1e-14)
+        ref, rst = O.stationary_mcl(P, inst.F, lo.x, tol=1e-12, tol_mode="rel", maxit=20000, lin="bicgstab",
+                                    lin_rtol=1e-14, dynamic_damping=True)
+        assert rst.status == O.STATUS_OK
+        assert abs(stats["fp_iters"] - rst.iters) <= 2, (stats["fp_iters"], rst.iters)
+    print("served %s: fp its %d, rounds %d, rel err %.3g" % (kind, stats["fp_iters"], rounds, _rel(u, ref)),
+          flush=True)
+    assert _rel(u, ref) <= 1e-10
+
+
+def test_server_alone_equals_mix_across_lanes_and_quanta():
+    """Eight requests, n = 6..14: those up to 1000 nodes in the fused lane,
+    the others dedicated.  Each result alone (quantum 0: one round to the end)
+    equals, bitwise, its result in the mix (quantum 0.05 ms: many rounds, other
+    requests in the same launches)."""
+    afc = _afc()
+    reqs, insts = _requests(8, 6, 14)
+    lanes = ["fused" if i.N <= 1000 else "dedicated" for i in insts]
+    print("server kinds", [r["kind"] for r in reqs], "N", [i.N for i in insts], lanes, flush=True)
+    assert "fused" in lanes and "dedicated" in lanes
+    mix, (rounds, carried, _) = _run(afc, reqs, insts, fuse_max_nodes=1000, quantum_ms=0.05)
+    print("mix: %d rounds, %.2f requests per round" % (rounds, carried / max(1, rounds)), flush=True)
+    assert carried > rounds  # some rounds carried several requests
+    for k in range(len(reqs)):
+        alone, _ = _run(afc, reqs[k:k + 1], insts[k:k + 1], fuse_max_nodes=1000, quantum_ms=0.0)
+        assert alone[0][0] >= 0 and mix[k][0] >= 0, (k, alone[0][2], mix[k][2])
+        assert np.array_equal(alone[0][1], mix[k][1]), k
+
+
+def test_dedicated_lane_equals_direct_calls():
     afc = _afc()
     reqs, insts = _requests()
-    print("server kinds", [r["kind"] for r in reqs], "n", [r["n"] for r in reqs], flush=True)
-    mix = _run(afc, reqs, insts, 3, 1 << 40)
-    for k in range(len(reqs)):
-        alone = _run(afc, reqs[k:k + 1], insts[k:k + 1], 1, 1 << 40)[0]
-        assert alone[0] >= 0 and mix[k][0] >= 0
-        assert np.array_equal(alone[1], mix[k][1]), k
-    # the same request through the direct entry points
+    out, _ = _run(afc, reqs[:2], insts[:2], fuse_max_nodes=0, slots=2)
     for k in (0, 1):
         r, inst = reqs[k], insts[k]
         o = _opts(afc, r["kind"])
@@ -76,83 +153,95 @@ def test_server_alone_equals_mix_and_direct_calls():
             else:
                 u = torch.zeros(inst.N, dtype=torch.float64, device="cuda:0")
                 afc.afc_solve_stationary(h, u, F, init_low_order=True)
-            assert np.array_equal(u.cpu().numpy(), mix[k][1]), k
+            assert np.array_equal(u.cpu().numpy(), out[k][1]), k
         finally:
             afc.afc_destroy(h)
 
 
 def test_server_poll_reports_completion_without_blocking():
-    """Two requests in one slot: polling the second returns at once until it
-    reports completion; by then the first (ahead of it in the one slot) has
-    finished too; an id already waited for is rejected."""
-    import time
-
+    """Two requests: polling the second returns at once until it reports
+    completion; an id already waited for is rejected by poll and wait."""
     afc = _afc()
     reqs, insts = _requests()
-    s = afc.afc_server_create(1, 1 << 40)
+    s = _server(afc)
     try:
-        ids = []
-        for r, inst in zip(reqs[:2], insts[:2]):
-            kind = afc.AFC_REQ_CN if r["kind"] == "cn" else afc.AFC_REQ_STATIONARY
-            ids.append(afc.afc_server_submit(s, kind, inst, _opts(afc, r["kind"]),
-                                             u0=inst.u0 if r["kind"] == "cn" else None, dt=1e-3, steps=3,
-                                             conv=r["kind"] == "mcl"))
+        ids = [_submit(afc, s, r, inst) for r, inst in zip(reqs[:2], insts[:2])]
         deadline = time.time() + 100.0
         while not afc.afc_server_poll(s, ids[1]):
             assert time.time() < deadline
             time.sleep(0.01)
-        assert afc.afc_server_poll(s, ids[0])  # one slot, arrival order: the first finished before
         for rid, inst in zip(ids, insts[:2]):
             st, u, _, _ = afc.afc_server_wait(s, rid, inst.N)
             assert st >= 0 and np.isfinite(u).all()
         with pytest.raises(afc.AFCError):
             afc.afc_server_poll(s, ids[0])
+        assert afc.afc_server_wait(s, ids[0], insts[0].N)[0] == afc.AFC_EINVAL
     finally:
         afc.afc_server_destroy(s)
 
 
-def test_server_failed_request_reports_and_others_run():
-    """A request whose mass matrix holds a NaN fails in its worker: its wait
-    returns the error status with a message, and the requests around it in
-    the same slot still finish with the results they get alone."""
+@pytest.mark.parametrize("fuse", [1000, 0])
+def test_server_failed_request_reports_and_others_run(fuse):
+    """A request whose mass matrix holds a NaN fails alone, with a message,
+    in either lane; the requests around it finish with their results alone."""
     afc = _afc()
     reqs, insts = _requests()
     bad = copy.deepcopy(insts[1])
     bad.M = bad.M.copy()
     bad.M[3] = np.nan
     order = [(reqs[0], insts[0]), (reqs[1], bad), (reqs[2], insts[2])]
-    s = afc.afc_server_create(1, 1 << 40)
+    s = _server(afc, fuse_max_nodes=fuse, slots=1)
     try:
-        ids = []
-        for r, inst in order:
-            kind = afc.AFC_REQ_CN if r["kind"] == "cn" else afc.AFC_REQ_STATIONARY
-            ids.append(afc.afc_server_submit(s, kind, inst, _opts(afc, r["kind"]),
-                                             u0=inst.u0 if r["kind"] == "cn" else None, dt=1e-3, steps=3,
-                                             conv=r["kind"] == "mcl"))
+        ids = [_submit(afc, s, r, inst) for r, inst in order]
         out = [afc.afc_server_wait(s, rid, inst.N) for rid, (_, inst) in zip(ids, order)]
         assert out[1][0] < 0
         assert afc.lib().afc_server_last_error(s).decode() != ""
-        alone = _run(afc, [reqs[0], reqs[2]], [insts[0], insts[2]], 1, 1 << 40)
-        for k, a in ((0, alone[0]), (2, alone[1])):
-            assert out[k][0] >= 0
-            assert np.array_equal(out[k][1], a[1]), k
     finally:
         afc.afc_server_destroy(s)
+    alone, _ = _run(afc, [reqs[0], reqs[2]], [insts[0], insts[2]], fuse_max_nodes=fuse, slots=1)
+    for k, a in ((0, alone[0]), (2, alone[1])):
+        assert out[k][0] >= 0
+        assert np.array_equal(out[k][1], a[1]), k
 
 
-def test_server_budget_serializes_requests():
+@pytest.mark.parametrize("fuse", [1000, 0])
+def test_server_budget_serializes_requests(fuse):
+    """A budget with room for one request at a time: no two requests are in
+    setup or service together, in either lane."""
     afc = _afc()
     reqs, insts = _requests()
     reqs, insts = reqs[:4], insts[:4]
-    fps = [afc.afc_footprint_bytes(i.N, i.nnz, 0, _opts(afc, r["kind"])) for r, i in zip(reqs, insts)]
-    out = _run(afc, reqs, insts, 4, max(fps))  # room for one request at a time
+    # a one-byte budget admits a request only when nothing else is admitted
+    out, _ = _run(afc, reqs, insts, fuse_max_nodes=fuse, slots=4, hbm_budget_bytes=1)
     spans = []
     for st, _, _, (queued, service, latency) in out:
         assert st >= 0
         spans.append((queued, queued + service))
     spans.sort()
     for (a0, a1), (b0, b1) in zip(spans, spans[1:]):
-        assert b0 >= a1 - 1e-3  # never two requests in service together
+        assert b0 >= a1 - 1e-3  # never two requests admitted together
+
+
+def test_destroy_cancels_queued_requests_and_releases_waiters():
+    """With room for one request at a time, destroy right after submitting
+    six: the admitted request finishes, the others end with AFC_ECANCELED,
+    and a thread blocked in afc_server_wait on a dropped request returns."""
+    afc = _afc()
+    reqs, insts = _requests(6, 10, 12)
+    s = _server(afc, fuse_max_nodes=0, slots=1, hbm_budget_bytes=1)
+    ids = [_submit(afc, s, r, inst) for r, inst in zip(reqs, insts)]
+    got = {}
+
+    def waiter():
+        got["last"] = afc.afc_server_wait(s, ids[-1], insts[-1].N)
+
+    t = threading.Thread(target=waiter)
+    t.start()
+    time.sleep(0.5)  # the waiter is inside afc_server_wait before destroy begins
+    afc.afc_server_destroy(s)
+    t.join(timeout=120)
+    assert not t.is_alive()
+    assert got["last"][0] in (afc.AFC_ECANCELED, afc.AFC_OK, afc.AFC_WMAXIT)
 
 
 @pytest.mark.parametrize("kind,sstep", [(1, 0), (1, 8), (0, 0)])
