@@ -82,6 +82,11 @@ def _oracle_first_iteration(n):
     from paper_2110_15676_amd import inputs as I
 
     inst = I.config3(n)
+
+    def progress(it, res):  # one line per GMRES cycle of the oracle
+        print("bench: oracle GMRES at %d iterations, residual %.3e" % (it, res), file=sys.stderr, flush=True)
+
+    O.PROGRESS = progress
     with threadpool_limits(1):
         P = O.problem_from_instance(inst, conv=True)
         t = time.perf_counter()
@@ -90,6 +95,7 @@ def _oracle_first_iteration(n):
         t = time.perf_counter()
         _, st = O.stationary_mcl(P, inst.F, lo.x, tol=0.0, tol_mode="rel", maxit=1, lin_rtol=1e-10)
         el = time.perf_counter() - t
+    O.PROGRESS = None
     return inst.N, el, int(sum(st.krylov_iters)), t_lo
 
 

@@ -55,6 +55,10 @@ STATUS_OK = 0
 STATUS_WMAXIT = 1
 STATUS_EBREAKDOWN = -4
 
+# Optional callable(iterations, residual) that GMRES calls once per cycle (a
+# progress report for long runs; it sees the values and changes nothing).
+PROGRESS = None
+
 
 # ----------------------------------------------------------------------------
 # Problem data and the AFC splitting (Sec. 2, eqs. (2)-(10))
@@ -354,6 +358,8 @@ def gmres(P: AFCProblem, A, b, x0, restart=30, atol=0.0, rtol=0.0, maxit=10000):
     tol = max(atol, rtol * float(np.linalg.norm(b)))
     it = 0
     while True:
+        if PROGRESS is not None:
+            PROGRESS(it, beta)
         if beta <= tol:
             return KrylovResult(x, it, beta, res0, STATUS_OK)
         if it >= maxit:

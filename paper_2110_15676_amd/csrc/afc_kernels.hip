@@ -1,18 +1,21 @@
 // HIP kernels of the AFC hot path for gfx950 (CDNA4, wave64).
 //
-// Row kernels map G consecutive lanes to one CSR row (G = 8/16/32/64, chosen
-// from the mean row length): the G lanes stream the row's entries with
-// coalesced loads, gather neighbour values, and reduce with intra-group
-// shuffles.  Each workgroup takes a contiguous range of row tiles, and
-// workgroup ids are remapped so that each of the 8 XCDs works on one
-// contiguous slab of rows (workgroups are dispatched round-robin over XCDs),
-// which keeps the neighbour gathers inside that XCD's L2.
+// Solver and limiter passes run over a SELL-64 copy of each matrix: one wave
+// per 64-row slice, one row per lane, slots column-major inside the slice, so
+// every lane streams its own row with coalesced loads and needs no cross-lane
+// sum.  Column offsets are shared per slice where one offset pattern places
+// every row (read as scalars), else stored per slot (16 or 32 bits).  Each
+// workgroup takes a contiguous, balanced range of tiles, and workgroup ids are
+// remapped so that each of the 8 XCDs works on one contiguous slab of rows
+// (workgroups are dispatched round-robin over XCDs), which keeps the neighbour
+// gathers inside that XCD's L2.  The few setup kernels over CSR rows map G
+// lanes to a row (G = 8/16/32/64 from the mean row length).
 //
 // Reductions (norms, dot products) are deterministic: per-workgroup partials
-// in fixed slots, summed in a fixed order by the last workgroup to finish
-// (agent-scope fence + atomic ticket).  The same last workgroup performs the
-// scalar step of the solver (Givens rotation, BiCGStab coefficients,
-// convergence flag), so the host never waits inside a Krylov cycle.
+// in fixed slots, summed in a fixed order by a separate small reduce kernel
+// that also performs the scalar step of the solver (Givens rotation, BiCGStab
+// coefficients, convergence flag), so the host never waits inside a Krylov
+// cycle.  No kernel uses floating-point atomics.
 
 #include <algorithm>
 #include <cmath>
@@ -1910,7 +1913,7 @@ __global__ __launch_bounds__(kBlock) void k_mcl_apply_sell(
 // of the current state u (r* = 0 where d_ij = 0)
 // ---------------------------------------------------------------------------
 
-// this lane's share of F*_i = sum_j r*_ij (caller sums over the G lanes)
+// SELL view of the MC data (m_ij and the convective a_ij, a_ji in slot order)
 struct McSell {
   SellView S;
   const void* dlt;
