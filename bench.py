@@ -252,9 +252,10 @@ def solve_to_tolerance(afc, torch, inst, make_opts, rel_tol, cap, lin_eta=0.0, d
     }
 
 
-def bench_batch(afc, torch, I, count, steps, nseq):
+def bench_batch(afc, torch, I, count, steps, every):
     """256 seeded P1 CN-FCT instances x 20 steps in one persistent launch, and
-    the same instances one at a time through afc_step_cn (a subset, scaled)."""
+    every `every`-th instance one at a time through afc_step_cn (an unbiased
+    sample of the same size mix; the rate is that sample's solves/s)."""
     import numpy as np
 
     insts = [I.config4_instance(p) for p in I.config4_params(count)]
@@ -282,7 +283,9 @@ def bench_batch(afc, torch, I, count, steps, nseq):
     finally:
         afc.afc_batch_destroy(b)
     tseq = 0.0
-    for inst in insts[:nseq]:
+    sample = insts[::every]
+    nseq = len(sample)
+    for inst in sample:
         h = afc.afc_create_instance(inst, o, conv=False)
         try:
             uk = torch.tensor(inst.u0, device="cuda:0")
@@ -301,7 +304,9 @@ def bench_batch(afc, torch, I, count, steps, nseq):
                     % (count, int(offs[-1]), steps),
         "solves_per_s": count / tb, "seconds": tb, "status": st,
         "fp_iters": int(sum(x["fp_iters"] for x in stats)), "krylov_iters": int(sum(x["krylov_iters"] for x in stats)),
-        "one_at_a_time_solves_per_s": seq_rate, "one_at_a_time_sample": nseq,
+        "one_at_a_time_solves_per_s": seq_rate,
+        "one_at_a_time_sample": "every %d-th instance (%d instances, mean %.0f nodes; all %d: mean %.0f)" % (
+            every, nseq, sum(i.N for i in sample) / nseq, count, sum(i.N for i in insts) / count),
         "speedup": (count / tb) / seq_rate,
         "schedule": {"threads": sched[0], "workgroups": sched[1], "autotune_s": round(tune_s, 3),
                      "trial_ms": [round(t, 2) for t in trials]},
@@ -509,6 +514,9 @@ def bench_serve(afc, torch, I, count, sample_every):
     reqs = I.config5_requests(count)
     insts = [I.config5_instance(r) for r in reqs]
     cfg = afc.afc_server_default_config()
+    # warm-up: ten requests of the same kind of stream (not reported)
+    wreqs = I.config5_requests(10, seed=(0, 5, 9))
+    serve_run(afc, wreqs, [I.config5_instance(r) for r in wreqs], 200.0, cfg)
     print("bench: serving %d requests at 200/s" % count, file=sys.stderr, flush=True)
     at200, _ = serve_run(afc, reqs, insts, 200.0, cfg)
     sat = at200["solves_per_s"]
@@ -956,7 +964,7 @@ def main():
     batch = None
     if not args.no_batch:
         print("bench: batched CN-FCT", file=sys.stderr, flush=True)
-        batch = bench_batch(afc, torch, I, 256, 20, 8)
+        batch = bench_batch(afc, torch, I, 256, 20, 4)
     cn = None
     if not args.no_cn:
         print("bench: CN (nonlinear vs linear Zal+CN)", file=sys.stderr, flush=True)

@@ -484,19 +484,19 @@ def manufactured(elem: str, n: int, t: float | None = None):
     return inst, u_star(inst.coords)
 
 
-def config5_requests(count: int, rate: float = 200.0, nmin: int = 16, nmax: int = 96):
+def config5_requests(count: int, rate: float = 200.0, nmin: int = 16, nmax: int = 96, seed=(0, 5)):
     """Seeded request stream of the serving workload: exponential inter-arrival
     gaps of mean 1/rate seconds, kind ~ Bernoulli(1/2) between 'cn' (20 CN-FCT
     steps, dt = 1e-3, u0 = 1 on [0.2,0.45]^3, inflow Dirichlet u = 0) and
     'mcl' (stationary, f = 1 on [0.25,0.5]^3, u = 0 on the boundary), Q1 mesh
     n = round(exp(U(ln nmin, ln nmax))), eps = 10^U(-8,-3), |b| = 1 in a
     random direction, c ~ U(0, 1)."""
-    rng = np.random.default_rng((0, 5, 1))
+    rng = np.random.default_rng((*seed, 1))
     gaps = rng.exponential(1.0 / rate, size=count)
     t = np.cumsum(gaps) - gaps[0]
     out = []
     for k in range(count):
-        r = np.random.default_rng((0, 5, 2, k))
+        r = np.random.default_rng((*seed, 2, k))
         kind = "cn" if r.uniform() < 0.5 else "mcl"
         n = int(round(math.exp(r.uniform(math.log(nmin), math.log(nmax)))))
         eps = float(10.0 ** r.uniform(-8.0, -3.0))
