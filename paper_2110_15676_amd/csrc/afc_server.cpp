@@ -27,6 +27,7 @@
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -607,9 +608,13 @@ afc_status afc_server_submit(afc_server* s, const afc_request* q, int64_t* id) {
                        !(q->kind == AFC_REQ_STATIONARY && q->opt.limiter != AFC_LIMITER_MCL) &&
                        r->rp.front() == 0 && r->rp.back() == p.nnz;
   if (fusable) {
-    bool monotone = true;
-    for (int i = 0; i < p.n && monotone; ++i) monotone = r->rp[i] <= r->rp[i + 1];
-    r->lane = monotone ? LANE_FUSED : LANE_DEDICATED;
+    // the fused layout stores column offsets j - i in 16 bits
+    bool ok = true;
+    for (int i = 0; i < p.n && ok; ++i) {
+      ok = r->rp[i] <= r->rp[i + 1];
+      for (int32_t k = r->rp[i]; ok && k < r->rp[i + 1]; ++k) ok = std::abs(r->col[k] - i) <= 32767;
+    }
+    r->lane = ok ? LANE_FUSED : LANE_DEDICATED;
   } else {
     r->lane = LANE_DEDICATED;
   }
