@@ -7,7 +7,7 @@ c = 1, f = 1 on [0.25, 0.5]^3, u = 0 on the boundary.  One step is one
 fixed-point iteration of the paper's scheme (Sec. 4): MCL bounds, limited
 fluxes and the FP64 nonlinear residual, then the linear solve of the
 low-order matrix to ||b - A x|| <= 1e-10 ||b|| with GMRES(30)-Jacobi, FP32
-Arnoldi (s-step blocks of 8 basis vectors unless --sstep says otherwise)
+Arnoldi (s-step blocks of 15 basis vectors unless --sstep says otherwise)
 inside FP64 iterative refinement.  Steps continue from the low-order
 solution (computed before timing).  value = nodes x steps / seconds
 (DOF-iterations/s).
@@ -768,8 +768,8 @@ def main():
     ap.add_argument("--n", type=int, default=128, help="cells per direction (128 is the workload)")
     ap.add_argument("--fp64-steps", type=int, default=5)
     ap.add_argument("--mu-steps", type=int, default=5)
-    ap.add_argument("--sstep", type=int, default=8,
-                    help="GMRES basis block size s (0: one vector per step; 2..8: s-step blocks)")
+    ap.add_argument("--sstep", type=int, default=15,
+                    help="GMRES basis block size s (0: one vector per step; 2..16: s-step blocks)")
     ap.add_argument("--classical-steps", type=int, default=5,
                     help="steps timed again with one basis vector per Arnoldi step (secondary)")
     ap.add_argument("--cpu-n", type=int, default=64,

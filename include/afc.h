@@ -121,13 +121,14 @@ typedef struct {
                                events on the handle's stream (afc_kernel_time) */
   int32_t limiter;          /* AFC_LIMITER_* of afc_solve_stationary          */
   int32_t sstep;            /* mixed-precision GMRES: 0 = one basis vector per
-                               step (classical Gram-Schmidt); s = 2..8 = blocks
+                               step (classical Gram-Schmidt); s = 2..16 = blocks
                                of s vectors from shifted matrix powers
                                (A - I)^j v, orthonormalized together (block
                                Gram-Schmidt + Cholesky QR).  Same Krylov space
                                and minimal-residual iterate as GMRES in exact
-                               arithmetic; a block whose QR fails makes the rest
-                               of the solve use s = 0.                         */
+                               arithmetic; a block whose QR fails halves s for
+                               the handle's later cycles and solves (s = 0
+                               below 2) until afc_set_options is called.       */
   double sstep_shift;       /* theta of the shifted powers (default 1: the
                                Jacobi-scaled matrix has unit diagonal)         */
   int32_t graphs;           /* 1 (default): each GMRES cycle is captured once

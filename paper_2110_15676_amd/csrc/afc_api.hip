@@ -70,7 +70,7 @@ afc_status check_options(const afc_options& o, std::string& why) {
   if (o.profile != 0 && o.profile != 1) return why = "profile must be 0 or 1", AFC_EINVAL;
   if (o.graphs != 0 && o.graphs != 1) return why = "graphs must be 0 or 1", AFC_EINVAL;
   if (o.limiter != AFC_LIMITER_MCL && o.limiter != AFC_LIMITER_MU) return why = "limiter", AFC_EINVAL;
-  if (o.sstep != 0 && (o.sstep < 2 || o.sstep > afc::kSMax)) return why = "sstep must be 0 or 2..8", AFC_EINVAL;
+  if (o.sstep != 0 && (o.sstep < 2 || o.sstep > afc::kSMax)) return why = "sstep must be 0 or 2..16", AFC_EINVAL;
   if (!std::isfinite(o.sstep_shift)) return why = "sstep_shift must be finite", AFC_EINVAL;
   if (!(o.lin_eta >= 0 && o.lin_eta < 1)) return why = "lin_eta must be in [0, 1)", AFC_EINVAL;
   if (o.lanes_per_row != 0 && o.lanes_per_row != 8 && o.lanes_per_row != 16 && o.lanes_per_row != 32 &&
@@ -308,7 +308,11 @@ SolveOut solve_gmres(afc_handle* h, const SysMat& S, const double* b, double* x,
   // s-step variant (mixed precision): blocks of s basis vectors from the
   // shifted powers (A - theta I)^j (default theta = 1, the centre of the
   // Gershgorin discs of the Jacobi-scaled matrix)
-  const int s = mixed ? h->opt.sstep : 0;
+  // A cycle whose status shows a failed block QR makes later cycles, in this
+  // and later solves on the handle, use half the block size (one vector per
+  // step below 2) until the options are set again.
+  int s = mixed ? std::min(h->opt.sstep, h->sstep_cap) : 0;
+  if (s < 2) s = 0;
   const double theta = h->opt.sstep_shift;
   // The last block is not orthogonalized in place: no later step reads its
   // vectors, and the x update takes them raw with their coefficients.
@@ -330,45 +334,55 @@ SolveOut solve_gmres(afc_handle* h, const SysMat& S, const double* b, double* x,
     afc::residual(h, S.S64, b, x, r, 2);
     afc::cast_v0(h, r);
   };
-  bool use_s = s >= 2;
-  if (use_s && !h->partials_blk) {
+  if (s && !h->partials_blk) {
     h->partials_blk = dalloc<double>(h, (size_t)afc::kBlkRows * afc::kRedBlocks);
     HIP_OK(hipMemsetAsync(h->partials_blk, 0, sizeof(double) * afc::kBlkRows * afc::kRedBlocks, h->stream));
   }
   const int fails0 = h->host_status->sfail;
   uint64_t theta_bits = 0;
   std::memcpy(&theta_bits, &theta, sizeof(theta_bits));
-  hipGraphExec_t graph = nullptr, graph_s = nullptr;
-  if (h->opt.graphs && !h->opt.profile) {
-    graph = cached_graph(h, {key_int(1), S.S32, S.S64, S.dinv, b, x, r, h->V32, h->V64, h->w[0], key_int(m),
-                             key_int(mixed), key_int(h->ldv)},
-                         cycle);
-    if (use_s)
-      graph_s = cached_graph(h, {key_int(3), S.S32, S.S64, S.dinv, b, x, r, h->V32, key_int(m), key_int(s),
-                                 key_int(h->ldv), key_int((int64_t)theta_bits)},
-                             cycle_sstep);
-  }
-  auto issue = [&](bool sstep) {
-    if (sstep) {
-      if (graph_s)
-        HIP_OK(hipGraphLaunch(graph_s, h->stream));
+  const bool graphs = h->opt.graphs && !h->opt.profile;
+  // graphs are looked up right before their launch, so a capture for a new
+  // block size cannot have evicted the one being launched
+  auto issue = [&]() {
+    if (s) {
+      if (graphs)
+        HIP_OK(hipGraphLaunch(cached_graph(h, {key_int(3), S.S32, S.S64, S.dinv, b, x, r, h->V32, key_int(m),
+                                               key_int(s), key_int(h->ldv), key_int((int64_t)theta_bits)},
+                                           cycle_sstep),
+                              h->stream));
       else
         cycle_sstep();
-    } else if (graph) {
-      HIP_OK(hipGraphLaunch(graph, h->stream));
+    } else if (graphs) {
+      HIP_OK(hipGraphLaunch(cached_graph(h, {key_int(1), S.S32, S.S64, S.dinv, b, x, r, h->V32, h->V64, h->w[0],
+                                             key_int(m), key_int(mixed), key_int(h->ldv)},
+                                         cycle),
+                            h->stream));
     } else {
       cycle();
     }
   };
-  if (!graph) {  // one cycle at a time (profiling, or graphs switched off)
+  int fails_seen = fails0;
+  // after the status of a cycle run with block size s_used: a new failure halves it
+  auto after_status = [&](int sfail, int s_used) {
+    if (sfail != fails_seen) {
+      fails_seen = sfail;
+      if (s_used) {
+        s = std::min(s, s_used / 2 >= 2 ? s_used / 2 : 0);
+        h->sstep_cap = std::min(h->sstep_cap, std::max(s, 1));
+      }
+    }
+  };
+  if (h->opt.profile) {  // one cycle at a time, so that each cycle's work can be accounted
     int cycle_it0 = it0;
     while (res > tol) {
-      issue(use_s);
+      const int s_used = s;
+      issue();
       o.sweeps += 1;
       sync_status(h);
-      if (use_s) {
-        afc::prof_sstep_cycle(h, m, s, h->host_status->iters - cycle_it0);
-        if (h->host_status->sfail != fails0) use_s = false;  // a block's QR failed: one-vector steps from here
+      if (s_used) {
+        afc::prof_sstep_cycle(h, m, s_used, h->host_status->iters - cycle_it0);
+        after_status(h->host_status->sfail, s_used);
       } else {
         afc::prof_gmres_cycle(h, mixed, m, h->host_status->iters - cycle_it0);
       }
@@ -385,21 +399,26 @@ SolveOut solve_gmres(afc_handle* h, const SysMat& S, const double* b, double* x,
       }
     }
   } else if (res > tol) {
-    // Replayed cycles are kept one ahead: the next cycle is queued before the
-    // host waits for the status of the one in flight, when that cycle is not
-    // expected to converge and the next one stays within the iteration and
-    // sweep caps.  This hides the host's round trip between cycles.  A cycle
-    // that starts after the solve converged finds ks->solved set, and every
-    // kernel of it returns at once.
+    // Cycles (replayed graphs, or the same launches issued directly) are kept
+    // one ahead: the next cycle is queued before the host waits for the
+    // status of the one in flight, when that cycle is not expected to
+    // converge and the next one stays within the iteration and sweep caps.
+    // This hides the host's round trip between cycles.  A cycle that starts
+    // after the solve converged finds ks->solved set, and every kernel of it
+    // returns at once.  A failed s-step block halves the block size from the
+    // first cycle queued after its status is seen; since graphs and direct
+    // launches take the same queueing decisions, both give the same iterates.
     ensure_ring(h);
     int queued = 0, seen = 0;  // cycles issued; cycles whose status was read
+    int slot_s[2] = {0, 0};    // block size each ring slot's cycle ran with
     int64_t its = 0;
     // residual factor expected of one cycle: the inner tolerance bounds a
     // mixed-precision sweep; unknown (no look-ahead) before the first FP64 cycle
     double rate = mixed ? inner_rel : 0.0;
     auto queue = [&]() {
-      issue(use_s);
       const int slot = queued & 1;
+      slot_s[slot] = s;
+      issue();
       HIP_OK(hipMemcpyAsync(h->ring + slot * afc::kStatusBytes, h->ks, afc::kStatusBytes, hipMemcpyDeviceToHost,
                             h->stream));
       HIP_OK(hipEventRecord(h->ring_ev[slot], h->stream));
@@ -414,7 +433,7 @@ SolveOut solve_gmres(afc_handle* h, const SysMat& S, const double* b, double* x,
       const afc::KState* st = reinterpret_cast<const afc::KState*>(h->ring + slot * afc::kStatusBytes);
       ++seen;
       o.sweeps += 1;
-      if (use_s && st->sfail != fails0) use_s = false;  // a block's QR failed: one-vector steps from here
+      after_status(st->sfail, slot_s[slot]);
       const double prev = res;
       res = st->beta;
       its = st->iters - it0;
@@ -1051,6 +1070,7 @@ afc_status afc_set_options(afc_handle* h, const afc_options* opt) {
   h->opt = *opt;
   h->stream = static_cast<hipStream_t>(opt->stream);
   h->G = pick_lanes(h->nnz, h->N, opt->lanes_per_row);
+  h->sstep_cap = afc::kMaxRestart;
   return AFC_OK;
 }
 

@@ -15,7 +15,7 @@ constexpr int kBlock = 256;        // threads per workgroup (4 wave64)
 constexpr int kMaxRestart = 64;    // GMRES restart cap (Hessenberg lives on device)
 constexpr int kMaxRed = 72;        // values a single fused reduction may produce
 constexpr int kRedBlocks = 2048;   // cap on workgroups of reduction kernels
-constexpr int kSMax = 8;           // largest s-step GMRES block
+constexpr int kSMax = 16;          // largest s-step GMRES block (two halves of eight columns)
 // values of one s-step block reduction: C = V^T W ((m+1) x s) and the Gram W^T W (s(s+1)/2)
 constexpr int kBlkRows = (kMaxRestart + 1) * kSMax + kSMax * (kSMax + 1) / 2;
 
@@ -143,6 +143,7 @@ struct afc_handle_s {
   int Vm = 0;
   int ldv = 0;  // basis / work vector stride: N rounded up to 64 (16-byte aligned rows)
   int bicg_last = 2;  // BiCGStab iterations of the handle's last solve (first chunk size)
+  int sstep_cap = afc::kMaxRestart;  // s-step block size cap: halved by a failed block QR, reset by afc_set_options
   double* partials = nullptr;  // kMaxRed * kRedBlocks
   double* partials_res = nullptr;  // one per workgroup of the FP64 SELL residual
   double* partials_blk = nullptr;  // kBlkRows * kRedBlocks (s-step GMRES, allocated on first use)

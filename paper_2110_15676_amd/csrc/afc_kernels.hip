@@ -661,6 +661,9 @@ __device__ __forceinline__ int gram_row(int nv, int s, int i, int j) {
   return nv * s + i * s - i * (i - 1) / 2 + (j - i);
 }
 
+// Blocks of up to eight vectors: each thread holds the FP64 copies of its
+// 16-byte chunk of W_1..W_s in registers; every row V_q and the Gram rows take
+// one eight-value wave reduction per chunk, accumulated per wave in LDS.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_sstep_dots(int N, int ldv, const T* __restrict__ V, int k, int s,
                                                      const KState* __restrict__ ks, double* __restrict__ partials) {
@@ -669,21 +672,21 @@ __global__ __launch_bounds__(kBlock) void k_sstep_dots(int N, int ldv, const T* 
   constexpr int CH = kBlock * VN;
   constexpr int NW = kBlock / 64;
   constexpr int QU = 4;  // basis vectors loaded together (loads in flight)
-  static_assert(kSMax == 8, "one eight-value wave reduction per basis vector");
-  __shared__ double sh[kBlkRows][NW];
+  constexpr int HC = 8;  // block columns (one eight-value reduction per row)
+  extern __shared__ double sh[];  // [row][NW]
   const int nv = k + 1;
   const int nrows = nv * s + s * (s + 1) / 2;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int p = lane >> 3;  // the product whose wave total this lane receives
   const bool writer = (lane & 7) == 0 && p < s;
-  for (int q = threadIdx.x; q < nrows * NW; q += kBlock) sh[q / NW][q % NW] = 0.0;
+  for (int q = threadIdx.x; q < nrows * NW; q += kBlock) sh[q] = 0.0;
   __syncthreads();
   const T* __restrict__ W = V + (size_t)(k + 1) * ldv;
   for (int base = blockIdx.x * CH; base < N; base += gridDim.x * CH) {
     const int e = base + threadIdx.x * VN;
-    double w[kSMax][VN];
+    double w[HC][VN];
 #pragma unroll
-    for (int j = 0; j < kSMax; ++j) {
+    for (int j = 0; j < HC; ++j) {
       T t[VN];
 #pragma unroll
       for (int c = 0; c < VN; ++c) t[c] = T(0);
@@ -700,26 +703,26 @@ __global__ __launch_bounds__(kBlock) void k_sstep_dots(int N, int ldv, const T* 
 #pragma unroll
       for (int u = 0; u < QU; ++u) {
         if (q0 + u < nv) {
-          double v[kSMax];
+          double v[HC];
 #pragma unroll
-          for (int j = 0; j < kSMax; ++j) {
+          for (int j = 0; j < HC; ++j) {
             double t = 0.0;
 #pragma unroll
             for (int c = 0; c < VN; ++c) t += (double)a[u][c] * w[j][c];
             v[j] = t;
           }
           const double x = wave_sum8(v);
-          if (writer) sh[(q0 + u) * s + p][wv] += x;
+          if (writer) sh[((q0 + u) * s + p) * NW + wv] += x;
         }
       }
     }
     // Gram entries (W_i, W_j), i <= j < s: one reduction per i
 #pragma unroll
-    for (int i = 0; i < kSMax; ++i) {
+    for (int i = 0; i < HC; ++i) {
       if (i < s) {
-        double v[kSMax];
+        double v[HC];
 #pragma unroll
-        for (int j = 0; j < kSMax; ++j) {
+        for (int j = 0; j < HC; ++j) {
           double t = 0.0;
           if (j >= i) {
 #pragma unroll
@@ -728,7 +731,7 @@ __global__ __launch_bounds__(kBlock) void k_sstep_dots(int N, int ldv, const T* 
           v[j] = t;
         }
         const double x = wave_sum8(v);
-        if (writer && p >= i) sh[gram_row(nv, s, i, p)][wv] += x;
+        if (writer && p >= i) sh[gram_row(nv, s, i, p) * NW + wv] += x;
       }
     }
   }
@@ -736,8 +739,92 @@ __global__ __launch_bounds__(kBlock) void k_sstep_dots(int N, int ldv, const T* 
   for (int r = threadIdx.x; r < nrows; r += kBlock) {
     double t = 0.0;
 #pragma unroll
-    for (int w = 0; w < NW; ++w) t += sh[r][w];
+    for (int w = 0; w < NW; ++w) t += sh[r * NW + w];
     partials[(size_t)r * kRedBlocks + blockIdx.x] = t;
+  }
+}
+
+// The same projections as one tall-skinny product on the FP64 matrix cores
+// (blocks of more than eight vectors): D = R^T [W_0..W_{s-1}] with the rows
+// R = [W_0..W_{s-1}, V_0..V_k] in tiles of 16, accumulated over the elements
+// by v_mfma_f64_16x16x4f64 (FP32 data converted to FP64: exact products,
+// FP64 sums, no cross-lane reductions in the loop).  Lane l feeds row
+// 16 t + (l & 15) of tile t and element group l >> 4; with W first, the
+// column operand W_{l & 15} is tile 0's own row operand.  Each wave takes a
+// contiguous range of 32-element chunks (eight consecutive elements per lane,
+// two 16-byte loads per row) and loads the next chunk before multiplying the
+// current one.  The four waves' tiles are summed in LDS in a fixed order.
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+
+template <int NT>
+__global__ __launch_bounds__(kBlock) void k_sstep_dots_mfma(int N, int ldv, const float* __restrict__ V, int k,
+                                                           int s, const KState* __restrict__ ks,
+                                                           double* __restrict__ partials) {
+  if (ks->done) return;
+  constexpr int EPL = 8;        // elements per lane and chunk
+  constexpr int CE = 4 * EPL;   // elements per chunk
+  constexpr int NW = kBlock / 64;
+  const int nv = k + 1, nr = nv + s;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const float* __restrict__ W = V + (size_t)(k + 1) * ldv;
+  const float* rp[NT];
+  bool rv[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int r = 16 * t + li;
+    rv[t] = r < nr;
+    rp[t] = r < s ? W + (size_t)r * ldv : (r < nr ? V + (size_t)(r - s) * ldv : V);
+  }
+  const bool bcol = li < s;
+  mfma_d4 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = mfma_d4{0.0, 0.0, 0.0, 0.0};
+  const int nch = (N + CE - 1) / CE;
+  const int gw = blockIdx.x * NW + wv, nw = gridDim.x * NW;
+  const int c0 = (int)((int64_t)gw * nch / nw), c1 = (int)((int64_t)(gw + 1) * nch / nw);
+  auto load = [&](int c, float (&a)[NT][EPL]) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int f = 0; f < EPL / 4; ++f) {
+        float q[4] = {0.f, 0.f, 0.f, 0.f};
+        if (rv[t] && c < c1) load16(rp[t], c * CE + lk * EPL + 4 * f, N, q);
+#pragma unroll
+        for (int x = 0; x < 4; ++x) a[t][4 * f + x] = q[x];
+      }
+  };
+  float a[NT][EPL];
+  load(c0, a);
+  for (int c = c0; c < c1; ++c) {
+    float an[NT][EPL];
+    load(c + 1, an);
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) {
+      const double b = bcol ? (double)a[0][e] : 0.0;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)a[t][e], b, acc[t], 0, 0, 0);
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) a[t][e] = an[t][e];
+  }
+  // D[16 t + i][j] of this wave: lane j + 16 (i % 4), register i / 4
+  __shared__ double sh[NW][NT * 256];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sh[wv][(16 * t + lk + 4 * v) * 16 + li] = acc[t][v];
+  __syncthreads();
+  for (int q = threadIdx.x; q < NT * 256; q += kBlock) {
+    const int r = q >> 4, j = q & 15;
+    if (j >= s || r >= nr || (r < s && r > j)) continue;
+    const int row = r < s ? gram_row(nv, s, r, j) : (r - s) * s + j;
+    double x = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) x += sh[w][q];
+    partials[(size_t)row * kRedBlocks + blockIdx.x] = x;
   }
 }
 
@@ -757,17 +844,20 @@ __global__ __launch_bounds__(kBlock) void k_sstep_sums(KState* ks, const double*
 // run one column per lane of the first wave, with the pivots broadcast by
 // readlane; every entry is formed by the same operations in the same order as
 // a column-by-column loop on one thread would use.
+template <int SM>
 __global__ __launch_bounds__(kBlock) void k_sstep_small(KState* ks, int k, int s, int m, double theta) {
-  constexpr int kRows = kMaxRestart + 1 + kSMax;
-  constexpr int kHL = kMaxRestart * (kMaxRestart + 1);
-  constexpr int kHLU = (kHL + kBlock - 1) / kBlock;
+  static_assert(SM <= kSMax, "block size within the device state");
+  constexpr int kRows = kMaxRestart + 1;                          // nr = k + 1 + s <= m + 1
+  constexpr int kHLd = kMaxRestart * (kMaxRestart + 1);           // staged index range (c, r), r <= k
+  constexpr int kHLU = (kHLd + kBlock - 1) / kBlock;
+  constexpr int kHL = (kMaxRestart - 1) * (kMaxRestart + 2) / 2;  // banded: column c < k holds rows 0..c+1
   constexpr int kBU = (kBlkRows + kBlock - 1) / kBlock;
   __shared__ double B[kBlkRows];  // the block's reduced rows: C[q s + j] = (V_q, W_{j+1}), then W^T W
-  __shared__ double G[kSMax * kSMax], R[kSMax * kSMax], Ri[kSMax * kSMax];
-  __shared__ double Z[kRows * (kSMax + 1)];  // coordinates of W_0..W_s in [V_0..V_k, Q_1..Q_s]
-  __shared__ double M1[kRows * kSMax];
-  __shared__ double Hn[kRows * kSMax];       // new Hessenberg columns k..k+s-1
-  __shared__ double HL[kHL];                 // raw Hessenberg columns 0..k-1
+  __shared__ double G[SM * SM], R[SM * SM], Ri[SM * SM];
+  __shared__ double Z[kRows * (SM + 1)];  // coordinates of W_0..W_s in [V_0..V_k, Q_1..Q_s]
+  __shared__ double M1[kRows * SM];
+  __shared__ double Hn[kRows * SM];       // new Hessenberg columns k..k+s-1
+  __shared__ double HL[kHL];                 // raw Hessenberg columns 0..k-1, column c at c (c + 3) / 2
   __shared__ double gcs[kMaxRestart], gsn[kMaxRestart], gg[kMaxRestart + 1];  // rotations and rhs, staged
   __shared__ int ok, ncols, stop, nonfinite;
   const int was_done = ks->done;
@@ -803,8 +893,13 @@ __global__ __launch_bounds__(kBlock) void k_sstep_small(KState* ks, int k, int s
     }
     if (t <= k) g0 = ks->g[t];
 #pragma unroll
-    for (int u = 0; u < kHLU; ++u)
-      if (threadIdx.x + u * kBlock < k * (k + 1)) HL[threadIdx.x + u * kBlock] = hv[u];
+    for (int u = 0; u < kHLU; ++u) {
+      const int t = threadIdx.x + u * kBlock;
+      if (t < k * (k + 1)) {
+        const int c = t / (k + 1), r = t % (k + 1);
+        if (r <= c + 1) HL[c * (c + 3) / 2 + r] = hv[u];
+      }
+    }
 #pragma unroll
     for (int u = 0; u < kBU; ++u)
       if (threadIdx.x + u * kBlock < nrows) B[threadIdx.x + u * kBlock] = bv[u];
@@ -826,15 +921,15 @@ __global__ __launch_bounds__(kBlock) void k_sstep_small(KState* ks, int k, int s
   // pivot and entries are broadcast from lane j
   if (threadIdx.x < 64) {
     const int i = threadIdx.x;
-    double gc[kSMax], rc[kSMax];
+    double gc[SM], rc[SM];
 #pragma unroll
-    for (int p = 0; p < kSMax; ++p) {
+    for (int p = 0; p < SM; ++p) {
       gc[p] = (i < s && p < s) ? G[p * s + i] : 0.0;
       rc[p] = 0.0;
     }
     bool good = true;
 #pragma unroll
-    for (int j = 0; j < kSMax; ++j) {
+    for (int j = 0; j < SM; ++j) {
       if (j < s && good) {
         double d = gc[j];
 #pragma unroll
@@ -844,7 +939,7 @@ __global__ __launch_bounds__(kBlock) void k_sstep_small(KState* ks, int k, int s
           good = false;
         } else {
           const double rjj = sqrt(dj);
-          double rpj[kSMax];
+          double rpj[SM];
 #pragma unroll
           for (int p = 0; p < j; ++p) rpj[p] = lane_value(rc[p], j);
           if (i == j) {
@@ -860,7 +955,7 @@ __global__ __launch_bounds__(kBlock) void k_sstep_small(KState* ks, int k, int s
     }
     if (good && i < s) {
 #pragma unroll
-      for (int p = 0; p < kSMax; ++p)
+      for (int p = 0; p < SM; ++p)
         if (p < s) R[p * s + i] = rc[p];
     }
     if (i == 0) ok = good;
@@ -877,21 +972,21 @@ __global__ __launch_bounds__(kBlock) void k_sstep_small(KState* ks, int k, int s
   if (threadIdx.x < s) {  // R^{-1}: lane j solves for its column by back substitution
     const int j = threadIdx.x;
     const double djj = 1.0 / R[j * s + j];
-    double ric[kSMax];
+    double ric[SM];
 #pragma unroll
-    for (int p = 0; p < kSMax; ++p) ric[p] = p == j ? djj : 0.0;
+    for (int p = 0; p < SM; ++p) ric[p] = p == j ? djj : 0.0;
 #pragma unroll
-    for (int i = kSMax - 2; i >= 0; --i) {
+    for (int i = SM - 2; i >= 0; --i) {
       if (i < j) {
         double v = 0.0;
 #pragma unroll
-        for (int p = i + 1; p < kSMax; ++p)
+        for (int p = i + 1; p < SM; ++p)
           if (p <= j) v += R[i * s + p] * ric[p];
         ric[i] = -v / R[i * s + i];
       }
     }
 #pragma unroll
-    for (int i = 0; i < kSMax; ++i)
+    for (int i = 0; i < SM; ++i)
       if (i < s) Ri[i * s + j] = ric[i];
   }
   __syncthreads();
@@ -922,15 +1017,15 @@ __global__ __launch_bounds__(kBlock) void k_sstep_small(KState* ks, int k, int s
     const int r = t / s, j = t % s;
     double v = theta * Z[r * (s + 1) + j] + Z[r * (s + 1) + j + 1];
     if (r <= k)
-      for (int c = max(r - 1, 0); c < k; ++c) v -= HL[c * (k + 1) + r] * Z[c * (s + 1) + j];
+      for (int c = max(r - 1, 0); c < k; ++c) v -= HL[c * (c + 3) / 2 + r] * Z[c * (s + 1) + j];
     M1[t] = v;
   }
   __syncthreads();
   if (threadIdx.x < nr) {  // Hn = M1 T^{-1}, one row per thread, the row in registers
     const int r = threadIdx.x;
-    double h[kSMax];
+    double h[SM];
 #pragma unroll
-    for (int j = 0; j < kSMax; ++j) {
+    for (int j = 0; j < SM; ++j) {
       if (j < s) {
         double v = M1[r * s + j];
 #pragma unroll
@@ -980,14 +1075,14 @@ __global__ __launch_bounds__(kBlock) void k_sstep_small(KState* ks, int k, int s
   if (threadIdx.x < 64) {
     const int j = threadIdx.x;
     const bool mine = j < ns;
-    double v[kSMax + 1];
+    double v[SM + 1];
 #pragma unroll
-    for (int r = 0; r <= kSMax; ++r) v[r] = (mine && k + r < nr) ? Hn[(k + r) * s + j] : 0.0;
+    for (int r = 0; r <= SM; ++r) v[r] = (mine && k + r < nr) ? Hn[(k + r) * s + j] : 0.0;
     const double tol = ks->tol;
     double gk = gg[k];
     int st = 0, nf = 0, nc = 0;
 #pragma unroll
-    for (int t = 0; t < kSMax; ++t) {
+    for (int t = 0; t < SM; ++t) {
       if (t < ns && !st) {
         const double cur = lane_value(v[t], t);
         const double hk1 = lane_value(v[t + 1], t);
@@ -1021,7 +1116,7 @@ __global__ __launch_bounds__(kBlock) void k_sstep_small(KState* ks, int k, int s
       }
     }
 #pragma unroll
-    for (int r = 0; r <= kSMax; ++r)
+    for (int r = 0; r <= SM; ++r)
       if (mine && k + r < nr) Hn[(k + r) * s + j] = v[r];
     if (j == 0) {
       ncols = nc;  // columns completed by this block
@@ -1054,28 +1149,37 @@ __global__ __launch_bounds__(kBlock) void k_sstep_small(KState* ks, int k, int s
 
 // Q = W R^{-1} - V (C R^{-1}), in place over the block V[k+1..k+s].  The
 // basis part is summed first and W read last, so that W and the
-// accumulators are not live together.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_sstep_update(int N, int ldv, T* __restrict__ V, int k, int s,
-                                                       const KState* __restrict__ ks) {
+// accumulators are not live together.  Output columns come in halves of
+// eight: group h of four waves forms Q_{8h..8h+7} for the same elements as
+// the other group (R^{-1} is upper triangular, so group 1 also reads
+// W_0..W_7); with two groups every read of W precedes, by a workgroup
+// barrier, the in-place stores.
+template <typename T, int NH>
+__global__ __launch_bounds__(kBlock * NH) __attribute__((amdgpu_waves_per_eu(NH > 1 ? 4 : 1))) void k_sstep_update(int N, int ldv, T* __restrict__ V, int k, int s,
+                                                            const KState* __restrict__ ks) {
   constexpr int VN = 16 / sizeof(T);
   constexpr int CH = kBlock * VN;
-  constexpr int QU = 4;  // basis vectors loaded together
+  constexpr int QU = NH > 1 ? 2 : 4;  // basis vectors loaded together
+  constexpr int HC = 8;  // output columns per group
+  static_assert((NH == 1 || NH == 2) && 2 * HC >= kSMax, "at most two groups of eight columns");
   __shared__ double D[(kMaxRestart + 1) * kSMax], Ri[kSMax * kSMax];
   __shared__ int okb;
   if (threadIdx.x == 0) okb = ks->blk_ok;
   __syncthreads();
   if (!okb) return;
   const int nv = k + 1;
-  for (int t = threadIdx.x; t < nv * s; t += kBlock) D[t] = ks->dco[t];
-  for (int t = threadIdx.x; t < s * s; t += kBlock) Ri[t] = ks->rinv[t];
+  for (int t = threadIdx.x; t < nv * s; t += blockDim.x) D[t] = ks->dco[t];
+  for (int t = threadIdx.x; t < s * s; t += blockDim.x) Ri[t] = ks->rinv[t];
   __syncthreads();
+  const int grp = NH > 1 ? (int)(threadIdx.x / kBlock) : 0;
+  const int tid = threadIdx.x - grp * kBlock;
+  const int j0 = grp * HC, sj = min(HC, s - j0);
   T* __restrict__ W = V + (size_t)(k + 1) * ldv;
   for (int base = blockIdx.x * CH; base < N; base += gridDim.x * CH) {
-    const int e = base + threadIdx.x * VN;
-    double acc[kSMax][VN];
+    const int e = base + tid * VN;
+    double acc[HC][VN];
 #pragma unroll
-    for (int j = 0; j < kSMax; ++j)
+    for (int j = 0; j < HC; ++j)
 #pragma unroll
       for (int c = 0; c < VN; ++c) acc[j][c] = 0.0;
     for (int q0 = 0; q0 < nv; q0 += QU) {
@@ -1087,35 +1191,34 @@ __global__ __launch_bounds__(kBlock) void k_sstep_update(int N, int ldv, T* __re
       for (int u = 0; u < QU; ++u) {
         if (q0 + u < nv) {
 #pragma unroll
-          for (int j = 0; j < kSMax; ++j)
-            if (j < s) {
-              const double d = D[(q0 + u) * s + j];
+          for (int j = 0; j < HC; ++j)
+            if (j < sj) {
+              const double d = D[(q0 + u) * s + j0 + j];
 #pragma unroll
               for (int c = 0; c < VN; ++c) acc[j][c] -= d * (double)a[u][c];
             }
         }
       }
     }
+    for (int i = 0; i < j0 + sj; ++i) {
+      T w[VN];
+      load16(W + (size_t)i * ldv, e, N, w);
 #pragma unroll
-    for (int i = 0; i < kSMax; ++i)
-      if (i < s) {
-        T w[VN];
-        load16(W + (size_t)i * ldv, e, N, w);
+      for (int j = 0; j < HC; ++j)
+        if (i <= j0 + j && j < sj) {
+          const double r = Ri[i * s + j0 + j];
 #pragma unroll
-        for (int j = 0; j < kSMax; ++j)
-          if (i <= j && j < s) {
-            const double r = Ri[i * s + j];
+          for (int c = 0; c < VN; ++c) acc[j][c] += r * (double)w[c];
+        }
+    }
+    if (NH > 1) __syncthreads();  // both groups have read W_0..W_7 of these elements
 #pragma unroll
-            for (int c = 0; c < VN; ++c) acc[j][c] += r * (double)w[c];
-          }
-      }
-#pragma unroll
-    for (int j = 0; j < kSMax; ++j)
-      if (j < s) {
+    for (int j = 0; j < HC; ++j)
+      if (j < sj) {
         T o[VN];
 #pragma unroll
         for (int c = 0; c < VN; ++c) o[c] = (T)acc[j][c];
-        store16(W + (size_t)j * ldv, e, N, o);
+        store16(W + (size_t)(j0 + j) * ldv, e, N, o);
       }
   }
 }
@@ -1838,7 +1941,9 @@ __global__ __launch_bounds__(kBlock) void k_mcl_bounds_sell(SellView S, const vo
 // r*_ij from d_ij = -max(c_ij, 0, c_ji) and the bar states in product form
 // 2 d_ij ubar_ij = d_ij (u_i + u_j) + c_ij (u_j - u_i); F*_i = sum_j r*_ij;
 // b = F + F*, r = b - A_low u; reductions: R^2 (free rows), ||b||^2, ||r||^2.
-// A_low, c_ij and c_ji come in SELL slot order (Sal, Scc, SccT).
+// A_low, c_ij and c_ji come in SELL slot order (Sal, Scc, SccT).  Those three
+// streams are read once, with nontemporal loads, so that they do not push the
+// gathered node vectors (u, u^max, u^min of the neighbour planes) out of L2.
 __global__ __launch_bounds__(kBlock) void k_mcl_apply_sell(
     SellView S, const void* __restrict__ dlt, int d16, const uint32_t* __restrict__ mask,
     const double* __restrict__ Scc, const double* __restrict__ SccT, const double* __restrict__ Sal,
@@ -1876,9 +1981,9 @@ __global__ __launch_bounds__(kBlock) void k_mcl_apply_sell(
       const int j = i + dj;
       const size_t v = (size_t)base + 64 * p + lane;
       const double uj = u[j];
-      au += Sal[v] * uj;
+      au += __builtin_nontemporal_load(Sal + v) * uj;
       if (dj == 0 || alpha_mode == AFC_ALPHA_ZERO) continue;
-      const double c = Scc[v], ct = SccT[v];
+      const double c = __builtin_nontemporal_load(Scc + v), ct = __builtin_nontemporal_load(SccT + v);
       const double d = -fmax(fmax(c, 0.0), ct);
       if (d == 0.0) continue;
       const double rf = d * (uj - ui);
@@ -2172,15 +2277,20 @@ void take_events(afc_handle_s* h, hipEvent_t* a, hipEvent_t* b) {
 // folded into the totals is the kernel's own execution, with no gap from
 // separately recorded event packets.
 template <typename... KArgs, typename... Args>
-void launch(H* h, int kid, void (*kernel)(KArgs...), dim3 grid, dim3 block, Args... args) {
+void launch_shm(H* h, int kid, void (*kernel)(KArgs...), dim3 grid, dim3 block, size_t shm, Args... args) {
   if (!h->opt.profile) {
-    kernel<<<grid, block, 0, h->stream>>>(args...);
+    kernel<<<grid, block, shm, h->stream>>>(args...);
     return;
   }
   hipEvent_t a, b;
   take_events(h, &a, &b);
-  hipExtLaunchKernelGGL(kernel, grid, block, 0, h->stream, a, b, 0, static_cast<KArgs>(args)...);
+  hipExtLaunchKernelGGL(kernel, grid, block, shm, h->stream, a, b, 0, static_cast<KArgs>(args)...);
   h->ev_pending.push_back({a, b, kid});
+}
+
+template <typename... KArgs, typename... Args>
+void launch(H* h, int kid, void (*kernel)(KArgs...), dim3 grid, dim3 block, Args... args) {
+  launch_shm(h, kid, kernel, grid, block, 0, args...);
 }
 
 }  // namespace
@@ -2373,20 +2483,46 @@ void gmres_last_givens(H* h, bool fp32, int k, int m) {
 // SIMD, so that no workgroup starts late and runs its chunk alone at the end
 int sstep_grid(const H* h) { return std::min(vec16_grid(h, kBlock * 4), 1024); }
 
+// blocks of up to eight vectors: wave reductions (LDS holds the output rows of
+// every wave); larger blocks: the FP64 matrix cores, in row tiles of 16
 void sstep_dots(H* h, int k, int s) {
-  launch(h, AFC_KERNEL_DOTS, k_sstep_dots<float>, sstep_grid(h), kBlock, h->N, h->ldv, (const float*)h->V32, k, s,
-         (const KState*)h->ks, h->partials_blk);
+  if (s <= 8) {
+    const size_t shm = sizeof(double) * ((size_t)(k + 1) * s + s * (s + 1) / 2) * (kBlock / 64);
+    launch_shm(h, AFC_KERNEL_DOTS, k_sstep_dots<float>, sstep_grid(h), kBlock, shm, h->N, h->ldv,
+               (const float*)h->V32, k, s, (const KState*)h->ks, h->partials_blk);
+    return;
+  }
+  const int nt = (k + 1 + s + 15) / 16;
+#define AFC_DOTS_MFMA(NT)                                                                                   \
+  launch(h, AFC_KERNEL_DOTS, k_sstep_dots_mfma<NT>, sstep_grid(h), kBlock, h->N, h->ldv, (const float*)h->V32, \
+         k, s, (const KState*)h->ks, h->partials_blk)
+  static_assert(kMaxRestart + 1 <= 5 * 16, "row tiles of the largest block");
+  switch (nt) {
+    case 1: AFC_DOTS_MFMA(1); break;
+    case 2: AFC_DOTS_MFMA(2); break;
+    case 3: AFC_DOTS_MFMA(3); break;
+    case 4: AFC_DOTS_MFMA(4); break;
+    default: AFC_DOTS_MFMA(5); break;
+  }
+#undef AFC_DOTS_MFMA
 }
 
 void sstep_reduce(H* h, int k, int s, int m, double theta) {
   const int nrows = (k + 1) * s + s * (s + 1) / 2;
   launch(h, AFC_KERNEL_FINISH, k_sstep_sums, nrows, kBlock, h->ks, (const double*)h->partials_blk, sstep_grid(h));
-  launch(h, AFC_KERNEL_FINISH, k_sstep_small, 1, kBlock, h->ks, k, s, m, theta);
+  if (s <= 8)
+    launch(h, AFC_KERNEL_FINISH, k_sstep_small<8>, 1, kBlock, h->ks, k, s, m, theta);
+  else
+    launch(h, AFC_KERNEL_FINISH, k_sstep_small<kSMax>, 1, kBlock, h->ks, k, s, m, theta);
 }
 
 void sstep_update(H* h, int k, int s) {
-  launch(h, AFC_KERNEL_UPDATE, k_sstep_update<float>, gmres_grid(h, true), kBlock, h->N, h->ldv, h->V32, k, s,
-         (const KState*)h->ks);
+  if (s <= 8)
+    launch(h, AFC_KERNEL_UPDATE, k_sstep_update<float, 1>, gmres_grid(h, true), kBlock, h->N, h->ldv, h->V32, k,
+           s, (const KState*)h->ks);
+  else
+    launch(h, AFC_KERNEL_UPDATE, k_sstep_update<float, 2>, gmres_grid(h, true), 2 * kBlock, h->N, h->ldv, h->V32,
+           k, s, (const KState*)h->ks);
 }
 
 void gmres_solve(H* h, int m) { k_gmres_solve<<<1, 64, 0, h->stream>>>(h->ks, m); }

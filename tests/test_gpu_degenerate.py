@@ -53,7 +53,7 @@ def _all_dirichlet(n):
                    dir_fn=lambda X: np.sin(3 * X[:, 0]) + X[:, 1] * X[:, 2])
 
 
-@pytest.mark.parametrize("prec,sstep", [(0, 0), (1, 0), (1, 8)])
+@pytest.mark.parametrize("prec,sstep", [(0, 0), (1, 0), (1, 8), (1, 15)])
 def test_every_node_dirichlet(prec, sstep):
     """Q1 5^3 (216 nodes), all of them Dirichlet nodes."""
     afc = _afc()
@@ -140,7 +140,7 @@ def test_constant_state_is_kept_by_crank_nicolson(krylov, prec, sstep):
         afc.afc_destroy(h)
 
 
-@pytest.mark.parametrize("prec,sstep", [(0, 0), (1, 8)])
+@pytest.mark.parametrize("prec,sstep", [(0, 0), (1, 8), (1, 15)])
 def test_zero_data_stops_at_once(prec, sstep):
     """F = 0 and u_D = 0 on Q1 6^3: the solution is zero, reached with no
     Krylov iteration and no NaN."""

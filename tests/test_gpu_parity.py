@@ -455,7 +455,7 @@ def test_cn_damped_fixed_point_parity(omega, dyn):
         afc.afc_destroy(h)
 
 
-@pytest.mark.parametrize("sstep", [0, 8])
+@pytest.mark.parametrize("sstep", [0, 8, 15])
 def test_kernel_work_accounting(sstep):
     """Profiled launches: SpMV launches with work = Krylov iterations plus, per
     cycle, at most one (one vector per step: the launch after the last
@@ -628,11 +628,11 @@ def test_mu_alpha_modes_and_renumbered(mode, name):
         afc.afc_destroy(h)
 
 
-@pytest.mark.parametrize("sstep", [8, 0])
+@pytest.mark.parametrize("sstep", [15, 8, 0])
 def test_mcl_full_size_iteration_in_bench_configuration(sstep):
     """Q1 128^3 (the stationary MCL workload) in the configuration bench.py
-    times (FP32 GMRES(30)-Jacobi in s-step blocks of 8 inside FP64
-    refinement, 1e-10 ||b||; and with one basis vector per step): the
+    times (FP32 GMRES(30)-Jacobi in s-step blocks of 15 inside FP64
+    refinement, 1e-10 ||b||; also blocks of 8 and one basis vector per step): the
     low-order start and one fixed-point iteration, checked with the oracle's
     FP64 operators at full size: the nonlinear residual the GPU reports, and
     the linear residual of the iterate against b = F + F*(u) assembled by the
@@ -668,7 +668,7 @@ def test_mcl_full_size_iteration_in_bench_configuration(sstep):
     assert np.linalg.norm(b - P.matvec(As, u1)) <= 1.01e-10 * np.linalg.norm(b)
 
 
-@pytest.mark.parametrize("sstep", [2, 5, 8])
+@pytest.mark.parametrize("sstep", [2, 5, 8, 9, 12, 15, 16])
 def test_sstep_gmres_parity(sstep):
     """s-step GMRES (blocks of s basis vectors) in the mixed-precision solve of
     the stationary MCL workload at 12^3: same solution as the oracle, Krylov
@@ -693,17 +693,17 @@ def test_sstep_gmres_parity(sstep):
     assert its[sstep] <= 1.25 * its[0] + 8 * stats["fp_iters"]
 
 
-@pytest.mark.parametrize("n", [2, 3, 4])
-def test_sstep_tiny_and_ragged_sizes(n):
-    """s-step blocks of 8 on meshes of 27, 64 and 125 nodes (below one slice,
+@pytest.mark.parametrize("n,sstep", [(2, 8), (3, 8), (4, 8), (2, 16), (3, 15), (4, 15)])
+def test_sstep_tiny_and_ragged_sizes(n, sstep):
+    """s-step blocks of 8, 15 and 16 on meshes of 27, 64 and 125 nodes (below one slice,
     exactly one, a ragged second): Krylov spaces smaller than a block, the
     Gram matrix of a block rank-deficient; the solution still matches the
     oracle."""
     afc = _afc()
     inst = I.config3(n)
     ref, rst = _mcl_ref(inst, 1e-12, 1e-14)
-    print("sstep tiny n=%d N=%d" % (n, inst.N), flush=True)
-    h = afc.afc_create_instance(inst, _opts(precision=1, sstep=8, fp_tol=1e-12, fp_tol_mode=1, fp_maxit=2000,
+    print("sstep tiny n=%d N=%d sstep=%d" % (n, inst.N, sstep), flush=True)
+    h = afc.afc_create_instance(inst, _opts(precision=1, sstep=sstep, fp_tol=1e-12, fp_tol_mode=1, fp_maxit=2000,
                                             lin_atol=0.0, lin_rtol=1e-14), conv=True)
     try:
         u = _dev(np.zeros(inst.N))
@@ -714,12 +714,14 @@ def test_sstep_tiny_and_ragged_sizes(n):
         afc.afc_destroy(h)
 
 
-def test_sstep_renumbered_and_graph_replay():
+@pytest.mark.parametrize("sstep", [5, 15])
+def test_sstep_renumbered_and_graph_replay(sstep):
     afc = _afc()
     inst = I.renumbered(I.config3(10))
     outs = []
     for g in (1, 0):
-        h = afc.afc_create_instance(inst, _opts(precision=1, sstep=5, graphs=g, fp_tol=0.0, fp_tol_mode=1, fp_maxit=1,
+        print("renumbered sstep=%d graphs=%d" % (sstep, g), flush=True)
+        h = afc.afc_create_instance(inst, _opts(precision=1, sstep=sstep, graphs=g, fp_tol=0.0, fp_tol_mode=1, fp_maxit=1,
                                                 lin_atol=0.0, lin_rtol=1e-10), conv=True)
         try:
             u = _dev(np.zeros(inst.N))
@@ -738,13 +740,15 @@ def test_sstep_renumbered_and_graph_replay():
     assert _rel(outs[0], ref) <= 1e-8
 
 
-def test_sstep_failed_block_falls_back():
+@pytest.mark.parametrize("sstep", [5, 15])
+def test_sstep_failed_block_falls_back(sstep):
     """A shift that overflows the FP32 powers makes the first block's Cholesky
     QR fail; the solve continues with one-vector steps and converges."""
     afc = _afc()
     inst = I.config3(10)
     ref, _ = _mcl_ref(inst, 1e-12, 1e-14)
-    h = afc.afc_create_instance(inst, _opts(precision=1, sstep=5, sstep_shift=1e30, fp_tol=1e-12, fp_tol_mode=1,
+    print("failed block sstep=%d" % sstep, flush=True)
+    h = afc.afc_create_instance(inst, _opts(precision=1, sstep=sstep, sstep_shift=1e30, fp_tol=1e-12, fp_tol_mode=1,
                                             fp_maxit=2000, lin_atol=0.0, lin_rtol=1e-14), conv=True)
     try:
         u = _dev(np.zeros(inst.N))
@@ -763,6 +767,13 @@ def test_sstep_failed_block_falls_back():
     (5, 300, 8, 1),   # a block cut to the cycle: one block of 5
     (12, 300, 8, 1),  # blocks of 8 and 4
     (30, 10, 8, 1),   # the inner step cap shortens the cycle to 10: blocks of 8 and 2
+    (64, 300, 16, 1),  # four blocks of 16 (two column groups each)
+    (64, 300, 15, 1),  # four blocks of 15 and a last block of 4
+    (30, 300, 15, 1),  # two blocks of 15 (the 128^3 bench configuration)
+    (30, 300, 12, 1),  # blocks of 12, 12 and 6
+    (12, 300, 15, 1),  # a block cut to the cycle: one block of 12
+    (30, 10, 15, 1),  # the inner step cap shortens the cycle to 10: one block of 10
+    (64, 300, 9, 1),  # the smallest two-group block: seven blocks of 9 and one of 1
 ])
 def test_gmres_restart_lengths(restart, inner, sstep, prec):
     """GMRES cycles from 5 to the 64-vector limit, with and without s-step
@@ -948,19 +959,21 @@ def test_graph_replay_matches_plain_launches(prec):
 def test_graph_queue_stops_at_caps(cap):
     """Replayed GMRES cycles are queued one ahead of the host; at an
     iteration or sweep cap the solve must stop exactly where cycles launched one
-    at a time stop: same status, iterations, sweeps and bitwise result."""
+    at a time stop (the profiling mode, which accounts every cycle on its own):
+    same status, iterations, sweeps and bitwise result."""
     afc = _afc()
     inst = I.config3(10)
+    modes = [dict(graphs=1, profile=0), dict(graphs=0, profile=1)]
     hs = [afc.afc_create_instance(inst, _opts(precision=1, fp_tol=0.0, fp_tol_mode=1, fp_maxit=0, lin_atol=0.0,
-                                              lin_rtol=1e-12, graphs=g), conv=True)
-          for g in (1, 0)]
+                                              lin_rtol=1e-12, **md), conv=True)
+          for md in modes]
     try:
         us = [_dev(np.zeros(inst.N)) for _ in hs]
         F = _dev(inst.F)
-        for h, u in zip(hs, us):
+        for h, u, md in zip(hs, us, modes):
             afc.afc_solve_stationary(h, u, F, init_low_order=True)
             afc.afc_set_options(h, _opts(precision=1, fp_tol=0.0, fp_tol_mode=1, fp_maxit=2, lin_atol=0.0,
-                                         lin_rtol=1e-12, graphs=int(h is hs[0]), **cap))
+                                         lin_rtol=1e-12, **md, **cap))
         outs = [afc.afc_solve_stationary(h, u, F, raise_on_error=False) for h, u in zip(hs, us)]
         print("cap %s: %s" % (cap, [(st, s["krylov_iters"], s["refine_sweeps"]) for st, s in outs]), flush=True)
         assert outs[0][0] == outs[1][0]
