@@ -859,17 +859,13 @@ __global__ __launch_bounds__(kBlock) void k_sstep_small(KState* ks, int k, int s
   __shared__ double Hn[kRows * SM];       // new Hessenberg columns k..k+s-1
   __shared__ double HL[kHL];                 // raw Hessenberg columns 0..k-1, column c at c (c + 3) / 2
   __shared__ double gcs[kMaxRestart], gsn[kMaxRestart], gg[kMaxRestart + 1];  // rotations and rhs, staged
+  __shared__ double rdiag[SM];               // 1 / R_jj
   __shared__ int ok, ncols, stop, nonfinite;
-  const int was_done = ks->done;
-  __syncthreads();  // every thread has read done before thread 0 may set it below
-  if (was_done) {
-    if (threadIdx.x == 0) ks->blk_ok = 0;
-    return;
-  }
   const int nv = k + 1, nr = nv + s;
   const int nrows = nv * s + s * (s + 1) / 2;
   const double* C = B;
-  {  // every global read of the kernel in flight at once
+  {  // every global read of the kernel in flight at once, the done flag included
+    const int was_done = ks->done;
     double hv[kHLU], bv[kBU];
 #pragma unroll
     for (int u = 0; u < kHLU; ++u) {
@@ -892,6 +888,11 @@ __global__ __launch_bounds__(kBlock) void k_sstep_small(KState* ks, int k, int s
       sn0 = ks->sn[t];
     }
     if (t <= k) g0 = ks->g[t];
+    __syncthreads();  // every thread has read done before thread 0 may set it below
+    if (was_done) {
+      if (threadIdx.x == 0) ks->blk_ok = 0;
+      return;
+    }
 #pragma unroll
     for (int u = 0; u < kHLU; ++u) {
       const int t = threadIdx.x + u * kBlock;
@@ -917,79 +918,85 @@ __global__ __launch_bounds__(kBlock) void k_sstep_small(KState* ks, int k, int s
     G[t] = g;
   }
   __syncthreads();
-  // G = R^T R, R upper triangular: lane i holds column i of R; column j's
-  // pivot and entries are broadcast from lane j
+  // G = R^T R with R upper triangular (left-looking), then R^{-1}, in the
+  // first wave: lane i holds column i of G and of R.  At step j every lane
+  // reads column j of R (rows p < j, written to LDS by the earlier steps) and
+  // the pivot G_jj as broadcasts, forms R_jj and 1 / R_jj itself, and lane
+  // i > j its entry R_ji; row j of R then goes to LDS.  The wave's LDS
+  // accesses take effect in program order, so no barrier is needed between
+  // steps.  Lane j then solves for column j of R^{-1} by back substitution
+  // with the reciprocal pivots (no division on the chain).
   if (threadIdx.x < 64) {
     const int i = threadIdx.x;
-    double gc[SM], rc[SM];
+    double gc[SM], rc[SM], dinv[SM];
 #pragma unroll
     for (int p = 0; p < SM; ++p) {
       gc[p] = (i < s && p < s) ? G[p * s + i] : 0.0;
       rc[p] = 0.0;
+      dinv[p] = 0.0;
     }
     bool good = true;
 #pragma unroll
     for (int j = 0; j < SM; ++j) {
       if (j < s && good) {
-        double d = gc[j];
+        double rpj[SM];
 #pragma unroll
-        for (int p = 0; p < j; ++p) d -= rc[p] * rc[p];
-        const double dj = lane_value(d, j);
-        if (!(dj > 0.0) || !isfinite(dj)) {
-          good = false;
+        for (int p = 0; p < j; ++p) rpj[p] = R[p * s + j];
+        double d = G[j * s + j];
+#pragma unroll
+        for (int p = 0; p < j; ++p) d -= rpj[p] * rpj[p];
+        if (!(d > 0.0) || !isfinite(d)) {
+          good = false;  // the same on every lane
         } else {
-          const double rjj = sqrt(dj);
-          double rpj[SM];
-#pragma unroll
-          for (int p = 0; p < j; ++p) rpj[p] = lane_value(rc[p], j);
+          const double rjj = sqrt(d);
+          dinv[j] = 1.0 / rjj;
           if (i == j) {
             rc[j] = rjj;
           } else if (i > j && i < s) {
             double v = gc[j];
 #pragma unroll
             for (int p = 0; p < j; ++p) v -= rpj[p] * rc[p];
-            rc[j] = v / rjj;
+            rc[j] = v * dinv[j];
           }
+          if (i < s) R[j * s + i] = i >= j ? rc[j] : 0.0;
         }
       }
     }
-    if (good && i < s) {
+    if (i == 0) ok = good;
+    if (good && i == 0) {
 #pragma unroll
       for (int p = 0; p < SM; ++p)
-        if (p < s) R[p * s + i] = rc[p];
+        if (p < s) rdiag[p] = dinv[p];
     }
-    if (i == 0) ok = good;
+    if (good && i < s) {
+      const int j = i;  // column j of R^{-1}
+      double ric[SM];
+#pragma unroll
+      for (int p = 0; p < SM; ++p) ric[p] = p == j ? dinv[p] : 0.0;
+#pragma unroll
+      for (int r = SM - 2; r >= 0; --r) {
+        if (r < j) {
+          double v = 0.0;
+#pragma unroll
+          for (int p = r + 1; p < SM; ++p)
+            if (p <= j) v += R[r * s + p] * ric[p];
+          ric[r] = -v * dinv[r];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < SM; ++r)
+        if (r < s) Ri[r * s + j] = ric[r];
+    }
   }
   __syncthreads();
   if (!ok) {
     if (threadIdx.x == 0) {
       ks->blk_ok = 0;
-      ks->sfail += 1;  // sticky count of failed blocks (the host falls back to one-vector steps)
+      ks->sfail += 1;  // sticky count of failed blocks (the host halves the block size)
       ks->done = 1;
     }
     return;
   }
-  if (threadIdx.x < s) {  // R^{-1}: lane j solves for its column by back substitution
-    const int j = threadIdx.x;
-    const double djj = 1.0 / R[j * s + j];
-    double ric[SM];
-#pragma unroll
-    for (int p = 0; p < SM; ++p) ric[p] = p == j ? djj : 0.0;
-#pragma unroll
-    for (int i = SM - 2; i >= 0; --i) {
-      if (i < j) {
-        double v = 0.0;
-#pragma unroll
-        for (int p = i + 1; p < SM; ++p)
-          if (p <= j) v += R[i * s + p] * ric[p];
-        ric[i] = -v / R[i * s + i];
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < SM; ++i)
-      if (i < s) Ri[i * s + j] = ric[i];
-  }
-  __syncthreads();
   // update coefficients: Q = W R^{-1} - V (C R^{-1})
   for (int t = threadIdx.x; t < nv * s; t += blockDim.x) {
     const int q = t / s, j = t % s;
@@ -1030,7 +1037,7 @@ __global__ __launch_bounds__(kBlock) void k_sstep_small(KState* ks, int k, int s
         double v = M1[r * s + j];
 #pragma unroll
         for (int i = 0; i < j; ++i) v -= h[i] * Z[(k + i) * (s + 1) + j];
-        h[j] = v / Z[(k + j) * (s + 1) + j];
+        h[j] = j == 0 ? v : v * rdiag[j - 1];  // T_00 = 1, T_jj = R_{j-1,j-1}
         Hn[r * s + j] = h[j];
       }
     }
@@ -1086,14 +1093,15 @@ __global__ __launch_bounds__(kBlock) void k_sstep_small(KState* ks, int k, int s
       if (t < ns && !st) {
         const double cur = lane_value(v[t], t);
         const double hk1 = lane_value(v[t + 1], t);
-        const double den = hypot(cur, hk1);
+        const double den = sqrt(fma(cur, cur, hk1 * hk1));  // |H| entries are O(||A|| beta): no overflow
         if (!isfinite(den)) {
           nf = 1;
           st = 1;
         } else if (den == 0.0) {  // the new direction adds nothing: the column stays as rotated
           st = 1;
         } else {
-          const double cs = cur / den, sn = hk1 / den;
+          const double inv = 1.0 / den;
+          const double cs = cur * inv, sn = hk1 * inv;
           if (j == t) {
             v[t] = den;
             v[t + 1] = 0.0;
@@ -1147,36 +1155,28 @@ __global__ __launch_bounds__(kBlock) void k_sstep_small(KState* ks, int k, int s
   }
 }
 
-// Q = W R^{-1} - V (C R^{-1}), in place over the block V[k+1..k+s].  The
-// basis part is summed first and W read last, so that W and the
-// accumulators are not live together.  Output columns come in halves of
-// eight: group h of four waves forms Q_{8h..8h+7} for the same elements as
-// the other group (R^{-1} is upper triangular, so group 1 also reads
-// W_0..W_7); with two groups every read of W precedes, by a workgroup
-// barrier, the in-place stores.
-template <typename T, int NH>
-__global__ __launch_bounds__(kBlock * NH) __attribute__((amdgpu_waves_per_eu(NH > 1 ? 4 : 1))) void k_sstep_update(int N, int ldv, T* __restrict__ V, int k, int s,
-                                                            const KState* __restrict__ ks) {
+// Q = W R^{-1} - V (C R^{-1}), in place over the block V[k+1..k+s] (blocks of
+// up to eight vectors).  The basis part is summed first and W read last, so
+// that W and the accumulators are not live together.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_sstep_update(int N, int ldv, T* __restrict__ V, int k, int s,
+                                                       const KState* __restrict__ ks) {
   constexpr int VN = 16 / sizeof(T);
   constexpr int CH = kBlock * VN;
-  constexpr int QU = NH > 1 ? 2 : 4;  // basis vectors loaded together
-  constexpr int HC = 8;  // output columns per group
-  static_assert((NH == 1 || NH == 2) && 2 * HC >= kSMax, "at most two groups of eight columns");
-  __shared__ double D[(kMaxRestart + 1) * kSMax], Ri[kSMax * kSMax];
+  constexpr int QU = 4;  // basis vectors loaded together
+  constexpr int HC = 8;  // output columns
+  __shared__ double D[(kMaxRestart + 1) * HC], Ri[HC * HC];
   __shared__ int okb;
   if (threadIdx.x == 0) okb = ks->blk_ok;
   __syncthreads();
   if (!okb) return;
   const int nv = k + 1;
-  for (int t = threadIdx.x; t < nv * s; t += blockDim.x) D[t] = ks->dco[t];
-  for (int t = threadIdx.x; t < s * s; t += blockDim.x) Ri[t] = ks->rinv[t];
+  for (int t = threadIdx.x; t < nv * s; t += kBlock) D[t] = ks->dco[t];
+  for (int t = threadIdx.x; t < s * s; t += kBlock) Ri[t] = ks->rinv[t];
   __syncthreads();
-  const int grp = NH > 1 ? (int)(threadIdx.x / kBlock) : 0;
-  const int tid = threadIdx.x - grp * kBlock;
-  const int j0 = grp * HC, sj = min(HC, s - j0);
   T* __restrict__ W = V + (size_t)(k + 1) * ldv;
   for (int base = blockIdx.x * CH; base < N; base += gridDim.x * CH) {
-    const int e = base + tid * VN;
+    const int e = base + threadIdx.x * VN;
     double acc[HC][VN];
 #pragma unroll
     for (int j = 0; j < HC; ++j)
@@ -1192,36 +1192,103 @@ __global__ __launch_bounds__(kBlock * NH) __attribute__((amdgpu_waves_per_eu(NH 
         if (q0 + u < nv) {
 #pragma unroll
           for (int j = 0; j < HC; ++j)
-            if (j < sj) {
-              const double d = D[(q0 + u) * s + j0 + j];
+            if (j < s) {
+              const double d = D[(q0 + u) * s + j];
 #pragma unroll
               for (int c = 0; c < VN; ++c) acc[j][c] -= d * (double)a[u][c];
             }
         }
       }
     }
-    for (int i = 0; i < j0 + sj; ++i) {
-      T w[VN];
-      load16(W + (size_t)i * ldv, e, N, w);
 #pragma unroll
-      for (int j = 0; j < HC; ++j)
-        if (i <= j0 + j && j < sj) {
-          const double r = Ri[i * s + j0 + j];
+    for (int i = 0; i < HC; ++i)
+      if (i < s) {
+        T w[VN];
+        load16(W + (size_t)i * ldv, e, N, w);
 #pragma unroll
-          for (int c = 0; c < VN; ++c) acc[j][c] += r * (double)w[c];
-        }
-    }
-    if (NH > 1) __syncthreads();  // both groups have read W_0..W_7 of these elements
+        for (int j = 0; j < HC; ++j)
+          if (i <= j && j < s) {
+            const double r = Ri[i * s + j];
+#pragma unroll
+            for (int c = 0; c < VN; ++c) acc[j][c] += r * (double)w[c];
+          }
+      }
 #pragma unroll
     for (int j = 0; j < HC; ++j)
-      if (j < sj) {
+      if (j < s) {
         T o[VN];
 #pragma unroll
         for (int c = 0; c < VN; ++c) o[c] = (T)acc[j][c];
-        store16(W + (size_t)(j0 + j) * ldv, e, N, o);
+        store16(W + (size_t)j * ldv, e, N, o);
       }
   }
 }
+
+// The same update for blocks of more than eight vectors, on the FP64 matrix
+// cores: Q^T = Coef^T [W_0..W_{s-1}, V_0..V_k]^T with Coef = [R^{-1}; -C R^{-1}]
+// (K = s + k + 1 rows, taken four at a time by v_mfma_f64_16x16x4f64).  A
+// wave takes 64-element tiles; lane l loads four consecutive elements of row
+// 4 g + (l >> 4) of each row group g at element 4 (l & 15) (256 contiguous
+// bytes per row and load), and the four elements become the four MFMA
+// chains x = 0..3, so that lane l ends with Q_{(l >> 4) + 4 v} at elements
+// 4 (l & 15) + x and stores them as one 16-byte write per column.  Every row
+// of a tile is read before the tile's in-place stores; waves own disjoint
+// tiles.
+template <int KG>
+__global__ __launch_bounds__(kBlock) void k_sstep_update_mfma(int N, int ldv, float* __restrict__ V, int k, int s,
+                                                             const KState* __restrict__ ks) {
+  constexpr int NW = kBlock / 64;
+  if (!ks->blk_ok) return;
+  const int nv = k + 1, K = s + nv;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  float* __restrict__ W = V + (size_t)(k + 1) * ldv;
+  // A operand of row group g: Coef[4 g + lk][li]
+  double cf[KG];
+  const float* rp[KG];
+  bool rv[KG];
+#pragma unroll
+  for (int g = 0; g < KG; ++g) {
+    const int r = 4 * g + lk;
+    double c = 0.0;
+    if (r < K && li < s) c = r < s ? (r <= li ? ks->rinv[r * s + li] : 0.0) : -ks->dco[(r - s) * s + li];
+    cf[g] = c;
+    rv[g] = r < K;
+    rp[g] = r < s ? W + (size_t)r * ldv : (r < K ? V + (size_t)(r - s) * ldv : V);
+  }
+  const int ntile = (N + 63) / 64;
+  const int gw = blockIdx.x * NW + wv, nw = gridDim.x * NW;
+  const int t0 = (int)((int64_t)gw * ntile / nw), t1 = (int)((int64_t)(gw + 1) * ntile / nw);
+  for (int t = t0; t < t1; ++t) {
+    const int e = t * 64 + 4 * li;
+    float a[KG][4];
+#pragma unroll
+    for (int g = 0; g < KG; ++g) {
+#pragma unroll
+      for (int x = 0; x < 4; ++x) a[g][x] = 0.f;
+      if (rv[g]) load16(rp[g], e, N, a[g]);
+    }
+    mfma_d4 acc[4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x) acc[x] = mfma_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int g = 0; g < KG; ++g)
+#pragma unroll
+      for (int x = 0; x < 4; ++x) acc[x] = __builtin_amdgcn_mfma_f64_16x16x4f64(cf[g], (double)a[g][x], acc[x], 0, 0, 0);
+    // lane l holds Q_i, i = lk + 4 v, at elements e .. e + 3
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = lk + 4 * v;
+      if (i < s) {
+        float o[4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x) o[x] = (float)acc[x][v];
+        store16(W + (size_t)i * ldv, e, N, o);
+      }
+    }
+  }
+}
+
 
 // back substitution R y = g over the columns completed in the cycle (one
 // wave): lane j holds row j of R and g_j; y_i = g_i / R_ii, broadcast from
@@ -2516,13 +2583,27 @@ void sstep_reduce(H* h, int k, int s, int m, double theta) {
     launch(h, AFC_KERNEL_FINISH, k_sstep_small<kSMax>, 1, kBlock, h->ks, k, s, m, theta);
 }
 
+// blocks of up to eight vectors: FP64 FMAs per element; larger blocks: the
+// FP64 matrix cores, in row groups of four (K = s + k + 1 <= m rows)
 void sstep_update(H* h, int k, int s) {
-  if (s <= 8)
-    launch(h, AFC_KERNEL_UPDATE, k_sstep_update<float, 1>, gmres_grid(h, true), kBlock, h->N, h->ldv, h->V32, k,
-           s, (const KState*)h->ks);
+  if (s <= 8) {
+    launch(h, AFC_KERNEL_UPDATE, k_sstep_update<float>, gmres_grid(h, true), kBlock, h->N, h->ldv, h->V32, k, s,
+           (const KState*)h->ks);
+    return;
+  }
+  const int kg = (k + 1 + s + 3) / 4;
+  const int nb = sstep_grid(h);
+  static_assert(kMaxRestart <= 4 * 16, "row groups of the largest updated block");
+  if (kg <= 4)
+    launch(h, AFC_KERNEL_UPDATE, k_sstep_update_mfma<4>, nb, kBlock, h->N, h->ldv, h->V32, k, s, (const KState*)h->ks);
+  else if (kg <= 8)
+    launch(h, AFC_KERNEL_UPDATE, k_sstep_update_mfma<8>, nb, kBlock, h->N, h->ldv, h->V32, k, s, (const KState*)h->ks);
+  else if (kg <= 12)
+    launch(h, AFC_KERNEL_UPDATE, k_sstep_update_mfma<12>, nb, kBlock, h->N, h->ldv, h->V32, k, s,
+           (const KState*)h->ks);
   else
-    launch(h, AFC_KERNEL_UPDATE, k_sstep_update<float, 2>, gmres_grid(h, true), 2 * kBlock, h->N, h->ldv, h->V32,
-           k, s, (const KState*)h->ks);
+    launch(h, AFC_KERNEL_UPDATE, k_sstep_update_mfma<16>, nb, kBlock, h->N, h->ldv, h->V32, k, s,
+           (const KState*)h->ks);
 }
 
 void gmres_solve(H* h, int m) { k_gmres_solve<<<1, 64, 0, h->stream>>>(h->ks, m); }
