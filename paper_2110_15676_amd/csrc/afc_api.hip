@@ -329,7 +329,7 @@ SolveOut solve_gmres(afc_handle* h, const SysMat& S, const double* b, double* x,
       kb = k;
       sbl = sb;
     }
-    afc::gmres_solve(h, m);
+    afc::gmres_solve(h, m, kb, sbl);
     afc::sstep_xupdate(h, kb, sbl, S.dinv, x);
     afc::residual(h, S.S64, b, x, r, 2);
     afc::cast_v0(h, r);

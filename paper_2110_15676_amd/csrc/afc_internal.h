@@ -52,6 +52,10 @@ struct KState {
   double dco[(kMaxRestart + 1) * kSMax];
   double rinv[kSMax * kSMax];
   int blk_ok;                                 // the running block's QR succeeded
+  // x update of an s-step cycle: combined coefficients of V_0..V_{xnq-1}, then
+  // of the xnw raw vectors of the last block (written by the back substitution)
+  int xnq, xnw;
+  double xco[kMaxRestart + 1 + kSMax];
 };
 
 // bytes of KState copied back to the host: scalars + red[0..7]

@@ -52,7 +52,7 @@ void spmv32(H* h, const float* A32, const float* x, float theta, int rev, float*
 void sstep_dots(H* h, int k, int s);
 void sstep_reduce(H* h, int k, int s, int m, double theta);
 void sstep_update(H* h, int k, int s);
-void gmres_solve(H* h, int m);
+void gmres_solve(H* h, int m, int kb = 0, int sb = 0);  // sb > 0: also the x-update coefficients of an s-step cycle
 void gmres_xupdate(H* h, bool fp32, const double* dinv, double* x);
 // end of an s-step cycle whose last block (start kb, sb vectors) was not orthogonalized in place
 void sstep_xupdate(H* h, int kb, int sb, const double* dinv, double* x);

@@ -342,7 +342,7 @@ __global__ __launch_bounds__(kBlock) void k_sell_spmv32(SellView S, const TI* __
     if (i >= S.N) continue;
     float acc = sell_row<8>(S, dlt, val, s, i, [&](int j) { return x[j]; });
     if (theta != 1.0f) acc += (1.0f - theta) * x[i];
-    y[i] = acc;
+    __builtin_nontemporal_store(acc, y + i);
   }
 }
 
@@ -935,31 +935,24 @@ __global__ __launch_bounds__(kBlock) void k_sstep_small(KState* ks, int k, int s
       rc[p] = 0.0;
       dinv[p] = 0.0;
     }
-    bool good = true;
+    bool good = true;  // the same on every lane: formed from broadcast values only
 #pragma unroll
     for (int j = 0; j < SM; ++j) {
-      if (j < s && good) {
+      if (j < s) {
         double rpj[SM];
 #pragma unroll
         for (int p = 0; p < j; ++p) rpj[p] = R[p * s + j];
-        double d = G[j * s + j];
+        double d = G[j * s + j], v = gc[j];
 #pragma unroll
-        for (int p = 0; p < j; ++p) d -= rpj[p] * rpj[p];
-        if (!(d > 0.0) || !isfinite(d)) {
-          good = false;  // the same on every lane
-        } else {
-          const double rjj = sqrt(d);
-          dinv[j] = 1.0 / rjj;
-          if (i == j) {
-            rc[j] = rjj;
-          } else if (i > j && i < s) {
-            double v = gc[j];
-#pragma unroll
-            for (int p = 0; p < j; ++p) v -= rpj[p] * rc[p];
-            rc[j] = v * dinv[j];
-          }
-          if (i < s) R[j * s + i] = i >= j ? rc[j] : 0.0;
+        for (int p = 0; p < j; ++p) {
+          d -= rpj[p] * rpj[p];
+          v -= rpj[p] * rc[p];
         }
+        good = good && d > 0.0 && isfinite(d);
+        const double rjj = sqrt(d);
+        dinv[j] = 1.0 / rjj;
+        rc[j] = i == j ? rjj : (i > j ? v * dinv[j] : 0.0);
+        if (i < s) R[j * s + i] = rc[j];
       }
     }
     if (i == 0) ok = good;
@@ -968,24 +961,26 @@ __global__ __launch_bounds__(kBlock) void k_sstep_small(KState* ks, int k, int s
       for (int p = 0; p < SM; ++p)
         if (p < s) rdiag[p] = dinv[p];
     }
-    if (good && i < s) {
-      const int j = i;  // column j of R^{-1}
+    if (good) {
+      // column i of R^{-1}: entries below the diagonal stay 0, entries above
+      // by back substitution; rows of R beyond s read as 0
       double ric[SM];
 #pragma unroll
-      for (int p = 0; p < SM; ++p) ric[p] = p == j ? dinv[p] : 0.0;
+      for (int p = 0; p < SM; ++p) ric[p] = p == i ? dinv[p] : 0.0;
 #pragma unroll
       for (int r = SM - 2; r >= 0; --r) {
-        if (r < j) {
+        if (r < s - 1) {
           double v = 0.0;
 #pragma unroll
-          for (int p = r + 1; p < SM; ++p)
-            if (p <= j) v += R[r * s + p] * ric[p];
-          ric[r] = -v * dinv[r];
+          for (int p = r + 1; p < SM; ++p) v += (p < s ? R[r * s + p] : 0.0) * ric[p];
+          ric[r] = r < i ? -v * dinv[r] : ric[r];
         }
       }
+      if (i < s) {
 #pragma unroll
-      for (int r = 0; r < SM; ++r)
-        if (r < s) Ri[r * s + j] = ric[r];
+        for (int r = 0; r < SM; ++r)
+          if (r < s) Ri[r * s + i] = ric[r];
+      }
     }
   }
   __syncthreads();
@@ -1102,14 +1097,10 @@ __global__ __launch_bounds__(kBlock) void k_sstep_small(KState* ks, int k, int s
         } else {
           const double inv = 1.0 / den;
           const double cs = cur * inv, sn = hk1 * inv;
-          if (j == t) {
-            v[t] = den;
-            v[t + 1] = 0.0;
-          } else if (j > t && mine) {
-            const double a = v[t], b = v[t + 1];
-            v[t] = cs * a + sn * b;
-            v[t + 1] = -sn * a + cs * b;
-          }
+          const double a = v[t], b = v[t + 1];
+          const bool later = j > t && mine;
+          v[t] = j == t ? den : (later ? cs * a + sn * b : a);
+          v[t + 1] = j == t ? 0.0 : (later ? -sn * a + cs * b : b);
           const double gn = -sn * gk;
           if (j == 0) {
             gcs[k + t] = cs;
@@ -1293,7 +1284,10 @@ __global__ __launch_bounds__(kBlock) void k_sstep_update_mfma(int N, int ldv, fl
 // back substitution R y = g over the columns completed in the cycle (one
 // wave): lane j holds row j of R and g_j; y_i = g_i / R_ii, broadcast from
 // lane i, then g_j -= R_ji y_i on the rows above, for i from the last row up
-__global__ __launch_bounds__(64) void k_gmres_solve(KState* ks, int m) {
+// sb > 0: the cycle ended with an s-step block of sb raw vectors starting at
+// kb; lane t then also forms the combined coefficient t of the x update
+// (see k_sstep_xupdate) into ks->xco.
+__global__ __launch_bounds__(64) void k_gmres_solve(KState* ks, int m, int kb, int sb) {
   static_assert(kMaxRestart <= 64, "one row of R per lane");
   if (ks->solved) return;
   const int kk = ks->k;
@@ -1311,7 +1305,30 @@ __global__ __launch_bounds__(64) void k_gmres_solve(KState* ks, int m) {
       if (j == i) gj = yi;
     }
   }
-  if (j < kk) ks->coef[j] = gj * ks->sc[j];
+  const double cj = gj * ks->sc[j < kk ? j : 0];
+  if (j < kk) ks->coef[j] = cj;
+  if (sb <= 0) return;
+  __shared__ double cf[kMaxRestart];
+  if (j < kk) cf[j] = cj;
+  __syncthreads();
+  const int J = min(kk - kb - 1, sb);  // block vectors used by the solution
+  const int nq = J > 0 ? kb + 1 : kk, nw = J > 0 ? sb : 0;
+  for (int t = j; t < nq + nw; t += 64) {
+    double v;
+    if (t < nq) {  // a_q = y_q - sum_{i < J} y_{kb+1+i} (C R^{-1})_{q i}
+      v = cf[t];
+      for (int i = 0; i < J; ++i) v -= cf[kb + 1 + i] * ks->dco[t * sb + i];
+    } else {       // b_i = sum_{i <= l < J} y_{kb+1+l} (R^{-1})_{i l}
+      const int i = t - nq;
+      v = 0.0;
+      for (int l = i; l < J; ++l) v += cf[kb + 1 + l] * ks->rinv[i * sb + l];
+    }
+    ks->xco[t] = v;
+  }
+  if (j == 0) {
+    ks->xnq = nq;
+    ks->xnw = nw;
+  }
 }
 
 // End of an s-step cycle whose last block starts at kb with sb vectors: the
@@ -1330,21 +1347,11 @@ __global__ __launch_bounds__(kBlock) void k_sstep_xupdate(int N, int ldv, const 
   constexpr int CH = kBlock * VN;
   constexpr int QU = 4;
   __shared__ double a[kMaxRestart + 1 + kSMax];
-  const int kk = ks->k;
-  const int J = min(kk - kb - 1, sb);
-  const int nq = J > 0 ? kb + 1 : kk;  // basis vectors V_0.. with coefficients
-  const int nw = J > 0 ? sb : 0;       // raw block vectors with coefficients
-  for (int q = threadIdx.x; q < nq; q += kBlock) {
-    double v = ks->coef[q];
-    for (int j = 0; j < J; ++j) v -= ks->coef[kb + 1 + j] * ks->dco[q * sb + j];
-    a[q] = v;
-  }
-  for (int i = threadIdx.x; i < nw; i += kBlock) {
-    double v = 0.0;
-    for (int j = i; j < J; ++j) v += ks->coef[kb + 1 + j] * ks->rinv[i * sb + j];
-    a[nq + i] = v;
-  }
+  const int nq = ks->xnq;  // basis vectors V_0.. with coefficients
+  const int nw = ks->xnw;  // raw block vectors with coefficients
+  for (int q = threadIdx.x; q < nq + nw; q += kBlock) a[q] = ks->xco[q];
   __syncthreads();
+  const bool vec = ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(dinv)) & 15) == 0;
   const int nt = nq + nw;  // V_0..V_{nq-1}, then V_{kb+1..kb+nw} (the raw W)
   for (int base = blockIdx.x * CH; base < N; base += gridDim.x * CH) {
     const int e = base + threadIdx.x * VN;
@@ -1367,9 +1374,22 @@ __global__ __launch_bounds__(kBlock) void k_sstep_xupdate(int N, int ldv, const 
         }
       }
     }
+    if (vec && VN == 4 && e + 4 <= N) {  // two 16-byte accesses per array
+      double2* xp = reinterpret_cast<double2*>(x + e);
+      const double2* dp = reinterpret_cast<const double2*>(dinv + e);
+      const double2 d0 = dp[0], d1 = dp[1];
+      double2 x0 = xp[0], x1 = xp[1];
+      x0.x += d0.x * acc[0];
+      x0.y += d0.y * acc[1 % VN];
+      x1.x += d1.x * acc[2 % VN];
+      x1.y += d1.y * acc[3 % VN];
+      xp[0] = x0;
+      xp[1] = x1;
+    } else {
 #pragma unroll
-    for (int c = 0; c < VN; ++c)
-      if (e + c < N) x[e + c] += dinv[e + c] * acc[c];
+      for (int c = 0; c < VN; ++c)
+        if (e + c < N) x[e + c] += dinv[e + c] * acc[c];
+    }
   }
 }
 
@@ -2606,7 +2626,7 @@ void sstep_update(H* h, int k, int s) {
            (const KState*)h->ks);
 }
 
-void gmres_solve(H* h, int m) { k_gmres_solve<<<1, 64, 0, h->stream>>>(h->ks, m); }
+void gmres_solve(H* h, int m, int kb, int sb) { k_gmres_solve<<<1, 64, 0, h->stream>>>(h->ks, m, kb, sb); }
 
 void sstep_xupdate(H* h, int kb, int sb, const double* dinv, double* x) {
   k_sstep_xupdate<float><<<vec16_grid(h, kBlock * 4), kBlock, 0, h->stream>>>(h->N, h->ldv, h->V32, dinv, x, h->ks,
