@@ -592,7 +592,7 @@ def traffic_probe(n, sstep):
         add("k_sell_spmv32", afc.AFC_KERNEL_SPMV32, h)
         # blocks of more than eight vectors: the projections run on the matrix cores
         add(pre + ("_dots_mfma" if ss > 8 else "_dots"), afc.AFC_KERNEL_DOTS, h)
-        add(pre + "_update", afc.AFC_KERNEL_UPDATE, h)
+        add(pre + ("_update_mfma" if ss > 8 else "_update"), afc.AFC_KERNEL_UPDATE, h)
         add("k_sell_residual", afc.AFC_KERNEL_RESIDUAL, h)
         afc.afc_destroy(h)
         del u
@@ -639,8 +639,8 @@ def traffic_summarize(fetch_csv, write_csv, probe_log, n):
     sf, sw = gib_kib / (sum(cf[:3]) / 3), gib_kib / (sum(cw[:3]) / 3)
     table = {}
     for name in ("k_sell_spmv32", "k_gmres_dots", "k_gmres_update", "k_gmres_reduce", "k_sstep_dots",
-                 "k_sstep_dots_mfma", "k_sstep_update", "k_sstep_sums", "k_sell_residual", "k_mcl_bounds_sell",
-                 "k_mcl_apply_sell"):
+                 "k_sstep_dots_mfma", "k_sstep_update", "k_sstep_update_mfma", "k_sstep_sums", "k_sell_residual",
+                 "k_mcl_bounds_sell", "k_mcl_apply_sell"):
         f = [v for v in series(fe, name) if v > 1024]
         w = [v for v in series(wr, name) if v > 1024]
         if f:
