@@ -312,6 +312,15 @@ SolveOut solve_gmres(afc_handle* h, const SysMat& S, const double* b, double* x,
   // and later solves on the handle, use half the block size (one vector per
   // step below 2) until the options are set again.
   int s = mixed ? std::min(h->opt.sstep, h->sstep_cap) : 0;
+  // A solve expected to take fewer iterations than a block (the handle's
+  // previous solve, e.g. inexact fixed-point solves) uses blocks of 4 or 8,
+  // whichever first covers them, so that a block computes few powers beyond
+  // the solve's end; two extra sizes keep the graph cache small.
+  for (int q = 4; q <= 8; q *= 2)
+    if (h->gmres_last <= q && q < s) {
+      s = q;
+      break;
+    }
   if (s < 2) s = 0;
   const double theta = h->opt.sstep_shift;
   // The last block is not orthogonalized in place: no later step reads its
@@ -454,6 +463,7 @@ SolveOut solve_gmres(afc_handle* h, const SysMat& S, const double* b, double* x,
   o.iters = h->host_status->iters - it0;
   if (mixed) o.inner = o.iters;
   o.res = res;
+  h->gmres_last = (int)std::min<int64_t>(o.iters, 1 << 30);
   return o;
 }
 
@@ -1071,6 +1081,7 @@ afc_status afc_set_options(afc_handle* h, const afc_options* opt) {
   h->stream = static_cast<hipStream_t>(opt->stream);
   h->G = pick_lanes(h->nnz, h->N, opt->lanes_per_row);
   h->sstep_cap = afc::kMaxRestart;
+  h->gmres_last = 1 << 30;
   return AFC_OK;
 }
 

@@ -148,6 +148,7 @@ struct afc_handle_s {
   int ldv = 0;  // basis / work vector stride: N rounded up to 64 (16-byte aligned rows)
   int bicg_last = 2;  // BiCGStab iterations of the handle's last solve (first chunk size)
   int sstep_cap = afc::kMaxRestart;  // s-step block size cap: halved by a failed block QR, reset by afc_set_options
+  int gmres_last = 1 << 30;          // Krylov iterations of the handle's last GMRES solve (block size choice)
   double* partials = nullptr;  // kMaxRed * kRedBlocks
   double* partials_res = nullptr;  // one per workgroup of the FP64 SELL residual
   double* partials_blk = nullptr;  // kBlkRows * kRedBlocks (s-step GMRES, allocated on first use)
