@@ -265,12 +265,31 @@ SolveOut solve_gmres(afc_handle* h, const SysMat& S, const double* b, double* x,
   const bool mixed = h->opt.precision == AFC_PREC_MIXED;
   // MIXED: one refinement sweep = one FP32 cycle of at most min(restart, inner_maxit) steps
   const int m = mixed ? std::min(h->opt.restart, h->opt.inner_maxit) : h->opt.restart;
-  ensure_basis(h, m, mixed);
   const double inner_rel = mixed ? h->opt.inner_rtol : 0.0;
   const int64_t cap = h->opt.lin_maxit;
-  if (mixed) {
+  // s-step blocks (both precisions): blocks of s basis vectors from the
+  // shifted powers (A - theta I)^j (default theta = 1, the centre of the
+  // Gershgorin discs of the Jacobi-scaled matrix).  A cycle whose status
+  // shows a failed block QR makes later cycles, in this and later solves on
+  // the handle, use half the block size (one vector per step below 2) until
+  // the options are set again.
+  int s = std::min(h->opt.sstep, h->sstep_cap);
+  // A solve expected to take fewer iterations than a block (the handle's
+  // previous solve, e.g. inexact fixed-point solves) uses blocks of 4 or 8,
+  // whichever first covers them, so that a block computes few powers beyond
+  // the solve's end; two extra sizes keep the graph cache small.
+  for (int q = 4; q <= 8; q *= 2)
+    if (h->gmres_last <= q && q < s) {
+      s = q;
+      break;
+    }
+  if (s < 2) s = 0;
+  ensure_basis(h, m, mixed);
+  // start vector: normalized in the basis precision (mixed, and FP64 s-step
+  // cycles), or FP64 r with its scale 1/beta (FP64 one-vector cycles)
+  if (mixed || s) {
     afc::cycle_start(h, 2, red_idx, tol, inner_rel);
-    afc::cast_v0(h, r);
+    afc::cast_v0(h, r, !mixed);
   } else {
     afc::copy(h, h->V64, r);
     afc::cycle_start(h, 1, red_idx, tol, 0.0);
@@ -305,23 +324,6 @@ SolveOut solve_gmres(afc_handle* h, const SysMat& S, const double* b, double* x,
       afc::residual(h, S.S64, b, x, h->V64, 1);
     }
   };
-  // s-step variant (mixed precision): blocks of s basis vectors from the
-  // shifted powers (A - theta I)^j (default theta = 1, the centre of the
-  // Gershgorin discs of the Jacobi-scaled matrix)
-  // A cycle whose status shows a failed block QR makes later cycles, in this
-  // and later solves on the handle, use half the block size (one vector per
-  // step below 2) until the options are set again.
-  int s = mixed ? std::min(h->opt.sstep, h->sstep_cap) : 0;
-  // A solve expected to take fewer iterations than a block (the handle's
-  // previous solve, e.g. inexact fixed-point solves) uses blocks of 4 or 8,
-  // whichever first covers them, so that a block computes few powers beyond
-  // the solve's end; two extra sizes keep the graph cache small.
-  for (int q = 4; q <= 8; q *= 2)
-    if (h->gmres_last <= q && q < s) {
-      s = q;
-      break;
-    }
-  if (s < 2) s = 0;
   const double theta = h->opt.sstep_shift;
   // The last block is not orthogonalized in place: no later step reads its
   // vectors, and the x update takes them raw with their coefficients.
@@ -329,19 +331,23 @@ SolveOut solve_gmres(afc_handle* h, const SysMat& S, const double* b, double* x,
     int kb = 0, sbl = 0;
     for (int k = 0; k < m; k += s) {
       const int sb = std::min(s, m - k);
-      for (int j = 1; j <= sb; ++j)  // alternating sweep directions (cache reuse between the SpMVs)
-        afc::spmv32(h, S.S32, h->V32 + (size_t)(k + j - 1) * h->ldv, (float)theta, (j + 1) & 1,
-                    h->V32 + (size_t)(k + j) * h->ldv);
-      afc::sstep_dots(h, k, sb);
-      afc::sstep_reduce(h, k, sb, m, theta);
-      if (k + sb < m) afc::sstep_update(h, k, sb);
+      for (int j = 1; j <= sb; ++j) {  // alternating sweep directions (cache reuse between the SpMVs)
+        const size_t src = (size_t)(k + j - 1) * h->ldv, dst = (size_t)(k + j) * h->ldv;
+        if (mixed)
+          afc::spmv32(h, S.S32, h->V32 + src, (float)theta, (j + 1) & 1, h->V32 + dst);
+        else
+          afc::spmv64(h, S.S64, S.dinv, h->V64 + src, theta, (j + 1) & 1, h->V64 + dst);
+      }
+      afc::sstep_dots(h, k, sb, !mixed);
+      afc::sstep_reduce(h, k, sb, m, theta, !mixed);
+      if (k + sb < m) afc::sstep_update(h, k, sb, !mixed);
       kb = k;
       sbl = sb;
     }
     afc::gmres_solve(h, m, kb, sbl);
-    afc::sstep_xupdate(h, kb, sbl, S.dinv, x);
+    afc::sstep_xupdate(h, kb, sbl, S.dinv, x, !mixed);
     afc::residual(h, S.S64, b, x, r, 2);
-    afc::cast_v0(h, r);
+    afc::cast_v0(h, r, !mixed);
   };
   if (s && !h->partials_blk) {
     h->partials_blk = dalloc<double>(h, (size_t)afc::kBlkRows * afc::kRedBlocks);
@@ -356,8 +362,9 @@ SolveOut solve_gmres(afc_handle* h, const SysMat& S, const double* b, double* x,
   auto issue = [&]() {
     if (s) {
       if (graphs)
-        HIP_OK(hipGraphLaunch(cached_graph(h, {key_int(3), S.S32, S.S64, S.dinv, b, x, r, h->V32, key_int(m),
-                                               key_int(s), key_int(h->ldv), key_int((int64_t)theta_bits)},
+        HIP_OK(hipGraphLaunch(cached_graph(h, {key_int(3), S.S32, S.S64, S.dinv, b, x, r, h->V32, h->V64,
+                                               key_int(m), key_int(mixed), key_int(s), key_int(h->ldv),
+                                               key_int((int64_t)theta_bits)},
                                            cycle_sstep),
                               h->stream));
       else
@@ -390,7 +397,7 @@ SolveOut solve_gmres(afc_handle* h, const SysMat& S, const double* b, double* x,
       o.sweeps += 1;
       sync_status(h);
       if (s_used) {
-        afc::prof_sstep_cycle(h, m, s_used, h->host_status->iters - cycle_it0);
+        afc::prof_sstep_cycle(h, m, s_used, h->host_status->iters - cycle_it0, !mixed);
         after_status(h->host_status->sfail, s_used);
       } else {
         afc::prof_gmres_cycle(h, mixed, m, h->host_status->iters - cycle_it0);

@@ -180,7 +180,7 @@ namespace afc {
 // Algorithmic HBM bytes of one GMRES cycle whose Arnoldi process completed kk
 // columns out of m, added to the per-kernel work counters (profiling only).
 void prof_gmres_cycle(afc_handle_s* h, bool fp32, int m, int kk);
-void prof_sstep_cycle(afc_handle_s* h, int m, int s, int kk);  // the same for an s-step cycle
+void prof_sstep_cycle(afc_handle_s* h, int m, int s, int kk, bool fp64);  // the same for an s-step cycle
 void prof_collect(afc_handle_s* h);  // fold completed event pairs into the totals
 void prof_release(afc_handle_s* h);
 }  // namespace afc

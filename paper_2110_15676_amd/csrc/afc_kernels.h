@@ -33,7 +33,7 @@ int sell_grid(const H* h, bool reduce);
 // that the solve's cycle_start stored in the device state.
 void residual(H* h, const double* A, const double* b, const double* x, double* r, int mode);
 void cycle_start(H* h, int mode, int red_idx, double tol_abs, double tol_rel);  // from a finished reduction
-void cast_v0(H* h, const double* r);
+void cast_v0(H* h, const double* r, bool fp64 = false);  // V[0] = r / beta in the basis precision
 
 // --- GMRES (right Jacobi), FP64 or FP32 Arnoldi --------------------------------
 // Arnoldi step k = spmv + dots + reduce (finalizes the projections and the
@@ -45,17 +45,20 @@ void gmres_dots(H* h, bool fp32, int k);
 void gmres_reduce(H* h, bool fp32, int k, int m);
 void gmres_update(H* h, bool fp32, int k);
 void gmres_last_givens(H* h, bool fp32, int k, int m);
-// s-step GMRES block (FP32 basis): the shifted powers are spmv32 calls into
+// s-step GMRES block (FP32 basis in mixed precision, FP64 basis in FP64 mode):
+// the shifted powers are spmv32 / spmv64 calls into
 // V[k+1..k+s]; then projections + Gram, the block reduction (Cholesky QR,
 // Hessenberg columns, Givens) and the in-place orthonormalization
 void spmv32(H* h, const float* A32, const float* x, float theta, int rev, float* y);
-void sstep_dots(H* h, int k, int s);
-void sstep_reduce(H* h, int k, int s, int m, double theta);
-void sstep_update(H* h, int k, int s);
+// y = A (dinv .* x) - theta x (FP64; the SELL FP64 system matrix)
+void spmv64(H* h, const double* A, const double* dinv, const double* x, double theta, int rev, double* y);
+void sstep_dots(H* h, int k, int s, bool fp64 = false);
+void sstep_reduce(H* h, int k, int s, int m, double theta, bool fp64 = false);
+void sstep_update(H* h, int k, int s, bool fp64 = false);
 void gmres_solve(H* h, int m, int kb = 0, int sb = 0);  // sb > 0: also the x-update coefficients of an s-step cycle
 void gmres_xupdate(H* h, bool fp32, const double* dinv, double* x);
 // end of an s-step cycle whose last block (start kb, sb vectors) was not orthogonalized in place
-void sstep_xupdate(H* h, int kb, int sb, const double* dinv, double* x);
+void sstep_xupdate(H* h, int kb, int sb, const double* dinv, double* x, bool fp64 = false);
 
 // --- BiCGStab (right Jacobi, FP64) ----------------------------------------------
 struct BicgVec { double *x, *r, *rhat, *p, *v, *s, *t; };

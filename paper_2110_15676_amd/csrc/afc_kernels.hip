@@ -175,12 +175,13 @@ __global__ void k_cycle_start(KState* ks, int mode, int idx, double tol_abs, dou
   if (threadIdx.x == 0 && blockIdx.x == 0) cycle_start_dev(ks, mode, ks->red[idx], tol_abs, tol_rel);
 }
 
-__global__ __launch_bounds__(kBlock) void k_cast_v0(int N, const double* __restrict__ r, float* __restrict__ V0,
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cast_v0(int N, const double* __restrict__ r, T* __restrict__ V0,
                                                     const KState* __restrict__ ks) {
   if (ks->solved) return;
   const double beta = ks->beta;
   const double inv = beta > 0.0 ? 1.0 / beta : 0.0;
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) V0[i] = (float)(r[i] * inv);
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) V0[i] = (T)(r[i] * inv);
 }
 
 // Givens step for Arnoldi column k, called by every thread of one workgroup:
@@ -346,21 +347,30 @@ __global__ __launch_bounds__(kBlock) void k_sell_spmv32(SellView S, const TI* __
   }
 }
 
-// FP64: y = A (sc .* x)
+// FP64: y = A (sc .* x); theta != 0: y = A (sc .* x) - theta x (the shifted
+// powers of s-step GMRES with sc = D^{-1}); rev as in k_sell_spmv32
 template <typename TI>
 __global__ __launch_bounds__(kBlock) void k_sell_spmv64(SellView S, const TI* __restrict__ dlt,
                                                         const double* __restrict__ val,
                                                         const double* __restrict__ sc, const double* __restrict__ x,
-                                                        const KState* __restrict__ ks, double* __restrict__ y) {
+                                                        const KState* __restrict__ ks, double theta, int rev,
+                                                        double* __restrict__ y) {
   if (ks->done) return;
+  const int nt = (S.nsl + kBlock / 64 - 1) / (kBlock / 64);
   int t0, t1;
-  tile_range((S.nsl + kBlock / 64 - 1) / (kBlock / 64), t0, t1);
-  for (int t = t0; t < t1; ++t) {
+  if (rev)
+    tile_range_rev(nt, t0, t1);
+  else
+    tile_range(nt, t0, t1);
+  for (int tt = t0; tt < t1; ++tt) {
+    const int t = rev ? t1 - 1 - (tt - t0) : tt;
     const int s = wave_slice(t);
     if (s >= S.nsl) continue;
     const int i = s * 64 + (threadIdx.x & 63);
     if (i >= S.N) continue;
-    y[i] = sell_row<8>(S, dlt, val, s, i, [&](int j) { return sc[j] * x[j]; });
+    double acc = sell_row<8>(S, dlt, val, s, i, [&](int j) { return sc[j] * x[j]; });
+    if (theta != 0.0) acc -= theta * x[i];
+    y[i] = acc;
   }
 }
 
@@ -756,19 +766,20 @@ __global__ __launch_bounds__(kBlock) void k_sstep_dots(int N, int ldv, const T* 
 // current one.  The four waves' tiles are summed in LDS in a fixed order.
 typedef double mfma_d4 __attribute__((ext_vector_type(4)));
 
-template <int NT>
-__global__ __launch_bounds__(kBlock) void k_sstep_dots_mfma(int N, int ldv, const float* __restrict__ V, int k,
-                                                           int s, const KState* __restrict__ ks,
+template <typename T, int NT>
+__global__ __launch_bounds__(kBlock) void k_sstep_dots_mfma(int N, int ldv, const T* __restrict__ V, int k, int s,
+                                                           const KState* __restrict__ ks,
                                                            double* __restrict__ partials) {
   if (ks->done) return;
   constexpr int EPL = 8;        // elements per lane and chunk
   constexpr int CE = 4 * EPL;   // elements per chunk
+  constexpr int VN = 16 / sizeof(T);
   constexpr int NW = kBlock / 64;
   const int nv = k + 1, nr = nv + s;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const float* __restrict__ W = V + (size_t)(k + 1) * ldv;
-  const float* rp[NT];
+  const T* __restrict__ W = V + (size_t)(k + 1) * ldv;
+  const T* rp[NT];
   bool rv[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
@@ -783,21 +794,23 @@ __global__ __launch_bounds__(kBlock) void k_sstep_dots_mfma(int N, int ldv, cons
   const int nch = (N + CE - 1) / CE;
   const int gw = blockIdx.x * NW + wv, nw = gridDim.x * NW;
   const int c0 = (int)((int64_t)gw * nch / nw), c1 = (int)((int64_t)(gw + 1) * nch / nw);
-  auto load = [&](int c, float (&a)[NT][EPL]) {
+  auto load = [&](int c, T (&a)[NT][EPL]) {
 #pragma unroll
     for (int t = 0; t < NT; ++t)
 #pragma unroll
-      for (int f = 0; f < EPL / 4; ++f) {
-        float q[4] = {0.f, 0.f, 0.f, 0.f};
-        if (rv[t] && c < c1) load16(rp[t], c * CE + lk * EPL + 4 * f, N, q);
+      for (int f = 0; f < EPL / VN; ++f) {
+        T q[VN];
 #pragma unroll
-        for (int x = 0; x < 4; ++x) a[t][4 * f + x] = q[x];
+        for (int x = 0; x < VN; ++x) q[x] = T(0);
+        if (rv[t] && c < c1) load16(rp[t], c * CE + lk * EPL + VN * f, N, q);
+#pragma unroll
+        for (int x = 0; x < VN; ++x) a[t][VN * f + x] = q[x];
       }
   };
-  float a[NT][EPL];
+  T a[NT][EPL];
   load(c0, a);
   for (int c = c0; c < c1; ++c) {
-    float an[NT][EPL];
+    T an[NT][EPL];
     load(c + 1, an);
 #pragma unroll
     for (int e = 0; e < EPL; ++e) {
@@ -1225,18 +1238,19 @@ __global__ __launch_bounds__(kBlock) void k_sstep_update(int N, int ldv, T* __re
 // 4 (l & 15) + x and stores them as one 16-byte write per column.  Every row
 // of a tile is read before the tile's in-place stores; waves own disjoint
 // tiles.
-template <int KG>
-__global__ __launch_bounds__(kBlock) void k_sstep_update_mfma(int N, int ldv, float* __restrict__ V, int k, int s,
+template <typename T, int KG>
+__global__ __launch_bounds__(kBlock) void k_sstep_update_mfma(int N, int ldv, T* __restrict__ V, int k, int s,
                                                              const KState* __restrict__ ks) {
   constexpr int NW = kBlock / 64;
+  constexpr int VN = 16 / sizeof(T);
   if (!ks->blk_ok) return;
   const int nv = k + 1, K = s + nv;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  float* __restrict__ W = V + (size_t)(k + 1) * ldv;
+  T* __restrict__ W = V + (size_t)(k + 1) * ldv;
   // A operand of row group g: Coef[4 g + lk][li]
   double cf[KG];
-  const float* rp[KG];
+  const T* rp[KG];
   bool rv[KG];
 #pragma unroll
   for (int g = 0; g < KG; ++g) {
@@ -1252,12 +1266,20 @@ __global__ __launch_bounds__(kBlock) void k_sstep_update_mfma(int N, int ldv, fl
   const int t0 = (int)((int64_t)gw * ntile / nw), t1 = (int)((int64_t)(gw + 1) * ntile / nw);
   for (int t = t0; t < t1; ++t) {
     const int e = t * 64 + 4 * li;
-    float a[KG][4];
+    T a[KG][4];
 #pragma unroll
     for (int g = 0; g < KG; ++g) {
 #pragma unroll
-      for (int x = 0; x < 4; ++x) a[g][x] = 0.f;
-      if (rv[g]) load16(rp[g], e, N, a[g]);
+      for (int x = 0; x < 4; ++x) a[g][x] = T(0);
+      if (rv[g]) {
+#pragma unroll
+        for (int f = 0; f < 4 / VN; ++f) {
+          T q[VN];
+          load16(rp[g], e + VN * f, N, q);
+#pragma unroll
+          for (int x = 0; x < VN; ++x) a[g][VN * f + x] = q[x];
+        }
+      }
     }
     mfma_d4 acc[4];
 #pragma unroll
@@ -1271,10 +1293,13 @@ __global__ __launch_bounds__(kBlock) void k_sstep_update_mfma(int N, int ldv, fl
     for (int v = 0; v < 4; ++v) {
       const int i = lk + 4 * v;
       if (i < s) {
-        float o[4];
 #pragma unroll
-        for (int x = 0; x < 4; ++x) o[x] = (float)acc[x][v];
-        store16(W + (size_t)i * ldv, e, N, o);
+        for (int f = 0; f < 4 / VN; ++f) {
+          T o[VN];
+#pragma unroll
+          for (int x = 0; x < VN; ++x) o[x] = (T)acc[VN * f + x][v];
+          store16(W + (size_t)i * ldv, e + VN * f, N, o);
+        }
       }
     }
   }
@@ -2506,20 +2531,28 @@ void cycle_start(H* h, int mode, int red_idx, double tol_abs, double tol_rel) {
   k_cycle_start<<<1, 64, 0, h->stream>>>(h->ks, mode, red_idx, tol_abs, tol_rel);
 }
 
-void cast_v0(H* h, const double* r) { k_cast_v0<<<vec_grid(h), kBlock, 0, h->stream>>>(h->N, r, h->V32, h->ks); }
+void cast_v0(H* h, const double* r, bool fp64) {
+  if (fp64)
+    k_cast_v0<double><<<vec_grid(h), kBlock, 0, h->stream>>>(h->N, r, h->V64, h->ks);
+  else
+    k_cast_v0<float><<<vec_grid(h), kBlock, 0, h->stream>>>(h->N, r, h->V32, h->ks);
+}
 
 // workgroups of the GMRES vector kernels: one 16-byte access per thread and
 // vector per chunk, at most kRedBlocks partials per row
 int gmres_grid(const H* h, bool fp32) { return vec16_grid(h, kBlock * (fp32 ? 4 : 2)); }
 
-void gmres_spmv64(H* h, const double* A, const double* dinv, int k) {
-  const double* x = h->V64 + (size_t)k * h->ldv;
+void spmv64(H* h, const double* A, const double* dinv, const double* x, double theta, int rev, double* y) {
   if (h->dlt16)
     launch(h, AFC_KERNEL_SPMV64, k_sell_spmv64<int16_t>, sell_grid(h, false), kBlock, sell_view(h),
-           static_cast<const int16_t*>(h->sl_dlt), A, dinv, x, (const KState*)h->ks, h->w[0]);
+           static_cast<const int16_t*>(h->sl_dlt), A, dinv, x, (const KState*)h->ks, theta, rev, y);
   else
     launch(h, AFC_KERNEL_SPMV64, k_sell_spmv64<int32_t>, sell_grid(h, false), kBlock, sell_view(h),
-           static_cast<const int32_t*>(h->sl_dlt), A, dinv, x, (const KState*)h->ks, h->w[0]);
+           static_cast<const int32_t*>(h->sl_dlt), A, dinv, x, (const KState*)h->ks, theta, rev, y);
+}
+
+void gmres_spmv64(H* h, const double* A, const double* dinv, int k) {
+  spmv64(h, A, dinv, h->V64 + (size_t)k * h->ldv, 0.0, 0, h->w[0]);
 }
 
 void spmv32(H* h, const float* A32, const float* x, float theta, int rev, float* y) {
@@ -2572,17 +2605,19 @@ int sstep_grid(const H* h) { return std::min(vec16_grid(h, kBlock * 4), 1024); }
 
 // blocks of up to eight vectors: wave reductions (LDS holds the output rows of
 // every wave); larger blocks: the FP64 matrix cores, in row tiles of 16
-void sstep_dots(H* h, int k, int s) {
+template <typename T>
+void sstep_dots_t(H* h, const T* V, int k, int s) {
   if (s <= 8) {
     const size_t shm = sizeof(double) * ((size_t)(k + 1) * s + s * (s + 1) / 2) * (kBlock / 64);
-    launch_shm(h, AFC_KERNEL_DOTS, k_sstep_dots<float>, sstep_grid(h), kBlock, shm, h->N, h->ldv,
-               (const float*)h->V32, k, s, (const KState*)h->ks, h->partials_blk);
+    const int nb = std::min(vec16_grid(h, kBlock * (int)(16 / sizeof(T))), 1024);
+    launch_shm(h, AFC_KERNEL_DOTS, k_sstep_dots<T>, nb, kBlock, shm, h->N, h->ldv, V, k, s, (const KState*)h->ks,
+               h->partials_blk);
     return;
   }
   const int nt = (k + 1 + s + 15) / 16;
-#define AFC_DOTS_MFMA(NT)                                                                                   \
-  launch(h, AFC_KERNEL_DOTS, k_sstep_dots_mfma<NT>, sstep_grid(h), kBlock, h->N, h->ldv, (const float*)h->V32, \
-         k, s, (const KState*)h->ks, h->partials_blk)
+#define AFC_DOTS_MFMA(NT)                                                                                       \
+  launch(h, AFC_KERNEL_DOTS, k_sstep_dots_mfma<T, NT>, sstep_grid(h), kBlock, h->N, h->ldv, V, k, s, \
+         (const KState*)h->ks, h->partials_blk)
   static_assert(kMaxRestart + 1 <= 5 * 16, "row tiles of the largest block");
   switch (nt) {
     case 1: AFC_DOTS_MFMA(1); break;
@@ -2594,9 +2629,22 @@ void sstep_dots(H* h, int k, int s) {
 #undef AFC_DOTS_MFMA
 }
 
-void sstep_reduce(H* h, int k, int s, int m, double theta) {
+// partial slots per output row of the projections just launched
+int sstep_dots_grid(const H* h, int s, bool fp64) {
+  return s <= 8 ? std::min(vec16_grid(h, kBlock * (fp64 ? 2 : 4)), 1024) : sstep_grid(h);
+}
+
+void sstep_dots(H* h, int k, int s, bool fp64) {
+  if (fp64)
+    sstep_dots_t<double>(h, h->V64, k, s);
+  else
+    sstep_dots_t<float>(h, h->V32, k, s);
+}
+
+void sstep_reduce(H* h, int k, int s, int m, double theta, bool fp64) {
   const int nrows = (k + 1) * s + s * (s + 1) / 2;
-  launch(h, AFC_KERNEL_FINISH, k_sstep_sums, nrows, kBlock, h->ks, (const double*)h->partials_blk, sstep_grid(h));
+  launch(h, AFC_KERNEL_FINISH, k_sstep_sums, nrows, kBlock, h->ks, (const double*)h->partials_blk,
+         sstep_dots_grid(h, s, fp64));
   if (s <= 8)
     launch(h, AFC_KERNEL_FINISH, k_sstep_small<8>, 1, kBlock, h->ks, k, s, m, theta);
   else
@@ -2605,9 +2653,10 @@ void sstep_reduce(H* h, int k, int s, int m, double theta) {
 
 // blocks of up to eight vectors: FP64 FMAs per element; larger blocks: the
 // FP64 matrix cores, in row groups of four (K = s + k + 1 <= m rows)
-void sstep_update(H* h, int k, int s) {
+template <typename T>
+void sstep_update_t(H* h, T* V, int k, int s) {
   if (s <= 8) {
-    launch(h, AFC_KERNEL_UPDATE, k_sstep_update<float>, gmres_grid(h, true), kBlock, h->N, h->ldv, h->V32, k, s,
+    launch(h, AFC_KERNEL_UPDATE, k_sstep_update<T>, gmres_grid(h, sizeof(T) == 4), kBlock, h->N, h->ldv, V, k, s,
            (const KState*)h->ks);
     return;
   }
@@ -2615,22 +2664,33 @@ void sstep_update(H* h, int k, int s) {
   const int nb = sstep_grid(h);
   static_assert(kMaxRestart <= 4 * 16, "row groups of the largest updated block");
   if (kg <= 4)
-    launch(h, AFC_KERNEL_UPDATE, k_sstep_update_mfma<4>, nb, kBlock, h->N, h->ldv, h->V32, k, s, (const KState*)h->ks);
+    launch(h, AFC_KERNEL_UPDATE, k_sstep_update_mfma<T, 4>, nb, kBlock, h->N, h->ldv, V, k, s, (const KState*)h->ks);
   else if (kg <= 8)
-    launch(h, AFC_KERNEL_UPDATE, k_sstep_update_mfma<8>, nb, kBlock, h->N, h->ldv, h->V32, k, s, (const KState*)h->ks);
+    launch(h, AFC_KERNEL_UPDATE, k_sstep_update_mfma<T, 8>, nb, kBlock, h->N, h->ldv, V, k, s, (const KState*)h->ks);
   else if (kg <= 12)
-    launch(h, AFC_KERNEL_UPDATE, k_sstep_update_mfma<12>, nb, kBlock, h->N, h->ldv, h->V32, k, s,
+    launch(h, AFC_KERNEL_UPDATE, k_sstep_update_mfma<T, 12>, nb, kBlock, h->N, h->ldv, V, k, s,
            (const KState*)h->ks);
   else
-    launch(h, AFC_KERNEL_UPDATE, k_sstep_update_mfma<16>, nb, kBlock, h->N, h->ldv, h->V32, k, s,
+    launch(h, AFC_KERNEL_UPDATE, k_sstep_update_mfma<T, 16>, nb, kBlock, h->N, h->ldv, V, k, s,
            (const KState*)h->ks);
+}
+
+void sstep_update(H* h, int k, int s, bool fp64) {
+  if (fp64)
+    sstep_update_t<double>(h, h->V64, k, s);
+  else
+    sstep_update_t<float>(h, h->V32, k, s);
 }
 
 void gmres_solve(H* h, int m, int kb, int sb) { k_gmres_solve<<<1, 64, 0, h->stream>>>(h->ks, m, kb, sb); }
 
-void sstep_xupdate(H* h, int kb, int sb, const double* dinv, double* x) {
-  k_sstep_xupdate<float><<<vec16_grid(h, kBlock * 4), kBlock, 0, h->stream>>>(h->N, h->ldv, h->V32, dinv, x, h->ks,
-                                                                               kb, sb);
+void sstep_xupdate(H* h, int kb, int sb, const double* dinv, double* x, bool fp64) {
+  if (fp64)
+    k_sstep_xupdate<double><<<vec16_grid(h, kBlock * 2), kBlock, 0, h->stream>>>(h->N, h->ldv, h->V64, dinv, x,
+                                                                                  h->ks, kb, sb);
+  else
+    k_sstep_xupdate<float><<<vec16_grid(h, kBlock * 4), kBlock, 0, h->stream>>>(h->N, h->ldv, h->V32, dinv, x,
+                                                                                 h->ks, kb, sb);
 }
 
 void gmres_xupdate(H* h, bool fp32, const double* dinv, double* x) {
@@ -2826,21 +2886,24 @@ void prof_gmres_cycle(afc_handle_s* h, bool fp32, int m, int kk) {
   }
 }
 
-void prof_sstep_cycle(afc_handle_s* h, int m, int s, int kk) {
+void prof_sstep_cycle(afc_handle_s* h, int m, int s, int kk, bool fp64) {
   if (!h->opt.profile) return;
   const double N = (double)h->N;
-  const double nbv = (double)sstep_grid(h);
+  const double vb = fp64 ? 8.0 : 4.0;
+  const int kid = fp64 ? AFC_KERNEL_SPMV64 : AFC_KERNEL_SPMV32;
   // blocks that ran: up to the one holding column kk (a converged block still
   // orthonormalizes its vectors)
   for (int k = 0; k < m && k <= kk; k += s) {
     const int sb = std::min(s, m - k);
-    // matrix, x = V[k+j] (its diagonal term feeds the shift too), y
-    h->prof_bytes[AFC_KERNEL_SPMV32] += sb * (krylov_matrix_bytes(h) + 2.0 * 4.0 * N);
-    h->prof_work[AFC_KERNEL_SPMV32] += sb;
-    h->prof_bytes[AFC_KERNEL_DOTS] += 4.0 * N * (k + 1 + sb) + 8.0 * nbv * ((k + 1) * sb + sb * (sb + 1) / 2);
+    const double nbv = (double)sstep_dots_grid(h, sb, fp64);
+    // matrix, x = V[k+j] (FP32: its diagonal term feeds the shift too; FP64:
+    // and the Jacobi scales), y
+    h->prof_bytes[kid] += sb * (fp64 ? sell_matrix_bytes(h, 8) + 3.0 * vb * N : krylov_matrix_bytes(h) + 2.0 * vb * N);
+    h->prof_work[kid] += sb;
+    h->prof_bytes[AFC_KERNEL_DOTS] += vb * N * (k + 1 + sb) + 8.0 * nbv * ((k + 1) * sb + sb * (sb + 1) / 2);
     h->prof_work[AFC_KERNEL_DOTS] += 1;
     if (k + sb < m) {  // the last block is not orthogonalized in place (sstep_xupdate reads it raw)
-      h->prof_bytes[AFC_KERNEL_UPDATE] += 4.0 * N * (k + 1 + 2 * sb);
+      h->prof_bytes[AFC_KERNEL_UPDATE] += vb * N * (k + 1 + 2 * sb);
       h->prof_work[AFC_KERNEL_UPDATE] += 1;
     }
     if (k + sb >= kk && kk < m) break;

@@ -628,19 +628,20 @@ def test_mu_alpha_modes_and_renumbered(mode, name):
         afc.afc_destroy(h)
 
 
-@pytest.mark.parametrize("sstep", [15, 8, 0])
-def test_mcl_full_size_iteration_in_bench_configuration(sstep):
+@pytest.mark.parametrize("sstep,prec", [(15, 1), (8, 1), (0, 1), (15, 0)])
+def test_mcl_full_size_iteration_in_bench_configuration(sstep, prec):
     """Q1 128^3 (the stationary MCL workload) in the configuration bench.py
     times (FP32 GMRES(30)-Jacobi in s-step blocks of 15 inside FP64
-    refinement, 1e-10 ||b||; also blocks of 8 and one basis vector per step): the
+    refinement, 1e-10 ||b||; also blocks of 8, one basis vector per step, and
+    FP64 GMRES in blocks of 15): the
     low-order start and one fixed-point iteration, checked with the oracle's
     FP64 operators at full size: the nonlinear residual the GPU reports, and
     the linear residual of the iterate against b = F + F*(u) assembled by the
     oracle from the GPU's own starting state."""
     afc = _afc()
     inst = I.config3(128)
-    print("full size: N=%d nnz=%d sstep=%d" % (inst.N, inst.nnz, sstep), flush=True)
-    o = dict(precision=1, krylov=1, restart=30, fp_tol=0.0, fp_tol_mode=1, lin_atol=0.0, lin_rtol=1e-10,
+    print("full size: N=%d nnz=%d sstep=%d prec=%d" % (inst.N, inst.nnz, sstep, prec), flush=True)
+    o = dict(precision=prec, krylov=1, restart=30, fp_tol=0.0, fp_tol_mode=1, lin_atol=0.0, lin_rtol=1e-10,
              lin_maxit=100000, sstep=sstep)
     h = afc.afc_create_instance(inst, _opts(fp_maxit=0, **o), conv=True)
     try:
@@ -668,24 +669,26 @@ def test_mcl_full_size_iteration_in_bench_configuration(sstep):
     assert np.linalg.norm(b - P.matvec(As, u1)) <= 1.01e-10 * np.linalg.norm(b)
 
 
-@pytest.mark.parametrize("sstep", [2, 5, 8, 9, 12, 15, 16])
-def test_sstep_gmres_parity(sstep):
-    """s-step GMRES (blocks of s basis vectors) in the mixed-precision solve of
-    the stationary MCL workload at 12^3: same solution as the oracle, Krylov
-    iterations close to the one-vector method's."""
+@pytest.mark.parametrize("sstep,prec", [(2, 1), (5, 1), (8, 1), (9, 1), (12, 1), (15, 1), (16, 1), (5, 0), (8, 0),
+                                        (15, 0)])
+def test_sstep_gmres_parity(sstep, prec):
+    """s-step GMRES (blocks of s basis vectors) in the mixed-precision and the
+    FP64 solve of the stationary MCL workload at 12^3: same solution as the
+    oracle (1e-8 mixed, 1e-10 FP64), Krylov iterations close to the
+    one-vector method's."""
     afc = _afc()
     inst = I.config3(12)
     ref, rst = _mcl_ref(inst, 1e-12, 1e-14)
     its = {}
     for s in (0, sstep):
-        print("sstep=%d" % s, flush=True)
-        h = afc.afc_create_instance(inst, _opts(precision=1, sstep=s, fp_tol=1e-12, fp_tol_mode=1, fp_maxit=2000,
+        print("sstep=%d prec=%d" % (s, prec), flush=True)
+        h = afc.afc_create_instance(inst, _opts(precision=prec, sstep=s, fp_tol=1e-12, fp_tol_mode=1, fp_maxit=2000,
                                                 lin_atol=0.0, lin_rtol=1e-14), conv=True)
         try:
             u = _dev(np.zeros(inst.N))
             st, stats = afc.afc_solve_stationary(h, u, _dev(inst.F), init_low_order=True)
             assert st == 0, stats
-            assert _rel(u.cpu().numpy(), ref) <= 1e-8
+            assert _rel(u.cpu().numpy(), ref) <= (1e-8 if prec else 1e-10)
             its[s] = stats["krylov_iters"]
         finally:
             afc.afc_destroy(h)
@@ -714,14 +717,14 @@ def test_sstep_tiny_and_ragged_sizes(n, sstep):
         afc.afc_destroy(h)
 
 
-@pytest.mark.parametrize("sstep", [5, 15])
-def test_sstep_renumbered_and_graph_replay(sstep):
+@pytest.mark.parametrize("sstep,prec", [(5, 1), (15, 1), (15, 0)])
+def test_sstep_renumbered_and_graph_replay(sstep, prec):
     afc = _afc()
     inst = I.renumbered(I.config3(10))
     outs = []
     for g in (1, 0):
-        print("renumbered sstep=%d graphs=%d" % (sstep, g), flush=True)
-        h = afc.afc_create_instance(inst, _opts(precision=1, sstep=sstep, graphs=g, fp_tol=0.0, fp_tol_mode=1, fp_maxit=1,
+        print("renumbered sstep=%d prec=%d graphs=%d" % (sstep, prec, g), flush=True)
+        h = afc.afc_create_instance(inst, _opts(precision=prec, sstep=sstep, graphs=g, fp_tol=0.0, fp_tol_mode=1, fp_maxit=1,
                                                 lin_atol=0.0, lin_rtol=1e-10), conv=True)
         try:
             u = _dev(np.zeros(inst.N))
@@ -740,21 +743,21 @@ def test_sstep_renumbered_and_graph_replay(sstep):
     assert _rel(outs[0], ref) <= 1e-8
 
 
-@pytest.mark.parametrize("sstep", [5, 15])
-def test_sstep_failed_block_falls_back(sstep):
+@pytest.mark.parametrize("sstep,prec", [(5, 1), (15, 1), (15, 0)])
+def test_sstep_failed_block_falls_back(sstep, prec):
     """A shift that overflows the FP32 powers makes the first block's Cholesky
     QR fail; the solve continues with one-vector steps and converges."""
     afc = _afc()
     inst = I.config3(10)
     ref, _ = _mcl_ref(inst, 1e-12, 1e-14)
-    print("failed block sstep=%d" % sstep, flush=True)
-    h = afc.afc_create_instance(inst, _opts(precision=1, sstep=sstep, sstep_shift=1e30, fp_tol=1e-12, fp_tol_mode=1,
+    print("failed block sstep=%d prec=%d" % (sstep, prec), flush=True)
+    h = afc.afc_create_instance(inst, _opts(precision=prec, sstep=sstep, sstep_shift=1e30, fp_tol=1e-12, fp_tol_mode=1,
                                             fp_maxit=2000, lin_atol=0.0, lin_rtol=1e-14), conv=True)
     try:
         u = _dev(np.zeros(inst.N))
         st, stats = afc.afc_solve_stationary(h, u, _dev(inst.F), init_low_order=True)
         assert st == 0, stats
-        assert _rel(u.cpu().numpy(), ref) <= 1e-8
+        assert _rel(u.cpu().numpy(), ref) <= (1e-8 if prec else 1e-10)
     finally:
         afc.afc_destroy(h)
 
@@ -773,7 +776,10 @@ def test_sstep_failed_block_falls_back(sstep):
     (30, 300, 12, 1),  # blocks of 12, 12 and 6
     (12, 300, 15, 1),  # a block cut to the cycle: one block of 12
     (30, 10, 15, 1),  # the inner step cap shortens the cycle to 10: one block of 10
-    (64, 300, 9, 1),  # the smallest two-group block: seven blocks of 9 and one of 1
+    (64, 300, 9, 1),  # seven blocks of 9 and one of 1
+    (64, 300, 15, 0),  # FP64 basis: four blocks of 15 and a last block of 4
+    (30, 300, 15, 0),  # FP64 basis: two blocks of 15
+    (30, 300, 5, 0),  # FP64 basis: six blocks of 5 (wave-reduction kernels)
 ])
 def test_gmres_restart_lengths(restart, inner, sstep, prec):
     """GMRES cycles from 5 to the 64-vector limit, with and without s-step
