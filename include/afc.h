@@ -120,15 +120,18 @@ typedef struct {
   int32_t profile;          /* 1: time every launch of the hot kernels with HIP
                                events on the handle's stream (afc_kernel_time) */
   int32_t limiter;          /* AFC_LIMITER_* of afc_solve_stationary          */
-  int32_t sstep;            /* mixed-precision GMRES: 0 = one basis vector per
+  int32_t sstep;            /* GMRES (FP64 and mixed): 0 = one basis vector per
                                step (classical Gram-Schmidt); s = 2..16 = blocks
                                of s vectors from shifted matrix powers
                                (A - I)^j v, orthonormalized together (block
-                               Gram-Schmidt + Cholesky QR).  Same Krylov space
-                               and minimal-residual iterate as GMRES in exact
+                               Gram-Schmidt + Cholesky QR), in the basis
+                               precision of the mode.  Same Krylov space and
+                               minimal-residual iterate as GMRES in exact
                                arithmetic; a block whose QR fails halves s for
                                the handle's later cycles and solves (s = 0
-                               below 2) until afc_set_options is called.       */
+                               below 2) until afc_set_options is called; a
+                               solve following one of at most 4 (8) Krylov
+                               iterations uses blocks of 4 (8).                */
   double sstep_shift;       /* theta of the shifted powers (default 1: the
                                Jacobi-scaled matrix has unit diagonal)         */
   int32_t graphs;           /* 1 (default): each GMRES cycle is captured once
