@@ -400,18 +400,19 @@ def test_mcl_damped_fixed_point_parity(prec, omega, dyn):
         afc.afc_destroy(h)
 
 
-@pytest.mark.parametrize("prec", [0, 1])
-def test_mcl_inexact_fixed_point_parity(prec):
+@pytest.mark.parametrize("prec,sstep", [(0, 0), (1, 0), (1, 15), (0, 15)])
+def test_mcl_inexact_fixed_point_parity(prec, sstep):
     """Inexact linear solves (each to 1e-2 of the current nonlinear residual)
     on the stationary MCL workload at 12^3: the oracle run with the same
     option takes the same fixed-point iterations, and both reach the strict
-    run's solution."""
+    run's solution.  With s-step GMRES the short solves switch to blocks of 4
+    or 8 after the first one."""
     afc = _afc()
     inst = I.config3(12)
     ref, rst = _mcl_ref(inst, 1e-12, 1e-14, maxit=4000, lin_eta=1e-2)
     strict, _ = _mcl_ref(inst, 1e-12, 1e-14, maxit=4000)
-    print("mcl inexact n=12 prec=%d oracle fp its %d" % (prec, rst.iters), flush=True)
-    h = afc.afc_create_instance(inst, _opts(precision=prec, fp_tol=1e-12, fp_tol_mode=1, fp_maxit=4000,
+    print("mcl inexact n=12 prec=%d sstep=%d oracle fp its %d" % (prec, sstep, rst.iters), flush=True)
+    h = afc.afc_create_instance(inst, _opts(precision=prec, sstep=sstep, fp_tol=1e-12, fp_tol_mode=1, fp_maxit=4000,
                                             lin_atol=0.0, lin_rtol=1e-14, lin_eta=1e-2), conv=True)
     try:
         u = _dev(np.zeros(inst.N))
