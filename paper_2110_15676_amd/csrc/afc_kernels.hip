@@ -374,6 +374,59 @@ __global__ __launch_bounds__(kBlock) void k_sell_spmv64(SellView S, const TI* __
   }
 }
 
+// Lane shifts across the wave (DPP wave_shr:1 / wave_shl:1 with bound_ctrl:
+// the lane with no source reads 0), the edge lane then selected explicitly.
+// (Passing the edge value as the DPP's old operand instead gave wrong sums
+// beside the edge lanes on gfx950; this form matched the gathers bitwise.)
+__device__ __forceinline__ double lane_from_prev(double v) {  // lane l gets lane l - 1's value
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, 0x138, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x138, 0xf, 0xf, true);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double lane_from_next(double v) {  // lane l gets lane l + 1's value
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, 0x130, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x130, 0xf, 0xf, true);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double lane_double(double v, int l) {  // lane l's value, wave-uniform
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+// sum_p val[p] x[i + delta_p] over a full uniform slice whose 27 offsets are
+// nine runs (c - 1, c, c + 1) in slot order (the trilinear stencil with its
+// diagonal): the wave loads x[i + c] once per run and takes the two neighbours
+// from the adjacent lanes; lane 0's x[i - 1 + c] and lane 63's x[i + 1 + c] of
+// the nine runs come in one 18-lane load.  Every x index used is one of the
+// row's own column indices, which the layout keeps in range for every row of
+// a uniform slice.  Products are added in slot order, as in sell_row.
+__device__ __forceinline__ double sell_row27_runs(const double* __restrict__ v, const int (&c)[9], int i0, int lane,
+                                                  const double* __restrict__ x) {
+  int ce = c[0];
+#pragma unroll
+  for (int w = 1; w < 9; ++w) ce = (lane >> 1) == w ? c[w] : ce;
+  double ev = 0.0;
+  if (lane < 18) ev = x[i0 + ce + ((lane & 1) ? 64 : -1)];
+  double a[27], xc[9];
+#pragma unroll
+  for (int w = 0; w < 9; ++w) xc[w] = x[i0 + lane + c[w]];
+#pragma unroll
+  for (int q = 0; q < 27; ++q) a[q] = v[64 * q];
+  double acc = 0.0;
+#pragma unroll
+  for (int w = 0; w < 9; ++w) {
+    const double el = lane_double(ev, 2 * w), er = lane_double(ev, 2 * w + 1);
+    const double l = lane_from_prev(xc[w]), r = lane_from_next(xc[w]);
+    acc += a[3 * w] * (lane == 0 ? el : l);
+    acc += a[3 * w + 1] * xc[w];
+    acc += a[3 * w + 2] * (lane == 63 ? er : r);
+  }
+  return acc;
+}
+
 // r = b - A x (FP64) with ||r||^2 partials
 template <typename TI>
 __global__ __launch_bounds__(kBlock) void k_sell_residual(SellView S, const TI* __restrict__ dlt,
@@ -390,7 +443,22 @@ __global__ __launch_bounds__(kBlock) void k_sell_residual(SellView S, const TI* 
     if (s >= S.nsl) continue;
     const int i = s * 64 + (threadIdx.x & 63);
     if (i >= S.N) continue;
-    const double ri = bvec[i] - sell_row<8>(S, dlt, val, s, i, [&](int j) { return x[j]; });
+    // full uniform slices with the 27-offset run pattern take the x values by
+    // runs (every lane of the wave is active there); the rest gathers
+    const int b0 = S.sl_ptr[s], doff = S.sl_dl[s];
+    bool runs = doff < 0 && s * 64 + 64 <= S.N && S.sl_ptr[s + 1] - b0 == 64 * 27;
+    int c[9];
+    if (runs) {
+      const int* __restrict__ pp = S.pat + ~doff;
+#pragma unroll
+      for (int w = 0; w < 9; ++w) {
+        c[w] = pp[3 * w + 1];
+        runs = runs && pp[3 * w] == c[w] - 1 && pp[3 * w + 2] == c[w] + 1;
+      }
+    }
+    const double ax = runs ? sell_row27_runs(val + b0 + (i & 63), c, s * 64, i & 63, x)
+                           : sell_row<8>(S, dlt, val, s, i, [&](int j) { return x[j]; });
+    const double ri = bvec[i] - ax;
     r[i] = ri;
     nrm[0] += ri * ri;
   }
@@ -1264,14 +1332,16 @@ __global__ __launch_bounds__(kBlock) void k_sstep_update_mfma(int N, int ldv, T*
   const int ntile = (N + 63) / 64;
   const int gw = blockIdx.x * NW + wv, nw = gridDim.x * NW;
   const int t0 = (int)((int64_t)gw * ntile / nw), t1 = (int)((int64_t)(gw + 1) * ntile / nw);
-  for (int t = t0; t < t1; ++t) {
+  // rows of tile t (zeros past the wave's range); with up to eight row groups
+  // the next tile is loaded before the current one is multiplied
+  constexpr bool kPrefetch = KG <= 8;
+  auto load_tile = [&](int t, T (&a)[KG][4]) {
     const int e = t * 64 + 4 * li;
-    T a[KG][4];
 #pragma unroll
     for (int g = 0; g < KG; ++g) {
 #pragma unroll
       for (int x = 0; x < 4; ++x) a[g][x] = T(0);
-      if (rv[g]) {
+      if (rv[g] && t < t1) {
 #pragma unroll
         for (int f = 0; f < 4 / VN; ++f) {
           T q[VN];
@@ -1280,6 +1350,21 @@ __global__ __launch_bounds__(kBlock) void k_sstep_update_mfma(int N, int ldv, T*
           for (int x = 0; x < VN; ++x) a[g][VN * f + x] = q[x];
         }
       }
+    }
+  };
+  T an[KG][4];
+  if (kPrefetch) load_tile(t0, an);
+  for (int t = t0; t < t1; ++t) {
+    const int e = t * 64 + 4 * li;
+    T a[KG][4];
+    if (kPrefetch) {
+#pragma unroll
+      for (int g = 0; g < KG; ++g)
+#pragma unroll
+        for (int x = 0; x < 4; ++x) a[g][x] = an[g][x];
+      load_tile(t + 1, an);
+    } else {
+      load_tile(t, a);
     }
     mfma_d4 acc[4];
 #pragma unroll
@@ -1370,7 +1455,7 @@ __global__ __launch_bounds__(kBlock) void k_sstep_xupdate(int N, int ldv, const 
   if (ks->solved) return;
   constexpr int VN = 16 / sizeof(T);
   constexpr int CH = kBlock * VN;
-  constexpr int QU = 4;
+  constexpr int QU = 8;  // basis vectors loaded together
   __shared__ double a[kMaxRestart + 1 + kSMax];
   const int nq = ks->xnq;  // basis vectors V_0.. with coefficients
   const int nw = ks->xnw;  // raw block vectors with coefficients
@@ -1380,6 +1465,16 @@ __global__ __launch_bounds__(kBlock) void k_sstep_xupdate(int N, int ldv, const 
   const int nt = nq + nw;  // V_0..V_{nq-1}, then V_{kb+1..kb+nw} (the raw W)
   for (int base = blockIdx.x * CH; base < N; base += gridDim.x * CH) {
     const int e = base + threadIdx.x * VN;
+    const bool vx = vec && VN == 4 && e + 4 <= N;
+    double2 d0{0.0, 0.0}, d1{0.0, 0.0}, x0{0.0, 0.0}, x1{0.0, 0.0};
+    if (vx) {  // x and D^{-1} in flight with the first basis loads
+      const double2* dp = reinterpret_cast<const double2*>(dinv + e);
+      const double2* xq = reinterpret_cast<const double2*>(x + e);
+      d0 = dp[0];
+      d1 = dp[1];
+      x0 = xq[0];
+      x1 = xq[1];
+    }
     double acc[VN];
 #pragma unroll
     for (int c = 0; c < VN; ++c) acc[c] = 0.0;
@@ -1399,11 +1494,8 @@ __global__ __launch_bounds__(kBlock) void k_sstep_xupdate(int N, int ldv, const 
         }
       }
     }
-    if (vec && VN == 4 && e + 4 <= N) {  // two 16-byte accesses per array
+    if (vx) {  // two 16-byte accesses per array
       double2* xp = reinterpret_cast<double2*>(x + e);
-      const double2* dp = reinterpret_cast<const double2*>(dinv + e);
-      const double2 d0 = dp[0], d1 = dp[1];
-      double2 x0 = xp[0], x1 = xp[1];
       x0.x += d0.x * acc[0];
       x0.y += d0.y * acc[1 % VN];
       x1.x += d1.x * acc[2 % VN];
