@@ -76,6 +76,35 @@ def test_q1_structured_mostly_uniform():
     assert info["pattern_ints"] < 27 * info["uniform_slices"]  # patterns are shared
 
 
+def test_q1_run_slices_read_in_range():
+    """The FP64 residual takes full uniform slices whose 27 offsets are nine
+    runs (c - 1, c, c + 1) by loading x[i + c] per run and shifting across
+    lanes; lane 0 also reads x[i0 + c - 1] and lane 63 x[i0 + 63 + c + 1].
+    Those are column indices of the slice's own rows, so the layout must keep
+    them in [0, N); and a Q1 mesh must give such slices (most of them)."""
+    afc = _afc()
+    for n in (12, 16):
+        inst = I.config3(n)
+        N = inst.N
+        info, slp, sdl, pat, pos, lane = afc.afc_sell_layout(inst.row_ptr, inst.col)
+        runs = 0
+        for s in range(info["slices"]):
+            L = (slp[s + 1] - slp[s]) // 64
+            if sdl[s] >= 0 or L != 27 or s * 64 + 64 > N:
+                continue
+            p = pat[~sdl[s]: ~sdl[s] + 27].astype(np.int64)
+            c = p[1::3]
+            if not (np.array_equal(p[0::3], c - 1) and np.array_equal(p[2::3], c + 1)):
+                continue
+            runs += 1
+            i0 = s * 64
+            rows = i0 + np.arange(64)
+            j = rows[:, None] + p[None, :]
+            assert np.all(j >= 0) and np.all(j < N)
+            assert np.all(i0 + c - 1 >= 0) and np.all(i0 + 63 + c + 1 < N)
+        assert runs >= 0.75 * info["slices"], (n, runs, info["slices"])
+
+
 def test_p1_structured():
     inst = I.config1(6)
     info = _check_layout(inst.row_ptr, inst.col)
