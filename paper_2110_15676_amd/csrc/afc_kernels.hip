@@ -317,6 +317,81 @@ __device__ __forceinline__ TA sell_row(const SellView& S, const TI* __restrict__
   return acc;
 }
 
+// Lane shifts with an edge value: lane l takes lane l - 1's value and lane 0
+// the edge value (or lane l + 1's and lane 63 the edge).  The edge value is
+// put into the lane that wraps around (63, or 0) and the whole wave is rotated
+// by one (DPP wave_ror:1 / wave_rol:1), so every lane reads an active lane and
+// no select follows the move.  (A select after a shift was lowered by running
+// the move with the edge lane masked off; a DPP read from a disabled lane
+// counts as out of range, and its neighbour then read 0.)
+__device__ __forceinline__ int rot_prev(int v) { return __builtin_amdgcn_mov_dpp(v, 0x13C, 0xf, 0xf, false); }
+__device__ __forceinline__ int rot_next(int v) { return __builtin_amdgcn_mov_dpp(v, 0x134, 0xf, 0xf, false); }
+__device__ __forceinline__ double lane_from_prev(double v, double edge, int lane) {  // lane 0: edge
+  const long long b = __builtin_bit_cast(long long, lane == 63 ? edge : v);
+  const int lo = rot_prev((int)b), hi = rot_prev((int)(b >> 32));
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double lane_from_next(double v, double edge, int lane) {  // lane 63: edge
+  const long long b = __builtin_bit_cast(long long, lane == 0 ? edge : v);
+  const int lo = rot_next((int)b), hi = rot_next((int)(b >> 32));
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double lane_double(double v, int l) {  // lane l's value, wave-uniform
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+// Stencil runs.  A full uniform slice whose 27 offsets are nine runs
+// (c - 1, c, c + 1) in slot order (the trilinear stencil with its diagonal)
+// forms X(i + c) once per run in each lane and takes the two neighbours'
+// values from the adjacent lanes; lane 0's X(i - 1 + c) and lane 63's
+// X(i + 1 + c) of the nine runs come from one 18-lane load.  Every index used
+// is one of the row's own column indices, which the layout keeps in range for
+// every row of a uniform slice.  X is formed as sell_row forms it (x_j, or a
+// product such as D^{-1}_j x_j) and products are added in slot order, so the
+// sums equal sell_row's bitwise.  The whole wave must be active.
+//
+// slice_runs27: whether slice s has that form (wave-uniform), and its centres
+__device__ __forceinline__ bool slice_runs27(const SellView& S, int s, int (&c)[9]) {
+  const int doff = S.sl_dl[s];
+  bool runs = doff < 0 && s * 64 + 64 <= S.N && S.sl_ptr[s + 1] - S.sl_ptr[s] == 64 * 27;
+  if (runs) {
+    const int* __restrict__ pp = S.pat + ~doff;
+#pragma unroll
+    for (int w = 0; w < 9; ++w) {
+      c[w] = pp[3 * w + 1];
+      runs = runs && pp[3 * w] == c[w] - 1 && pp[3 * w + 2] == c[w] + 1;
+    }
+  }
+  return runs;
+}
+// sell_row27_runs: sum_p val[p] X(i + delta_p) for such a slice, vs its first slot
+template <typename XF>
+__device__ __forceinline__ double sell_row27_runs(const double* __restrict__ vs, const int (&c)[9], int i0, int lane,
+                                                    XF xf) {
+  int ce = c[0];
+#pragma unroll
+  for (int w = 1; w < 9; ++w) ce = (lane >> 1) == w ? c[w] : ce;
+  double ev = 0.0;
+  if (lane < 18) ev = xf(i0 + ce + ((lane & 1) ? 64 : -1));
+  double a[27], xc[9];
+#pragma unroll
+  for (int w = 0; w < 9; ++w) xc[w] = xf(i0 + lane + c[w]);
+#pragma unroll
+  for (int q = 0; q < 27; ++q) a[q] = vs[(unsigned)(lane + 64 * q)];
+  double acc = 0.0;
+#pragma unroll
+  for (int w = 0; w < 9; ++w) {
+    const double el = lane_double(ev, 2 * w), er = lane_double(ev, 2 * w + 1);
+    const double l = lane_from_prev(xc[w], el, lane), r = lane_from_next(xc[w], er, lane);
+    acc += a[3 * w] * l;
+    acc += a[3 * w + 1] * xc[w];
+    acc += a[3 * w + 2] * r;
+  }
+  return acc;
+}
+
 // FP32: y = A x (Jacobi-scaled FP32 matrix, unscaled basis vector)
 // y = A x - theta x (theta != 0: the shifted powers of s-step GMRES), A the
 // Jacobi-scaled matrix stored without its diagonal (all ones): the diagonal
@@ -367,64 +442,18 @@ __global__ __launch_bounds__(kBlock) void k_sell_spmv64(SellView S, const TI* __
     const int s = wave_slice(t);
     if (s >= S.nsl) continue;
     const int i = s * 64 + (threadIdx.x & 63);
-    if (i >= S.N) continue;
-    double acc = sell_row<8>(S, dlt, val, s, i, [&](int j) { return sc[j] * x[j]; });
+    const auto xf = [&](int j) { return sc[j] * x[j]; };
+    int c[9];
+    double acc;
+    if (slice_runs27(S, s, c)) {  // wave-uniform; a full slice, every lane has a row
+      acc = sell_row27_runs(val + S.sl_ptr[s], c, s * 64, i & 63, xf);
+    } else {
+      if (i >= S.N) continue;
+      acc = sell_row<8>(S, dlt, val, s, i, xf);
+    }
     if (theta != 0.0) acc -= theta * x[i];
     y[i] = acc;
   }
-}
-
-// Lane shifts across the wave (DPP wave_shr:1 / wave_shl:1 with bound_ctrl:
-// the lane with no source reads 0), the edge lane then selected explicitly.
-// (Passing the edge value as the DPP's old operand instead gave wrong sums
-// beside the edge lanes on gfx950; this form matched the gathers bitwise.)
-__device__ __forceinline__ double lane_from_prev(double v) {  // lane l gets lane l - 1's value
-  const long long b = __builtin_bit_cast(long long, v);
-  const int lo = __builtin_amdgcn_mov_dpp((int)b, 0x138, 0xf, 0xf, true);
-  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x138, 0xf, 0xf, true);
-  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
-}
-__device__ __forceinline__ double lane_from_next(double v) {  // lane l gets lane l + 1's value
-  const long long b = __builtin_bit_cast(long long, v);
-  const int lo = __builtin_amdgcn_mov_dpp((int)b, 0x130, 0xf, 0xf, true);
-  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x130, 0xf, 0xf, true);
-  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
-}
-__device__ __forceinline__ double lane_double(double v, int l) {  // lane l's value, wave-uniform
-  const long long b = __builtin_bit_cast(long long, v);
-  const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
-  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
-}
-
-// sum_p val[p] x[i + delta_p] over a full uniform slice whose 27 offsets are
-// nine runs (c - 1, c, c + 1) in slot order (the trilinear stencil with its
-// diagonal): the wave loads x[i + c] once per run and takes the two neighbours
-// from the adjacent lanes; lane 0's x[i - 1 + c] and lane 63's x[i + 1 + c] of
-// the nine runs come in one 18-lane load.  Every x index used is one of the
-// row's own column indices, which the layout keeps in range for every row of
-// a uniform slice.  Products are added in slot order, as in sell_row.
-__device__ __forceinline__ double sell_row27_runs(const double* __restrict__ v, const int (&c)[9], int i0, int lane,
-                                                  const double* __restrict__ x) {
-  int ce = c[0];
-#pragma unroll
-  for (int w = 1; w < 9; ++w) ce = (lane >> 1) == w ? c[w] : ce;
-  double ev = 0.0;
-  if (lane < 18) ev = x[i0 + ce + ((lane & 1) ? 64 : -1)];
-  double a[27], xc[9];
-#pragma unroll
-  for (int w = 0; w < 9; ++w) xc[w] = x[i0 + lane + c[w]];
-#pragma unroll
-  for (int q = 0; q < 27; ++q) a[q] = v[64 * q];
-  double acc = 0.0;
-#pragma unroll
-  for (int w = 0; w < 9; ++w) {
-    const double el = lane_double(ev, 2 * w), er = lane_double(ev, 2 * w + 1);
-    const double l = lane_from_prev(xc[w]), r = lane_from_next(xc[w]);
-    acc += a[3 * w] * (lane == 0 ? el : l);
-    acc += a[3 * w + 1] * xc[w];
-    acc += a[3 * w + 2] * (lane == 63 ? er : r);
-  }
-  return acc;
 }
 
 // r = b - A x (FP64) with ||r||^2 partials
@@ -442,22 +471,17 @@ __global__ __launch_bounds__(kBlock) void k_sell_residual(SellView S, const TI* 
     const int s = wave_slice(t);
     if (s >= S.nsl) continue;
     const int i = s * 64 + (threadIdx.x & 63);
-    if (i >= S.N) continue;
     // full uniform slices with the 27-offset run pattern take the x values by
     // runs (every lane of the wave is active there); the rest gathers
-    const int b0 = S.sl_ptr[s], doff = S.sl_dl[s];
-    bool runs = doff < 0 && s * 64 + 64 <= S.N && S.sl_ptr[s + 1] - b0 == 64 * 27;
+    const auto xf = [&](int j) { return x[j]; };
     int c[9];
-    if (runs) {
-      const int* __restrict__ pp = S.pat + ~doff;
-#pragma unroll
-      for (int w = 0; w < 9; ++w) {
-        c[w] = pp[3 * w + 1];
-        runs = runs && pp[3 * w] == c[w] - 1 && pp[3 * w + 2] == c[w] + 1;
-      }
+    double ax;
+    if (slice_runs27(S, s, c)) {  // wave-uniform; a full slice, every lane has a row
+      ax = sell_row27_runs(val + S.sl_ptr[s], c, s * 64, i & 63, xf);
+    } else {
+      if (i >= S.N) continue;
+      ax = sell_row<8>(S, dlt, val, s, i, xf);
     }
-    const double ax = runs ? sell_row27_runs(val + b0 + (i & 63), c, s * 64, i & 63, x)
-                           : sell_row<8>(S, dlt, val, s, i, [&](int j) { return x[j]; });
     const double ri = bvec[i] - ax;
     r[i] = ri;
     nrm[0] += ri * ri;
@@ -1712,8 +1736,15 @@ __global__ __launch_bounds__(kBlock) void k_bicg_v(SellView S, const TI* __restr
     const int s = wave_slice(t);
     if (s >= S.nsl) continue;
     const int i = s * 64 + (threadIdx.x & 63);
-    if (i >= S.N) continue;
-    const double q = sell_row<8>(S, dlt, A, s, i, [&](int j) { return dinv[j] * p[j]; });
+    const auto xf = [&](int j) { return dinv[j] * p[j]; };
+    int c[9];
+    double q;
+    if (slice_runs27(S, s, c)) {  // wave-uniform; a full slice, every lane has a row
+      q = sell_row27_runs(A + S.sl_ptr[s], c, s * 64, i & 63, xf);
+    } else {
+      if (i >= S.N) continue;
+      q = sell_row<8>(S, dlt, A, s, i, xf);
+    }
     v[i] = q;
     acc[0] += rhat[i] * q;
   }
@@ -1748,8 +1779,15 @@ __global__ __launch_bounds__(kBlock) void k_bicg_t(SellView S, const TI* __restr
     const int s = wave_slice(t);
     if (s >= S.nsl) continue;
     const int i = s * 64 + (threadIdx.x & 63);
-    if (i >= S.N) continue;
-    const double q = sell_row<8>(S, dlt, A, s, i, [&](int j) { return dinv[j] * sv[j]; });
+    const auto xf = [&](int j) { return dinv[j] * sv[j]; };
+    int c[9];
+    double q;
+    if (slice_runs27(S, s, c)) {  // wave-uniform; a full slice, every lane has a row
+      q = sell_row27_runs(A + S.sl_ptr[s], c, s * 64, i & 63, xf);
+    } else {
+      if (i >= S.N) continue;
+      q = sell_row<8>(S, dlt, A, s, i, xf);
+    }
     tv[i] = q;
     acc[0] += q * sv[i];
     acc[1] += q * q;
