@@ -285,6 +285,28 @@ afc_status afc_kernel_time(afc_handle *h, int32_t kernel, double *total_ms, int6
  * SPMV64, DOTS, UPDATE, RESIDUAL and MCL classes; 0 for FINISH.  Returns EINVAL for an unknown kernel id. */
 afc_status afc_kernel_work(afc_handle *h, int32_t kernel, double *bytes, int64_t *launches_with_work);
 
+/* One application of the stationary MCL system's operators by the solvers'
+ * own SELL-64 kernels, for tests that check those kernels element by element.
+ * A is the low-order operator A_low of eq. (5) that the stationary solve
+ * iterates with (Sec. 4), D = diag(A).  op:
+ *   AFC_APPLY_RESIDUAL (0)  y := y - A x   (FP64, the refinement residual)
+ *   AFC_APPLY_SCALED64 (1)  y = A D^{-1} x (FP64 SpMV of the FP64 GMRES)
+ *   AFC_APPLY_SCALED32 (2)  y = A D^{-1} x with the FP32 Jacobi-scaled copy
+ *                           and the FP32 SpMV of the mixed GMRES (x rounded to
+ *                           FP32, y the FP32 result widened)
+ *   AFC_APPLY_BICG     (3)  y = A D^{-1} x by the BiCGStab SpMV (FP64)
+ * x and y are device pointers to n doubles on the handle's device and must not
+ * overlap.  Runs on the handle's stream and waits for it.  A scratch vector
+ * is allocated on the first call (freed by afc_destroy).  EINVAL for a null or
+ * aliased pointer or an unknown op; EDEVICE / ENOMEM on a HIP error. */
+enum {
+  AFC_APPLY_RESIDUAL = 0,
+  AFC_APPLY_SCALED64 = 1,
+  AFC_APPLY_SCALED32 = 2,
+  AFC_APPLY_BICG = 3
+};
+afc_status afc_apply_operator(afc_handle *h, int32_t op, const double *x, double *y);
+
 /* Storage of the SELL-64 copy of the Krylov system matrices (sizes only).
  * Rows are taken in slices of 64 consecutive rows, each padded to its longest
  * row; a slice whose rows all fit one shared list of column offsets j - i

@@ -80,7 +80,7 @@ EXPORTS = [
     "afc_solve_stationary", "afc_destroy", "afc_status_str", "afc_last_error", "afc_kernel_time",
     "afc_batch_create", "afc_batch_offsets", "afc_batch_step_cn", "afc_batch_last_error", "afc_batch_destroy",
     "afc_footprint_bytes", "afc_server_create", "afc_server_submit", "afc_server_wait", "afc_server_poll", "afc_server_last_error",
-    "afc_server_destroy", "afc_get_sell_info", "afc_get_krylov_sell_info", "afc_sell_layout", "afc_kernel_work",
+    "afc_server_destroy", "afc_get_sell_info", "afc_get_krylov_sell_info", "afc_sell_layout", "afc_kernel_work", "afc_apply_operator",
     "afc_batch_set_schedule", "afc_batch_get_schedule", "afc_batch_autotune", "afc_step_cn_linear",
     "afc_step_mc_ssprk3", "afc_step_mc_cn", "afc_step_ssprk3_noalloc", "afc_residual_history",
     "afc_server_default_config", "afc_server_create_cfg", "afc_server_info",
@@ -125,6 +125,8 @@ def lib():
         L.afc_kernel_time.restype = c_int32
         L.afc_kernel_work.argtypes = [c_void_p, c_int32, POINTER(c_double), POINTER(c_int64)]
         L.afc_kernel_work.restype = c_int32
+        L.afc_apply_operator.argtypes = [c_void_p, c_int32, c_void_p, c_void_p]
+        L.afc_apply_operator.restype = c_int32
         L.afc_get_sell_info.argtypes = [c_void_p, POINTER(afc_sell_info)]
         L.afc_get_sell_info.restype = c_int32
         L.afc_get_krylov_sell_info.argtypes = [c_void_p, POINTER(afc_sell_info)]
@@ -359,6 +361,17 @@ def afc_kernel_time(h, kernel, reset=False):
     if st != AFC_OK:
         raise AFCError(st, "afc_kernel_time")
     return ms.value, n.value
+
+
+AFC_APPLY_RESIDUAL, AFC_APPLY_SCALED64, AFC_APPLY_SCALED32, AFC_APPLY_BICG = 0, 1, 2, 3
+
+
+def afc_apply_operator(h, op, x, y):
+    """y := y - A x (op 0) or y = A D^{-1} x (ops 1-3, FP64 / FP32 / BiCGStab
+    SpMV) by the library's SELL kernels; x, y: device tensors of n doubles."""
+    st = lib().afc_apply_operator(h, int(op), x.data_ptr(), y.data_ptr())
+    if st != AFC_OK:
+        raise AFCError(st, "afc_apply_operator")
 
 
 def afc_kernel_work(h, kernel):

@@ -130,7 +130,7 @@ void free_all(afc_handle* h) {
   f(h->ks_ptr); f(h->ks_dl); f(h->ks_pat); f(h->ks_dlt); f(h->kpos);
   for (auto*& p : h->w) f(p);
   h->w.clear();
-  f(h->V64); f(h->V32);
+  f(h->V64); f(h->V32); f(h->apply_tmp);
   f(h->partials); f(h->partials_res); f(h->partials_blk); f(h->ks);
   if (h->host_status) (void)hipHostFree(h->host_status);
   h->host_status = nullptr;
@@ -1268,6 +1268,25 @@ afc_status afc_kernel_work(afc_handle* h, int32_t kernel, double* bytes, int64_t
   if (!h || kernel < 0 || kernel >= AFC_KERNEL_COUNT) return AFC_EINVAL;
   if (bytes) *bytes = h->prof_bytes[kernel];
   if (launches_with_work) *launches_with_work = h->prof_work[kernel];
+  return AFC_OK;
+}
+
+afc_status afc_apply_operator(afc_handle* h, int32_t op, const double* x, double* y) {
+  if (!h || !x || !y || x == y || op < 0 || op > 3) return AFC_EINVAL;
+  try {
+    HIP_OK(hipSetDevice(h->device));
+    if (!h->apply_tmp) h->apply_tmp = dalloc<double>(h, (size_t)h->ldv);
+    if (op == 0)
+      HIP_OK(hipMemcpyAsync(h->apply_tmp, y, sizeof(double) * h->N, hipMemcpyDeviceToDevice, h->stream));
+    afc::apply_operator(h, op, x, y, h->apply_tmp);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(h->stream));
+  } catch (const Fail& f) {
+    return f.st;
+  } catch (...) {
+    h->last_error = "unexpected host exception";
+    return AFC_EDEVICE;
+  }
   return AFC_OK;
 }
 

@@ -144,6 +144,7 @@ struct afc_handle_s {
   std::vector<double*> w;
   double* V64 = nullptr;  // (m+1) x N
   float* V32 = nullptr;   // (m+1) x N
+  double* apply_tmp = nullptr;  // ldv doubles for afc_apply_operator (allocated on first use)
   int Vm = 0;
   int ldv = 0;  // basis / work vector stride: N rounded up to 64 (16-byte aligned rows)
   int bicg_last = 2;  // BiCGStab iterations of the handle's last solve (first chunk size)

@@ -51,6 +51,7 @@ void gmres_last_givens(H* h, bool fp32, int k, int m);
 // Hessenberg columns, Givens) and the in-place orthonormalization
 void spmv32(H* h, const float* A32, const float* x, float theta, int rev, float* y);
 // y = A (dinv .* x) - theta x (FP64; the SELL FP64 system matrix)
+void apply_operator(H* h, int op, const double* x, double* y, double* tmp);
 void spmv64(H* h, const double* A, const double* dinv, const double* x, double theta, int rev, double* y);
 void sstep_dots(H* h, int k, int s, bool fp64 = false);
 void sstep_reduce(H* h, int k, int s, int m, double theta, bool fp64 = false);

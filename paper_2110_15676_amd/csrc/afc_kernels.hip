@@ -2832,6 +2832,50 @@ void gmres_xupdate(H* h, bool fp32, const double* dinv, double* x) {
                                                                                  h->ks);
 }
 
+// One application of a Krylov operator of the stationary MCL system (A_low,
+// D = diag(A_low)) by the solvers' own SELL kernels: op 0 y := y - A x (the
+// FP64 residual kernel), 1 y = A D^{-1} x (FP64 SpMV of the FP64 GMRES), 2 the
+// same in FP32 (the Jacobi-scaled FP32 copy and the FP32 SpMV of the mixed
+// GMRES, x and y converted), 3 y = A D^{-1} x by the BiCGStab SpMV.  tmp
+// holds ldv doubles (op 0: a copy of the input y, taken by the caller, as the
+// kernel's b; op 2: the two FP32 vectors).  The SpMV kernels skip their work once a solve is flagged done,
+// so the flag is cleared first.
+__global__ void k_to_f32(int N, const double* __restrict__ x, float* __restrict__ y) {
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) y[i] = (float)x[i];
+}
+__global__ void k_to_f64(int N, const float* __restrict__ x, double* __restrict__ y) {
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) y[i] = (double)x[i];
+}
+__global__ void k_clear_done(KState* ks) { ks->done = 0; }
+
+void apply_operator(H* h, int op, const double* x, double* y, double* tmp) {
+  float* tmp32 = reinterpret_cast<float*>(tmp);
+  k_clear_done<<<1, 1, 0, h->stream>>>(h->ks);
+  const int nb = sell_grid(h, false);
+  if (op == 0) {
+    if (h->dlt16)
+      k_sell_residual<int16_t><<<nb, kBlock, 0, h->stream>>>(sell_view(h), static_cast<const int16_t*>(h->sl_dlt),
+                                                              h->S64_mcl, tmp, x, y, h->partials_res, nullptr);
+    else
+      k_sell_residual<int32_t><<<nb, kBlock, 0, h->stream>>>(sell_view(h), static_cast<const int32_t*>(h->sl_dlt),
+                                                              h->S64_mcl, tmp, x, y, h->partials_res, nullptr);
+  } else if (op == 1) {
+    spmv64(h, h->S64_mcl, h->dinv_mcl, x, 0.0, 0, y);
+  } else if (op == 2) {
+    k_to_f32<<<vec_grid(h), kBlock, 0, h->stream>>>(h->N, x, tmp32);
+    spmv32(h, h->S32_mcl, tmp32, 0.0f, 0, tmp32 + h->ldv);
+    k_to_f64<<<vec_grid(h), kBlock, 0, h->stream>>>(h->N, tmp32 + h->ldv, y);
+  } else {
+    const int nr = sell_grid(h, true);
+    if (h->dlt16)
+      k_bicg_v<int16_t><<<nr, kBlock, 0, h->stream>>>(sell_view(h), static_cast<const int16_t*>(h->sl_dlt),
+                                                       h->S64_mcl, h->dinv_mcl, x, x, y, h->ks, h->partials);
+    else
+      k_bicg_v<int32_t><<<nr, kBlock, 0, h->stream>>>(sell_view(h), static_cast<const int32_t*>(h->sl_dlt),
+                                                       h->S64_mcl, h->dinv_mcl, x, x, y, h->ks, h->partials);
+  }
+}
+
 void bicg_init(H* h, const BicgVec& b, double tol) {
   const int nb = vec_grid(h);
   k_bicg_init<<<nb, kBlock, 0, h->stream>>>(h->N, b.r, b.rhat, b.p, b.v, h->ks, h->partials, tol);
