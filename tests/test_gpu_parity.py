@@ -668,9 +668,11 @@ def test_mcl_full_size_iteration_in_bench_configuration(sstep, prec):
     print("Krylov iterations: low order %d (oracle %d), first iteration %d (oracle %d)"
           % (k_lo, ref["low_order_krylov_iters"], k_fp, ref["first_iteration_krylov_iters"]), flush=True)
     assert k_fp <= 1.03 * ref["first_iteration_krylov_iters"] + 3
-    # from zero the mixed solve restarts at every FP64 refinement sweep (about
-    # 505 against 444 measured); FP64 GMRES restarts as the oracle's does
-    assert k_lo <= (1.2 if prec else 1.03) * ref["low_order_krylov_iters"] + 3
+    # the low-order solve from zero in FP32 blocks of more than eight vectors
+    # takes more iterations (505 against 444 measured: the FP32 block basis
+    # loses accuracy on the rough first residuals); one vector per step,
+    # blocks of 8 and FP64 blocks of 15 take the oracle's count
+    assert k_lo <= (1.2 if prec and sstep > 8 else 1.03) * ref["low_order_krylov_iters"] + 3
     print("full size: GPU done, oracle operators", flush=True)
     P = O.problem_from_instance(inst, conv=True)
     d, As = O.stationary_matrix(P)
